@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the matrix-free product y = H x on one particle-number sector.
+
+Workload: periodic spin-1/2 J1-J2 XXZ chain, L=32 sites, n=16 up spins
+(601,080,390 states), J1=1, J2=0.5, Delta=1, index split 8/8/8/8; x ~ N(0,1)
+from a seeded device generator (synthetic data).  One step is one H*X over the
+whole sector: every row decoded (Alg. iii), every bond applied, every reached
+state ranked (eq. index), x gathered, y written.
+
+Three forms are timed: the batched FP32 block of k=8 columns (the headline
+`value`), FP32 k=1, and the plain FP64 k=1 product.  `value` counts sector
+states per second per column (dim * k / time).  One JSON line is printed.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "H·x sector states/s + HBM GB/s, XXZ L=32 N=16; FP32 batched vs plain FP64"
+PEAK_HBM_GBS = 8000.0
+L, N_UP, SPLIT = 32, 16, [8, 8, 8, 8]
+J1, J2, DELTA = 1.0, 0.5, 1.0
+KERNEL_SOURCES = ["hx_impl.h", "device_common.h", "dcs_internal.h", "hx_dispatch.hip"]
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "hx_L32_counters.md")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2407_14591_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(variant: str):
+    """HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE, WRITE_SIZE),
+    valid only while the kernel sources are unchanged since the measurement."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    txt = open(COUNTERS_FILE).read()
+    m = re.search(r"kernel_source_sha:\s*([0-9a-f]+)", txt)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(rf"traffic_bytes_per_launch\[{variant}\]:\s*([0-9.eE+]+)", txt)
+    return float(m.group(1)) if m else None
+
+
+def time_variant(fn, stream, steps: int, warmup: int):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / 1e3  # seconds for `steps` launches
+
+
+def cpu_baseline(x_host, target_s: float = 15.0):
+    """The FP64 C oracle (OpenMP over contiguous row blocks, as the paper's
+    workers) timed on a contiguous block of rows from the middle of the sector."""
+    import numpy as np
+    import synth
+    from oracle import native
+    ns = native.NativeSector(2, L, N_UP, SPLIT)
+    bonds, jxy, jz = synth.j1j2_chain(L, J1, J2, DELTA)
+    t = native.NativeTerms(bonds, jxy, jz)
+    probe = 1 << 18
+    first = (ns.dim - probe) // 2
+    t0 = time.perf_counter()
+    native.hx_range(ns, t, x_host, first, probe)
+    rate = probe / (time.perf_counter() - t0)
+    rows = int(min(ns.dim, max(probe, rate * target_s)))
+    first = (ns.dim - rows) // 2
+    t0 = time.perf_counter()
+    native.hx_range(ns, t, x_host, first, rows)
+    el = time.perf_counter() - t0
+    return {"value": rows / el, "unit": "sector states/s", "cores": native.num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 y=Hx on {rows} contiguous rows [{first}, {first + rows}) of the "
+                      f"L=32 n=16 sector ({el:.1f} s, OpenMP static row blocks)",
+            "seconds": el}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--variants", default="f32k8,f32k1,f64k1",
+                    help="comma list; the first is the headline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU row sharding is a design, see the design notes)", file=sys.stderr)
+        return 2
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: one process only", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2407_14591_amd as dq
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    s = dq.Sector(L, N_UP, 2, SPLIT, device=0)
+    bonds, jxy, jz = synth.j1j2_chain(L, J1, J2, DELTA)
+    terms = dq.Terms(bonds)
+    jxy_d = torch.tensor(jxy, device=dev)
+    jz_d = torch.tensor(jz, device=dev)
+    D = s.dim
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(synth.SEED_X)
+    stream = torch.cuda.current_stream(dev)
+    results = {}
+    x_host = None
+    for v in args.variants.split(","):
+        dt = torch.float32 if v.startswith("f32") else torch.float64
+        k = int(v.split("k")[1])
+        shape = (D,) if k == 1 else (D, k)
+        x = torch.randn(shape, generator=gen, device=dev, dtype=torch.float64)
+        if v == "f64k1" and not args.no_cpu_baseline:
+            x_host = x.cpu().numpy()
+        x = x.to(dt)
+        y = torch.empty_like(x)
+
+        def step():
+            dq.hamiltonian_apply(s, terms, jxy_d, jz_d, x, out=y)
+
+        el = time_variant(step, stream, args.steps, args.warmup)
+        per = el / args.steps
+        es = 4 if dt == torch.float32 else 8
+        bytes_alg = D * k * 2 * es  # read x once, write y once
+        results[v] = {"k": k, "dtype": "f32" if es == 4 else "f64", "seconds_per_step": per,
+                      "states_per_s": D * k / per, "algorithmic_bytes": bytes_alg,
+                      "achieved_GBs": bytes_alg / per / 1e9}
+        del x, y
+        torch.cuda.empty_cache()
+
+    head = args.variants.split(",")[0]
+    r = results[head]
+    traffic = read_traffic(head)
+    out = {
+        "metric": METRIC,
+        "value": r["states_per_s"],
+        "unit": "sector states/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["seconds_per_step"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": r["dtype"],
+        "data": "synthetic",
+        "config": {"workload": "J1-J2 XXZ chain L=32 n=16 periodic, J1=1 J2=0.5 Delta=1, split 8/8/8/8",
+                   "dim": D, "k": r["k"], "vector_dtype": r["dtype"], "variant": head,
+                   "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": r["achieved_GBs"] / PEAK_HBM_GBS,
+                     "traffic": traffic},
+        "variants": {k_: {"states_per_s": v_["states_per_s"], "ms": v_["seconds_per_step"] * 1e3,
+                          "achieved_GBs": v_["achieved_GBs"]} for k_, v_ in results.items()},
+    }
+    if "f64k1" in results:
+        out["speedup_vs_plain_f64_per_column"] = r["states_per_s"] / results["f64k1"]["states_per_s"]
+    if x_host is not None:
+        out["cpu_baseline"] = cpu_baseline(x_host)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

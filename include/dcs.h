@@ -1,0 +1,267 @@
+/*
+ * dcs.h - C ABI of the MI355X (gfx950) library for number-conserving sectors:
+ * the divide-and-conquer basis index and the matrix-free product y = H x.
+ *
+ * The method is that of R. Schaefer and D. J. Luitz, "DanceQ: High-performance
+ * library for number-conserving bases", SciPost Phys. Codebases 48 (2025),
+ * arXiv:2407.14591.  Section references below are to that paper.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - A sector is the set of product states of L sites with Q states each
+ *    (digits 0..Q-1) whose digit sum is n (Sec. 2.1).  Its states are numbered
+ *    0..D-1 in the canonical order of Sec. 3.1-3.2: the sites are cut into
+ *    subsystems P_0..P_{N-1} (consecutive sites, P_0 first); P_0 varies
+ *    slowest; inside a subsystem, words are grouped by their digit sum (lower
+ *    first) and ordered lexicographically (first site most significant).
+ *  - State encoding (Sec. 4.2): one uint64_t per state, ceil(log2 Q) bits per
+ *    site, site 0 in the most significant field of the low L*ceil(log2 Q)
+ *    bits, plain binary digits.  Bits above that must be zero.
+ *  - Pointers named d_* are device pointers on the sector's device; h_* are
+ *    host pointers.  The caller owns every pointer it passes; the library
+ *    owns only the objects it creates (their tables live on the device).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls that take a
+ *    stream only enqueue work on it and return; results are ready when the
+ *    stream is synchronised.  Calls without a stream may synchronise.
+ *  - Every call returns DCS_OK (0) or a negative status; dcs_last_error()
+ *    gives a message for the last failing call of the calling thread.  No
+ *    exception crosses the ABI.  A kernel fault surfaces at the caller's next
+ *    synchronisation of the stream.
+ *  - Index type: indices are uint64_t in the ABI.  Sectors with D < 2^32 - 1 run
+ *    their kernels with 32-bit index arithmetic; larger ones with 64-bit.  The
+ *    environment variable DCS_INDEX_BITS=64, read by dcs_sector_create, forces
+ *    64-bit arithmetic (to test those kernels on small sectors).
+ */
+#ifndef DCS_H
+#define DCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define DCS_OK 0
+#define DCS_EINVAL (-1)       /* bad argument */
+#define DCS_ERANGE (-2)       /* index range past the end of the sector */
+#define DCS_ENOMEM (-3)       /* device or host allocation failed */
+#define DCS_EHIP (-4)         /* a HIP runtime call failed (message has the HIP error) */
+#define DCS_EUNSUPPORTED (-5) /* valid but beyond this build's limits (message says which) */
+
+/* ---- element types of vectors ------------------------------------------- */
+#define DCS_F32 0
+#define DCS_F64 1
+
+/* ---- Lanczos re-orthogonalisation modes --------------------------------- */
+#define DCS_REORTH_NONE 0  /* plain three-term recurrence */
+#define DCS_REORTH_LOCAL 1 /* one Gram-Schmidt pass against v_{j-1}, v_j */
+#define DCS_REORTH_FULL 2  /* two classical Gram-Schmidt passes against all v_0..v_j */
+
+#define DCS_INVALID_INDEX UINT64_MAX /* rank of an invalid state, unrank of an index >= D */
+
+/* Limits of this build */
+#define DCS_MAX_SITES 64
+#define DCS_MAX_SUBSYSTEMS 8
+#define DCS_MAX_BONDS 256
+
+typedef struct dcs_sector dcs_sector;
+typedef struct dcs_terms dcs_terms;
+typedef struct dcs_plan dcs_plan;
+
+/* Message for the last failing call on this thread ("" if none).  The string
+ * stays valid until the next library call on the same thread. */
+const char *dcs_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int dcs_version(void);
+
+/* ========================================================================== */
+/* Sector: the basis with its divide-and-conquer index (Sec. 3.2, 4.2)        */
+/* ========================================================================== */
+
+/*
+ * Build the index of the sector (L sites, local dimension Q = local_dim,
+ * digit sum n = n_particles) cut into num_subsystems consecutive parts of
+ * sizes[0..N-1] sites (P_0 first).  sizes == NULL selects the most-equal
+ * split into ceil(L / floor(9 / ceil(log2 Q))) parts, shorter parts first.
+ *
+ * The host computes the sector dimension D_Q (App. A), the offsets and strides
+ * of eq. offset / eq. stride for every (subsystem, lambda, n_k), and the local
+ * lookup tables (Sec. 4.2, memory-aligned list, lexicographic inside each
+ * digit sum), then copies them to `device`.  The returned object owns them.
+ *
+ * Errors: DCS_EINVAL if Q < 2, L < 1, L*ceil(log2 Q) > 64, n outside
+ * [0, (Q-1)L], sizes not positive or not summing to L; DCS_EUNSUPPORTED if
+ * N > DCS_MAX_SUBSYSTEMS, a subsystem word wider than 14 bits, or tables too
+ * large for on-chip memory (112 KiB); DCS_ENOMEM / DCS_EHIP on allocation.
+ */
+int dcs_sector_create(int L, int n_particles, int local_dim, int num_subsystems,
+                      const int *sizes, int device, dcs_sector **out);
+
+/* Free the sector's device tables and the object.  NULL is accepted. */
+int dcs_sector_destroy(dcs_sector *sector);
+
+/* Exact sector dimension D_Q(L, n) (eq. dim). */
+int dcs_sector_dim(const dcs_sector *sector, uint64_t *dim);
+
+/* Number of subsystems and their sizes (sizes may be NULL; else >= N entries). */
+int dcs_sector_split(const dcs_sector *sector, int *num_subsystems, int *sizes);
+
+/*
+ * Batched rank, function (i) of Sec. 2.2 / Alg. i: d_idx[t] = index of
+ * d_states[t] = sum_k offset_k(n_k, lambda_k) + stride_k(n_k, lambda_k) * index_k
+ * (eq. index, eq. ck).  A state that is not in the sector (a digit >= Q, bits
+ * above L*ceil(log2 Q), or the wrong digit sum) gets DCS_INVALID_INDEX and, if
+ * d_num_invalid != NULL, is added to *d_num_invalid (a device counter that the
+ * call increments, not clears).  count == 0 is a no-op.  d_states and d_idx
+ * must not overlap.
+ */
+int dcs_rank(const dcs_sector *sector, const uint64_t *d_states, uint64_t *d_idx, size_t count,
+             uint64_t *d_num_invalid, void *stream);
+
+/*
+ * Batched unrank, function (iii) of Sec. 2.2 / Alg. iii: d_states[t] = the state
+ * with index d_idx[t].  Indices >= D give DCS_INVALID_INDEX (as a state value)
+ * and are counted like dcs_rank's invalid states.
+ */
+int dcs_unrank(const dcs_sector *sector, const uint64_t *d_idx, uint64_t *d_states, size_t count,
+               uint64_t *d_num_invalid, void *stream);
+
+/*
+ * Enumeration, function (ii) of Sec. 2.2 applied count-1 times from state
+ * `first`: d_states[t] = state with index first + t.  Does not wrap: returns
+ * DCS_ERANGE if first + count > D (the paper's increment wraps to the first
+ * state; a range past the end is an error here).
+ */
+int dcs_enumerate(const dcs_sector *sector, uint64_t first, size_t count, uint64_t *d_states,
+                  void *stream);
+
+/* ========================================================================== */
+/* Terms: the bond topology of an XXZ Hamiltonian                             */
+/* ========================================================================== */
+
+/*
+ * H = sum_b [ Jxy_b/2 (S+_i S-_j + S-_i S+_j) + Jz_b Sz_i Sz_j ] + sum_i h_i Sz_i
+ * (eq. H_30 and App. D, with per-bond couplings), spin S = (Q-1)/2, Sz = d - S
+ * for digit d.  This object holds the topology only: bond b joins sites
+ * site_i[b] != site_j[b] (host arrays, copied).  The couplings are passed to
+ * every apply call, so they can change without rebuilding anything.
+ *
+ * Errors: DCS_EINVAL for num_bonds < 0, a negative site, site_i == site_j;
+ * DCS_EUNSUPPORTED for num_bonds > DCS_MAX_BONDS or a site >= DCS_MAX_SITES.
+ */
+int dcs_terms_create(int num_bonds, const int32_t *site_i, const int32_t *site_j,
+                     dcs_terms **out);
+int dcs_terms_destroy(dcs_terms *terms);
+
+/* ========================================================================== */
+/* Matrix-free product (Sec. 2.2, Sec. 4.4)                                   */
+/* ========================================================================== */
+
+/*
+ * Y = H X on the sector, X and Y of shape [D][k] row-major (k contiguous
+ * columns per basis state), element type dtype (DCS_F32 or DCS_F64), k in
+ * {1, 2, 4, 8}.  d_jxy and d_jz hold num_bonds FP64 couplings (device); d_h
+ * holds L FP64 fields or is NULL.  Each output row is computed by one thread
+ * from the row's state (pull: H is real symmetric), so Y is written once,
+ * with no atomics, and the result is bitwise reproducible.  X and Y must not
+ * overlap.  All bond sites must be < L.
+ * Arithmetic: products and sums in dtype; couplings rounded to dtype.
+ */
+int dcs_hamiltonian_apply(const dcs_sector *sector, const dcs_terms *terms, const double *d_jxy,
+                          const double *d_jz, const double *d_h, int dtype, int k,
+                          const void *d_x, void *d_y, void *stream);
+
+/*
+ * Workspace bytes that dcs_hamiltonian_apply_adjoint needs for this pair.
+ */
+int dcs_adjoint_workspace_size(const dcs_sector *sector, const dcs_terms *terms,
+                               size_t *bytes);
+
+/*
+ * Fused backward of y = H(theta) x for an upstream gradient g (k = 1):
+ *   d_grad_x[s]     = (H g)_s                         (H^T = H)
+ *   d_grad_jxy[b]   = sum_s g_s ((S+_i S-_j + S-_i S+_j)/2 x)_s
+ *   d_grad_jz[b]    = sum_s g_s (Sz_i Sz_j x)_s
+ *   d_grad_h[i]     = sum_s g_s (Sz_i x)_s            (skipped if d_grad_h == NULL)
+ * Every reached state is ranked once and used for both g and x.  The bond
+ * sums are reduced per workgroup into d_workspace and then in a fixed order,
+ * so the result is deterministic.  The coupling gradients are FP64 whatever
+ * dtype is.  d_grad_x may be NULL (only coupling gradients).
+ */
+int dcs_hamiltonian_apply_adjoint(const dcs_sector *sector, const dcs_terms *terms,
+                                  const double *d_jxy, const double *d_jz, const double *d_h,
+                                  int dtype, const void *d_x, const void *d_g, void *d_grad_x,
+                                  double *d_grad_jxy, double *d_grad_jz, double *d_grad_h,
+                                  void *d_workspace, size_t workspace_bytes, void *stream);
+
+/* ========================================================================== */
+/* Batched: many sectors in one launch                                        */
+/* ========================================================================== */
+
+/*
+ * A plan applies H to one vector per sector for num_sectors sectors in a
+ * single persistent launch.  Sector s uses terms[s] with couplings
+ * d_jxy[s], d_jz[s] (device FP64 arrays; the pointers are recorded, the
+ * values are read at apply time).  The sectors may differ in L, n, Q and
+ * split.  The plan does not own the sectors or terms; they must outlive it.
+ */
+int dcs_plan_create(int num_sectors, dcs_sector *const *sectors, dcs_terms *const *terms,
+                    const double *const *d_jxy, const double *const *d_jz, dcs_plan **out);
+int dcs_plan_destroy(dcs_plan *plan);
+
+/* y_s = H_s x_s for every sector s; d_x[s], d_y[s] are device vectors of
+ * D_s elements of dtype (k = 1). */
+int dcs_plan_apply(const dcs_plan *plan, int dtype, const void *const *d_x, void *const *d_y,
+                   void *stream);
+
+/* ========================================================================== */
+/* Lanczos (Sec. 2.1 and App. D name it; the iteration is the textbook one)   */
+/* ========================================================================== */
+
+/*
+ * Device workspace bytes for dcs_lanczos with these arguments.
+ */
+int dcs_lanczos_workspace_size(const dcs_sector *sector, int vec_dtype, int steps, int reorth,
+                               int want_vector, size_t *bytes);
+
+/*
+ * Lanczos on the sector with FP64 scalars and vectors of vec_dtype:
+ *   v_0 = v0/|v0|;  w = H v_j - beta_{j-1} v_{j-1};  alpha_j = v_j.w;
+ *   w -= alpha_j v_j;  re-orthogonalise (reorth);  beta_j = |w|;  v_{j+1} = w/beta_j.
+ * Dot products, norms and the re-orthogonalisation coefficients are
+ * accumulated in FP64 on the device; vectors are stored in vec_dtype.
+ * Stops early when beta_j <= 1e-12 max_i(|alpha_i|, beta_i) or after D steps.
+ * The Ritz values (eigenvalues of the tridiagonal T, Sturm bisection in FP64 on
+ * the device) are returned in increasing order.
+ *
+ * d_v0: start vector (D elements, vec_dtype, device; not modified).
+ * h_alpha[steps], h_beta[steps]: host outputs (beta has steps_done-1 valid entries).
+ * h_steps_done: host output.  h_eig[num_eig]: the num_eig lowest Ritz values.
+ * d_ground_vec: if not NULL, receives the normalised Ritz vector of the lowest
+ * Ritz value (vec_dtype, D elements); it is assembled from the stored basis
+ * (DCS_REORTH_FULL) or by repeating the recurrence (other modes).
+ * Synchronises `stream` before returning (the outputs are on the host).
+ */
+int dcs_lanczos(const dcs_sector *sector, const dcs_terms *terms, const double *d_jxy,
+                const double *d_jz, const double *d_h, int vec_dtype, int steps, int reorth,
+                const void *d_v0, double *h_alpha, double *h_beta, int *h_steps_done,
+                int num_eig, double *h_eig, void *d_ground_vec, void *d_workspace,
+                size_t workspace_bytes, void *stream);
+
+/*
+ * Eigenvalues of a symmetric tridiagonal matrix (diagonal h_alpha[m],
+ * off-diagonal h_beta[m-1]) by Sturm-sequence bisection in FP64 on the
+ * device; h_eig receives the num_eig lowest in increasing order.  Exposed so
+ * the eigensolve step of dcs_lanczos can be checked on its own.
+ */
+int dcs_tridiag_eigvals(const double *h_alpha, const double *h_beta, int m, int num_eig,
+                        double *h_eig, int device);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCS_H */

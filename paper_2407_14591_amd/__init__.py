@@ -1,0 +1,292 @@
+"""MI355X-native divide-and-conquer sector index and matrix-free H*x.
+
+Python front of libdcs.so (C ABI in include/dcs.h).  PyTorch supplies device
+memory and the current stream; every step of the computation runs in the
+library's HIP kernels.  The names follow the ABI: ``sector_create`` ->
+:class:`Sector`, ``rank`` / ``unrank`` / ``enumerate`` -> its methods,
+``terms_create`` -> :class:`Terms`, ``hamiltonian_apply``,
+``hamiltonian_apply_adjoint``, ``plan_create`` / ``plan_apply`` -> :class:`Plan`,
+``lanczos``.
+
+Method: R. Schaefer and D. J. Luitz, arXiv:2407.14591 (DanceQ).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib
+from ._lib import (DCS_F32, DCS_F64, DCS_INVALID_INDEX, DCS_REORTH_FULL, DCS_REORTH_LOCAL,
+                   DCS_REORTH_NONE, DcsError, call)
+
+__all__ = ["Sector", "Terms", "Plan", "hamiltonian_apply", "hamiltonian_apply_adjoint",
+           "HApply", "lanczos", "tridiag_eigvals", "DcsError", "DCS_INVALID_INDEX",
+           "library_path"]
+
+
+def library_path() -> str:
+    _lib.lib()
+    return _lib.LIB_PATH
+
+
+def _stream(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(None)
+
+
+def _dtype_code(dt) -> int:
+    if dt == torch.float32:
+        return DCS_F32
+    if dt == torch.float64:
+        return DCS_F64
+    raise TypeError(f"vectors must be float32 or float64, not {dt}")
+
+
+def _check_dev(t, device, name, dtype=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{name} must be a CUDA tensor on device {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype not in (dtype if isinstance(dtype, tuple) else (dtype,)):
+        raise TypeError(f"{name} has dtype {t.dtype}")
+
+
+class Sector:
+    """One particle-number sector with its divide-and-conquer index (dcs_sector_create)."""
+
+    def __init__(self, L: int, n: int, Q: int = 2, split=None, device: int = 0):
+        self._h = C.c_void_p()
+        if split is None:
+            call("dcs_sector_create", L, n, Q, 0, None, device, C.byref(self._h))
+        else:
+            arr = (C.c_int * len(split))(*split)
+            call("dcs_sector_create", L, n, Q, len(split), arr, device, C.byref(self._h))
+        self.L, self.n, self.Q, self.device = L, n, Q, device
+        d = C.c_uint64()
+        call("dcs_sector_dim", self._h, C.byref(d))
+        self.dim = int(d.value)
+        num = C.c_int()
+        sizes = (C.c_int * 64)()
+        call("dcs_sector_split", self._h, C.byref(num), sizes)
+        self.split = [sizes[i] for i in range(num.value)]
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.lib().dcs_sector_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _counter(self, count_invalid):
+        return torch.zeros(1, dtype=torch.int64, device=f"cuda:{self.device}") if count_invalid else None
+
+    def rank(self, states: torch.Tensor, out: torch.Tensor | None = None, count_invalid=False):
+        """Indices of packed states (int64/uint64 tensor); invalid -> DCS_INVALID_INDEX."""
+        _check_dev(states, self.device, "states", (torch.int64, torch.uint64))
+        out = torch.empty_like(states) if out is None else out
+        cnt = self._counter(count_invalid)
+        call("dcs_rank", self._h, _ptr(states), _ptr(out), states.numel(), _ptr(cnt),
+             _stream(self.device))
+        return (out, cnt) if count_invalid else out
+
+    def unrank(self, idx: torch.Tensor, out: torch.Tensor | None = None, count_invalid=False):
+        _check_dev(idx, self.device, "idx", (torch.int64, torch.uint64))
+        out = torch.empty_like(idx) if out is None else out
+        cnt = self._counter(count_invalid)
+        call("dcs_unrank", self._h, _ptr(idx), _ptr(out), idx.numel(), _ptr(cnt),
+             _stream(self.device))
+        return (out, cnt) if count_invalid else out
+
+    def enumerate(self, first: int, count: int, out: torch.Tensor | None = None):
+        out = torch.empty(count, dtype=torch.int64, device=f"cuda:{self.device}") if out is None else out
+        call("dcs_enumerate", self._h, first, count, _ptr(out), _stream(self.device))
+        return out
+
+
+class Terms:
+    """Bond topology of an XXZ Hamiltonian (dcs_terms_create)."""
+
+    def __init__(self, bonds):
+        self.bonds = [(int(i), int(j)) for i, j in bonds]
+        nb = len(self.bonds)
+        si = (C.c_int32 * max(nb, 1))(*[b[0] for b in self.bonds])
+        sj = (C.c_int32 * max(nb, 1))(*[b[1] for b in self.bonds])
+        self._h = C.c_void_p()
+        call("dcs_terms_create", nb, si, sj, C.byref(self._h))
+        self.num_bonds = nb
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.lib().dcs_terms_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _couplings(sector, terms, jxy, jz, h):
+    for name, c, n in (("jxy", jxy, terms.num_bonds), ("jz", jz, terms.num_bonds)):
+        _check_dev(c, sector.device, name, torch.float64)
+        if c.numel() != n:
+            raise ValueError(f"{name} has {c.numel()} entries, expected {n}")
+    if h is not None:
+        _check_dev(h, sector.device, "h", torch.float64)
+        if h.numel() != sector.L:
+            raise ValueError("h must hold one field per site")
+
+
+def hamiltonian_apply(sector: Sector, terms: Terms, jxy, jz, x, h=None, out=None):
+    """Y = H X (dcs_hamiltonian_apply); X is [dim] or [dim, k] float32/float64."""
+    _couplings(sector, terms, jxy, jz, h)
+    _check_dev(x, sector.device, "x", (torch.float32, torch.float64))
+    k = 1 if x.dim() == 1 else x.shape[1]
+    if x.shape[0] != sector.dim:
+        raise ValueError(f"x has {x.shape[0]} rows, sector dimension is {sector.dim}")
+    out = torch.empty_like(x) if out is None else out
+    _check_dev(out, sector.device, "out", x.dtype)
+    call("dcs_hamiltonian_apply", sector._h, terms._h, _ptr(jxy), _ptr(jz), _ptr(h),
+         _dtype_code(x.dtype), k, _ptr(x), _ptr(out), _stream(sector.device))
+    return out
+
+
+def hamiltonian_apply_adjoint(sector: Sector, terms: Terms, jxy, jz, x, g, h=None,
+                              want_grad_x=True, want_grad_h=False):
+    """(H g, dL/dJxy, dL/dJz, dL/dh) for y = H x and dL/dy = g (dcs_hamiltonian_apply_adjoint)."""
+    _couplings(sector, terms, jxy, jz, h)
+    _check_dev(x, sector.device, "x", (torch.float32, torch.float64))
+    _check_dev(g, sector.device, "g", x.dtype)
+    dev = x.device
+    gx = torch.empty_like(x) if want_grad_x else None
+    gj = torch.empty(terms.num_bonds, dtype=torch.float64, device=dev)
+    gz = torch.empty(terms.num_bonds, dtype=torch.float64, device=dev)
+    gh = torch.empty(sector.L, dtype=torch.float64, device=dev) if want_grad_h else None
+    nbytes = C.c_size_t()
+    call("dcs_adjoint_workspace_size", sector._h, terms._h, C.byref(nbytes))
+    ws = torch.empty(max(nbytes.value, 8), dtype=torch.uint8, device=dev)
+    call("dcs_hamiltonian_apply_adjoint", sector._h, terms._h, _ptr(jxy), _ptr(jz), _ptr(h),
+         _dtype_code(x.dtype), _ptr(x), _ptr(g), _ptr(gx), _ptr(gj), _ptr(gz), _ptr(gh), _ptr(ws),
+         nbytes.value, _stream(sector.device))
+    return gx, gj, gz, gh
+
+
+class HApply(torch.autograd.Function):
+    """y = H(jxy, jz) x with the fused hand-written backward.
+
+    backward: grad_x = H g (H is real symmetric), grad_jxy_b = g . (A_b x),
+    grad_jz_b = g . (Z_b x), all from one launch that ranks every reached state once.
+    """
+
+    @staticmethod
+    def forward(ctx, x, jxy, jz, sector, terms):
+        ctx.sector, ctx.terms = sector, terms
+        ctx.save_for_backward(x, jxy, jz)
+        return hamiltonian_apply(sector, terms, jxy.detach().contiguous(),
+                                 jz.detach().contiguous(), x.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        x, jxy, jz = ctx.saved_tensors
+        gx, gj, gz, _ = hamiltonian_apply_adjoint(ctx.sector, ctx.terms, jxy.detach().contiguous(),
+                                                  jz.detach().contiguous(),
+                                                  x.detach().contiguous(), g.contiguous(),
+                                                  want_grad_x=ctx.needs_input_grad[0])
+        return gx, gj, gz, None, None
+
+
+def lanczos(sector: Sector, terms: Terms, jxy, jz, v0, steps: int, reorth="auto",
+            num_eig: int = 1, want_vector=False, h=None, hbm_fraction: float = 0.5):
+    """Lanczos with FP64 scalars (dcs_lanczos).  Returns a dict with alpha, beta,
+    steps_done, eig (lowest num_eig Ritz values), reorth mode and the ground vector."""
+    _couplings(sector, terms, jxy, jz, h)
+    _check_dev(v0, sector.device, "v0", (torch.float32, torch.float64))
+    dtype = _dtype_code(v0.dtype)
+    modes = {"none": DCS_REORTH_NONE, "local": DCS_REORTH_LOCAL, "full": DCS_REORTH_FULL}
+    if reorth == "auto":
+        # full re-orthogonalisation when the stored basis fits in the given share of free HBM
+        free, _ = torch.cuda.mem_get_info(sector.device)
+        need = C.c_size_t()
+        call("dcs_lanczos_workspace_size", sector._h, dtype, steps, DCS_REORTH_FULL,
+             int(want_vector), C.byref(need))
+        reorth = "full" if need.value <= hbm_fraction * free else "local"
+    mode = modes[reorth]
+    nbytes = C.c_size_t()
+    call("dcs_lanczos_workspace_size", sector._h, dtype, steps, mode, int(want_vector),
+         C.byref(nbytes))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=v0.device)
+    alpha = (C.c_double * steps)()
+    beta = (C.c_double * steps)()
+    done = C.c_int()
+    ne = max(1, num_eig)
+    eig = (C.c_double * ne)()
+    psi = torch.empty_like(v0) if want_vector else None
+    call("dcs_lanczos", sector._h, terms._h, _ptr(jxy), _ptr(jz), _ptr(h), dtype, steps, mode,
+         _ptr(v0), alpha, beta, C.byref(done), ne, eig, _ptr(psi), _ptr(ws), nbytes.value,
+         _stream(sector.device))
+    m = done.value
+    return {"alpha": [alpha[i] for i in range(m)], "beta": [beta[i] for i in range(max(m - 1, 0))],
+            "steps_done": m, "eig": [eig[i] for i in range(min(ne, m))], "reorth": reorth,
+            "vector": psi}
+
+
+def tridiag_eigvals(alpha, beta, num: int, device: int = 0):
+    m = len(alpha)
+    a = (C.c_double * m)(*alpha)
+    b = (C.c_double * max(m - 1, 1))(*(list(beta) or [0.0]))
+    out = (C.c_double * num)()
+    call("dcs_tridiag_eigvals", a, b, m, num, out, device)
+    return [out[i] for i in range(num)]
+
+
+class Plan:
+    """Many sectors applied in one launch (dcs_plan_create / dcs_plan_apply)."""
+
+    def __init__(self, items):
+        """items: list of (Sector, Terms, jxy, jz) with jxy, jz float64 device tensors."""
+        self.items = list(items)
+        n = len(self.items)
+        S = (C.c_void_p * n)(*[it[0]._h.value for it in self.items])
+        T = (C.c_void_p * n)(*[it[1]._h.value for it in self.items])
+        J = (C.c_void_p * n)(*[it[2].data_ptr() for it in self.items])
+        Z = (C.c_void_p * n)(*[it[3].data_ptr() for it in self.items])
+        for s, t, j, z in self.items:
+            _couplings(s, t, j, z, None)
+        self._h = C.c_void_p()
+        call("dcs_plan_create", n, S, T, J, Z, C.byref(self._h))
+        self.device = self.items[0][0].device if n else 0
+
+    def apply(self, xs, ys=None):
+        n = len(self.items)
+        if len(xs) != n:
+            raise ValueError("one vector per sector")
+        dt = xs[0].dtype
+        for (s, _, _, _), x in zip(self.items, xs):
+            _check_dev(x, s.device, "x", dt)
+            if x.numel() != s.dim:
+                raise ValueError("vector length differs from its sector dimension")
+        ys = [torch.empty_like(x) for x in xs] if ys is None else ys
+        X = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+        Y = (C.c_void_p * n)(*[y.data_ptr() for y in ys])
+        call("dcs_plan_apply", self._h, _dtype_code(dt), X, Y, _stream(self.device))
+        return ys
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.lib().dcs_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,164 @@
+// Internal declarations of the dcs library (not part of the ABI).
+//
+// Device data of a sector, built on the host by sector.cpp:
+//
+//  * fused contribution table ("c-table"), one row per (subsystem k, lambda):
+//      C_k[lambda][w] = offset_k(n(w), lambda) + stride_k(n(w), lambda) * index_k(w)
+//    for every word w of P_k (eq. ck with eq. offset / eq. stride), or the
+//    sentinel kBad when w has a digit >= Q or its digit sum n(w) cannot occur
+//    with lambda particles to the left.  The last subsystem has offset 0 and
+//    stride 1 (its digit sum is fixed by lambda), so it keeps a single row with
+//    the local index; rank checks its digit sum separately.  The paper keeps offsets, strides and
+//    the local table apart and multiplies at lookup time; for two subsystems
+//    it folds c_0 into P_0's table (Sec. 3.3.1).  Adding lambda as a table
+//    dimension applies that folding to every subsystem: a rank becomes N
+//    table reads and N-1 adds, index(s) = sum_k C_k[lambda_k][w_k].  The rows
+//    cover only the feasible lambda of each subsystem; for the workloads here
+//    the whole table is 9..64 KiB and is staged in LDS.
+//  * decode table per (k, lambda, m): offset_k(m, lambda), stride_k(m, lambda)
+//    and a float reciprocal of the stride (the quotient index_k is below
+//    2^14, so one float multiply plus a one-step correction is exact);
+//  * inverse local tables: the words of P_k listed by (digit sum, index).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "dcs.h"
+
+namespace dcs {
+
+constexpr int kMaxSub = DCS_MAX_SUBSYSTEMS;
+constexpr int kMaxSites = DCS_MAX_SITES;
+constexpr int kMaxBonds = DCS_MAX_BONDS;
+constexpr int kMaxWordBits = 14;
+constexpr size_t kLdsTableBudget = 112 * 1024;
+
+template <typename IdxT>
+struct Bad;
+template <>
+struct Bad<uint32_t> {
+    static constexpr uint32_t value = 0xFFFFFFFFu;
+};
+template <>
+struct Bad<uint64_t> {
+    static constexpr uint64_t value = ~0ull;
+};
+
+// Everything a kernel needs to know about a sector; passed by value.
+struct SectorDesc {
+    uint64_t dim;
+    int Q, nb, L, n, N;
+    int total_bits;                 // nb * L
+    int shift[kMaxSub];             // bit position of P_k's word in the state
+    int wbits[kMaxSub];             // nb * L_k
+    int gamma[kMaxSub];             // sites to the right of P_k
+    int mk[kMaxSub];                // (Q-1) * L_k
+    int lam_lo[kMaxSub], lam_hi[kMaxSub];
+    uint32_t ctab_row0[kMaxSub];    // entry of C_k[lam_lo[k]][0]
+    uint32_t ctab_rowlen[kMaxSub];  // entries per lambda row: 2^wbits, 0 for the last subsystem
+    uint32_t ctab_entries;
+    uint32_t dec_row0[kMaxSub];     // entry of (k, lam_lo[k], m=0); rows of mk[k]+1
+    uint32_t dec_entries;
+    uint32_t inv_start0[kMaxSub];   // entry of inv_start for (k, m=0); mk[k]+2 per k
+    uint32_t inv_start_entries;
+    uint32_t inv_entries;
+    uint32_t field_mask[4];         // bit t of every site field of a word (digit sums)
+    // byte offsets of the table arrays inside the sector's device blob
+    uint32_t lay_ctab, lay_doff, lay_dstr, lay_drcp, lay_invs, lay_inv, lay_bytes;
+    uint8_t site_sub[kMaxSites];    // subsystem of each site
+    uint8_t site_bit[kMaxSites];    // bit of the site's field inside its subsystem word
+};
+
+// Device-side arrays of one sector (one allocation, see sector.cpp for layout).
+struct SectorDev {
+    void *base = nullptr;
+    size_t bytes = 0;
+    size_t ctab_off = 0, dec_off_off = 0, dec_str_off = 0, dec_rcp_off = 0, inv_off = 0,
+           inv_start_off = 0;
+    // bytes the H*x kernels stage in LDS (c-table + decode + inverse tables)
+    size_t lds_bytes = 0;
+};
+
+}  // namespace dcs
+
+struct dcs_sector {
+    int device;
+    int split[dcs::kMaxSub];
+    bool wide;  // 64-bit indices (dim >= 2^32)
+    dcs::SectorDesc desc;
+    dcs::SectorDev dev;
+};
+
+struct dcs_terms {
+    int num_bonds;
+    int max_site;
+    int32_t si[dcs::kMaxBonds];
+    int32_t sj[dcs::kMaxBonds];
+};
+
+namespace dcs {
+
+// error state (capi.cpp)
+int set_error(int code, const char *fmt, ...);
+int check_hip(hipError_t e, const char *what);
+void clear_error();
+
+// Bond plan of one (sector, terms) pair: bonds sorted into classes (a, b) of
+// the subsystems of their two sites, a <= b, with i in P_a and j in P_b.
+struct BondPlan {
+    int nbonds;
+    int nclasses;                  // kMaxSub * (kMaxSub + 1) / 2
+    uint16_t cls_beg[kMaxSub * (kMaxSub + 1) / 2 + 1];
+    uint32_t pos[kMaxBonds];       // site_bit(i) | site_bit(j) << 8 | orig << 16
+    int16_t site_i[kMaxBonds];     // for the kernels that need sites
+    int16_t site_j[kMaxBonds];
+};
+
+inline int class_id(int a, int b, int nmax) {  // a <= b < nmax
+    return a * nmax - a * (a - 1) / 2 + (b - a);
+}
+
+int make_bond_plan(const dcs_sector *s, const dcs_terms *t, int nmax, BondPlan *plan);
+
+// kernels launchers (index_kernels.hip, hx_kernels.hip, lanczos.hip)
+int launch_rank(const dcs_sector *s, const uint64_t *st, uint64_t *idx, size_t count,
+                uint64_t *nbad, hipStream_t stream);
+int launch_unrank(const dcs_sector *s, const uint64_t *idx, uint64_t *st, size_t count,
+                  uint64_t *nbad, hipStream_t stream);
+int launch_enumerate(const dcs_sector *s, uint64_t first, size_t count, uint64_t *st,
+                     hipStream_t stream);
+int launch_hx(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
+              const double *h, int dtype, int k, const void *x, void *y, hipStream_t stream);
+size_t adjoint_ws_bytes(const dcs_sector *s, const dcs_terms *t);
+int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
+                   const double *h, int dtype, const void *x, const void *g, void *gx,
+                   double *gjxy, double *gjz, double *gh, void *ws, size_t ws_bytes,
+                   hipStream_t stream);
+
+int device_cu_count(int device);
+
+// Allow a kernel more than the default 64 KiB of dynamic LDS when it needs it.
+template <typename KernelT>
+inline int ensure_lds(KernelT kernel, size_t bytes) {
+    if (bytes <= 64 * 1024) return DCS_OK;
+    return check_hip(hipFuncSetAttribute((const void *)kernel,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes),
+                     "hipFuncSetAttribute(max dynamic LDS)");
+}
+
+// Makes `dev` current for the lifetime of the object and restores the caller's device.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace dcs

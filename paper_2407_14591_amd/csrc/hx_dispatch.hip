@@ -1,0 +1,109 @@
+// Dispatch of the matrix-free H*x and adjoint launchers by index type, value type,
+// column count and subsystem bound; the instantiations live in hx_f*_k*.hip and
+// hx_adjoint_f*.hip so they compile in parallel.
+#include "hx_impl.h"
+
+namespace dcs {
+namespace hx {
+#define DCS_HX_EXTERN(IDX, T, K, NMAX) \
+    extern template int launch_hx_t<IDX, T, K, NMAX>(const dcs_sector *, HxParams &, hipStream_t);
+#define DCS_HX_EXTERN_ALL(T, K)           \
+    DCS_HX_EXTERN(uint32_t, T, K, 4)      \
+    DCS_HX_EXTERN(uint32_t, T, K, 8)      \
+    DCS_HX_EXTERN(uint64_t, T, K, 4)      \
+    DCS_HX_EXTERN(uint64_t, T, K, 8)
+DCS_HX_EXTERN_ALL(float, 1)
+DCS_HX_EXTERN_ALL(float, 2)
+DCS_HX_EXTERN_ALL(float, 4)
+DCS_HX_EXTERN_ALL(float, 8)
+DCS_HX_EXTERN_ALL(double, 1)
+DCS_HX_EXTERN_ALL(double, 2)
+DCS_HX_EXTERN_ALL(double, 4)
+DCS_HX_EXTERN_ALL(double, 8)
+#define DCS_ADJ_EXTERN(IDX, T, NMAX)                                                         \
+    extern template int launch_adj_t<IDX, T, NMAX>(const dcs_sector *, HxParams &, double *, \
+                                                   double *, double *, hipStream_t);
+DCS_ADJ_EXTERN(uint32_t, float, 4)
+DCS_ADJ_EXTERN(uint32_t, float, 8)
+DCS_ADJ_EXTERN(uint64_t, float, 4)
+DCS_ADJ_EXTERN(uint64_t, float, 8)
+DCS_ADJ_EXTERN(uint32_t, double, 4)
+DCS_ADJ_EXTERN(uint32_t, double, 8)
+DCS_ADJ_EXTERN(uint64_t, double, 4)
+DCS_ADJ_EXTERN(uint64_t, double, 8)
+
+namespace {
+
+template <typename IdxT, typename T, int NMAX>
+int launch_hx_k(const dcs_sector *s, HxParams &P, int k, hipStream_t stream) {
+    switch (k) {
+        case 1: return launch_hx_t<IdxT, T, 1, NMAX>(s, P, stream);
+        case 2: return launch_hx_t<IdxT, T, 2, NMAX>(s, P, stream);
+        case 4: return launch_hx_t<IdxT, T, 4, NMAX>(s, P, stream);
+        default: return launch_hx_t<IdxT, T, 8, NMAX>(s, P, stream);
+    }
+}
+
+template <typename IdxT, int NMAX>
+int launch_hx_d(const dcs_sector *s, HxParams &P, int dtype, int k, hipStream_t stream) {
+    if (dtype == DCS_F32) return launch_hx_k<IdxT, float, NMAX>(s, P, k, stream);
+    return launch_hx_k<IdxT, double, NMAX>(s, P, k, stream);
+}
+
+int pick_nmax(const dcs_sector *s) { return s->desc.N <= 4 ? 4 : 8; }
+
+}  // namespace
+}  // namespace hx
+
+using namespace hx;
+
+int launch_hx(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
+              const double *h, int dtype, int k, const void *x, void *y, hipStream_t stream) {
+    DeviceGuard dg(s->device);
+    const int nmax = pick_nmax(s);
+    HxParams P;
+    if (int r = fill_params(s, t, nmax, jxy, jz, h, P)) return r;
+    P.x = x;
+    P.y = y;
+    if (s->wide)
+        return nmax == 4 ? launch_hx_d<uint64_t, 4>(s, P, dtype, k, stream)
+                         : launch_hx_d<uint64_t, 8>(s, P, dtype, k, stream);
+    return nmax == 4 ? launch_hx_d<uint32_t, 4>(s, P, dtype, k, stream)
+                     : launch_hx_d<uint32_t, 8>(s, P, dtype, k, stream);
+}
+
+size_t adjoint_ws_bytes(const dcs_sector *s, const dcs_terms *t) {
+    const size_t lds = s->desc.lay_bytes + coeff_lds_bytes<double>() +
+                       (size_t)(kHxThreads / 64) * (2 * t->num_bonds + s->desc.L) * sizeof(double);
+    const Grid g = plan_grid(s, lds);
+    return (size_t)g.wgs * (2 * t->num_bonds + s->desc.L) * sizeof(double);
+}
+
+int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
+                   const double *h, int dtype, const void *x, const void *g, void *gx,
+                   double *gjxy, double *gjz, double *gh, void *ws, size_t ws_bytes,
+                   hipStream_t stream) {
+    DeviceGuard dg(s->device);
+    const int nmax = pick_nmax(s);
+    HxParams P;
+    if (int r = fill_params(s, t, nmax, jxy, jz, h, P)) return r;
+    P.x = x;
+    P.g = g;
+    P.gx = gx;
+    P.partials = (double *)ws;
+    (void)ws_bytes;
+    if (s->wide) {
+        if (dtype == DCS_F32)
+            return nmax == 4 ? launch_adj_t<uint64_t, float, 4>(s, P, gjxy, gjz, gh, stream)
+                             : launch_adj_t<uint64_t, float, 8>(s, P, gjxy, gjz, gh, stream);
+        return nmax == 4 ? launch_adj_t<uint64_t, double, 4>(s, P, gjxy, gjz, gh, stream)
+                         : launch_adj_t<uint64_t, double, 8>(s, P, gjxy, gjz, gh, stream);
+    }
+    if (dtype == DCS_F32)
+        return nmax == 4 ? launch_adj_t<uint32_t, float, 4>(s, P, gjxy, gjz, gh, stream)
+                         : launch_adj_t<uint32_t, float, 8>(s, P, gjxy, gjz, gh, stream);
+    return nmax == 4 ? launch_adj_t<uint32_t, double, 4>(s, P, gjxy, gjz, gh, stream)
+                     : launch_adj_t<uint32_t, double, 8>(s, P, gjxy, gjz, gh, stream);
+}
+
+}  // namespace dcs

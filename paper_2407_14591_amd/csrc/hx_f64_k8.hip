@@ -1,0 +1,11 @@
+// Instantiations of the H*x launcher for double vectors with k=8 columns.
+#include "hx_impl.h"
+
+namespace dcs {
+namespace hx {
+template int launch_hx_t<uint32_t, double, 8, 4>(const dcs_sector *, HxParams &, hipStream_t);
+template int launch_hx_t<uint32_t, double, 8, 8>(const dcs_sector *, HxParams &, hipStream_t);
+template int launch_hx_t<uint64_t, double, 8, 4>(const dcs_sector *, HxParams &, hipStream_t);
+template int launch_hx_t<uint64_t, double, 8, 8>(const dcs_sector *, HxParams &, hipStream_t);
+}  // namespace hx
+}  // namespace dcs

@@ -1,0 +1,554 @@
+// Matrix-free Y = H X on one sector (Sec. 2.2 and 4.4 of arXiv:2407.14591),
+// and its fused adjoint.
+//
+// Pull formulation: one thread owns one output row.  It decodes its row's
+// state (Alg. iii, keeping the subsystem words w_k, lambda_k and the
+// contributions c_k), applies the XXZ bond terms, and ranks each reached
+// state incrementally: a hop between sites of P_a and P_b (a <= b) changes
+// only w_a, w_b and lambda_k for a < k <= b, so by eq. index
+//     col = row - sum_{k=a..b} c_k + sum_{k=a..b} C_k[lambda'_k][w'_k]
+// i.e. 1 table read for a hop inside one subsystem, b-a+1 otherwise.  The
+// paper's workers walk their rows with increment and rank every reached
+// state in full (Sec. 2.2, Alg. i-ii); on the GPU each thread decodes its own
+// row and only the touched terms are re-read.
+//
+// Launch shape: persistent workgroups (8 waves) each own one contiguous chunk
+// of rows, walked in tiles of 64 consecutive rows per wave; chunks are
+// assigned so that the workgroups of one XCD (dispatch order blockIdx % 8)
+// cover one contiguous eighth of the rows and share that XCD's L2.  The
+// sector tables and the per-bond coefficients sit in LDS.  Bonds are grouped
+// on the host into classes (a, b) so the subsystem indices are compile-time
+// constants inside the unrolled class loops (no dynamic register indexing).
+// Y is written exactly once per element, with no atomics.
+#pragma once
+
+#include <cstring>
+
+#include "device_common.h"
+
+namespace dcs {
+namespace hx {
+
+constexpr int kHxThreads = 512;
+constexpr int kMaxClasses = kMaxSub * (kMaxSub + 1) / 2;
+
+struct HxParams {
+    SectorDesc sd;
+    const char *blob;
+    const void *x;
+    void *y;
+    const void *g;      // adjoint: upstream gradient
+    void *gx;           // adjoint: H g
+    double *partials;   // adjoint: [num_wgs][2*nbonds + L]
+    const double *jxy, *jz, *h;
+    uint64_t rows_per_wg;
+    int nbonds;
+    int xcd_groups;     // workgroups per XCD when the grid is a multiple of 8, else 0
+    uint16_t cls_beg[kMaxClasses + 1];
+    uint32_t pos[kMaxBonds];
+};
+
+template <typename T, int K>
+struct Acc {
+    T v[K];
+};
+
+template <typename T, int K>
+__device__ __forceinline__ void gather_fma(Acc<T, K> &acc, T amp, const T *__restrict__ x,
+                                           uint64_t col) {
+    const T *p = x + col * K;
+    if constexpr (K == 1) {
+        acc.v[0] += amp * p[0];
+    } else if constexpr (sizeof(T) * K % 16 == 0) {
+        constexpr int V = 16 / sizeof(T);
+#pragma unroll
+        for (int c = 0; c < K; c += V) {
+            typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
+            const vec_t v = *reinterpret_cast<const vec_t *>(p + c);
+#pragma unroll
+            for (int e = 0; e < V; ++e) acc.v[c + e] += amp * v[e];
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < K; ++c) acc.v[c] += amp * p[c];
+    }
+}
+
+__device__ __forceinline__ uint32_t xcd_chunk(int xcd_groups) {
+    const uint32_t b = blockIdx.x;
+    if (!xcd_groups) return b;
+    return (b & 7u) * (uint32_t)xcd_groups + (b >> 3);
+}
+
+// Per-row state kept by a thread: subsystem words, the LDS row of C_k[lambda_k],
+// and the contributions c_k of the row.
+template <typename IdxT, int NMAX>
+struct RowState {
+    uint32_t w[NMAX];
+    uint32_t rb[NMAX];
+    IdxT c[NMAX];
+    uint64_t s;
+};
+
+template <typename IdxT, int NMAX>
+__device__ __forceinline__ void decode_row(const SectorDesc &sd, const Tables<IdxT> &T, IdxT row,
+                                           RowState<IdxT, NMAX> &r) {
+    int lam[NMAX];
+    r.s = unrank_state<IdxT, NMAX>(sd, T, row, r.w, lam, r.c);
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k)
+        r.rb[k] = (k < sd.N) ? sd.ctab_row0[k] + (uint32_t)(lam[k] - sd.lam_lo[k]) * sd.ctab_rowlen[k]
+                             : 0u;
+}
+
+// Column of the state reached by changing w_a -> wa, w_b -> wb and lambda_k by dl
+// for a < k <= b (one table row per unit of lambda; the last subsystem has one row).
+template <typename IdxT, int NMAX, int A, int B>
+__device__ __forceinline__ IdxT hop_col(const SectorDesc &sd, const Tables<IdxT> &T,
+                                        const RowState<IdxT, NMAX> &r, IdxT row, uint32_t wa,
+                                        uint32_t wb, int dl) {
+    if constexpr (A == B) {
+        return row - r.c[A] + T.ctab[r.rb[A] + wa];
+    } else {
+        IdxT col = row - r.c[A] + T.ctab[r.rb[A] + wa];
+#pragma unroll
+        for (int k = A + 1; k < B; ++k)
+            col += T.ctab[r.rb[k] + (uint32_t)(dl * (int)sd.ctab_rowlen[k]) + r.w[k]] - r.c[k];
+        col += T.ctab[r.rb[B] + (uint32_t)(dl * (int)sd.ctab_rowlen[B]) + wb] - r.c[B];
+        return col;
+    }
+}
+
+// One bond class (A, B): applies every bond of the class to the row.
+template <typename IdxT, typename T, int K, int NMAX, bool Q2, int A, int B, typename PT>
+__device__ __forceinline__ void apply_class(const PT &P, const SectorDesc &sd,
+                                            const Tables<IdxT> &Tb, const RowState<IdxT, NMAX> &r,
+                                            IdxT row, const T *__restrict__ x, const T *bamp,
+                                            const T *bjz, const T *ladder, Acc<T, K> &acc, T &diag) {
+    if constexpr (A >= NMAX || B >= NMAX) {
+        return;
+    } else {
+        const int cls = A * NMAX - A * (A - 1) / 2 + (B - A);
+        const int beg = P.cls_beg[cls], end = P.cls_beg[cls + 1];
+        for (int t = beg; t < end; ++t) {
+            const uint32_t pos = P.pos[t];
+            const uint32_t pil = pos & 0xFFu, pjl = (pos >> 8) & 0xFFu;
+            if constexpr (Q2) {
+                const uint32_t bi = (r.w[A] >> pil) & 1u, bj = (r.w[B] >> pjl) & 1u;
+                const T jz = bjz[t];
+                diag += (bi == bj) ? jz : -jz;
+                if (bi != bj) {
+                    IdxT col;
+                    if constexpr (A == B) {
+                        col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row,
+                                                        r.w[A] ^ ((1u << pil) | (1u << pjl)), 0, 0);
+                    } else {
+                        col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, r.w[A] ^ (1u << pil),
+                                                        r.w[B] ^ (1u << pjl), bi ? -1 : 1);
+                    }
+                    gather_fma<T, K>(acc, bamp[t], x, (uint64_t)col);
+                }
+            } else {
+                const uint32_t dm = (1u << sd.nb) - 1u;
+                const int Qm1 = sd.Q - 1;
+                const int di = (int)((r.w[A] >> pil) & dm), dj = (int)((r.w[B] >> pjl) & dm);
+                const T *up = ladder, *dn = ladder + 16, *mz = ladder + 32;
+                diag += bjz[t] * mz[di] * mz[dj];
+                if (di < Qm1 && dj > 0) {  // S+_i S-_j
+                    const uint32_t wa = r.w[A] + (1u << pil);
+                    IdxT col;
+                    if constexpr (A == B)
+                        col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa - (1u << pjl), 0, 0);
+                    else
+                        col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa, r.w[B] - (1u << pjl), 1);
+                    gather_fma<T, K>(acc, bamp[t] * up[di] * dn[dj], x, (uint64_t)col);
+                }
+                if (di > 0 && dj < Qm1) {  // S-_i S+_j
+                    const uint32_t wa = r.w[A] - (1u << pil);
+                    IdxT col;
+                    if constexpr (A == B)
+                        col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa + (1u << pjl), 0, 0);
+                    else
+                        col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa, r.w[B] + (1u << pjl), -1);
+                    gather_fma<T, K>(acc, bamp[t] * dn[di] * up[dj], x, (uint64_t)col);
+                }
+            }
+        }
+    }
+}
+
+template <typename IdxT, typename T, int K, int NMAX, bool Q2, int A, int B>
+struct ClassLoop {
+    template <typename PT>
+    __device__ __forceinline__ static void run(const PT &P, const SectorDesc &sd,
+                                               const Tables<IdxT> &Tb,
+                                               const RowState<IdxT, NMAX> &r, IdxT row,
+                                               const T *__restrict__ x, const T *bamp,
+                                               const T *bjz, const T *ladder, Acc<T, K> &acc,
+                                               T &diag) {
+        if constexpr (A < NMAX) {
+            if constexpr (B < NMAX) {
+                if (B < sd.N)
+                    apply_class<IdxT, T, K, NMAX, Q2, A, B>(P, sd, Tb, r, row, x, bamp, bjz, ladder,
+                                                            acc, diag);
+                ClassLoop<IdxT, T, K, NMAX, Q2, A, B + 1>::run(P, sd, Tb, r, row, x, bamp, bjz,
+                                                               ladder, acc, diag);
+            } else {
+                ClassLoop<IdxT, T, K, NMAX, Q2, A + 1, A + 1>::run(P, sd, Tb, r, row, x, bamp, bjz,
+                                                                   ladder, acc, diag);
+            }
+        }
+    }
+};
+
+// Stage per-bond coefficients (in plan order) and the ladder factors into LDS.
+template <typename T, bool Q2, typename PT>
+__device__ __forceinline__ void stage_coefficients(const PT &P, const SectorDesc &sd, T *bamp,
+                                                   T *bjz, T *ladder, T *hf) {
+    for (int t = threadIdx.x; t < P.nbonds; t += blockDim.x) {
+        const int orig = (int)(P.pos[t] >> 16);
+        bamp[t] = (T)(0.5 * P.jxy[orig]);
+        bjz[t] = Q2 ? (T)(0.25 * P.jz[orig]) : (T)P.jz[orig];
+    }
+    if (threadIdx.x < 16) {
+        const int d = threadIdx.x;
+        const double S = 0.5 * (sd.Q - 1), m = d - S;
+        ladder[d] = (T)(d < sd.Q ? sqrt(fmax(0.0, S * (S + 1) - m * (m + 1))) : 0.0);
+        ladder[16 + d] = (T)(d < sd.Q ? sqrt(fmax(0.0, S * (S + 1) - m * (m - 1))) : 0.0);
+        ladder[32 + d] = (T)m;
+    }
+    if (threadIdx.x < kMaxSites) hf[threadIdx.x] = (P.h && (int)threadIdx.x < sd.L) ? (T)P.h[threadIdx.x] : (T)0;
+}
+
+// y[row] = (H x)[row] for the rows of one wave tile [tile, min(tile+64, end)).
+template <typename IdxT, typename T, int K, int NMAX, bool Q2, typename PT>
+__device__ __forceinline__ void hx_tile(const PT &P, const SectorDesc &sd, const Tables<IdxT> &Tb,
+                                        const T *__restrict__ x, T *__restrict__ y, const T *bamp,
+                                        const T *bjz, const T *ladder, const T *hf, bool fields,
+                                        uint64_t tile, uint64_t end) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t row64 = tile + lane;
+    const bool active = row64 < end;
+    const IdxT row = (IdxT)(active ? row64 : tile);
+    RowState<IdxT, NMAX> r;
+    decode_row<IdxT, NMAX>(sd, Tb, row, r);
+    Acc<T, K> acc;
+#pragma unroll
+    for (int c = 0; c < K; ++c) acc.v[c] = (T)0;
+    T diag = (T)0;
+    ClassLoop<IdxT, T, K, NMAX, Q2, 0, 0>::run(P, sd, Tb, r, row, x, bamp, bjz, ladder, acc, diag);
+    if (fields) {
+        const uint32_t dm = (1u << sd.nb) - 1u;
+        for (int i = 0; i < sd.L; ++i)
+            diag += hf[i] * ladder[32 + (int)((r.s >> (sd.nb * (sd.L - 1 - i))) & dm)];
+    }
+    if (active) {
+        const T *xr = x + (uint64_t)row * K;
+        T *yr = y + (uint64_t)row * K;
+#pragma unroll
+        for (int c = 0; c < K; ++c) __builtin_nontemporal_store(acc.v[c] + diag * xr[c], yr + c);
+    }
+}
+
+// LDS layout behind the sector tables: bond coefficients, ladder factors, fields.
+template <typename T>
+struct CoeffLds {
+    T *bamp, *bjz, *ladder, *hf;
+    __device__ __forceinline__ CoeffLds(char *lds, uint32_t table_bytes) {
+        bamp = reinterpret_cast<T *>(lds + table_bytes);
+        bjz = bamp + kMaxBonds;
+        ladder = bjz + kMaxBonds;
+        hf = ladder + 48;
+    }
+};
+
+template <typename IdxT, typename T, int K, int NMAX, bool Q2>
+__global__ __launch_bounds__(kHxThreads) void hx_kernel(const HxParams P) {
+    extern __shared__ __align__(16) char lds[];
+    const SectorDesc &sd = P.sd;
+    stage_blob(lds, P.blob, sd.lay_bytes);
+    const CoeffLds<T> C(lds, sd.lay_bytes);
+    stage_coefficients<T, Q2>(P, sd, C.bamp, C.bjz, C.ladder, C.hf);
+    __syncthreads();
+    const Tables<IdxT> Tb = tables_at<IdxT>(lds, sd);
+    const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
+    T *__restrict__ y = reinterpret_cast<T *>(P.y);
+    const uint64_t chunk0 = (uint64_t)xcd_chunk(P.xcd_groups) * P.rows_per_wg;
+    const uint64_t chunk1 = min(chunk0 + P.rows_per_wg, sd.dim);
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (uint64_t tile = chunk0 + (uint64_t)wave * 64; tile < chunk1; tile += (uint64_t)nw * 64)
+        hx_tile<IdxT, T, K, NMAX, Q2>(P, sd, Tb, x, y, C.bamp, C.bjz, C.ladder, C.hf, P.h != nullptr,
+                                      tile, chunk1);
+}
+
+// ---------------------------------------------------------------- adjoint
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename IdxT, typename T, int NMAX, bool Q2, int A, int B>
+__device__ __forceinline__ void adjoint_class(const HxParams &P, const SectorDesc &sd,
+                                              const Tables<IdxT> &Tb,
+                                              const RowState<IdxT, NMAX> &r, IdxT row,
+                                              const T *__restrict__ x, const T *__restrict__ g,
+                                              T xr, T grow, const T *bamp, const T *bjz,
+                                              const T *ladder, double *wacc, T &hg, T &diag) {
+    const int cls = A * NMAX - A * (A - 1) / 2 + (B - A);
+    const int beg = P.cls_beg[cls], end = P.cls_beg[cls + 1];
+    const int lane = threadIdx.x & 63;
+    for (int t = beg; t < end; ++t) {
+        const uint32_t pos = P.pos[t];
+        const uint32_t pil = pos & 0xFFu, pjl = (pos >> 8) & 0xFFu;
+        T hop_x = (T)0;  // sum over hops of (ladder factors / 2) * x[col]
+        T zz;
+        if constexpr (Q2) {
+            const uint32_t bi = (r.w[A] >> pil) & 1u, bj = (r.w[B] >> pjl) & 1u;
+            zz = (bi == bj) ? (T)0.25 : (T)-0.25;
+            if (bi != bj) {
+                IdxT col;
+                if constexpr (A == B)
+                    col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, r.w[A] ^ ((1u << pil) | (1u << pjl)), 0, 0);
+                else
+                    col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, r.w[A] ^ (1u << pil),
+                                                    r.w[B] ^ (1u << pjl), bi ? -1 : 1);
+                hg += bamp[t] * g[col];
+                hop_x = (T)0.5 * x[col];
+            }
+        } else {
+            const uint32_t dm = (1u << sd.nb) - 1u;
+            const int Qm1 = sd.Q - 1;
+            const int di = (int)((r.w[A] >> pil) & dm), dj = (int)((r.w[B] >> pjl) & dm);
+            const T *up = ladder, *dn = ladder + 16, *mz = ladder + 32;
+            zz = mz[di] * mz[dj];
+            if (di < Qm1 && dj > 0) {
+                const uint32_t wa = r.w[A] + (1u << pil);
+                IdxT col;
+                if constexpr (A == B)
+                    col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa - (1u << pjl), 0, 0);
+                else
+                    col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa, r.w[B] - (1u << pjl), 1);
+                const T f = (T)0.5 * up[di] * dn[dj];
+                hg += (T)2 * bamp[t] * f * g[col];
+                hop_x += f * x[col];
+            }
+            if (di > 0 && dj < Qm1) {
+                const uint32_t wa = r.w[A] - (1u << pil);
+                IdxT col;
+                if constexpr (A == B)
+                    col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa + (1u << pjl), 0, 0);
+                else
+                    col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa, r.w[B] + (1u << pjl), -1);
+                const T f = (T)0.5 * dn[di] * up[dj];
+                hg += (T)2 * bamp[t] * f * g[col];
+                hop_x += f * x[col];
+            }
+        }
+        diag += (Q2 ? (T)4 : (T)1) * bjz[t] * zz;
+        const double vxy = wave_sum((double)grow * (double)hop_x);
+        const double vz = wave_sum((double)grow * (double)zz * (double)xr);
+        if (lane == 0) {
+            const int orig = (int)(pos >> 16);
+            wacc[2 * orig] += vxy;
+            wacc[2 * orig + 1] += vz;
+        }
+    }
+}
+
+template <typename IdxT, typename T, int NMAX, bool Q2, int A, int B>
+struct AdjLoop {
+    __device__ __forceinline__ static void run(const HxParams &P, const SectorDesc &sd,
+                                               const Tables<IdxT> &Tb,
+                                               const RowState<IdxT, NMAX> &r, IdxT row,
+                                               const T *__restrict__ x, const T *__restrict__ g,
+                                               T xr, T grow, const T *bamp, const T *bjz,
+                                               const T *ladder, double *wacc, T &hg, T &diag) {
+        if constexpr (A < NMAX) {
+            if constexpr (B < NMAX) {
+                if (B < sd.N)
+                    adjoint_class<IdxT, T, NMAX, Q2, A, B>(P, sd, Tb, r, row, x, g, xr, grow, bamp,
+                                                           bjz, ladder, wacc, hg, diag);
+                AdjLoop<IdxT, T, NMAX, Q2, A, B + 1>::run(P, sd, Tb, r, row, x, g, xr, grow, bamp,
+                                                          bjz, ladder, wacc, hg, diag);
+            } else {
+                AdjLoop<IdxT, T, NMAX, Q2, A + 1, A + 1>::run(P, sd, Tb, r, row, x, g, xr, grow,
+                                                              bamp, bjz, ladder, wacc, hg, diag);
+            }
+        }
+    }
+};
+
+// Each wave keeps its bond sums in its own LDS slice (one writer per slice),
+// then the workgroup adds the slices in wave order and writes one partial row.
+template <typename IdxT, typename T, int NMAX, bool Q2>
+__global__ __launch_bounds__(kHxThreads) void adjoint_kernel(const HxParams P) {
+    extern __shared__ __align__(16) char lds[];
+    const SectorDesc &sd = P.sd;
+    stage_blob(lds, P.blob, sd.lay_bytes);
+    T *bamp = reinterpret_cast<T *>(lds + sd.lay_bytes);
+    T *bjz = bamp + kMaxBonds;
+    T *ladder = bjz + kMaxBonds;
+    T *hf = ladder + 48;
+    double *wacc_all = reinterpret_cast<double *>(hf + kMaxSites);
+    const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nacc = 2 * P.nbonds + sd.L;
+    stage_coefficients<T, Q2>(P, sd, bamp, bjz, ladder, hf);
+    for (int i = threadIdx.x; i < nw * nacc; i += blockDim.x) wacc_all[i] = 0.0;
+    __syncthreads();
+    double *wacc = wacc_all + wave * nacc;
+    const Tables<IdxT> Tb = tables_at<IdxT>(lds, sd);
+    const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
+    const T *__restrict__ g = reinterpret_cast<const T *>(P.g);
+    T *__restrict__ gx = reinterpret_cast<T *>(P.gx);
+
+    const uint64_t chunk0 = (uint64_t)xcd_chunk(P.xcd_groups) * P.rows_per_wg;
+    const uint64_t chunk1 = min(chunk0 + P.rows_per_wg, sd.dim);
+    for (uint64_t tile = chunk0 + (uint64_t)wave * 64; tile < chunk1; tile += (uint64_t)nw * 64) {
+        const uint64_t row64 = tile + lane;
+        const bool active = row64 < chunk1;
+        const IdxT row = (IdxT)(active ? row64 : tile);
+        RowState<IdxT, NMAX> r;
+        decode_row<IdxT, NMAX>(sd, Tb, row, r);
+        const T xr = x[row];
+        const T grow = active ? g[row] : (T)0;  // inactive lanes add nothing to the bond sums
+        T hg = (T)0, diag = (T)0;
+        AdjLoop<IdxT, T, NMAX, Q2, 0, 0>::run(P, sd, Tb, r, row, x, g, xr, grow, bamp, bjz, ladder,
+                                              wacc, hg, diag);
+        const uint32_t dm = (1u << sd.nb) - 1u;
+        for (int i = 0; i < sd.L; ++i) {
+            const T mzi = ladder[32 + (int)((r.s >> (sd.nb * (sd.L - 1 - i))) & dm)];
+            if (P.h) diag += hf[i] * mzi;
+            const double v = wave_sum((double)grow * (double)mzi * (double)xr);
+            if (lane == 0) wacc[2 * P.nbonds + i] += v;
+        }
+        if (active && gx) gx[row] = hg + diag * g[row];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nacc; i += blockDim.x) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += wacc_all[w * nacc + i];
+        P.partials[(size_t)blockIdx.x * nacc + i] = s;
+    }
+}
+
+// Deterministic second stage: fixed-order sum over workgroups.
+template <int Unused = 0>
+__global__ void adjoint_reduce(const double *__restrict__ partials, int nwg, int nbonds, int L,
+                               double *gjxy, double *gjz, double *gh) {
+    const int nacc = 2 * nbonds + L;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nacc) return;
+    double s = 0.0;
+    for (int w = 0; w < nwg; ++w) s += partials[(size_t)w * nacc + i];
+    if (i < 2 * nbonds) {
+        if (i & 1)
+            gjz[i >> 1] = s;
+        else
+            gjxy[i >> 1] = s;
+    } else if (gh) {
+        gh[i - 2 * nbonds] = s;
+    }
+}
+
+// ---------------------------------------------------------------- launch
+
+struct Grid {
+    int wgs;
+    uint64_t rows_per_wg;
+    int xcd_groups;
+};
+
+inline Grid plan_grid(const dcs_sector *s, size_t lds_bytes) {
+    const uint64_t dim = s->desc.dim;
+    const int cus = device_cu_count(s->device);
+    const size_t lds_cu = 160 * 1024;
+    int per_cu = (int)(lds_cu / (lds_bytes ? lds_bytes : 1));
+    per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
+    const uint64_t tile = (uint64_t)(kHxThreads / 64) * 64;
+    uint64_t want = (uint64_t)cus * per_cu;
+    uint64_t tiles = (dim + tile - 1) / tile;
+    if (want > tiles) want = tiles;
+    if (want < 1) want = 1;
+    Grid g;
+    g.rows_per_wg = ((dim + want - 1) / want + 63) / 64 * 64;
+    g.wgs = (int)((dim + g.rows_per_wg - 1) / g.rows_per_wg);
+    g.xcd_groups = 0;
+    if (g.wgs >= 16) {
+        // round the grid up to a multiple of 8 so chunk = (b % 8) * groups + b / 8 is a bijection
+        const int groups = (g.wgs + 7) / 8;
+        g.wgs = groups * 8;
+        g.rows_per_wg = ((dim + g.wgs - 1) / g.wgs + 63) / 64 * 64;
+        g.xcd_groups = groups;
+    }
+    return g;
+}
+
+inline int fill_params(const dcs_sector *s, const dcs_terms *t, int nmax, const double *jxy,
+                const double *jz, const double *h, HxParams &P) {
+    BondPlan bp;
+    if (int r = make_bond_plan(s, t, nmax, &bp)) return r;
+    memset(&P, 0, sizeof(P));
+    P.sd = s->desc;
+    P.blob = (const char *)s->dev.base;
+    P.jxy = jxy;
+    P.jz = jz;
+    P.h = h;
+    P.nbonds = bp.nbonds;
+    for (int c = 0; c <= bp.nclasses; ++c) P.cls_beg[c] = bp.cls_beg[c];
+    for (int b = 0; b < bp.nbonds; ++b) P.pos[b] = bp.pos[b];
+    return DCS_OK;
+}
+
+template <typename T>
+inline size_t coeff_lds_bytes() {
+    return (2 * kMaxBonds + 48 + kMaxSites) * sizeof(T);
+}
+
+template <typename IdxT, typename T, int K, int NMAX>
+int launch_hx_t(const dcs_sector *s, HxParams &P, hipStream_t stream) {
+    const size_t lds = s->desc.lay_bytes + coeff_lds_bytes<T>();
+    const Grid g = plan_grid(s, lds);
+    P.rows_per_wg = g.rows_per_wg;
+    P.xcd_groups = g.xcd_groups;
+    if (s->desc.Q == 2) {
+        auto kern = hx_kernel<IdxT, T, K, NMAX, true>;
+        if (int r = ensure_lds(kern, lds)) return r;
+        kern<<<g.wgs, kHxThreads, lds, stream>>>(P);
+    } else {
+        auto kern = hx_kernel<IdxT, T, K, NMAX, false>;
+        if (int r = ensure_lds(kern, lds)) return r;
+        kern<<<g.wgs, kHxThreads, lds, stream>>>(P);
+    }
+    return check_hip(hipGetLastError(), "H*x kernel launch");
+}
+
+template <typename IdxT, typename T, int NMAX>
+int launch_adj_t(const dcs_sector *s, HxParams &P, double *gjxy, double *gjz, double *gh,
+                        hipStream_t stream) {
+    const int nacc = 2 * P.nbonds + s->desc.L;
+    const size_t lds = s->desc.lay_bytes + coeff_lds_bytes<T>() +
+                       (size_t)(kHxThreads / 64) * nacc * sizeof(double);
+    const size_t lds_plan = s->desc.lay_bytes + coeff_lds_bytes<double>() +
+                            (size_t)(kHxThreads / 64) * nacc * sizeof(double);
+    const Grid g = plan_grid(s, lds_plan);
+    P.rows_per_wg = g.rows_per_wg;
+    P.xcd_groups = g.xcd_groups;
+    if (s->desc.Q == 2) {
+        auto kern = adjoint_kernel<IdxT, T, NMAX, true>;
+        if (int r = ensure_lds(kern, lds)) return r;
+        kern<<<g.wgs, kHxThreads, lds, stream>>>(P);
+    } else {
+        auto kern = adjoint_kernel<IdxT, T, NMAX, false>;
+        if (int r = ensure_lds(kern, lds)) return r;
+        kern<<<g.wgs, kHxThreads, lds, stream>>>(P);
+    }
+    if (int r = check_hip(hipGetLastError(), "adjoint kernel launch")) return r;
+    adjoint_reduce<0><<<(nacc + 255) / 256, 256, 0, stream>>>(P.partials, g.wgs, P.nbonds, s->desc.L,
+                                                           gjxy, gjz, gh);
+    return check_hip(hipGetLastError(), "adjoint reduction launch");
+}
+
+}  // namespace hx
+}  // namespace dcs

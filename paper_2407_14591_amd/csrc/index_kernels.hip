@@ -1,0 +1,124 @@
+// Batched rank (Alg. i), unrank (Alg. iii) and enumeration of a sector.
+//
+// Persistent grid-stride kernels: every workgroup stages the sector's tables
+// into LDS once, then each thread handles one item per iteration.  Invalid
+// items are counted with one atomic per wavefront (ballot + popcount).
+#include "device_common.h"
+
+namespace dcs {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ void count_bad(uint64_t *nbad, bool bad) {
+    if (!nbad) return;
+    const uint64_t mask = __ballot(bad);
+    if (mask && (threadIdx.x % warpSize) == 0) atomicAdd((unsigned long long *)nbad, (unsigned long long)__popcll(mask));
+}
+
+template <typename IdxT>
+__global__ __launch_bounds__(kThreads) void rank_kernel(SectorDesc sd, const char *blob,
+                                                        const uint64_t *__restrict__ st,
+                                                        uint64_t *__restrict__ out, size_t count,
+                                                        uint64_t *nbad) {
+    extern __shared__ __align__(16) char lds[];
+    stage_blob(lds, blob, sd.lay_bytes);
+    __syncthreads();
+    const Tables<IdxT> T = tables_at<IdxT>(lds, sd);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t base = (size_t)blockIdx.x * blockDim.x; base < count; base += stride) {
+        const size_t i = base + threadIdx.x;
+        bool bad = false;
+        if (i < count) {
+            const IdxT r = rank_state<IdxT, true>(sd, T, st[i]);
+            bad = r == Bad<IdxT>::value;
+            out[i] = bad ? DCS_INVALID_INDEX : (uint64_t)r;
+        }
+        count_bad(nbad, bad);
+    }
+}
+
+template <typename IdxT>
+__global__ __launch_bounds__(kThreads) void unrank_kernel(SectorDesc sd, const char *blob,
+                                                          const uint64_t *__restrict__ idx,
+                                                          uint64_t *__restrict__ out, size_t count,
+                                                          uint64_t first, int use_first,
+                                                          uint64_t *nbad) {
+    extern __shared__ __align__(16) char lds[];
+    stage_blob(lds, blob, sd.lay_bytes);
+    __syncthreads();
+    const Tables<IdxT> T = tables_at<IdxT>(lds, sd);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t base = (size_t)blockIdx.x * blockDim.x; base < count; base += stride) {
+        const size_t i = base + threadIdx.x;
+        bool bad = false;
+        if (i < count) {
+            const uint64_t v = use_first ? first + i : idx[i];
+            bad = v >= sd.dim;
+            out[i] = bad ? DCS_INVALID_INDEX
+                         : unrank_state<IdxT, kMaxSub>(sd, T, (IdxT)v, nullptr, nullptr, nullptr);
+        }
+        count_bad(nbad, bad);
+    }
+}
+
+int grid_for(const dcs_sector *s, size_t count) {
+    const size_t blocks = (count + kThreads - 1) / kThreads;
+    const size_t cap = (size_t)device_cu_count(s->device) * 8;
+    return (int)(blocks < cap ? blocks : cap);
+}
+
+}  // namespace
+
+int launch_rank(const dcs_sector *s, const uint64_t *st, uint64_t *idx, size_t count,
+                uint64_t *nbad, hipStream_t stream) {
+    DeviceGuard g(s->device);
+    if (int r = s->wide ? ensure_lds(rank_kernel<uint64_t>, s->desc.lay_bytes)
+                        : ensure_lds(rank_kernel<uint32_t>, s->desc.lay_bytes))
+        return r;
+    const int grid = grid_for(s, count);
+    const char *blob = (const char *)s->dev.base;
+    if (s->wide)
+        rank_kernel<uint64_t><<<grid, kThreads, s->desc.lay_bytes, stream>>>(s->desc, blob, st, idx,
+                                                                              count, nbad);
+    else
+        rank_kernel<uint32_t><<<grid, kThreads, s->desc.lay_bytes, stream>>>(s->desc, blob, st, idx,
+                                                                              count, nbad);
+    return check_hip(hipGetLastError(), "rank kernel launch");
+}
+
+int launch_unrank(const dcs_sector *s, const uint64_t *idx, uint64_t *st, size_t count,
+                  uint64_t *nbad, hipStream_t stream) {
+    DeviceGuard g(s->device);
+    if (int r = s->wide ? ensure_lds(unrank_kernel<uint64_t>, s->desc.lay_bytes)
+                        : ensure_lds(unrank_kernel<uint32_t>, s->desc.lay_bytes))
+        return r;
+    const int grid = grid_for(s, count);
+    const char *blob = (const char *)s->dev.base;
+    if (s->wide)
+        unrank_kernel<uint64_t><<<grid, kThreads, s->desc.lay_bytes, stream>>>(
+            s->desc, blob, idx, st, count, 0, 0, nbad);
+    else
+        unrank_kernel<uint32_t><<<grid, kThreads, s->desc.lay_bytes, stream>>>(
+            s->desc, blob, idx, st, count, 0, 0, nbad);
+    return check_hip(hipGetLastError(), "unrank kernel launch");
+}
+
+int launch_enumerate(const dcs_sector *s, uint64_t first, size_t count, uint64_t *st,
+                     hipStream_t stream) {
+    DeviceGuard g(s->device);
+    if (int r = s->wide ? ensure_lds(unrank_kernel<uint64_t>, s->desc.lay_bytes)
+                        : ensure_lds(unrank_kernel<uint32_t>, s->desc.lay_bytes))
+        return r;
+    const int grid = grid_for(s, count);
+    const char *blob = (const char *)s->dev.base;
+    if (s->wide)
+        unrank_kernel<uint64_t><<<grid, kThreads, s->desc.lay_bytes, stream>>>(
+            s->desc, blob, nullptr, st, count, first, 1, nullptr);
+    else
+        unrank_kernel<uint32_t><<<grid, kThreads, s->desc.lay_bytes, stream>>>(
+            s->desc, blob, nullptr, st, count, first, 1, nullptr);
+    return check_hip(hipGetLastError(), "enumerate kernel launch");
+}
+
+}  // namespace dcs

@@ -1,0 +1,81 @@
+"""The C-ABI library loads and exports every entry point include/dcs.h declares;
+host-side argument checks work without a GPU.  CPU only."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dcs.h")
+LIB = os.path.join(ROOT, "paper_2407_14591_amd", "libdcs.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dcs_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2407_14591_amd import build
+        build.build()
+    return C.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ["dcs_sector_create", "dcs_sector_destroy", "dcs_sector_dim", "dcs_rank",
+                 "dcs_unrank", "dcs_enumerate", "dcs_terms_create", "dcs_hamiltonian_apply",
+                 "dcs_hamiltonian_apply_adjoint", "dcs_adjoint_workspace_size",
+                 "dcs_plan_create", "dcs_plan_apply", "dcs_lanczos", "dcs_last_error"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\s[TW]\s+(dcs_\w+)", out))
+    missing = [n for n in declared() if n not in exported]
+    assert not missing, missing
+    for n in declared():
+        getattr(lib, n)
+
+
+def test_binding_covers_every_entry_point():
+    from paper_2407_14591_amd import _lib
+    assert sorted(_lib.SIGNATURES) == declared()
+
+
+def test_host_side_errors(lib):
+    from paper_2407_14591_amd import _lib
+    l = _lib.lib()
+    out = C.c_void_p()
+    assert l.dcs_sector_create(0, 0, 2, 1, None, 0, C.byref(out)) == _lib.DCS_EINVAL
+    assert b"L=0" in l.dcs_last_error()
+    assert l.dcs_sector_create(70, 3, 2, 0, None, 0, C.byref(out)) == _lib.DCS_EINVAL
+    assert l.dcs_sector_create(10, 11, 2, 0, None, 0, C.byref(out)) == _lib.DCS_EINVAL
+    sizes = (C.c_int * 2)(4, 5)
+    assert l.dcs_sector_create(10, 5, 2, 2, sizes, 0, C.byref(out)) == _lib.DCS_EINVAL
+    sizes = (C.c_int * 2)(5, 15)
+    assert l.dcs_sector_create(20, 5, 2, 2, sizes, 0, C.byref(out)) == _lib.DCS_EUNSUPPORTED
+    si = (C.c_int32 * 2)(0, 1)
+    sj = (C.c_int32 * 2)(1, 1)
+    assert l.dcs_terms_create(2, si, sj, C.byref(out)) == _lib.DCS_EINVAL
+    sj = (C.c_int32 * 2)(1, 2)
+    assert l.dcs_terms_create(2, si, sj, C.byref(out)) == _lib.DCS_OK
+    assert l.dcs_terms_destroy(out) == _lib.DCS_OK
+    assert l.dcs_terms_create(300, None, None, C.byref(out)) == _lib.DCS_EUNSUPPORTED
+    assert l.dcs_version() >= 100
+
+
+def test_tables_fit_the_workloads():
+    """The per-subsystem word widths of every workload split stay within the
+    library's on-chip table limits (checked on the host, no GPU needed)."""
+    from oracle.sector import default_split
+    for Q, L, split in [(2, 32, [8, 8, 8, 8]), (2, 34, [8, 8, 9, 9]), (2, 16, [8, 8]),
+                        (2, 24, [8, 8, 8]), (2, 28, [7, 7, 7, 7]), (3, 16, default_split(3, 16))]:
+        nb = (Q - 1).bit_length()
+        assert max(split) * nb <= 14

@@ -1,0 +1,148 @@
+"""GPU adjoint of y = H(theta) x: parity with the oracle gradients, autograd
+gradcheck, finite differences (exact for a linear map) and the Hellmann-Feynman
+ground-energy gradient."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2407_14591_amd as dq
+import synth
+from gpu_common import DEV, rel_err, say
+from oracle import native
+from oracle.gradients import adjoint as o_adjoint, chain_rule_j_delta
+from oracle.hamiltonian import apply_h, full_basis_digit_sums, full_matrix
+from oracle.sector import BruteSector
+
+pytestmark = pytest.mark.gpu
+
+
+def dev_f64(a):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device=DEV)
+
+
+@pytest.mark.parametrize("Q,L,n,split", [(2, 10, 5, [5, 5]), (2, 12, 4, [4, 4, 4]),
+                                         (2, 9, 4, [1, 2, 3, 3]), (3, 6, 6, [2, 2, 2]),
+                                         (4, 5, 7, [2, 3])])
+def test_adjoint_matches_oracle(Q, L, n, split):
+    rng = np.random.default_rng(L * Q)
+    b = BruteSector(Q, L, n, split)
+    bonds = synth.chain_bonds(L, 1) + synth.chain_bonds(L, 2)
+    jxy, jz, h = rng.normal(size=len(bonds)), rng.normal(size=len(bonds)), rng.normal(size=L)
+    x, g = rng.normal(size=b.dim), rng.normal(size=b.dim)
+    gx, gj, gz, gh = o_adjoint(b, bonds, jxy, jz, x, g, h)
+    s, t = dq.Sector(L, n, Q, split), dq.Terms(bonds)
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        out = dq.hamiltonian_apply_adjoint(s, t, dev_f64(jxy), dev_f64(jz),
+                                           torch.tensor(x, device=DEV).to(dt),
+                                           torch.tensor(g, device=DEV).to(dt), h=dev_f64(h),
+                                           want_grad_h=True)
+        say("adjoint", Q, L, n, dt)
+        assert rel_err(out[0].double().cpu().numpy(), gx) <= tol
+        assert rel_err(out[1].cpu().numpy(), gj) <= tol
+        assert rel_err(out[2].cpu().numpy(), gz) <= tol
+        assert rel_err(out[3].cpu().numpy(), gh) <= tol
+
+
+def test_gradcheck_autograd():
+    L, n = 8, 4
+    s = dq.Sector(L, n, 2, [4, 4])
+    bonds = synth.chain_bonds(L, 1) + synth.chain_bonds(L, 2)
+    t = dq.Terms(bonds)
+    rng = np.random.default_rng(0)
+    x = torch.tensor(rng.normal(size=s.dim), device=DEV, requires_grad=True)
+    jxy = torch.tensor(rng.uniform(0.5, 1.5, len(bonds)), device=DEV, requires_grad=True)
+    jz = torch.tensor(rng.uniform(0, 2, len(bonds)), device=DEV, requires_grad=True)
+    f = lambda x_, a_, b_: dq.HApply.apply(x_, a_, b_, s, t)
+    assert torch.autograd.gradcheck(f, (x, jxy, jz), eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+def test_differentiable_workload_L24():
+    """L=24, n=12, per-bond J_b, Delta_b: coupling gradients against the C oracle
+    (g . H_b x with one unit bond at a time) and grad_x = H g."""
+    L, n, sp = 24, 12, [8, 8, 8]
+    bonds = synth.chain_bonds(L, 1)
+    J, Dl = synth.random_couplings(len(bonds))
+    jxy, jz = J, J * Dl
+    ns = native.NativeSector(2, L, n, sp)
+    x = synth.vector(ns.dim, synth.SEED_X)
+    g = synth.vector(ns.dim, synth.SEED_G)
+    ref_gx = native.hx_range(ns, native.NativeTerms(bonds, jxy, jz), g)
+    ref_gj = np.array([g @ native.hx_range(ns, native.NativeTerms([bd], [1.0], [0.0]), x) for bd in bonds])
+    ref_gz = np.array([g @ native.hx_range(ns, native.NativeTerms([bd], [0.0], [1.0]), x) for bd in bonds])
+    s, t = dq.Sector(L, n, 2, sp), dq.Terms(bonds)
+    gx, gj, gz, _ = dq.hamiltonian_apply_adjoint(s, t, dev_f64(jxy), dev_f64(jz),
+                                                 torch.tensor(x, device=DEV),
+                                                 torch.tensor(g, device=DEV))
+    assert rel_err(gx.cpu().numpy(), ref_gx) <= 1e-12
+    assert rel_err(gj.cpu().numpy(), ref_gj) <= 1e-12
+    assert rel_err(gz.cpu().numpy(), ref_gz) <= 1e-12
+    # chain rule to (J, Delta) through autograd against the oracle's chain rule
+    Jt = torch.tensor(J, device=DEV, requires_grad=True)
+    Dt = torch.tensor(Dl, device=DEV, requires_grad=True)
+    y = dq.HApply.apply(torch.tensor(x, device=DEV), Jt, Jt * Dt, s, t)
+    (y * torch.tensor(g, device=DEV)).sum().backward()
+    gJ, gD = chain_rule_j_delta(J, Dl, ref_gj, ref_gz)
+    assert rel_err(Jt.grad.cpu().numpy(), gJ) <= 1e-12
+    assert rel_err(Dt.grad.cpu().numpy(), gD) <= 1e-12
+    # deterministic: a second call is bitwise equal
+    _, gj2, gz2, _ = dq.hamiltonian_apply_adjoint(s, t, dev_f64(jxy), dev_f64(jz),
+                                                  torch.tensor(x, device=DEV),
+                                                  torch.tensor(g, device=DEV), want_grad_x=False)
+    assert torch.equal(gj, gj2) and torch.equal(gz, gz2)
+
+
+def hf_gradient(s, t, jxy, jz, steps=150):
+    v0 = torch.tensor(synth.vector(s.dim, synth.SEED_V0), device=DEV)
+    res = dq.lanczos(s, t, dev_f64(jxy), dev_f64(jz), v0, steps, reorth="full", num_eig=2,
+                     want_vector=True)
+    psi = res["vector"]
+    _, gj, gz, _ = dq.hamiltonian_apply_adjoint(s, t, dev_f64(jxy), dev_f64(jz), psi, psi,
+                                                want_grad_x=False)
+    return res["eig"], gj.cpu().numpy(), gz.cpu().numpy()
+
+
+def test_hellmann_feynman_dense_L12():
+    L, n = 12, 6
+    bonds = synth.chain_bonds(L, 1) + synth.chain_bonds(L, 2)
+    J, Dl = synth.random_couplings(len(bonds), seed=9)
+    jxy, jz = J, J * Dl
+    sel = np.nonzero(full_basis_digit_sums(2, L) == n)[0]
+    w, v = np.linalg.eigh(full_matrix(2, L, bonds, jxy, jz)[np.ix_(sel, sel)])
+    assert w[1] - w[0] > 1e-3
+    b = BruteSector(2, L, n, [6, 6])
+    # the dense ground vector in the full-space numbering -> canonical order
+    from oracle.sector import unpack
+    full_idx = [sum(q * 2 ** (L - 1 - i) for i, q in enumerate(unpack(int(st), 2, L))) for st in b.states]
+    pos = {f: k for k, f in enumerate(sel)}
+    psi = v[[pos[f] for f in full_idx], 0]
+    ref_gj = np.array([psi @ apply_h(b, [bd], [1.0], [0.0], psi) for bd in bonds])
+    ref_gz = np.array([psi @ apply_h(b, [bd], [0.0], [1.0], psi) for bd in bonds])
+    s, t = dq.Sector(L, n, 2, [6, 6]), dq.Terms(bonds)
+    eig, gj, gz = hf_gradient(s, t, jxy, jz)
+    assert abs(eig[0] - w[0]) < 1e-10
+    assert np.allclose(gj, ref_gj, atol=1e-8) and np.allclose(gz, ref_gz, atol=1e-8)
+
+
+def test_hellmann_feynman_finite_differences_L24():
+    """dE0/dtheta at the L=24 random-coupling workload: Hellmann-Feynman against
+    central finite differences of the Lanczos ground energy (step 1e-4)."""
+    L, n, sp = 24, 12, [8, 8, 8]
+    bonds = synth.chain_bonds(L, 1)
+    J, Dl = synth.random_couplings(len(bonds))
+    jxy, jz = J, J * Dl
+    s, t = dq.Sector(L, n, 2, sp), dq.Terms(bonds)
+    eig, gj, gz = hf_gradient(s, t, jxy, jz)
+    assert eig[1] - eig[0] > 1e-6          # non-degenerate ground state
+    eps = 1e-4
+    for b in (0, 7, 19):
+        e = np.zeros(len(bonds))
+        e[b] = eps
+        ep = hf_gradient(s, t, jxy + e, jz)[0][0]
+        em = hf_gradient(s, t, jxy - e, jz)[0][0]
+        fd = (ep - em) / (2 * eps)
+        say("HF jxy", b, gj[b], fd)
+        assert abs(fd - gj[b]) <= 1e-6 * max(1.0, abs(gj[b]))
+        ep = hf_gradient(s, t, jxy, jz + e)[0][0]
+        em = hf_gradient(s, t, jxy, jz - e)[0][0]
+        fd = (ep - em) / (2 * eps)
+        assert abs(fd - gz[b]) <= 1e-6 * max(1.0, abs(gz[b]))

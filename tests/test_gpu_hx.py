@@ -1,0 +1,170 @@
+"""GPU parity of Y = H X against the FP64 oracle.
+
+Tolerances (norm-wise relative error |y - y_ref| / |y_ref|): FP64 1e-12,
+FP32 1e-5, against the oracle run in FP64 on the FP64 input.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2407_14591_amd as dq
+import synth
+from gpu_common import DEV, rel_err, say, to_dev
+from oracle import native
+from oracle.hamiltonian import apply_h
+from oracle.sector import BruteSector
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+
+
+def dev_f64(a):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device=DEV)
+
+
+def random_graph(L, nb, rng):
+    bonds = set()
+    while len(bonds) < nb:
+        i, j = rng.integers(0, L, 2)
+        if i != j and (j, i) not in bonds:
+            bonds.add((int(i), int(j)))
+    return sorted(bonds)
+
+
+SMALL = [
+    # Q, L, n, split, topology
+    (2, 10, 5, [5, 5], "j1j2"),
+    (2, 12, 5, [4, 4, 4], "j1j2"),
+    (2, 12, 6, None, "graph"),
+    (2, 9, 4, [3, 3, 3], "j1j2"),
+    (2, 11, 4, [1, 2, 3, 1, 2, 1, 1], "graph"),
+    (2, 10, 3, [1] * 7 + [3], "j1j2"),
+    (2, 13, 6, [13], "chain"),
+    (2, 8, 0, [4, 4], "chain"),
+    (2, 8, 8, [4, 4], "chain"),
+    (2, 8, 1, [2, 6], "graph"),
+    (3, 6, 6, [2, 2, 2], "chain"),
+    (3, 7, 5, [3, 4], "graph"),
+    (3, 5, 7, [1, 1, 1, 2], "j1j2"),
+    (4, 5, 7, [2, 3], "chain"),
+    (5, 4, 6, [2, 2], "chain"),
+]
+
+
+def topology(kind, L, rng):
+    if kind == "chain":
+        return synth.chain_bonds(L, 1)
+    if kind == "j1j2":
+        return synth.chain_bonds(L, 1) + synth.chain_bonds(L, 2)
+    return random_graph(L, 2 * L, rng)
+
+
+@pytest.mark.parametrize("bits", ["32", "64"])
+def test_small_sectors_all_dtypes_and_k(monkeypatch, bits):
+    if bits == "64":
+        monkeypatch.setenv("DCS_INDEX_BITS", "64")
+    rng = np.random.default_rng(1)
+    for Q, L, n, sp, kind in SMALL:
+        b = BruteSector(Q, L, n, sp)
+        bonds = topology(kind, L, rng)
+        jxy, jz, h = rng.normal(size=len(bonds)), rng.normal(size=len(bonds)), rng.normal(size=L)
+        s = dq.Sector(L, n, Q, sp)
+        t = dq.Terms(bonds)
+        for use_h in (False, True):
+            for k in (1, 2, 4, 8):
+                x = rng.normal(size=(b.dim, k)) if k > 1 else rng.normal(size=b.dim)
+                y_ref = apply_h(b, bonds, jxy, jz, x, h if use_h else None)
+                for dt in (torch.float64, torch.float32):
+                    say("hx", Q, L, n, s.split, kind, k, dt, use_h, bits)
+                    xd = torch.tensor(x, device=DEV).to(dt)
+                    y = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), xd,
+                                             h=dev_f64(h) if use_h else None)
+                    assert rel_err(y.cpu().double().numpy(), y_ref) <= TOL[dt], (Q, L, n, k, dt)
+
+
+def test_bitwise_reproducible():
+    L, n = 20, 10
+    s = dq.Sector(L, n, 2, [6, 7, 7])
+    bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.5, 1.0)
+    t = dq.Terms(bonds)
+    x = torch.tensor(synth.vector(s.dim), device=DEV, dtype=torch.float32)
+    y1 = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), x)
+    y2 = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), x)
+    assert torch.equal(y1, y2)
+
+
+def test_plain_workload_L16_full():
+    """L=16, n=8, 8/8 Heisenberg chain: every row against the C oracle."""
+    L, n, sp = 16, 8, [8, 8]
+    s = dq.Sector(L, n, 2, sp)
+    ns = native.NativeSector(2, L, n, sp)
+    bonds, jxy, jz = synth.xxz_chain(L, 1.0, 1.0)
+    t = dq.Terms(bonds)
+    x = synth.vector(s.dim)
+    y_ref = native.hx_range(ns, native.NativeTerms(bonds, jxy, jz), x)
+    for dt in (torch.float64, torch.float32):
+        y = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), torch.tensor(x, device=DEV).to(dt))
+        assert rel_err(y.cpu().double().numpy(), y_ref) <= TOL[dt]
+
+
+def test_differentiable_workload_L24_full():
+    """L=24, n=12, 8/8/8 with per-bond J_b ~ U(0.5,1.5), Delta_b ~ U(0,2): all rows."""
+    L, n, sp = 24, 12, [8, 8, 8]
+    s = dq.Sector(L, n, 2, sp)
+    ns = native.NativeSector(2, L, n, sp)
+    bonds = synth.chain_bonds(L, 1)
+    J, D = synth.random_couplings(len(bonds))
+    jxy, jz = J, J * D
+    t = dq.Terms(bonds)
+    x = synth.vector(s.dim)
+    y_ref = native.hx_range(ns, native.NativeTerms(bonds, jxy, jz), x)
+    y = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), torch.tensor(x, device=DEV))
+    assert rel_err(y.cpu().numpy(), y_ref) <= 1e-12
+
+
+def sampled_rows(dim, count, seed):
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(0, dim, count).astype(np.uint64)
+    edge = np.concatenate([np.arange(0, 4096), np.arange(dim - 4096, dim)]).astype(np.uint64)
+    return np.concatenate([edge, rows])
+
+
+def test_k8_block_L28_sampled():
+    """L=28, n=14 (7/7/7/7), k=8 FP32 block: 200k sampled rows against the oracle."""
+    L, n, sp = 28, 14, [7, 7, 7, 7]
+    s = dq.Sector(L, n, 2, sp)
+    ns = native.NativeSector(2, L, n, sp)
+    bonds, jxy, jz = synth.xxz_chain(L, 1.0, 1.0)
+    x64 = synth.vector(s.dim, synth.SEED_X, np.float64, k=8)
+    rows = sampled_rows(s.dim, 200_000, 5)
+    y_ref = native.hx_rows(ns, native.NativeTerms(bonds, jxy, jz), x64, rows)
+    xd = torch.tensor(x64, device=DEV, dtype=torch.float32)
+    del x64
+    y = dq.hamiltonian_apply(s, dq.Terms(bonds), dev_f64(jxy), dev_f64(jz), xd)
+    got = y[torch.tensor(rows.astype(np.int64), device=DEV)].double().cpu().numpy()
+    assert rel_err(got, y_ref) <= 1e-5
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_headline_workload_L32_sampled(dt):
+    """L=32, n=16 (601,080,390 states, 8/8/8/8), J1-J2 with J2=0.5, Delta=1: the
+    launch the bench times, checked on 300k sampled rows (plus the first and last 4096)."""
+    L, n, sp = 32, 16, [8, 8, 8, 8]
+    s = dq.Sector(L, n, 2, sp)
+    ns = native.NativeSector(2, L, n, sp)
+    bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.5, 1.0)
+    say("generating x", s.dim)
+    xh = synth.vector(s.dim, synth.SEED_X, np.float64)
+    rows = sampled_rows(s.dim, 300_000, 6)
+    say("oracle rows")
+    y_ref = native.hx_rows(ns, native.NativeTerms(bonds, jxy, jz), xh, rows)
+    xd = torch.from_numpy(xh).to(DEV).to(dt)
+    del xh
+    y = dq.hamiltonian_apply(s, dq.Terms(bonds), dev_f64(jxy), dev_f64(jz), xd)
+    got = y[torch.tensor(rows.astype(np.int64), device=DEV)].double().cpu().numpy()
+    err = rel_err(got, y_ref)
+    say("rel err", err)
+    assert err <= TOL[dt]

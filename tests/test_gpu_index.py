@@ -1,0 +1,136 @@
+"""GPU parity of rank / unrank / enumerate against the oracle: bit-exact."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2407_14591_amd as dq
+import synth
+from gpu_common import DEV, say, to_dev, to_host_u64
+from oracle import native
+from oracle.sector import BruteSector, pack
+
+pytestmark = pytest.mark.gpu
+BAD = np.uint64(2 ** 64 - 1)
+
+
+def cases():
+    out = []
+    for L in range(1, 13):
+        for n in sorted({0, 1, L // 3, L // 2, L - 1, L}):
+            if not 0 <= n <= L:
+                continue
+            out.append((2, L, n, None))
+    out += [(2, 10, 4, [10]), (2, 10, 5, [1] * 7 + [3]), (2, 9, 4, [3, 3, 3]),
+            (2, 12, 6, [1, 2, 3, 4, 1, 1]), (2, 14, 7, [7, 7]), (2, 11, 3, [1, 10]),
+            (2, 13, 6, [2, 2, 2, 2, 2, 1, 1, 1])]
+    out += [(3, L, n, None) for L in (1, 3, 5, 6) for n in (0, L - 1, L, 2 * L)]
+    out += [(3, 6, 6, [2, 2, 2]), (3, 7, 5, [1, 6]), (4, 5, 7, [2, 3]), (4, 4, 6, [1, 1, 1, 1]),
+            (5, 4, 8, [2, 2]), (7, 4, 12, [2, 2])]
+    return out
+
+
+@pytest.mark.parametrize("bits", ["32", "64"])
+def test_rank_unrank_enumerate_small(monkeypatch, bits):
+    if bits == "64":
+        monkeypatch.setenv("DCS_INDEX_BITS", "64")
+    for Q, L, n, sp in cases():
+        b = BruteSector(Q, L, n, sp)
+        s = dq.Sector(L, n, Q, sp)
+        say("sector", Q, L, n, s.split, bits)
+        assert s.dim == b.dim and (sp is None or s.split == sp)
+        st = to_dev(b.states)
+        idx, bad = s.rank(st, count_invalid=True)
+        assert np.array_equal(to_host_u64(idx), np.arange(b.dim, dtype=np.uint64))
+        assert int(bad.item()) == 0
+        back, bad = s.unrank(to_dev(np.arange(b.dim, dtype=np.uint64)), count_invalid=True)
+        assert np.array_equal(to_host_u64(back), b.states)
+        assert np.array_equal(to_host_u64(s.enumerate(0, b.dim)), b.states)
+        # ragged sub-ranges
+        for first in {0, b.dim // 3, b.dim - 1}:
+            cnt = b.dim - first
+            assert np.array_equal(to_host_u64(s.enumerate(first, cnt)), b.states[first:])
+        s.close()
+
+
+def test_worked_example():
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_example_L9.json")))
+    s = dq.Sector(g["L"], g["n"], g["Q"], g["split"])
+    st = pack(g["state_digits"], 2)
+    assert int(to_host_u64(s.rank(to_dev(np.array([st], dtype=np.uint64))))[0]) == g["index"]
+    assert int(to_host_u64(s.unrank(to_dev(np.array([g["index"]], dtype=np.uint64))))[0]) == st
+
+
+def test_invalid_inputs_are_flagged_and_counted():
+    s = dq.Sector(9, 4, 2, [3, 3, 3])
+    bad_states = np.array([pack([1] * 5 + [0] * 4, 2), 0, 1 << 9, (1 << 9) | 0b1111, 0b111100000,
+                           ~np.uint64(0)], dtype=np.uint64)
+    idx, cnt = s.rank(to_dev(bad_states), count_invalid=True)
+    h = to_host_u64(idx)
+    assert np.all(h[[0, 1, 2, 3, 5]] == BAD)
+    assert h[4] != BAD                      # 111100000 has four particles: valid
+    assert int(cnt.item()) == 5
+    st, cnt = s.unrank(to_dev(np.array([0, 125, 126, 10 ** 12], dtype=np.uint64)), count_invalid=True)
+    h = to_host_u64(st)
+    assert h[2] == BAD and h[3] == BAD and int(cnt.item()) == 2
+    with pytest.raises(dq.DcsError) as e:
+        s.enumerate(100, 27)
+    assert e.value.code == -2
+    s3 = dq.Sector(4, 4, 3, [2, 2])   # Q=3: digit 3 (binary 11) is not a valid digit
+    st = np.array([pack([3, 1, 0, 0], 4), pack([2, 2, 0, 0], 4)], dtype=np.uint64)
+    h = to_host_u64(s3.rank(to_dev(st)))
+    assert h[0] == BAD and h[1] != BAD
+
+
+def test_degenerate_sectors():
+    for Q, L, n in [(2, 1, 0), (2, 1, 1), (2, 20, 0), (2, 20, 20), (3, 5, 10), (2, 64, 1)]:
+        s = dq.Sector(L, n, Q, None if L < 64 else [8] * 8)
+        ns = native.NativeSector(Q, L, n, s.split)
+        assert s.dim == ns.dim
+        m = min(s.dim, 1 << 16)
+        e = to_host_u64(s.enumerate(0, m))
+        assert np.array_equal(e, ns.unrank(np.arange(m)))
+
+
+@pytest.mark.parametrize("L,n,split", [(32, 16, [8, 8, 8, 8]), (34, 17, [8, 8, 9, 9]),
+                                       (28, 14, [7, 7, 7, 7]), (24, 12, [8, 8, 8]),
+                                       (40, 20, [5, 5, 5, 5, 5, 5, 5, 5]),
+                                       (36, 18, [6, 6, 6, 6, 6, 6])])
+def test_random_states_large(L, n, split):
+    """2^20 random states (uniform n-subsets) and random indices against the C oracle.
+    L=36 and L=40 have more than 2^32 states: the 64-bit kernels."""
+    ns = native.NativeSector(2, L, n, split)
+    s = dq.Sector(L, n, 2, split)
+    assert s.dim == ns.dim == math.comb(L, n)
+    states = synth.pack_digits(synth.random_states(2, L, n, 1 << 20, seed=L), 2)
+    got = to_host_u64(s.rank(to_dev(states)))
+    assert np.array_equal(got, ns.rank(states))
+    rng = np.random.default_rng(L)
+    idx = rng.integers(0, s.dim, 1 << 20, dtype=np.uint64)
+    idx[:3] = [0, s.dim - 1, s.dim // 2]
+    got = to_host_u64(s.unrank(to_dev(idx)))
+    assert np.array_equal(got, ns.unrank(idx))
+
+
+def test_full_sector_bijection_L32():
+    """Every one of the 601,080,390 states of L=32, n=16 (8/8/8/8): the GPU
+    enumeration equals the oracle's nested generation (no offsets or strides),
+    and rank maps it back to its position."""
+    L, n, split = 32, 16, [8, 8, 8, 8]
+    s = dq.Sector(L, n, 2, split)
+    ns = native.NativeSector(2, L, n, split)
+    chunk = 1 << 26
+    pos = 0
+    for ref in ns.iterate(chunk):
+        cnt = len(ref)
+        st = s.enumerate(pos, cnt)
+        idx = s.rank(st)
+        ar = torch.arange(pos, pos + cnt, dtype=torch.int64, device=DEV)
+        assert bool((idx == ar).all())
+        assert np.array_equal(to_host_u64(st), ref)
+        pos += cnt
+        say("bijection", pos)
+    assert pos == s.dim == math.comb(32, 16)

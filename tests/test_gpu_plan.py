@@ -1,0 +1,84 @@
+"""Many sectors in one launch (dcs_plan_*): parity with the oracle and with the
+one-sector launches."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2407_14591_amd as dq
+import synth
+from gpu_common import DEV, rel_err, say
+from oracle import native
+from oracle.hamiltonian import apply_h
+from oracle.sector import BruteSector, default_split
+
+pytestmark = pytest.mark.gpu
+
+
+def dev_f64(a):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device=DEV)
+
+
+def test_mixed_small_plan():
+    rng = np.random.default_rng(4)
+    specs = [(2, 10, n, None) for n in range(0, 11)] + [(3, 6, n, [2, 2, 2]) for n in (0, 3, 6, 12)] + \
+            [(4, 5, 7, [2, 3]), (2, 12, 6, [1, 2, 3, 4, 1, 1])]
+    items, refs, xs = [], [], []
+    for Q, L, n, sp in specs:
+        b = BruteSector(Q, L, n, sp or default_split(Q, L))
+        bonds = synth.chain_bonds(L, 1) + synth.chain_bonds(L, 2)
+        jxy, jz = rng.normal(size=len(bonds)), rng.normal(size=len(bonds))
+        x = rng.normal(size=b.dim)
+        refs.append(apply_h(b, bonds, jxy, jz, x))
+        items.append((dq.Sector(L, n, Q, sp), dq.Terms(bonds), dev_f64(jxy), dev_f64(jz)))
+        xs.append(x)
+    plan = dq.Plan(items)
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        ys = plan.apply([torch.tensor(x, device=DEV).to(dt) for x in xs])
+        for (s, _, _, _), y, r in zip(items, ys, refs):
+            assert rel_err(y.double().cpu().numpy(), r) <= tol, (s.L, s.n, s.Q)
+        # second apply with new vectors reuses the plan
+        ys2 = plan.apply([torch.tensor(2 * x, device=DEV).to(dt) for x in xs])
+        for y, y2 in zip(ys, ys2):
+            assert torch.allclose(2 * y, y2, rtol=1e-6 if dt == torch.float32 else 1e-14, atol=1e-5)
+
+
+def batched_workload():
+    """Every sector n = 0..L of periodic spin-1/2 XXZ chains L = 20, 22, 24, 26 and the
+    spin-1 chains L = 12..16 at total Sz = 0 (n = L), J = Delta = 1."""
+    specs = [(2, L, n) for L in (20, 22, 24, 26) for n in range(0, L + 1)]
+    specs += [(3, L, L) for L in range(12, 17)]
+    return specs
+
+
+def test_batched_workload_one_launch():
+    specs = batched_workload()
+    items, xs = [], []
+    total = 0
+    for Q, L, n in specs:
+        bonds, jxy, jz = synth.xxz_chain(L, 1.0, 1.0)
+        s = dq.Sector(L, n, Q)
+        items.append((s, dq.Terms(bonds), dev_f64(jxy), dev_f64(jz)))
+        g = torch.Generator(device=DEV)
+        g.manual_seed(1000 * L + 10 * n + Q)
+        xs.append(torch.randn(s.dim, generator=g, device=DEV, dtype=torch.float32))
+        total += s.dim
+    assert len(items) == 101 and total == 97_016_151
+    plan = dq.Plan(items)
+    ys = plan.apply(xs)
+    torch.cuda.synchronize()
+    # the one-launch result equals the per-sector launches bit for bit
+    for (s, t, j, z), x, y in zip(items, xs, ys):
+        y1 = dq.hamiltonian_apply(s, t, j, z, x)
+        assert torch.equal(y, y1), (s.L, s.n, s.Q)
+    # and the oracle on sampled rows of a few sectors
+    rng = np.random.default_rng(2)
+    for idx in (0, 30, 60, 95, 96, 100):
+        (s, _, _, _), x, y = items[idx], xs[idx], ys[idx]
+        Q, L, n = specs[idx]
+        bonds, jxy, jz = synth.xxz_chain(L, 1.0, 1.0)
+        ns = native.NativeSector(Q, L, n, s.split)
+        rows = rng.integers(0, s.dim, min(s.dim, 20000)).astype(np.uint64)
+        ref = native.hx_rows(ns, native.NativeTerms(bonds, jxy, jz), x.cpu().numpy(), rows)
+        got = y[torch.tensor(rows.astype(np.int64), device=DEV)].double().cpu().numpy()
+        say("plan sector", Q, L, n, rel_err(got, ref))
+        assert rel_err(got, ref) <= 1e-5
