@@ -104,6 +104,9 @@ def main(argv=None) -> int:
     ap.add_argument("--variants", default="f32k8,f32k1,f64k1",
                     help="comma list; the first is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also time a plain device copy of the FP32 vector size (the reference "
+                         "kernel for scaling the HBM byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -130,6 +133,16 @@ def main(argv=None) -> int:
     stream = torch.cuda.current_stream(dev)
     results = {}
     x_host = None
+    copy_info = None
+    if args.calibrate_copy:
+        a = torch.empty(D, dtype=torch.float32, device=dev).normal_(generator=gen)
+        b = torch.empty_like(a)
+        el = time_variant(lambda: b.copy_(a), stream, args.steps, args.warmup)
+        copy_info = {"bytes_per_copy": 2 * a.numel() * 4, "read_bytes": a.numel() * 4,
+                     "write_bytes": a.numel() * 4,
+                     "GBs": 2 * a.numel() * 4 * args.steps / el / 1e9}
+        del a, b
+        torch.cuda.empty_cache()
     for v in args.variants.split(","):
         dt = torch.float32 if v.startswith("f32") else torch.float64
         k = int(v.split("k")[1])
@@ -178,6 +191,8 @@ def main(argv=None) -> int:
         "variants": {k_: {"states_per_s": v_["states_per_s"], "ms": v_["seconds_per_step"] * 1e3,
                           "achieved_GBs": v_["achieved_GBs"]} for k_, v_ in results.items()},
     }
+    if copy_info:
+        out["copy_calibration"] = copy_info
     if "f64k1" in results:
         out["speedup_vs_plain_f64_per_column"] = r["states_per_s"] / results["f64k1"]["states_per_s"]
     if x_host is not None:

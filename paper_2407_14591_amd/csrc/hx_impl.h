@@ -41,9 +41,9 @@ struct HxParams {
     void *gx;           // adjoint: H g
     double *partials;   // adjoint: [num_wgs][2*nbonds + L]
     const double *jxy, *jz, *h;
-    uint64_t rows_per_wg;
+    uint64_t tiles;          // ceil(dim / kHxThreads): one tile per workgroup pass
     int nbonds;
-    int xcd_groups;     // workgroups per XCD when the grid is a multiple of 8, else 0
+    int xcd_groups;          // workgroups per XCD when the grid is a multiple of 8, else 0
     uint16_t cls_beg[kMaxClasses + 1];
     uint32_t pos[kMaxBonds];
 };
@@ -54,30 +54,66 @@ struct Acc {
 };
 
 template <typename T, int K>
-__device__ __forceinline__ void gather_fma(Acc<T, K> &acc, T amp, const T *__restrict__ x,
-                                           uint64_t col) {
+__device__ __forceinline__ Acc<T, K> gather(const T *__restrict__ x, uint64_t col) {
+    Acc<T, K> v;
     const T *p = x + col * K;
-    if constexpr (K == 1) {
-        acc.v[0] += amp * p[0];
-    } else if constexpr (sizeof(T) * K % 16 == 0) {
+    if constexpr (K > 1 && sizeof(T) * K % 16 == 0) {
         constexpr int V = 16 / sizeof(T);
+        typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
 #pragma unroll
         for (int c = 0; c < K; c += V) {
-            typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
-            const vec_t v = *reinterpret_cast<const vec_t *>(p + c);
+            const vec_t u = *reinterpret_cast<const vec_t *>(p + c);
 #pragma unroll
-            for (int e = 0; e < V; ++e) acc.v[c + e] += amp * v[e];
+            for (int e = 0; e < V; ++e) v.v[c + e] = u[e];
         }
     } else {
 #pragma unroll
-        for (int c = 0; c < K; ++c) acc.v[c] += amp * p[c];
+        for (int c = 0; c < K; ++c) v.v[c] = p[c];
     }
+    return v;
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void fma_acc(Acc<T, K> &acc, T amp, const Acc<T, K> &v) {
+#pragma unroll
+    for (int c = 0; c < K; ++c) acc.v[c] += amp * v.v[c];
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void gather_fma(Acc<T, K> &acc, T amp, const T *__restrict__ x,
+                                           uint64_t col) {
+    fma_acc<T, K>(acc, amp, gather<T, K>(x, col));
 }
 
 __device__ __forceinline__ uint32_t xcd_chunk(int xcd_groups) {
     const uint32_t b = blockIdx.x;
     if (!xcd_groups) return b;
     return (b & 7u) * (uint32_t)xcd_groups + (b >> 3);
+}
+
+// Tiles of this workgroup.  The tiles are grouped into super-tiles of one
+// pass of an XCD's workgroups (xcd_groups tiles); super-tile s goes to XCD
+// s % 8 (dispatch order blockIdx % 8) and workgroup j of that XCD takes tile j
+// of it.  The whole GPU thus sweeps one narrow window of rows: hops inside a
+// super-tile stay in the XCD's L2, and the farther hop targets of all XCDs
+// share one small footprint in the Infinity Cache.
+struct TileIter {
+    uint64_t xcd, j, groups, tiles, m;
+    bool linear;
+    __device__ __forceinline__ uint64_t tile() const {
+        return linear ? blockIdx.x + m * gridDim.x : (8 * m + xcd) * groups + j;
+    }
+};
+
+__device__ __forceinline__ TileIter my_tiles(uint64_t tiles, int xcd_groups) {
+    TileIter it;
+    it.tiles = tiles;
+    it.m = 0;
+    it.linear = xcd_groups == 0;
+    it.xcd = blockIdx.x & 7u;
+    it.j = blockIdx.x >> 3;
+    it.groups = (uint64_t)xcd_groups;
+    return it;
 }
 
 // Per-row state kept by a thread: subsystem words, the LDS row of C_k[lambda_k],
@@ -119,7 +155,36 @@ __device__ __forceinline__ IdxT hop_col(const SectorDesc &sd, const Tables<IdxT>
     }
 }
 
-// One bond class (A, B): applies every bond of the class to the row.
+// Q = 2, one bond t of class (A, B), without branches: the diagonal term is
+// added to `diag`; the returned column is the reached state's index when the
+// two sites differ (a hop) and the row itself otherwise, with `amp` = 0 then.
+// For a non-hop the table reads stay inside the current lambda rows, so every
+// LDS address is valid whatever the lane's state.
+template <typename IdxT, typename T, int NMAX, int A, int B, typename PT>
+__device__ __forceinline__ IdxT q2_bond(const PT &P, const SectorDesc &sd, const Tables<IdxT> &Tb,
+                                        const RowState<IdxT, NMAX> &r, IdxT row, int t,
+                                        const T *bamp, const T *bjz, T &amp, T &diag) {
+    const uint32_t pos = P.pos[t];
+    const uint32_t pil = pos & 0xFFu, pjl = (pos >> 8) & 0xFFu;
+    const uint32_t bi = (r.w[A] >> pil) & 1u, bj = (r.w[B] >> pjl) & 1u;
+    const bool hop = bi != bj;
+    const T jz = bjz[t];
+    diag += hop ? -jz : jz;
+    amp = hop ? bamp[t] : (T)0;
+    IdxT col;
+    if constexpr (A == B) {
+        col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, r.w[A] ^ ((1u << pil) | (1u << pjl)), 0, 0);
+    } else {
+        const int dl = hop ? (bi ? -1 : 1) : 0;
+        col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, r.w[A] ^ (1u << pil), r.w[B] ^ (1u << pjl),
+                                        dl);
+    }
+    return hop ? col : row;
+}
+
+// One bond class (A, B): applies every bond of the class to the row.  For Q = 2
+// the bonds go in batches: all the batch's columns, then all its gathers in
+// flight together, then the multiply-adds.
 template <typename IdxT, typename T, int K, int NMAX, bool Q2, int A, int B, typename PT>
 __device__ __forceinline__ void apply_class(const PT &P, const SectorDesc &sd,
                                             const Tables<IdxT> &Tb, const RowState<IdxT, NMAX> &r,
@@ -130,25 +195,33 @@ __device__ __forceinline__ void apply_class(const PT &P, const SectorDesc &sd,
     } else {
         const int cls = A * NMAX - A * (A - 1) / 2 + (B - A);
         const int beg = P.cls_beg[cls], end = P.cls_beg[cls + 1];
-        for (int t = beg; t < end; ++t) {
-            const uint32_t pos = P.pos[t];
-            const uint32_t pil = pos & 0xFFu, pjl = (pos >> 8) & 0xFFu;
-            if constexpr (Q2) {
-                const uint32_t bi = (r.w[A] >> pil) & 1u, bj = (r.w[B] >> pjl) & 1u;
-                const T jz = bjz[t];
-                diag += (bi == bj) ? jz : -jz;
-                if (bi != bj) {
-                    IdxT col;
-                    if constexpr (A == B) {
-                        col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row,
-                                                        r.w[A] ^ ((1u << pil) | (1u << pjl)), 0, 0);
+        if constexpr (Q2) {
+            // batches of NB bonds; the last batch of a class is cut by a uniform guard,
+            // its unused slots gather x[row] with amplitude 0
+            constexpr int NB = K <= 2 ? 8 : 4;
+            for (int t = beg; t < end; t += NB) {
+                T a[NB];
+                IdxT c[NB];
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    if (t + u < end) {
+                        c[u] = q2_bond<IdxT, T, NMAX, A, B>(P, sd, Tb, r, row, t + u, bamp, bjz, a[u],
+                                                            diag);
                     } else {
-                        col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, r.w[A] ^ (1u << pil),
-                                                        r.w[B] ^ (1u << pjl), bi ? -1 : 1);
+                        c[u] = row;
+                        a[u] = (T)0;
                     }
-                    gather_fma<T, K>(acc, bamp[t], x, (uint64_t)col);
                 }
-            } else {
+                Acc<T, K> v[NB];
+#pragma unroll
+                for (int u = 0; u < NB; ++u) v[u] = gather<T, K>(x, (uint64_t)c[u]);
+#pragma unroll
+                for (int u = 0; u < NB; ++u) fma_acc<T, K>(acc, a[u], v[u]);
+            }
+        } else {
+            for (int t = beg; t < end; ++t) {
+                const uint32_t pos = P.pos[t];
+                const uint32_t pil = pos & 0xFFu, pjl = (pos >> 8) & 0xFFu;
                 const uint32_t dm = (1u << sd.nb) - 1u;
                 const int Qm1 = sd.Q - 1;
                 const int di = (int)((r.w[A] >> pil) & dm), dj = (int)((r.w[B] >> pjl) & dm);
@@ -273,12 +346,13 @@ __global__ __launch_bounds__(kHxThreads) void hx_kernel(const HxParams P) {
     const Tables<IdxT> Tb = tables_at<IdxT>(lds, sd);
     const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
     T *__restrict__ y = reinterpret_cast<T *>(P.y);
-    const uint64_t chunk0 = (uint64_t)xcd_chunk(P.xcd_groups) * P.rows_per_wg;
-    const uint64_t chunk1 = min(chunk0 + P.rows_per_wg, sd.dim);
-    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (uint64_t tile = chunk0 + (uint64_t)wave * 64; tile < chunk1; tile += (uint64_t)nw * 64)
-        hx_tile<IdxT, T, K, NMAX, Q2>(P, sd, Tb, x, y, C.bamp, C.bjz, C.ladder, C.hf, P.h != nullptr,
-                                      tile, chunk1);
+    const uint64_t wrow = (uint64_t)(threadIdx.x >> 6) * 64;
+    for (TileIter it = my_tiles(P.tiles, P.xcd_groups); it.tile() < it.tiles; ++it.m) {
+        const uint64_t tile = it.tile() * kHxThreads + wrow;
+        if (tile < sd.dim)
+            hx_tile<IdxT, T, K, NMAX, Q2>(P, sd, Tb, x, y, C.bamp, C.bjz, C.ladder, C.hf,
+                                          P.h != nullptr, tile, sd.dim);
+    }
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -403,11 +477,11 @@ __global__ __launch_bounds__(kHxThreads) void adjoint_kernel(const HxParams P) {
     const T *__restrict__ g = reinterpret_cast<const T *>(P.g);
     T *__restrict__ gx = reinterpret_cast<T *>(P.gx);
 
-    const uint64_t chunk0 = (uint64_t)xcd_chunk(P.xcd_groups) * P.rows_per_wg;
-    const uint64_t chunk1 = min(chunk0 + P.rows_per_wg, sd.dim);
-    for (uint64_t tile = chunk0 + (uint64_t)wave * 64; tile < chunk1; tile += (uint64_t)nw * 64) {
+    for (TileIter it = my_tiles(P.tiles, P.xcd_groups); it.tile() < it.tiles; ++it.m) {
+        const uint64_t tile = it.tile() * kHxThreads + (uint64_t)wave * 64;
+        if (tile >= sd.dim) continue;
         const uint64_t row64 = tile + lane;
-        const bool active = row64 < chunk1;
+        const bool active = row64 < sd.dim;
         const IdxT row = (IdxT)(active ? row64 : tile);
         RowState<IdxT, NMAX> r;
         decode_row<IdxT, NMAX>(sd, Tb, row, r);
@@ -456,7 +530,7 @@ __global__ void adjoint_reduce(const double *__restrict__ partials, int nwg, int
 
 struct Grid {
     int wgs;
-    uint64_t rows_per_wg;
+    uint64_t tiles;
     int xcd_groups;
 };
 
@@ -466,21 +540,16 @@ inline Grid plan_grid(const dcs_sector *s, size_t lds_bytes) {
     const size_t lds_cu = 160 * 1024;
     int per_cu = (int)(lds_cu / (lds_bytes ? lds_bytes : 1));
     per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
-    const uint64_t tile = (uint64_t)(kHxThreads / 64) * 64;
-    uint64_t want = (uint64_t)cus * per_cu;
-    uint64_t tiles = (dim + tile - 1) / tile;
-    if (want > tiles) want = tiles;
-    if (want < 1) want = 1;
     Grid g;
-    g.rows_per_wg = ((dim + want - 1) / want + 63) / 64 * 64;
-    g.wgs = (int)((dim + g.rows_per_wg - 1) / g.rows_per_wg);
+    g.tiles = (dim + kHxThreads - 1) / kHxThreads;
+    uint64_t want = (uint64_t)cus * per_cu;
+    if (want > g.tiles) want = g.tiles;
+    if (want < 1) want = 1;
+    g.wgs = (int)want;
     g.xcd_groups = 0;
-    if (g.wgs >= 16) {
-        // round the grid up to a multiple of 8 so chunk = (b % 8) * groups + b / 8 is a bijection
-        const int groups = (g.wgs + 7) / 8;
-        g.wgs = groups * 8;
-        g.rows_per_wg = ((dim + g.wgs - 1) / g.wgs + 63) / 64 * 64;
-        g.xcd_groups = groups;
+    if (g.wgs >= 16 && g.tiles >= 64) {
+        g.xcd_groups = g.wgs / 8;
+        g.wgs = g.xcd_groups * 8;
     }
     return g;
 }
@@ -510,7 +579,7 @@ template <typename IdxT, typename T, int K, int NMAX>
 int launch_hx_t(const dcs_sector *s, HxParams &P, hipStream_t stream) {
     const size_t lds = s->desc.lay_bytes + coeff_lds_bytes<T>();
     const Grid g = plan_grid(s, lds);
-    P.rows_per_wg = g.rows_per_wg;
+    P.tiles = g.tiles;
     P.xcd_groups = g.xcd_groups;
     if (s->desc.Q == 2) {
         auto kern = hx_kernel<IdxT, T, K, NMAX, true>;
@@ -533,7 +602,7 @@ int launch_adj_t(const dcs_sector *s, HxParams &P, double *gjxy, double *gjz, do
     const size_t lds_plan = s->desc.lay_bytes + coeff_lds_bytes<double>() +
                             (size_t)(kHxThreads / 64) * nacc * sizeof(double);
     const Grid g = plan_grid(s, lds_plan);
-    P.rows_per_wg = g.rows_per_wg;
+    P.tiles = g.tiles;
     P.xcd_groups = g.xcd_groups;
     if (s->desc.Q == 2) {
         auto kern = adjoint_kernel<IdxT, T, NMAX, true>;
