@@ -31,6 +31,14 @@
  *    their kernels with 32-bit index arithmetic; larger ones with 64-bit.  The
  *    environment variable DCS_INDEX_BITS=64, read by dcs_sector_create, forces
  *    64-bit arithmetic (to test those kernels on small sectors).
+ *  - Two-pass product: for Q = 2 sectors with at least 2^22 states and two or
+ *    more subsystems, dcs_sector_create also builds a left/right view (cut after
+ *    N/2 subsystems) and dcs_hamiltonian_apply runs two kernels: one pass over
+ *    the rows for the bonds with a site right of the cut, then one over column
+ *    chunks for the bonds left of it (their hops keep the offset inside a run of
+ *    rows, so that pass reads x with L2 locality).  DCS_TWO_PASS_MIN_DIM (read
+ *    by dcs_sector_create) changes the 2^22 threshold; DCS_TWO_PASS=0 (read once
+ *    per process) forces the single pass.
  */
 #ifndef DCS_H
 #define DCS_H

@@ -80,6 +80,31 @@ struct SectorDev {
            inv_start_off = 0;
     // bytes the H*x kernels stage in LDS (c-table + decode + inverse tables)
     size_t lds_bytes = 0;
+    // work-queue counters of the H*x launches (8 per pass, zeroed by a kernel
+    // before each launch); calls on one sector must therefore not overlap
+    uint32_t *counters = nullptr;
+};
+constexpr int kNumCounters = 32;
+
+// Left/right view of a sector for the two-pass product.  Cut the subsystems at
+// K: for a fixed number m of particles in P_0..P_{K-1} ("left"), every left
+// configuration (w_0..w_{K-1}) owns one contiguous run of rows, of the same
+// length R(m) = D_Q(L - L_left, n - m), whose offsets are the right
+// configurations in canonical order.  A bond with both sites on the left moves
+// a row to the same offset of another run; a bond with both sites on the
+// right stays inside the run.
+constexpr int kMaxLeftM = 40;
+struct LeftInfo {
+    int K = 0;                 // 0: no two-pass view
+    int L_left = 0;
+    int m_lo = 0, m_count = 0; // left particle numbers with rows
+    uint32_t lbase[kMaxLeftM]; // first left configuration of block m - m_lo
+    uint32_t nleft[kMaxLeftM];
+    uint64_t ncols[kMaxLeftM]; // run length R(m)
+    uint32_t word_shift[kMaxSub];  // bit of P_k's word inside a packed left word
+    void *d_words = nullptr;   // uint32 packed left words, all blocks in order
+    void *d_runs = nullptr;    // run start (IdxT) of every left configuration
+    size_t count = 0;
 };
 
 }  // namespace dcs
@@ -90,6 +115,7 @@ struct dcs_sector {
     bool wide;  // 64-bit indices (dim >= 2^32)
     dcs::SectorDesc desc;
     dcs::SectorDev dev;
+    dcs::LeftInfo left;
 };
 
 struct dcs_terms {

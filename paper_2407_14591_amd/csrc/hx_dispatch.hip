@@ -1,12 +1,16 @@
 // Dispatch of the matrix-free H*x and adjoint launchers by index type, value type,
 // column count and subsystem bound; the instantiations live in hx_f*_k*.hip and
 // hx_adjoint_f*.hip so they compile in parallel.
+#include <cstdlib>
+
 #include "hx_impl.h"
 
 namespace dcs {
 namespace hx {
-#define DCS_HX_EXTERN(IDX, T, K, NMAX) \
-    extern template int launch_hx_t<IDX, T, K, NMAX>(const dcs_sector *, HxParams &, hipStream_t);
+#define DCS_HX_EXTERN(IDX, T, K, NMAX)                                                          \
+    extern template int launch_hx_t<IDX, T, K, NMAX>(const dcs_sector *, HxParams &, hipStream_t); \
+    extern template int launch_left_t<IDX, T, K, NMAX>(const dcs_sector *, const HxParams &,      \
+                                                       hipStream_t);
 #define DCS_HX_EXTERN_ALL(T, K)           \
     DCS_HX_EXTERN(uint32_t, T, K, 4)      \
     DCS_HX_EXTERN(uint32_t, T, K, 8)      \
@@ -34,13 +38,38 @@ DCS_ADJ_EXTERN(uint64_t, double, 8)
 
 namespace {
 
+// The two-pass form (LeftInfo) for Q = 2 sectors that have a left/right view:
+// hx_kernel without the left bond classes, then the left pass adding them.
+// DCS_TWO_PASS=0 in the environment selects the single pass everywhere.
+inline bool two_pass_enabled() {
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("DCS_TWO_PASS");
+        v = (e && e[0] == '0') ? 0 : 1;
+    }
+    return v == 1;
+}
+
+template <typename IdxT, typename T, int K, int NMAX>
+int launch_one(const dcs_sector *s, HxParams &P, hipStream_t stream) {
+    if (s->left.K > 0 && s->desc.Q == 2 && two_pass_enabled()) {
+        P.cls_mask = ~left_class_mask(s->left.K, NMAX);
+        P.far_below = s->left.K;  // the mixed classes leave the sweep window
+        if (int r = launch_hx_t<IdxT, T, K, NMAX>(s, P, stream)) return r;
+        return launch_left_t<IdxT, T, K, NMAX>(s, P, stream);
+    }
+    // one pass: the bonds touching the first half of the subsystems jump far
+    P.far_below = s->desc.dim >= (1ull << 22) ? s->desc.N / 2 : 0;
+    return launch_hx_t<IdxT, T, K, NMAX>(s, P, stream);
+}
+
 template <typename IdxT, typename T, int NMAX>
 int launch_hx_k(const dcs_sector *s, HxParams &P, int k, hipStream_t stream) {
     switch (k) {
-        case 1: return launch_hx_t<IdxT, T, 1, NMAX>(s, P, stream);
-        case 2: return launch_hx_t<IdxT, T, 2, NMAX>(s, P, stream);
-        case 4: return launch_hx_t<IdxT, T, 4, NMAX>(s, P, stream);
-        default: return launch_hx_t<IdxT, T, 8, NMAX>(s, P, stream);
+        case 1: return launch_one<IdxT, T, 1, NMAX>(s, P, stream);
+        case 2: return launch_one<IdxT, T, 2, NMAX>(s, P, stream);
+        case 4: return launch_one<IdxT, T, 4, NMAX>(s, P, stream);
+        default: return launch_one<IdxT, T, 8, NMAX>(s, P, stream);
     }
 }
 

@@ -22,6 +22,7 @@
 // Y is written exactly once per element, with no atomics.
 #pragma once
 
+#include <algorithm>
 #include <cstring>
 
 #include "device_common.h"
@@ -42,6 +43,10 @@ struct HxParams {
     double *partials;   // adjoint: [num_wgs][2*nbonds + L]
     const double *jxy, *jz, *h;
     uint64_t tiles;          // ceil(dim / kHxThreads): one tile per workgroup pass
+    uint32_t *counters;      // per-XCD tile queues (8), or NULL for a static schedule
+    uint64_t per_xcd;        // tiles of one XCD's range
+    uint64_t cls_mask;       // bond classes this launch applies (bit class_id)
+    int far_below;           // classes (a, b) with a < far_below gather non-temporally
     int nbonds;
     int xcd_groups;          // workgroups per XCD when the grid is a multiple of 8, else 0
     uint16_t cls_beg[kMaxClasses + 1];
@@ -69,6 +74,28 @@ __device__ __forceinline__ Acc<T, K> gather(const T *__restrict__ x, uint64_t co
     } else {
 #pragma unroll
         for (int c = 0; c < K; ++c) v.v[c] = p[c];
+    }
+    return v;
+}
+
+// Gather for a hop that leaves the sweep window: non-temporal, so the single-use
+// line does not push reusable lines of the window out of L2.
+template <typename T, int K>
+__device__ __forceinline__ Acc<T, K> gather_nt(const T *__restrict__ x, uint64_t col) {
+    Acc<T, K> v;
+    const T *p = x + col * K;
+    if constexpr (K > 1 && sizeof(T) * K % 16 == 0) {
+        constexpr int V = 16 / sizeof(T);
+        typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
+#pragma unroll
+        for (int c = 0; c < K; c += V) {
+            const vec_t u = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(p + c));
+#pragma unroll
+            for (int e = 0; e < V; ++e) v.v[c + e] = u[e];
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < K; ++c) v.v[c] = __builtin_nontemporal_load(p + c);
     }
     return v;
 }
@@ -114,6 +141,30 @@ __device__ __forceinline__ TileIter my_tiles(uint64_t tiles, int xcd_groups) {
     it.j = blockIdx.x >> 3;
     it.groups = (uint64_t)xcd_groups;
     return it;
+}
+
+// Dynamic tile queue per XCD.  XCD x (dispatch order blockIdx % 8) owns the
+// contiguous tile range [x * per_xcd, (x+1) * per_xcd); its workgroups take
+// the next tile from one counter, so at any time they work inside one narrow
+// window of that range and the hop targets near the window stay in the XCD's
+// L2 (a static round robin lets the workgroups drift apart over thousands of
+// tiles).  The counters are zeroed by zero_counters before the launch.
+__device__ __forceinline__ bool next_tile(uint32_t *counters, uint64_t tiles, uint64_t per_xcd,
+                                          uint32_t *slot, uint64_t &t) {
+    const uint32_t xcd = blockIdx.x & 7u;
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = atomicAdd(counters + xcd, 1u);
+    __syncthreads();
+    const uint64_t lt = *slot;
+    const uint64_t base = (uint64_t)xcd * per_xcd;
+    if (lt >= per_xcd || base + lt >= tiles) return false;
+    t = base + lt;
+    return true;
+}
+
+template <int Unused = 0>
+__global__ void zero_counters(uint32_t *c, int n) {
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
 }
 
 // Per-row state kept by a thread: subsystem words, the LDS row of C_k[lambda_k],
@@ -213,8 +264,13 @@ __device__ __forceinline__ void apply_class(const PT &P, const SectorDesc &sd,
                     }
                 }
                 Acc<T, K> v[NB];
+                if (A < P.far_below) {
 #pragma unroll
-                for (int u = 0; u < NB; ++u) v[u] = gather<T, K>(x, (uint64_t)c[u]);
+                    for (int u = 0; u < NB; ++u) v[u] = gather_nt<T, K>(x, (uint64_t)c[u]);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) v[u] = gather<T, K>(x, (uint64_t)c[u]);
+                }
 #pragma unroll
                 for (int u = 0; u < NB; ++u) fma_acc<T, K>(acc, a[u], v[u]);
             }
@@ -261,7 +317,7 @@ struct ClassLoop {
                                                T &diag) {
         if constexpr (A < NMAX) {
             if constexpr (B < NMAX) {
-                if (B < sd.N)
+                if (B < sd.N && ((P.cls_mask >> (A * NMAX - A * (A - 1) / 2 + (B - A))) & 1u))
                     apply_class<IdxT, T, K, NMAX, Q2, A, B>(P, sd, Tb, r, row, x, bamp, bjz, ladder,
                                                             acc, diag);
                 ClassLoop<IdxT, T, K, NMAX, Q2, A, B + 1>::run(P, sd, Tb, r, row, x, bamp, bjz,
@@ -347,11 +403,145 @@ __global__ __launch_bounds__(kHxThreads) void hx_kernel(const HxParams P) {
     const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
     T *__restrict__ y = reinterpret_cast<T *>(P.y);
     const uint64_t wrow = (uint64_t)(threadIdx.x >> 6) * 64;
+    if (P.counters) {
+        __shared__ uint32_t slot;
+        uint64_t t;
+        while (next_tile(P.counters, P.tiles, P.per_xcd, &slot, t)) {
+            const uint64_t tile = t * kHxThreads + wrow;
+            if (tile < sd.dim)
+                hx_tile<IdxT, T, K, NMAX, Q2>(P, sd, Tb, x, y, C.bamp, C.bjz, C.ladder, C.hf,
+                                              P.h != nullptr, tile, sd.dim);
+        }
+        return;
+    }
     for (TileIter it = my_tiles(P.tiles, P.xcd_groups); it.tile() < it.tiles; ++it.m) {
         const uint64_t tile = it.tile() * kHxThreads + wrow;
         if (tile < sd.dim)
             hx_tile<IdxT, T, K, NMAX, Q2>(P, sd, Tb, x, y, C.bamp, C.bjz, C.ladder, C.hf,
                                           P.h != nullptr, tile, sd.dim);
+    }
+}
+
+// ---------------------------------------------------------------- two-pass product, left pass
+//
+// For a sector cut at K subsystems (LeftInfo), the bonds with both sites in
+// P_0..P_{K-1} move a row to the same offset of another run (one run per left
+// configuration).  The left pass walks the rows column chunk by column chunk:
+// a tile holds a chunk of CC consecutive offsets (one 128-byte line of x per
+// run) for LPT left configurations, and the tiles of one chunk are adjacent in
+// the XCD sweep, so the whole left neighbourhood of a chunk is read while it
+// sits in L2.  It adds the left bonds' hops and diagonal terms to y; the
+// right and mixed bonds are applied by hx_kernel (class mask) in a first pass.
+struct LeftParams {
+    SectorDesc sd;
+    const char *blob;
+    const void *x;
+    void *y;
+    const double *jxy, *jz, *h;  // h is not used by this pass (NULL)
+    const uint32_t *words;       // packed left words of every left configuration
+    const void *runs;            // first row (IdxT) of every left configuration
+    uint64_t tiles;
+    uint32_t *counters;
+    uint64_t tiles_per_xcd;
+    uint64_t cls_mask;
+    int far_below;
+    int nbonds;
+    int xcd_groups;
+    int K;
+    int m_count;
+    uint32_t lbase[kMaxLeftM], nleft[kMaxLeftM], nlg[kMaxLeftM];
+    uint64_t ncols[kMaxLeftM];
+    uint64_t tbase[kMaxLeftM + 1];
+    uint32_t word_shift[kMaxSub];
+    uint16_t cls_beg[kMaxClasses + 1];
+    uint32_t pos[kMaxBonds];
+};
+
+template <typename T, int K>
+constexpr int left_chunk_cols() {
+    return (int)(128 / (K * sizeof(T))) > 0 ? (int)(128 / (K * sizeof(T))) : 1;
+}
+
+template <typename IdxT, typename T, int K, int NMAX>
+__global__ __launch_bounds__(kHxThreads) void left_kernel(const LeftParams P) {
+    extern __shared__ __align__(16) char lds[];
+    const SectorDesc &sd = P.sd;
+    stage_blob(lds, P.blob, sd.lay_bytes);
+    const CoeffLds<T> C(lds, sd.lay_bytes);
+    stage_coefficients<T, true>(P, sd, C.bamp, C.bjz, C.ladder, C.hf);
+    __syncthreads();
+    const Tables<IdxT> Tb = tables_at<IdxT>(lds, sd);
+    const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
+    T *__restrict__ y = reinterpret_cast<T *>(P.y);
+    const IdxT *__restrict__ runs = reinterpret_cast<const IdxT *>(P.runs);
+    constexpr int CC = left_chunk_cols<T, K>();
+    constexpr int LPT = kHxThreads / CC;
+    const uint32_t u = threadIdx.x;
+    // adjacent column chunks share cache lines of misaligned runs: one XCD takes a
+    // contiguous range of tiles through its queue
+    __shared__ uint32_t slot;
+    uint64_t t = 0;
+    uint64_t lin = blockIdx.x;
+    for (;;) {
+        if (P.counters) {
+            if (!next_tile(P.counters, P.tiles, P.tiles_per_xcd, &slot, t)) break;
+        } else {
+            if (lin >= P.tiles) break;
+            t = lin;
+            lin += gridDim.x;
+        }
+        int mi = 0;
+        while (mi + 1 < P.m_count && P.tbase[mi + 1] <= t) ++mi;
+        const uint32_t local = (uint32_t)(t - P.tbase[mi]);
+        const uint32_t cc = local / P.nlg[mi], lg = local - cc * P.nlg[mi];
+        const uint32_t li = lg * LPT + u / CC;
+        const uint64_t col = (uint64_t)cc * CC + u % CC;
+        const bool active = li < P.nleft[mi] && col < P.ncols[mi];
+        const uint32_t cfg = P.lbase[mi] + (active ? li : 0u);
+        const uint32_t pw = P.words[cfg];
+        RowState<IdxT, NMAX> r;
+        int lam = 0;
+#pragma unroll
+        for (int k = 0; k < NMAX; ++k) {
+            if (k < P.K) {
+                const uint32_t w = (pw >> P.word_shift[k]) & ((1u << sd.wbits[k]) - 1u);
+                r.w[k] = w;
+                r.rb[k] = sd.ctab_row0[k] + (uint32_t)(lam - sd.lam_lo[k]) * sd.ctab_rowlen[k];
+                r.c[k] = Tb.ctab[r.rb[k] + w];
+                lam += digit_sum(sd, w);
+            } else {
+                r.w[k] = 0;
+                r.rb[k] = 0;
+                r.c[k] = 0;
+            }
+        }
+        const IdxT row = runs[cfg] + (IdxT)(active ? col : 0);
+        Acc<T, K> acc;
+#pragma unroll
+        for (int c = 0; c < K; ++c) acc.v[c] = (T)0;
+        T diag = (T)0;
+        ClassLoop<IdxT, T, K, NMAX, true, 0, 0>::run(P, sd, Tb, r, row, x, C.bamp, C.bjz, C.ladder,
+                                                     acc, diag);
+        if (active) {
+            const Acc<T, K> xr = gather<T, K>(x, (uint64_t)row);
+            T *yr = y + (uint64_t)row * K;
+            if constexpr (K > 1 && sizeof(T) * K % 16 == 0) {
+                constexpr int V = 16 / sizeof(T);
+                typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
+#pragma unroll
+                for (int c = 0; c < K; c += V) {
+                    vec_t yv = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(yr + c));
+#pragma unroll
+                    for (int e = 0; e < V; ++e) yv[e] += acc.v[c + e] + diag * xr.v[c + e];
+                    __builtin_nontemporal_store(yv, reinterpret_cast<vec_t *>(yr + c));
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < K; ++c)
+                    __builtin_nontemporal_store(__builtin_nontemporal_load(yr + c) + acc.v[c] + diag * xr.v[c],
+                                                yr + c);
+            }
+        }
     }
 }
 
@@ -565,6 +755,8 @@ inline int fill_params(const dcs_sector *s, const dcs_terms *t, int nmax, const 
     P.jz = jz;
     P.h = h;
     P.nbonds = bp.nbonds;
+    P.cls_mask = ~0ull;
+    P.far_below = 0;
     for (int c = 0; c <= bp.nclasses; ++c) P.cls_beg[c] = bp.cls_beg[c];
     for (int b = 0; b < bp.nbonds; ++b) P.pos[b] = bp.pos[b];
     return DCS_OK;
@@ -581,6 +773,13 @@ int launch_hx_t(const dcs_sector *s, HxParams &P, hipStream_t stream) {
     const Grid g = plan_grid(s, lds);
     P.tiles = g.tiles;
     P.xcd_groups = g.xcd_groups;
+    P.counters = nullptr;
+    P.per_xcd = 0;
+    if (g.xcd_groups && s->dev.counters) {
+        P.counters = s->dev.counters;
+        P.per_xcd = (g.tiles + 7) / 8;
+        zero_counters<0><<<1, 64, 0, stream>>>(P.counters, 8);
+    }
     if (s->desc.Q == 2) {
         auto kern = hx_kernel<IdxT, T, K, NMAX, true>;
         if (int r = ensure_lds(kern, lds)) return r;
@@ -617,6 +816,67 @@ int launch_adj_t(const dcs_sector *s, HxParams &P, double *gjxy, double *gjz, do
     adjoint_reduce<0><<<(nacc + 255) / 256, 256, 0, stream>>>(P.partials, g.wgs, P.nbonds, s->desc.L,
                                                            gjxy, gjz, gh);
     return check_hip(hipGetLastError(), "adjoint reduction launch");
+}
+
+// Bond classes (a, b) with b < K: both sites on the left of the cut.
+inline uint64_t left_class_mask(int K, int nmax) {
+    uint64_t m = 0;
+    for (int a = 0; a < K; ++a)
+        for (int b = a; b < K; ++b) m |= 1ull << class_id(a, b, nmax);
+    return m;
+}
+
+template <typename IdxT, typename T, int K, int NMAX>
+int launch_left_t(const dcs_sector *s, const HxParams &H, hipStream_t stream) {
+    const LeftInfo &li = s->left;
+    LeftParams P;
+    memset(&P, 0, sizeof(P));
+    P.sd = H.sd;
+    P.blob = H.blob;
+    P.x = H.x;
+    P.y = H.y;
+    P.jxy = H.jxy;
+    P.jz = H.jz;
+    P.h = nullptr;
+    P.words = (const uint32_t *)li.d_words;
+    P.runs = li.d_runs;
+    P.nbonds = H.nbonds;
+    P.K = li.K;
+    P.m_count = li.m_count;
+    P.cls_mask = left_class_mask(li.K, NMAX);
+    memcpy(P.cls_beg, H.cls_beg, sizeof(P.cls_beg));
+    memcpy(P.pos, H.pos, sizeof(P.pos));
+    for (int k = 0; k < kMaxSub; ++k) P.word_shift[k] = li.word_shift[k];
+    constexpr int CC = left_chunk_cols<T, K>();
+    constexpr int LPT = kHxThreads / CC;
+    uint64_t tiles = 0;
+    for (int m = 0; m < li.m_count; ++m) {
+        P.lbase[m] = li.lbase[m];
+        P.nleft[m] = li.nleft[m];
+        P.ncols[m] = li.ncols[m];
+        const uint64_t ncc = (li.ncols[m] + CC - 1) / CC;
+        const uint64_t nlg = (li.nleft[m] + LPT - 1) / LPT;
+        P.nlg[m] = (uint32_t)nlg;
+        P.tbase[m] = tiles;
+        tiles += ncc * nlg;
+    }
+    P.tbase[li.m_count] = tiles;
+    P.tiles = tiles;
+    const size_t lds = s->desc.lay_bytes + coeff_lds_bytes<T>();
+    const Grid g = plan_grid(s, lds);
+    P.xcd_groups = g.xcd_groups;
+    const int wgs = (int)std::min<uint64_t>((uint64_t)g.wgs, tiles);
+    if (g.xcd_groups && wgs != g.wgs) P.xcd_groups = 0;
+    P.tiles_per_xcd = (tiles + 7) / 8;
+    P.counters = nullptr;
+    if (P.xcd_groups && s->dev.counters) {
+        P.counters = s->dev.counters + 8;
+        zero_counters<0><<<1, 64, 0, stream>>>(P.counters, 8);
+    }
+    auto kern = left_kernel<IdxT, T, K, NMAX>;
+    if (int r = ensure_lds(kern, lds)) return r;
+    kern<<<wgs, kHxThreads, lds, stream>>>(P);
+    return check_hip(hipGetLastError(), "left pass kernel launch");
 }
 
 }  // namespace hx

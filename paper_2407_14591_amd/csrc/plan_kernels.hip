@@ -21,6 +21,8 @@ struct PlanSector {
     const double *jxy, *jz, *h;
     int nbonds;
     int q2;
+    uint64_t cls_mask;
+    int far_below;
     uint16_t cls_beg[kMaxClasses + 1];
     uint32_t pos[kMaxBonds];
 };
@@ -147,6 +149,8 @@ extern "C" int dcs_plan_create(int nsec, dcs_sector *const *secs, dcs_terms *con
         ps.h = nullptr;
         ps.nbonds = bp.nbonds;
         ps.q2 = secs[s]->desc.Q == 2;
+        ps.cls_mask = ~0ull;
+        ps.far_below = 0;
         for (int c = 0; c <= bp.nclasses; ++c) ps.cls_beg[c] = bp.cls_beg[c];
         for (int b = 0; b < bp.nbonds; ++b) ps.pos[b] = bp.pos[b];
         for (uint64_t r0 = 0; r0 < ps.sd.dim; r0 += kHxThreads) tiles.push_back(make_uint2(s, (uint32_t)r0));

@@ -182,8 +182,100 @@ int upload(dcs_sector *s, HostTables<IdxT> &ht) {
                          hipGetErrorString(e));
     }
     e = hipMemcpy(d.base, host.data(), pos, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&d.counters, kNumCounters * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(d.counters, 0, kNumCounters * sizeof(uint32_t));
     hipSetDevice(prev);
-    return check_hip(e, "hipMemcpy of sector tables");
+    return check_hip(e, "sector tables and counters");
+}
+
+// Left configurations of the two-pass product (see LeftInfo): for every left
+// particle number m, the configurations (w_0..w_{K-1}) with digit sum m in
+// canonical order, with the first row of their run, sum_k C_k[lambda_k][w_k].
+constexpr uint64_t kTwoPassMinDim = 1ull << 22;
+constexpr size_t kMaxLeftConfigs = 1u << 22;
+
+template <typename IdxT>
+int build_left(const DimTable &Dt, dcs_sector *s, const HostTables<IdxT> &ht, const int *split) {
+    SectorDesc &sd = s->desc;
+    LeftInfo &li = s->left;
+    li.K = 0;
+    uint64_t min_dim = kTwoPassMinDim;
+    if (const char *e = getenv("DCS_TWO_PASS_MIN_DIM")) min_dim = strtoull(e, nullptr, 10);
+    if (sd.N < 2 || sd.Q != 2 || sd.dim < min_dim) return DCS_OK;
+    const int K = sd.N / 2;
+    int L_left = 0, bits = 0;
+    for (int k = 0; k < K; ++k) {
+        li.word_shift[k] = (uint32_t)bits;
+        L_left += split[k];
+        bits += sd.wbits[k];
+    }
+    const int Q = sd.Q, n = sd.n;
+    const int m_lo = std::max(0, n - (Q - 1) * (sd.L - L_left));
+    const int m_hi = std::min(n, (Q - 1) * L_left);
+    if (bits > 32 || m_hi - m_lo + 1 > kMaxLeftM) return DCS_OK;
+    uint64_t total = 0;
+    for (int m = m_lo; m <= m_hi; ++m) total += Dt.get(L_left, m);
+    if (total > kMaxLeftConfigs) return DCS_OK;
+    std::vector<uint32_t> words;
+    std::vector<IdxT> runs;
+    words.reserve(total);
+    runs.reserve(total);
+    uint32_t w[kMaxSub];
+    int lam[kMaxSub];
+    // nested loops over the left subsystems: digit sums in increasing order, then words
+    // in increasing (lexicographic) order, the last left subsystem taking what remains
+    auto rec = [&](auto &&self, int k, int rem) -> void {
+        if (k == K) {
+            if (rem != 0) return;
+            uint32_t pw = 0;
+            u128 start = 0;
+            for (int j = 0; j < K; ++j) {
+                pw |= w[j] << li.word_shift[j];
+                start += ht.ctab[sd.ctab_row0[j] + (uint32_t)(lam[j] - sd.lam_lo[j]) * sd.ctab_rowlen[j] + w[j]];
+            }
+            words.push_back(pw);
+            runs.push_back((IdxT)start);
+            return;
+        }
+        int rest_sites = 0;
+        for (int j = k + 1; j < K; ++j) rest_sites += split[j];
+        const int lo = std::max(0, rem - (Q - 1) * rest_sites);
+        const int hi = std::min(sd.mk[k], rem);
+        const int base = lam[k];
+        for (int nk = lo; nk <= hi; ++nk) {
+            const uint32_t b = ht.inv_start[sd.inv_start0[k] + nk];
+            const uint32_t e = ht.inv_start[sd.inv_start0[k] + nk + 1];
+            for (uint32_t i = b; i < e; ++i) {
+                w[k] = ht.inv[i];
+                if (k + 1 < K) lam[k + 1] = base + nk;
+                self(self, k + 1, rem - nk);
+            }
+        }
+    };
+    for (int m = m_lo; m <= m_hi; ++m) {
+        li.lbase[m - m_lo] = (uint32_t)words.size();
+        lam[0] = 0;
+        rec(rec, 0, m);
+        li.nleft[m - m_lo] = (uint32_t)(words.size() - li.lbase[m - m_lo]);
+        li.ncols[m - m_lo] = Dt.get(sd.L - L_left, n - m);
+    }
+    DeviceGuard g(s->device);
+    if (int r = check_hip(hipMalloc(&li.d_words, words.size() * sizeof(uint32_t)), "hipMalloc left words"))
+        return r;
+    if (int r = check_hip(hipMalloc(&li.d_runs, runs.size() * sizeof(IdxT)), "hipMalloc left runs"))
+        return r;
+    if (int r = check_hip(hipMemcpy(li.d_words, words.data(), words.size() * sizeof(uint32_t),
+                                    hipMemcpyHostToDevice), "copy left words"))
+        return r;
+    if (int r = check_hip(hipMemcpy(li.d_runs, runs.data(), runs.size() * sizeof(IdxT),
+                                    hipMemcpyHostToDevice), "copy left runs"))
+        return r;
+    li.K = K;
+    li.L_left = L_left;
+    li.m_lo = m_lo;
+    li.m_count = m_hi - m_lo + 1;
+    li.count = words.size();
+    return DCS_OK;
 }
 
 }  // namespace
@@ -307,16 +399,21 @@ extern "C" int dcs_sector_create(int L, int n, int Q, int N, const int *sizes, i
         HostTables<uint64_t> ht;
         r = build_tables(Dt, sd, split, ht);
         if (!r) r = upload(s, ht);
+        if (!r) r = build_left(Dt, s, ht, split);
     } else {
         HostTables<uint32_t> ht;
         r = build_tables(Dt, sd, split, ht);
         if (!r) r = upload(s, ht);
+        if (!r) r = build_left(Dt, s, ht, split);
     }
     if (!r && s->dev.lds_bytes > kLdsTableBudget)
         r = set_error(DCS_EUNSUPPORTED, "sector tables need %zu bytes > %zu of on-chip memory",
                       s->dev.lds_bytes, kLdsTableBudget);
     if (r) {
         if (s->dev.base) hipFree(s->dev.base);
+        if (s->dev.counters) hipFree(s->dev.counters);
+        if (s->left.d_words) hipFree(s->left.d_words);
+        if (s->left.d_runs) hipFree(s->left.d_runs);
         delete s;
         return r;
     }
@@ -333,6 +430,9 @@ extern "C" int dcs_sector_destroy(dcs_sector *s) {
         hipGetDevice(&prev);
         hipSetDevice(s->device);
         r = check_hip(hipFree(s->dev.base), "hipFree of sector tables");
+        if (s->dev.counters) hipFree(s->dev.counters);
+        if (s->left.d_words) hipFree(s->left.d_words);
+        if (s->left.d_runs) hipFree(s->left.d_runs);
         hipSetDevice(prev);
     }
     delete s;

@@ -168,3 +168,38 @@ def test_headline_workload_L32_sampled(dt):
     err = rel_err(got, y_ref)
     say("rel err", err)
     assert err <= TOL[dt]
+
+
+@pytest.mark.parametrize("L,n,split,k,dt", [
+    (12, 6, [3, 3, 3, 3], 1, torch.float64), (12, 5, [4, 4, 4], 8, torch.float32),
+    (14, 7, [3, 4, 3, 4], 4, torch.float32), (16, 8, [8, 8], 2, torch.float64),
+    (13, 6, [2, 2, 2, 2, 2, 3], 1, torch.float32), (15, 7, [3, 3, 3, 3, 3], 8, torch.float64)])
+def test_two_pass_small(monkeypatch, L, n, split, k, dt):
+    """The two-pass form (rows for the bonds right of the cut, column chunks for the
+    bonds left of it) forced on small sectors, against the oracle."""
+    monkeypatch.setenv("DCS_TWO_PASS_MIN_DIM", "0")
+    rng = np.random.default_rng(L + k)
+    b = BruteSector(2, L, n, split)
+    bonds = random_graph(L, 2 * L, rng) + synth.chain_bonds(L, 1)
+    jxy, jz, h = rng.normal(size=len(bonds)), rng.normal(size=len(bonds)), rng.normal(size=L)
+    s, t = dq.Sector(L, n, 2, split), dq.Terms(bonds)
+    for x in (rng.normal(size=(b.dim, k)) if k > 1 else rng.normal(size=b.dim),):
+        for use_h in (False, True):
+            y_ref = apply_h(b, bonds, jxy, jz, x, h if use_h else None)
+            y = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), torch.tensor(x, device=DEV).to(dt),
+                                     h=dev_f64(h) if use_h else None)
+            assert rel_err(y.cpu().double().numpy(), y_ref) <= TOL[dt], (L, n, split, k, dt, use_h)
+
+
+def test_two_pass_L26_all_rows():
+    """L=26, n=13 (10,400,600 states, split 8/9/9): the two-pass form on every row."""
+    L, n, sp = 26, 13, [8, 9, 9]
+    s = dq.Sector(L, n, 2, sp)
+    ns = native.NativeSector(2, L, n, sp)
+    bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.5, 1.0)
+    x = synth.vector(s.dim)
+    y_ref = native.hx_range(ns, native.NativeTerms(bonds, jxy, jz), x)
+    for dt in (torch.float64, torch.float32):
+        y = dq.hamiltonian_apply(s, dq.Terms(bonds), dev_f64(jxy), dev_f64(jz),
+                                 torch.tensor(x, device=DEV).to(dt))
+        assert rel_err(y.cpu().double().numpy(), y_ref) <= TOL[dt]

@@ -50,7 +50,9 @@ def batched_workload():
     return specs
 
 
-def test_batched_workload_one_launch():
+def test_batched_workload_one_launch(monkeypatch):
+    # one-pass products for the bitwise comparison with the plan (same summation order)
+    monkeypatch.setenv("DCS_TWO_PASS_MIN_DIM", str(1 << 62))
     specs = batched_workload()
     items, xs = [], []
     total = 0
