@@ -25,6 +25,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "dcs.h"
 
@@ -86,25 +87,50 @@ struct SectorDev {
 };
 constexpr int kNumCounters = 32;
 
-// Left/right view of a sector for the two-pass product.  Cut the subsystems at
+// Left/right view of a sector for the split product.  Cut the subsystems at
 // K: for a fixed number m of particles in P_0..P_{K-1} ("left"), every left
-// configuration (w_0..w_{K-1}) owns one contiguous run of rows, of the same
-// length R(m) = D_Q(L - L_left, n - m), whose offsets are the right
-// configurations in canonical order.  A bond with both sites on the left moves
-// a row to the same offset of another run; a bond with both sites on the
-// right stays inside the run.
+// configuration (w_0..w_{K-1}) owns one contiguous run of rows of the same
+// length R(m) = D_Q(L - L_left, n - m); the offset inside a run is the index
+// of the right configuration (w_K..w_{N-1}) in its own sub-sector (eq. index
+// is a sum over subsystems, so row = run start + offset).  A bond with both
+// sites left of the cut maps a row to the same offset of another run; a bond
+// with both sites right of it stays inside the run.  Those two families act
+// on small sub-sectors (2^16 configurations at L = 32) and are stored as sparse
+// rows of (target, bond) once per (sector, terms) pair, like the paper's
+// cluster matrices (App. C); the few bonds that cross the cut keep the
+// on-the-fly rank.
 constexpr int kMaxLeftM = 40;
+constexpr int kMaxSplitCache = 4;
+
+struct SplitCsr {
+    uint64_t terms_id = 0;           // 0: empty slot
+    int nmax = 0;
+    uint32_t *d_lptr = nullptr;      // left rows: entry range of every left configuration
+    uint64_t *d_lent = nullptr;      // target run start (low 48 bits) | plan bond << 48
+    uint32_t *d_rptr = nullptr;      // right rows: entry range of every right configuration
+    uint32_t *d_rent = nullptr;      // target offset (low 24 bits) | plan bond << 24
+    double *d_diag = nullptr;        // diagonal of the left and right families, per call
+    uint64_t lnnz = 0, rnnz = 0;
+};
+
 struct LeftInfo {
-    int K = 0;                 // 0: no two-pass view
+    int K = 0;                 // 0: no split view
     int L_left = 0;
     int m_lo = 0, m_count = 0; // left particle numbers with rows
     uint32_t lbase[kMaxLeftM]; // first left configuration of block m - m_lo
     uint32_t nleft[kMaxLeftM];
     uint64_t ncols[kMaxLeftM]; // run length R(m)
-    uint32_t word_shift[kMaxSub];  // bit of P_k's word inside a packed left word
+    uint32_t rbase[kMaxLeftM]; // first right configuration of block m - m_lo
+    uint32_t word_shift[kMaxSub];  // bit of P_k's word inside a packed left / right word
     void *d_words = nullptr;   // uint32 packed left words, all blocks in order
     void *d_runs = nullptr;    // run start (IdxT) of every left configuration
-    size_t count = 0;
+    void *d_rwords = nullptr;  // uint32 packed right words, all blocks in order
+    size_t count = 0, rcount = 0;
+    std::vector<uint32_t> h_words, h_rwords;
+    std::vector<uint64_t> h_runs;
+    std::vector<uint64_t> h_ctab;  // host copy of the fused contribution table
+    SplitCsr csr[kMaxSplitCache];
+    int next_slot = 0;
 };
 
 }  // namespace dcs
@@ -119,6 +145,7 @@ struct dcs_sector {
 };
 
 struct dcs_terms {
+    uint64_t id;  // unique per created object (keys the per-sector sparse rows)
     int num_bonds;
     int max_site;
     int32_t si[dcs::kMaxBonds];
@@ -148,6 +175,11 @@ inline int class_id(int a, int b, int nmax) {  // a <= b < nmax
 }
 
 int make_bond_plan(const dcs_sector *s, const dcs_terms *t, int nmax, BondPlan *plan);
+void free_split(dcs_sector *s);
+void free_csr(SplitCsr &c);
+// Sparse rows of the left and right bond families of (s, t) in the order of
+// `plan` (built on first use, cached per terms object); NULL if s has no view.
+SplitCsr *split_csr(dcs_sector *s, const dcs_terms *t, const BondPlan &plan, int nmax);
 
 // kernels launchers (index_kernels.hip, hx_kernels.hip, lanczos.hip)
 int launch_rank(const dcs_sector *s, const uint64_t *st, uint64_t *idx, size_t count,

@@ -9,8 +9,8 @@ namespace dcs {
 namespace hx {
 #define DCS_HX_EXTERN(IDX, T, K, NMAX)                                                          \
     extern template int launch_hx_t<IDX, T, K, NMAX>(const dcs_sector *, HxParams &, hipStream_t); \
-    extern template int launch_left_t<IDX, T, K, NMAX>(const dcs_sector *, const HxParams &,      \
-                                                       hipStream_t);
+    extern template int launch_split_t<IDX, T, K, NMAX>(dcs_sector *, const HxParams &,           \
+                                                        const SplitCsr &, hipStream_t);
 #define DCS_HX_EXTERN_ALL(T, K)           \
     DCS_HX_EXTERN(uint32_t, T, K, 4)      \
     DCS_HX_EXTERN(uint32_t, T, K, 8)      \
@@ -38,8 +38,8 @@ DCS_ADJ_EXTERN(uint64_t, double, 8)
 
 namespace {
 
-// The two-pass form (LeftInfo) for Q = 2 sectors that have a left/right view:
-// hx_kernel without the left bond classes, then the left pass adding them.
+// The split form (LeftInfo) for Q = 2 sectors that have a split view: the
+// sparse rows of the left and right bond families plus the crossing bonds.
 // DCS_TWO_PASS=0 in the environment selects the single pass everywhere.
 inline bool two_pass_enabled() {
     static int v = -1;
@@ -51,32 +51,28 @@ inline bool two_pass_enabled() {
 }
 
 template <typename IdxT, typename T, int K, int NMAX>
-int launch_one(const dcs_sector *s, HxParams &P, hipStream_t stream) {
-    if (s->left.K > 0 && s->desc.Q == 2 && two_pass_enabled()) {
-        P.cls_mask = ~left_class_mask(s->left.K, NMAX);
-        P.far_below = s->left.K;  // the mixed classes leave the sweep window
-        if (int r = launch_hx_t<IdxT, T, K, NMAX>(s, P, stream)) return r;
-        return launch_left_t<IdxT, T, K, NMAX>(s, P, stream);
-    }
+int launch_one(const dcs_sector *s, HxParams &P, const SplitCsr *csr, hipStream_t stream) {
+    if (csr) return launch_split_t<IdxT, T, K, NMAX>(const_cast<dcs_sector *>(s), P, *csr, stream);
     // one pass: the bonds touching the first half of the subsystems jump far
     P.far_below = s->desc.dim >= (1ull << 22) ? s->desc.N / 2 : 0;
     return launch_hx_t<IdxT, T, K, NMAX>(s, P, stream);
 }
 
 template <typename IdxT, typename T, int NMAX>
-int launch_hx_k(const dcs_sector *s, HxParams &P, int k, hipStream_t stream) {
+int launch_hx_k(const dcs_sector *s, HxParams &P, const SplitCsr *csr, int k, hipStream_t stream) {
     switch (k) {
-        case 1: return launch_one<IdxT, T, 1, NMAX>(s, P, stream);
-        case 2: return launch_one<IdxT, T, 2, NMAX>(s, P, stream);
-        case 4: return launch_one<IdxT, T, 4, NMAX>(s, P, stream);
-        default: return launch_one<IdxT, T, 8, NMAX>(s, P, stream);
+        case 1: return launch_one<IdxT, T, 1, NMAX>(s, P, csr, stream);
+        case 2: return launch_one<IdxT, T, 2, NMAX>(s, P, csr, stream);
+        case 4: return launch_one<IdxT, T, 4, NMAX>(s, P, csr, stream);
+        default: return launch_one<IdxT, T, 8, NMAX>(s, P, csr, stream);
     }
 }
 
 template <typename IdxT, int NMAX>
-int launch_hx_d(const dcs_sector *s, HxParams &P, int dtype, int k, hipStream_t stream) {
-    if (dtype == DCS_F32) return launch_hx_k<IdxT, float, NMAX>(s, P, k, stream);
-    return launch_hx_k<IdxT, double, NMAX>(s, P, k, stream);
+int launch_hx_d(const dcs_sector *s, HxParams &P, const SplitCsr *csr, int dtype, int k,
+                hipStream_t stream) {
+    if (dtype == DCS_F32) return launch_hx_k<IdxT, float, NMAX>(s, P, csr, k, stream);
+    return launch_hx_k<IdxT, double, NMAX>(s, P, csr, k, stream);
 }
 
 int pick_nmax(const dcs_sector *s) { return s->desc.N <= 4 ? 4 : 8; }
@@ -91,14 +87,21 @@ int launch_hx(const dcs_sector *s, const dcs_terms *t, const double *jxy, const 
     DeviceGuard dg(s->device);
     const int nmax = pick_nmax(s);
     HxParams P;
-    if (int r = fill_params(s, t, nmax, jxy, jz, h, P)) return r;
+    BondPlan bp;
+    if (int r = fill_params(s, t, nmax, jxy, jz, h, P, &bp)) return r;
     P.x = x;
     P.y = y;
+    const SplitCsr *csr = nullptr;
+    if (s->left.K > 0 && s->desc.Q == 2 && two_pass_enabled()) {
+        clear_error();
+        csr = split_csr(const_cast<dcs_sector *>(s), t, bp, nmax);
+        if (!csr && dcs_last_error()[0]) return DCS_EHIP;
+    }
     if (s->wide)
-        return nmax == 4 ? launch_hx_d<uint64_t, 4>(s, P, dtype, k, stream)
-                         : launch_hx_d<uint64_t, 8>(s, P, dtype, k, stream);
-    return nmax == 4 ? launch_hx_d<uint32_t, 4>(s, P, dtype, k, stream)
-                     : launch_hx_d<uint32_t, 8>(s, P, dtype, k, stream);
+        return nmax == 4 ? launch_hx_d<uint64_t, 4>(s, P, csr, dtype, k, stream)
+                         : launch_hx_d<uint64_t, 8>(s, P, csr, dtype, k, stream);
+    return nmax == 4 ? launch_hx_d<uint32_t, 4>(s, P, csr, dtype, k, stream)
+                     : launch_hx_d<uint32_t, 8>(s, P, csr, dtype, k, stream);
 }
 
 size_t adjoint_ws_bytes(const dcs_sector *s, const dcs_terms *t) {

@@ -1,4 +1,4 @@
-// Instantiations of the H*x launchers (one pass and left pass) for double vectors with k=2 columns.
+// Instantiations of the H*x launchers (one pass and split) for double vectors with k=2 columns.
 #include "hx_impl.h"
 
 namespace dcs {
@@ -7,9 +7,13 @@ template int launch_hx_t<uint32_t, double, 2, 4>(const dcs_sector *, HxParams &,
 template int launch_hx_t<uint32_t, double, 2, 8>(const dcs_sector *, HxParams &, hipStream_t);
 template int launch_hx_t<uint64_t, double, 2, 4>(const dcs_sector *, HxParams &, hipStream_t);
 template int launch_hx_t<uint64_t, double, 2, 8>(const dcs_sector *, HxParams &, hipStream_t);
-template int launch_left_t<uint32_t, double, 2, 4>(const dcs_sector *, const HxParams &, hipStream_t);
-template int launch_left_t<uint32_t, double, 2, 8>(const dcs_sector *, const HxParams &, hipStream_t);
-template int launch_left_t<uint64_t, double, 2, 4>(const dcs_sector *, const HxParams &, hipStream_t);
-template int launch_left_t<uint64_t, double, 2, 8>(const dcs_sector *, const HxParams &, hipStream_t);
+template int launch_split_t<uint32_t, double, 2, 4>(dcs_sector *, const HxParams &, const SplitCsr &,
+                                                   hipStream_t);
+template int launch_split_t<uint32_t, double, 2, 8>(dcs_sector *, const HxParams &, const SplitCsr &,
+                                                   hipStream_t);
+template int launch_split_t<uint64_t, double, 2, 4>(dcs_sector *, const HxParams &, const SplitCsr &,
+                                                   hipStream_t);
+template int launch_split_t<uint64_t, double, 2, 8>(dcs_sector *, const HxParams &, const SplitCsr &,
+                                                   hipStream_t);
 }  // namespace hx
 }  // namespace dcs

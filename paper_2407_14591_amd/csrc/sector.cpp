@@ -1,6 +1,7 @@
 // Host-side sector planner: dimensions, offsets, strides and the device tables
 // of the divide-and-conquer index (Sec. 3.2 and 4.2 of arXiv:2407.14591).
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -259,7 +260,43 @@ int build_left(const DimTable &Dt, dcs_sector *s, const HostTables<IdxT> &ht, co
         li.nleft[m - m_lo] = (uint32_t)(words.size() - li.lbase[m - m_lo]);
         li.ncols[m - m_lo] = Dt.get(sd.L - L_left, n - m);
     }
+    // right configurations of every block in offset order, checked against the
+    // fused table: offset = sum_{k>=K} C_k[lambda_k][w_k]
+    int rbits = 0;
+    for (int k = K; k < sd.N; ++k) {
+        li.word_shift[k] = (uint32_t)rbits;
+        rbits += sd.wbits[k];
+    }
+    if (rbits > 32) return DCS_OK;
+    std::vector<uint32_t> rwords;
+    auto rrec = [&](auto &&self, int k, int rem, uint32_t acc) -> void {
+        if (k == sd.N) {
+            if (rem == 0) rwords.push_back(acc);
+            return;
+        }
+        int rest_sites = 0;
+        for (int j = k + 1; j < sd.N; ++j) rest_sites += split[j];
+        const int lo = std::max(0, rem - (Q - 1) * rest_sites);
+        const int hi = std::min(sd.mk[k], rem);
+        for (int nk = lo; nk <= hi; ++nk) {
+            const uint32_t b = ht.inv_start[sd.inv_start0[k] + nk];
+            const uint32_t e = ht.inv_start[sd.inv_start0[k] + nk + 1];
+            for (uint32_t i = b; i < e; ++i)
+                self(self, k + 1, rem - nk, acc | ((uint32_t)ht.inv[i] << li.word_shift[k]));
+        }
+    };
+    for (int m = m_lo; m <= m_hi; ++m) {
+        li.rbase[m - m_lo] = (uint32_t)rwords.size();
+        rrec(rrec, K, n - m, 0u);
+        if (rwords.size() - li.rbase[m - m_lo] != li.ncols[m - m_lo])
+            return set_error(DCS_EHIP, "internal: right configurations of block %d", m);
+    }
     DeviceGuard g(s->device);
+    if (int r = check_hip(hipMalloc(&li.d_rwords, rwords.size() * sizeof(uint32_t)), "hipMalloc right words"))
+        return r;
+    if (int r = check_hip(hipMemcpy(li.d_rwords, rwords.data(), rwords.size() * sizeof(uint32_t),
+                                    hipMemcpyHostToDevice), "copy right words"))
+        return r;
     if (int r = check_hip(hipMalloc(&li.d_words, words.size() * sizeof(uint32_t)), "hipMalloc left words"))
         return r;
     if (int r = check_hip(hipMalloc(&li.d_runs, runs.size() * sizeof(IdxT)), "hipMalloc left runs"))
@@ -275,10 +312,33 @@ int build_left(const DimTable &Dt, dcs_sector *s, const HostTables<IdxT> &ht, co
     li.m_lo = m_lo;
     li.m_count = m_hi - m_lo + 1;
     li.count = words.size();
+    li.rcount = rwords.size();
+    li.h_words = std::move(words);
+    li.h_rwords = std::move(rwords);
+    li.h_runs.assign(runs.begin(), runs.end());
+    li.h_ctab.assign(ht.ctab.begin(), ht.ctab.end());
     return DCS_OK;
 }
 
 }  // namespace
+
+void free_csr(SplitCsr &c) {
+    hipFree(c.d_lptr);
+    hipFree(c.d_lent);
+    hipFree(c.d_rptr);
+    hipFree(c.d_rent);
+    hipFree(c.d_diag);
+    c = SplitCsr();
+}
+
+void free_split(dcs_sector *s) {
+    LeftInfo &li = s->left;
+    hipFree(li.d_words);
+    hipFree(li.d_runs);
+    hipFree(li.d_rwords);
+    li.d_words = li.d_runs = li.d_rwords = nullptr;
+    for (int i = 0; i < kMaxSplitCache; ++i) free_csr(li.csr[i]);
+}
 
 int make_bond_plan(const dcs_sector *s, const dcs_terms *t, int nmax, BondPlan *p) {
     const SectorDesc &sd = s->desc;
@@ -412,8 +472,7 @@ extern "C" int dcs_sector_create(int L, int n, int Q, int N, const int *sizes, i
     if (r) {
         if (s->dev.base) hipFree(s->dev.base);
         if (s->dev.counters) hipFree(s->dev.counters);
-        if (s->left.d_words) hipFree(s->left.d_words);
-        if (s->left.d_runs) hipFree(s->left.d_runs);
+        free_split(s);
         delete s;
         return r;
     }
@@ -431,8 +490,7 @@ extern "C" int dcs_sector_destroy(dcs_sector *s) {
         hipSetDevice(s->device);
         r = check_hip(hipFree(s->dev.base), "hipFree of sector tables");
         if (s->dev.counters) hipFree(s->dev.counters);
-        if (s->left.d_words) hipFree(s->left.d_words);
-        if (s->left.d_runs) hipFree(s->left.d_runs);
+        free_split(s);
         hipSetDevice(prev);
     }
     delete s;
@@ -466,6 +524,8 @@ extern "C" int dcs_terms_create(int num_bonds, const int32_t *si, const int32_t 
     if (num_bonds > 0 && (!si || !sj)) return set_error(DCS_EINVAL, "NULL site arrays");
     dcs_terms *t = new (std::nothrow) dcs_terms();
     if (!t) return set_error(DCS_ENOMEM, "host allocation failed");
+    static std::atomic<uint64_t> next_id{1};
+    t->id = next_id++;
     t->num_bonds = num_bonds;
     t->max_site = -1;
     for (int b = 0; b < num_bonds; ++b) {
