@@ -31,14 +31,17 @@
  *    their kernels with 32-bit index arithmetic; larger ones with 64-bit.  The
  *    environment variable DCS_INDEX_BITS=64, read by dcs_sector_create, forces
  *    64-bit arithmetic (to test those kernels on small sectors).
- *  - Two-pass product: for Q = 2 sectors with at least 2^22 states and two or
+ *  - Split product: for Q = 2 sectors with at least 2^22 states and two or
  *    more subsystems, dcs_sector_create also builds a left/right view (cut after
- *    N/2 subsystems) and dcs_hamiltonian_apply runs two kernels: one pass over
- *    the rows for the bonds with a site right of the cut, then one over column
- *    chunks for the bonds left of it (their hops keep the offset inside a run of
- *    rows, so that pass reads x with L2 locality).  DCS_TWO_PASS_MIN_DIM (read
- *    by dcs_sector_create) changes the 2^22 threshold; DCS_TWO_PASS=0 (read once
- *    per process) forces the single pass.
+ *    N/2 subsystems: every left configuration owns a contiguous run of rows, one
+ *    per right configuration).  The first dcs_hamiltonian_apply with a terms
+ *    object builds that pair's target tables (host work, then kept with the
+ *    sector for the next calls; up to four terms objects per sector) and every
+ *    product runs three kernels: the diagonal per configuration of each side,
+ *    one pass over the rows for the bonds right of and across the cut, and one
+ *    over column chunks for the bonds left of it.  DCS_SPLIT_MIN_DIM (read by
+ *    dcs_sector_create) changes the 2^22 threshold; DCS_SPLIT=0 (read once per
+ *    process) forces the single pass.
  */
 #ifndef DCS_H
 #define DCS_H

@@ -90,27 +90,52 @@ constexpr int kNumCounters = 32;
 // Left/right view of a sector for the split product.  Cut the subsystems at
 // K: for a fixed number m of particles in P_0..P_{K-1} ("left"), every left
 // configuration (w_0..w_{K-1}) owns one contiguous run of rows of the same
-// length R(m) = D_Q(L - L_left, n - m); the offset inside a run is the index
-// of the right configuration (w_K..w_{N-1}) in its own sub-sector (eq. index
+// length, one row per right configuration (w_K..w_{N-1}) (the rank of eq. index
 // is a sum over subsystems, so row = run start + offset).  A bond with both
 // sites left of the cut maps a row to the same offset of another run; a bond
-// with both sites right of it stays inside the run.  Those two families act
-// on small sub-sectors (2^16 configurations at L = 32) and are stored as sparse
-// rows of (target, bond) once per (sector, terms) pair, like the paper's
-// cluster matrices (App. C); the few bonds that cross the cut keep the
-// on-the-fly rank.
+// with both sites right of it stays inside the run; a bond across the cut
+// flips one site on each side.  All three act on small sub-sectors (2^16
+// configurations per side at L = 32), so their targets are tabulated once per
+// (sector, terms) pair, like the paper's cluster matrices (App. C).
 constexpr int kMaxLeftM = 40;
 constexpr int kMaxSplitCache = 4;
+constexpr int kMaxCross = 96;       // bonds across the cut
+constexpr int kMaxCrossSites = 32;  // distinct sites of those bonds on either side
 
-struct SplitCsr {
+struct CrossBond {
+    uint8_t si, sj;      // slot of the left / right site in the flip tables
+    uint8_t lbit, rbit;  // bit of the left / right site in the packed left / right word
+    uint16_t bond;       // index in the terms
+    uint16_t pad;
+};
+
+// Bond or field entry of the per-configuration diagonal (one side of the cut).
+struct DiagTerm {
+    uint8_t side;        // 0 left, 1 right
+    uint8_t bi, bj;      // bits in the packed word of that side (bj unused for a field)
+    uint8_t is_field;
+    uint16_t index;      // bond index in the terms, or site for a field
+    uint16_t pad;
+};
+
+struct SplitRows {
     uint64_t terms_id = 0;           // 0: empty slot
-    int nmax = 0;
-    uint32_t *d_lptr = nullptr;      // left rows: entry range of every left configuration
-    uint64_t *d_lent = nullptr;      // target run start (low 48 bits) | plan bond << 48
-    uint32_t *d_rptr = nullptr;      // right rows: entry range of every right configuration
-    uint32_t *d_rent = nullptr;      // target offset (low 24 bits) | plan bond << 24
-    double *d_diag = nullptr;        // diagonal of the left and right families, per call
-    uint64_t lnnz = 0, rnnz = 0;
+    uint32_t *d_lptr = nullptr;      // left family: entry range of every left configuration
+    uint64_t *d_lent = nullptr;      // target run start (low 48 bits) | bond << 48
+    uint16_t *d_vo = nullptr;        // right family: [bond group][right configuration][8] target
+                                     // offset in the run, 0xFFFF where the bond does not hop
+    uint64_t *d_xl = nullptr;        // crossing: [left site slot][left configuration] run start of
+                                     // the configuration with that site flipped, ~0 if none
+    uint16_t *d_xo = nullptr;        // crossing: [group of 8 right site slots][right configuration][8]
+                                     // offset of the configuration with that site flipped in its
+                                     // block, 0xFFFF if none
+    uint64_t *d_runs = nullptr;      // run start of every left configuration
+    double *d_diag = nullptr;        // per call: left | right configuration diagonals
+    int nR = 0, nX = 0, nIs = 0, nJs = 0, nD = 0;
+    uint64_t lnnz = 0;
+    uint16_t r_bond[kMaxBonds];      // bond index of every right-family bond
+    CrossBond x[kMaxCross];
+    DiagTerm d[kMaxBonds + kMaxSites];
 };
 
 struct LeftInfo {
@@ -129,7 +154,7 @@ struct LeftInfo {
     std::vector<uint32_t> h_words, h_rwords;
     std::vector<uint64_t> h_runs;
     std::vector<uint64_t> h_ctab;  // host copy of the fused contribution table
-    SplitCsr csr[kMaxSplitCache];
+    SplitRows rows[kMaxSplitCache];
     int next_slot = 0;
 };
 
@@ -176,10 +201,11 @@ inline int class_id(int a, int b, int nmax) {  // a <= b < nmax
 
 int make_bond_plan(const dcs_sector *s, const dcs_terms *t, int nmax, BondPlan *plan);
 void free_split(dcs_sector *s);
-void free_csr(SplitCsr &c);
-// Sparse rows of the left and right bond families of (s, t) in the order of
-// `plan` (built on first use, cached per terms object); NULL if s has no view.
-SplitCsr *split_csr(dcs_sector *s, const dcs_terms *t, const BondPlan &plan, int nmax);
+void free_rows(SplitRows &c);
+// Target tables of the split product of (s, t) (built on first use, cached per
+// terms object); NULL if s has no split view or the tables do not apply (an
+// error is set only for a failure).
+SplitRows *split_rows(dcs_sector *s, const dcs_terms *t);
 
 // kernels launchers (index_kernels.hip, hx_kernels.hip, lanczos.hip)
 int launch_rank(const dcs_sector *s, const uint64_t *st, uint64_t *idx, size_t count,

@@ -3,14 +3,26 @@
 // hx_adjoint_f*.hip so they compile in parallel.
 #include <cstdlib>
 
-#include "hx_impl.h"
+#include "split_impl.h"
 
 namespace dcs {
+namespace sp {
+#define DCS_SPLIT_EXTERN(T, K)                                                                   \
+    extern template int launch_split_t<T, K>(dcs_sector *, const SplitRows &, const void *, void *, \
+                                             const double *, const double *, const double *, int,   \
+                                             hipStream_t);
+DCS_SPLIT_EXTERN(float, 1)
+DCS_SPLIT_EXTERN(float, 2)
+DCS_SPLIT_EXTERN(float, 4)
+DCS_SPLIT_EXTERN(float, 8)
+DCS_SPLIT_EXTERN(double, 1)
+DCS_SPLIT_EXTERN(double, 2)
+DCS_SPLIT_EXTERN(double, 4)
+DCS_SPLIT_EXTERN(double, 8)
+}  // namespace sp
 namespace hx {
 #define DCS_HX_EXTERN(IDX, T, K, NMAX)                                                          \
-    extern template int launch_hx_t<IDX, T, K, NMAX>(const dcs_sector *, HxParams &, hipStream_t); \
-    extern template int launch_split_t<IDX, T, K, NMAX>(dcs_sector *, const HxParams &,           \
-                                                        const SplitCsr &, hipStream_t);
+    extern template int launch_hx_t<IDX, T, K, NMAX>(const dcs_sector *, HxParams &, hipStream_t);
 #define DCS_HX_EXTERN_ALL(T, K)           \
     DCS_HX_EXTERN(uint32_t, T, K, 4)      \
     DCS_HX_EXTERN(uint32_t, T, K, 8)      \
@@ -38,41 +50,49 @@ DCS_ADJ_EXTERN(uint64_t, double, 8)
 
 namespace {
 
-// The split form (LeftInfo) for Q = 2 sectors that have a split view: the
-// sparse rows of the left and right bond families plus the crossing bonds.
-// DCS_TWO_PASS=0 in the environment selects the single pass everywhere.
-inline bool two_pass_enabled() {
+// The split form (LeftInfo) for Q = 2 sectors that have a split view.
+// DCS_SPLIT=0 in the environment selects the single pass everywhere.
+inline bool split_enabled() {
     static int v = -1;
     if (v < 0) {
-        const char *e = getenv("DCS_TWO_PASS");
+        const char *e = getenv("DCS_SPLIT");
         v = (e && e[0] == '0') ? 0 : 1;
     }
     return v == 1;
 }
 
 template <typename IdxT, typename T, int K, int NMAX>
-int launch_one(const dcs_sector *s, HxParams &P, const SplitCsr *csr, hipStream_t stream) {
-    if (csr) return launch_split_t<IdxT, T, K, NMAX>(const_cast<dcs_sector *>(s), P, *csr, stream);
-    // one pass: the bonds touching the first half of the subsystems jump far
+int launch_one(const dcs_sector *s, HxParams &P, hipStream_t stream) {
+    // the bonds touching the first half of the subsystems jump far
     P.far_below = s->desc.dim >= (1ull << 22) ? s->desc.N / 2 : 0;
     return launch_hx_t<IdxT, T, K, NMAX>(s, P, stream);
 }
 
 template <typename IdxT, typename T, int NMAX>
-int launch_hx_k(const dcs_sector *s, HxParams &P, const SplitCsr *csr, int k, hipStream_t stream) {
+int launch_hx_k(const dcs_sector *s, HxParams &P, int k, hipStream_t stream) {
     switch (k) {
-        case 1: return launch_one<IdxT, T, 1, NMAX>(s, P, csr, stream);
-        case 2: return launch_one<IdxT, T, 2, NMAX>(s, P, csr, stream);
-        case 4: return launch_one<IdxT, T, 4, NMAX>(s, P, csr, stream);
-        default: return launch_one<IdxT, T, 8, NMAX>(s, P, csr, stream);
+        case 1: return launch_one<IdxT, T, 1, NMAX>(s, P, stream);
+        case 2: return launch_one<IdxT, T, 2, NMAX>(s, P, stream);
+        case 4: return launch_one<IdxT, T, 4, NMAX>(s, P, stream);
+        default: return launch_one<IdxT, T, 8, NMAX>(s, P, stream);
     }
 }
 
 template <typename IdxT, int NMAX>
-int launch_hx_d(const dcs_sector *s, HxParams &P, const SplitCsr *csr, int dtype, int k,
-                hipStream_t stream) {
-    if (dtype == DCS_F32) return launch_hx_k<IdxT, float, NMAX>(s, P, csr, k, stream);
-    return launch_hx_k<IdxT, double, NMAX>(s, P, csr, k, stream);
+int launch_hx_d(const dcs_sector *s, HxParams &P, int dtype, int k, hipStream_t stream) {
+    if (dtype == DCS_F32) return launch_hx_k<IdxT, float, NMAX>(s, P, k, stream);
+    return launch_hx_k<IdxT, double, NMAX>(s, P, k, stream);
+}
+
+template <typename T>
+int launch_split_k(dcs_sector *s, const SplitRows &c, const void *x, void *y, const double *jxy,
+                   const double *jz, const double *h, int nbonds, int k, hipStream_t stream) {
+    switch (k) {
+        case 1: return sp::launch_split_t<T, 1>(s, c, x, y, jxy, jz, h, nbonds, stream);
+        case 2: return sp::launch_split_t<T, 2>(s, c, x, y, jxy, jz, h, nbonds, stream);
+        case 4: return sp::launch_split_t<T, 4>(s, c, x, y, jxy, jz, h, nbonds, stream);
+        default: return sp::launch_split_t<T, 8>(s, c, x, y, jxy, jz, h, nbonds, stream);
+    }
 }
 
 int pick_nmax(const dcs_sector *s) { return s->desc.N <= 4 ? 4 : 8; }
@@ -85,23 +105,30 @@ using namespace hx;
 int launch_hx(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
               const double *h, int dtype, int k, const void *x, void *y, hipStream_t stream) {
     DeviceGuard dg(s->device);
+    if (s->left.K > 0 && s->desc.Q == 2 && split_enabled()) {
+        if (t->max_site >= s->desc.L)
+            return set_error(DCS_EINVAL, "bond site %d outside the sector's %d sites", t->max_site,
+                             s->desc.L);
+        clear_error();
+        const SplitRows *c = split_rows(const_cast<dcs_sector *>(s), t);
+        if (c) {
+            dcs_sector *sm = const_cast<dcs_sector *>(s);
+            return dtype == DCS_F32
+                       ? launch_split_k<float>(sm, *c, x, y, jxy, jz, h, t->num_bonds, k, stream)
+                       : launch_split_k<double>(sm, *c, x, y, jxy, jz, h, t->num_bonds, k, stream);
+        }
+        if (dcs_last_error()[0]) return DCS_EHIP;
+    }
     const int nmax = pick_nmax(s);
     HxParams P;
-    BondPlan bp;
-    if (int r = fill_params(s, t, nmax, jxy, jz, h, P, &bp)) return r;
+    if (int r = fill_params(s, t, nmax, jxy, jz, h, P)) return r;
     P.x = x;
     P.y = y;
-    const SplitCsr *csr = nullptr;
-    if (s->left.K > 0 && s->desc.Q == 2 && two_pass_enabled()) {
-        clear_error();
-        csr = split_csr(const_cast<dcs_sector *>(s), t, bp, nmax);
-        if (!csr && dcs_last_error()[0]) return DCS_EHIP;
-    }
     if (s->wide)
-        return nmax == 4 ? launch_hx_d<uint64_t, 4>(s, P, csr, dtype, k, stream)
-                         : launch_hx_d<uint64_t, 8>(s, P, csr, dtype, k, stream);
-    return nmax == 4 ? launch_hx_d<uint32_t, 4>(s, P, csr, dtype, k, stream)
-                     : launch_hx_d<uint32_t, 8>(s, P, csr, dtype, k, stream);
+        return nmax == 4 ? launch_hx_d<uint64_t, 4>(s, P, dtype, k, stream)
+                         : launch_hx_d<uint64_t, 8>(s, P, dtype, k, stream);
+    return nmax == 4 ? launch_hx_d<uint32_t, 4>(s, P, dtype, k, stream)
+                     : launch_hx_d<uint32_t, 8>(s, P, dtype, k, stream);
 }
 
 size_t adjoint_ws_bytes(const dcs_sector *s, const dcs_terms *t) {

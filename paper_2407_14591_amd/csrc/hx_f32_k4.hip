@@ -1,5 +1,5 @@
 // Instantiations of the H*x launchers (one pass and split) for float vectors with k=4 columns.
-#include "hx_impl.h"
+#include "split_impl.h"
 
 namespace dcs {
 namespace hx {
@@ -7,13 +7,9 @@ template int launch_hx_t<uint32_t, float, 4, 4>(const dcs_sector *, HxParams &, 
 template int launch_hx_t<uint32_t, float, 4, 8>(const dcs_sector *, HxParams &, hipStream_t);
 template int launch_hx_t<uint64_t, float, 4, 4>(const dcs_sector *, HxParams &, hipStream_t);
 template int launch_hx_t<uint64_t, float, 4, 8>(const dcs_sector *, HxParams &, hipStream_t);
-template int launch_split_t<uint32_t, float, 4, 4>(dcs_sector *, const HxParams &, const SplitCsr &,
-                                                   hipStream_t);
-template int launch_split_t<uint32_t, float, 4, 8>(dcs_sector *, const HxParams &, const SplitCsr &,
-                                                   hipStream_t);
-template int launch_split_t<uint64_t, float, 4, 4>(dcs_sector *, const HxParams &, const SplitCsr &,
-                                                   hipStream_t);
-template int launch_split_t<uint64_t, float, 4, 8>(dcs_sector *, const HxParams &, const SplitCsr &,
-                                                   hipStream_t);
 }  // namespace hx
+namespace sp {
+template int launch_split_t<float, 4>(dcs_sector *, const SplitRows &, const void *, void *,
+                                     const double *, const double *, const double *, int, hipStream_t);
+}  // namespace sp
 }  // namespace dcs

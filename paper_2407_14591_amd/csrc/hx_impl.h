@@ -422,12 +422,6 @@ __global__ __launch_bounds__(kHxThreads) void hx_kernel(const HxParams P) {
     }
 }
 
-// Offsets per column chunk of the left-family pass: one 128-byte line of x per run.
-template <typename T, int K>
-constexpr int left_chunk_cols() {
-    return (int)(128 / (K * sizeof(T))) > 0 ? (int)(128 / (K * sizeof(T))) : 1;
-}
-
 // ---------------------------------------------------------------- adjoint
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -702,309 +696,6 @@ int launch_adj_t(const dcs_sector *s, HxParams &P, double *gjxy, double *gjz, do
     return check_hip(hipGetLastError(), "adjoint reduction launch");
 }
 
-
-// ---------------------------------------------------------------- split product
-//
-// H = (left family) + (right family) + (crossing bonds) for a sector with a
-// split view (LeftInfo) and Q = 2.  Three kernels per product:
-//  * split_diag_kernel: the diagonal terms of the two families (and the
-//    fields) for every left and every right configuration, from this call's
-//    couplings (a few hundred thousand entries);
-//  * split_right_kernel: one tile = 512 consecutive offsets of one run; each
-//    row adds its right-family hops from the sparse rows (targets are offsets
-//    in the same run), the crossing bonds with the on-the-fly rank, and the
-//    whole diagonal, and writes y;
-//  * split_left_kernel: one tile = a column chunk of LPT runs; each row adds
-//    its left-family hops (targets: the same offset in other runs) to y.
-struct SplitParams {
-    HxParams H;                 // sector, vectors, couplings, bond plan, crossing-class mask
-    const uint32_t *lwords, *rwords;
-    const void *runs;           // IdxT run start per left configuration
-    const uint32_t *lptr, *rptr, *rent;
-    const uint64_t *lent;
-    double *diag;               // [left configurations | right configurations]
-    uint32_t *counters;
-    uint64_t tiles, per_xcd;
-    int cut;                    // K: subsystems left of the cut
-    int m_count;
-    uint32_t nleft_all;         // number of left configurations (offset of the right part in diag)
-    uint32_t lbase[kMaxLeftM], nleft[kMaxLeftM], rbase[kMaxLeftM], nsub[kMaxLeftM];
-    uint64_t ncols[kMaxLeftM];
-    uint64_t tbase[kMaxLeftM + 1];
-    uint32_t word_shift[kMaxSub];
-};
-static_assert(sizeof(SplitParams) <= 4096, "kernel arguments are limited to 4 KiB");
-
-// Diagonal of the left (g < nleft_all) and right families per configuration.
-template <int NMAX>
-__global__ __launch_bounds__(256) void split_diag_kernel(const SplitParams P, uint32_t total) {
-    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    const SectorDesc &sd = P.H.sd;
-    const bool is_left = g < P.nleft_all;
-    const uint32_t pw = is_left ? P.lwords[g] : P.rwords[g - P.nleft_all];
-    uint32_t w[NMAX];
-#pragma unroll
-    for (int k = 0; k < NMAX; ++k)
-        w[k] = (k < sd.N && ((k < P.cut) == is_left)) ? (pw >> P.word_shift[k]) & ((1u << sd.wbits[k]) - 1u)
-                                                     : 0u;
-    double d = 0.0;
-    for (int a = 0; a < NMAX; ++a)
-        for (int b = a; b < NMAX; ++b) {
-            if (b >= sd.N) continue;
-            if (is_left ? (b >= P.cut) : (a < P.cut)) continue;
-            const int cls = a * NMAX - a * (a - 1) / 2 + (b - a);  // class (a, b)
-            uint32_t wa = 0, wb = 0;
-#pragma unroll
-            for (int k = 0; k < NMAX; ++k) {
-                if (k == a) wa = w[k];
-                if (k == b) wb = w[k];
-            }
-            for (int t = P.H.cls_beg[cls]; t < P.H.cls_beg[cls + 1]; ++t) {
-                const uint32_t pos = P.H.pos[t];
-                const uint32_t bi = (wa >> (pos & 0xFFu)) & 1u, bj = (wb >> ((pos >> 8) & 0xFFu)) & 1u;
-                const double jz = 0.25 * P.H.jz[pos >> 16];
-                d += bi == bj ? jz : -jz;
-            }
-        }
-    if (P.H.h) {
-        for (int i = 0; i < sd.L; ++i) {
-            const int k = sd.site_sub[i];
-            if ((k < P.cut) != is_left) continue;
-            uint32_t wk = 0;
-#pragma unroll
-            for (int q = 0; q < NMAX; ++q)
-                if (q == k) wk = w[q];
-            d += P.H.h[i] * ((double)((wk >> sd.site_bit[i]) & 1u) - 0.5);
-        }
-    }
-    P.diag[g] = d;
-}
-
-template <typename IdxT, typename T, int K, int NMAX>
-__global__ __launch_bounds__(kHxThreads) void split_right_kernel(const SplitParams P) {
-    extern __shared__ __align__(16) char lds[];
-    const HxParams &H = P.H;
-    const SectorDesc &sd = H.sd;
-    stage_blob(lds, H.blob, sd.lay_bytes);
-    const CoeffLds<T> C(lds, sd.lay_bytes);
-    stage_coefficients<T, true>(H, sd, C.bamp, C.bjz, C.ladder, C.hf);
-    __syncthreads();
-    const Tables<IdxT> Tb = tables_at<IdxT>(lds, sd);
-    const T *__restrict__ x = reinterpret_cast<const T *>(H.x);
-    T *__restrict__ y = reinterpret_cast<T *>(H.y);
-    const IdxT *__restrict__ runs = reinterpret_cast<const IdxT *>(P.runs);
-    __shared__ uint32_t slot;
-    uint64_t t;
-    while (next_tile(P.counters, P.tiles, P.per_xcd, &slot, t)) {
-        int mi = 0;
-        while (mi + 1 < P.m_count && P.tbase[mi + 1] <= t) ++mi;
-        const uint32_t local = (uint32_t)(t - P.tbase[mi]);
-        const uint32_t L = local / P.nsub[mi], ch = local - L * P.nsub[mi];
-        const uint32_t gl = P.lbase[mi] + L;
-        const uint64_t r = (uint64_t)ch * kHxThreads + threadIdx.x;
-        const bool active = r < P.ncols[mi];
-        const uint32_t gr = P.rbase[mi] + (uint32_t)(active ? r : 0);
-        const uint32_t lw = P.lwords[gl], rw = P.rwords[gr];
-        const IdxT rs = runs[gl];
-        const IdxT row = rs + (IdxT)(active ? r : 0);
-        RowState<IdxT, NMAX> st;
-        int lam = 0;
-#pragma unroll
-        for (int k = 0; k < NMAX; ++k) {
-            if (k < sd.N) {
-                const uint32_t w = ((k < P.cut ? lw : rw) >> P.word_shift[k]) & ((1u << sd.wbits[k]) - 1u);
-                st.w[k] = w;
-                st.rb[k] = sd.ctab_row0[k] + (uint32_t)(lam - sd.lam_lo[k]) * sd.ctab_rowlen[k];
-                st.c[k] = Tb.ctab[st.rb[k] + w];
-                lam += __popc(w);
-            } else {
-                st.w[k] = 0;
-                st.rb[k] = 0;
-                st.c[k] = 0;
-            }
-        }
-        Acc<T, K> acc;
-#pragma unroll
-        for (int c = 0; c < K; ++c) acc.v[c] = (T)0;
-        // right family: sparse row of this offset, four entries at a time
-        uint32_t e = P.rptr[gr];
-        const uint32_t e1 = active ? P.rptr[gr + 1] : e;
-        while (__ballot(e < e1)) {
-            T a[4];
-            uint64_t cols[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const bool ok = e + u < e1;
-                const uint32_t ent = ok ? P.rent[e + u] : 0u;
-                cols[u] = ok ? (uint64_t)(rs + (IdxT)(ent & 0xFFFFFFu)) : (uint64_t)row;
-                a[u] = ok ? C.bamp[ent >> 24] : (T)0;
-            }
-            Acc<T, K> v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = gather<T, K>(x, cols[u]);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) fma_acc<T, K>(acc, a[u], v[u]);
-            e += 4;
-        }
-        // crossing bonds: on-the-fly rank of the touched subsystems
-        T diag = (T)0;
-        ClassLoop<IdxT, T, K, NMAX, true, 0, 0>::run(H, sd, Tb, st, row, x, C.bamp, C.bjz, C.ladder,
-                                                     acc, diag);
-        diag += (T)(P.diag[gl] + P.diag[P.nleft_all + gr]);
-        if (active) {
-            const Acc<T, K> xr = gather<T, K>(x, (uint64_t)row);
-            T *yr = y + (uint64_t)row * K;
-#pragma unroll
-            for (int c = 0; c < K; ++c) __builtin_nontemporal_store(acc.v[c] + diag * xr.v[c], yr + c);
-        }
-    }
-}
-
-template <typename IdxT, typename T, int K>
-__global__ __launch_bounds__(kHxThreads) void split_left_kernel(const SplitParams P) {
-    __shared__ T bamp[kMaxBonds];
-    for (int q = threadIdx.x; q < P.H.nbonds; q += blockDim.x)
-        bamp[q] = (T)(0.5 * P.H.jxy[P.H.pos[q] >> 16]);
-    __syncthreads();
-    const T *__restrict__ x = reinterpret_cast<const T *>(P.H.x);
-    T *__restrict__ y = reinterpret_cast<T *>(P.H.y);
-    const IdxT *__restrict__ runs = reinterpret_cast<const IdxT *>(P.runs);
-    constexpr int CC = left_chunk_cols<T, K>();
-    constexpr int LPT = kHxThreads / CC;
-    const uint32_t u0 = threadIdx.x;
-    __shared__ uint32_t slot;
-    uint64_t t;
-    while (next_tile(P.counters, P.tiles, P.per_xcd, &slot, t)) {
-        int mi = 0;
-        while (mi + 1 < P.m_count && P.tbase[mi + 1] <= t) ++mi;
-        const uint32_t local = (uint32_t)(t - P.tbase[mi]);
-        const uint32_t cc = local / P.nsub[mi], lg = local - cc * P.nsub[mi];
-        const uint32_t li = lg * LPT + u0 / CC;
-        const uint64_t col = (uint64_t)cc * CC + u0 % CC;
-        const bool active = li < P.nleft[mi] && col < P.ncols[mi];
-        const uint32_t gl = P.lbase[mi] + (active ? li : 0u);
-        const uint64_t c0 = active ? col : 0;
-        const IdxT row = runs[gl] + (IdxT)c0;
-        Acc<T, K> acc;
-#pragma unroll
-        for (int c = 0; c < K; ++c) acc.v[c] = (T)0;
-        uint32_t e = P.lptr[gl];
-        const uint32_t e1 = active ? P.lptr[gl + 1] : e;
-        while (__ballot(e < e1)) {
-            T a[4];
-            uint64_t cols[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const bool ok = e + u < e1;
-                const uint64_t ent = ok ? P.lent[e + u] : 0ull;
-                cols[u] = ok ? (ent & 0xFFFFFFFFFFFFull) + c0 : (uint64_t)row;
-                a[u] = ok ? bamp[ent >> 48] : (T)0;
-            }
-            Acc<T, K> v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = gather<T, K>(x, cols[u]);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) fma_acc<T, K>(acc, a[u], v[u]);
-            e += 4;
-        }
-        if (active) {
-            T *yr = y + (uint64_t)row * K;
-            if constexpr (K > 1 && sizeof(T) * K % 16 == 0) {
-                constexpr int V = 16 / sizeof(T);
-                typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
-#pragma unroll
-                for (int c = 0; c < K; c += V) {
-                    vec_t yv = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(yr + c));
-#pragma unroll
-                    for (int q = 0; q < V; ++q) yv[q] += acc.v[c + q];
-                    __builtin_nontemporal_store(yv, reinterpret_cast<vec_t *>(yr + c));
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < K; ++c)
-                    __builtin_nontemporal_store(__builtin_nontemporal_load(yr + c) + acc.v[c], yr + c);
-            }
-        }
-    }
-}
-
-// Bond classes (a, b) with a < K <= b: they cross the cut.
-inline uint64_t crossing_class_mask(int K, int N, int nmax) {
-    uint64_t m = 0;
-    for (int a = 0; a < K; ++a)
-        for (int b = K; b < N; ++b) m |= 1ull << class_id(a, b, nmax);
-    return m;
-}
-
-template <typename IdxT, typename T, int K, int NMAX>
-int launch_split_t(dcs_sector *s, const HxParams &H, const SplitCsr &csr, hipStream_t stream) {
-    const LeftInfo &li = s->left;
-    SplitParams P;
-    memset(&P, 0, sizeof(P));
-    P.H = H;
-    P.H.cls_mask = crossing_class_mask(li.K, s->desc.N, NMAX);
-    P.H.far_below = li.K;
-    P.lwords = (const uint32_t *)li.d_words;
-    P.rwords = (const uint32_t *)li.d_rwords;
-    P.runs = li.d_runs;
-    P.lptr = csr.d_lptr;
-    P.lent = csr.d_lent;
-    P.rptr = csr.d_rptr;
-    P.rent = csr.d_rent;
-    P.diag = csr.d_diag;
-    P.cut = li.K;
-    P.m_count = li.m_count;
-    P.nleft_all = (uint32_t)li.count;
-    for (int k = 0; k < kMaxSub; ++k) P.word_shift[k] = li.word_shift[k];
-    for (int m = 0; m < li.m_count; ++m) {
-        P.lbase[m] = li.lbase[m];
-        P.nleft[m] = li.nleft[m];
-        P.rbase[m] = li.rbase[m];
-        P.ncols[m] = li.ncols[m];
-    }
-    // 1. diagonal of the two families
-    const uint32_t total = (uint32_t)(li.count + li.rcount);
-    split_diag_kernel<NMAX><<<(total + 255) / 256, 256, 0, stream>>>(P, total);
-    if (int r = check_hip(hipGetLastError(), "split diagonal launch")) return r;
-    const size_t lds = s->desc.lay_bytes + coeff_lds_bytes<T>();
-    const Grid g = plan_grid(s, lds);
-    const int wgs = g.xcd_groups ? g.wgs : ((g.wgs + 7) / 8) * 8;
-    // 2. right family, crossing bonds and diagonal: tiles of 512 offsets of one run
-    uint64_t tiles = 0;
-    for (int m = 0; m < li.m_count; ++m) {
-        P.nsub[m] = (uint32_t)((li.ncols[m] + kHxThreads - 1) / kHxThreads);
-        P.tbase[m] = tiles;
-        tiles += (uint64_t)li.nleft[m] * P.nsub[m];
-    }
-    P.tbase[li.m_count] = tiles;
-    P.tiles = tiles;
-    P.per_xcd = (tiles + 7) / 8;
-    P.counters = s->dev.counters;
-    zero_counters<0><<<1, 64, 0, stream>>>(s->dev.counters, 16);
-    {
-        auto kern = split_right_kernel<IdxT, T, K, NMAX>;
-        if (int r = ensure_lds(kern, lds)) return r;
-        kern<<<wgs, kHxThreads, lds, stream>>>(P);
-        if (int r = check_hip(hipGetLastError(), "split right kernel launch")) return r;
-    }
-    // 3. left family: column chunks of LPT runs
-    constexpr int CC = left_chunk_cols<T, K>();
-    constexpr int LPT = kHxThreads / CC;
-    tiles = 0;
-    for (int m = 0; m < li.m_count; ++m) {
-        const uint64_t ncc = (li.ncols[m] + CC - 1) / CC;
-        P.nsub[m] = (uint32_t)((li.nleft[m] + LPT - 1) / LPT);
-        P.tbase[m] = tiles;
-        tiles += ncc * P.nsub[m];
-    }
-    P.tbase[li.m_count] = tiles;
-    P.tiles = tiles;
-    P.per_xcd = (tiles + 7) / 8;
-    P.counters = s->dev.counters + 8;
-    split_left_kernel<IdxT, T, K><<<wgs, kHxThreads, 0, stream>>>(P);
-    return check_hip(hipGetLastError(), "split left kernel launch");
-}
 
 }  // namespace hx
 }  // namespace dcs

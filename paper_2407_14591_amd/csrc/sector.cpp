@@ -189,10 +189,10 @@ int upload(dcs_sector *s, HostTables<IdxT> &ht) {
     return check_hip(e, "sector tables and counters");
 }
 
-// Left configurations of the two-pass product (see LeftInfo): for every left
+// Left configurations of the split product (see LeftInfo): for every left
 // particle number m, the configurations (w_0..w_{K-1}) with digit sum m in
 // canonical order, with the first row of their run, sum_k C_k[lambda_k][w_k].
-constexpr uint64_t kTwoPassMinDim = 1ull << 22;
+constexpr uint64_t kSplitMinDim = 1ull << 22;
 constexpr size_t kMaxLeftConfigs = 1u << 22;
 
 template <typename IdxT>
@@ -200,8 +200,8 @@ int build_left(const DimTable &Dt, dcs_sector *s, const HostTables<IdxT> &ht, co
     SectorDesc &sd = s->desc;
     LeftInfo &li = s->left;
     li.K = 0;
-    uint64_t min_dim = kTwoPassMinDim;
-    if (const char *e = getenv("DCS_TWO_PASS_MIN_DIM")) min_dim = strtoull(e, nullptr, 10);
+    uint64_t min_dim = kSplitMinDim;
+    if (const char *e = getenv("DCS_SPLIT_MIN_DIM")) min_dim = strtoull(e, nullptr, 10);
     if (sd.N < 2 || sd.Q != 2 || sd.dim < min_dim) return DCS_OK;
     const int K = sd.N / 2;
     int L_left = 0, bits = 0;
@@ -322,13 +322,15 @@ int build_left(const DimTable &Dt, dcs_sector *s, const HostTables<IdxT> &ht, co
 
 }  // namespace
 
-void free_csr(SplitCsr &c) {
+void free_rows(SplitRows &c) {
     hipFree(c.d_lptr);
     hipFree(c.d_lent);
-    hipFree(c.d_rptr);
-    hipFree(c.d_rent);
+    hipFree(c.d_vo);
+    hipFree(c.d_xl);
+    hipFree(c.d_xo);
+    hipFree(c.d_runs);
     hipFree(c.d_diag);
-    c = SplitCsr();
+    c = SplitRows();
 }
 
 void free_split(dcs_sector *s) {
@@ -337,7 +339,7 @@ void free_split(dcs_sector *s) {
     hipFree(li.d_runs);
     hipFree(li.d_rwords);
     li.d_words = li.d_runs = li.d_rwords = nullptr;
-    for (int i = 0; i < kMaxSplitCache; ++i) free_csr(li.csr[i]);
+    for (int i = 0; i < kMaxSplitCache; ++i) free_rows(li.rows[i]);
 }
 
 int make_bond_plan(const dcs_sector *s, const dcs_terms *t, int nmax, BondPlan *p) {

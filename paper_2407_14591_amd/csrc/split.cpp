@@ -1,6 +1,7 @@
-// Sparse rows of the bond families left and right of the cut of a sector's
-// split view (LeftInfo): built on the host from the fused contribution table,
-// once per (sector, terms) pair, and cached in the sector.
+// Target tables of the split product (LeftInfo): built on the host from the
+// fused contribution table, once per (sector, terms) pair, and cached in the
+// sector.  Every target is the rank of eq. index of a configuration that one
+// bond reaches, evaluated per side of the cut.
 #include <algorithm>
 #include <vector>
 
@@ -10,59 +11,81 @@ namespace dcs {
 
 namespace {
 
-struct FamilyBond {
-    int a, b;        // subsystems of the two sites, a <= b
-    uint32_t pil, pjl;  // bits of the sites inside their subsystem words
-    uint32_t t;      // position in the bond plan
+struct SideBond {
+    int a, b;             // subsystems of the two sites
+    uint32_t pi, pj;      // bits of the sites inside their subsystem words
+    uint16_t bond;        // index in the terms
 };
 
 }  // namespace
 
-SplitCsr *split_csr(dcs_sector *s, const dcs_terms *t, const BondPlan &plan, int nmax) {
+SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
     LeftInfo &li = s->left;
     const SectorDesc &sd = s->desc;
     if (li.K == 0 || sd.Q != 2 || li.h_rwords.empty()) return nullptr;
     for (int i = 0; i < kMaxSplitCache; ++i)
-        if (li.csr[i].terms_id == t->id && li.csr[i].nmax == nmax) return &li.csr[i];
+        if (li.rows[i].terms_id == t->id) return &li.rows[i];
     const int K = li.K, N = sd.N;
-    std::vector<FamilyBond> left, right;
-    for (int a = 0; a < nmax; ++a)
-        for (int b = a; b < nmax; ++b) {
-            const int cls = class_id(a, b, nmax);
-            for (int q = plan.cls_beg[cls]; q < plan.cls_beg[cls + 1]; ++q) {
-                FamilyBond fb{a, b, plan.pos[q] & 0xFFu, (plan.pos[q] >> 8) & 0xFFu, (uint32_t)q};
-                if (b < K)
-                    left.push_back(fb);
-                else if (a >= K)
-                    right.push_back(fb);
-            }
+    for (int mi = 0; mi < li.m_count; ++mi)
+        if (li.ncols[mi] >= 0xFFFFu) return nullptr;  // offsets are 16-bit
+    auto packed_bit = [&](int site) -> uint8_t {
+        return (uint8_t)(li.word_shift[sd.site_sub[site]] + sd.site_bit[site]);
+    };
+    SplitRows c;
+    c.terms_id = t->id;
+    std::vector<SideBond> left, right;
+    std::vector<int> lsites, rsites;  // crossing sites per slot
+    for (int q = 0; q < t->num_bonds; ++q) {
+        int i = t->si[q], j = t->sj[q];
+        int a = sd.site_sub[i], b = sd.site_sub[j];
+        if (a > b) {
+            std::swap(i, j);
+            std::swap(a, b);
         }
+        if (b < K || a >= K) {
+            SideBond fb{a, b, sd.site_bit[i], sd.site_bit[j], (uint16_t)q};
+            (b < K ? left : right).push_back(fb);
+            c.d[c.nD++] = DiagTerm{(uint8_t)(b < K ? 0 : 1), packed_bit(i), packed_bit(j), 0,
+                                   (uint16_t)q, 0};
+            continue;
+        }
+        if (c.nX == kMaxCross) return nullptr;
+        auto slot = [](std::vector<int> &v, int site) -> int {
+            auto it = std::find(v.begin(), v.end(), site);
+            if (it != v.end()) return (int)(it - v.begin());
+            v.push_back(site);
+            return (int)v.size() - 1;
+        };
+        const int si = slot(lsites, i), sj = slot(rsites, j);
+        if (si >= kMaxCrossSites || sj >= kMaxCrossSites) return nullptr;
+        c.x[c.nX++] = CrossBond{(uint8_t)si, (uint8_t)sj, packed_bit(i), packed_bit(j), (uint16_t)q, 0};
+    }
+    for (int i = 0; i < sd.L; ++i)
+        c.d[c.nD++] = DiagTerm{(uint8_t)(sd.site_sub[i] < K ? 0 : 1), packed_bit(i), 0, 1, (uint16_t)i, 0};
+    c.nR = (int)right.size();
+    c.nIs = (int)lsites.size();
+    c.nJs = (int)rsites.size();
+    for (int b = 0; b < c.nR; ++b) c.r_bond[b] = right[b].bond;
+
     auto cval = [&](int k, int lam, uint32_t w) -> uint64_t {
         return li.h_ctab[sd.ctab_row0[k] + (uint32_t)(lam - sd.lam_lo[k]) * sd.ctab_rowlen[k] + w];
     };
     auto unpack = [&](uint32_t pw, int k) -> uint32_t {
         return (pw >> li.word_shift[k]) & ((1u << sd.wbits[k]) - 1u);
     };
-    // a hop of bond fb on the words w (lambda prefix lam): new words and lambda shift
-    auto hop = [&](const FamilyBond &fb, const uint32_t *w, uint32_t *w2, int *dl) -> bool {
-        const uint32_t bi = (w[fb.a] >> fb.pil) & 1u, bj = (w[fb.b] >> fb.pjl) & 1u;
-        if (bi == bj) return false;
-        for (int k = 0; k < N; ++k) w2[k] = w[k];
-        w2[fb.a] ^= 1u << fb.pil;
-        w2[fb.b] ^= 1u << fb.pjl;
-        *dl = bi ? -1 : 1;  // site i (in P_a) loses or gains the particle
-        return true;
+    // sum of C_k[lambda_k][w_k] over subsystems k0..k1-1, lambda starting at lam0
+    auto rank_part = [&](const uint32_t *w, int k0, int k1, int lam0) -> uint64_t {
+        uint64_t v = 0;
+        int lam = lam0;
+        for (int k = k0; k < k1; ++k) {
+            v += cval(k, lam, w[k]);
+            lam += __builtin_popcount(w[k]);
+        }
+        return v;
     };
-    SplitCsr c;
-    c.terms_id = t->id;
-    c.nmax = nmax;
-    std::vector<uint32_t> lptr(li.count + 1), rptr(li.rcount + 1);
-    std::vector<uint64_t> lent;
-    std::vector<uint32_t> rent;
-    uint32_t w[kMaxSub] = {0}, w2[kMaxSub];
-    int lam[kMaxSub + 1];
-    // every left target must be the run start of a left configuration with the
-    // same particle count (so the target row shares the offset's run length)
+    auto in_block = [&](int m) { return m >= li.m_lo && m < li.m_lo + li.m_count; };
+    // every left target must be the run start of a left configuration of the
+    // expected block (so the target's run has the offset's length)
     std::vector<std::pair<uint64_t, int>> run_block(li.count);
     for (int mi = 0; mi < li.m_count; ++mi)
         for (uint32_t q = 0; q < li.nleft[mi]; ++q)
@@ -72,72 +95,107 @@ SplitCsr *split_csr(dcs_sector *s, const dcs_terms *t, const BondPlan &plan, int
         auto it = std::lower_bound(run_block.begin(), run_block.end(), std::make_pair(run, -1));
         return (it != run_block.end() && it->first == run) ? it->second : -1;
     };
-    int gmi = 0;
-    for (size_t g = 0; g < li.count; ++g) {
-        while (gmi + 1 < li.m_count && g >= li.lbase[gmi + 1]) ++gmi;
-        lptr[g] = (uint32_t)lent.size();
-        lam[0] = 0;
-        for (int k = 0; k < K; ++k) {
-            w[k] = unpack(li.h_words[g], k);
-            lam[k + 1] = lam[k] + __builtin_popcount(w[k]);
-        }
-        for (const FamilyBond &fb : left) {
-            int dl;
-            if (!hop(fb, w, w2, &dl)) continue;
-            uint64_t run = 0;
-            for (int k = 0; k < K; ++k) run += cval(k, lam[k] + ((k > fb.a && k <= fb.b) ? dl : 0), w2[k]);
-            if (run >= (1ull << 48) || block_of_run(run) != gmi)
-                return set_error(DCS_EHIP, "internal: left target is not a run of the same block"), nullptr;
-            lent.push_back(run | ((uint64_t)fb.t << 48));
+
+    // left family rows and crossing left flips
+    std::vector<uint32_t> lptr(li.count + 1);
+    std::vector<uint64_t> lent;
+    std::vector<uint64_t> xl((size_t)c.nIs * li.count, ~0ull);
+    uint32_t w[kMaxSub] = {0}, w2[kMaxSub];
+    for (int mi = 0; mi < li.m_count; ++mi) {
+        const int m = li.m_lo + mi;
+        for (uint32_t q = 0; q < li.nleft[mi]; ++q) {
+            const size_t g = li.lbase[mi] + q;
+            lptr[g] = (uint32_t)lent.size();
+            for (int k = 0; k < K; ++k) w[k] = unpack(li.h_words[g], k);
+            for (const SideBond &fb : left) {
+                if (((w[fb.a] >> fb.pi) & 1u) == ((w[fb.b] >> fb.pj) & 1u)) continue;
+                std::copy(w, w + K, w2);
+                w2[fb.a] ^= 1u << fb.pi;
+                w2[fb.b] ^= 1u << fb.pj;
+                const uint64_t run = rank_part(w2, 0, K, 0);
+                if (run >= (1ull << 48) || block_of_run(run) != mi)
+                    return set_error(DCS_EHIP, "internal: left target is not a run of the same block"),
+                           nullptr;
+                lent.push_back(run | ((uint64_t)fb.bond << 48));
+            }
+            for (int si = 0; si < c.nIs; ++si) {
+                const int site = lsites[si], k = sd.site_sub[site];
+                const uint32_t bit = 1u << sd.site_bit[site];
+                const int m2 = m + ((w[k] & bit) ? -1 : 1);
+                if (!in_block(m2)) continue;
+                std::copy(w, w + K, w2);
+                w2[k] ^= bit;
+                const uint64_t run = rank_part(w2, 0, K, 0);
+                if (block_of_run(run) != m2 - li.m_lo)
+                    return set_error(DCS_EHIP, "internal: flipped left configuration"), nullptr;
+                xl[(size_t)si * li.count + g] = run;
+            }
         }
     }
     lptr[li.count] = (uint32_t)lent.size();
+    c.lnnz = lent.size();
+
+    // right family targets and crossing right flips
+    const int nRq = (c.nR + 7) / 8;
+    std::vector<uint16_t> vo((size_t)nRq * li.rcount * 8, 0xFFFFu);
+    const int nJq = (c.nJs + 7) / 8;
+    std::vector<uint16_t> xo((size_t)nJq * li.rcount * 8, 0xFFFFu);
     for (int mi = 0; mi < li.m_count; ++mi) {
         const int m = li.m_lo + mi;
         for (uint64_t r = 0; r < li.ncols[mi]; ++r) {
             const size_t g = li.rbase[mi] + r;
-            rptr[g] = (uint32_t)rent.size();
-            lam[K] = m;
-            for (int k = K; k < N; ++k) {
-                w[k] = unpack(li.h_rwords[g], k);
-                lam[k + 1] = lam[k] + __builtin_popcount(w[k]);
-            }
-            for (const FamilyBond &fb : right) {
-                int dl;
-                if (!hop(fb, w, w2, &dl)) continue;
-                uint64_t off = 0;
-                for (int k = K; k < N; ++k)
-                    off += cval(k, lam[k] + ((k > fb.a && k <= fb.b) ? dl : 0), w2[k]);
-                if (off >= li.ncols[mi] || off >= (1u << 24))
+            for (int k = K; k < N; ++k) w[k] = unpack(li.h_rwords[g], k);
+            if (rank_part(w, K, N, m) != r)
+                return set_error(DCS_EHIP, "internal: right configuration order"), nullptr;
+            for (int b = 0; b < c.nR; ++b) {
+                const SideBond &fb = right[b];
+                if (((w[fb.a] >> fb.pi) & 1u) == ((w[fb.b] >> fb.pj) & 1u)) continue;
+                std::copy(w, w + N, w2);
+                w2[fb.a] ^= 1u << fb.pi;
+                w2[fb.b] ^= 1u << fb.pj;
+                const uint64_t off = rank_part(w2, K, N, m);
+                if (off >= li.ncols[mi])
                     return set_error(DCS_EHIP, "internal: right offset out of its run"), nullptr;
-                rent.push_back((uint32_t)off | (fb.t << 24));
+                vo[((size_t)(b / 8) * li.rcount + g) * 8 + b % 8] = (uint16_t)off;
+            }
+            for (int sj = 0; sj < c.nJs; ++sj) {
+                const int site = rsites[sj], k = sd.site_sub[site];
+                const uint32_t bit = 1u << sd.site_bit[site];
+                // the particle moves to (+1 on the left) or from (-1) the other side
+                const int m2 = m + ((w[k] & bit) ? 1 : -1);
+                if (!in_block(m2)) continue;
+                std::copy(w, w + N, w2);
+                w2[k] ^= bit;
+                const uint64_t off = rank_part(w2, K, N, m2);
+                if (off >= li.ncols[m2 - li.m_lo])
+                    return set_error(DCS_EHIP, "internal: flipped right configuration"), nullptr;
+                xo[((size_t)(sj / 8) * li.rcount + g) * 8 + sj % 8] = (uint16_t)off;
             }
         }
     }
-    rptr[li.rcount] = (uint32_t)rent.size();
-    c.lnnz = lent.size();
-    c.rnnz = rent.size();
     DeviceGuard dg(s->device);
     auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
-        if (check_hip(hipMalloc(dst, bytes ? bytes : 8), "hipMalloc sparse rows")) return false;
-        if (bytes && check_hip(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), "copy sparse rows"))
+        if (check_hip(hipMalloc(dst, bytes ? bytes : 16), "hipMalloc split tables")) return false;
+        if (bytes && check_hip(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), "copy split tables"))
             return false;
         return true;
     };
     bool ok = up((void **)&c.d_lptr, lptr.data(), lptr.size() * sizeof(uint32_t)) &&
               up((void **)&c.d_lent, lent.data(), lent.size() * sizeof(uint64_t)) &&
-              up((void **)&c.d_rptr, rptr.data(), rptr.size() * sizeof(uint32_t)) &&
-              up((void **)&c.d_rent, rent.data(), rent.size() * sizeof(uint32_t)) &&
+              up((void **)&c.d_vo, vo.data(), vo.size() * sizeof(uint16_t)) &&
+              up((void **)&c.d_xl, xl.data(), xl.size() * sizeof(uint64_t)) &&
+              up((void **)&c.d_xo, xo.data(), xo.size() * sizeof(uint16_t)) &&
+              up((void **)&c.d_runs, li.h_runs.data(), li.h_runs.size() * sizeof(uint64_t)) &&
               check_hip(hipMalloc(&c.d_diag, (li.count + li.rcount) * sizeof(double)),
                         "hipMalloc split diagonal") == DCS_OK;
     if (!ok) {
-        free_csr(c);
+        free_rows(c);
         return nullptr;
     }
-    SplitCsr &slot = li.csr[li.next_slot];
+    SplitRows &slot = li.rows[li.next_slot];
     li.next_slot = (li.next_slot + 1) % kMaxSplitCache;
-    if (slot.terms_id) (void)hipDeviceSynchronize();  // the evicted rows may still be in use
-    free_csr(slot);
+    if (slot.terms_id) (void)hipDeviceSynchronize();  // the evicted tables may still be in use
+    free_rows(slot);
     slot = c;
     return &slot;
 }

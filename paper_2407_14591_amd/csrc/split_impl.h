@@ -1,0 +1,461 @@
+// Split product Y = H X for a Q = 2 sector with a left/right view (LeftInfo):
+// H = (left family) + (right family) + (bonds across the cut) + diagonal,
+// each family acting on one side of the cut only (Sec. 4.4's bond sum, with
+// the targets of every bond tabulated per side once per (sector, terms), in
+// the spirit of the paper's cluster matrices, App. C).
+//
+// Three kernels per product, all bound by the gathers of X:
+//  * split_diag_kernel: the diagonal of each side per configuration, from
+//    this call's couplings and fields (count + rcount entries);
+//  * split_rows_kernel: one tile = 512 consecutive offsets of one run (one
+//    left configuration).  The right family reads its targets from a table
+//    per right configuration (16-bit offsets in the run, 0xFFFF where the bond
+//    does not hop); a bond across the cut reads the run of the left
+//    configuration with its left site flipped and the offset of the right
+//    configuration with its right site flipped.  Adds the diagonal, writes Y.
+//  * split_cols_kernel: one wave = 64 consecutive elements of one run; the
+//    left family's targets are the same elements of other runs, listed once
+//    per left configuration and read with scalar loads (the whole wave
+//    shares them), so every gather is one contiguous 256/512-byte segment.
+//    Adds into Y.
+// Every gather is a buffer load bounded by its target run: a table entry that
+// marks "no hop" (or any offset past the run) reads zero and touches nothing.
+#pragma once
+
+#include "hx_impl.h"
+
+namespace dcs {
+namespace sp {
+
+using hx::Acc;
+
+constexpr int kThreads = 512;
+constexpr uint32_t kOob = 0x80000000u;  // past every run: all record counts here are < 2^31
+constexpr uint32_t kBufferWord3 = 0x00020000u;  // 32-bit data format, no swizzle
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             (int)kBufferWord3);
+}
+
+template <typename T, int K>
+__device__ __forceinline__ Acc<T, K> buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    Acc<T, K> v;
+    constexpr int B = K * (int)sizeof(T);
+    if constexpr (B == 4) {
+        const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+        __builtin_memcpy(&v, &u, 4);
+    } else if constexpr (B == 8) {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        __builtin_memcpy(&v, &u, 8);
+    } else {
+#pragma unroll
+        for (int i = 0; i < B / 16; ++i) {
+            const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u * i, 0, 0);
+            __builtin_memcpy(reinterpret_cast<char *>(&v) + 16 * i, &u, 16);
+        }
+    }
+    return v;
+}
+
+// Tables that no kernel writes, read through the constant address space so
+// that loads at a wave-uniform index become scalar loads (and the buffer
+// descriptors built from them stay scalar).
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+template <typename T>
+__device__ __forceinline__ cptr<T> ro(const T *p) {
+    return (cptr<T>)p;
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename TB>
+__device__ __forceinline__ int block_of_tile(const TB *tbase, int m_count, uint64_t t) {
+    int mi = 0;
+    while (mi + 1 < m_count && tbase[mi + 1] <= t) ++mi;
+    return mi;
+}
+
+// ------------------------------------------------------------------ diagonal
+struct DiagParams {
+    const uint32_t *lwords, *rwords;
+    const double *jz, *h;
+    double *out;
+    uint32_t count, rcount;
+    int nD;
+    DiagTerm d[kMaxBonds + kMaxSites];
+};
+static_assert(sizeof(DiagParams) <= 4096, "kernel arguments are limited to 4 KiB");
+
+template <int Unused = 0>
+__global__ __launch_bounds__(256) void split_diag_kernel(const DiagParams P) {
+    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    if (g >= P.count + P.rcount) return;
+    const uint32_t side = g < P.count ? 0u : 1u;
+    const uint32_t w = side ? P.rwords[g - P.count] : P.lwords[g];
+    double d = 0.0;
+    for (int q = 0; q < P.nD; ++q) {
+        const DiagTerm t = P.d[q];
+        if (t.side != side) continue;
+        const uint32_t bi = (w >> t.bi) & 1u;
+        if (t.is_field) {
+            if (P.h) d += P.h[t.index] * ((double)bi - 0.5);
+        } else {
+            const double jz = 0.25 * P.jz[t.index];
+            d += bi == ((w >> t.bj) & 1u) ? jz : -jz;
+        }
+    }
+    P.out[g] = d;
+}
+
+// Per-XCD tile queue (as hx::next_tile) with the next tile claimed one tile
+// ahead, so the latency of the claim overlaps the current tile's work.  Two
+// LDS slots alternate: the slot written during tile i was last read during
+// tile i-1, before the barrier that ends it.
+struct AheadQueue {
+    uint32_t *counters;
+    uint64_t tiles, per_xcd;
+    uint32_t *slot;  // LDS, 2 entries
+    uint32_t xcd, it, pending;
+
+    __device__ __forceinline__ AheadQueue(uint32_t *c, uint64_t n, uint64_t per, uint32_t *lds)
+        : counters(c), tiles(n), per_xcd(per), slot(lds), xcd(blockIdx.x & 7u), it(0), pending(0) {
+        if (threadIdx.x == 0) slot[0] = atomicAdd(counters + xcd, 1u);
+        __syncthreads();
+    }
+    __device__ __forceinline__ bool get(uint64_t &t) {
+        const uint64_t lt = slot[it & 1u];
+        const uint64_t base = (uint64_t)xcd * per_xcd;
+        if (lt >= per_xcd || base + lt >= tiles) return false;
+        t = uniform64(base + lt);
+        if (threadIdx.x == 0) pending = atomicAdd(counters + xcd, 1u);
+        return true;
+    }
+    __device__ __forceinline__ void finish() {
+        if (threadIdx.x == 0) slot[(it + 1u) & 1u] = pending;
+        ++it;
+        __syncthreads();
+    }
+};
+
+// ------------------------------------------------------------------ rows
+struct RowParams {
+    const void *x;
+    void *y;
+    const double *jxy, *jz;
+    const uint32_t *lwords, *rwords;
+    const uint64_t *runs, *xl;
+    const uint16_t *vo, *xo;
+    const double *dl, *dr;
+    uint32_t *counters;
+    uint64_t tiles, per_xcd;
+    uint32_t count, rcount;
+    int m_count, nR, nX;
+    uint32_t lbase[kMaxLeftM], rbase[kMaxLeftM], ncols[kMaxLeftM], nsub[kMaxLeftM];
+    uint64_t tbase[kMaxLeftM + 1];
+    uint16_t rbond[kMaxBonds];
+    CrossBond xb[kMaxCross];
+};
+static_assert(sizeof(RowParams) <= 4096, "kernel arguments are limited to 4 KiB");
+
+// Gathers in flight per batch, sized for about 96 registers of gathered data:
+// every gather is one whole row of K values (RB bytes, one to four 16-byte loads).
+template <typename T, int K>
+struct RowBatch {
+    static constexpr uint32_t RB = K * sizeof(T);
+    static constexpr int R = RB <= 8 ? 32 : (RB == 16 ? 16 : 8);  // right family, whole table rows
+    static constexpr int X = RB <= 16 ? 8 : (RB == 32 ? 4 : 2);                    // across the cut
+};
+
+template <typename T, int K>
+__global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P) {
+    using B = RowBatch<T, K>;
+    constexpr uint32_t RB = B::RB;
+    __shared__ T ramp[kMaxBonds + 32];
+    __shared__ T xamp[kMaxCross + 8], xjz[kMaxCross + 8];
+    __shared__ uint32_t slots[2];
+    for (int q = threadIdx.x; q < kMaxBonds + 32; q += kThreads)
+        ramp[q] = q < P.nR ? (T)(0.5 * P.jxy[P.rbond[q]]) : (T)0;
+    for (int q = threadIdx.x; q < kMaxCross + 8; q += kThreads) {
+        xamp[q] = q < P.nX ? (T)(0.5 * P.jxy[P.xb[q].bond]) : (T)0;
+        xjz[q] = q < P.nX ? (T)(0.25 * P.jz[P.xb[q].bond]) : (T)0;
+    }
+    const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
+    T *__restrict__ y = reinterpret_cast<T *>(P.y);
+    const int nRq = (P.nR + 7) >> 3;
+    AheadQueue Q(P.counters, P.tiles, P.per_xcd, slots);  // its barrier also publishes the LDS above
+    uint64_t t;
+    while (Q.get(t)) {
+        const int mi = block_of_tile(P.tbase, P.m_count, t);
+        const uint32_t local = (uint32_t)(t - P.tbase[mi]);
+        const uint32_t lq = local / P.nsub[mi], ch = local - lq * P.nsub[mi];
+        const uint32_t gl = P.lbase[mi] + lq;
+        const uint32_t ncols = P.ncols[mi];
+        const uint32_t r = ch * kThreads + threadIdx.x;
+        const bool active = r < ncols;
+        const uint32_t gr = P.rbase[mi] + (active ? r : 0u);
+        const uint64_t R = ro(P.runs)[gl];
+        const uint32_t lw = ro(P.lwords)[gl];
+        const double dl = ro(P.dl)[gl];
+        const auto rs = rsrc(x + R * K, ncols * RB);
+        const uint32_t rw = P.rwords[gr];
+        const double dr = P.dr[gr];
+        const Acc<T, K> xs = buf_load<T, K>(rs, r * RB);  // past the run for inactive lanes: zero
+        Acc<T, K> acc;
+#pragma unroll
+        for (int c = 0; c < K; ++c) acc.v[c] = (T)0;
+        // right family: B::R targets per batch, 8 per 16-byte table row
+        for (int q0 = 0; q0 < nRq * 8; q0 += B::R) {
+            uint32_t ov[B::R];
+#pragma unroll
+            for (int i = 0; i < B::R / 8; ++i) {
+                const int qr = (q0 >> 3) + i;
+                const uint4 tv = qr < nRq ? *reinterpret_cast<const uint4 *>(P.vo + ((size_t)qr * P.rcount + gr) * 8)
+                                          : make_uint4(~0u, ~0u, ~0u, ~0u);
+                const uint32_t wv[4] = {tv.x, tv.y, tv.z, tv.w};
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    ov[i * 8 + u] = ((u & 1) ? (wv[u >> 1] >> 16) : (wv[u >> 1] & 0xFFFFu)) * RB;
+            }
+            Acc<T, K> xv[B::R];
+#pragma unroll
+            for (int u = 0; u < B::R; ++u) xv[u] = buf_load<T, K>(rs, ov[u]);
+#pragma unroll
+            for (int u = 0; u < B::R; ++u) hx::fma_acc<T, K>(acc, ramp[q0 + u], xv[u]);
+        }
+        // bonds across the cut: B::X per batch
+        T diag = (T)(dl + dr);
+        uint4 xw = make_uint4(~0u, ~0u, ~0u, ~0u);
+        int xw_group = -1;
+        for (int x0 = 0; x0 < P.nX; x0 += B::X) {
+            Acc<T, K> xv[B::X];
+            bool hop[B::X];
+#pragma unroll
+            for (int u = 0; u < B::X; ++u) {
+                const bool ok = x0 + u < P.nX;
+                const CrossBond cb = P.xb[ok ? x0 + u : 0];
+                const uint32_t bi = (lw >> cb.lbit) & 1u;
+                const uint64_t Rx = ok ? ro(P.xl)[(size_t)cb.si * P.count + gl] : ~0ull;
+                int mx = mi + (bi ? -1 : 1);
+                mx = mx < 0 ? 0 : (mx >= P.m_count ? P.m_count - 1 : mx);
+                const bool valid = Rx != ~0ull;
+                const auto rx = rsrc(x + (valid ? Rx : 0ull) * K, valid ? P.ncols[mx] * RB : 0u);
+                if ((int)(cb.sj >> 3) != xw_group) {  // uniform: table row of this site group
+                    xw_group = cb.sj >> 3;
+                    xw = *reinterpret_cast<const uint4 *>(P.xo + ((size_t)xw_group * P.rcount + gr) * 8);
+                }
+                const uint32_t sj = cb.sj & 7u;
+                const uint32_t wsel = sj >> 1 == 0 ? xw.x : (sj >> 1 == 1 ? xw.y : (sj >> 1 == 2 ? xw.z : xw.w));
+                const uint32_t xo = (sj & 1u) ? (wsel >> 16) : (wsel & 0xFFFFu);
+                hop[u] = ok && bi != ((rw >> cb.rbit) & 1u);
+                xv[u] = buf_load<T, K>(rx, hop[u] ? xo * RB : kOob);
+            }
+#pragma unroll
+            for (int u = 0; u < B::X; ++u) {
+                hx::fma_acc<T, K>(acc, xamp[x0 + u], xv[u]);
+                diag += hop[u] ? -xjz[x0 + u] : xjz[x0 + u];
+            }
+        }
+        if (active) {
+            T *yr = y + (R + r) * K;
+#pragma unroll
+            for (int c = 0; c < K; ++c) __builtin_nontemporal_store(acc.v[c] + diag * xs.v[c], yr + c);
+        }
+        Q.finish();
+    }
+}
+
+// ------------------------------------------------------------------ columns
+struct ColParams {
+    const void *x;
+    void *y;
+    const double *jxy;
+    const uint32_t *lptr;
+    const uint64_t *lent, *runs;
+    uint32_t *counters;
+    uint64_t tiles, per_xcd;
+    int m_count, nbonds;
+    uint32_t lbase[kMaxLeftM], nleft[kMaxLeftM], ncols[kMaxLeftM], ngrp[kMaxLeftM];
+    uint64_t tbase[kMaxLeftM + 1];
+};
+static_assert(sizeof(ColParams) <= 4096, "kernel arguments are limited to 4 KiB");
+
+constexpr int kColWaves = kThreads / 64;  // left configurations per tile (one per wave)
+constexpr int kColBatch = 8;              // gathers in flight per wave
+constexpr uint32_t kColLaneBytes = 16;    // bytes of x per lane and gather
+constexpr uint32_t kColWaveBytes = 64 * kColLaneBytes;
+
+template <typename T, int K>
+__global__ __launch_bounds__(kThreads) void split_cols_kernel(const ColParams P) {
+    constexpr int V = kColLaneBytes / sizeof(T);
+    typedef T vec_t __attribute__((ext_vector_type(V)));
+    __shared__ T amp[kMaxBonds];
+    __shared__ uint32_t slots[2];
+    for (int q = threadIdx.x; q < kMaxBonds; q += kThreads)
+        amp[q] = q < P.nbonds ? (T)(0.5 * P.jxy[q]) : (T)0;
+    const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
+    T *__restrict__ y = reinterpret_cast<T *>(P.y);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    AheadQueue Q(P.counters, P.tiles, P.per_xcd, slots);
+    uint64_t t;
+    while (Q.get(t)) {
+        const int mi = block_of_tile(P.tbase, P.m_count, t);
+        const uint32_t local = (uint32_t)(t - P.tbase[mi]);
+        const uint32_t c = local / P.ngrp[mi], lg = local - c * P.ngrp[mi];
+        const uint32_t li = lg * kColWaves + wave;
+        if (li < P.nleft[mi]) {  // uniform per wave
+            const uint32_t gl = P.lbase[mi] + li;
+            const uint32_t nrec = P.ncols[mi] * (uint32_t)(K * sizeof(T));
+            const uint32_t boff = c * kColWaveBytes + lane * kColLaneBytes;  // byte of the run
+            vec_t acc = (vec_t)(T)0;
+            const uint32_t q1 = ro(P.lptr)[gl + 1];
+            // the last chunk of a run may end inside a lane's 16 bytes: there
+            // every value is loaded on its own, so no load straddles the run end
+            const bool tail = (c + 1) * kColWaveBytes > nrec;  // uniform per wave
+            for (uint32_t q0 = ro(P.lptr)[gl]; q0 < q1; q0 += kColBatch) {
+                vec_t v[kColBatch];
+                T a[kColBatch];
+#pragma unroll
+                for (int u = 0; u < kColBatch; ++u) {
+                    const bool ok = q0 + u < q1;
+                    const uint64_t ent = ro(P.lent)[ok ? q0 + u : q0];
+                    const auto r = rsrc(x + (ent & 0xFFFFFFFFFFFFull) * K, ok ? nrec : 0u);
+                    if (!tail) {
+                        const auto raw = __builtin_amdgcn_raw_buffer_load_b128(r, boff, 0, 0);
+                        __builtin_memcpy(&v[u], &raw, 16);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < V; ++i)
+                            v[u][i] = buf_load<T, 1>(r, boff + i * (uint32_t)sizeof(T)).v[0];
+                    }
+                    a[u] = amp[ent >> 48];
+                }
+#pragma unroll
+                for (int u = 0; u < kColBatch; ++u) acc += a[u] * v[u];
+            }
+            if (boff < nrec) {
+                T *ys = reinterpret_cast<T *>(reinterpret_cast<char *>(y + ro(P.runs)[gl] * K) + boff);
+                if (boff + kColLaneBytes <= nrec) {
+                    vec_t *yp = reinterpret_cast<vec_t *>(ys);
+                    __builtin_nontemporal_store(__builtin_nontemporal_load(yp) + acc, yp);
+                } else {
+                    for (int i = 0; i < V; ++i)
+                        if (boff + i * (uint32_t)sizeof(T) < nrec)
+                            __builtin_nontemporal_store(__builtin_nontemporal_load(ys + i) + acc[i], ys + i);
+                }
+            }
+        }
+        Q.finish();
+    }
+}
+
+// ------------------------------------------------------------------ launch
+inline int split_grid(const dcs_sector *s, uint64_t tiles) {
+    const uint64_t cus = (uint64_t)device_cu_count(s->device);
+    uint64_t w = cus * 4;
+    const uint64_t cap = ((tiles + 7) / 8) * 8;
+    if (w > cap) w = cap;
+    w = ((w + 7) / 8) * 8;  // every XCD queue (blockIdx % 8) has workgroups
+    return (int)(w ? w : 8);
+}
+
+template <typename T, int K>
+int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, const double *jxy,
+                   const double *jz, const double *h, int nbonds, hipStream_t stream) {
+    const LeftInfo &li = s->left;
+    const uint32_t count = (uint32_t)li.count, rcount = (uint32_t)li.rcount;
+    // 1. diagonal per configuration of each side
+    {
+        DiagParams D;
+        memset(&D, 0, sizeof(D));
+        D.lwords = (const uint32_t *)li.d_words;
+        D.rwords = (const uint32_t *)li.d_rwords;
+        D.jz = jz;
+        D.h = h;
+        D.out = c.d_diag;
+        D.count = count;
+        D.rcount = rcount;
+        D.nD = c.nD;
+        memcpy(D.d, c.d, sizeof(D.d));
+        split_diag_kernel<0><<<(count + rcount + 255) / 256, 256, 0, stream>>>(D);
+        if (int r = check_hip(hipGetLastError(), "split diagonal launch")) return r;
+    }
+    hx::zero_counters<0><<<1, 64, 0, stream>>>(s->dev.counters, 16);
+    // 2. right family, bonds across the cut, diagonal: tiles of 512 offsets of one run
+    {
+        RowParams P;
+        memset(&P, 0, sizeof(P));
+        P.x = x;
+        P.y = y;
+        P.jxy = jxy;
+        P.jz = jz;
+        P.lwords = (const uint32_t *)li.d_words;
+        P.rwords = (const uint32_t *)li.d_rwords;
+        P.runs = c.d_runs;
+        P.xl = c.d_xl;
+        P.vo = c.d_vo;
+        P.xo = c.d_xo;
+        P.dl = c.d_diag;
+        P.dr = c.d_diag + count;
+        P.counters = s->dev.counters;
+        P.count = count;
+        P.rcount = rcount;
+        P.m_count = li.m_count;
+        P.nR = c.nR;
+        P.nX = c.nX;
+        uint64_t tiles = 0;
+        for (int m = 0; m < li.m_count; ++m) {
+            P.lbase[m] = li.lbase[m];
+            P.rbase[m] = li.rbase[m];
+            P.ncols[m] = (uint32_t)li.ncols[m];
+            P.nsub[m] = (uint32_t)((li.ncols[m] + kThreads - 1) / kThreads);
+            P.tbase[m] = tiles;
+            tiles += (uint64_t)li.nleft[m] * P.nsub[m];
+        }
+        P.tbase[li.m_count] = tiles;
+        P.tiles = tiles;
+        P.per_xcd = (tiles + 7) / 8;
+        memcpy(P.rbond, c.r_bond, sizeof(P.rbond));
+        memcpy(P.xb, c.x, sizeof(P.xb));
+        split_rows_kernel<T, K><<<split_grid(s, tiles), kThreads, 0, stream>>>(P);
+        if (int r = check_hip(hipGetLastError(), "split rows launch")) return r;
+    }
+    // 3. left family: waves of 1 KiB of one run, tiles of 8 runs, column-chunk major
+    {
+        ColParams P;
+        memset(&P, 0, sizeof(P));
+        P.x = x;
+        P.y = y;
+        P.jxy = jxy;
+        P.lptr = c.d_lptr;
+        P.lent = c.d_lent;
+        P.runs = c.d_runs;
+        P.counters = s->dev.counters + 8;
+        P.m_count = li.m_count;
+        P.nbonds = nbonds;
+        uint64_t tiles = 0;
+        for (int m = 0; m < li.m_count; ++m) {
+            const uint64_t nchunk = (li.ncols[m] * K * sizeof(T) + kColWaveBytes - 1) / kColWaveBytes;
+            P.lbase[m] = li.lbase[m];
+            P.nleft[m] = li.nleft[m];
+            P.ncols[m] = (uint32_t)li.ncols[m];
+            P.ngrp[m] = (li.nleft[m] + kColWaves - 1) / kColWaves;
+            P.tbase[m] = tiles;
+            tiles += nchunk * P.ngrp[m];
+        }
+        P.tbase[li.m_count] = tiles;
+        P.tiles = tiles;
+        P.per_xcd = (tiles + 7) / 8;
+        split_cols_kernel<T, K><<<split_grid(s, tiles), kThreads, 0, stream>>>(P);
+        return check_hip(hipGetLastError(), "split columns launch");
+    }
+}
+
+}  // namespace sp
+}  // namespace dcs

@@ -173,11 +173,16 @@ def test_headline_workload_L32_sampled(dt):
 @pytest.mark.parametrize("L,n,split,k,dt", [
     (12, 6, [3, 3, 3, 3], 1, torch.float64), (12, 5, [4, 4, 4], 8, torch.float32),
     (14, 7, [3, 4, 3, 4], 4, torch.float32), (16, 8, [8, 8], 2, torch.float64),
-    (13, 6, [2, 2, 2, 2, 2, 3], 1, torch.float32), (15, 7, [3, 3, 3, 3, 3], 8, torch.float64)])
-def test_two_pass_small(monkeypatch, L, n, split, k, dt):
-    """The two-pass form (rows for the bonds right of the cut, column chunks for the
-    bonds left of it) forced on small sectors, against the oracle."""
-    monkeypatch.setenv("DCS_TWO_PASS_MIN_DIM", "0")
+    (13, 6, [2, 2, 2, 2, 2, 3], 1, torch.float32), (15, 7, [3, 3, 3, 3, 3], 8, torch.float64),
+    (12, 0, [6, 6], 1, torch.float64), (12, 12, [6, 6], 2, torch.float32),
+    (12, 1, [4, 4, 4], 4, torch.float64), (13, 12, [3, 3, 3, 4], 1, torch.float32),
+    (14, 2, [7, 7], 8, torch.float32), (16, 8, [4, 4, 4, 4], 2, torch.float32)])
+def test_split_small(monkeypatch, L, n, split, k, dt):
+    """The split product (rows for the bonds right of and across the cut, column
+    chunks for the bonds left of it) forced on small sectors, against the oracle;
+    random bond graphs put many bonds across the cut, and n = 0, 1, L-1, L give
+    runs of length one."""
+    monkeypatch.setenv("DCS_SPLIT_MIN_DIM", "0")
     rng = np.random.default_rng(L + k)
     b = BruteSector(2, L, n, split)
     bonds = random_graph(L, 2 * L, rng) + synth.chain_bonds(L, 1)
@@ -191,8 +196,8 @@ def test_two_pass_small(monkeypatch, L, n, split, k, dt):
             assert rel_err(y.cpu().double().numpy(), y_ref) <= TOL[dt], (L, n, split, k, dt, use_h)
 
 
-def test_two_pass_L26_all_rows():
-    """L=26, n=13 (10,400,600 states, split 8/9/9): the two-pass form on every row."""
+def test_split_L26_all_rows():
+    """L=26, n=13 (10,400,600 states, split 8/9/9): the split product on every row."""
     L, n, sp = 26, 13, [8, 9, 9]
     s = dq.Sector(L, n, 2, sp)
     ns = native.NativeSector(2, L, n, sp)

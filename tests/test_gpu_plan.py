@@ -52,7 +52,7 @@ def batched_workload():
 
 def test_batched_workload_one_launch(monkeypatch):
     # one-pass products for the bitwise comparison with the plan (same summation order)
-    monkeypatch.setenv("DCS_TWO_PASS_MIN_DIM", str(1 << 62))
+    monkeypatch.setenv("DCS_SPLIT_MIN_DIM", str(1 << 62))
     specs = batched_workload()
     items, xs = [], []
     total = 0
