@@ -40,8 +40,9 @@
  *    product runs three kernels: the diagonal per configuration of each side,
  *    one pass over the rows for the bonds right of and across the cut, and one
  *    over column chunks for the bonds left of it.  DCS_SPLIT_MIN_DIM (read by
- *    dcs_sector_create) changes the 2^22 threshold; DCS_SPLIT=0 (read once per
- *    process) forces the single pass.
+ *    dcs_sector_create) changes the 2^22 threshold; DCS_SPLIT=0 (read at every
+ *    product) forces the single pass; DCS_SPLIT_LDS=0 (likewise) keeps the row
+ *    pass from staging runs of x in on-chip memory.
  */
 #ifndef DCS_H
 #define DCS_H

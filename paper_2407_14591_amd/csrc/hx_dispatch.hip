@@ -51,14 +51,10 @@ DCS_ADJ_EXTERN(uint64_t, double, 8)
 namespace {
 
 // The split form (LeftInfo) for Q = 2 sectors that have a split view.
-// DCS_SPLIT=0 in the environment selects the single pass everywhere.
+// DCS_SPLIT=0 in the environment (read at every product) selects the single pass.
 inline bool split_enabled() {
-    static int v = -1;
-    if (v < 0) {
-        const char *e = getenv("DCS_SPLIT");
-        v = (e && e[0] == '0') ? 0 : 1;
-    }
-    return v == 1;
+    const char *e = getenv("DCS_SPLIT");
+    return !(e && e[0] == '0');
 }
 
 template <typename IdxT, typename T, int K, int NMAX>

@@ -119,19 +119,20 @@ __global__ __launch_bounds__(256) void split_diag_kernel(const DiagParams P) {
 // tile i-1, before the barrier that ends it.
 struct AheadQueue {
     uint32_t *counters;
-    uint64_t tiles, per_xcd;
-    uint32_t *slot;  // LDS, 2 entries
+    uint64_t base, end;  // this XCD's tile range
+    uint32_t *slot;      // LDS, 2 entries
     uint32_t xcd, it, pending;
 
-    __device__ __forceinline__ AheadQueue(uint32_t *c, uint64_t n, uint64_t per, uint32_t *lds)
-        : counters(c), tiles(n), per_xcd(per), slot(lds), xcd(blockIdx.x & 7u), it(0), pending(0) {
+    __device__ __forceinline__ AheadQueue(uint32_t *c, const uint64_t *xbase, uint32_t *lds)
+        : counters(c), slot(lds), xcd(blockIdx.x & 7u), it(0), pending(0) {
+        base = xbase[xcd];
+        end = xbase[xcd + 1];
         if (threadIdx.x == 0) slot[0] = atomicAdd(counters + xcd, 1u);
         __syncthreads();
     }
     __device__ __forceinline__ bool get(uint64_t &t) {
         const uint64_t lt = slot[it & 1u];
-        const uint64_t base = (uint64_t)xcd * per_xcd;
-        if (lt >= per_xcd || base + lt >= tiles) return false;
+        if (base + lt >= end) return false;
         t = uniform64(base + lt);
         if (threadIdx.x == 0) pending = atomicAdd(counters + xcd, 1u);
         return true;
@@ -143,6 +144,12 @@ struct AheadQueue {
     }
 };
 
+// Tile ranges of the 8 XCDs: equal counts, or (weights given) equal sums of weight.
+inline void xcd_ranges(uint64_t tiles, uint64_t *xbase) {
+    const uint64_t per = (tiles + 7) / 8;
+    for (int x = 0; x <= 8; ++x) xbase[x] = std::min<uint64_t>(tiles, (uint64_t)x * per);
+}
+
 // ------------------------------------------------------------------ rows
 struct RowParams {
     const void *x;
@@ -153,7 +160,7 @@ struct RowParams {
     const uint16_t *vo, *xo;
     const double *dl, *dr;
     uint32_t *counters;
-    uint64_t tiles, per_xcd;
+    uint64_t xbase[9];  // tile range of every XCD
     uint32_t count, rcount;
     int m_count, nR, nX;
     uint32_t lbase[kMaxLeftM], rbase[kMaxLeftM], ncols[kMaxLeftM], nsub[kMaxLeftM];
@@ -188,7 +195,7 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P)
     const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
     T *__restrict__ y = reinterpret_cast<T *>(P.y);
     const int nRq = (P.nR + 7) >> 3;
-    AheadQueue Q(P.counters, P.tiles, P.per_xcd, slots);  // its barrier also publishes the LDS above
+    AheadQueue Q(P.counters, P.xbase, slots);  // its barrier also publishes the LDS above
     uint64_t t;
     while (Q.get(t)) {
         const int mi = block_of_tile(P.tbase, P.m_count, t);
@@ -222,9 +229,18 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P)
                 for (int u = 0; u < 8; ++u)
                     ov[i * 8 + u] = ((u & 1) ? (wv[u >> 1] >> 16) : (wv[u >> 1] & 0xFFFFu)) * RB;
             }
+            // a bond with no hop on any lane of the wave (frequent for bonds inside
+            // the first right subsystem, whose hops are shared by runs of rows) is skipped
             Acc<T, K> xv[B::R];
 #pragma unroll
-            for (int u = 0; u < B::R; ++u) xv[u] = buf_load<T, K>(rs, ov[u]);
+            for (int u = 0; u < B::R; ++u) {
+                if (__builtin_amdgcn_ballot_w64(active && ov[u] < 0xFFFFu * RB)) {
+                    xv[u] = buf_load<T, K>(rs, ov[u]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < K; ++c) xv[u].v[c] = (T)0;
+                }
+            }
 #pragma unroll
             for (int u = 0; u < B::R; ++u) hx::fma_acc<T, K>(acc, ramp[q0 + u], xv[u]);
         }
@@ -253,7 +269,12 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P)
                 const uint32_t wsel = sj >> 1 == 0 ? xw.x : (sj >> 1 == 1 ? xw.y : (sj >> 1 == 2 ? xw.z : xw.w));
                 const uint32_t xo = (sj & 1u) ? (wsel >> 16) : (wsel & 0xFFFFu);
                 hop[u] = ok && bi != ((rw >> cb.rbit) & 1u);
-                xv[u] = buf_load<T, K>(rx, hop[u] ? xo * RB : kOob);
+                if (__builtin_amdgcn_ballot_w64(active && hop[u])) {
+                    xv[u] = buf_load<T, K>(rx, hop[u] ? xo * RB : kOob);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < K; ++c) xv[u].v[c] = (T)0;
+                }
             }
 #pragma unroll
             for (int u = 0; u < B::X; ++u) {
@@ -270,6 +291,133 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P)
     }
 }
 
+// Rows kernel with the run of X staged in LDS (rows of at most 8 bytes and runs
+// that fit): one tile = one left configuration's whole run.  The right family
+// (and the diagonal) read the staged run; entry ncols of the staged run is
+// zero and stands for "no hop".  Bonds across the cut gather from HBM as above.
+constexpr uint32_t kRowLdsMax = 112 * 1024;
+
+template <typename T, int K>
+__global__ __launch_bounds__(kThreads) void split_rows_lds_kernel(const RowParams P) {
+    using B = RowBatch<T, K>;
+    using V = Acc<T, K>;
+    constexpr uint32_t RB = B::RB;
+    static_assert(RB <= 8, "staged runs hold rows of at most 8 bytes");
+    extern __shared__ __align__(16) char dyn[];
+    V *xr = reinterpret_cast<V *>(dyn);
+    __shared__ T ramp[kMaxBonds + 32];
+    __shared__ T xamp[kMaxCross + 8], xjz[kMaxCross + 8];
+    __shared__ uint32_t slots[2];
+    for (int q = threadIdx.x; q < kMaxBonds + 32; q += kThreads)
+        ramp[q] = q < P.nR ? (T)(0.5 * P.jxy[P.rbond[q]]) : (T)0;
+    for (int q = threadIdx.x; q < kMaxCross + 8; q += kThreads) {
+        xamp[q] = q < P.nX ? (T)(0.5 * P.jxy[P.xb[q].bond]) : (T)0;
+        xjz[q] = q < P.nX ? (T)(0.25 * P.jz[P.xb[q].bond]) : (T)0;
+    }
+    const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
+    T *__restrict__ y = reinterpret_cast<T *>(P.y);
+    const int nRq = (P.nR + 7) >> 3;
+    AheadQueue Q(P.counters, P.xbase, slots);
+    uint64_t t;
+    while (Q.get(t)) {
+        const int mi = block_of_tile(P.tbase, P.m_count, t);
+        const uint32_t gl = (uint32_t)t;  // tiles enumerate the left configurations
+        const uint32_t ncols = P.ncols[mi];
+        const uint64_t R = ro(P.runs)[gl];
+        const uint32_t lw = ro(P.lwords)[gl];
+        const double dl = ro(P.dl)[gl];
+        const uint32_t bytes = ncols * RB;
+        // stage the run: 16-byte pieces, then the last few 4-byte words
+        {
+            const auto rs = rsrc(x + R * K, bytes);
+            uint4 *d16 = reinterpret_cast<uint4 *>(dyn);
+            for (uint32_t i = threadIdx.x; i < bytes / 16; i += kThreads) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, i * 16u, 0, 0);
+                __builtin_memcpy(&d16[i], &v, 16);
+            }
+            uint32_t *d4 = reinterpret_cast<uint32_t *>(dyn);
+            const uint32_t w0 = (bytes / 16) * 4;
+            if (threadIdx.x < (bytes / 4) - w0)
+                d4[w0 + threadIdx.x] = __builtin_amdgcn_raw_buffer_load_b32(rs, (w0 + threadIdx.x) * 4u, 0, 0);
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int c = 0; c < K; ++c) xr[ncols].v[c] = (T)0;
+            }
+        }
+        __syncthreads();
+        for (uint32_t c0 = 0; c0 < ncols; c0 += kThreads) {
+            const uint32_t r = c0 + threadIdx.x;
+            const bool active = r < ncols;
+            const uint32_t gr = P.rbase[mi] + (active ? r : 0u);
+            const uint32_t rw = P.rwords[gr];
+            const double dr = P.dr[gr];
+            V acc;
+#pragma unroll
+            for (int c = 0; c < K; ++c) acc.v[c] = (T)0;
+            for (int q0 = 0; q0 < nRq * 8; q0 += 32) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int qr = (q0 >> 3) + i;
+                    const uint4 tv = qr < nRq ? *reinterpret_cast<const uint4 *>(P.vo + ((size_t)qr * P.rcount + gr) * 8)
+                                              : make_uint4(~0u, ~0u, ~0u, ~0u);
+                    const uint32_t wv[4] = {tv.x, tv.y, tv.z, tv.w};
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const uint32_t e = (u & 1) ? (wv[u >> 1] >> 16) : (wv[u >> 1] & 0xFFFFu);
+                        const V v = xr[e < ncols ? e : ncols];
+                        hx::fma_acc<T, K>(acc, ramp[q0 + i * 8 + u], v);
+                    }
+                }
+            }
+            T diag = (T)(dl + dr);
+            uint4 xw = make_uint4(~0u, ~0u, ~0u, ~0u);
+            int xw_group = -1;
+            for (int x0 = 0; x0 < P.nX; x0 += B::X) {
+                V xv[B::X];
+                bool hop[B::X];
+#pragma unroll
+                for (int u = 0; u < B::X; ++u) {
+                    const bool ok = x0 + u < P.nX;
+                    const CrossBond cb = P.xb[ok ? x0 + u : 0];
+                    const uint32_t bi = (lw >> cb.lbit) & 1u;
+                    const uint64_t Rx = ok ? ro(P.xl)[(size_t)cb.si * P.count + gl] : ~0ull;
+                    int mx = mi + (bi ? -1 : 1);
+                    mx = mx < 0 ? 0 : (mx >= P.m_count ? P.m_count - 1 : mx);
+                    const bool valid = Rx != ~0ull;
+                    const auto rx = rsrc(x + (valid ? Rx : 0ull) * K, valid ? P.ncols[mx] * RB : 0u);
+                    if ((int)(cb.sj >> 3) != xw_group) {
+                        xw_group = cb.sj >> 3;
+                        xw = *reinterpret_cast<const uint4 *>(P.xo + ((size_t)xw_group * P.rcount + gr) * 8);
+                    }
+                    const uint32_t sj = cb.sj & 7u;
+                    const uint32_t wsel =
+                        sj >> 1 == 0 ? xw.x : (sj >> 1 == 1 ? xw.y : (sj >> 1 == 2 ? xw.z : xw.w));
+                    const uint32_t xo = (sj & 1u) ? (wsel >> 16) : (wsel & 0xFFFFu);
+                    hop[u] = ok && bi != ((rw >> cb.rbit) & 1u);
+                    if (__builtin_amdgcn_ballot_w64(active && hop[u])) {
+                        xv[u] = buf_load<T, K>(rx, hop[u] ? xo * RB : kOob);
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < K; ++c) xv[u].v[c] = (T)0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < B::X; ++u) {
+                    hx::fma_acc<T, K>(acc, xamp[x0 + u], xv[u]);
+                    diag += hop[u] ? -xjz[x0 + u] : xjz[x0 + u];
+                }
+            }
+            if (active) {
+                const V xs = xr[r];
+                T *yr = y + (R + r) * K;
+#pragma unroll
+                for (int c = 0; c < K; ++c) __builtin_nontemporal_store(acc.v[c] + diag * xs.v[c], yr + c);
+            }
+        }
+        Q.finish();  // its barrier also ends the reads of the staged run
+    }
+}
+
 // ------------------------------------------------------------------ columns
 struct ColParams {
     const void *x;
@@ -278,7 +426,7 @@ struct ColParams {
     const uint32_t *lptr;
     const uint64_t *lent, *runs;
     uint32_t *counters;
-    uint64_t tiles, per_xcd;
+    uint64_t xbase[9];
     int m_count, nbonds;
     uint32_t lbase[kMaxLeftM], nleft[kMaxLeftM], ncols[kMaxLeftM], ngrp[kMaxLeftM];
     uint64_t tbase[kMaxLeftM + 1];
@@ -302,7 +450,7 @@ __global__ __launch_bounds__(kThreads) void split_cols_kernel(const ColParams P)
     T *__restrict__ y = reinterpret_cast<T *>(P.y);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
-    AheadQueue Q(P.counters, P.tiles, P.per_xcd, slots);
+    AheadQueue Q(P.counters, P.xbase, slots);
     uint64_t t;
     while (Q.get(t)) {
         const int mi = block_of_tile(P.tbase, P.m_count, t);
@@ -356,6 +504,12 @@ __global__ __launch_bounds__(kThreads) void split_cols_kernel(const ColParams P)
 }
 
 // ------------------------------------------------------------------ launch
+// DCS_SPLIT_LDS=0 in the environment (read at every product) keeps the runs out of LDS.
+inline bool rows_lds_enabled() {
+    const char *e = getenv("DCS_SPLIT_LDS");
+    return !(e && e[0] == '0');
+}
+
 inline int split_grid(const dcs_sector *s, uint64_t tiles) {
     const uint64_t cus = (uint64_t)device_cu_count(s->device);
     uint64_t w = cus * 4;
@@ -419,12 +573,52 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
             tiles += (uint64_t)li.nleft[m] * P.nsub[m];
         }
         P.tbase[li.m_count] = tiles;
-        P.tiles = tiles;
-        P.per_xcd = (tiles + 7) / 8;
+        xcd_ranges(tiles, P.xbase);
         memcpy(P.rbond, c.r_bond, sizeof(P.rbond));
         memcpy(P.xb, c.x, sizeof(P.xb));
-        split_rows_kernel<T, K><<<split_grid(s, tiles), kThreads, 0, stream>>>(P);
-        if (int r = check_hip(hipGetLastError(), "split rows launch")) return r;
+        uint64_t max_cols = 0;
+        for (int m = 0; m < li.m_count; ++m) max_cols = std::max<uint64_t>(max_cols, li.ncols[m]);
+        const size_t lds = ((max_cols + 1) * RowBatch<T, K>::RB + 15) / 16 * 16;
+        bool staged = false;
+        if constexpr (RowBatch<T, K>::RB <= 8) {
+            if (lds <= kRowLdsMax && rows_lds_enabled()) {
+                // one tile per left configuration
+                // one tile per left configuration; the XCD ranges hold equal row counts
+                for (int m = 0; m < li.m_count; ++m) P.tbase[m] = li.lbase[m];
+                P.tbase[li.m_count] = count;
+                {
+                    const uint64_t total = s->desc.dim;
+                    uint64_t acc = 0, g = 0;
+                    P.xbase[0] = 0;
+                    for (int xq = 1; xq < 8; ++xq) {
+                        const uint64_t want = total * xq / 8;
+                        for (int m = 0; m < li.m_count; ++m) {
+                            const uint64_t g1 = (uint64_t)li.lbase[m] + li.nleft[m];
+                            while (g < g1 && acc + li.ncols[m] <= want) {
+                                acc += li.ncols[m];
+                                ++g;
+                            }
+                            if (g < g1) break;
+                        }
+                        P.xbase[xq] = g;
+                    }
+                    P.xbase[8] = count;
+                }
+                auto kern = split_rows_lds_kernel<T, K>;
+                if (int r = ensure_lds(kern, lds)) return r;
+                const int per_cu = std::max<int>(1, std::min<int>(4, (int)((160 * 1024) / (lds + 4096))));
+                int wgs = device_cu_count(s->device) * per_cu;
+                wgs = std::min<int>(wgs, (int)(((uint64_t)count + 7) / 8 * 8));
+                wgs = (wgs + 7) / 8 * 8;
+                kern<<<wgs, kThreads, lds, stream>>>(P);
+                if (int r = check_hip(hipGetLastError(), "split rows (staged runs) launch")) return r;
+                staged = true;
+            }
+        }
+        if (!staged) {
+            split_rows_kernel<T, K><<<split_grid(s, tiles), kThreads, 0, stream>>>(P);
+            if (int r = check_hip(hipGetLastError(), "split rows launch")) return r;
+        }
     }
     // 3. left family: waves of 1 KiB of one run, tiles of 8 runs, column-chunk major
     {
@@ -450,8 +644,7 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
             tiles += nchunk * P.ngrp[m];
         }
         P.tbase[li.m_count] = tiles;
-        P.tiles = tiles;
-        P.per_xcd = (tiles + 7) / 8;
+        xcd_ranges(tiles, P.xbase);
         split_cols_kernel<T, K><<<split_grid(s, tiles), kThreads, 0, stream>>>(P);
         return check_hip(hipGetLastError(), "split columns launch");
     }

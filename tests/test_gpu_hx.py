@@ -177,12 +177,14 @@ def test_headline_workload_L32_sampled(dt):
     (12, 0, [6, 6], 1, torch.float64), (12, 12, [6, 6], 2, torch.float32),
     (12, 1, [4, 4, 4], 4, torch.float64), (13, 12, [3, 3, 3, 4], 1, torch.float32),
     (14, 2, [7, 7], 8, torch.float32), (16, 8, [4, 4, 4, 4], 2, torch.float32)])
-def test_split_small(monkeypatch, L, n, split, k, dt):
+@pytest.mark.parametrize("staged", ["1", "0"])
+def test_split_small(monkeypatch, L, n, split, k, dt, staged):
     """The split product (rows for the bonds right of and across the cut, column
     chunks for the bonds left of it) forced on small sectors, against the oracle;
     random bond graphs put many bonds across the cut, and n = 0, 1, L-1, L give
     runs of length one."""
     monkeypatch.setenv("DCS_SPLIT_MIN_DIM", "0")
+    monkeypatch.setenv("DCS_SPLIT_LDS", staged)
     rng = np.random.default_rng(L + k)
     b = BruteSector(2, L, n, split)
     bonds = random_graph(L, 2 * L, rng) + synth.chain_bonds(L, 1)
@@ -196,8 +198,11 @@ def test_split_small(monkeypatch, L, n, split, k, dt):
             assert rel_err(y.cpu().double().numpy(), y_ref) <= TOL[dt], (L, n, split, k, dt, use_h)
 
 
-def test_split_L26_all_rows():
-    """L=26, n=13 (10,400,600 states, split 8/9/9): the split product on every row."""
+@pytest.mark.parametrize("staged", ["1", "0"])
+def test_split_L26_all_rows(monkeypatch, staged):
+    """L=26, n=13 (10,400,600 states, split 8/9/9): the split product on every row,
+    with and without the runs of x staged in LDS."""
+    monkeypatch.setenv("DCS_SPLIT_LDS", staged)
     L, n, sp = 26, 13, [8, 9, 9]
     s = dq.Sector(L, n, 2, sp)
     ns = native.NativeSector(2, L, n, sp)
@@ -208,3 +213,31 @@ def test_split_L26_all_rows():
         y = dq.hamiltonian_apply(s, dq.Terms(bonds), dev_f64(jxy), dev_f64(jz),
                                  torch.tensor(x, device=DEV).to(dt))
         assert rel_err(y.cpu().double().numpy(), y_ref) <= TOL[dt]
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 8])
+def test_split_matches_single_pass_L24(monkeypatch, k):
+    """L=24, n=12 (2,704,156 states) with the split view forced on: the split product
+    (staged and unstaged runs) against the single pass, both ways in FP64 and FP32."""
+    monkeypatch.setenv("DCS_SPLIT_MIN_DIM", "0")
+    L, n = 24, 12
+    s = dq.Sector(L, n, 2, [6, 6, 6, 6])
+    bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.5, 1.0)
+    t = dq.Terms(bonds)
+    h = synth.gaussian(L, synth.SEED_G)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(k)
+    for dt in (torch.float64, torch.float32):
+        x = torch.randn((s.dim, k) if k > 1 else (s.dim,), generator=g, device=DEV,
+                        dtype=torch.float64).to(dt)
+        out = {}
+        for mode, env in (("single", {"DCS_SPLIT": "0"}), ("staged", {"DCS_SPLIT_LDS": "1"}),
+                          ("global", {"DCS_SPLIT_LDS": "0"})):
+            for key in ("DCS_SPLIT", "DCS_SPLIT_LDS"):
+                monkeypatch.delenv(key, raising=False)
+            for key, v in env.items():
+                monkeypatch.setenv(key, v)
+            out[mode] = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), x,
+                                             h=dev_f64(h)).double().cpu().numpy()
+        for mode in ("staged", "global"):
+            assert rel_err(out[mode], out["single"]) <= TOL[dt], (k, dt, mode)
