@@ -297,20 +297,49 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P)
 // zero and stands for "no hop".  Bonds across the cut gather from HBM as above.
 constexpr uint32_t kRowLdsMax = 112 * 1024;
 
+// Per-lane table data of one chunk of a run (loaded one chunk ahead).
+struct ChunkIdx {
+    uint4 tv[4];   // right-family targets of the first 32 bonds
+    uint4 xw;      // flipped-right-site offsets of the first 8 site slots
+    uint32_t rw;   // packed right word
+    double dr;     // right diagonal
+};
+
+__device__ __forceinline__ ChunkIdx load_chunk_idx(const RowParams &P, int mi, uint32_t r, uint32_t ncols,
+                                                   int nRq) {
+    ChunkIdx c;
+    const uint32_t gr = P.rbase[mi] + (r < ncols ? r : 0u);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        c.tv[i] = i < nRq ? *reinterpret_cast<const uint4 *>(P.vo + ((size_t)i * P.rcount + gr) * 8)
+                          : make_uint4(~0u, ~0u, ~0u, ~0u);
+    c.xw = P.nX > 0 ? *reinterpret_cast<const uint4 *>(P.xo + (size_t)gr * 8) : make_uint4(~0u, ~0u, ~0u, ~0u);
+    c.rw = P.rwords[gr];
+    c.dr = P.dr[gr];
+    return c;
+}
+
+__device__ __forceinline__ uint32_t u16_of(const uint4 &v, uint32_t i) {  // i uniform, < 8
+    const uint32_t w = (i >> 1) == 0 ? v.x : ((i >> 1) == 1 ? v.y : ((i >> 1) == 2 ? v.z : v.w));
+    return (i & 1u) ? (w >> 16) : (w & 0xFFFFu);
+}
+
 template <typename T, int K>
 __global__ __launch_bounds__(kThreads) void split_rows_lds_kernel(const RowParams P) {
-    using B = RowBatch<T, K>;
     using V = Acc<T, K>;
-    constexpr uint32_t RB = B::RB;
+    constexpr uint32_t RB = K * sizeof(T);
     static_assert(RB <= 8, "staged runs hold rows of at most 8 bytes");
+    constexpr int XF = 32;  // bonds across the cut whose gather descriptors are set up once per run
+    constexpr int XB = 4;   // of those, gathers in flight per batch
     extern __shared__ __align__(16) char dyn[];
     V *xr = reinterpret_cast<V *>(dyn);
-    __shared__ T ramp[kMaxBonds + 32];
-    __shared__ T xamp[kMaxCross + 8], xjz[kMaxCross + 8];
+    __shared__ T ramp[kMaxBonds];
+    __shared__ T xamp[kMaxCross], xjz[kMaxCross];
+    __shared__ uint4 xinfo[XF];  // per bond across the cut: run base (lo, hi), bytes | bit << 31
     __shared__ uint32_t slots[2];
-    for (int q = threadIdx.x; q < kMaxBonds + 32; q += kThreads)
+    for (int q = threadIdx.x; q < kMaxBonds; q += kThreads)
         ramp[q] = q < P.nR ? (T)(0.5 * P.jxy[P.rbond[q]]) : (T)0;
-    for (int q = threadIdx.x; q < kMaxCross + 8; q += kThreads) {
+    for (int q = threadIdx.x; q < kMaxCross; q += kThreads) {
         xamp[q] = q < P.nX ? (T)(0.5 * P.jxy[P.xb[q].bond]) : (T)0;
         xjz[q] = q < P.nX ? (T)(0.25 * P.jz[P.xb[q].bond]) : (T)0;
     }
@@ -327,7 +356,20 @@ __global__ __launch_bounds__(kThreads) void split_rows_lds_kernel(const RowParam
         const uint32_t lw = ro(P.lwords)[gl];
         const double dl = ro(P.dl)[gl];
         const uint32_t bytes = ncols * RB;
-        // stage the run: 16-byte pieces, then the last few 4-byte words
+        // gather descriptors of the first XF bonds across the cut, one lane per bond
+        const int nXF = P.nX < XF ? P.nX : XF;
+        if ((int)threadIdx.x < nXF) {
+            const CrossBond cb = P.xb[threadIdx.x];
+            const uint32_t b0 = (lw >> cb.lbit) & 1u;
+            const uint64_t Rx = ro(P.xl)[(size_t)cb.si * P.count + gl];
+            int mx = mi + (b0 ? -1 : 1);
+            mx = mx < 0 ? 0 : (mx >= P.m_count ? P.m_count - 1 : mx);
+            const bool valid = Rx != ~0ull;
+            const uint64_t base = reinterpret_cast<uint64_t>(x + (valid ? Rx : 0ull) * K);
+            xinfo[threadIdx.x] = make_uint4((uint32_t)base, (uint32_t)(base >> 32),
+                                            (valid ? P.ncols[mx] * RB : 0u) | (b0 << 31), 0u);
+        }
+        // stage the run: 16-byte pieces, then the last few 4-byte words; entry ncols is zero
         {
             const auto rs = rsrc(x + R * K, bytes);
             uint4 *d16 = reinterpret_cast<uint4 *>(dyn);
@@ -344,68 +386,90 @@ __global__ __launch_bounds__(kThreads) void split_rows_lds_kernel(const RowParam
                 for (int c = 0; c < K; ++c) xr[ncols].v[c] = (T)0;
             }
         }
+        ChunkIdx cur = load_chunk_idx(P, mi, threadIdx.x, ncols, nRq);
         __syncthreads();
         for (uint32_t c0 = 0; c0 < ncols; c0 += kThreads) {
             const uint32_t r = c0 + threadIdx.x;
             const bool active = r < ncols;
-            const uint32_t gr = P.rbase[mi] + (active ? r : 0u);
-            const uint32_t rw = P.rwords[gr];
-            const double dr = P.dr[gr];
+            ChunkIdx nxt = cur;
+            if (c0 + kThreads < ncols) nxt = load_chunk_idx(P, mi, r + kThreads, ncols, nRq);
             V acc;
 #pragma unroll
             for (int c = 0; c < K; ++c) acc.v[c] = (T)0;
-            for (int q0 = 0; q0 < nRq * 8; q0 += 32) {
+            // right family from the staged run
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int qr = (q0 >> 3) + i;
-                    const uint4 tv = qr < nRq ? *reinterpret_cast<const uint4 *>(P.vo + ((size_t)qr * P.rcount + gr) * 8)
-                                              : make_uint4(~0u, ~0u, ~0u, ~0u);
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t wv[4] = {cur.tv[i].x, cur.tv[i].y, cur.tv[i].z, cur.tv[i].w};
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const uint32_t e = (u & 1) ? (wv[u >> 1] >> 16) : (wv[u >> 1] & 0xFFFFu);
+                    hx::fma_acc<T, K>(acc, ramp[i * 8 + u], xr[e < ncols ? e : ncols]);
+                }
+            }
+            if (nRq > 4) {  // more than 32 right-family bonds
+                const uint32_t gr = P.rbase[mi] + (active ? r : 0u);
+                for (int qr = 4; qr < nRq; ++qr) {
+                    const uint4 tv = *reinterpret_cast<const uint4 *>(P.vo + ((size_t)qr * P.rcount + gr) * 8);
                     const uint32_t wv[4] = {tv.x, tv.y, tv.z, tv.w};
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
                         const uint32_t e = (u & 1) ? (wv[u >> 1] >> 16) : (wv[u >> 1] & 0xFFFFu);
-                        const V v = xr[e < ncols ? e : ncols];
-                        hx::fma_acc<T, K>(acc, ramp[q0 + i * 8 + u], v);
+                        hx::fma_acc<T, K>(acc, ramp[qr * 8 + u], xr[e < ncols ? e : ncols]);
                     }
                 }
             }
-            T diag = (T)(dl + dr);
-            uint4 xw = make_uint4(~0u, ~0u, ~0u, ~0u);
-            int xw_group = -1;
-            for (int x0 = 0; x0 < P.nX; x0 += B::X) {
-                V xv[B::X];
-                bool hop[B::X];
+            // bonds across the cut
+            T diag = (T)(dl + cur.dr);
+            for (int q0 = 0; q0 < nXF; q0 += XB) {
+                V xv[XB];
+                bool hop[XB];
 #pragma unroll
-                for (int u = 0; u < B::X; ++u) {
-                    const bool ok = x0 + u < P.nX;
-                    const CrossBond cb = P.xb[ok ? x0 + u : 0];
-                    const uint32_t bi = (lw >> cb.lbit) & 1u;
-                    const uint64_t Rx = ok ? ro(P.xl)[(size_t)cb.si * P.count + gl] : ~0ull;
-                    int mx = mi + (bi ? -1 : 1);
-                    mx = mx < 0 ? 0 : (mx >= P.m_count ? P.m_count - 1 : mx);
-                    const bool valid = Rx != ~0ull;
-                    const auto rx = rsrc(x + (valid ? Rx : 0ull) * K, valid ? P.ncols[mx] * RB : 0u);
-                    if ((int)(cb.sj >> 3) != xw_group) {
-                        xw_group = cb.sj >> 3;
-                        xw = *reinterpret_cast<const uint4 *>(P.xo + ((size_t)xw_group * P.rcount + gr) * 8);
+                for (int u = 0; u < XB; ++u) {
+                    const bool ok = q0 + u < nXF;
+                    const int q = ok ? q0 + u : 0;
+                    const CrossBond cb = P.xb[q];
+                    const uint4 info = xinfo[q];
+                    const uint32_t lo = __builtin_amdgcn_readfirstlane(info.x);
+                    const uint32_t hi = __builtin_amdgcn_readfirstlane(info.y);
+                    const uint32_t nb = __builtin_amdgcn_readfirstlane(info.z);
+                    const auto rr = rsrc(reinterpret_cast<const void *>(((uint64_t)hi << 32) | lo),
+                                         nb & 0x7FFFFFFFu);
+                    uint32_t xo;
+                    if (cb.sj < 8) {
+                        xo = u16_of(cur.xw, cb.sj);
+                    } else {
+                        const uint32_t gr = P.rbase[mi] + (active ? r : 0u);
+                        xo = P.xo[((size_t)(cb.sj >> 3) * P.rcount + gr) * 8 + (cb.sj & 7u)];
                     }
-                    const uint32_t sj = cb.sj & 7u;
-                    const uint32_t wsel =
-                        sj >> 1 == 0 ? xw.x : (sj >> 1 == 1 ? xw.y : (sj >> 1 == 2 ? xw.z : xw.w));
-                    const uint32_t xo = (sj & 1u) ? (wsel >> 16) : (wsel & 0xFFFFu);
-                    hop[u] = ok && bi != ((rw >> cb.rbit) & 1u);
+                    hop[u] = ok && (nb >> 31) != ((cur.rw >> cb.rbit) & 1u);
                     if (__builtin_amdgcn_ballot_w64(active && hop[u])) {
-                        xv[u] = buf_load<T, K>(rx, hop[u] ? xo * RB : kOob);
+                        xv[u] = buf_load<T, K>(rr, hop[u] ? xo * RB : kOob);
                     } else {
 #pragma unroll
                         for (int c = 0; c < K; ++c) xv[u].v[c] = (T)0;
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < B::X; ++u) {
-                    hx::fma_acc<T, K>(acc, xamp[x0 + u], xv[u]);
-                    diag += hop[u] ? -xjz[x0 + u] : xjz[x0 + u];
+                for (int u = 0; u < XB; ++u) {
+                    if (q0 + u < nXF) {
+                        hx::fma_acc<T, K>(acc, xamp[q0 + u], xv[u]);
+                        diag += hop[u] ? -xjz[q0 + u] : xjz[q0 + u];
+                    }
                 }
+            }
+            for (int q = XF; q < P.nX; ++q) {  // more than XF bonds across the cut
+                const CrossBond cb = P.xb[q];
+                const uint32_t b0 = (lw >> cb.lbit) & 1u;
+                const uint64_t Rx = ro(P.xl)[(size_t)cb.si * P.count + gl];
+                int mx = mi + (b0 ? -1 : 1);
+                mx = mx < 0 ? 0 : (mx >= P.m_count ? P.m_count - 1 : mx);
+                const bool valid = Rx != ~0ull;
+                const auto rr = rsrc(x + (valid ? Rx : 0ull) * K, valid ? P.ncols[mx] * RB : 0u);
+                const uint32_t gr = P.rbase[mi] + (active ? r : 0u);
+                const uint32_t xo = P.xo[((size_t)(cb.sj >> 3) * P.rcount + gr) * 8 + (cb.sj & 7u)];
+                const bool h = b0 != ((cur.rw >> cb.rbit) & 1u);
+                hx::fma_acc<T, K>(acc, xamp[q], buf_load<T, K>(rr, h ? xo * RB : kOob));
+                diag += h ? -xjz[q] : xjz[q];
             }
             if (active) {
                 const V xs = xr[r];
@@ -413,6 +477,7 @@ __global__ __launch_bounds__(kThreads) void split_rows_lds_kernel(const RowParam
 #pragma unroll
                 for (int c = 0; c < K; ++c) __builtin_nontemporal_store(acc.v[c] + diag * xs.v[c], yr + c);
             }
+            cur = nxt;
         }
         Q.finish();  // its barrier also ends the reads of the staged run
     }
@@ -606,8 +671,11 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
                 }
                 auto kern = split_rows_lds_kernel<T, K>;
                 if (int r = ensure_lds(kern, lds)) return r;
-                const int per_cu = std::max<int>(1, std::min<int>(4, (int)((160 * 1024) / (lds + 4096))));
-                int wgs = device_cu_count(s->device) * per_cu;
+                int per_cu = 1;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds) != hipSuccess ||
+                    per_cu < 1)
+                    per_cu = 1;
+                int wgs = device_cu_count(s->device) * std::min(per_cu, 4);
                 wgs = std::min<int>(wgs, (int)(((uint64_t)count + 7) / 8 * 8));
                 wgs = (wgs + 7) / 8 * 8;
                 kern<<<wgs, kThreads, lds, stream>>>(P);
