@@ -9,9 +9,18 @@ state ranked (eq. index), x gathered, y written.
 
 Three forms are timed: the batched FP32 block of k=8 columns (the headline
 `value`), FP32 k=1, and the plain FP64 k=1 product.  `value` counts sector
-states per second per column (dim * k / time).  One JSON line is printed.
+states per second per column (dim * k / time).  One product is one call of
+dcs_hamiltonian_apply: on this sector the split product's launches (diagonal
+per side configuration, row pass, column pass).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+Besides the headline, `workloads` times the other measured cases of the
+method (skipped with --no-extras): the k=8 FP32 block on L=28 n=14, the fused
+adjoint on L=24 n=12 with per-bond couplings, all 101 sectors of the batched
+workload in one launch, and 200 Lanczos steps on the L=32 sector with FP32
+and with FP64 vectors (FP64 scalars; E0 = -12 exactly at this coupling ratio,
+the Majumdar-Ghosh point).  One JSON line is printed.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
 """
 from __future__ import annotations
 
@@ -30,7 +39,8 @@ METRIC = "H·x sector states/s + HBM GB/s, XXZ L=32 N=16; FP32 batched vs plain 
 PEAK_HBM_GBS = 8000.0
 L, N_UP, SPLIT = 32, 16, [8, 8, 8, 8]
 J1, J2, DELTA = 1.0, 0.5, 1.0
-KERNEL_SOURCES = ["hx_impl.h", "device_common.h", "dcs_internal.h", "hx_dispatch.hip"]
+KERNEL_SOURCES = ["split_impl.h", "split.cpp", "hx_impl.h", "device_common.h", "dcs_internal.h",
+                  "hx_dispatch.hip"]
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "hx_L32_counters.md")
 
 
@@ -70,6 +80,80 @@ def time_variant(fn, stream, steps: int, warmup: int):
     return start.elapsed_time(end) / 1e3  # seconds for `steps` launches
 
 
+def extra_workloads(dq, synth, torch, steps: int, warmup: int):
+    """The other measured cases (dict of results); every input is seeded and synthetic."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+
+    def timed(fn, n=steps, w=warmup):
+        return time_variant(fn, stream, n, w) / n
+
+    # k=8 FP32 block on L=28, n=14 (40,116,600 rows), XXZ J = Delta = 1
+    s = dq.Sector(28, 14, 2, [7, 7, 7, 7], device=0)
+    bonds, jxy, jz = synth.xxz_chain(28, 1.0, 1.0)
+    t = dq.Terms(bonds)
+    jd, zd = torch.tensor(jxy, device=dev), torch.tensor(jz, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(synth.SEED_X)
+    x = torch.randn((s.dim, 8), generator=g, device=dev, dtype=torch.float32)
+    y = torch.empty_like(x)
+    per = timed(lambda: dq.hamiltonian_apply(s, t, jd, zd, x, out=y))
+    out["hx_L28_f32k8"] = {"ms": per * 1e3, "states_per_s": s.dim * 8 / per,
+                           "achieved_GBs": s.dim * 8 * 2 * 4 / per / 1e9}
+    del x, y, s, t
+
+    # fused adjoint on L=24, n=12, per-bond J_b, Delta_b (24 bonds), FP64
+    s = dq.Sector(24, 12, 2, [8, 8, 8], device=0)
+    bonds = synth.chain_bonds(24, 1)
+    J, D = synth.random_couplings(len(bonds))
+    t = dq.Terms(bonds)
+    jd, zd = torch.tensor(J, device=dev), torch.tensor(J * D, device=dev)
+    x = torch.randn(s.dim, generator=g, device=dev, dtype=torch.float64)
+    gv = torch.randn(s.dim, generator=g, device=dev, dtype=torch.float64)
+    per_f = timed(lambda: dq.hamiltonian_apply(s, t, jd, zd, x))
+    per_a = timed(lambda: dq.hamiltonian_apply_adjoint(s, t, jd, zd, x, gv))
+    out["adjoint_L24_f64"] = {"forward_ms": per_f * 1e3, "adjoint_ms": per_a * 1e3,
+                              "adjoint_states_per_s": s.dim / per_a,
+                              "adjoint_compulsory_GBs": s.dim * 24 / per_a / 1e9}
+    del x, gv, s, t
+
+    # all sectors of L = 20..26 (spin 1/2, n = 0..L) and spin-1 L = 12..16 at Sz = 0, one launch
+    items, xs, total = [], [], 0
+    specs = [(2, ls, ns) for ls in (20, 22, 24, 26) for ns in range(ls + 1)]
+    specs += [(3, ls, ls) for ls in range(12, 17)]
+    for q_, ls, ns in specs:
+        b, j_, z_ = synth.xxz_chain(ls, 1.0, 1.0)
+        sec = dq.Sector(ls, ns, q_, device=0)
+        items.append((sec, dq.Terms(b), torch.tensor(j_, device=dev), torch.tensor(z_, device=dev)))
+        xs.append(torch.randn(sec.dim, generator=g, device=dev, dtype=torch.float32))
+        total += sec.dim
+    plan = dq.Plan(items)
+    ys = [torch.empty_like(v) for v in xs]
+    per = timed(lambda: plan.apply(xs, ys))
+    out["plan_101_sectors_f32"] = {"sectors": len(items), "rows": total, "ms": per * 1e3,
+                                   "states_per_s": total / per}
+    del plan, items, xs, ys
+
+    # 200 Lanczos steps on the L=32, n=16 J1-J2 sector (J2/J1 = 1/2: E0 = -3L/8 = -12)
+    s = dq.Sector(L, N_UP, 2, SPLIT, device=0)
+    bonds, jxy, jz = synth.j1j2_chain(L, J1, J2, DELTA)
+    t = dq.Terms(bonds)
+    jd, zd = torch.tensor(jxy, device=dev), torch.tensor(jz, device=dev)
+    for dt, name in ((torch.float32, "lanczos_L32_f32vec"), (torch.float64, "lanczos_L32_f64vec")):
+        v0 = torch.randn(s.dim, generator=g, device=dev, dtype=torch.float64).to(dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = dq.lanczos(s, t, jd, zd, v0, 200, reorth="local")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"steps": r["steps_done"], "seconds": el, "ms_per_step": el / r["steps_done"] * 1e3,
+                     "reorth": r["reorth"], "E0": r["eig"][0], "E0_error_vs_exact": r["eig"][0] + 12.0}
+        del v0
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(x_host, target_s: float = 15.0):
     """The FP64 C oracle (OpenMP over contiguous row blocks, as the paper's
     workers) timed on a contiguous block of rows from the middle of the sector."""
@@ -104,6 +188,7 @@ def main(argv=None) -> int:
     ap.add_argument("--variants", default="f32k8,f32k1,f64k1",
                     help="comma list; the first is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="time the headline product only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also time a plain device copy of the FP32 vector size (the reference "
                          "kernel for scaling the HBM byte counters)")
@@ -187,7 +272,9 @@ def main(argv=None) -> int:
                    "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": r["achieved_GBs"] / PEAK_HBM_GBS,
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     "kernel": "one H*X product (split_diag + split_rows + split_cols launches); "
+                               "algorithmic bytes = dim*k*(4+4): read X once, write Y once"},
         "variants": {k_: {"states_per_s": v_["states_per_s"], "ms": v_["seconds_per_step"] * 1e3,
                           "achieved_GBs": v_["achieved_GBs"]} for k_, v_ in results.items()},
     }
@@ -195,6 +282,8 @@ def main(argv=None) -> int:
         out["copy_calibration"] = copy_info
     if "f64k1" in results:
         out["speedup_vs_plain_f64_per_column"] = r["states_per_s"] / results["f64k1"]["states_per_s"]
+    if not args.no_extras:
+        out["workloads"] = extra_workloads(dq, synth, torch, args.steps, args.warmup)
     if x_host is not None:
         out["cpu_baseline"] = cpu_baseline(x_host)
     print(json.dumps(out), flush=True)
