@@ -142,6 +142,7 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
     jd, zd = torch.tensor(jxy, device=dev), torch.tensor(jz, device=dev)
     for dt, name in ((torch.float32, "lanczos_L32_f32vec"), (torch.float64, "lanczos_L32_f64vec")):
         v0 = torch.randn(s.dim, generator=g, device=dev, dtype=torch.float64).to(dt)
+        dq.hamiltonian_apply(s, t, jd, zd, v0)  # builds this terms object's tables before the clock
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = dq.lanczos(s, t, jd, zd, v0, 200, reorth="local")

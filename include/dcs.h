@@ -68,7 +68,7 @@ extern "C" {
 
 /* ---- Lanczos re-orthogonalisation modes --------------------------------- */
 #define DCS_REORTH_NONE 0  /* plain three-term recurrence */
-#define DCS_REORTH_LOCAL 1 /* one Gram-Schmidt pass against v_{j-1}, v_j */
+#define DCS_REORTH_LOCAL 1 /* exact projection out of span(v_{j-1}, v_j) each step */
 #define DCS_REORTH_FULL 2  /* two classical Gram-Schmidt passes against all v_0..v_j */
 
 #define DCS_INVALID_INDEX UINT64_MAX /* rank of an invalid state, unrank of an index >= D */
@@ -245,6 +245,15 @@ int dcs_lanczos_workspace_size(const dcs_sector *sector, int vec_dtype, int step
  *   w -= alpha_j v_j;  re-orthogonalise (reorth);  beta_j = |w|;  v_{j+1} = w/beta_j.
  * Dot products, norms and the re-orthogonalisation coefficients are
  * accumulated in FP64 on the device; vectors are stored in vec_dtype.
+ * DCS_REORTH_FULL stores the basis and re-orthogonalises against all of it
+ * (classical Gram-Schmidt twice).  DCS_REORTH_NONE and DCS_REORTH_LOCAL keep
+ * two unnormalised vectors u_j (v_j = u_j/|u_j|) and take two passes over the
+ * vectors per step after w = H u_j: the dots u_j.w, u_{j-1}.w, u_j.u_{j-1},
+ * then u_{j+1} = w/|u_j| - A u_{j-1} - B u_j with its norm.  NONE uses the
+ * three-term coefficients (A, B) = (beta_{j-1}/|u_{j-1}|, alpha_j/|u_j|); LOCAL
+ * solves the 2x2 Gram system so that H v_j is projected out of
+ * span(v_{j-1}, v_j) exactly for the stored operands (alpha_j is then the
+ * coefficient of v_j).
  * Stops early when beta_j <= 1e-12 max_i(|alpha_i|, beta_i) or after D steps.
  * The Ritz values (eigenvalues of the tridiagonal T, Sturm bisection in FP64 on
  * the device) are returned in increasing order.

@@ -27,6 +27,7 @@ struct LzState {
     int steps_done;    // number of alpha values recorded
     double scale;      // running max of |alpha_i|, beta_i
     double inv_beta;   // 1 / beta_j for the next normalisation
+    double sc, scp;    // two-vector form: 1/|u_j| and 1/|u_{j-1}| of the stored vectors
 };
 
 template <typename T>
@@ -197,6 +198,126 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *partial
     }
 }
 
+// ---- two-vector form (no stored basis) --------------------------------------
+//
+// The stored vectors are the unnormalised u_j (v_j = u_j / |u_j|, u_0 = v0), so
+// no pass rescales a vector.  One step after w = H u_j is two passes:
+//  * k_gram: u_j.w, u_{j-1}.w, u_j.u_{j-1};
+//  * k_lz_update: u_{j+1} = s w - A u_{j-1} - B u_j and |u_{j+1}|^2,
+// with the coefficients from k_lz_coef.  With re-orthogonalisation (LOCAL)
+// (A, B) project H v_j onto span(v_{j-1}, v_j) exactly (the 2x2 Gram system of
+// the stored operands); without it they are the three-term recurrence's
+// (beta_{j-1}, alpha_j).  The coefficients are recorded so the Ritz vector
+// pass repeats the same vectors bit for bit.
+
+// partials: slot 0 u_j.w, slot 1 u_{j-1}.w, slot 2 u_j.u_{j-1}
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_gram(const T *__restrict__ w, const T *__restrict__ uj,
+                                                      const T *__restrict__ ujm1, uint64_t n,
+                                                      double *partials, const LzState *st) {
+    if (st->done) return;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const double wi = ld(w, i), a = ld(uj, i);
+        s0 += a * wi;
+        if (ujm1) {
+            const double b = ld(ujm1, i);
+            s1 += b * wi;
+            s2 += a * b;
+        }
+    }
+    block_partial(s0, partials, 3, 0);
+    block_partial(s1, partials, 3, 1);
+    block_partial(s2, partials, 3, 2);
+}
+
+// Step coefficients from the reduced sums g[0..2]; rec[3j..3j+2] = (s, A, B).
+__global__ void k_lz_coef(const double *g, LzState *st, double *alpha, const double *beta,
+                          double *rec, int j, int local) {
+    if (st->done || threadIdx.x != 0) return;
+    const double s = st->sc, p = st->scp;
+    const double r1 = s * s * g[0];  // v_j . H v_j
+    const double r0 = p * s * g[1];  // v_{j-1} . H v_j
+    const double gm = p * s * g[2];  // v_{j-1} . v_j
+    double a = 0.0, b = r1;
+    if (j > 0) {
+        if (local) {
+            const double det = 1.0 - gm * gm;
+            a = (r0 - gm * r1) / det;
+            b = (r1 - gm * r0) / det;
+        } else {
+            a = beta[j - 1];
+            b = r1 - a * gm;
+        }
+    }
+    alpha[j] = b;
+    st->steps_done = j + 1;
+    st->scale = fmax(st->scale, fabs(b));
+    rec[3 * j] = s;
+    rec[3 * j + 1] = a * p;
+    rec[3 * j + 2] = b * s;
+}
+
+// out = s w - A ujm1 - B uj with (s, A, B) = c[0..2]; partial of |out|^2 when
+// partials is not NULL.  out may alias ujm1: each element is read before it is
+// written, by the same thread.
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_lz_update(const T *__restrict__ w, const T *__restrict__ uj,
+                                                           const T *ujm1, T *out, uint64_t n,
+                                                           const double *c, double *partials,
+                                                           const LzState *st) {
+    if (st && st->done) return;
+    const double sw = c[0], A = c[1], B = c[2];
+    double s = 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        double v = sw * ld(w, i) - B * ld(uj, i);
+        if (ujm1) v -= A * ld(ujm1, i);
+        const T vt = (T)v;
+        out[i] = vt;
+        s += (double)vt * (double)vt;
+    }
+    if (partials) block_partial(s, partials, 1, 0);
+}
+
+// beta_j = sqrt(sum of partials); breakdown test; the new vector's 1/|u|.
+__global__ __launch_bounds__(kReduceThreads) void k_lz_norm(const double *partials, int nblocks, LzState *st,
+                                                            double *beta, int j, int m) {
+    if (st->done) return;
+    __shared__ double red[kReduceThreads];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partials[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double b = sqrt(red[0]);
+        st->scale = fmax(st->scale, b);
+        if (j + 1 >= m || b <= kBreakdownTol * st->scale) {
+            st->done = 1;
+        } else {
+            beta[j] = b;
+            st->scp = st->sc;
+            st->sc = 1.0 / b;
+        }
+    }
+}
+
+// psi (+)= y_j * s_j * u (y = Ritz coefficients, s_j = rec[3j])
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_axpy_rec(T *__restrict__ psi, const T *__restrict__ u,
+                                                          uint64_t n, const double *y, const double *rec,
+                                                          int j, int first) {
+    const double c = y[j] * rec[3 * j];
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        psi[i] = (T)((first ? 0.0 : ld(psi, i)) + c * ld(u, i));
+}
+
 // ---- tridiagonal eigenvalues: Sturm bisection ------------------------------
 
 // Number of eigenvalues of T below x (LDL^T pivots of T - x I).
@@ -312,22 +433,6 @@ __global__ __launch_bounds__(kVecThreads) void k_axpy_s(T *__restrict__ psi, con
         psi[i] = (T)((first ? 0.0 : ld(psi, i)) + c * ld(v, i));
 }
 
-// out = (hv - alpha_j v_j - beta_{j-1} v_{j-1}) / beta_j  (recurrence replay).
-// out may alias vprev: every element is read before it is written, by the same thread.
-template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_replay(const T *__restrict__ hv, const T *vj,
-                                                        const T *vprev, T *out,
-                                                        const double *alpha, const double *beta,
-                                                        int j, uint64_t n) {
-    const double a = alpha[j], b = j > 0 ? beta[j - 1] : 0.0, ib = 1.0 / beta[j];
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        double wi = ld(hv, i) - a * ld(vj, i);
-        if (vprev) wi -= b * ld(vprev, i);
-        out[i] = (T)(wi * ib);
-    }
-}
-
 int vec_blocks(uint64_t n) {
     uint64_t b = (n + kVecThreads * 4 - 1) / (kVecThreads * 4);
     if (b > kMaxVecBlocks) b = kMaxVecBlocks;
@@ -337,7 +442,7 @@ int vec_blocks(uint64_t n) {
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 struct Layout {
-    size_t V, w, psi_tmp, partials, alpha, beta, coef, state, trid, total;
+    size_t V, w, psi_tmp, partials, alpha, beta, coef, rec, state, trid, total;
     int m, nvec;
 };
 
@@ -362,6 +467,8 @@ Layout layout(const dcs_sector *s, int dtype, int steps, int reorth, int want_ve
     p = align256(p + (size_t)L.m * sizeof(double));
     L.coef = p;
     p = align256(p + (size_t)(L.m + 4) * sizeof(double));
+    L.rec = p;  // two-vector form: (s, A, B) per step
+    p = align256(p + (size_t)(3 * L.m + 3) * sizeof(double));
     L.state = p;
     p = align256(p + sizeof(LzState));
     L.trid = p;  // eigenvalues, eigenvector and inverse-iteration work
@@ -392,36 +499,56 @@ int run_lanczos(const dcs_sector *s, const dcs_terms *t, const double *jxy, cons
 
     if (int r = check_hip(hipMemsetAsync(st, 0, sizeof(LzState), stream), "hipMemsetAsync"))
         return r;
-    // v_0 = v0 / |v0|
-    k_norm2<T><<<nb, kVecThreads, 0, stream>>>((const T *)v0, n, part);
-    k_reduce<<<1, kReduceThreads, 0, stream>>>(part, nb, 1, &st->inv_beta, 3, nullptr, alpha, beta,
-                                               0, L.m);
-    k_scale<T><<<nb, kVecThreads, 0, stream>>>((const T *)v0, vec(0), n, &st->inv_beta, nullptr);
-    if (int r = chk("Lanczos start")) return r;
-    for (int j = 0; j < L.m; ++j) {
-        if (int r = launch_hx(s, t, jxy, jz, h, dtype, 1, vec(j), w, stream)) return r;
-        k_sub_dot<T><<<nb, kVecThreads, 0, stream>>>(w, vec(j), j > 0 ? vec(j - 1) : nullptr,
-                                                     j > 0 ? beta + j - 1 : nullptr, n, part, st);
-        k_reduce<<<1, kReduceThreads, 0, stream>>>(part, nb, 1, nullptr, 1, st, alpha, beta, j, L.m);
-        if (reorth == DCS_REORTH_NONE) {
-            // w -= alpha_j v_j, |w|^2
-            k_sub_multi<T><<<nb, kVecThreads, 0, stream>>>(w, V, n, ring, j, 1, alpha + j, part, st);
-        } else {
-            const int i0 = reorth == DCS_REORTH_FULL ? 0 : std::max(0, j - 1);
-            const int cnt = j - i0 + 1;
-            const int passes = reorth == DCS_REORTH_FULL ? 2 : 1;
-            for (int p = 0; p < passes; ++p) {
-                k_multidot<T, 4><<<nb, kVecThreads, 0, stream>>>(
-                    w, V, n, ring, i0, cnt, p == 0 ? vec(j) : nullptr, alpha + j, part, st);
-                k_reduce<<<1, kReduceThreads, 0, stream>>>(part, nb, cnt, coef, 0, st, alpha, beta,
-                                                           j, L.m);
-                k_sub_multi<T><<<nb, kVecThreads, 0, stream>>>(w, V, n, ring, i0, cnt, coef, part, st);
+    double *rec = (double *)(ws + L.rec);
+    const T *u0 = (const T *)v0;
+    // two-vector form: u_0 = v0 as given, u_{j>0} in the ring
+    auto uvec = [&](int i) -> const T * { return i == 0 ? u0 : V + (uint64_t)(i & 1) * n; };
+    if (ring) {
+        k_norm2<T><<<nb, kVecThreads, 0, stream>>>(u0, n, part);
+        k_reduce<<<1, kReduceThreads, 0, stream>>>(part, nb, 1, &st->sc, 3, nullptr, alpha, beta, 0,
+                                                   L.m);
+        if (int r = chk("Lanczos start")) return r;
+        for (int j = 0; j < L.m; ++j) {
+            if (int r = launch_hx(s, t, jxy, jz, h, dtype, 1, uvec(j), w, stream)) return r;
+            const T *ujm1 = j > 0 ? uvec(j - 1) : nullptr;
+            k_gram<T><<<nb, kVecThreads, 0, stream>>>(w, uvec(j), ujm1, n, part, st);
+            k_reduce<<<1, kReduceThreads, 0, stream>>>(part, nb, 3, coef, 0, st, alpha, beta, j, L.m);
+            k_lz_coef<<<1, 64, 0, stream>>>(coef, st, alpha, beta, rec, j,
+                                            reorth == DCS_REORTH_LOCAL ? 1 : 0);
+            if (j + 1 < L.m) {
+                k_lz_update<T><<<nb, kVecThreads, 0, stream>>>(w, uvec(j), ujm1, V + (uint64_t)((j + 1) & 1) * n,
+                                                               n, rec + 3 * j, part, st);
+                k_lz_norm<<<1, kReduceThreads, 0, stream>>>(part, nb, st, beta, j, L.m);
             }
+            if (int r = chk("Lanczos step")) return r;
         }
-        k_reduce<<<1, kReduceThreads, 0, stream>>>(part, nb, 1, nullptr, 2, st, alpha, beta, j, L.m);
-        if (j + 1 < L.m)
-            k_scale<T><<<nb, kVecThreads, 0, stream>>>(w, vec(j + 1), n, &st->inv_beta, st);
-        if (int r = chk("Lanczos step")) return r;
+    } else {
+        // v_0 = v0 / |v0|
+        k_norm2<T><<<nb, kVecThreads, 0, stream>>>((const T *)v0, n, part);
+        k_reduce<<<1, kReduceThreads, 0, stream>>>(part, nb, 1, &st->inv_beta, 3, nullptr, alpha,
+                                                   beta, 0, L.m);
+        k_scale<T><<<nb, kVecThreads, 0, stream>>>((const T *)v0, vec(0), n, &st->inv_beta, nullptr);
+        if (int r = chk("Lanczos start")) return r;
+        for (int j = 0; j < L.m; ++j) {
+            if (int r = launch_hx(s, t, jxy, jz, h, dtype, 1, vec(j), w, stream)) return r;
+            k_sub_dot<T><<<nb, kVecThreads, 0, stream>>>(w, vec(j), j > 0 ? vec(j - 1) : nullptr,
+                                                         j > 0 ? beta + j - 1 : nullptr, n, part, st);
+            k_reduce<<<1, kReduceThreads, 0, stream>>>(part, nb, 1, nullptr, 1, st, alpha, beta, j,
+                                                       L.m);
+            // full re-orthogonalisation: classical Gram-Schmidt twice against v_0..v_j
+            for (int p = 0; p < 2; ++p) {
+                k_multidot<T, 4><<<nb, kVecThreads, 0, stream>>>(
+                    w, V, n, 0, 0, j + 1, p == 0 ? vec(j) : nullptr, alpha + j, part, st);
+                k_reduce<<<1, kReduceThreads, 0, stream>>>(part, nb, j + 1, coef, 0, st, alpha, beta,
+                                                           j, L.m);
+                k_sub_multi<T><<<nb, kVecThreads, 0, stream>>>(w, V, n, 0, 0, j + 1, coef, part, st);
+            }
+            k_reduce<<<1, kReduceThreads, 0, stream>>>(part, nb, 1, nullptr, 2, st, alpha, beta, j,
+                                                       L.m);
+            if (j + 1 < L.m)
+                k_scale<T><<<nb, kVecThreads, 0, stream>>>(w, vec(j + 1), n, &st->inv_beta, st);
+            if (int r = chk("Lanczos step")) return r;
+        }
     }
     LzState hs;
     if (int r = check_hip(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, stream),
@@ -464,19 +591,16 @@ int run_lanczos(const dcs_sector *s, const dcs_terms *t, const double *jxy, cons
         for (int j = 0; j < md; ++j)
             k_axpy_s<T><<<nb, kVecThreads, 0, stream>>>(psi, vec(j), n, svec, j, j == 0);
     } else {
-        // replay the three-term recurrence with the recorded alpha, beta
+        // repeat the recorded two-vector recurrence (same kernels, same vectors)
         T *R = (T *)(ws + L.psi_tmp);
-        auto rv = [&](int i) -> T * { return R + (uint64_t)(i & 1) * n; };
-        k_norm2<T><<<nb, kVecThreads, 0, stream>>>((const T *)v0, n, part);
-        k_reduce<<<1, kReduceThreads, 0, stream>>>(part, nb, 1, inv, 3, nullptr, alpha, beta, 0,
-                                                   L.m);
-        k_scale<T><<<nb, kVecThreads, 0, stream>>>((const T *)v0, rv(0), n, inv, nullptr);
-        k_axpy_s<T><<<nb, kVecThreads, 0, stream>>>(psi, rv(0), n, svec, 0, 1);
+        auto rv = [&](int i) -> const T * { return i == 0 ? u0 : R + (uint64_t)(i & 1) * n; };
+        k_axpy_rec<T><<<nb, kVecThreads, 0, stream>>>(psi, rv(0), n, svec, rec, 0, 1);
         for (int j = 0; j + 1 < md; ++j) {
             if (int r = launch_hx(s, t, jxy, jz, h, dtype, 1, rv(j), w, stream)) return r;
-            k_replay<T><<<nb, kVecThreads, 0, stream>>>(w, rv(j), j > 0 ? rv(j - 1) : nullptr,
-                                                        rv(j + 1), alpha, beta, j, n);
-            k_axpy_s<T><<<nb, kVecThreads, 0, stream>>>(psi, rv(j + 1), n, svec, j + 1, 0);
+            k_lz_update<T><<<nb, kVecThreads, 0, stream>>>(w, rv(j), j > 0 ? rv(j - 1) : nullptr,
+                                                           R + (uint64_t)((j + 1) & 1) * n, n,
+                                                           rec + 3 * j, nullptr, nullptr);
+            k_axpy_rec<T><<<nb, kVecThreads, 0, stream>>>(psi, rv(j + 1), n, svec, rec, j + 1, 0);
             if (int r = chk("Ritz vector replay")) return r;
         }
     }
