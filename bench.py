@@ -16,9 +16,10 @@ per side configuration, row pass, column pass).
 Besides the headline, `workloads` times the other measured cases of the
 method (skipped with --no-extras): the k=8 FP32 block on L=28 n=14, the fused
 adjoint on L=24 n=12 with per-bond couplings, all 101 sectors of the batched
-workload in one launch, and 200 Lanczos steps on the L=32 sector with FP32
+workload in one launch, 200 Lanczos steps on the L=32 sector with FP32
 and with FP64 vectors (FP64 scalars; E0 = -12 exactly at this coupling ratio,
-the Majumdar-Ghosh point).  One JSON line is printed.
+the Majumdar-Ghosh point), and on L=34, n=17 (2,333,606,220 states) the FP32
+product and 150 Lanczos steps.  One JSON line is printed.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
 """
@@ -152,6 +153,29 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
                      "reorth": r["reorth"], "E0": r["eig"][0], "E0_error_vs_exact": r["eig"][0] + 12.0}
         del v0
         torch.cuda.empty_cache()
+    del s, t
+
+    # L=34, n=17 (2,333,606,220 rows, 8/8/9/9) Heisenberg chain, FP32 vectors: H*x and 150 Lanczos steps
+    s = dq.Sector(34, 17, 2, [8, 8, 9, 9], device=0)
+    bonds, jxy, jz = synth.xxz_chain(34, 1.0, 1.0)
+    t = dq.Terms(bonds)
+    jd, zd = torch.tensor(jxy, device=dev), torch.tensor(jz, device=dev)
+    x = torch.randn(s.dim, generator=g, device=dev, dtype=torch.float32)
+    y = torch.empty_like(x)
+    per = timed(lambda: dq.hamiltonian_apply(s, t, jd, zd, x, out=y), n=max(3, steps // 4), w=1)
+    out["hx_L34_f32k1"] = {"ms": per * 1e3, "states_per_s": s.dim / per,
+                           "achieved_GBs": s.dim * 2 * 4 / per / 1e9}
+    del y
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = dq.lanczos(s, t, jd, zd, x, 150, reorth="local")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["lanczos_L34_f32vec"] = {"steps": r["steps_done"], "seconds": el,
+                                 "ms_per_step": el / r["steps_done"] * 1e3, "reorth": r["reorth"],
+                                 "E0": r["eig"][0]}
+    del x
+    torch.cuda.empty_cache()
     return out
 
 

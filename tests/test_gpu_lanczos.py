@@ -135,3 +135,19 @@ def test_headline_workload_L32_majumdar_ghosh(dt):
     err = abs(e0 + 12.0) / 12.0
     say("L32 MG", dt, res["steps_done"], e0, "rel err", err)
     assert err <= (1e-9 if dt == torch.float64 else 1e-5)
+
+
+def test_large_workload_L34():
+    """L=34, n=17 (2,333,606,220 states, 8/8/9/9) Heisenberg chain: 150 steps with FP32
+    vectors and FP64 scalars (local re-orthogonalisation); E0 against the Bethe ansatz."""
+    L, n = 34, 17
+    s = dq.Sector(L, n, 2, [8, 8, 9, 9])
+    bonds, jxy, jz = synth.xxz_chain(L, 1.0, 1.0)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(synth.SEED_V0)
+    v0 = torch.randn(s.dim, generator=g, device=DEV, dtype=torch.float32)
+    res = dq.lanczos(s, dq.Terms(bonds), dev_f64(jxy), dev_f64(jz), v0, 150, reorth="local")
+    e_b = bethe_e0(L)
+    say("L34", res["steps_done"], res["eig"][0], e_b)
+    assert res["steps_done"] == 150
+    assert abs(res["eig"][0] - e_b) <= 1e-6 * abs(e_b)
