@@ -132,6 +132,8 @@ struct SplitRows {
     uint64_t *d_runs = nullptr;      // run start of every left configuration
     double *d_diag = nullptr;        // per call: left | right configuration diagonals
     int nR = 0, nX = 0, nIs = 0, nJs = 0, nD = 0;
+    int nRloc = 0;                   // right-family bonds inside the last subsystem (listed first)
+    uint32_t margin = 0;             // rows of the largest run of equal P_K..P_{N-2} words
     uint64_t lnnz = 0;
     uint16_t r_bond[kMaxBonds];      // bond index of every right-family bond
     CrossBond x[kMaxCross];

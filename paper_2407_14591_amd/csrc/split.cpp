@@ -62,6 +62,21 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
     }
     for (int i = 0; i < sd.L; ++i)
         c.d[c.nD++] = DiagTerm{(uint8_t)(sd.site_sub[i] < K ? 0 : 1), packed_bit(i), 0, 1, (uint16_t)i, 0};
+    // bonds inside the last subsystem first: their targets share the row's words of
+    // P_K..P_{N-2}, i.e. lie within `margin` rows of it
+    std::stable_partition(right.begin(), right.end(),
+                          [&](const SideBond &fb) { return fb.a == N - 1 && fb.b == N - 1; });
+    for (const SideBond &fb : right) c.nRloc += (fb.a == N - 1 && fb.b == N - 1) ? 1 : 0;
+    {
+        const int l = sd.wbits[N - 1];  // sites of the last subsystem (Q = 2)
+        uint64_t best = 1;
+        for (int m = 0; m <= l; ++m) {
+            uint64_t b = 1;
+            for (int i = 0; i < m; ++i) b = b * (uint64_t)(l - i) / (uint64_t)(i + 1);
+            best = std::max(best, b);
+        }
+        c.margin = (uint32_t)best;
+    }
     c.nR = (int)right.size();
     c.nIs = (int)lsites.size();
     c.nJs = (int)rsites.size();

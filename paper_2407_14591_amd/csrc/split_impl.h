@@ -74,12 +74,24 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-template <typename TB>
-__device__ __forceinline__ int block_of_tile(const TB *tbase, int m_count, uint64_t t) {
-    int mi = 0;
-    while (mi + 1 < m_count && tbase[mi + 1] <= t) ++mi;
-    return mi;
-}
+// Block (left particle number) of a tile.  The tiles one workgroup takes only
+// increase (its XCD's queue counter), so the search resumes where it stopped and
+// the block bounds stay in registers.
+struct BlockCursor {
+    const uint64_t *tbase;
+    int m_count, mi;
+    uint64_t hi;  // tbase[mi + 1]
+    __device__ __forceinline__ BlockCursor(const uint64_t *tb, int mc) : tbase(tb), m_count(mc), mi(0) {
+        hi = tbase[1];
+    }
+    __device__ __forceinline__ int operator()(uint64_t t) {
+        while (t >= hi && mi + 1 < m_count) {
+            ++mi;
+            hi = tbase[mi + 1];
+        }
+        return mi;
+    }
+};
 
 // ------------------------------------------------------------------ diagonal
 struct DiagParams {
@@ -163,6 +175,8 @@ struct RowParams {
     uint64_t xbase[9];  // tile range of every XCD
     uint32_t count, rcount;
     int m_count, nR, nX;
+    int nRloc;        // right-family bonds [0, nRloc) read from the staged rows of the tile
+    uint32_t margin;  // staged rows on either side of the tile
     uint32_t lbase[kMaxLeftM], rbase[kMaxLeftM], ncols[kMaxLeftM], nsub[kMaxLeftM];
     uint64_t tbase[kMaxLeftM + 1];
     uint16_t rbond[kMaxBonds];
@@ -179,10 +193,41 @@ struct RowBatch {
     static constexpr int X = RB <= 16 ? 8 : (RB == 32 ? 4 : 2);                    // across the cut
 };
 
+// Rows of x staged in LDS per tile: the tile's rows and `margin` rows on either
+// side (bonds inside the last subsystem never leave that window), then one zero
+// row.  Dwords, or 16-byte pieces when rows are whole 16-byte units.
+template <typename T, int K>
+__device__ __forceinline__ void stage_rows(char *lds, const T *x, uint64_t R, uint32_t s0, uint32_t s1,
+                                           uint32_t zero_row) {
+    constexpr uint32_t RB = K * sizeof(T);
+    const auto rs = rsrc(x + (R + s0) * K, (s1 - s0) * RB);
+    const uint32_t bytes = (s1 - s0) * RB;
+    if constexpr (RB % 16 == 0) {
+        uint4 *d = reinterpret_cast<uint4 *>(lds);
+        for (uint32_t i = threadIdx.x; i < bytes / 16; i += kThreads) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, i * 16u, 0, 0);
+            __builtin_memcpy(&d[i], &v, 16);
+        }
+    } else {
+        uint32_t *d = reinterpret_cast<uint32_t *>(lds);
+        for (uint32_t i = threadIdx.x; i < bytes / 4; i += kThreads)
+            d[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, i * 4u, 0, 0);
+    }
+    if (threadIdx.x < RB / 4) reinterpret_cast<uint32_t *>(lds + (size_t)zero_row * RB)[threadIdx.x] = 0u;
+}
+
+template <typename T, int K>
+__device__ __forceinline__ Acc<T, K> lds_row(const char *lds, uint32_t row) {
+    Acc<T, K> v;
+    __builtin_memcpy(&v, lds + (size_t)row * (K * sizeof(T)), K * sizeof(T));
+    return v;
+}
+
 template <typename T, int K>
 __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P) {
     using B = RowBatch<T, K>;
     constexpr uint32_t RB = B::RB;
+    extern __shared__ __align__(16) char rows_lds[];
     __shared__ T ramp[kMaxBonds + 32];
     __shared__ T xamp[kMaxCross + 8], xjz[kMaxCross + 8];
     __shared__ uint32_t slots[2];
@@ -196,9 +241,10 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P)
     T *__restrict__ y = reinterpret_cast<T *>(P.y);
     const int nRq = (P.nR + 7) >> 3;
     AheadQueue Q(P.counters, P.xbase, slots);  // its barrier also publishes the LDS above
+    BlockCursor blk(P.tbase, P.m_count);
     uint64_t t;
     while (Q.get(t)) {
-        const int mi = block_of_tile(P.tbase, P.m_count, t);
+        const int mi = blk(t);
         const uint32_t local = (uint32_t)(t - P.tbase[mi]);
         const uint32_t lq = local / P.nsub[mi], ch = local - lq * P.nsub[mi];
         const uint32_t gl = P.lbase[mi] + lq;
@@ -212,42 +258,33 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P)
         const auto rs = rsrc(x + R * K, ncols * RB);
         const uint32_t rw = P.rwords[gr];
         const double dr = P.dr[gr];
-        const Acc<T, K> xs = buf_load<T, K>(rs, r * RB);  // past the run for inactive lanes: zero
+        // table rows of this tile's rows, loaded before anything waits
+        uint4 tv0[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            tv0[i] = i < nRq ? *reinterpret_cast<const uint4 *>(P.vo + ((size_t)i * P.rcount + gr) * 8)
+                             : make_uint4(~0u, ~0u, ~0u, ~0u);
+        const uint4 xw0 = P.nX > 0 ? *reinterpret_cast<const uint4 *>(P.xo + (size_t)gr * 8)
+                                   : make_uint4(~0u, ~0u, ~0u, ~0u);
+        // the tile's window of the run in LDS (when bonds inside the last subsystem exist)
+        const bool staged = P.nRloc > 0;
+        const uint32_t r0 = ch * kThreads;
+        const uint32_t s0 = r0 > P.margin ? r0 - P.margin : 0u;
+        const uint32_t s1 = min(ncols, r0 + kThreads + P.margin);
+        const uint32_t zero_row = kThreads + 2 * P.margin;
+        if (staged) {
+            stage_rows<T, K>(rows_lds, x, R, s0, s1, zero_row);
+            __syncthreads();
+        }
+        const Acc<T, K> xs = staged ? lds_row<T, K>(rows_lds, active ? r - s0 : zero_row)
+                                    : buf_load<T, K>(rs, r * RB);  // past the run: zero
         Acc<T, K> acc;
 #pragma unroll
         for (int c = 0; c < K; ++c) acc.v[c] = (T)0;
-        // right family: B::R targets per batch, 8 per 16-byte table row
-        for (int q0 = 0; q0 < nRq * 8; q0 += B::R) {
-            uint32_t ov[B::R];
-#pragma unroll
-            for (int i = 0; i < B::R / 8; ++i) {
-                const int qr = (q0 >> 3) + i;
-                const uint4 tv = qr < nRq ? *reinterpret_cast<const uint4 *>(P.vo + ((size_t)qr * P.rcount + gr) * 8)
-                                          : make_uint4(~0u, ~0u, ~0u, ~0u);
-                const uint32_t wv[4] = {tv.x, tv.y, tv.z, tv.w};
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    ov[i * 8 + u] = ((u & 1) ? (wv[u >> 1] >> 16) : (wv[u >> 1] & 0xFFFFu)) * RB;
-            }
-            // a bond with no hop on any lane of the wave (frequent for bonds inside
-            // the first right subsystem, whose hops are shared by runs of rows) is skipped
-            Acc<T, K> xv[B::R];
-#pragma unroll
-            for (int u = 0; u < B::R; ++u) {
-                if (__builtin_amdgcn_ballot_w64(active && ov[u] < 0xFFFFu * RB)) {
-                    xv[u] = buf_load<T, K>(rs, ov[u]);
-                } else {
-#pragma unroll
-                    for (int c = 0; c < K; ++c) xv[u].v[c] = (T)0;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < B::R; ++u) hx::fma_acc<T, K>(acc, ramp[q0 + u], xv[u]);
-        }
         // bonds across the cut: B::X per batch
         T diag = (T)(dl + dr);
-        uint4 xw = make_uint4(~0u, ~0u, ~0u, ~0u);
-        int xw_group = -1;
+        uint4 xw = xw0;
+        int xw_group = 0;
         for (int x0 = 0; x0 < P.nX; x0 += B::X) {
             Acc<T, K> xv[B::X];
             bool hop[B::X];
@@ -281,6 +318,46 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P)
                 hx::fma_acc<T, K>(acc, xamp[x0 + u], xv[u]);
                 diag += hop[u] ? -xjz[x0 + u] : xjz[x0 + u];
             }
+        }
+        // right family: B::R targets per batch, 8 per 16-byte table row; bonds
+        // [0, nRloc) from the staged window, the others from the run in HBM.  The
+        // first four table rows (32 bonds) were loaded at the start of the tile.
+        for (int q0 = 0; q0 < nRq * 8; q0 += B::R) {
+            uint32_t ov[B::R];
+#pragma unroll
+            for (int i = 0; i < B::R / 8; ++i) {
+                const int qr = (q0 >> 3) + i;
+                uint4 tv = make_uint4(~0u, ~0u, ~0u, ~0u);
+                if (qr < 4) {
+#pragma unroll
+                    for (int z = 0; z < 4; ++z)
+                        if (z == qr) tv = tv0[z];
+                } else if (qr < nRq) {
+                    tv = *reinterpret_cast<const uint4 *>(P.vo + ((size_t)qr * P.rcount + gr) * 8);
+                }
+                const uint32_t wv[4] = {tv.x, tv.y, tv.z, tv.w};
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    ov[i * 8 + u] = ((u & 1) ? (wv[u >> 1] >> 16) : (wv[u >> 1] & 0xFFFFu)) * RB;
+            }
+            // a bond with no hop on any lane of the wave (frequent for bonds inside
+            // the first right subsystem, whose hops are shared by runs of rows) is skipped
+            Acc<T, K> xv[B::R];
+#pragma unroll
+            for (int u = 0; u < B::R; ++u) {
+                if (q0 + u < P.nRloc) {
+                    const uint32_t e = ov[u] / RB;
+                    const uint32_t wr = (e < s0 || e >= s1) ? zero_row : e - s0;  // 0xFFFF: no hop
+                    xv[u] = lds_row<T, K>(rows_lds, wr);
+                } else if (__builtin_amdgcn_ballot_w64(active && ov[u] < 0xFFFFu * RB)) {
+                    xv[u] = buf_load<T, K>(rs, ov[u]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < K; ++c) xv[u].v[c] = (T)0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < B::R; ++u) hx::fma_acc<T, K>(acc, ramp[q0 + u], xv[u]);
         }
         if (active) {
             T *yr = y + (R + r) * K;
@@ -347,9 +424,10 @@ __global__ __launch_bounds__(kThreads) void split_rows_lds_kernel(const RowParam
     T *__restrict__ y = reinterpret_cast<T *>(P.y);
     const int nRq = (P.nR + 7) >> 3;
     AheadQueue Q(P.counters, P.xbase, slots);
+    BlockCursor blk(P.tbase, P.m_count);
     uint64_t t;
     while (Q.get(t)) {
-        const int mi = block_of_tile(P.tbase, P.m_count, t);
+        const int mi = blk(t);
         const uint32_t gl = (uint32_t)t;  // tiles enumerate the left configurations
         const uint32_t ncols = P.ncols[mi];
         const uint64_t R = ro(P.runs)[gl];
@@ -516,9 +594,10 @@ __global__ __launch_bounds__(kThreads) void split_cols_kernel(const ColParams P)
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
     AheadQueue Q(P.counters, P.xbase, slots);
+    BlockCursor blk(P.tbase, P.m_count);
     uint64_t t;
     while (Q.get(t)) {
-        const int mi = block_of_tile(P.tbase, P.m_count, t);
+        const int mi = blk(t);
         const uint32_t local = (uint32_t)(t - P.tbase[mi]);
         const uint32_t c = local / P.ngrp[mi], lg = local - c * P.ngrp[mi];
         const uint32_t li = lg * kColWaves + wave;
@@ -684,7 +763,12 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
             }
         }
         if (!staged) {
-            split_rows_kernel<T, K><<<split_grid(s, tiles), kThreads, 0, stream>>>(P);
+            P.nRloc = c.nRloc;
+            P.margin = c.margin;
+            const size_t wl = P.nRloc > 0 ? (size_t)(kThreads + 2 * c.margin + 1) * RowBatch<T, K>::RB : 0;
+            auto kern = split_rows_kernel<T, K>;
+            if (int r = ensure_lds(kern, wl)) return r;
+            kern<<<split_grid(s, tiles), kThreads, wl, stream>>>(P);
             if (int r = check_hip(hipGetLastError(), "split rows launch")) return r;
         }
     }
