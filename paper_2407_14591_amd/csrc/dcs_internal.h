@@ -101,6 +101,7 @@ constexpr int kMaxLeftM = 40;
 constexpr int kMaxSplitCache = 4;
 constexpr int kMaxCross = 96;       // bonds across the cut
 constexpr int kMaxCrossSites = 32;  // distinct sites of those bonds on either side
+constexpr uint32_t kMaxClusterRuns = 70;  // left configurations per cluster of the column pass
 
 struct CrossBond {
     uint8_t si, sj;      // slot of the left / right site in the flip tables
@@ -121,7 +122,8 @@ struct DiagTerm {
 struct SplitRows {
     uint64_t terms_id = 0;           // 0: empty slot
     uint32_t *d_lptr = nullptr;      // left family: entry range of every left configuration
-    uint64_t *d_lent = nullptr;      // target run start (low 48 bits) | bond << 48
+    uint64_t *d_lent = nullptr;      // target run start (low 48 bits) | bond << 48, or, for a target
+                                     // in the own cluster, 1 << 63 | bond << 48 | index in the cluster
     uint16_t *d_vo = nullptr;        // right family: [bond group][right configuration][8] target
                                      // offset in the run, 0xFFFF where the bond does not hop
     uint64_t *d_xl = nullptr;        // crossing: [left site slot][left configuration] run start of
@@ -130,6 +132,14 @@ struct SplitRows {
                                      // offset of the configuration with that site flipped in its
                                      // block, 0xFFFF if none
     uint64_t *d_runs = nullptr;      // run start of every left configuration
+    // clusters of the left family: consecutive left configurations (one block)
+    // with equal words of P_0..P_{K-2}, at most kMaxClusterRuns each; bonds
+    // inside P_{K-1} map a cluster onto itself
+    uint32_t *d_clstart = nullptr;   // first left configuration of every cluster
+    uint32_t *d_clsize = nullptr;    // its number of left configurations
+    uint32_t clbase[kMaxLeftM];      // first cluster of block m - m_lo
+    uint32_t nclust[kMaxLeftM];
+    uint32_t max_cluster = 0;
     double *d_diag = nullptr;        // per call: left | right configuration diagonals
     int nR = 0, nX = 0, nIs = 0, nJs = 0, nD = 0;
     int nRloc = 0;                   // right-family bonds inside the last subsystem (listed first)

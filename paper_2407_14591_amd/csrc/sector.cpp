@@ -329,6 +329,8 @@ void free_rows(SplitRows &c) {
     hipFree(c.d_xl);
     hipFree(c.d_xo);
     hipFree(c.d_runs);
+    hipFree(c.d_clstart);
+    hipFree(c.d_clsize);
     hipFree(c.d_diag);
     c = SplitRows();
 }

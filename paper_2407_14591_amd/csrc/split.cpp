@@ -111,6 +111,29 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
         return (it != run_block.end() && it->first == run) ? it->second : -1;
     };
 
+    // clusters: consecutive left configurations of one block with equal words of
+    // P_0..P_{K-2} (the bonds inside P_{K-1} keep them), split at kMaxClusterRuns
+    std::vector<uint32_t> clstart, clsize, cl_of(li.count);
+    {
+        const uint32_t keep = K >= 2 ? ((1u << li.word_shift[K - 1]) - 1u) : 0u;  // bits of P_0..P_{K-2}
+        for (int mi = 0; mi < li.m_count; ++mi) {
+            c.clbase[mi] = (uint32_t)clstart.size();
+            for (uint32_t q = 0; q < li.nleft[mi]; ++q) {
+                const uint32_t g = li.lbase[mi] + q;
+                const bool fresh = clstart.empty() || q == 0 ||
+                                   ((li.h_words[g] ^ li.h_words[clstart.back()]) & keep) != 0 ||
+                                   clsize.back() == kMaxClusterRuns;
+                if (fresh) {
+                    clstart.push_back(g);
+                    clsize.push_back(0);
+                }
+                cl_of[g] = (uint32_t)clstart.size() - 1;
+                ++clsize.back();
+            }
+            c.nclust[mi] = (uint32_t)clstart.size() - c.clbase[mi];
+        }
+        for (uint32_t z : clsize) c.max_cluster = std::max(c.max_cluster, z);
+    }
     // left family rows and crossing left flips
     std::vector<uint32_t> lptr(li.count + 1);
     std::vector<uint64_t> lent;
@@ -131,7 +154,16 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
                 if (run >= (1ull << 48) || block_of_run(run) != mi)
                     return set_error(DCS_EHIP, "internal: left target is not a run of the same block"),
                            nullptr;
-                lent.push_back(run | ((uint64_t)fb.bond << 48));
+                // the target's left configuration (runs of one block are in configuration order)
+                const auto it = std::lower_bound(li.h_runs.begin() + li.lbase[mi],
+                                                 li.h_runs.begin() + li.lbase[mi] + li.nleft[mi], run);
+                const uint32_t g2 = (uint32_t)(it - li.h_runs.begin());
+                if (it == li.h_runs.begin() + li.lbase[mi] + li.nleft[mi] || *it != run)
+                    return set_error(DCS_EHIP, "internal: left target configuration"), nullptr;
+                if (cl_of[g2] == cl_of[g])
+                    lent.push_back((1ull << 63) | ((uint64_t)fb.bond << 48) | (g2 - clstart[cl_of[g]]));
+                else
+                    lent.push_back(run | ((uint64_t)fb.bond << 48));
             }
             for (int si = 0; si < c.nIs; ++si) {
                 const int site = lsites[si], k = sd.site_sub[site];
@@ -201,6 +233,8 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
               up((void **)&c.d_xl, xl.data(), xl.size() * sizeof(uint64_t)) &&
               up((void **)&c.d_xo, xo.data(), xo.size() * sizeof(uint16_t)) &&
               up((void **)&c.d_runs, li.h_runs.data(), li.h_runs.size() * sizeof(uint64_t)) &&
+              up((void **)&c.d_clstart, clstart.data(), clstart.size() * sizeof(uint32_t)) &&
+              up((void **)&c.d_clsize, clsize.data(), clsize.size() * sizeof(uint32_t)) &&
               check_hip(hipMalloc(&c.d_diag, (li.count + li.rcount) * sizeof(double)),
                         "hipMalloc split diagonal") == DCS_OK;
     if (!ok) {

@@ -568,26 +568,33 @@ struct ColParams {
     const double *jxy;
     const uint32_t *lptr;
     const uint64_t *lent, *runs;
+    const uint32_t *clstart, *clsize;
     uint32_t *counters;
     uint64_t xbase[9];
     int m_count, nbonds;
-    uint32_t lbase[kMaxLeftM], nleft[kMaxLeftM], ncols[kMaxLeftM], ngrp[kMaxLeftM];
+    uint32_t ncols[kMaxLeftM], clbase[kMaxLeftM], nclust[kMaxLeftM];
     uint64_t tbase[kMaxLeftM + 1];
 };
 static_assert(sizeof(ColParams) <= 4096, "kernel arguments are limited to 4 KiB");
 
-constexpr int kColWaves = kThreads / 64;  // left configurations per tile (one per wave)
+constexpr int kColThreads = 1024;  // 16 waves share one staged cluster
+constexpr int kColWaves = kColThreads / 64;
 constexpr int kColBatch = 8;              // gathers in flight per wave
 constexpr uint32_t kColLaneBytes = 16;    // bytes of x per lane and gather
 constexpr uint32_t kColWaveBytes = 64 * kColLaneBytes;
 
+// One tile = one cluster of left configurations (see SplitRows) at one 1 KiB
+// chunk of their runs.  The chunk of every run of the cluster is first copied
+// to LDS; the targets inside the cluster (bonds inside P_{K-1}) are then read
+// there, the others from HBM.  Wave w takes the cluster's runs w, w+8, ...
 template <typename T, int K>
-__global__ __launch_bounds__(kThreads) void split_cols_kernel(const ColParams P) {
+__global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams P) {
     constexpr int V = kColLaneBytes / sizeof(T);
     typedef T vec_t __attribute__((ext_vector_type(V)));
+    extern __shared__ __align__(16) char cl_lds[];  // [cluster run][kColWaveBytes]
     __shared__ T amp[kMaxBonds];
     __shared__ uint32_t slots[2];
-    for (int q = threadIdx.x; q < kMaxBonds; q += kThreads)
+    for (int q = threadIdx.x; q < kMaxBonds; q += kColThreads)
         amp[q] = q < P.nbonds ? (T)(0.5 * P.jxy[q]) : (T)0;
     const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
     T *__restrict__ y = reinterpret_cast<T *>(P.y);
@@ -599,17 +606,34 @@ __global__ __launch_bounds__(kThreads) void split_cols_kernel(const ColParams P)
     while (Q.get(t)) {
         const int mi = blk(t);
         const uint32_t local = (uint32_t)(t - P.tbase[mi]);
-        const uint32_t c = local / P.ngrp[mi], lg = local - c * P.ngrp[mi];
-        const uint32_t li = lg * kColWaves + wave;
-        if (li < P.nleft[mi]) {  // uniform per wave
-            const uint32_t gl = P.lbase[mi] + li;
-            const uint32_t nrec = P.ncols[mi] * (uint32_t)(K * sizeof(T));
-            const uint32_t boff = c * kColWaveBytes + lane * kColLaneBytes;  // byte of the run
+        const uint32_t c = local / P.nclust[mi], cl = P.clbase[mi] + (local - c * P.nclust[mi]);
+        const uint32_t g0 = ro(P.clstart)[cl], size = ro(P.clsize)[cl];
+        const uint32_t nrec = P.ncols[mi] * (uint32_t)(K * sizeof(T));
+        const uint32_t boff = c * kColWaveBytes + lane * kColLaneBytes;  // byte of the run
+        // the last chunk of a run may end inside a lane's 16 bytes: there every
+        // value is loaded on its own, so no load straddles the run end
+        const bool tail = (c + 1) * kColWaveBytes > nrec;  // uniform
+        auto load16 = [&](__amdgpu_buffer_rsrc_t r) -> vec_t {
+            vec_t v;
+            if (!tail) {
+                const auto raw = __builtin_amdgcn_raw_buffer_load_b128(r, boff, 0, 0);
+                __builtin_memcpy(&v, &raw, 16);
+            } else {
+#pragma unroll
+                for (int i = 0; i < V; ++i) v[i] = buf_load<T, 1>(r, boff + i * (uint32_t)sizeof(T)).v[0];
+            }
+            return v;
+        };
+        // stage the chunk of every run of the cluster (zeros past a run's end)
+        for (uint32_t i = wave; i < size; i += kColWaves) {
+            const vec_t v = load16(rsrc(x + ro(P.runs)[g0 + i] * K, nrec));
+            *reinterpret_cast<vec_t *>(cl_lds + (size_t)i * kColWaveBytes + lane * kColLaneBytes) = v;
+        }
+        __syncthreads();
+        for (uint32_t i = wave; i < size; i += kColWaves) {
+            const uint32_t gl = g0 + i;
             vec_t acc = (vec_t)(T)0;
             const uint32_t q1 = ro(P.lptr)[gl + 1];
-            // the last chunk of a run may end inside a lane's 16 bytes: there
-            // every value is loaded on its own, so no load straddles the run end
-            const bool tail = (c + 1) * kColWaveBytes > nrec;  // uniform per wave
             for (uint32_t q0 = ro(P.lptr)[gl]; q0 < q1; q0 += kColBatch) {
                 vec_t v[kColBatch];
                 T a[kColBatch];
@@ -617,16 +641,14 @@ __global__ __launch_bounds__(kThreads) void split_cols_kernel(const ColParams P)
                 for (int u = 0; u < kColBatch; ++u) {
                     const bool ok = q0 + u < q1;
                     const uint64_t ent = ro(P.lent)[ok ? q0 + u : q0];
-                    const auto r = rsrc(x + (ent & 0xFFFFFFFFFFFFull) * K, ok ? nrec : 0u);
-                    if (!tail) {
-                        const auto raw = __builtin_amdgcn_raw_buffer_load_b128(r, boff, 0, 0);
-                        __builtin_memcpy(&v[u], &raw, 16);
+                    if (ok && (ent >> 63)) {  // uniform: a run of this cluster
+                        const uint32_t j = (uint32_t)(ent & 0xFFFFu);
+                        v[u] = *reinterpret_cast<const vec_t *>(cl_lds + (size_t)(j < size ? j : 0) * kColWaveBytes +
+                                                                lane * kColLaneBytes);
                     } else {
-#pragma unroll
-                        for (int i = 0; i < V; ++i)
-                            v[u][i] = buf_load<T, 1>(r, boff + i * (uint32_t)sizeof(T)).v[0];
+                        v[u] = load16(rsrc(x + (ent & 0xFFFFFFFFFFFFull) * K, ok ? nrec : 0u));
                     }
-                    a[u] = amp[ent >> 48];
+                    a[u] = ok ? amp[(ent >> 48) & 0xFFu] : (T)0;
                 }
 #pragma unroll
                 for (int u = 0; u < kColBatch; ++u) acc += a[u] * v[u];
@@ -637,13 +659,13 @@ __global__ __launch_bounds__(kThreads) void split_cols_kernel(const ColParams P)
                     vec_t *yp = reinterpret_cast<vec_t *>(ys);
                     __builtin_nontemporal_store(__builtin_nontemporal_load(yp) + acc, yp);
                 } else {
-                    for (int i = 0; i < V; ++i)
-                        if (boff + i * (uint32_t)sizeof(T) < nrec)
-                            __builtin_nontemporal_store(__builtin_nontemporal_load(ys + i) + acc[i], ys + i);
+                    for (int e = 0; e < V; ++e)
+                        if (boff + e * (uint32_t)sizeof(T) < nrec)
+                            __builtin_nontemporal_store(__builtin_nontemporal_load(ys + e) + acc[e], ys + e);
                 }
             }
         }
-        Q.finish();
+        Q.finish();  // its barrier also ends the reads of the staged chunks
     }
 }
 
@@ -772,7 +794,7 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
             if (int r = check_hip(hipGetLastError(), "split rows launch")) return r;
         }
     }
-    // 3. left family: waves of 1 KiB of one run, tiles of 8 runs, column-chunk major
+    // 3. left family: tiles of one cluster of runs at one 1 KiB chunk, chunk major
     {
         ColParams P;
         memset(&P, 0, sizeof(P));
@@ -782,22 +804,26 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
         P.lptr = c.d_lptr;
         P.lent = c.d_lent;
         P.runs = c.d_runs;
+        P.clstart = c.d_clstart;
+        P.clsize = c.d_clsize;
         P.counters = s->dev.counters + 8;
         P.m_count = li.m_count;
         P.nbonds = nbonds;
         uint64_t tiles = 0;
         for (int m = 0; m < li.m_count; ++m) {
             const uint64_t nchunk = (li.ncols[m] * K * sizeof(T) + kColWaveBytes - 1) / kColWaveBytes;
-            P.lbase[m] = li.lbase[m];
-            P.nleft[m] = li.nleft[m];
             P.ncols[m] = (uint32_t)li.ncols[m];
-            P.ngrp[m] = (li.nleft[m] + kColWaves - 1) / kColWaves;
+            P.clbase[m] = c.clbase[m];
+            P.nclust[m] = c.nclust[m];
             P.tbase[m] = tiles;
-            tiles += nchunk * P.ngrp[m];
+            tiles += nchunk * c.nclust[m];
         }
         P.tbase[li.m_count] = tiles;
         xcd_ranges(tiles, P.xbase);
-        split_cols_kernel<T, K><<<split_grid(s, tiles), kThreads, 0, stream>>>(P);
+        const size_t lds = (size_t)std::max<uint32_t>(c.max_cluster, 1) * kColWaveBytes;
+        auto kern = split_cols_kernel<T, K>;
+        if (int r = ensure_lds(kern, lds)) return r;
+        kern<<<split_grid(s, tiles), kColThreads, lds, stream>>>(P);
         return check_hip(hipGetLastError(), "split columns launch");
     }
 }
