@@ -14,7 +14,8 @@ dcs_hamiltonian_apply: on this sector the split product's launches (diagonal
 per side configuration, row pass, column pass).
 
 Besides the headline, `workloads` times the other measured cases of the
-method (skipped with --no-extras): the k=8 FP32 block on L=28 n=14, the fused
+method (skipped with --no-extras): rank and unrank of 2^24 random states of the
+L=32 sector, the k=8 FP32 block on L=28 n=14, the fused
 adjoint on L=24 n=12 with per-bond couplings, all 101 sectors of the batched
 workload in one launch, 200 Lanczos steps on the L=32 sector with FP32
 and with FP64 vectors (FP64 scalars; E0 = -12 exactly at this coupling ratio,
@@ -90,13 +91,29 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
     def timed(fn, n=steps, w=warmup):
         return time_variant(fn, stream, n, w) / n
 
+    # rank and unrank of 2^24 uniformly random states of the L=32, n=16 sector (the paper's
+    # random trial states: a uniform n-subset of the sites per state, drawn on the device)
+    s = dq.Sector(L, N_UP, 2, SPLIT, device=0)
+    cnt = 1 << 24
+    g = torch.Generator(device=dev)
+    g.manual_seed(synth.SEED_X)
+    occ = torch.rand((cnt, L), generator=g, device=dev).argsort(dim=1)[:, :N_UP]
+    states = (torch.ones(cnt, N_UP, dtype=torch.int64, device=dev) << (L - 1 - occ)).sum(dim=1)
+    del occ
+    idx = torch.empty_like(states)
+    back = torch.empty_like(states)
+    per_r = timed(lambda: s.rank(states, out=idx))
+    per_u = timed(lambda: s.unrank(idx, out=back))
+    assert torch.equal(back, states)
+    out["rank_unrank_L32"] = {"states": cnt, "rank_ms": per_r * 1e3, "unrank_ms": per_u * 1e3,
+                              "rank_per_s": cnt / per_r, "unrank_per_s": cnt / per_u}
+    del states, idx, back, s
+
     # k=8 FP32 block on L=28, n=14 (40,116,600 rows), XXZ J = Delta = 1
     s = dq.Sector(28, 14, 2, [7, 7, 7, 7], device=0)
     bonds, jxy, jz = synth.xxz_chain(28, 1.0, 1.0)
     t = dq.Terms(bonds)
     jd, zd = torch.tensor(jxy, device=dev), torch.tensor(jz, device=dev)
-    g = torch.Generator(device=dev)
-    g.manual_seed(synth.SEED_X)
     x = torch.randn((s.dim, 8), generator=g, device=dev, dtype=torch.float32)
     y = torch.empty_like(x)
     per = timed(lambda: dq.hamiltonian_apply(s, t, jd, zd, x, out=y))
