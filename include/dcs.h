@@ -181,6 +181,11 @@ int dcs_terms_destroy(dcs_terms *terms);
  * with no atomics, and the result is bitwise reproducible.  X and Y must not
  * overlap.  All bond sites must be < L.
  * Arithmetic: products and sums in dtype; couplings rounded to dtype.
+ * Calls on one sector must not overlap in time (they share the sector's tile
+ * counters and its cached split tables).  On a sector with a split view the
+ * first call with a terms object builds that pair's tables on the host and
+ * allocates them on the device (see "Split product" above); later calls
+ * allocate nothing.
  */
 int dcs_hamiltonian_apply(const dcs_sector *sector, const dcs_terms *terms, const double *d_jxy,
                           const double *d_jz, const double *d_h, int dtype, int k,

@@ -25,6 +25,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 #include "dcs.h"
@@ -168,6 +170,7 @@ struct LeftInfo {
     std::vector<uint64_t> h_ctab;  // host copy of the fused contribution table
     SplitRows rows[kMaxSplitCache];
     int next_slot = 0;
+    std::unique_ptr<std::mutex> rows_lock{new std::mutex};  // guards rows[] and next_slot
 };
 
 }  // namespace dcs

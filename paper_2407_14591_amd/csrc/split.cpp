@@ -23,6 +23,7 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
     LeftInfo &li = s->left;
     const SectorDesc &sd = s->desc;
     if (li.K == 0 || sd.Q != 2 || li.h_rwords.empty()) return nullptr;
+    std::lock_guard<std::mutex> guard(*li.rows_lock);  // concurrent first calls build the tables once
     for (int i = 0; i < kMaxSplitCache; ++i)
         if (li.rows[i].terms_id == t->id) return &li.rows[i];
     const int K = li.K, N = sd.N;
