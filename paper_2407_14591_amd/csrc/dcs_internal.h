@@ -142,7 +142,7 @@ struct SplitRows {
     uint32_t clbase[kMaxLeftM];      // first cluster of block m - m_lo
     uint32_t nclust[kMaxLeftM];
     uint32_t max_cluster = 0;
-    double *d_diag = nullptr;        // per call: left | right configuration diagonals
+    double *d_diag = nullptr;        // per call: left | right configuration diagonals, coupling factors
     int nR = 0, nX = 0, nIs = 0, nJs = 0, nD = 0;
     int nRloc = 0;                   // right-family bonds inside the last subsystem (listed first)
     uint32_t margin = 0;             // rows of the largest run of equal P_K..P_{N-2} words

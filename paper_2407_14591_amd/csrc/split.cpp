@@ -236,7 +236,8 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
               up((void **)&c.d_runs, li.h_runs.data(), li.h_runs.size() * sizeof(uint64_t)) &&
               up((void **)&c.d_clstart, clstart.data(), clstart.size() * sizeof(uint32_t)) &&
               up((void **)&c.d_clsize, clsize.data(), clsize.size() * sizeof(uint32_t)) &&
-              check_hip(hipMalloc(&c.d_diag, (li.count + li.rcount) * sizeof(double)),
+              // diagonal of both sides, then the per-call coupling factors (1024 doubles + 1024 floats)
+              check_hip(hipMalloc(&c.d_diag, ((li.count + li.rcount + 1) / 2 * 2 + 1536) * sizeof(double)),
                         "hipMalloc split diagonal") == DCS_OK;
     if (!ok) {
         free_rows(c);

@@ -6,18 +6,21 @@
 //
 // Three kernels per product, all bound by the gathers of X:
 //  * split_diag_kernel: the diagonal of each side per configuration, from
-//    this call's couplings and fields (count + rcount entries);
-//  * split_rows_kernel: one tile = 512 consecutive offsets of one run (one
-//    left configuration).  The right family reads its targets from a table
-//    per right configuration (16-bit offsets in the run, 0xFFFF where the bond
-//    does not hop); a bond across the cut reads the run of the left
-//    configuration with its left site flipped and the offset of the right
-//    configuration with its right site flipped.  Adds the diagonal, writes Y.
-//  * split_cols_kernel: one wave = 64 consecutive elements of one run; the
-//    left family's targets are the same elements of other runs, listed once
-//    per left configuration and read with scalar loads (the whole wave
-//    shares them), so every gather is one contiguous 256/512-byte segment.
-//    Adds into Y.
+//    this call's couplings and fields (count + rcount entries), and the
+//    coupling factors of the call in the compute type;
+//  * split_rows_kernel / split_rows_lds_kernel: one tile = 512 consecutive
+//    offsets of one run (one left configuration), or (rows of at most 8 bytes
+//    whose run fits LDS) one whole run staged in LDS.  The right family reads
+//    its targets from a table per right configuration (16-bit offsets in the
+//    run, 0xFFFF where the bond does not hop); a bond across the cut reads the
+//    run of the left configuration with its left site flipped and the offset
+//    of the right configuration with its right site flipped.  Adds the
+//    diagonal, writes Y.
+//  * split_cols_kernel: one tile = one cluster of left configurations at one
+//    1 KiB chunk of their runs; the left family's targets are the same bytes
+//    of other runs, listed once per left configuration and read with scalar
+//    loads (the whole wave shares them), so every gather is one contiguous
+//    1 KiB segment; targets inside the cluster come from LDS.  Adds into Y.
 // Every gather is a buffer load bounded by its target run: a table entry that
 // marks "no hop" (or any offset past the run) reads zero and touches nothing.
 #pragma once
@@ -32,6 +35,14 @@ using hx::Acc;
 constexpr int kThreads = 512;
 constexpr uint32_t kOob = 0x80000000u;  // past every run: all record counts here are < 2^31
 constexpr uint32_t kBufferWord3 = 0x00020000u;  // 32-bit data format, no swizzle
+
+// Per-call coupling factors in the compute type, written by split_diag_kernel
+// after the diagonal (one table per value type) and read with scalar loads.
+constexpr int kAmpRight = 0;     // 1/2 Jxy of the right-family bonds (by position, 288 slots)
+constexpr int kAmpCross = 288;   // 1/2 Jxy of the bonds across the cut (128 slots)
+constexpr int kJzCross = 416;    // 1/4 Jz of the bonds across the cut (128 slots)
+constexpr int kAmpBond = 544;    // 1/2 Jxy by bond index (256 slots)
+constexpr int kAmpEntries = 1024;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
@@ -96,16 +107,36 @@ struct BlockCursor {
 // ------------------------------------------------------------------ diagonal
 struct DiagParams {
     const uint32_t *lwords, *rwords;
-    const double *jz, *h;
+    const double *jxy, *jz, *h;
     double *out;
+    double *amp64;  // kAmpEntries doubles, then kAmpEntries floats
     uint32_t count, rcount;
-    int nD;
+    int nD, nR, nX, nbonds;
     DiagTerm d[kMaxBonds + kMaxSites];
+    uint16_t rbond[kMaxBonds];
+    uint16_t xbond[kMaxCross];
 };
 static_assert(sizeof(DiagParams) <= 4096, "kernel arguments are limited to 4 KiB");
 
 template <int Unused = 0>
 __global__ __launch_bounds__(256) void split_diag_kernel(const DiagParams P) {
+    if (blockIdx.x == 0) {
+        float *amp32 = reinterpret_cast<float *>(P.amp64 + kAmpEntries);
+        for (int q = threadIdx.x; q < kAmpEntries; q += 256) {
+            double v = 0.0;
+            if (q < kAmpCross) {
+                if (q - kAmpRight < P.nR) v = 0.5 * P.jxy[P.rbond[q - kAmpRight]];
+            } else if (q < kJzCross) {
+                if (q - kAmpCross < P.nX) v = 0.5 * P.jxy[P.xbond[q - kAmpCross]];
+            } else if (q < kAmpBond) {
+                if (q - kJzCross < P.nX) v = 0.25 * P.jz[P.xbond[q - kJzCross]];
+            } else if (q - kAmpBond < P.nbonds) {
+                v = 0.5 * P.jxy[q - kAmpBond];
+            }
+            P.amp64[q] = v;
+            amp32[q] = (float)v;
+        }
+    }
     const uint32_t g = blockIdx.x * 256u + threadIdx.x;
     if (g >= P.count + P.rcount) return;
     const uint32_t side = g < P.count ? 0u : 1u;
@@ -166,7 +197,7 @@ inline void xcd_ranges(uint64_t tiles, uint64_t *xbase) {
 struct RowParams {
     const void *x;
     void *y;
-    const double *jxy, *jz;
+    const void *amp;  // coupling factors of the compute type (kAmp* layout)
     const uint32_t *lwords, *rwords;
     const uint64_t *runs, *xl;
     const uint16_t *vo, *xo;
@@ -228,14 +259,20 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P)
     using B = RowBatch<T, K>;
     constexpr uint32_t RB = B::RB;
     extern __shared__ __align__(16) char rows_lds[];
-    __shared__ T ramp[kMaxBonds + 32];
-    __shared__ T xamp[kMaxCross + 8], xjz[kMaxCross + 8];
+    __shared__ T ramp[kAmpCross - kAmpRight];
+    __shared__ T xamp[kJzCross - kAmpCross], xjz[kAmpBond - kJzCross];
     __shared__ uint32_t slots[2];
-    for (int q = threadIdx.x; q < kMaxBonds + 32; q += kThreads)
-        ramp[q] = q < P.nR ? (T)(0.5 * P.jxy[P.rbond[q]]) : (T)0;
-    for (int q = threadIdx.x; q < kMaxCross + 8; q += kThreads) {
-        xamp[q] = q < P.nX ? (T)(0.5 * P.jxy[P.xb[q].bond]) : (T)0;
-        xjz[q] = q < P.nX ? (T)(0.25 * P.jz[P.xb[q].bond]) : (T)0;
+    {
+        const T *A = reinterpret_cast<const T *>(P.amp);
+        for (int q = threadIdx.x; q < kAmpBond; q += kThreads) {
+            const T v = A[q];
+            if (q < kAmpCross)
+                ramp[q] = v;
+            else if (q < kJzCross)
+                xamp[q - kAmpCross] = v;
+            else
+                xjz[q - kJzCross] = v;
+        }
     }
     const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
     T *__restrict__ y = reinterpret_cast<T *>(P.y);
@@ -410,16 +447,10 @@ __global__ __launch_bounds__(kThreads) void split_rows_lds_kernel(const RowParam
     constexpr int XB = 4;   // of those, gathers in flight per batch
     extern __shared__ __align__(16) char dyn[];
     V *xr = reinterpret_cast<V *>(dyn);
-    __shared__ T ramp[kMaxBonds];
-    __shared__ T xamp[kMaxCross], xjz[kMaxCross];
     __shared__ uint4 xinfo[XF];  // per bond across the cut: run base (lo, hi), bytes | bit << 31
     __shared__ uint32_t slots[2];
-    for (int q = threadIdx.x; q < kMaxBonds; q += kThreads)
-        ramp[q] = q < P.nR ? (T)(0.5 * P.jxy[P.rbond[q]]) : (T)0;
-    for (int q = threadIdx.x; q < kMaxCross; q += kThreads) {
-        xamp[q] = q < P.nX ? (T)(0.5 * P.jxy[P.xb[q].bond]) : (T)0;
-        xjz[q] = q < P.nX ? (T)(0.25 * P.jz[P.xb[q].bond]) : (T)0;
-    }
+    const cptr<T> A = ro(reinterpret_cast<const T *>(P.amp));
+    const cptr<T> ramp = A + kAmpRight, xamp = A + kAmpCross, xjz = A + kJzCross;
     const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
     T *__restrict__ y = reinterpret_cast<T *>(P.y);
     const int nRq = (P.nR + 7) >> 3;
@@ -565,7 +596,7 @@ __global__ __launch_bounds__(kThreads) void split_rows_lds_kernel(const RowParam
 struct ColParams {
     const void *x;
     void *y;
-    const double *jxy;
+    const void *amp;  // coupling factors of the compute type (kAmp* layout)
     const uint32_t *lptr;
     const uint64_t *lent, *runs;
     const uint32_t *clstart, *clsize;
@@ -592,10 +623,10 @@ __global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams
     constexpr int V = kColLaneBytes / sizeof(T);
     typedef T vec_t __attribute__((ext_vector_type(V)));
     extern __shared__ __align__(16) char cl_lds[];  // [cluster run][kColWaveBytes]
-    __shared__ T amp[kMaxBonds];
     __shared__ uint32_t slots[2];
+    __shared__ T amp[kMaxBonds];
     for (int q = threadIdx.x; q < kMaxBonds; q += kColThreads)
-        amp[q] = q < P.nbonds ? (T)(0.5 * P.jxy[q]) : (T)0;
+        amp[q] = reinterpret_cast<const T *>(P.amp)[kAmpBond + q];
     const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
     T *__restrict__ y = reinterpret_cast<T *>(P.y);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -690,19 +721,28 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
                    const double *jz, const double *h, int nbonds, hipStream_t stream) {
     const LeftInfo &li = s->left;
     const uint32_t count = (uint32_t)li.count, rcount = (uint32_t)li.rcount;
-    // 1. diagonal per configuration of each side
+    double *amp64 = c.d_diag + (count + rcount + 1) / 2 * 2;  // 16-byte aligned after the diagonal
+    const void *amp = sizeof(T) == 8 ? (const void *)amp64 : (const void *)(amp64 + kAmpEntries);
+    // 1. diagonal per configuration of each side, coupling factors
     {
         DiagParams D;
         memset(&D, 0, sizeof(D));
         D.lwords = (const uint32_t *)li.d_words;
         D.rwords = (const uint32_t *)li.d_rwords;
+        D.jxy = jxy;
         D.jz = jz;
         D.h = h;
         D.out = c.d_diag;
+        D.amp64 = amp64;
         D.count = count;
         D.rcount = rcount;
         D.nD = c.nD;
+        D.nR = c.nR;
+        D.nX = c.nX;
+        D.nbonds = nbonds;
         memcpy(D.d, c.d, sizeof(D.d));
+        memcpy(D.rbond, c.r_bond, sizeof(D.rbond));
+        for (int q = 0; q < c.nX; ++q) D.xbond[q] = c.x[q].bond;
         split_diag_kernel<0><<<(count + rcount + 255) / 256, 256, 0, stream>>>(D);
         if (int r = check_hip(hipGetLastError(), "split diagonal launch")) return r;
     }
@@ -713,8 +753,7 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
         memset(&P, 0, sizeof(P));
         P.x = x;
         P.y = y;
-        P.jxy = jxy;
-        P.jz = jz;
+        P.amp = amp;
         P.lwords = (const uint32_t *)li.d_words;
         P.rwords = (const uint32_t *)li.d_rwords;
         P.runs = c.d_runs;
@@ -800,7 +839,7 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
         memset(&P, 0, sizeof(P));
         P.x = x;
         P.y = y;
-        P.jxy = jxy;
+        P.amp = amp;
         P.lptr = c.d_lptr;
         P.lent = c.d_lent;
         P.runs = c.d_runs;

@@ -264,3 +264,27 @@ def test_large_workload_L34_sampled():
     err = rel_err(got, y_ref)
     say("rel err", err)
     assert err <= TOL[torch.float32]
+
+
+def test_split_tables_cache_and_couplings(monkeypatch):
+    """One split sector with six terms objects (more than the four cached table sets,
+    so sets are evicted and rebuilt) and couplings changed between calls: every
+    product equals the single pass on the same input (FP64)."""
+    monkeypatch.setenv("DCS_SPLIT_MIN_DIM", "0")
+    L, n = 18, 9
+    s = dq.Sector(L, n, 2, [5, 4, 5, 4])
+    rng = np.random.default_rng(11)
+    x = torch.tensor(rng.normal(size=s.dim), device=DEV)
+    graphs = [random_graph(L, L + 3 * i, rng) + synth.chain_bonds(L, 1) for i in range(6)]
+    terms = [dq.Terms(b) for b in graphs]
+    for rep in range(2):
+        for b, t in zip(graphs, terms):
+            for _ in range(2):  # same tables, new couplings
+                jxy, jz = dev_f64(rng.normal(size=len(b))), dev_f64(rng.normal(size=len(b)))
+                h = dev_f64(rng.normal(size=L))
+                monkeypatch.delenv("DCS_SPLIT", raising=False)
+                y_split = dq.hamiltonian_apply(s, t, jxy, jz, x, h=h)
+                monkeypatch.setenv("DCS_SPLIT", "0")
+                y_one = dq.hamiltonian_apply(s, t, jxy, jz, x, h=h)
+                assert rel_err(y_split.cpu().numpy(), y_one.cpu().numpy()) <= 1e-12, rep
+    monkeypatch.delenv("DCS_SPLIT", raising=False)
