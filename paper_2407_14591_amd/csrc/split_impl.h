@@ -438,11 +438,19 @@ __device__ __forceinline__ uint32_t u16_of(const uint4 &v, uint32_t i) {  // i u
     return (i & 1u) ? (w >> 16) : (w & 0xFFFFu);
 }
 
+// Threads per workgroup of the staged-run pass: 512 for 4-byte rows (three runs
+// fit one CU's LDS), 1024 for 8-byte rows (one run per CU, shared by 16 waves).
 template <typename T, int K>
-__global__ __launch_bounds__(kThreads) void split_rows_lds_kernel(const RowParams P) {
+constexpr int lds_rows_threads() {
+    return K * sizeof(T) == 4 ? 512 : 1024;
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_kernel(const RowParams P) {
     using V = Acc<T, K>;
     constexpr uint32_t RB = K * sizeof(T);
     static_assert(RB <= 8, "staged runs hold rows of at most 8 bytes");
+    constexpr int NT = lds_rows_threads<T, K>();
     constexpr int XF = 32;  // bonds across the cut whose gather descriptors are set up once per run
     constexpr int XB = 4;   // of those, gathers in flight per batch
     extern __shared__ __align__(16) char dyn[];
@@ -482,7 +490,7 @@ __global__ __launch_bounds__(kThreads) void split_rows_lds_kernel(const RowParam
         {
             const auto rs = rsrc(x + R * K, bytes);
             uint4 *d16 = reinterpret_cast<uint4 *>(dyn);
-            for (uint32_t i = threadIdx.x; i < bytes / 16; i += kThreads) {
+            for (uint32_t i = threadIdx.x; i < bytes / 16; i += NT) {
                 const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, i * 16u, 0, 0);
                 __builtin_memcpy(&d16[i], &v, 16);
             }
@@ -497,11 +505,11 @@ __global__ __launch_bounds__(kThreads) void split_rows_lds_kernel(const RowParam
         }
         ChunkIdx cur = load_chunk_idx(P, mi, threadIdx.x, ncols, nRq);
         __syncthreads();
-        for (uint32_t c0 = 0; c0 < ncols; c0 += kThreads) {
+        for (uint32_t c0 = 0; c0 < ncols; c0 += NT) {
             const uint32_t r = c0 + threadIdx.x;
             const bool active = r < ncols;
             ChunkIdx nxt = cur;
-            if (c0 + kThreads < ncols) nxt = load_chunk_idx(P, mi, r + kThreads, ncols, nRq);
+            if (c0 + NT < ncols) nxt = load_chunk_idx(P, mi, r + NT, ncols, nRq);
             V acc;
 #pragma unroll
             for (int c = 0; c < K; ++c) acc.v[c] = (T)0;
@@ -812,13 +820,14 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
                 auto kern = split_rows_lds_kernel<T, K>;
                 if (int r = ensure_lds(kern, lds)) return r;
                 int per_cu = 1;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds) != hipSuccess ||
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, lds_rows_threads<T, K>(), lds) !=
+                        hipSuccess ||
                     per_cu < 1)
                     per_cu = 1;
                 int wgs = device_cu_count(s->device) * std::min(per_cu, 4);
                 wgs = std::min<int>(wgs, (int)(((uint64_t)count + 7) / 8 * 8));
                 wgs = (wgs + 7) / 8 * 8;
-                kern<<<wgs, kThreads, lds, stream>>>(P);
+                kern<<<wgs, lds_rows_threads<T, K>(), lds, stream>>>(P);
                 if (int r = check_hip(hipGetLastError(), "split rows (staged runs) launch")) return r;
                 staged = true;
             }
