@@ -258,7 +258,11 @@ int dcs_lanczos_workspace_size(const dcs_sector *sector, int vec_dtype, int step
  * three-term coefficients (A, B) = (beta_{j-1}/|u_{j-1}|, alpha_j/|u_j|); LOCAL
  * solves the 2x2 Gram system so that H v_j is projected out of
  * span(v_{j-1}, v_j) exactly for the stored operands (alpha_j is then the
- * coefficient of v_j).
+ * coefficient of v_j).  In these two modes steps 2.. are replayed from two
+ * captured HIP graphs (one per parity of j; the launches read j from the
+ * workspace) on a private stream ordered after and before `stream`;
+ * DCS_LANCZOS_GRAPH=0 in the environment launches every step eagerly (the
+ * results are identical bit for bit).
  * Stops early when beta_j <= 1e-12 max_i(|alpha_i|, beta_i) or after D steps.
  * The Ritz values (eigenvalues of the tridiagonal T, Sturm bisection in FP64 on
  * the device) are returned in increasing order.

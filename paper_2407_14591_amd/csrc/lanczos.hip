@@ -8,6 +8,7 @@
 // bisection of the tridiagonal matrix in FP64 on the device.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -28,6 +29,7 @@ struct LzState {
     double scale;      // running max of |alpha_i|, beta_i
     double inv_beta;   // 1 / beta_j for the next normalisation
     double sc, scp;    // two-vector form: 1/|u_j| and 1/|u_{j-1}| of the stored vectors
+    int j;             // two-vector form: the current step (kernels of a captured step read it)
 };
 
 template <typename T>
@@ -234,8 +236,9 @@ __global__ __launch_bounds__(kVecThreads) void k_gram(const T *__restrict__ w, c
 
 // Step coefficients from the reduced sums g[0..2]; rec[3j..3j+2] = (s, A, B).
 __global__ void k_lz_coef(const double *g, LzState *st, double *alpha, const double *beta,
-                          double *rec, int j, int local) {
+                          double *rec, int local) {
     if (st->done || threadIdx.x != 0) return;
+    const int j = st->j;
     const double s = st->sc, p = st->scp;
     const double r1 = s * s * g[0];  // v_j . H v_j
     const double r0 = p * s * g[1];  // v_{j-1} . H v_j
@@ -259,15 +262,17 @@ __global__ void k_lz_coef(const double *g, LzState *st, double *alpha, const dou
     rec[3 * j + 2] = b * s;
 }
 
-// out = s w - A ujm1 - B uj with (s, A, B) = c[0..2]; partial of |out|^2 when
+// out = s w - A ujm1 - B uj with (s, A, B) = rec[3j..3j+2] (j = st->j when st is
+// given); partial of |out|^2 when
 // partials is not NULL.  out may alias ujm1: each element is read before it is
 // written, by the same thread.
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_lz_update(const T *__restrict__ w, const T *__restrict__ uj,
                                                            const T *ujm1, T *out, uint64_t n,
-                                                           const double *c, double *partials,
+                                                           const double *rec, int j, double *partials,
                                                            const LzState *st) {
     if (st && st->done) return;
+    const double *c = rec + 3 * (st ? st->j : j);
     const double sw = c[0], A = c[1], B = c[2];
     double s = 0.0;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -283,8 +288,9 @@ __global__ __launch_bounds__(kVecThreads) void k_lz_update(const T *__restrict__
 
 // beta_j = sqrt(sum of partials); breakdown test; the new vector's 1/|u|.
 __global__ __launch_bounds__(kReduceThreads) void k_lz_norm(const double *partials, int nblocks, LzState *st,
-                                                            double *beta, int j, int m) {
+                                                            double *beta, int m) {
     if (st->done) return;
+    const int j = st->j;
     __shared__ double red[kReduceThreads];
     double s = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partials[b];
@@ -303,6 +309,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_lz_norm(const double *partia
             beta[j] = b;
             st->scp = st->sc;
             st->sc = 1.0 / b;
+            st->j = j + 1;
         }
     }
 }
@@ -477,6 +484,48 @@ Layout layout(const dcs_sector *s, int dtype, int steps, int reorth, int want_ve
     return L;
 }
 
+// DCS_LANCZOS_GRAPH=0 in the environment (read at every call) launches every step
+// eagerly instead of replaying captured steps.
+bool lanczos_graph_enabled() {
+    const char *e = getenv("DCS_LANCZOS_GRAPH");
+    return !(e && e[0] == '0');
+}
+
+// Steps 2..m-1 of the two-vector form as two captured HIP graphs (one per parity
+// of j), replayed on a private stream ordered after and before `stream`.  The
+// step's launches read the step index from device memory, so a replay needs no
+// host work.
+template <typename StepFn, typename T>
+int replay_steps(StepFn &step, T *ring0, T *ring1, int m, hipStream_t stream) {
+    hipStream_t gs = nullptr;
+    hipEvent_t ev = nullptr;
+    hipGraphExec_t ex[2] = {nullptr, nullptr};
+    int r = check_hip(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking), "Lanczos graph stream");
+    if (!r) r = check_hip(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "Lanczos graph event");
+    if (!r) r = check_hip(hipEventRecord(ev, stream), "Lanczos graph event record");
+    if (!r) r = check_hip(hipStreamWaitEvent(gs, ev, 0), "Lanczos graph stream wait");
+    for (int p = 0; p < 2 && !r; ++p) {
+        T *cur = p ? ring1 : ring0, *prev = p ? ring0 : ring1;
+        hipGraph_t g = nullptr;
+        r = check_hip(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal), "Lanczos capture");
+        if (r) break;
+        const int rs = step(cur, prev, prev, gs);
+        const int re = check_hip(hipStreamEndCapture(gs, &g), "Lanczos end capture");
+        r = rs ? rs : re;
+        if (!r) r = check_hip(hipGraphInstantiate(&ex[p], g, nullptr, nullptr, 0), "Lanczos graph instantiate");
+        if (g) hipGraphDestroy(g);
+    }
+    for (int j = 2; j < m && !r; ++j) r = check_hip(hipGraphLaunch(ex[j & 1], gs), "Lanczos graph launch");
+    if (!r) r = check_hip(hipEventRecord(ev, gs), "Lanczos graph event record");
+    if (!r) r = check_hip(hipStreamWaitEvent(stream, ev, 0), "Lanczos graph join");
+    if (gs) hipStreamSynchronize(gs);
+    for (auto &e : ex)
+        if (e) hipGraphExecDestroy(e);
+    if (ev) hipEventDestroy(ev);
+    if (gs) hipStreamDestroy(gs);
+    return r;
+}
+
 template <typename T>
 int run_lanczos(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
                 const double *h, int dtype, int steps, int reorth, const void *v0, double *h_alpha,
@@ -501,26 +550,37 @@ int run_lanczos(const dcs_sector *s, const dcs_terms *t, const double *jxy, cons
         return r;
     double *rec = (double *)(ws + L.rec);
     const T *u0 = (const T *)v0;
-    // two-vector form: u_0 = v0 as given, u_{j>0} in the ring
-    auto uvec = [&](int i) -> const T * { return i == 0 ? u0 : V + (uint64_t)(i & 1) * n; };
+    // two-vector form: u_0 = v0 as given, u_{j>0} in the ring (slot j & 1)
     if (ring) {
         k_norm2<T><<<nb, kVecThreads, 0, stream>>>(u0, n, part);
         k_reduce<<<1, kReduceThreads, 0, stream>>>(part, nb, 1, &st->sc, 3, nullptr, alpha, beta, 0,
                                                    L.m);
         if (int r = chk("Lanczos start")) return r;
-        for (int j = 0; j < L.m; ++j) {
-            if (int r = launch_hx(s, t, jxy, jz, h, dtype, 1, uvec(j), w, stream)) return r;
-            const T *ujm1 = j > 0 ? uvec(j - 1) : nullptr;
-            k_gram<T><<<nb, kVecThreads, 0, stream>>>(w, uvec(j), ujm1, n, part, st);
-            k_reduce<<<1, kReduceThreads, 0, stream>>>(part, nb, 3, coef, 0, st, alpha, beta, j, L.m);
-            k_lz_coef<<<1, 64, 0, stream>>>(coef, st, alpha, beta, rec, j,
-                                            reorth == DCS_REORTH_LOCAL ? 1 : 0);
-            if (j + 1 < L.m) {
-                k_lz_update<T><<<nb, kVecThreads, 0, stream>>>(w, uvec(j), ujm1, V + (uint64_t)((j + 1) & 1) * n,
-                                                               n, rec + 3 * j, part, st);
-                k_lz_norm<<<1, kReduceThreads, 0, stream>>>(part, nb, st, beta, j, L.m);
+        const int local = reorth == DCS_REORTH_LOCAL ? 1 : 0;
+        T *ring0 = V, *ring1 = V + n;
+        // one step; the kernels take the step index from the device state, so the
+        // same launches serve every step of one parity (u_j, u_{j-1}, u_{j+1} slots)
+        auto step = [&](const T *uj, const T *ujm1, T *out, hipStream_t q) -> int {
+            if (int r = launch_hx(s, t, jxy, jz, h, dtype, 1, uj, w, q)) return r;
+            k_gram<T><<<nb, kVecThreads, 0, q>>>(w, uj, ujm1, n, part, st);
+            k_reduce<<<1, kReduceThreads, 0, q>>>(part, nb, 3, coef, 0, st, alpha, beta, 0, L.m);
+            k_lz_coef<<<1, 64, 0, q>>>(coef, st, alpha, beta, rec, local);
+            k_lz_update<T><<<nb, kVecThreads, 0, q>>>(w, uj, ujm1, out, n, rec, 0, part, st);
+            k_lz_norm<<<1, kReduceThreads, 0, q>>>(part, nb, st, beta, L.m);
+            return chk("Lanczos step");
+        };
+        if (int r = step(u0, nullptr, ring1, stream)) return r;               // j = 0
+        if (L.m > 1)
+            if (int r = step(ring1, u0, ring0, stream)) return r;             // j = 1
+        if (L.m > 2) {
+            if (lanczos_graph_enabled()) {
+                if (int r = replay_steps(step, ring0, ring1, L.m, stream)) return r;
+            } else {
+                for (int j = 2; j < L.m; ++j) {
+                    T *cur = (j & 1) ? ring1 : ring0, *prev = (j & 1) ? ring0 : ring1;
+                    if (int r = step(cur, prev, prev, stream)) return r;
+                }
             }
-            if (int r = chk("Lanczos step")) return r;
         }
     } else {
         // v_0 = v0 / |v0|
@@ -599,7 +659,7 @@ int run_lanczos(const dcs_sector *s, const dcs_terms *t, const double *jxy, cons
             if (int r = launch_hx(s, t, jxy, jz, h, dtype, 1, rv(j), w, stream)) return r;
             k_lz_update<T><<<nb, kVecThreads, 0, stream>>>(w, rv(j), j > 0 ? rv(j - 1) : nullptr,
                                                            R + (uint64_t)((j + 1) & 1) * n, n,
-                                                           rec + 3 * j, nullptr, nullptr);
+                                                           rec, j, nullptr, nullptr);
             k_axpy_rec<T><<<nb, kVecThreads, 0, stream>>>(psi, rv(j + 1), n, svec, rec, j + 1, 0);
             if (int r = chk("Ritz vector replay")) return r;
         }
