@@ -185,7 +185,12 @@ int dcs_terms_destroy(dcs_terms *terms);
  * counters and its cached split tables).  On a sector with a split view the
  * first call with a terms object builds that pair's tables on the host and
  * allocates them on the device (see "Split product" above); later calls
- * allocate nothing.
+ * allocate nothing.  Autotuner: the first call for a (terms, dtype, k) on a
+ * sector with a split view also times the launch forms (split product with
+ * runs staged in on-chip memory, split product without, single pass; each
+ * twice, HIP events, synchronising the stream), keeps the fastest for that key
+ * and returns its Y; later calls use it.  Inside stream capture, or with
+ * DCS_AUTOTUNE=0 in the environment, the default form (staged split) is used.
  */
 int dcs_hamiltonian_apply(const dcs_sector *sector, const dcs_terms *terms, const double *d_jxy,
                           const double *d_jz, const double *d_h, int dtype, int k,

@@ -25,6 +25,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <vector>
@@ -170,7 +171,8 @@ struct LeftInfo {
     std::vector<uint64_t> h_ctab;  // host copy of the fused contribution table
     SplitRows rows[kMaxSplitCache];
     int next_slot = 0;
-    std::unique_ptr<std::mutex> rows_lock{new std::mutex};  // guards rows[] and next_slot
+    std::unique_ptr<std::mutex> rows_lock{new std::mutex};  // guards rows[], next_slot, tuned
+    std::map<uint64_t, int> tuned;  // autotuned launch form per (terms id, dtype, k)
 };
 
 }  // namespace dcs

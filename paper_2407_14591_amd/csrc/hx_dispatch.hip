@@ -2,6 +2,7 @@
 // column count and subsystem bound; the instantiations live in hx_f*_k*.hip and
 // hx_adjoint_f*.hip so they compile in parallel.
 #include <cstdlib>
+#include <mutex>
 
 #include "split_impl.h"
 
@@ -10,7 +11,7 @@ namespace sp {
 #define DCS_SPLIT_EXTERN(T, K)                                                                   \
     extern template int launch_split_t<T, K>(dcs_sector *, const SplitRows &, const void *, void *, \
                                              const double *, const double *, const double *, int,   \
-                                             hipStream_t);
+                                             bool, hipStream_t);
 DCS_SPLIT_EXTERN(float, 1)
 DCS_SPLIT_EXTERN(float, 2)
 DCS_SPLIT_EXTERN(float, 4)
@@ -82,12 +83,13 @@ int launch_hx_d(const dcs_sector *s, HxParams &P, int dtype, int k, hipStream_t 
 
 template <typename T>
 int launch_split_k(dcs_sector *s, const SplitRows &c, const void *x, void *y, const double *jxy,
-                   const double *jz, const double *h, int nbonds, int k, hipStream_t stream) {
+                   const double *jz, const double *h, int nbonds, int k, bool staged_ok,
+                   hipStream_t stream) {
     switch (k) {
-        case 1: return sp::launch_split_t<T, 1>(s, c, x, y, jxy, jz, h, nbonds, stream);
-        case 2: return sp::launch_split_t<T, 2>(s, c, x, y, jxy, jz, h, nbonds, stream);
-        case 4: return sp::launch_split_t<T, 4>(s, c, x, y, jxy, jz, h, nbonds, stream);
-        default: return sp::launch_split_t<T, 8>(s, c, x, y, jxy, jz, h, nbonds, stream);
+        case 1: return sp::launch_split_t<T, 1>(s, c, x, y, jxy, jz, h, nbonds, staged_ok, stream);
+        case 2: return sp::launch_split_t<T, 2>(s, c, x, y, jxy, jz, h, nbonds, staged_ok, stream);
+        case 4: return sp::launch_split_t<T, 4>(s, c, x, y, jxy, jz, h, nbonds, staged_ok, stream);
+        default: return sp::launch_split_t<T, 8>(s, c, x, y, jxy, jz, h, nbonds, staged_ok, stream);
     }
 }
 
@@ -98,23 +100,10 @@ int pick_nmax(const dcs_sector *s) { return s->desc.N <= 4 ? 4 : 8; }
 
 using namespace hx;
 
-int launch_hx(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
-              const double *h, int dtype, int k, const void *x, void *y, hipStream_t stream) {
-    DeviceGuard dg(s->device);
-    if (s->left.K > 0 && s->desc.Q == 2 && split_enabled()) {
-        if (t->max_site >= s->desc.L)
-            return set_error(DCS_EINVAL, "bond site %d outside the sector's %d sites", t->max_site,
-                             s->desc.L);
-        clear_error();
-        const SplitRows *c = split_rows(const_cast<dcs_sector *>(s), t);
-        if (c) {
-            dcs_sector *sm = const_cast<dcs_sector *>(s);
-            return dtype == DCS_F32
-                       ? launch_split_k<float>(sm, *c, x, y, jxy, jz, h, t->num_bonds, k, stream)
-                       : launch_split_k<double>(sm, *c, x, y, jxy, jz, h, t->num_bonds, k, stream);
-        }
-        if (dcs_last_error()[0]) return DCS_EHIP;
-    }
+namespace {
+
+int launch_single(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
+                  const double *h, int dtype, int k, const void *x, void *y, hipStream_t stream) {
     const int nmax = pick_nmax(s);
     HxParams P;
     if (int r = fill_params(s, t, nmax, jxy, jz, h, P)) return r;
@@ -125,6 +114,101 @@ int launch_hx(const dcs_sector *s, const dcs_terms *t, const double *jxy, const 
                          : launch_hx_d<uint64_t, 8>(s, P, dtype, k, stream);
     return nmax == 4 ? launch_hx_d<uint32_t, 4>(s, P, dtype, k, stream)
                      : launch_hx_d<uint32_t, 8>(s, P, dtype, k, stream);
+}
+
+// Launch forms of a product on a sector with a split view.
+enum Form { kFormSplitStaged = 0, kFormSplitGlobal = 1, kFormSingle = 2, kNumForms = 3 };
+
+int launch_form(dcs_sector *s, const dcs_terms *t, const SplitRows &c, int form, const double *jxy,
+                const double *jz, const double *h, int dtype, int k, const void *x, void *y,
+                hipStream_t stream) {
+    if (form == kFormSingle) return launch_single(s, t, jxy, jz, h, dtype, k, x, y, stream);
+    const bool staged = form == kFormSplitStaged;
+    return dtype == DCS_F32 ? launch_split_k<float>(s, c, x, y, jxy, jz, h, t->num_bonds, k, staged, stream)
+                            : launch_split_k<double>(s, c, x, y, jxy, jz, h, t->num_bonds, k, staged, stream);
+}
+
+// DCS_AUTOTUNE=0 in the environment (read at every call) keeps the default form.
+bool autotune_enabled() {
+    const char *e = getenv("DCS_AUTOTUNE");
+    return !(e && e[0] == '0');
+}
+
+// Autotuner: the first product of a (terms, dtype, k) on a split sector times
+// every launch form twice (HIP events on the caller's stream, second run
+// counted) and keeps the fastest for that key in the sector.  Every form
+// writes the same Y (up to rounding order), so the call's result is valid
+// whichever form ran last; the fastest runs last.
+int tuned_form(dcs_sector *s, const dcs_terms *t, const SplitRows &c, const double *jxy,
+               const double *jz, const double *h, int dtype, int k, const void *x, void *y,
+               hipStream_t stream, bool *ran) {
+    *ran = false;
+    const uint64_t key = (t->id << 8) | ((uint64_t)dtype << 4) | (uint64_t)k;
+    LeftInfo &li = s->left;
+    {
+        std::lock_guard<std::mutex> g(*li.rows_lock);
+        auto it = li.tuned.find(key);
+        if (it != li.tuned.end()) return it->second;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (!autotune_enabled() || hipStreamIsCapturing(stream, &cs) != hipSuccess ||
+        cs != hipStreamCaptureStatusNone)
+        return kFormSplitStaged;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (check_hip(hipEventCreate(&e0), "autotune event") || check_hip(hipEventCreate(&e1), "autotune event")) {
+        if (e0) hipEventDestroy(e0);
+        return -1;
+    }
+    float best_ms = 0.f;
+    int best = kFormSplitStaged;
+    int r = DCS_OK;
+    for (int f = 0; f < kNumForms && !r; ++f) {
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && !r; ++rep) {
+            r = check_hip(hipEventRecord(e0, stream), "autotune record");
+            if (!r) r = launch_form(s, t, c, f, jxy, jz, h, dtype, k, x, y, stream);
+            if (!r) r = check_hip(hipEventRecord(e1, stream), "autotune record");
+            if (!r) r = check_hip(hipEventSynchronize(e1), "autotune synchronise");
+            if (!r) r = check_hip(hipEventElapsedTime(&ms, e0, e1), "autotune time");
+        }
+        if (!r && (f == 0 || ms < best_ms)) {
+            best_ms = ms;
+            best = f;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (r) return -1;
+    {
+        std::lock_guard<std::mutex> g(*li.rows_lock);
+        li.tuned[key] = best;
+    }
+    *ran = best == kNumForms - 1;  // the fastest form was the last one timed: Y is its output
+    return best;
+}
+
+}  // namespace
+
+int launch_hx(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
+              const double *h, int dtype, int k, const void *x, void *y, hipStream_t stream) {
+    DeviceGuard dg(s->device);
+    if (s->left.K > 0 && s->desc.Q == 2 && split_enabled()) {
+        if (t->max_site >= s->desc.L)
+            return set_error(DCS_EINVAL, "bond site %d outside the sector's %d sites", t->max_site,
+                             s->desc.L);
+        clear_error();
+        dcs_sector *sm = const_cast<dcs_sector *>(s);
+        const SplitRows *c = split_rows(sm, t);
+        if (c) {
+            bool ran = false;
+            const int form = tuned_form(sm, t, *c, jxy, jz, h, dtype, k, x, y, stream, &ran);
+            if (form < 0) return DCS_EHIP;
+            if (ran) return DCS_OK;
+            return launch_form(sm, t, *c, form, jxy, jz, h, dtype, k, x, y, stream);
+        }
+        if (dcs_last_error()[0]) return DCS_EHIP;
+    }
+    return launch_single(s, t, jxy, jz, h, dtype, k, x, y, stream);
 }
 
 size_t adjoint_ws_bytes(const dcs_sector *s, const dcs_terms *t) {

@@ -724,9 +724,10 @@ inline int split_grid(const dcs_sector *s, uint64_t tiles) {
     return (int)(w ? w : 8);
 }
 
+// staged: allow the staged-run rows pass (rows of at most 8 bytes whose runs fit LDS)
 template <typename T, int K>
 int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, const double *jxy,
-                   const double *jz, const double *h, int nbonds, hipStream_t stream) {
+                   const double *jz, const double *h, int nbonds, bool staged_ok, hipStream_t stream) {
     const LeftInfo &li = s->left;
     const uint32_t count = (uint32_t)li.count, rcount = (uint32_t)li.rcount;
     double *amp64 = c.d_diag + (count + rcount + 1) / 2 * 2;  // 16-byte aligned after the diagonal
@@ -794,7 +795,7 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
         const size_t lds = ((max_cols + 1) * RowBatch<T, K>::RB + 15) / 16 * 16;
         bool staged = false;
         if constexpr (RowBatch<T, K>::RB <= 8) {
-            if (lds <= kRowLdsMax && rows_lds_enabled()) {
+            if (lds <= kRowLdsMax && staged_ok && rows_lds_enabled()) {
                 // one tile per left configuration
                 // one tile per left configuration; the XCD ranges hold equal row counts
                 for (int m = 0; m < li.m_count; ++m) P.tbase[m] = li.lbase[m];

@@ -185,6 +185,7 @@ def test_split_small(monkeypatch, L, n, split, k, dt, staged):
     runs of length one."""
     monkeypatch.setenv("DCS_SPLIT_MIN_DIM", "0")
     monkeypatch.setenv("DCS_SPLIT_LDS", staged)
+    monkeypatch.setenv("DCS_AUTOTUNE", "0")  # keep the split form (the tuner may pick another)
     rng = np.random.default_rng(L + k)
     b = BruteSector(2, L, n, split)
     bonds = random_graph(L, 2 * L, rng) + synth.chain_bonds(L, 1)
@@ -203,6 +204,7 @@ def test_split_L26_all_rows(monkeypatch, staged):
     """L=26, n=13 (10,400,600 states, split 8/9/9): the split product on every row,
     with and without the runs of x staged in LDS."""
     monkeypatch.setenv("DCS_SPLIT_LDS", staged)
+    monkeypatch.setenv("DCS_AUTOTUNE", "0")
     L, n, sp = 26, 13, [8, 9, 9]
     s = dq.Sector(L, n, 2, sp)
     ns = native.NativeSector(2, L, n, sp)
@@ -220,6 +222,7 @@ def test_split_matches_single_pass_L24(monkeypatch, k):
     """L=24, n=12 (2,704,156 states) with the split view forced on: the split product
     (staged and unstaged runs) against the single pass, both ways in FP64 and FP32."""
     monkeypatch.setenv("DCS_SPLIT_MIN_DIM", "0")
+    monkeypatch.setenv("DCS_AUTOTUNE", "0")
     L, n = 24, 12
     s = dq.Sector(L, n, 2, [6, 6, 6, 6])
     bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.5, 1.0)
@@ -271,6 +274,7 @@ def test_split_tables_cache_and_couplings(monkeypatch):
     so sets are evicted and rebuilt) and couplings changed between calls: every
     product equals the single pass on the same input (FP64)."""
     monkeypatch.setenv("DCS_SPLIT_MIN_DIM", "0")
+    monkeypatch.setenv("DCS_AUTOTUNE", "0")
     L, n = 18, 9
     s = dq.Sector(L, n, 2, [5, 4, 5, 4])
     rng = np.random.default_rng(11)
@@ -288,3 +292,31 @@ def test_split_tables_cache_and_couplings(monkeypatch):
                 y_one = dq.hamiltonian_apply(s, t, jxy, jz, x, h=h)
                 assert rel_err(y_split.cpu().numpy(), y_one.cpu().numpy()) <= 1e-12, rep
     monkeypatch.delenv("DCS_SPLIT", raising=False)
+
+
+@pytest.mark.parametrize("k,dt", [(1, torch.float32), (8, torch.float32), (1, torch.float64)])
+def test_autotuned_form(monkeypatch, k, dt):
+    """With the autotuner on, the first product of a (terms, dtype, k) times the launch
+    forms and returns the fastest one's Y: it matches the oracle, and later calls are
+    bitwise equal to it; each form on its own also matches the oracle."""
+    monkeypatch.setenv("DCS_SPLIT_MIN_DIM", "0")
+    L, n, sp = 20, 10, [5, 5, 5, 5]
+    s = dq.Sector(L, n, 2, sp)
+    bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.5, 1.0)
+    t = dq.Terms(bonds)
+    x = synth.vector(s.dim, synth.SEED_X, k=k)
+    y_ref = native.hx_range(native.NativeSector(2, L, n, sp), native.NativeTerms(bonds, jxy, jz), x)
+    xd = torch.tensor(x, device=DEV).to(dt)
+    monkeypatch.delenv("DCS_AUTOTUNE", raising=False)
+    y1 = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), xd)
+    y2 = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), xd)
+    assert torch.equal(y1, y2)
+    assert rel_err(y1.double().cpu().numpy(), y_ref) <= TOL[dt]
+    monkeypatch.setenv("DCS_AUTOTUNE", "0")
+    for env in ({"DCS_SPLIT_LDS": "1"}, {"DCS_SPLIT_LDS": "0"}, {"DCS_SPLIT": "0"}):
+        for key in ("DCS_SPLIT", "DCS_SPLIT_LDS"):
+            monkeypatch.delenv(key, raising=False)
+        for key, v in env.items():
+            monkeypatch.setenv(key, v)
+        y = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), xd)
+        assert rel_err(y.double().cpu().numpy(), y_ref) <= TOL[dt], env

@@ -162,6 +162,7 @@ def test_captured_steps_match_eager(monkeypatch, split_view, reorth, dt):
     repeated with eager products in between (single pass and split product)."""
     if split_view:
         monkeypatch.setenv("DCS_SPLIT_MIN_DIM", "0")
+        monkeypatch.setenv("DCS_AUTOTUNE", "0")
     L, n = 20, 10
     s = dq.Sector(L, n, 2, [5, 5, 5, 5])
     bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.3, 0.8)
