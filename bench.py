@@ -196,6 +196,46 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
     return out
 
 
+def split_sweep(dq, synth, torch, steps: int, warmup: int):
+    """Rank, unrank and FP32 H*x throughput on the L=32, n=16 sector versus the number
+    of subsystems (most-equal splits, shorter parts first): the paper's question of
+    the best split, asked of the GPU kernels.  Splits whose tables exceed on-chip
+    memory are reported as unsupported."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    cnt = 1 << 24
+    g = torch.Generator(device=dev)
+    g.manual_seed(synth.SEED_X)
+    occ = torch.rand((cnt, L), generator=g, device=dev).argsort(dim=1)[:, :N_UP]
+    states = (torch.ones(cnt, N_UP, dtype=torch.int64, device=dev) << (L - 1 - occ)).sum(dim=1)
+    del occ
+    bonds, jxy, jz = synth.j1j2_chain(L, J1, J2, DELTA)
+    jd, zd = torch.tensor(jxy, device=dev), torch.tensor(jz, device=dev)
+    x = torch.randn(601080390, generator=g, device=dev, dtype=torch.float32)
+    y = torch.empty_like(x)
+    out = {}
+    for nsub in (2, 3, 4, 5, 6, 7, 8):
+        sizes = [L // nsub + (1 if i >= nsub - L % nsub else 0) for i in range(nsub)]
+        key = "/".join(map(str, sizes))
+        try:
+            s = dq.Sector(L, N_UP, 2, sizes, device=0)
+        except Exception as e:  # tables beyond the on-chip budget
+            out[key] = {"supported": False, "reason": str(e).splitlines()[0][:160]}
+            continue
+        idx = torch.empty_like(states)
+        back = torch.empty_like(states)
+        per_r = time_variant(lambda: s.rank(states, out=idx), stream, steps, warmup) / steps
+        per_u = time_variant(lambda: s.unrank(idx, out=back), stream, steps, warmup) / steps
+        ok = bool(torch.equal(back, states))
+        t = dq.Terms(bonds)
+        per_h = time_variant(lambda: dq.hamiltonian_apply(s, t, jd, zd, x, out=y), stream,
+                             max(2, steps // 4), 1) / max(2, steps // 4)
+        out[key] = {"supported": True, "rank_per_s": cnt / per_r, "unrank_per_s": cnt / per_u,
+                    "roundtrip_ok": ok, "hx_f32k1_ms": per_h * 1e3, "hx_states_per_s": s.dim / per_h}
+        del idx, back, s, t
+    return out
+
+
 def cpu_baseline(x_host, target_s: float = 15.0):
     """The FP64 C oracle (OpenMP over contiguous row blocks, as the paper's
     workers) timed on a contiguous block of rows from the middle of the sector."""
@@ -231,6 +271,8 @@ def main(argv=None) -> int:
                     help="comma list; the first is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="time the headline product only")
+    ap.add_argument("--split-sweep", action="store_true",
+                    help="also time rank, unrank and H*x versus the number of subsystems")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also time a plain device copy of the FP32 vector size (the reference "
                          "kernel for scaling the HBM byte counters)")
@@ -326,6 +368,8 @@ def main(argv=None) -> int:
         out["speedup_vs_plain_f64_per_column"] = r["states_per_s"] / results["f64k1"]["states_per_s"]
     if not args.no_extras:
         out["workloads"] = extra_workloads(dq, synth, torch, args.steps, args.warmup)
+    if args.split_sweep:
+        out["split_sweep"] = split_sweep(dq, synth, torch, args.steps, args.warmup)
     if x_host is not None:
         out["cpu_baseline"] = cpu_baseline(x_host)
     print(json.dumps(out), flush=True)
