@@ -228,7 +228,10 @@ int dcs_hamiltonian_apply_adjoint(const dcs_sector *sector, const dcs_terms *ter
  * single persistent launch.  Sector s uses terms[s] with couplings
  * d_jxy[s], d_jz[s] (device FP64 arrays; the pointers are recorded, the
  * values are read at apply time).  The sectors may differ in L, n, Q and
- * split.  The plan does not own the sectors or terms; they must outlive it.
+ * split.  Sectors that have a split view (Q = 2, see "Split product") are
+ * left out of the launch and run their own split product after it, on the
+ * same stream.  The plan does not own the sectors or terms; they must
+ * outlive it.
  */
 int dcs_plan_create(int num_sectors, dcs_sector *const *sectors, dcs_terms *const *terms,
                     const double *const *d_jxy, const double *const *d_jz, dcs_plan **out);

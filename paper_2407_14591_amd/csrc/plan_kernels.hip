@@ -99,6 +99,14 @@ struct dcs_plan {
     hipEvent_t io_copied = nullptr;
     bool io_pending = false;
     std::vector<uint64_t> dims;
+    // sectors with a split view run their own split product after the launch
+    struct Own {
+        int index;
+        dcs_sector *sector;
+        const dcs_terms *terms;
+        const double *jxy, *jz;
+    };
+    std::vector<Own> own;
 };
 
 static void plan_free(dcs_plan *p) {
@@ -153,6 +161,7 @@ extern "C" int dcs_plan_create(int nsec, dcs_sector *const *secs, dcs_terms *con
         ps.far_below = 0;
         for (int c = 0; c <= bp.nclasses; ++c) ps.cls_beg[c] = bp.cls_beg[c];
         for (int b = 0; b < bp.nbonds; ++b) ps.pos[b] = bp.pos[b];
+        if (secs[s]->left.K > 0 && secs[s]->desc.Q == 2) continue;  // split product of its own
         for (uint64_t r0 = 0; r0 < ps.sd.dim; r0 += kHxThreads) tiles.push_back(make_uint2(s, (uint32_t)r0));
     }
     dcs_plan *p = new (std::nothrow) dcs_plan();
@@ -162,17 +171,22 @@ extern "C" int dcs_plan_create(int nsec, dcs_sector *const *secs, dcs_terms *con
     p->nmax = nmax;
     p->ntiles = (uint32_t)tiles.size();
     p->lds_bytes = lds;
-    for (int s = 0; s < nsec; ++s) p->dims.push_back(secs[s]->desc.dim);
+    for (int s = 0; s < nsec; ++s) {
+        p->dims.push_back(secs[s]->desc.dim);
+        if (secs[s]->left.K > 0 && secs[s]->desc.Q == 2)
+            p->own.push_back(dcs_plan::Own{s, secs[s], terms[s], jxy[s], jz[s]});
+    }
     DeviceGuard g(device);
     int r = check_hip(hipMalloc(&p->d_secs, nsec * sizeof(PlanSector)), "hipMalloc plan");
     if (!r) r = check_hip(hipMalloc(&p->d_io, nsec * sizeof(PlanIO)), "hipMalloc plan io");
-    if (!r) r = check_hip(hipMalloc(&p->d_tiles, tiles.size() * sizeof(uint2)), "hipMalloc tiles");
+    if (!r) r = check_hip(hipMalloc(&p->d_tiles, std::max<size_t>(tiles.size(), 1) * sizeof(uint2)),
+                          "hipMalloc tiles");
     if (!r) r = check_hip(hipHostMalloc(&p->h_io, nsec * sizeof(PlanIO)), "hipHostMalloc");
     if (!r) r = check_hip(hipEventCreateWithFlags(&p->io_copied, hipEventDisableTiming), "event");
     if (!r)
         r = check_hip(hipMemcpy(p->d_secs, hs.data(), nsec * sizeof(PlanSector), hipMemcpyHostToDevice),
                       "copy plan");
-    if (!r)
+    if (!r && !tiles.empty())
         r = check_hip(hipMemcpy(p->d_tiles, tiles.data(), tiles.size() * sizeof(uint2),
                                 hipMemcpyHostToDevice),
                       "copy tiles");
@@ -239,7 +253,14 @@ extern "C" int dcs_plan_apply(const dcs_plan *pc, int dtype, const void *const *
         return r;
     if (int r = check_hip(hipEventRecord(p->io_copied, stream), "record plan io event")) return r;
     p->io_pending = true;
-    if (dtype == DCS_F32)
-        return p->nmax == 4 ? launch_plan<float, 4>(p, stream) : launch_plan<float, 8>(p, stream);
-    return p->nmax == 4 ? launch_plan<double, 4>(p, stream) : launch_plan<double, 8>(p, stream);
+    if (p->ntiles > 0) {
+        const int r = dtype == DCS_F32
+                          ? (p->nmax == 4 ? launch_plan<float, 4>(p, stream) : launch_plan<float, 8>(p, stream))
+                          : (p->nmax == 4 ? launch_plan<double, 4>(p, stream) : launch_plan<double, 8>(p, stream));
+        if (r) return r;
+    }
+    for (const auto &o : p->own)
+        if (int r = launch_hx(o.sector, o.terms, o.jxy, o.jz, nullptr, dtype, 1, xs[o.index], ys[o.index], stream))
+            return r;
+    return DCS_OK;
 }

@@ -84,3 +84,34 @@ def test_batched_workload_one_launch(monkeypatch):
         got = y[torch.tensor(rows.astype(np.int64), device=DEV)].double().cpu().numpy()
         say("plan sector", Q, L, n, rel_err(got, ref))
         assert rel_err(got, ref) <= 1e-5
+
+
+def test_batched_workload_with_split_sectors():
+    """The batched workload with the default split threshold: the seven L=26 sectors of
+    at least 2^22 states run their own split product after the one launch; every
+    sector's y equals its own product bit for bit, and sampled rows match the oracle."""
+    specs = batched_workload()
+    items, xs = [], []
+    for Q, L, n in specs:
+        bonds, jxy, jz = synth.xxz_chain(L, 1.0, 1.0)
+        s = dq.Sector(L, n, Q)
+        items.append((s, dq.Terms(bonds), dev_f64(jxy), dev_f64(jz)))
+        g = torch.Generator(device=DEV)
+        g.manual_seed(7 * L + n + Q)
+        xs.append(torch.randn(s.dim, generator=g, device=DEV, dtype=torch.float32))
+    plan = dq.Plan(items)
+    ys = plan.apply(xs)
+    ys2 = plan.apply(xs)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    for idx, ((s, t, j, z), x, y, y2) in enumerate(zip(items, xs, ys, ys2)):
+        assert torch.equal(y, y2)
+        assert torch.equal(y, dq.hamiltonian_apply(s, t, j, z, x)), specs[idx]
+        Q, L, n = specs[idx]
+        if s.dim >= (1 << 22):
+            bonds, jxy, jz = synth.xxz_chain(L, 1.0, 1.0)
+            ns = native.NativeSector(Q, L, n, s.split)
+            rows = rng.integers(0, s.dim, 20000).astype(np.uint64)
+            ref = native.hx_rows(ns, native.NativeTerms(bonds, jxy, jz), x.cpu().numpy(), rows)
+            got = y[torch.tensor(rows.astype(np.int64), device=DEV)].double().cpu().numpy()
+            assert rel_err(got, ref) <= 1e-5, specs[idx]
