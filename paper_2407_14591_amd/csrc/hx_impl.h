@@ -49,6 +49,7 @@ struct HxParams {
     int far_below;           // classes (a, b) with a < far_below gather non-temporally
     int nbonds;
     int xcd_groups;          // workgroups per XCD when the grid is a multiple of 8, else 0
+    int want_fields;         // adjoint: accumulate the field gradients
     uint16_t cls_beg[kMaxClasses + 1];
     uint32_t pos[kMaxBonds];
 };
@@ -558,11 +559,15 @@ __global__ __launch_bounds__(kHxThreads) void adjoint_kernel(const HxParams P) {
         AdjLoop<IdxT, T, NMAX, Q2, 0, 0>::run(P, sd, Tb, r, row, x, g, xr, grow, bamp, bjz, ladder,
                                               wacc, hg, diag);
         const uint32_t dm = (1u << sd.nb) - 1u;
-        for (int i = 0; i < sd.L; ++i) {
-            const T mzi = ladder[32 + (int)((r.s >> (sd.nb * (sd.L - 1 - i))) & dm)];
-            if (P.h) diag += hf[i] * mzi;
-            const double v = wave_sum((double)grow * (double)mzi * (double)xr);
-            if (lane == 0) wacc[2 * P.nbonds + i] += v;
+        if (P.h || P.want_fields) {
+            for (int i = 0; i < sd.L; ++i) {
+                const T mzi = ladder[32 + (int)((r.s >> (sd.nb * (sd.L - 1 - i))) & dm)];
+                if (P.h) diag += hf[i] * mzi;
+                if (P.want_fields) {  // uniform: one cross-lane sum per site only when asked for
+                    const double v = wave_sum((double)grow * (double)mzi * (double)xr);
+                    if (lane == 0) wacc[2 * P.nbonds + i] += v;
+                }
+            }
         }
         if (active && gx) gx[row] = hg + diag * g[row];
     }
@@ -681,6 +686,7 @@ int launch_adj_t(const dcs_sector *s, HxParams &P, double *gjxy, double *gjz, do
     const Grid g = plan_grid(s, lds_plan);
     P.tiles = g.tiles;
     P.xcd_groups = g.xcd_groups;
+    P.want_fields = gh != nullptr;
     if (s->desc.Q == 2) {
         auto kern = adjoint_kernel<IdxT, T, NMAX, true>;
         if (int r = ensure_lds(kern, lds)) return r;
