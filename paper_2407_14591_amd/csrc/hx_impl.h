@@ -425,10 +425,29 @@ __global__ __launch_bounds__(kHxThreads) void hx_kernel(const HxParams P) {
 
 // ---------------------------------------------------------------- adjoint
 
+// Sum over the 64 lanes of a wave (all lanes active), returned in every lane:
+// row shifts by 1, 2, 4, 8 leave each 16-lane row's sum in its last lane, two
+// row broadcasts carry it to lane 63, which is read back.  VALU data-parallel
+// moves only, in a fixed order (deterministic).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_move<0x111, 0xF>(v);  // row_shr:1
+    v += dpp_move<0x112, 0xF>(v);  // row_shr:2
+    v += dpp_move<0x114, 0xF>(v);  // row_shr:4
+    v += dpp_move<0x118, 0xF>(v);  // row_shr:8
+    v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 template <typename IdxT, typename T, int NMAX, bool Q2, int A, int B>
