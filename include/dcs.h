@@ -31,7 +31,7 @@
  *    their kernels with 32-bit index arithmetic; larger ones with 64-bit.  The
  *    environment variable DCS_INDEX_BITS=64, read by dcs_sector_create, forces
  *    64-bit arithmetic (to test those kernels on small sectors).
- *  - Split product: for Q = 2 sectors with at least 2^22 states and two or
+ *  - Split product: for Q = 2 sectors with at least 2^20 states and two or
  *    more subsystems, dcs_sector_create also builds a left/right view (cut after
  *    N/2 subsystems: every left configuration owns a contiguous run of rows, one
  *    per right configuration).  The first dcs_hamiltonian_apply with a terms
@@ -40,7 +40,7 @@
  *    product runs three kernels: the diagonal per configuration of each side,
  *    one pass over the rows for the bonds right of and across the cut, and one
  *    over column chunks for the bonds left of it.  DCS_SPLIT_MIN_DIM (read by
- *    dcs_sector_create) changes the 2^22 threshold; DCS_SPLIT=0 (read at every
+ *    dcs_sector_create) changes the 2^20 threshold; DCS_SPLIT=0 (read at every
  *    product) forces the single pass; DCS_SPLIT_LDS=0 (likewise) keeps the row
  *    pass from staging runs of x in on-chip memory.
  */

@@ -192,7 +192,7 @@ int upload(dcs_sector *s, HostTables<IdxT> &ht) {
 // Left configurations of the split product (see LeftInfo): for every left
 // particle number m, the configurations (w_0..w_{K-1}) with digit sum m in
 // canonical order, with the first row of their run, sum_k C_k[lambda_k][w_k].
-constexpr uint64_t kSplitMinDim = 1ull << 22;
+constexpr uint64_t kSplitMinDim = 1ull << 20;
 constexpr size_t kMaxLeftConfigs = 1u << 22;
 
 template <typename IdxT>

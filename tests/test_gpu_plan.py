@@ -87,9 +87,10 @@ def test_batched_workload_one_launch(monkeypatch):
 
 
 def test_batched_workload_with_split_sectors():
-    """The batched workload with the default split threshold: the seven L=26 sectors of
-    at least 2^22 states run their own split product after the one launch; every
-    sector's y equals its own product bit for bit, and sampled rows match the oracle."""
+    """The batched workload with the default split threshold: the sectors of at least
+    2^20 states run their own split product after the one launch; every sector's y
+    equals its own product bit for bit, and sampled rows of those sectors match the
+    oracle."""
     specs = batched_workload()
     items, xs = [], []
     for Q, L, n in specs:
@@ -108,7 +109,7 @@ def test_batched_workload_with_split_sectors():
         assert torch.equal(y, y2)
         assert torch.equal(y, dq.hamiltonian_apply(s, t, j, z, x)), specs[idx]
         Q, L, n = specs[idx]
-        if s.dim >= (1 << 22):
+        if s.dim >= (1 << 20):
             bonds, jxy, jz = synth.xxz_chain(L, 1.0, 1.0)
             ns = native.NativeSector(Q, L, n, s.split)
             rows = rng.integers(0, s.dim, 20000).astype(np.uint64)
