@@ -18,7 +18,7 @@ namespace dcs {
 namespace {
 
 constexpr int kVecThreads = 256;
-constexpr int kMaxVecBlocks = 1024;
+constexpr int kMaxVecBlocks = 2048;
 constexpr int kReduceThreads = 256;
 constexpr double kBreakdownTol = 1e-12;
 
@@ -35,6 +35,17 @@ struct LzState {
 template <typename T>
 __device__ __forceinline__ double ld(const T *p, uint64_t i) {
     return (double)p[i];
+}
+
+// 16-byte vector of T and a test that a pointer allows it.
+template <typename T>
+struct V16 {
+    static constexpr int N = 16 / sizeof(T);
+    typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
+};
+
+__device__ __forceinline__ bool aligned16(const void *p) {
+    return ((uintptr_t)p & 15u) == 0;
 }
 
 // Block-level sum of `v` into slot `slot` of this block's partial row.
@@ -219,8 +230,31 @@ __global__ __launch_bounds__(kVecThreads) void k_gram(const T *__restrict__ w, c
                                                       double *partials, const LzState *st) {
     if (st->done) return;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t g0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t head = 0;  // elements done by the 16-byte loop
+    if (aligned16(w) && aligned16(uj) && (!ujm1 || aligned16(ujm1))) {
+        constexpr int N = V16<T>::N;
+        typedef typename V16<T>::type vt;
+        const uint64_t nv = n / N;
+        for (uint64_t i = g0; i < nv; i += stride) {
+            const vt wv = reinterpret_cast<const vt *>(w)[i], av = reinterpret_cast<const vt *>(uj)[i];
+            if (ujm1) {
+                const vt bv = reinterpret_cast<const vt *>(ujm1)[i];
+#pragma unroll
+                for (int e = 0; e < N; ++e) {
+                    s0 += (double)av[e] * (double)wv[e];
+                    s1 += (double)bv[e] * (double)wv[e];
+                    s2 += (double)av[e] * (double)bv[e];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < N; ++e) s0 += (double)av[e] * (double)wv[e];
+            }
+        }
+        head = nv * N;
+    }
+    for (uint64_t i = head + g0; i < n; i += stride) {
         const double wi = ld(w, i), a = ld(uj, i);
         s0 += a * wi;
         if (ujm1) {
@@ -275,8 +309,29 @@ __global__ __launch_bounds__(kVecThreads) void k_lz_update(const T *__restrict__
     const double *c = rec + 3 * (st ? st->j : j);
     const double sw = c[0], A = c[1], B = c[2];
     double s = 0.0;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t g0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t head = 0;
+    if (aligned16(w) && aligned16(uj) && (!ujm1 || aligned16(ujm1)) && aligned16(out)) {
+        constexpr int N = V16<T>::N;
+        typedef typename V16<T>::type vt;
+        const uint64_t nv = n / N;
+        for (uint64_t i = g0; i < nv; i += stride) {
+            const vt wv = reinterpret_cast<const vt *>(w)[i], av = reinterpret_cast<const vt *>(uj)[i];
+            vt bv = (vt)(T)0;
+            if (ujm1) bv = reinterpret_cast<const vt *>(ujm1)[i];
+            vt ov;
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                const T vte = (T)(sw * (double)wv[e] - B * (double)av[e] - A * (double)bv[e]);
+                ov[e] = vte;
+                s += (double)vte * (double)vte;
+            }
+            reinterpret_cast<vt *>(out)[i] = ov;  // may overwrite ujm1[i], read above by this thread
+        }
+        head = nv * N;
+    }
+    for (uint64_t i = head + g0; i < n; i += stride) {
         double v = sw * ld(w, i) - B * ld(uj, i);
         if (ujm1) v -= A * ld(ujm1, i);
         const T vt = (T)v;
@@ -448,6 +503,10 @@ int vec_blocks(uint64_t n) {
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
+// Slot stride of the two-vector ring: a multiple of 64 elements, so both slots
+// allow 16-byte vector access.
+inline uint64_t ring_stride(uint64_t n) { return (n + 63) / 64 * 64; }
+
 struct Layout {
     size_t V, w, psi_tmp, partials, alpha, beta, coef, rec, state, trid, total;
     int m, nvec;
@@ -461,11 +520,11 @@ Layout layout(const dcs_sector *s, int dtype, int steps, int reorth, int want_ve
     L.nvec = reorth == DCS_REORTH_FULL ? L.m : 2;
     size_t p = 0;
     L.V = p;
-    p = align256(p + (size_t)L.nvec * n * es);
+    p = align256(p + (size_t)L.nvec * (reorth == DCS_REORTH_FULL ? n : ring_stride(n)) * es);
     L.w = p;
     p = align256(p + n * es);
     L.psi_tmp = p;  // second-pass vectors (ring of 2) when the basis is not stored
-    if (want_vec && reorth != DCS_REORTH_FULL) p = align256(p + 2 * n * es);
+    if (want_vec && reorth != DCS_REORTH_FULL) p = align256(p + 2 * ring_stride(n) * es);
     L.partials = p;
     p = align256(p + (size_t)kMaxVecBlocks * (size_t)std::max(L.m, 2) * sizeof(double));
     L.alpha = p;
@@ -557,7 +616,7 @@ int run_lanczos(const dcs_sector *s, const dcs_terms *t, const double *jxy, cons
                                                    L.m);
         if (int r = chk("Lanczos start")) return r;
         const int local = reorth == DCS_REORTH_LOCAL ? 1 : 0;
-        T *ring0 = V, *ring1 = V + n;
+        T *ring0 = V, *ring1 = V + ring_stride(n);
         // one step; the kernels take the step index from the device state, so the
         // same launches serve every step of one parity (u_j, u_{j-1}, u_{j+1} slots)
         auto step = [&](const T *uj, const T *ujm1, T *out, hipStream_t q) -> int {
@@ -653,12 +712,12 @@ int run_lanczos(const dcs_sector *s, const dcs_terms *t, const double *jxy, cons
     } else {
         // repeat the recorded two-vector recurrence (same kernels, same vectors)
         T *R = (T *)(ws + L.psi_tmp);
-        auto rv = [&](int i) -> const T * { return i == 0 ? u0 : R + (uint64_t)(i & 1) * n; };
+        auto rv = [&](int i) -> const T * { return i == 0 ? u0 : R + (uint64_t)(i & 1) * ring_stride(n); };
         k_axpy_rec<T><<<nb, kVecThreads, 0, stream>>>(psi, rv(0), n, svec, rec, 0, 1);
         for (int j = 0; j + 1 < md; ++j) {
             if (int r = launch_hx(s, t, jxy, jz, h, dtype, 1, rv(j), w, stream)) return r;
             k_lz_update<T><<<nb, kVecThreads, 0, stream>>>(w, rv(j), j > 0 ? rv(j - 1) : nullptr,
-                                                           R + (uint64_t)((j + 1) & 1) * n, n,
+                                                           R + (uint64_t)((j + 1) & 1) * ring_stride(n), n,
                                                            rec, j, nullptr, nullptr);
             k_axpy_rec<T><<<nb, kVecThreads, 0, stream>>>(psi, rv(j + 1), n, svec, rec, j + 1, 0);
             if (int r = chk("Ritz vector replay")) return r;
