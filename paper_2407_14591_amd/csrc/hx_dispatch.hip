@@ -211,10 +211,10 @@ int launch_hx(const dcs_sector *s, const dcs_terms *t, const double *jxy, const 
     return launch_single(s, t, jxy, jz, h, dtype, k, x, y, stream);
 }
 
+// An upper bound: the adjoint's tiles of several rows per thread need at most as many
+// workgroups as tiles of one row per thread.
 size_t adjoint_ws_bytes(const dcs_sector *s, const dcs_terms *t) {
-    const size_t lds = s->desc.lay_bytes + coeff_lds_bytes<double>() +
-                       (size_t)(kHxThreads / 64) * (2 * t->num_bonds + s->desc.L) * sizeof(double);
-    const Grid g = plan_grid(s, lds);
+    const Grid g = plan_grid(s, adj_lds_bytes(s, t->num_bonds, coeff_lds_bytes<double>()));
     return (size_t)g.wgs * (2 * t->num_bonds + s->desc.L) * sizeof(double);
 }
 

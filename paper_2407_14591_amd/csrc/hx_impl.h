@@ -450,101 +450,218 @@ __device__ __forceinline__ double wave_sum(double v) {
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-template <typename IdxT, typename T, int NMAX, bool Q2, int A, int B>
+// Rows per lane of the adjoint: each lane carries R rows (R tiles of 64 rows
+// per wave), so every cross-lane sum covers 64 * R rows.  One row per lane
+// keeps the registers (and the occupancy) of the forward pass.
+template <typename IdxT, int NMAX>
+constexpr int adj_rows() {
+    return 1;
+}
+
+// Bonds per batch of the adjoint's Q = 2 path (2 sums per bond: 8 or 16 values).
+template <int R>
+constexpr int adj_batch() {
+    return 4;
+}
+
+template <typename IdxT, typename T, int NMAX, int R>
+struct AdjRows {
+    RowState<IdxT, NMAX> r[R];
+    IdxT row[R];
+    T xr[R], grow[R], hg[R], diag[R];
+};
+
+// Row sums of N = 8 or 16 values at once.  Each step pairs every lane with a
+// lane of the same 16-lane row that holds the same subset of the values (row
+// mirror, half-row mirror, quad mirror); the lane keeps one half of the subset,
+// adds its partner's copy of that half and hands over the other half.  After
+// log2(N) steps lane i of each row holds the sum over 16 / N * ... lanes of
+// v[(i & 15) >> (16 / N - 1)]; a last plain step (N = 8) completes the row.
+// About 4 moves and one add per value replace a separate cross-lane sum per
+// value; fixed order (deterministic).
+template <int N, int H, int CTRL>
+__device__ __forceinline__ void half_step(double (&v)[N], bool upper) {
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const double lo = v[k], hi = v[k + H];
+        const double keep = upper ? hi : lo, send = upper ? lo : hi;
+        v[k] = keep + dpp_move<CTRL, 0xF>(send);
+    }
+}
+
+template <int N>
+__device__ __forceinline__ double row_transpose_sum(double (&v)[N]) {
+    static_assert(N == 8 || N == 16, "8 or 16 values");
+    const int l = threadIdx.x & 15;
+    if constexpr (N == 16) {
+        half_step<N, 8, 0x140>(v, l & 8);  // row_mirror: i <-> 15 - i
+        half_step<N, 4, 0x141>(v, l & 4);  // row_half_mirror: i <-> 7 - i in each half row
+        half_step<N, 2, 0x1B>(v, l & 2);   // quad_perm [3,2,1,0]
+        half_step<N, 1, 0xB1>(v, l & 1);   // quad_perm [1,0,3,2]
+    } else {
+        half_step<N, 4, 0x140>(v, l & 8);
+        half_step<N, 2, 0x141>(v, l & 4);
+        half_step<N, 1, 0x1B>(v, l & 2);
+        v[0] += dpp_move<0xB1, 0xF>(v[0]);  // lanes i and i ^ 1 hold the same value
+    }
+    return v[0];
+}
+
+// Wave totals of v[0..N): lane i < 16 holds the total of v[i >> (16 / N - 1)]
+// (fixed order, the same bits in both lanes of every pair).
+template <int N>
+__device__ __forceinline__ double wave_transpose_sum(double (&v)[N]) {
+    double s = row_transpose_sum<N>(v);
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    return s;
+}
+
+// Adds to a wave's accumulator in LDS; every slot has one writing lane for the
+// whole launch, so the order of the additions is fixed.
+__device__ __forceinline__ void lds_add(double *p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// One bond class (A, B) of the adjoint for the R rows of every lane.  For Q = 2
+// the bonds go in batches of 8: every column of the batch, the gathers of g and
+// x, then the 16 bond sums of the batch in one transposed row sum.
+template <typename IdxT, typename T, int NMAX, bool Q2, int A, int B, int R>
 __device__ __forceinline__ void adjoint_class(const HxParams &P, const SectorDesc &sd,
                                               const Tables<IdxT> &Tb,
-                                              const RowState<IdxT, NMAX> &r, IdxT row,
                                               const T *__restrict__ x, const T *__restrict__ g,
-                                              T xr, T grow, const T *bamp, const T *bjz,
-                                              const T *ladder, double *wacc, T &hg, T &diag) {
+                                              const T *bamp, const T *bjz, const T *ladder,
+                                              const int *borig, double *wacc,
+                                              AdjRows<IdxT, T, NMAX, R> &W) {
     const int cls = A * NMAX - A * (A - 1) / 2 + (B - A);
     const int beg = P.cls_beg[cls], end = P.cls_beg[cls + 1];
     const int lane = threadIdx.x & 63;
-    for (int t = beg; t < end; ++t) {
-        const uint32_t pos = P.pos[t];
-        const uint32_t pil = pos & 0xFFu, pjl = (pos >> 8) & 0xFFu;
-        T hop_x = (T)0;  // sum over hops of (ladder factors / 2) * x[col]
-        T zz;
-        if constexpr (Q2) {
-            const uint32_t bi = (r.w[A] >> pil) & 1u, bj = (r.w[B] >> pjl) & 1u;
-            zz = (bi == bj) ? (T)0.25 : (T)-0.25;
-            if (bi != bj) {
-                IdxT col;
-                if constexpr (A == B)
-                    col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, r.w[A] ^ ((1u << pil) | (1u << pjl)), 0, 0);
-                else
-                    col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, r.w[A] ^ (1u << pil),
-                                                    r.w[B] ^ (1u << pjl), bi ? -1 : 1);
-                hg += bamp[t] * g[col];
-                hop_x = (T)0.5 * x[col];
+    if constexpr (Q2) {
+        constexpr int NB = adj_batch<R>();
+        constexpr int SH = NB == 8 ? 0 : 1;  // lane of value j: j << SH
+        for (int t = beg; t < end; t += NB) {
+            double val[2 * NB];
+#pragma unroll
+            for (int v = 0; v < 2 * NB; ++v) val[v] = 0.0;
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                IdxT c[NB];
+                T amp[NB];
+#pragma unroll
+                for (int v = 0; v < NB; ++v) {
+                    if (t + v < end) {  // uniform
+                        // diagonal into diag; the column is the row itself for a non-hop
+                        c[v] = q2_bond<IdxT, T, NMAX, A, B>(P, sd, Tb, W.r[u], W.row[u], t + v, bamp,
+                                                            bjz, amp[v], W.diag[u]);
+                    } else {
+                        c[v] = W.row[u];
+                        amp[v] = (T)0;
+                    }
+                }
+                T gv[NB], xv[NB];
+#pragma unroll
+                for (int v = 0; v < NB; ++v) {
+                    gv[v] = g[c[v]];
+                    xv[v] = x[c[v]];
+                }
+                const double p = (double)W.grow[u] * (double)W.xr[u];
+#pragma unroll
+                for (int v = 0; v < NB; ++v) {
+                    const bool hop = c[v] != W.row[u];
+                    W.hg[u] += amp[v] * gv[v];
+                    if (t + v < end) {
+                        val[2 * v] += hop ? (double)W.grow[u] * (double)((T)0.5 * xv[v]) : 0.0;
+                        val[2 * v + 1] += hop ? -0.25 * p : 0.25 * p;
+                    }
+                }
             }
-        } else {
-            const uint32_t dm = (1u << sd.nb) - 1u;
-            const int Qm1 = sd.Q - 1;
-            const int di = (int)((r.w[A] >> pil) & dm), dj = (int)((r.w[B] >> pjl) & dm);
-            const T *up = ladder, *dn = ladder + 16, *mz = ladder + 32;
-            zz = mz[di] * mz[dj];
-            if (di < Qm1 && dj > 0) {
-                const uint32_t wa = r.w[A] + (1u << pil);
-                IdxT col;
-                if constexpr (A == B)
-                    col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa - (1u << pjl), 0, 0);
-                else
-                    col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa, r.w[B] - (1u << pjl), 1);
-                const T f = (T)0.5 * up[di] * dn[dj];
-                hg += (T)2 * bamp[t] * f * g[col];
-                hop_x += f * x[col];
-            }
-            if (di > 0 && dj < Qm1) {
-                const uint32_t wa = r.w[A] - (1u << pil);
-                IdxT col;
-                if constexpr (A == B)
-                    col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa + (1u << pjl), 0, 0);
-                else
-                    col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa, r.w[B] + (1u << pjl), -1);
-                const T f = (T)0.5 * dn[di] * up[dj];
-                hg += (T)2 * bamp[t] * f * g[col];
-                hop_x += f * x[col];
-            }
+            // value 2v + k (k = 0: jxy, 1: jz) of bond t + v ends in lane (2v + k) << SH
+            const double sum = wave_transpose_sum<2 * NB>(val);
+            const int j = lane >> SH, vi = j >> 1;
+            if (lane < 16 && (lane & ((1 << SH) - 1)) == 0 && t + vi < end)
+                lds_add(wacc + 2 * borig[t + vi] + (j & 1), sum);
         }
-        diag += (Q2 ? (T)4 : (T)1) * bjz[t] * zz;
-        const double vxy = wave_sum((double)grow * (double)hop_x);
-        const double vz = wave_sum((double)grow * (double)zz * (double)xr);
-        if (lane == 0) {
-            const int orig = (int)(pos >> 16);
-            wacc[2 * orig] += vxy;
-            wacc[2 * orig + 1] += vz;
+    } else {
+        for (int t = beg; t < end; ++t) {
+            const uint32_t pos = P.pos[t];
+            const uint32_t pil = pos & 0xFFu, pjl = (pos >> 8) & 0xFFu;
+            double sxy = 0.0, sz = 0.0;  // this lane's share of the bond's two sums
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                const RowState<IdxT, NMAX> &r = W.r[u];
+                const IdxT row = W.row[u];
+                const uint32_t dm = (1u << sd.nb) - 1u;
+                const int Qm1 = sd.Q - 1;
+                const int di = (int)((r.w[A] >> pil) & dm), dj = (int)((r.w[B] >> pjl) & dm);
+                const T *up = ladder, *dn = ladder + 16, *mz = ladder + 32;
+                const T zz = mz[di] * mz[dj];
+                T hop_x = (T)0;  // sum over hops of (ladder factors / 2) * x[col]
+                if (di < Qm1 && dj > 0) {
+                    const uint32_t wa = r.w[A] + (1u << pil);
+                    IdxT col;
+                    if constexpr (A == B)
+                        col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa - (1u << pjl), 0, 0);
+                    else
+                        col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa, r.w[B] - (1u << pjl), 1);
+                    const T f = (T)0.5 * up[di] * dn[dj];
+                    W.hg[u] += (T)2 * bamp[t] * f * g[col];
+                    hop_x += f * x[col];
+                }
+                if (di > 0 && dj < Qm1) {
+                    const uint32_t wa = r.w[A] - (1u << pil);
+                    IdxT col;
+                    if constexpr (A == B)
+                        col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa + (1u << pjl), 0, 0);
+                    else
+                        col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa, r.w[B] + (1u << pjl), -1);
+                    const T f = (T)0.5 * dn[di] * up[dj];
+                    W.hg[u] += (T)2 * bamp[t] * f * g[col];
+                    hop_x += f * x[col];
+                }
+                W.diag[u] += bjz[t] * zz;
+                sxy += (double)W.grow[u] * (double)hop_x;
+                sz += (double)W.grow[u] * (double)zz * (double)W.xr[u];
+            }
+            const double vxy = wave_sum(sxy);
+            const double vz = wave_sum(sz);
+            if (lane == 0) {
+                const int orig = (int)(pos >> 16);
+                wacc[2 * orig] += vxy;
+                wacc[2 * orig + 1] += vz;
+            }
         }
     }
 }
 
-template <typename IdxT, typename T, int NMAX, bool Q2, int A, int B>
+template <typename IdxT, typename T, int NMAX, bool Q2, int A, int B, int R>
 struct AdjLoop {
     __device__ __forceinline__ static void run(const HxParams &P, const SectorDesc &sd,
                                                const Tables<IdxT> &Tb,
-                                               const RowState<IdxT, NMAX> &r, IdxT row,
                                                const T *__restrict__ x, const T *__restrict__ g,
-                                               T xr, T grow, const T *bamp, const T *bjz,
-                                               const T *ladder, double *wacc, T &hg, T &diag) {
+                                               const T *bamp, const T *bjz, const T *ladder,
+                                               const int *borig, double *wacc,
+                                               AdjRows<IdxT, T, NMAX, R> &W) {
         if constexpr (A < NMAX) {
             if constexpr (B < NMAX) {
                 if (B < sd.N)
-                    adjoint_class<IdxT, T, NMAX, Q2, A, B>(P, sd, Tb, r, row, x, g, xr, grow, bamp,
-                                                           bjz, ladder, wacc, hg, diag);
-                AdjLoop<IdxT, T, NMAX, Q2, A, B + 1>::run(P, sd, Tb, r, row, x, g, xr, grow, bamp,
-                                                          bjz, ladder, wacc, hg, diag);
+                    adjoint_class<IdxT, T, NMAX, Q2, A, B, R>(P, sd, Tb, x, g, bamp, bjz, ladder,
+                                                              borig, wacc, W);
+                AdjLoop<IdxT, T, NMAX, Q2, A, B + 1, R>::run(P, sd, Tb, x, g, bamp, bjz, ladder,
+                                                             borig, wacc, W);
             } else {
-                AdjLoop<IdxT, T, NMAX, Q2, A + 1, A + 1>::run(P, sd, Tb, r, row, x, g, xr, grow,
-                                                              bamp, bjz, ladder, wacc, hg, diag);
+                AdjLoop<IdxT, T, NMAX, Q2, A + 1, A + 1, R>::run(P, sd, Tb, x, g, bamp, bjz,
+                                                                 ladder, borig, wacc, W);
             }
         }
     }
 };
 
-// Each wave keeps its bond sums in its own LDS slice (one writer per slice),
-// then the workgroup adds the slices in wave order and writes one partial row.
+// Each wave keeps its bond and field sums in its own LDS slice, then the
+// workgroup adds the slices in wave order and writes one partial row.  A tile is
+// kHxThreads * R rows; wave w takes R consecutive 64-row pieces of it.
 template <typename IdxT, typename T, int NMAX, bool Q2>
 __global__ __launch_bounds__(kHxThreads) void adjoint_kernel(const HxParams P) {
+    constexpr int R = adj_rows<IdxT, NMAX>();
     extern __shared__ __align__(16) char lds[];
     const SectorDesc &sd = P.sd;
     stage_blob(lds, P.blob, sd.lay_bytes);
@@ -555,8 +672,10 @@ __global__ __launch_bounds__(kHxThreads) void adjoint_kernel(const HxParams P) {
     double *wacc_all = reinterpret_cast<double *>(hf + kMaxSites);
     const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nacc = 2 * P.nbonds + sd.L;
+    int *borig = reinterpret_cast<int *>(wacc_all + nw * nacc);  // bond of each plan slot
     stage_coefficients<T, Q2>(P, sd, bamp, bjz, ladder, hf);
     for (int i = threadIdx.x; i < nw * nacc; i += blockDim.x) wacc_all[i] = 0.0;
+    for (int t = threadIdx.x; t < P.nbonds; t += blockDim.x) borig[t] = (int)(P.pos[t] >> 16);
     __syncthreads();
     double *wacc = wacc_all + wave * nacc;
     const Tables<IdxT> Tb = tables_at<IdxT>(lds, sd);
@@ -565,55 +684,89 @@ __global__ __launch_bounds__(kHxThreads) void adjoint_kernel(const HxParams P) {
     T *__restrict__ gx = reinterpret_cast<T *>(P.gx);
 
     for (TileIter it = my_tiles(P.tiles, P.xcd_groups); it.tile() < it.tiles; ++it.m) {
-        const uint64_t tile = it.tile() * kHxThreads + (uint64_t)wave * 64;
-        if (tile >= sd.dim) continue;
-        const uint64_t row64 = tile + lane;
-        const bool active = row64 < sd.dim;
-        const IdxT row = (IdxT)(active ? row64 : tile);
-        RowState<IdxT, NMAX> r;
-        decode_row<IdxT, NMAX>(sd, Tb, row, r);
-        const T xr = x[row];
-        const T grow = active ? g[row] : (T)0;  // inactive lanes add nothing to the bond sums
-        T hg = (T)0, diag = (T)0;
-        AdjLoop<IdxT, T, NMAX, Q2, 0, 0>::run(P, sd, Tb, r, row, x, g, xr, grow, bamp, bjz, ladder,
-                                              wacc, hg, diag);
+        const uint64_t base = it.tile() * ((uint64_t)kHxThreads * R) + (uint64_t)wave * (64 * R);
+        if (base >= sd.dim) continue;
+        AdjRows<IdxT, T, NMAX, R> W;
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const uint64_t row64 = base + 64 * u + lane;
+            const bool active = row64 < sd.dim;
+            // a lane past the end decodes a valid row and adds nothing (g = 0)
+            W.row[u] = (IdxT)(active ? row64 : base);
+            decode_row<IdxT, NMAX>(sd, Tb, W.row[u], W.r[u]);
+            W.xr[u] = x[W.row[u]];
+            W.grow[u] = active ? g[W.row[u]] : (T)0;
+            W.hg[u] = (T)0;
+            W.diag[u] = (T)0;
+        }
+        AdjLoop<IdxT, T, NMAX, Q2, 0, 0, R>::run(P, sd, Tb, x, g, bamp, bjz, ladder, borig, wacc, W);
         const uint32_t dm = (1u << sd.nb) - 1u;
         if (P.h || P.want_fields) {
-            for (int i = 0; i < sd.L; ++i) {
-                const T mzi = ladder[32 + (int)((r.s >> (sd.nb * (sd.L - 1 - i))) & dm)];
-                if (P.h) diag += hf[i] * mzi;
-                if (P.want_fields) {  // uniform: one cross-lane sum per site only when asked for
-                    const double v = wave_sum((double)grow * (double)mzi * (double)xr);
-                    if (lane == 0) wacc[2 * P.nbonds + i] += v;
+            // sites in batches of 16: the field sums of a batch in one transposed sum
+            for (int i0 = 0; i0 < sd.L; i0 += 16) {
+                double val[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    val[k] = 0.0;
+                    const int i = i0 + k;
+                    if (i < sd.L) {  // uniform
+                        const int sh = sd.nb * (sd.L - 1 - i);
+#pragma unroll
+                        for (int u = 0; u < R; ++u) {
+                            const T mzi = ladder[32 + (int)((W.r[u].s >> sh) & dm)];
+                            if (P.h) W.diag[u] += hf[i] * mzi;
+                            val[k] += (double)W.grow[u] * (double)mzi * (double)W.xr[u];
+                        }
+                    }
+                }
+                if (P.want_fields) {  // uniform: the cross-lane sums only when asked for
+                    const double sum = wave_transpose_sum<16>(val);
+                    if (lane < 16 && i0 + lane < sd.L) lds_add(wacc + 2 * P.nbonds + i0 + lane, sum);
                 }
             }
         }
-        if (active && gx) gx[row] = hg + diag * g[row];
+        if (gx) {
+#pragma unroll
+            for (int u = 0; u < R; ++u)
+                if (base + 64 * u + lane < sd.dim) gx[W.row[u]] = W.hg[u] + W.diag[u] * W.grow[u];
+        }
     }
     __syncthreads();
+    // partials[i][workgroup]: each sum's partials are contiguous for the reduction
     for (int i = threadIdx.x; i < nacc; i += blockDim.x) {
         double s = 0.0;
         for (int w = 0; w < nw; ++w) s += wacc_all[w * nacc + i];
-        P.partials[(size_t)blockIdx.x * nacc + i] = s;
+        P.partials[(size_t)i * gridDim.x + blockIdx.x] = s;
     }
 }
 
-// Deterministic second stage: fixed-order sum over workgroups.
+// Deterministic second stage: one workgroup of kAdjReduceThreads per sum; each
+// thread adds a fixed stride of the workgroup partials (coalesced), then the
+// wave sums and the four waves are added in a fixed order.
+constexpr int kAdjReduceThreads = 256;
+
 template <int Unused = 0>
-__global__ void adjoint_reduce(const double *__restrict__ partials, int nwg, int nbonds, int L,
-                               double *gjxy, double *gjz, double *gh) {
-    const int nacc = 2 * nbonds + L;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nacc) return;
+__global__ __launch_bounds__(kAdjReduceThreads) void adjoint_reduce(
+    const double *__restrict__ partials, int nwg, int nbonds, double *gjxy, double *gjz,
+    double *gh) {
+    __shared__ double part[kAdjReduceThreads / 64];
+    const int i = blockIdx.x;
+    const double *p = partials + (size_t)i * nwg;
     double s = 0.0;
-    for (int w = 0; w < nwg; ++w) s += partials[(size_t)w * nacc + i];
+    for (int w = threadIdx.x; w < nwg; w += kAdjReduceThreads) s += p[w];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double tot = 0.0;
+    for (int w = 0; w < kAdjReduceThreads / 64; ++w) tot += part[w];
     if (i < 2 * nbonds) {
         if (i & 1)
-            gjz[i >> 1] = s;
+            gjz[i >> 1] = tot;
         else
-            gjxy[i >> 1] = s;
+            gjxy[i >> 1] = tot;
     } else if (gh) {
-        gh[i - 2 * nbonds] = s;
+        gh[i - 2 * nbonds] = tot;
     }
 }
 
@@ -625,14 +778,16 @@ struct Grid {
     int xcd_groups;
 };
 
-inline Grid plan_grid(const dcs_sector *s, size_t lds_bytes) {
+// rows_per_thread: rows each thread of a tile covers (the adjoint's R).
+inline Grid plan_grid(const dcs_sector *s, size_t lds_bytes, int rows_per_thread = 1) {
     const uint64_t dim = s->desc.dim;
     const int cus = device_cu_count(s->device);
     const size_t lds_cu = 160 * 1024;
     int per_cu = (int)(lds_cu / (lds_bytes ? lds_bytes : 1));
     per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
     Grid g;
-    g.tiles = (dim + kHxThreads - 1) / kHxThreads;
+    const uint64_t tile_rows = (uint64_t)kHxThreads * rows_per_thread;
+    g.tiles = (dim + tile_rows - 1) / tile_rows;
     uint64_t want = (uint64_t)cus * per_cu;
     if (want > g.tiles) want = g.tiles;
     if (want < 1) want = 1;
@@ -694,15 +849,21 @@ int launch_hx_t(const dcs_sector *s, HxParams &P, hipStream_t stream) {
     return check_hip(hipGetLastError(), "H*x kernel launch");
 }
 
+// LDS of the adjoint kernel: tables, coefficients, one accumulator slice per
+// wave, the bond index of every plan slot.
+inline size_t adj_lds_bytes(const dcs_sector *s, int nbonds, size_t coeff_bytes) {
+    return s->desc.lay_bytes + coeff_bytes +
+           (size_t)(kHxThreads / 64) * (2 * nbonds + s->desc.L) * sizeof(double) +
+           (size_t)kMaxBonds * sizeof(int);
+}
+
 template <typename IdxT, typename T, int NMAX>
 int launch_adj_t(const dcs_sector *s, HxParams &P, double *gjxy, double *gjz, double *gh,
                         hipStream_t stream) {
     const int nacc = 2 * P.nbonds + s->desc.L;
-    const size_t lds = s->desc.lay_bytes + coeff_lds_bytes<T>() +
-                       (size_t)(kHxThreads / 64) * nacc * sizeof(double);
-    const size_t lds_plan = s->desc.lay_bytes + coeff_lds_bytes<double>() +
-                            (size_t)(kHxThreads / 64) * nacc * sizeof(double);
-    const Grid g = plan_grid(s, lds_plan);
+    const size_t lds = adj_lds_bytes(s, P.nbonds, coeff_lds_bytes<T>());
+    const Grid g = plan_grid(s, adj_lds_bytes(s, P.nbonds, coeff_lds_bytes<double>()),
+                             adj_rows<IdxT, NMAX>());
     P.tiles = g.tiles;
     P.xcd_groups = g.xcd_groups;
     P.want_fields = gh != nullptr;
@@ -716,8 +877,8 @@ int launch_adj_t(const dcs_sector *s, HxParams &P, double *gjxy, double *gjz, do
         kern<<<g.wgs, kHxThreads, lds, stream>>>(P);
     }
     if (int r = check_hip(hipGetLastError(), "adjoint kernel launch")) return r;
-    adjoint_reduce<0><<<(nacc + 255) / 256, 256, 0, stream>>>(P.partials, g.wgs, P.nbonds, s->desc.L,
-                                                           gjxy, gjz, gh);
+    adjoint_reduce<0><<<nacc, kAdjReduceThreads, 0, stream>>>(P.partials, g.wgs, P.nbonds, gjxy,
+                                                               gjz, gh);
     return check_hip(hipGetLastError(), "adjoint reduction launch");
 }
 
