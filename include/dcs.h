@@ -208,10 +208,15 @@ int dcs_adjoint_workspace_size(const dcs_sector *sector, const dcs_terms *terms,
  *   d_grad_jxy[b]   = sum_s g_s ((S+_i S-_j + S-_i S+_j)/2 x)_s
  *   d_grad_jz[b]    = sum_s g_s (Sz_i Sz_j x)_s
  *   d_grad_h[i]     = sum_s g_s (Sz_i x)_s            (skipped if d_grad_h == NULL)
- * Every reached state is ranked once and used for both g and x.  The bond
- * sums are reduced per workgroup into d_workspace and then in a fixed order,
- * so the result is deterministic.  The coupling gradients are FP64 whatever
- * dtype is.  d_grad_x may be NULL (only coupling gradients).
+ * One pass ranks every reached state once and uses it for both g and x.  On a
+ * sector with a split view whose products run on the split tables (the form
+ * the autotuner keeps for this terms object and dtype at k = 1, see
+ * dcs_hamiltonian_apply, including its first-call timing), d_grad_x comes from
+ * that product applied to g and the pass forms only the sums (it gathers x,
+ * not g).  The sums are reduced per workgroup into d_workspace and then in a
+ * fixed order, so the result is deterministic.  The coupling gradients are
+ * FP64 whatever dtype is.  d_grad_x may be NULL (only coupling gradients);
+ * it must not overlap d_x or d_g.
  */
 int dcs_hamiltonian_apply_adjoint(const dcs_sector *sector, const dcs_terms *terms,
                                   const double *d_jxy, const double *d_jz, const double *d_h,

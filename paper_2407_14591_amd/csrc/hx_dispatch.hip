@@ -223,12 +223,39 @@ int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, c
                    double *gjxy, double *gjz, double *gh, void *ws, size_t ws_bytes,
                    hipStream_t stream) {
     DeviceGuard dg(s->device);
+    // grad_x = H g is a product (H is real symmetric).  Where the sector's
+    // products run on the split tables, that product computes it and the adjoint
+    // kernel only forms the coupling and field sums (it gathers x, not g).  Where
+    // the single pass is the faster product, the fused kernel does both.
+    if (gx && s->left.K > 0 && s->desc.Q == 2 && split_enabled()) {
+        if (t->max_site >= s->desc.L)
+            return set_error(DCS_EINVAL, "bond site %d outside the sector's %d sites", t->max_site,
+                             s->desc.L);
+        clear_error();
+        dcs_sector *sm = const_cast<dcs_sector *>(s);
+        const SplitRows *c = split_rows(sm, t);
+        if (c) {
+            bool ran = false;
+            const int form = tuned_form(sm, t, *c, jxy, jz, h, dtype, 1, g, gx, stream, &ran);
+            if (form < 0) return DCS_EHIP;
+            if (form != kFormSingle) {
+                if (!ran) {
+                    if (int r = launch_form(sm, t, *c, form, jxy, jz, h, dtype, 1, g, gx, stream))
+                        return r;
+                }
+                gx = nullptr;
+            }
+        } else if (dcs_last_error()[0]) {
+            return DCS_EHIP;
+        }
+    }
     const int nmax = pick_nmax(s);
     HxParams P;
     if (int r = fill_params(s, t, nmax, jxy, jz, h, P)) return r;
     P.x = x;
     P.g = g;
     P.gx = gx;
+    P.far_below = s->desc.dim >= (1ull << 22) ? s->desc.N / 2 : 0;
     P.partials = (double *)ws;
     (void)ws_bytes;
     if (s->wide) {

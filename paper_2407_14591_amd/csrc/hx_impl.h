@@ -458,10 +458,10 @@ constexpr int adj_rows() {
     return 1;
 }
 
-// Bonds per batch of the adjoint's Q = 2 path (2 sums per bond: 8 or 16 values).
+// Bonds per batch of the adjoint's Q = 2 path (2 sums per bond: 4, 8 or 16 values).
 template <int R>
 constexpr int adj_batch() {
-    return 4;
+    return 2;
 }
 
 template <typename IdxT, typename T, int NMAX, int R>
@@ -491,23 +491,28 @@ __device__ __forceinline__ void half_step(double (&v)[N], bool upper) {
 
 template <int N>
 __device__ __forceinline__ double row_transpose_sum(double (&v)[N]) {
-    static_assert(N == 8 || N == 16, "8 or 16 values");
+    static_assert(N == 4 || N == 8 || N == 16, "4, 8 or 16 values");
     const int l = threadIdx.x & 15;
     if constexpr (N == 16) {
         half_step<N, 8, 0x140>(v, l & 8);  // row_mirror: i <-> 15 - i
         half_step<N, 4, 0x141>(v, l & 4);  // row_half_mirror: i <-> 7 - i in each half row
         half_step<N, 2, 0x1B>(v, l & 2);   // quad_perm [3,2,1,0]
         half_step<N, 1, 0xB1>(v, l & 1);   // quad_perm [1,0,3,2]
-    } else {
+    } else if constexpr (N == 8) {
         half_step<N, 4, 0x140>(v, l & 8);
         half_step<N, 2, 0x141>(v, l & 4);
         half_step<N, 1, 0x1B>(v, l & 2);
         v[0] += dpp_move<0xB1, 0xF>(v[0]);  // lanes i and i ^ 1 hold the same value
+    } else {
+        half_step<N, 2, 0x140>(v, l & 8);
+        half_step<N, 1, 0x141>(v, l & 4);
+        v[0] += dpp_move<0x1B, 0xF>(v[0]);  // the quad holds one value: two plain steps
+        v[0] += dpp_move<0xB1, 0xF>(v[0]);
     }
     return v[0];
 }
 
-// Wave totals of v[0..N): lane i < 16 holds the total of v[i >> (16 / N - 1)]
+// Wave totals of v[0..N): lane i < 16 holds the total of v[i / (16 / N)]
 // (fixed order, the same bits in both lanes of every pair).
 template <int N>
 __device__ __forceinline__ double wave_transpose_sum(double (&v)[N]) {
@@ -526,7 +531,7 @@ __device__ __forceinline__ void lds_add(double *p, double v) {
 // One bond class (A, B) of the adjoint for the R rows of every lane.  For Q = 2
 // the bonds go in batches of 8: every column of the batch, the gathers of g and
 // x, then the 16 bond sums of the batch in one transposed row sum.
-template <typename IdxT, typename T, int NMAX, bool Q2, int A, int B, int R>
+template <typename IdxT, typename T, int NMAX, bool Q2, bool GX, int A, int B, int R>
 __device__ __forceinline__ void adjoint_class(const HxParams &P, const SectorDesc &sd,
                                               const Tables<IdxT> &Tb,
                                               const T *__restrict__ x, const T *__restrict__ g,
@@ -538,7 +543,7 @@ __device__ __forceinline__ void adjoint_class(const HxParams &P, const SectorDes
     const int lane = threadIdx.x & 63;
     if constexpr (Q2) {
         constexpr int NB = adj_batch<R>();
-        constexpr int SH = NB == 8 ? 0 : 1;  // lane of value j: j << SH
+        constexpr int SH = NB == 8 ? 0 : (NB == 4 ? 1 : 2);  // lane of value j: j << SH
         for (int t = beg; t < end; t += NB) {
             double val[2 * NB];
 #pragma unroll
@@ -559,16 +564,24 @@ __device__ __forceinline__ void adjoint_class(const HxParams &P, const SectorDes
                     }
                 }
                 T gv[NB], xv[NB];
+                if (A < P.far_below) {  // far targets: streamed past the caches, as in the forward pass
 #pragma unroll
-                for (int v = 0; v < NB; ++v) {
-                    gv[v] = g[c[v]];
-                    xv[v] = x[c[v]];
+                    for (int v = 0; v < NB; ++v) {
+                        if constexpr (GX) gv[v] = __builtin_nontemporal_load(g + c[v]);
+                        xv[v] = __builtin_nontemporal_load(x + c[v]);
+                    }
+                } else {
+#pragma unroll
+                    for (int v = 0; v < NB; ++v) {
+                        if constexpr (GX) gv[v] = g[c[v]];
+                        xv[v] = x[c[v]];
+                    }
                 }
                 const double p = (double)W.grow[u] * (double)W.xr[u];
 #pragma unroll
                 for (int v = 0; v < NB; ++v) {
                     const bool hop = c[v] != W.row[u];
-                    W.hg[u] += amp[v] * gv[v];
+                    if constexpr (GX) W.hg[u] += amp[v] * gv[v];
                     if (t + v < end) {
                         val[2 * v] += hop ? (double)W.grow[u] * (double)((T)0.5 * xv[v]) : 0.0;
                         val[2 * v + 1] += hop ? -0.25 * p : 0.25 * p;
@@ -604,7 +617,7 @@ __device__ __forceinline__ void adjoint_class(const HxParams &P, const SectorDes
                     else
                         col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa, r.w[B] - (1u << pjl), 1);
                     const T f = (T)0.5 * up[di] * dn[dj];
-                    W.hg[u] += (T)2 * bamp[t] * f * g[col];
+                    if constexpr (GX) W.hg[u] += (T)2 * bamp[t] * f * g[col];
                     hop_x += f * x[col];
                 }
                 if (di > 0 && dj < Qm1) {
@@ -615,7 +628,7 @@ __device__ __forceinline__ void adjoint_class(const HxParams &P, const SectorDes
                     else
                         col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa, r.w[B] + (1u << pjl), -1);
                     const T f = (T)0.5 * dn[di] * up[dj];
-                    W.hg[u] += (T)2 * bamp[t] * f * g[col];
+                    if constexpr (GX) W.hg[u] += (T)2 * bamp[t] * f * g[col];
                     hop_x += f * x[col];
                 }
                 W.diag[u] += bjz[t] * zz;
@@ -633,7 +646,7 @@ __device__ __forceinline__ void adjoint_class(const HxParams &P, const SectorDes
     }
 }
 
-template <typename IdxT, typename T, int NMAX, bool Q2, int A, int B, int R>
+template <typename IdxT, typename T, int NMAX, bool Q2, bool GX, int A, int B, int R>
 struct AdjLoop {
     __device__ __forceinline__ static void run(const HxParams &P, const SectorDesc &sd,
                                                const Tables<IdxT> &Tb,
@@ -644,12 +657,12 @@ struct AdjLoop {
         if constexpr (A < NMAX) {
             if constexpr (B < NMAX) {
                 if (B < sd.N)
-                    adjoint_class<IdxT, T, NMAX, Q2, A, B, R>(P, sd, Tb, x, g, bamp, bjz, ladder,
+                    adjoint_class<IdxT, T, NMAX, Q2, GX, A, B, R>(P, sd, Tb, x, g, bamp, bjz, ladder,
                                                               borig, wacc, W);
-                AdjLoop<IdxT, T, NMAX, Q2, A, B + 1, R>::run(P, sd, Tb, x, g, bamp, bjz, ladder,
+                AdjLoop<IdxT, T, NMAX, Q2, GX, A, B + 1, R>::run(P, sd, Tb, x, g, bamp, bjz, ladder,
                                                              borig, wacc, W);
             } else {
-                AdjLoop<IdxT, T, NMAX, Q2, A + 1, A + 1, R>::run(P, sd, Tb, x, g, bamp, bjz,
+                AdjLoop<IdxT, T, NMAX, Q2, GX, A + 1, A + 1, R>::run(P, sd, Tb, x, g, bamp, bjz,
                                                                  ladder, borig, wacc, W);
             }
         }
@@ -658,11 +671,11 @@ struct AdjLoop {
 
 // Each wave keeps its bond and field sums in its own LDS slice, then the
 // workgroup adds the slices in wave order and writes one partial row.  A tile is
-// kHxThreads * R rows; wave w takes R consecutive 64-row pieces of it.
-template <typename IdxT, typename T, int NMAX, bool Q2>
-__global__ __launch_bounds__(kHxThreads) void adjoint_kernel(const HxParams P) {
+// kHxThreads * R rows; wave w takes R consecutive 64-row pieces of it.  GX: the
+// kernel also computes grad_x = H g (else only the sums: no gathers of g).
+template <typename IdxT, typename T, int NMAX, bool Q2, bool GX>
+__device__ __forceinline__ void adjoint_body(const HxParams &P, char *lds) {
     constexpr int R = adj_rows<IdxT, NMAX>();
-    extern __shared__ __align__(16) char lds[];
     const SectorDesc &sd = P.sd;
     stage_blob(lds, P.blob, sd.lay_bytes);
     T *bamp = reinterpret_cast<T *>(lds + sd.lay_bytes);
@@ -683,9 +696,9 @@ __global__ __launch_bounds__(kHxThreads) void adjoint_kernel(const HxParams P) {
     const T *__restrict__ g = reinterpret_cast<const T *>(P.g);
     T *__restrict__ gx = reinterpret_cast<T *>(P.gx);
 
-    for (TileIter it = my_tiles(P.tiles, P.xcd_groups); it.tile() < it.tiles; ++it.m) {
-        const uint64_t base = it.tile() * ((uint64_t)kHxThreads * R) + (uint64_t)wave * (64 * R);
-        if (base >= sd.dim) continue;
+    auto tile_rows = [&](uint64_t tile) {
+        const uint64_t base = tile * ((uint64_t)kHxThreads * R) + (uint64_t)wave * (64 * R);
+        if (base >= sd.dim) return;
         AdjRows<IdxT, T, NMAX, R> W;
 #pragma unroll
         for (int u = 0; u < R; ++u) {
@@ -699,14 +712,15 @@ __global__ __launch_bounds__(kHxThreads) void adjoint_kernel(const HxParams P) {
             W.hg[u] = (T)0;
             W.diag[u] = (T)0;
         }
-        AdjLoop<IdxT, T, NMAX, Q2, 0, 0, R>::run(P, sd, Tb, x, g, bamp, bjz, ladder, borig, wacc, W);
+        AdjLoop<IdxT, T, NMAX, Q2, GX, 0, 0, R>::run(P, sd, Tb, x, g, bamp, bjz, ladder, borig, wacc,
+                                                     W);
         const uint32_t dm = (1u << sd.nb) - 1u;
         if (P.h || P.want_fields) {
-            // sites in batches of 16: the field sums of a batch in one transposed sum
-            for (int i0 = 0; i0 < sd.L; i0 += 16) {
-                double val[16];
+            // sites in batches of 8: the field sums of a batch in one transposed sum
+            for (int i0 = 0; i0 < sd.L; i0 += 8) {
+                double val[8];
 #pragma unroll
-                for (int k = 0; k < 16; ++k) {
+                for (int k = 0; k < 8; ++k) {
                     val[k] = 0.0;
                     const int i = i0 + k;
                     if (i < sd.L) {  // uniform
@@ -720,17 +734,24 @@ __global__ __launch_bounds__(kHxThreads) void adjoint_kernel(const HxParams P) {
                     }
                 }
                 if (P.want_fields) {  // uniform: the cross-lane sums only when asked for
-                    const double sum = wave_transpose_sum<16>(val);
-                    if (lane < 16 && i0 + lane < sd.L) lds_add(wacc + 2 * P.nbonds + i0 + lane, sum);
+                    // the total of val[k] is in lane 2k
+                    const double sum = wave_transpose_sum<8>(val);
+                    const int k = lane >> 1;
+                    if (lane < 16 && (lane & 1) == 0 && i0 + k < sd.L)
+                        lds_add(wacc + 2 * P.nbonds + i0 + k, sum);
                 }
             }
         }
-        if (gx) {
+        if constexpr (GX) {
 #pragma unroll
             for (int u = 0; u < R; ++u)
                 if (base + 64 * u + lane < sd.dim) gx[W.row[u]] = W.hg[u] + W.diag[u] * W.grow[u];
         }
-    }
+    };
+    // a static tile order: which workgroup adds which rows must not depend on timing,
+    // so that the partial sums, and the gradients, are reproducible bit for bit
+    for (TileIter it = my_tiles(P.tiles, P.xcd_groups); it.tile() < it.tiles; ++it.m)
+        tile_rows(it.tile());
     __syncthreads();
     // partials[i][workgroup]: each sum's partials are contiguous for the reduction
     for (int i = threadIdx.x; i < nacc; i += blockDim.x) {
@@ -738,6 +759,23 @@ __global__ __launch_bounds__(kHxThreads) void adjoint_kernel(const HxParams P) {
         for (int w = 0; w < nw; ++w) s += wacc_all[w * nacc + i];
         P.partials[(size_t)i * gridDim.x + blockIdx.x] = s;
     }
+}
+
+// The fused adjoint (grad_x and the sums), used where the single pass is the
+// faster product, i.e. on sectors whose tables leave room for eight waves per
+// SIMD: the register budget is set for that occupancy.
+template <typename IdxT, typename T, int NMAX, bool Q2>
+__global__ __launch_bounds__(kHxThreads) __attribute__((amdgpu_waves_per_eu(8))) void
+adjoint_kernel(const HxParams P) {
+    extern __shared__ __align__(16) char lds[];
+    adjoint_body<IdxT, T, NMAX, Q2, true>(P, lds);
+}
+
+// The sums only (grad_x comes from the split product).
+template <typename IdxT, typename T, int NMAX, bool Q2>
+__global__ __launch_bounds__(kHxThreads) void adjoint_sums_kernel(const HxParams P) {
+    extern __shared__ __align__(16) char lds[];
+    adjoint_body<IdxT, T, NMAX, Q2, false>(P, lds);
 }
 
 // Deterministic second stage: one workgroup of kAdjReduceThreads per sum; each
@@ -867,15 +905,12 @@ int launch_adj_t(const dcs_sector *s, HxParams &P, double *gjxy, double *gjz, do
     P.tiles = g.tiles;
     P.xcd_groups = g.xcd_groups;
     P.want_fields = gh != nullptr;
-    if (s->desc.Q == 2) {
-        auto kern = adjoint_kernel<IdxT, T, NMAX, true>;
-        if (int r = ensure_lds(kern, lds)) return r;
-        kern<<<g.wgs, kHxThreads, lds, stream>>>(P);
-    } else {
-        auto kern = adjoint_kernel<IdxT, T, NMAX, false>;
-        if (int r = ensure_lds(kern, lds)) return r;
-        kern<<<g.wgs, kHxThreads, lds, stream>>>(P);
-    }
+    auto kern = s->desc.Q == 2 ? (P.gx ? adjoint_kernel<IdxT, T, NMAX, true>
+                                       : adjoint_sums_kernel<IdxT, T, NMAX, true>)
+                               : (P.gx ? adjoint_kernel<IdxT, T, NMAX, false>
+                                       : adjoint_sums_kernel<IdxT, T, NMAX, false>);
+    if (int r = ensure_lds(kern, lds)) return r;
+    kern<<<g.wgs, kHxThreads, lds, stream>>>(P);
     if (int r = check_hip(hipGetLastError(), "adjoint kernel launch")) return r;
     adjoint_reduce<0><<<nacc, kAdjReduceThreads, 0, stream>>>(P.partials, g.wgs, P.nbonds, gjxy,
                                                                gjz, gh);
