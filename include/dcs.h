@@ -234,16 +234,19 @@ int dcs_hamiltonian_apply_adjoint(const dcs_sector *sector, const dcs_terms *ter
  * d_jxy[s], d_jz[s] (device FP64 arrays; the pointers are recorded, the
  * values are read at apply time).  The sectors may differ in L, n, Q and
  * split.  Sectors that have a split view (Q = 2, see "Split product") are
- * left out of the launch and run their own split product after it, on the
- * same stream.  The plan does not own the sectors or terms; they must
- * outlive it.
+ * left out of the launch and run their own product after it, on the same
+ * stream, in the form the autotuner keeps for them (dcs_hamiltonian_apply).
+ * Tiles go to the workgroups through per-XCD counters; every row is written
+ * by one thread, so the result does not depend on the schedule.  The plan
+ * does not own the sectors or terms; they must outlive it.
  */
 int dcs_plan_create(int num_sectors, dcs_sector *const *sectors, dcs_terms *const *terms,
                     const double *const *d_jxy, const double *const *d_jz, dcs_plan **out);
 int dcs_plan_destroy(dcs_plan *plan);
 
 /* y_s = H_s x_s for every sector s; d_x[s], d_y[s] are device vectors of
- * D_s elements of dtype (k = 1). */
+ * D_s elements of dtype (k = 1).  Calls on one plan must not overlap in time
+ * (they share its tile counters). */
 int dcs_plan_apply(const dcs_plan *plan, int dtype, const void *const *d_x, void *const *d_y,
                    void *stream);
 

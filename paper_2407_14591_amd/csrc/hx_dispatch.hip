@@ -139,11 +139,15 @@ bool autotune_enabled() {
 // counted) and keeps the fastest for that key in the sector.  Every form
 // writes the same Y (up to rounding order), so the call's result is valid
 // whichever form ran last; the fastest runs last.
+inline uint64_t tuned_key(const dcs_terms *t, int dtype, int k) {
+    return (t->id << 8) | ((uint64_t)dtype << 4) | (uint64_t)k;
+}
+
 int tuned_form(dcs_sector *s, const dcs_terms *t, const SplitRows &c, const double *jxy,
                const double *jz, const double *h, int dtype, int k, const void *x, void *y,
                hipStream_t stream, bool *ran) {
     *ran = false;
-    const uint64_t key = (t->id << 8) | ((uint64_t)dtype << 4) | (uint64_t)k;
+    const uint64_t key = tuned_key(t, dtype, k);
     LeftInfo &li = s->left;
     {
         std::lock_guard<std::mutex> g(*li.rows_lock);

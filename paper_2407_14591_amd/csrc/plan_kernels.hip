@@ -1,11 +1,16 @@
 // Many sectors in one persistent launch: y_s = H_s x_s for every sector s of a plan.
 //
 // The rows of all sectors are cut into tiles of kHxThreads rows that never
-// cross a sector boundary, listed sector by sector.  Each workgroup owns a
-// contiguous range of tiles (XCD-aware, as for one sector); when its tile
-// moves to another sector it re-stages that sector's tables and bond
-// coefficients into LDS.  Sectors may differ in L, n, Q and split; each tile
-// takes the Q=2 or general-Q bond code by a uniform branch.
+// cross a sector boundary, listed sector by sector.  The tiles go out in
+// chunks of kPlanChunk consecutive tiles, dealt round robin to the 8 XCDs; the
+// workgroups of an XCD (dispatch order blockIdx % 8) take the next tile of
+// their XCD's sequence from one counter, claimed one tile ahead, so sectors of
+// unequal cost per row (spin 1 against spin 1/2) spread evenly over the chip.
+// When a workgroup's tile moves to another sector it re-stages that sector's
+// tables and bond coefficients into LDS.  Sectors may differ in L, n, Q and
+// split; each tile takes the Q=2 or general-Q bond code by a uniform branch.
+// Each row is written by one thread, so the result does not depend on which
+// workgroup took which tile.
 #include <algorithm>
 #include <vector>
 
@@ -37,19 +42,31 @@ struct PlanArgs {
     const PlanIO *io;
     const uint2 *tiles;  // (sector, first row)
     uint32_t ntiles;
-    uint32_t tiles_per_wg;
-    int xcd_groups;
+    uint32_t *counters;  // one per XCD, zero at launch
 };
+
+constexpr uint32_t kPlanChunk = 256;
+
+// Tile of position i in XCD x's sequence (chunks dealt round robin).
+__device__ __forceinline__ uint32_t plan_tile(uint32_t i, uint32_t x) {
+    return ((i / kPlanChunk) * 8u + x) * kPlanChunk + i % kPlanChunk;
+}
 
 template <typename IdxT, typename T, int NMAX>
 __global__ __launch_bounds__(kHxThreads) void plan_kernel(const PlanArgs A) {
     extern __shared__ __align__(16) char lds[];
-    const uint32_t g = xcd_chunk(A.xcd_groups);
-    const uint32_t t0 = g * A.tiles_per_wg;
-    const uint32_t t1 = min(t0 + A.tiles_per_wg, A.ntiles);
+    __shared__ uint32_t slot[2];
+    const uint32_t xcd = blockIdx.x & 7u;
     const int wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) slot[0] = atomicAdd(A.counters + xcd, 1u);
+    __syncthreads();
+    uint32_t cur_slot = slot[0];
+    int b = 0;
     int cur = -1;
-    for (uint32_t t = t0; t < t1; ++t) {
+    // an XCD's sequence is increasing in the tile index: the first position past
+    // the list ends the workgroup
+    for (uint32_t t = plan_tile(cur_slot, xcd); t < A.ntiles; t = plan_tile(cur_slot, xcd)) {
+        if (threadIdx.x == 0) slot[b ^ 1] = atomicAdd(A.counters + xcd, 1u);  // the next, ahead
         const uint2 tl = A.tiles[t];
         const int sid = (int)tl.x;
         const PlanSector &ps = A.secs[sid];
@@ -77,6 +94,9 @@ __global__ __launch_bounds__(kHxThreads) void plan_kernel(const PlanArgs A) {
                 hx_tile<IdxT, T, 1, NMAX, false>(ps, ps.sd, Tb, x, y, C.bamp, C.bjz, C.ladder, C.hf,
                                                  false, tile, end);
         }
+        __syncthreads();  // slot[b ^ 1] is written; slot[b] is free for the claim after next
+        b ^= 1;
+        cur_slot = slot[b];
     }
 }
 
@@ -99,7 +119,9 @@ struct dcs_plan {
     hipEvent_t io_copied = nullptr;
     bool io_pending = false;
     std::vector<uint64_t> dims;
-    // sectors with a split view run their own split product after the launch
+    uint32_t *d_counters = nullptr;  // the tile queue's per-XCD counters
+    // sectors with a split view run their own product after the launch, in the
+    // form the autotuner keeps for them
     struct Own {
         int index;
         dcs_sector *sector;
@@ -119,6 +141,7 @@ static void plan_free(dcs_plan *p) {
     hipFree(p->d_secs);
     hipFree(p->d_io);
     hipFree(p->d_tiles);
+    hipFree(p->d_counters);
     hipHostFree(p->h_io);
     delete p;
 }
@@ -158,10 +181,10 @@ extern "C" int dcs_plan_create(int nsec, dcs_sector *const *secs, dcs_terms *con
         ps.nbonds = bp.nbonds;
         ps.q2 = secs[s]->desc.Q == 2;
         ps.cls_mask = ~0ull;
-        ps.far_below = 0;
+        ps.far_below = ps.sd.dim >= (1ull << 22) ? ps.sd.N / 2 : 0;  // as for one sector
         for (int c = 0; c <= bp.nclasses; ++c) ps.cls_beg[c] = bp.cls_beg[c];
         for (int b = 0; b < bp.nbonds; ++b) ps.pos[b] = bp.pos[b];
-        if (secs[s]->left.K > 0 && secs[s]->desc.Q == 2) continue;  // split product of its own
+        if (secs[s]->left.K > 0 && secs[s]->desc.Q == 2) continue;  // a product of its own
         for (uint64_t r0 = 0; r0 < ps.sd.dim; r0 += kHxThreads) tiles.push_back(make_uint2(s, (uint32_t)r0));
     }
     dcs_plan *p = new (std::nothrow) dcs_plan();
@@ -182,6 +205,7 @@ extern "C" int dcs_plan_create(int nsec, dcs_sector *const *secs, dcs_terms *con
     if (!r) r = check_hip(hipMalloc(&p->d_tiles, std::max<size_t>(tiles.size(), 1) * sizeof(uint2)),
                           "hipMalloc tiles");
     if (!r) r = check_hip(hipHostMalloc(&p->h_io, nsec * sizeof(PlanIO)), "hipHostMalloc");
+    if (!r) r = check_hip(hipMalloc(&p->d_counters, 8 * sizeof(uint32_t)), "hipMalloc plan counters");
     if (!r) r = check_hip(hipEventCreateWithFlags(&p->io_copied, hipEventDisableTiming), "event");
     if (!r)
         r = check_hip(hipMemcpy(p->d_secs, hs.data(), nsec * sizeof(PlanSector), hipMemcpyHostToDevice),
@@ -206,24 +230,24 @@ extern "C" int dcs_plan_destroy(dcs_plan *p) {
 
 template <typename T, int NMAX>
 static int launch_plan(dcs_plan *p, hipStream_t stream) {
+    const uint2 *tiles = p->d_tiles;
+    const uint32_t ntiles = p->ntiles;
     const int cus = device_cu_count(p->device);
     int per_cu = (int)((160 * 1024) / p->lds_bytes);
     per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
-    uint32_t wgs = (uint32_t)std::min<uint64_t>((uint64_t)cus * per_cu, p->ntiles);
+    // a multiple of 8 workgroups, so that every XCD's tile sequence has workers
+    uint64_t wgs = std::min<uint64_t>((uint64_t)cus * per_cu, ntiles);
+    wgs = std::max<uint64_t>(8, (wgs + 7) / 8 * 8);
     PlanArgs A;
     A.secs = p->d_secs;
     A.io = p->d_io;
-    A.tiles = p->d_tiles;
-    A.ntiles = p->ntiles;
-    A.xcd_groups = 0;
-    if (wgs >= 16) {
-        wgs = (wgs + 7) / 8 * 8;
-        A.xcd_groups = (int)(wgs / 8);
-    }
-    A.tiles_per_wg = (p->ntiles + wgs - 1) / wgs;
+    A.tiles = tiles;
+    A.ntiles = ntiles;
+    A.counters = p->d_counters;
+    zero_counters<0><<<1, 64, 0, stream>>>(p->d_counters, 8);
     auto kern = plan_kernel<uint32_t, T, NMAX>;
     if (int r = ensure_lds(kern, p->lds_bytes)) return r;
-    kern<<<wgs, kHxThreads, p->lds_bytes, stream>>>(A);
+    kern<<<(unsigned)wgs, kHxThreads, p->lds_bytes, stream>>>(A);
     return check_hip(hipGetLastError(), "plan kernel launch");
 }
 
