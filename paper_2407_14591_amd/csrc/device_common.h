@@ -16,6 +16,17 @@ struct Tables {
     const uint16_t *inv;    // words by (digit sum, local index)
 };
 
+// A kernel's first (by-value) argument, read where it lies in the kernel
+// argument segment (constant memory; the first argument starts at offset 0).
+// Uniform field reads then become scalar loads.  Without this, the compiler
+// makes a per-lane copy of a large argument block in scratch memory when the
+// kernel body is large (the single pass with more than four subsystems), and
+// spills scalar registers in others.
+template <typename P>
+__device__ __forceinline__ const P &kernel_arg0() {
+    return *(const P *)__builtin_amdgcn_kernarg_segment_ptr();
+}
+
 template <typename IdxT>
 __device__ __forceinline__ Tables<IdxT> tables_at(const char *base, const SectorDesc &sd) {
     Tables<IdxT> t;

@@ -393,7 +393,9 @@ struct CoeffLds {
 };
 
 template <typename IdxT, typename T, int K, int NMAX, bool Q2>
-__global__ __launch_bounds__(kHxThreads) void hx_kernel(const HxParams P) {
+__global__ __launch_bounds__(kHxThreads) void hx_kernel(const HxParams P_arg) {
+    (void)P_arg;
+    const HxParams &P = kernel_arg0<HxParams>();
     extern __shared__ __align__(16) char lds[];
     const SectorDesc &sd = P.sd;
     stage_blob(lds, P.blob, sd.lay_bytes);
@@ -766,16 +768,18 @@ __device__ __forceinline__ void adjoint_body(const HxParams &P, char *lds) {
 // SIMD: the register budget is set for that occupancy.
 template <typename IdxT, typename T, int NMAX, bool Q2>
 __global__ __launch_bounds__(kHxThreads) __attribute__((amdgpu_waves_per_eu(8))) void
-adjoint_kernel(const HxParams P) {
+adjoint_kernel(const HxParams P_arg) {
+    (void)P_arg;
     extern __shared__ __align__(16) char lds[];
-    adjoint_body<IdxT, T, NMAX, Q2, true>(P, lds);
+    adjoint_body<IdxT, T, NMAX, Q2, true>(kernel_arg0<HxParams>(), lds);
 }
 
 // The sums only (grad_x comes from the split product).
 template <typename IdxT, typename T, int NMAX, bool Q2>
-__global__ __launch_bounds__(kHxThreads) void adjoint_sums_kernel(const HxParams P) {
+__global__ __launch_bounds__(kHxThreads) void adjoint_sums_kernel(const HxParams P_arg) {
+    (void)P_arg;
     extern __shared__ __align__(16) char lds[];
-    adjoint_body<IdxT, T, NMAX, Q2, false>(P, lds);
+    adjoint_body<IdxT, T, NMAX, Q2, false>(kernel_arg0<HxParams>(), lds);
 }
 
 // Deterministic second stage: one workgroup of kAdjReduceThreads per sum; each

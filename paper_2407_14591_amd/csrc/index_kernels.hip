@@ -17,10 +17,12 @@ __device__ __forceinline__ void count_bad(uint64_t *nbad, bool bad) {
 }
 
 template <typename IdxT>
-__global__ __launch_bounds__(kThreads) void rank_kernel(SectorDesc sd, const char *blob,
+__global__ __launch_bounds__(kThreads) void rank_kernel(SectorDesc sd_arg, const char *blob,
                                                         const uint64_t *__restrict__ st,
                                                         uint64_t *__restrict__ out, size_t count,
                                                         uint64_t *nbad) {
+    (void)sd_arg;
+    const SectorDesc &sd = kernel_arg0<SectorDesc>();
     extern __shared__ __align__(16) char lds[];
     stage_blob(lds, blob, sd.lay_bytes);
     __syncthreads();
@@ -39,11 +41,13 @@ __global__ __launch_bounds__(kThreads) void rank_kernel(SectorDesc sd, const cha
 }
 
 template <typename IdxT>
-__global__ __launch_bounds__(kThreads) void unrank_kernel(SectorDesc sd, const char *blob,
+__global__ __launch_bounds__(kThreads) void unrank_kernel(SectorDesc sd_arg, const char *blob,
                                                           const uint64_t *__restrict__ idx,
                                                           uint64_t *__restrict__ out, size_t count,
                                                           uint64_t first, int use_first,
                                                           uint64_t *nbad) {
+    (void)sd_arg;
+    const SectorDesc &sd = kernel_arg0<SectorDesc>();
     extern __shared__ __align__(16) char lds[];
     stage_blob(lds, blob, sd.lay_bytes);
     __syncthreads();

@@ -119,7 +119,9 @@ struct DiagParams {
 static_assert(sizeof(DiagParams) <= 4096, "kernel arguments are limited to 4 KiB");
 
 template <int Unused = 0>
-__global__ __launch_bounds__(256) void split_diag_kernel(const DiagParams P) {
+__global__ __launch_bounds__(256) void split_diag_kernel(const DiagParams P_arg) {
+    (void)P_arg;
+    const DiagParams &P = kernel_arg0<DiagParams>();
     if (blockIdx.x == 0) {
         float *amp32 = reinterpret_cast<float *>(P.amp64 + kAmpEntries);
         for (int q = threadIdx.x; q < kAmpEntries; q += 256) {
@@ -255,7 +257,9 @@ __device__ __forceinline__ Acc<T, K> lds_row(const char *lds, uint32_t row) {
 }
 
 template <typename T, int K>
-__global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P) {
+__global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_arg) {
+    (void)P_arg;
+    const RowParams &P = kernel_arg0<RowParams>();
     using B = RowBatch<T, K>;
     constexpr uint32_t RB = B::RB;
     extern __shared__ __align__(16) char rows_lds[];
@@ -446,7 +450,9 @@ constexpr int lds_rows_threads() {
 }
 
 template <typename T, int K>
-__global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_kernel(const RowParams P) {
+__global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_kernel(const RowParams P_arg) {
+    (void)P_arg;
+    const RowParams &P = kernel_arg0<RowParams>();
     using V = Acc<T, K>;
     constexpr uint32_t RB = K * sizeof(T);
     static_assert(RB <= 8, "staged runs hold rows of at most 8 bytes");
@@ -627,7 +633,9 @@ constexpr uint32_t kColWaveBytes = 64 * kColLaneBytes;
 // to LDS; the targets inside the cluster (bonds inside P_{K-1}) are then read
 // there, the others from HBM.  Wave w takes the cluster's runs w, w+8, ...
 template <typename T, int K>
-__global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams P) {
+__global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams P_arg) {
+    (void)P_arg;
+    const ColParams &P = kernel_arg0<ColParams>();
     constexpr int V = kColLaneBytes / sizeof(T);
     typedef T vec_t __attribute__((ext_vector_type(V)));
     extern __shared__ __align__(16) char cl_lds[];  // [cluster run][kColWaveBytes]
