@@ -36,6 +36,8 @@ struct PlanIO {
     const void *x;
     void *y;
 };
+static_assert(sizeof(PlanIO) == 2 * sizeof(void *), "PlanIO is read as two pointers");
+static_assert(sizeof(uint2) == 2 * sizeof(uint32_t), "tiles are read as two words");
 
 struct PlanArgs {
     const PlanSector *secs;
@@ -46,6 +48,13 @@ struct PlanArgs {
 };
 
 constexpr uint32_t kPlanChunk = 256;
+
+// The plan's device arrays are read-only during a launch: read them through the
+// constant address space, so that wave-uniform reads become scalar loads.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *const_view(const T *p) {
+    return (const __attribute__((address_space(4))) T *)p;
+}
 
 // Tile of position i in XCD x's sequence (chunks dealt round robin).
 __device__ __forceinline__ uint32_t plan_tile(uint32_t i, uint32_t x) {
@@ -67,9 +76,10 @@ __global__ __launch_bounds__(kHxThreads) void plan_kernel(const PlanArgs A) {
     // the list ends the workgroup
     for (uint32_t t = plan_tile(cur_slot, xcd); t < A.ntiles; t = plan_tile(cur_slot, xcd)) {
         if (threadIdx.x == 0) slot[b ^ 1] = atomicAdd(A.counters + xcd, 1u);  // the next, ahead
-        const uint2 tl = A.tiles[t];
-        const int sid = (int)tl.x;
-        const PlanSector &ps = A.secs[sid];
+        const uint32_t *tw = reinterpret_cast<const uint32_t *>(A.tiles);
+        const int sid = (int)const_view(tw)[2 * t];
+        const uint32_t row0 = const_view(tw)[2 * t + 1];
+        const PlanSector &ps = *(const PlanSector *)(const_view(A.secs) + sid);
         const CoeffLds<T> C(lds, ps.sd.lay_bytes);
         if (sid != cur) {
             __syncthreads();
@@ -82,10 +92,11 @@ __global__ __launch_bounds__(kHxThreads) void plan_kernel(const PlanArgs A) {
             cur = sid;
         }
         const Tables<IdxT> Tb = tables_at<IdxT>(lds, ps.sd);
-        const T *__restrict__ x = reinterpret_cast<const T *>(A.io[sid].x);
-        T *__restrict__ y = reinterpret_cast<T *>(A.io[sid].y);
-        const uint64_t end = min((uint64_t)tl.y + kHxThreads, ps.sd.dim);
-        const uint64_t tile = (uint64_t)tl.y + (uint64_t)wave * 64;
+        const void *const *io = reinterpret_cast<const void *const *>(A.io);  // (x, y) per sector
+        const T *__restrict__ x = reinterpret_cast<const T *>(const_view(io)[2 * sid]);
+        T *__restrict__ y = reinterpret_cast<T *>(const_cast<void *>(const_view(io)[2 * sid + 1]));
+        const uint64_t end = min((uint64_t)row0 + kHxThreads, ps.sd.dim);
+        const uint64_t tile = (uint64_t)row0 + (uint64_t)wave * 64;
         if (tile < end) {
             if (ps.q2)
                 hx_tile<IdxT, T, 1, NMAX, true>(ps, ps.sd, Tb, x, y, C.bamp, C.bjz, C.ladder, C.hf,
