@@ -39,10 +39,12 @@
  *    sector for the next calls; up to four terms objects per sector) and every
  *    product runs three kernels: the diagonal per configuration of each side,
  *    one pass over the rows for the bonds right of and across the cut, and one
- *    over column chunks for the bonds left of it.  DCS_SPLIT_MIN_DIM (read by
- *    dcs_sector_create) changes the 2^20 threshold; DCS_SPLIT=0 (read at every
- *    product) forces the single pass; DCS_SPLIT_LDS=0 (likewise) keeps the row
- *    pass from staging runs of x in on-chip memory.
+ *    over column chunks for the bonds left of it (or, in the fused form, two:
+ *    the row pass also applies the bonds left of the cut).  DCS_SPLIT_MIN_DIM
+ *    (read by dcs_sector_create) changes the 2^20 threshold; DCS_SPLIT=0 (read
+ *    at every product) forces the single pass; DCS_SPLIT_LDS=0 (likewise) keeps
+ *    the row pass from staging runs of x in on-chip memory; DCS_SPLIT_FUSED=1
+ *    (likewise) makes the fused form the default form.
  */
 #ifndef DCS_H
 #define DCS_H
@@ -187,10 +189,11 @@ int dcs_terms_destroy(dcs_terms *terms);
  * allocates them on the device (see "Split product" above); later calls
  * allocate nothing.  Autotuner: the first call for a (terms, dtype, k) on a
  * sector with a split view also times the launch forms (split product with
- * runs staged in on-chip memory, split product without, single pass; each
- * twice, HIP events, synchronising the stream), keeps the fastest for that key
- * and returns its Y; later calls use it.  Inside stream capture, or with
- * DCS_AUTOTUNE=0 in the environment, the default form (staged split) is used.
+ * runs staged in on-chip memory, split product without, fused split product,
+ * single pass; each twice, HIP events, synchronising the stream), keeps the
+ * fastest for that key and returns its Y; later calls use it.  Inside stream
+ * capture, or with DCS_AUTOTUNE=0 in the environment, the default form (staged
+ * split, or fused with DCS_SPLIT_FUSED=1) is used.
  */
 int dcs_hamiltonian_apply(const dcs_sector *sector, const dcs_terms *terms, const double *d_jxy,
                           const double *d_jz, const double *d_h, int dtype, int k,

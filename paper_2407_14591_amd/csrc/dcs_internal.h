@@ -140,6 +140,7 @@ struct SplitRows {
     // inside P_{K-1} map a cluster onto itself
     uint32_t *d_clstart = nullptr;   // first left configuration of every cluster
     uint32_t *d_clsize = nullptr;    // its number of left configurations
+    uint64_t *d_lrun = nullptr;      // the left family entries with run starts only: bond << 48 | run
     uint32_t clbase[kMaxLeftM];      // first cluster of block m - m_lo
     uint32_t nclust[kMaxLeftM];
     uint32_t max_cluster = 0;

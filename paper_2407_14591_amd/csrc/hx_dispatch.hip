@@ -11,7 +11,7 @@ namespace sp {
 #define DCS_SPLIT_EXTERN(T, K)                                                                   \
     extern template int launch_split_t<T, K>(dcs_sector *, const SplitRows &, const void *, void *, \
                                              const double *, const double *, const double *, int,   \
-                                             bool, hipStream_t);
+                                             int, hipStream_t);
 DCS_SPLIT_EXTERN(float, 1)
 DCS_SPLIT_EXTERN(float, 2)
 DCS_SPLIT_EXTERN(float, 4)
@@ -83,13 +83,13 @@ int launch_hx_d(const dcs_sector *s, HxParams &P, int dtype, int k, hipStream_t 
 
 template <typename T>
 int launch_split_k(dcs_sector *s, const SplitRows &c, const void *x, void *y, const double *jxy,
-                   const double *jz, const double *h, int nbonds, int k, bool staged_ok,
+                   const double *jz, const double *h, int nbonds, int k, int variant,
                    hipStream_t stream) {
     switch (k) {
-        case 1: return sp::launch_split_t<T, 1>(s, c, x, y, jxy, jz, h, nbonds, staged_ok, stream);
-        case 2: return sp::launch_split_t<T, 2>(s, c, x, y, jxy, jz, h, nbonds, staged_ok, stream);
-        case 4: return sp::launch_split_t<T, 4>(s, c, x, y, jxy, jz, h, nbonds, staged_ok, stream);
-        default: return sp::launch_split_t<T, 8>(s, c, x, y, jxy, jz, h, nbonds, staged_ok, stream);
+        case 1: return sp::launch_split_t<T, 1>(s, c, x, y, jxy, jz, h, nbonds, variant, stream);
+        case 2: return sp::launch_split_t<T, 2>(s, c, x, y, jxy, jz, h, nbonds, variant, stream);
+        case 4: return sp::launch_split_t<T, 4>(s, c, x, y, jxy, jz, h, nbonds, variant, stream);
+        default: return sp::launch_split_t<T, 8>(s, c, x, y, jxy, jz, h, nbonds, variant, stream);
     }
 }
 
@@ -116,22 +116,38 @@ int launch_single(const dcs_sector *s, const dcs_terms *t, const double *jxy, co
                      : launch_hx_d<uint32_t, 8>(s, P, dtype, k, stream);
 }
 
-// Launch forms of a product on a sector with a split view.
-enum Form { kFormSplitStaged = 0, kFormSplitGlobal = 1, kFormSingle = 2, kNumForms = 3 };
+// Launch forms of a product on a sector with a split view: the split product
+// with runs staged in LDS where they fit, without, with the left family applied
+// by the row pass (no column pass), and the single pass.
+enum Form {
+    kFormSplitStaged = 0,
+    kFormSplitGlobal = 1,
+    kFormSplitFused = 2,
+    kFormSingle = 3,
+    kNumForms = 4
+};
 
 int launch_form(dcs_sector *s, const dcs_terms *t, const SplitRows &c, int form, const double *jxy,
                 const double *jz, const double *h, int dtype, int k, const void *x, void *y,
                 hipStream_t stream) {
     if (form == kFormSingle) return launch_single(s, t, jxy, jz, h, dtype, k, x, y, stream);
-    const bool staged = form == kFormSplitStaged;
-    return dtype == DCS_F32 ? launch_split_k<float>(s, c, x, y, jxy, jz, h, t->num_bonds, k, staged, stream)
-                            : launch_split_k<double>(s, c, x, y, jxy, jz, h, t->num_bonds, k, staged, stream);
+    const int variant = form == kFormSplitStaged ? sp::kSplitStagedOk
+                                                 : (form == kFormSplitGlobal ? sp::kSplitGlobal : sp::kSplitFused);
+    return dtype == DCS_F32 ? launch_split_k<float>(s, c, x, y, jxy, jz, h, t->num_bonds, k, variant, stream)
+                            : launch_split_k<double>(s, c, x, y, jxy, jz, h, t->num_bonds, k, variant, stream);
 }
 
 // DCS_AUTOTUNE=0 in the environment (read at every call) keeps the default form.
 bool autotune_enabled() {
     const char *e = getenv("DCS_AUTOTUNE");
     return !(e && e[0] == '0');
+}
+
+// The default form: the staged split, or (DCS_SPLIT_FUSED=1, read at every call)
+// the split form whose rows pass also applies the left family.
+int default_form() {
+    const char *e = getenv("DCS_SPLIT_FUSED");
+    return (e && e[0] == '1') ? kFormSplitFused : kFormSplitStaged;
 }
 
 // Autotuner: the first product of a (terms, dtype, k) on a split sector times
@@ -157,7 +173,7 @@ int tuned_form(dcs_sector *s, const dcs_terms *t, const SplitRows &c, const doub
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (!autotune_enabled() || hipStreamIsCapturing(stream, &cs) != hipSuccess ||
         cs != hipStreamCaptureStatusNone)
-        return kFormSplitStaged;
+        return default_form();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (check_hip(hipEventCreate(&e0), "autotune event") || check_hip(hipEventCreate(&e1), "autotune event")) {
         if (e0) hipEventDestroy(e0);

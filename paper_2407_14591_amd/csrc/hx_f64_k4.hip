@@ -10,7 +10,7 @@ template int launch_hx_t<uint64_t, double, 4, 8>(const dcs_sector *, HxParams &,
 }  // namespace hx
 namespace sp {
 template int launch_split_t<double, 4>(dcs_sector *, const SplitRows &, const void *, void *,
-                                     const double *, const double *, const double *, int, bool,
+                                     const double *, const double *, const double *, int, int,
                                      hipStream_t);
 }  // namespace sp
 }  // namespace dcs

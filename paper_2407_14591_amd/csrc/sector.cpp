@@ -331,6 +331,7 @@ void free_rows(SplitRows &c) {
     hipFree(c.d_runs);
     hipFree(c.d_clstart);
     hipFree(c.d_clsize);
+    hipFree(c.d_lrun);
     hipFree(c.d_diag);
     c = SplitRows();
 }

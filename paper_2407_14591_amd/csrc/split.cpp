@@ -222,6 +222,15 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
         }
     }
     DeviceGuard dg(s->device);
+    // the left family with every target as a run start (bond << 48 | run), for the
+    // rows pass that applies the left family itself
+    std::vector<uint64_t> lrun(lent.size());
+    for (uint32_t g = 0; g < li.count; ++g)
+        for (uint32_t q = lptr[g]; q < lptr[g + 1]; ++q) {
+            const uint64_t e = lent[q];
+            lrun[q] = (e >> 63) ? ((e & (0xFFull << 48)) | li.h_runs[clstart[cl_of[g]] + (uint32_t)(e & 0xFFFFu)])
+                                : e;
+        }
     auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
         if (check_hip(hipMalloc(dst, bytes ? bytes : 16), "hipMalloc split tables")) return false;
         if (bytes && check_hip(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), "copy split tables"))
@@ -236,6 +245,7 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
               up((void **)&c.d_runs, li.h_runs.data(), li.h_runs.size() * sizeof(uint64_t)) &&
               up((void **)&c.d_clstart, clstart.data(), clstart.size() * sizeof(uint32_t)) &&
               up((void **)&c.d_clsize, clsize.data(), clsize.size() * sizeof(uint32_t)) &&
+              up((void **)&c.d_lrun, lrun.data(), lrun.size() * sizeof(uint64_t)) &&
               // diagonal of both sides, then the per-call coupling factors (1024 doubles + 1024 floats)
               check_hip(hipMalloc(&c.d_diag, ((li.count + li.rcount + 1) / 2 * 2 + 1536) * sizeof(double)),
                         "hipMalloc split diagonal") == DCS_OK;

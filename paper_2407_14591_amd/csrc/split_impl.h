@@ -204,6 +204,8 @@ struct RowParams {
     const uint64_t *runs, *xl;
     const uint16_t *vo, *xo;
     const double *dl, *dr;
+    const uint32_t *lptr;  // left family (the fused form): entries of every left configuration
+    const uint64_t *lrun;  // bond << 48 | run start of the target
     uint32_t *counters;
     uint64_t xbase[9];  // tile range of every XCD
     uint32_t count, rcount;
@@ -256,7 +258,10 @@ __device__ __forceinline__ Acc<T, K> lds_row(const char *lds, uint32_t row) {
     return v;
 }
 
-template <typename T, int K>
+// LEFT: the pass also applies the left family (the fused form, no column pass):
+// a left bond maps the tile's run onto another run of the same block, row r onto
+// row r, so its gathers are contiguous across the wave.
+template <typename T, int K, bool LEFT>
 __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_arg) {
     (void)P_arg;
     const RowParams &P = kernel_arg0<RowParams>();
@@ -265,6 +270,7 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
     extern __shared__ __align__(16) char rows_lds[];
     __shared__ T ramp[kAmpCross - kAmpRight];
     __shared__ T xamp[kJzCross - kAmpCross], xjz[kAmpBond - kJzCross];
+    __shared__ T lamp[LEFT ? kMaxBonds : 1];
     __shared__ uint32_t slots[2];
     {
         const T *A = reinterpret_cast<const T *>(P.amp);
@@ -277,6 +283,8 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
             else
                 xjz[q - kJzCross] = v;
         }
+        if constexpr (LEFT)
+            for (int q = threadIdx.x; q < kMaxBonds; q += kThreads) lamp[q] = A[kAmpBond + q];
     }
     const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
     T *__restrict__ y = reinterpret_cast<T *>(P.y);
@@ -399,6 +407,25 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
             }
 #pragma unroll
             for (int u = 0; u < B::R; ++u) hx::fma_acc<T, K>(acc, ramp[q0 + u], xv[u]);
+        }
+        if constexpr (LEFT) {
+            // left family: B::R target runs per batch (wave-uniform list), row r of each;
+            // lanes past the run end read zeros
+            const uint32_t q1 = ro(P.lptr)[gl + 1];
+            for (uint32_t q0 = ro(P.lptr)[gl]; q0 < q1; q0 += B::R) {
+                Acc<T, K> xv[B::R];
+                T a[B::R];
+#pragma unroll
+                for (int u = 0; u < B::R; ++u) {
+                    const bool ok = q0 + u < q1;  // uniform
+                    const uint64_t e = ro(P.lrun)[ok ? q0 + u : q0];
+                    const auto rl = rsrc(x + (e & 0xFFFFFFFFFFFFull) * K, ok ? ncols * RB : 0u);
+                    xv[u] = buf_load<T, K>(rl, r * RB);
+                    a[u] = ok ? lamp[(e >> 48) & 0xFFu] : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < B::R; ++u) hx::fma_acc<T, K>(acc, a[u], xv[u]);
+            }
         }
         if (active) {
             T *yr = y + (R + r) * K;
@@ -732,10 +759,15 @@ inline int split_grid(const dcs_sector *s, uint64_t tiles) {
     return (int)(w ? w : 8);
 }
 
-// staged: allow the staged-run rows pass (rows of at most 8 bytes whose runs fit LDS)
+// Variants of the split product: the staged-run rows pass allowed (rows of at
+// most 8 bytes whose runs fit LDS), the rows pass from HBM, or the rows pass
+// that also applies the left family (no column pass).
+constexpr int kSplitStagedOk = 0, kSplitGlobal = 1, kSplitFused = 2;
+
 template <typename T, int K>
 int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, const double *jxy,
-                   const double *jz, const double *h, int nbonds, bool staged_ok, hipStream_t stream) {
+                   const double *jz, const double *h, int nbonds, int variant, hipStream_t stream) {
+    const bool staged_ok = variant == kSplitStagedOk, fused = variant == kSplitFused;
     const LeftInfo &li = s->left;
     const uint32_t count = (uint32_t)li.count, rcount = (uint32_t)li.rcount;
     double *amp64 = c.d_diag + (count + rcount + 1) / 2 * 2;  // 16-byte aligned after the diagonal
@@ -844,13 +876,16 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
         if (!staged) {
             P.nRloc = c.nRloc;
             P.margin = c.margin;
+            P.lptr = c.d_lptr;
+            P.lrun = c.d_lrun;
             const size_t wl = P.nRloc > 0 ? (size_t)(kThreads + 2 * c.margin + 1) * RowBatch<T, K>::RB : 0;
-            auto kern = split_rows_kernel<T, K>;
+            auto kern = fused ? split_rows_kernel<T, K, true> : split_rows_kernel<T, K, false>;
             if (int r = ensure_lds(kern, wl)) return r;
             kern<<<split_grid(s, tiles), kThreads, wl, stream>>>(P);
             if (int r = check_hip(hipGetLastError(), "split rows launch")) return r;
         }
     }
+    if (fused) return DCS_OK;  // the rows pass applied the left family
     // 3. left family: tiles of one cluster of runs at one 1 KiB chunk, chunk major
     {
         ColParams P;

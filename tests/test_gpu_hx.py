@@ -177,14 +177,16 @@ def test_headline_workload_L32_sampled(dt):
     (12, 0, [6, 6], 1, torch.float64), (12, 12, [6, 6], 2, torch.float32),
     (12, 1, [4, 4, 4], 4, torch.float64), (13, 12, [3, 3, 3, 4], 1, torch.float32),
     (14, 2, [7, 7], 8, torch.float32), (16, 8, [4, 4, 4, 4], 2, torch.float32)])
-@pytest.mark.parametrize("staged", ["1", "0"])
+@pytest.mark.parametrize("staged", ["1", "0", "fused"])
 def test_split_small(monkeypatch, L, n, split, k, dt, staged):
     """The split product (rows for the bonds right of and across the cut, column
-    chunks for the bonds left of it) forced on small sectors, against the oracle;
-    random bond graphs put many bonds across the cut, and n = 0, 1, L-1, L give
-    runs of length one."""
+    chunks for the bonds left of it; or the fused form, whose row pass also
+    applies the bonds left of the cut) forced on small sectors, against the
+    oracle; random bond graphs put many bonds across the cut, and n = 0, 1, L-1,
+    L give runs of length one."""
     monkeypatch.setenv("DCS_SPLIT_MIN_DIM", "0")
-    monkeypatch.setenv("DCS_SPLIT_LDS", staged)
+    monkeypatch.setenv("DCS_SPLIT_LDS", "1" if staged == "fused" else staged)
+    monkeypatch.setenv("DCS_SPLIT_FUSED", "1" if staged == "fused" else "0")
     monkeypatch.setenv("DCS_AUTOTUNE", "0")  # keep the split form (the tuner may pick another)
     rng = np.random.default_rng(L + k)
     b = BruteSector(2, L, n, split)
@@ -199,11 +201,12 @@ def test_split_small(monkeypatch, L, n, split, k, dt, staged):
             assert rel_err(y.cpu().double().numpy(), y_ref) <= TOL[dt], (L, n, split, k, dt, use_h)
 
 
-@pytest.mark.parametrize("staged", ["1", "0"])
+@pytest.mark.parametrize("staged", ["1", "0", "fused"])
 def test_split_L26_all_rows(monkeypatch, staged):
     """L=26, n=13 (10,400,600 states, split 8/9/9): the split product on every row,
-    with and without the runs of x staged in LDS."""
-    monkeypatch.setenv("DCS_SPLIT_LDS", staged)
+    with and without the runs of x staged in LDS, and the fused form."""
+    monkeypatch.setenv("DCS_SPLIT_LDS", "1" if staged == "fused" else staged)
+    monkeypatch.setenv("DCS_SPLIT_FUSED", "1" if staged == "fused" else "0")
     monkeypatch.setenv("DCS_AUTOTUNE", "0")
     L, n, sp = 26, 13, [8, 9, 9]
     s = dq.Sector(L, n, 2, sp)
@@ -220,7 +223,7 @@ def test_split_L26_all_rows(monkeypatch, staged):
 @pytest.mark.parametrize("k", [1, 2, 4, 8])
 def test_split_matches_single_pass_L24(monkeypatch, k):
     """L=24, n=12 (2,704,156 states) with the split view forced on: the split product
-    (staged and unstaged runs) against the single pass, both ways in FP64 and FP32."""
+    (staged and unstaged runs, fused form) against the single pass, in FP64 and FP32."""
     monkeypatch.setenv("DCS_SPLIT_MIN_DIM", "0")
     monkeypatch.setenv("DCS_AUTOTUNE", "0")
     L, n = 24, 12
@@ -235,14 +238,14 @@ def test_split_matches_single_pass_L24(monkeypatch, k):
                         dtype=torch.float64).to(dt)
         out = {}
         for mode, env in (("single", {"DCS_SPLIT": "0"}), ("staged", {"DCS_SPLIT_LDS": "1"}),
-                          ("global", {"DCS_SPLIT_LDS": "0"})):
-            for key in ("DCS_SPLIT", "DCS_SPLIT_LDS"):
+                          ("global", {"DCS_SPLIT_LDS": "0"}), ("fused", {"DCS_SPLIT_FUSED": "1"})):
+            for key in ("DCS_SPLIT", "DCS_SPLIT_LDS", "DCS_SPLIT_FUSED"):
                 monkeypatch.delenv(key, raising=False)
             for key, v in env.items():
                 monkeypatch.setenv(key, v)
             out[mode] = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), x,
                                              h=dev_f64(h)).double().cpu().numpy()
-        for mode in ("staged", "global"):
+        for mode in ("staged", "global", "fused"):
             assert rel_err(out[mode], out["single"]) <= TOL[dt], (k, dt, mode)
 
 
@@ -313,8 +316,8 @@ def test_autotuned_form(monkeypatch, k, dt):
     assert torch.equal(y1, y2)
     assert rel_err(y1.double().cpu().numpy(), y_ref) <= TOL[dt]
     monkeypatch.setenv("DCS_AUTOTUNE", "0")
-    for env in ({"DCS_SPLIT_LDS": "1"}, {"DCS_SPLIT_LDS": "0"}, {"DCS_SPLIT": "0"}):
-        for key in ("DCS_SPLIT", "DCS_SPLIT_LDS"):
+    for env in ({"DCS_SPLIT_LDS": "1"}, {"DCS_SPLIT_LDS": "0"}, {"DCS_SPLIT_FUSED": "1"}, {"DCS_SPLIT": "0"}):
+        for key in ("DCS_SPLIT", "DCS_SPLIT_LDS", "DCS_SPLIT_FUSED"):
             monkeypatch.delenv(key, raising=False)
         for key, v in env.items():
             monkeypatch.setenv(key, v)
