@@ -653,7 +653,7 @@ static_assert(sizeof(ColParams) <= 4096, "kernel arguments are limited to 4 KiB"
 
 constexpr int kColThreads = 1024;  // 16 waves share one staged cluster
 constexpr int kColWaves = kColThreads / 64;
-constexpr int kColBatch = 8;              // gathers in flight per wave
+constexpr int kColBatch = 4;              // gathers in flight per wave (2, 6, 8, 16 measured slower)
 constexpr uint32_t kColLaneBytes = 16;    // bytes of x per lane and gather
 constexpr uint32_t kColWaveBytes = 64 * kColLaneBytes;
 
