@@ -487,7 +487,7 @@ __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_ker
     static_assert(RB <= 8, "staged runs hold rows of at most 8 bytes");
     constexpr int NT = lds_rows_threads<T, K>();
     constexpr int XF = 32;  // bonds across the cut whose gather descriptors are set up once per run
-    constexpr int XB = 4;   // of those, gathers in flight per batch
+    constexpr int XB = 2;   // of those, gathers in flight per batch (1, 4 and 8 measured slower)
     extern __shared__ __align__(16) char dyn[];
     V *xr = reinterpret_cast<V *>(dyn);
     __shared__ uint4 xinfo[XF];  // per bond across the cut: run base (lo, hi), bytes | bit << 31
