@@ -214,10 +214,13 @@ int dcs_adjoint_workspace_size(const dcs_sector *sector, const dcs_terms *terms,
  * One pass ranks every reached state once and uses it for both g and x.  On a
  * sector with a split view whose products run on the split tables (the form
  * the autotuner keeps for this terms object and dtype at k = 1, see
- * dcs_hamiltonian_apply, including its first-call timing), d_grad_x comes from
- * that product applied to g and the pass forms only the sums (it gathers x,
- * not g).  The sums are reduced per workgroup into d_workspace and then in a
- * fixed order, so the result is deterministic.  The coupling gradients are
+ * dcs_hamiltonian_apply, including its first-call timing), d_grad_x can also
+ * come from that product applied to g, the pass then forming only the sums (it
+ * gathers x, not g); the first call for a (terms, dtype) times both ways (each
+ * twice, HIP events, synchronising the stream) and keeps the faster (the split
+ * way inside stream capture or with DCS_AUTOTUNE=0).  The sums are reduced per
+ * workgroup into d_workspace and then in a fixed order, so the result is
+ * deterministic.  The coupling gradients are
  * FP64 whatever dtype is.  d_grad_x may be NULL (only coupling gradients);
  * it must not overlap d_x or d_g.
  */

@@ -238,37 +238,12 @@ size_t adjoint_ws_bytes(const dcs_sector *s, const dcs_terms *t) {
     return (size_t)g.wgs * (2 * t->num_bonds + s->desc.L) * sizeof(double);
 }
 
-int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
-                   const double *h, int dtype, const void *x, const void *g, void *gx,
-                   double *gjxy, double *gjz, double *gh, void *ws, size_t ws_bytes,
-                   hipStream_t stream) {
-    DeviceGuard dg(s->device);
-    // grad_x = H g is a product (H is real symmetric).  Where the sector's
-    // products run on the split tables, that product computes it and the adjoint
-    // kernel only forms the coupling and field sums (it gathers x, not g).  Where
-    // the single pass is the faster product, the fused kernel does both.
-    if (gx && s->left.K > 0 && s->desc.Q == 2 && split_enabled()) {
-        if (t->max_site >= s->desc.L)
-            return set_error(DCS_EINVAL, "bond site %d outside the sector's %d sites", t->max_site,
-                             s->desc.L);
-        clear_error();
-        dcs_sector *sm = const_cast<dcs_sector *>(s);
-        const SplitRows *c = split_rows(sm, t);
-        if (c) {
-            bool ran = false;
-            const int form = tuned_form(sm, t, *c, jxy, jz, h, dtype, 1, g, gx, stream, &ran);
-            if (form < 0) return DCS_EHIP;
-            if (form != kFormSingle) {
-                if (!ran) {
-                    if (int r = launch_form(sm, t, *c, form, jxy, jz, h, dtype, 1, g, gx, stream))
-                        return r;
-                }
-                gx = nullptr;
-            }
-        } else if (dcs_last_error()[0]) {
-            return DCS_EHIP;
-        }
-    }
+namespace {
+
+// The adjoint pass (the fused kernel when gx is given, else the sums only).
+int adjoint_pass(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
+                 const double *h, int dtype, const void *x, const void *g, void *gx, double *gjxy,
+                 double *gjz, double *gh, void *ws, hipStream_t stream) {
     const int nmax = pick_nmax(s);
     HxParams P;
     if (int r = fill_params(s, t, nmax, jxy, jz, h, P)) return r;
@@ -277,7 +252,6 @@ int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, c
     P.gx = gx;
     P.far_below = s->desc.dim >= (1ull << 22) ? s->desc.N / 2 : 0;
     P.partials = (double *)ws;
-    (void)ws_bytes;
     if (s->wide) {
         if (dtype == DCS_F32)
             return nmax == 4 ? launch_adj_t<uint64_t, float, 4>(s, P, gjxy, gjz, gh, stream)
@@ -290,6 +264,88 @@ int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, c
                          : launch_adj_t<uint32_t, float, 8>(s, P, gjxy, gjz, gh, stream);
     return nmax == 4 ? launch_adj_t<uint32_t, double, 4>(s, P, gjxy, gjz, gh, stream)
                      : launch_adj_t<uint32_t, double, 8>(s, P, gjxy, gjz, gh, stream);
+}
+
+// Milliseconds of one run of fn on the stream (HIP events, synchronising); -1 on error.
+template <typename F>
+float time_on_stream(F &&fn, hipStream_t stream) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return -1.f;
+    }
+    float ms = -1.f;
+    if (hipEventRecord(e0, stream) == hipSuccess && fn() == DCS_OK &&
+        hipEventRecord(e1, stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        ms = -1.f;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return ms;
+}
+
+}  // namespace
+
+int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
+                   const double *h, int dtype, const void *x, const void *g, void *gx,
+                   double *gjxy, double *gjz, double *gh, void *ws, size_t ws_bytes,
+                   hipStream_t stream) {
+    DeviceGuard dg(s->device);
+    (void)ws_bytes;
+    auto fused = [&]() {
+        return adjoint_pass(s, t, jxy, jz, h, dtype, x, g, gx, gjxy, gjz, gh, ws, stream);
+    };
+    // grad_x = H g is a product (H is real symmetric).  Where the sector's
+    // products run on the split tables, that product can compute it, and the
+    // adjoint pass then forms only the coupling and field sums (it gathers x, not
+    // g).  Which of the two ways is faster depends on the sector: the autotuner
+    // times both on the first call for a (terms, dtype) and keeps the faster.
+    if (!(gx && s->left.K > 0 && s->desc.Q == 2 && split_enabled())) return fused();
+    if (t->max_site >= s->desc.L)
+        return set_error(DCS_EINVAL, "bond site %d outside the sector's %d sites", t->max_site,
+                         s->desc.L);
+    clear_error();
+    dcs_sector *sm = const_cast<dcs_sector *>(s);
+    const SplitRows *c = split_rows(sm, t);
+    if (!c) return dcs_last_error()[0] ? DCS_EHIP : fused();
+    bool ran = false;
+    const int form = tuned_form(sm, t, *c, jxy, jz, h, dtype, 1, g, gx, stream, &ran);
+    if (form < 0) return DCS_EHIP;
+    if (form == kFormSingle) return fused();
+    auto split_way = [&]() {
+        if (int r = launch_form(sm, t, *c, form, jxy, jz, h, dtype, 1, g, gx, stream)) return r;
+        return adjoint_pass(s, t, jxy, jz, h, dtype, x, g, nullptr, gjxy, gjz, gh, ws, stream);
+    };
+    const uint64_t key = tuned_key(t, dtype, 0);  // k = 0: the adjoint's entry
+    LeftInfo &li = sm->left;
+    int way = -1;
+    {
+        std::lock_guard<std::mutex> lk(*li.rows_lock);
+        auto it = li.tuned.find(key);
+        if (it != li.tuned.end()) way = it->second;
+    }
+    if (way < 0) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (!autotune_enabled() || hipStreamIsCapturing(stream, &cs) != hipSuccess ||
+            cs != hipStreamCaptureStatusNone)
+            return split_way();
+        float best = 0.f;
+        for (int w = 0; w < 2; ++w) {
+            float ms = 0.f;
+            for (int rep = 0; rep < 2; ++rep) {
+                ms = w == 0 ? time_on_stream(fused, stream) : time_on_stream(split_way, stream);
+                if (ms < 0.f) return dcs_last_error()[0] ? DCS_EHIP : set_error(DCS_EHIP, "adjoint autotune timing");
+            }
+            if (w == 0 || ms < best) {
+                best = ms;
+                way = w;
+            }
+        }
+        std::lock_guard<std::mutex> lk(*li.rows_lock);
+        li.tuned[key] = way;
+    }
+    return way == 0 ? fused() : split_way();
 }
 
 }  // namespace dcs
