@@ -148,12 +148,14 @@ def test_hellmann_feynman_finite_differences_L24():
         assert abs(fd - gz[b]) <= 1e-6 * max(1.0, abs(gz[b]))
 
 
-def test_adjoint_on_split_products(monkeypatch):
-    """L=26, n=13 with the split product for grad_x (autotuner off: the staged
-    split form): grad_x equals the product H g bit for bit, the coupling and
-    field sums equal those of the fused single-pass adjoint bit for bit, and
-    three bonds' sums match the C oracle."""
-    monkeypatch.setenv("DCS_AUTOTUNE", "0")
+@pytest.mark.parametrize("autotune", ["0", "1"])
+def test_adjoint_on_split_products(monkeypatch, autotune):
+    """L=26, n=13.  Autotuner off: grad_x comes from the staged split product and
+    equals the product H g bit for bit.  Autotuner on: the first call times the
+    fused pass against split product plus sums pass; grad_x matches H g.  Either
+    way the coupling and field sums equal those of the fused single-pass adjoint
+    bit for bit, and three bonds' sums match the C oracle."""
+    monkeypatch.setenv("DCS_AUTOTUNE", autotune)
     L, n = 26, 13
     bonds = synth.chain_bonds(L, 1) + synth.chain_bonds(L, 2)[:5]
     J, Dl = synth.random_couplings(len(bonds), seed=11)
@@ -167,7 +169,12 @@ def test_adjoint_on_split_products(monkeypatch):
         xd, gd = torch.tensor(x, device=DEV).to(dt), torch.tensor(g, device=DEV).to(dt)
         args = (s, t, dev_f64(jxy), dev_f64(jz), xd, gd)
         gx, gj, gz, gh = dq.hamiltonian_apply_adjoint(*args, h=dev_f64(hf), want_grad_h=True)
-        assert torch.equal(gx, dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), gd, h=dev_f64(hf)))
+        hg = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), gd, h=dev_f64(hf))
+        if autotune == "0":
+            assert torch.equal(gx, hg)
+        assert rel_err(gx.double().cpu().numpy(), hg.double().cpu().numpy()) <= tol
+        again = dq.hamiltonian_apply_adjoint(*args, h=dev_f64(hf), want_grad_h=True)
+        assert all(torch.equal(a, b) for a, b in zip((gx, gj, gz, gh), again))
         monkeypatch.setenv("DCS_SPLIT", "0")
         gx1, gj1, gz1, gh1 = dq.hamiltonian_apply_adjoint(*args, h=dev_f64(hf), want_grad_h=True)
         monkeypatch.delenv("DCS_SPLIT")
