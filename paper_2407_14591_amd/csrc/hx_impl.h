@@ -249,8 +249,9 @@ __device__ __forceinline__ void apply_class(const PT &P, const SectorDesc &sd,
         const int beg = P.cls_beg[cls], end = P.cls_beg[cls + 1];
         if constexpr (Q2) {
             // batches of NB bonds; the last batch of a class is cut by a uniform guard,
-            // its unused slots gather x[row] with amplitude 0
-            constexpr int NB = K <= 2 ? 8 : 4;
+            // its unused slots gather x[row] with amplitude 0.  NB measured: 4 for FP32
+            // and 2 for FP64 rows of one or two values (8 cost up to 13% more)
+            constexpr int NB = K <= 2 ? (sizeof(T) == 8 ? 2 : 4) : 4;
             for (int t = beg; t < end; t += NB) {
                 T a[NB];
                 IdxT c[NB];
