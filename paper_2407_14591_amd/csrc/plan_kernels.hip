@@ -140,6 +140,13 @@ struct dcs_plan {
         const double *jxy, *jz;
     };
     std::vector<Own> own;
+    // After the first apply of a dtype (whose products the autotuner times on the
+    // caller's stream), the own products run on kSideStreams more streams beside
+    // it, forked and joined with events, so that their launch tails overlap.
+    static constexpr int kSideStreams = 3;
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork = nullptr, join[kSideStreams] = {};
+    bool applied[2] = {false, false};  // per dtype (F32, F64)
 };
 
 static void plan_free(dcs_plan *p) {
@@ -154,6 +161,14 @@ static void plan_free(dcs_plan *p) {
     hipFree(p->d_tiles);
     hipFree(p->d_counters);
     hipHostFree(p->h_io);
+    for (int i = 0; i < dcs_plan::kSideStreams; ++i) {
+        if (p->side[i]) {
+            hipStreamSynchronize(p->side[i]);
+            hipStreamDestroy(p->side[i]);
+        }
+        if (p->join[i]) hipEventDestroy(p->join[i]);
+    }
+    if (p->fork) hipEventDestroy(p->fork);
     delete p;
 }
 
@@ -218,6 +233,13 @@ extern "C" int dcs_plan_create(int nsec, dcs_sector *const *secs, dcs_terms *con
     if (!r) r = check_hip(hipHostMalloc(&p->h_io, nsec * sizeof(PlanIO)), "hipHostMalloc");
     if (!r) r = check_hip(hipMalloc(&p->d_counters, 8 * sizeof(uint32_t)), "hipMalloc plan counters");
     if (!r) r = check_hip(hipEventCreateWithFlags(&p->io_copied, hipEventDisableTiming), "event");
+    if (!r && p->own.size() > 1) {  // default priority, not synchronising with the null stream
+        r = check_hip(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming), "event");
+        for (int i = 0; i < dcs_plan::kSideStreams && !r; ++i) {
+            r = check_hip(hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking), "plan stream");
+            if (!r) r = check_hip(hipEventCreateWithFlags(&p->join[i], hipEventDisableTiming), "event");
+        }
+    }
     if (!r)
         r = check_hip(hipMemcpy(p->d_secs, hs.data(), nsec * sizeof(PlanSector), hipMemcpyHostToDevice),
                       "copy plan");
@@ -294,8 +316,33 @@ extern "C" int dcs_plan_apply(const dcs_plan *pc, int dtype, const void *const *
                           : (p->nmax == 4 ? launch_plan<double, 4>(p, stream) : launch_plan<double, 8>(p, stream));
         if (r) return r;
     }
-    for (const auto &o : p->own)
-        if (int r = launch_hx(o.sector, o.terms, o.jxy, o.jz, nullptr, dtype, 1, xs[o.index], ys[o.index], stream))
-            return r;
+    const int di = dtype == DCS_F32 ? 0 : 1;
+    if (!p->applied[di] || !p->fork) {  // the first apply of a dtype: one stream (autotuner timing)
+        for (const auto &o : p->own)
+            if (int r = launch_hx(o.sector, o.terms, o.jxy, o.jz, nullptr, dtype, 1, xs[o.index], ys[o.index], stream))
+                return r;
+        p->applied[di] = true;
+        return DCS_OK;
+    }
+    // fork: the side streams wait for the work queued so far on the caller's stream
+    if (int r = check_hip(hipEventRecord(p->fork, stream), "plan fork")) return r;
+    for (int i = 0; i < dcs_plan::kSideStreams; ++i)
+        if (int r = check_hip(hipStreamWaitEvent(p->side[i], p->fork, 0), "plan fork wait")) return r;
+    // own products dealt round robin over the caller's stream and the side streams
+    // (each sector has its own counters and tables, so they may run together)
+    int r = DCS_OK;
+    for (size_t q = 0; q < p->own.size() && !r; ++q) {
+        const auto &o = p->own[q];
+        const int lane = (int)(q % (dcs_plan::kSideStreams + 1));
+        hipStream_t st = lane == 0 ? stream : p->side[lane - 1];
+        r = launch_hx(o.sector, o.terms, o.jxy, o.jz, nullptr, dtype, 1, xs[o.index], ys[o.index], st);
+    }
+    // join, also after a failed launch, so that no side stream is left behind
+    for (int i = 0; i < dcs_plan::kSideStreams; ++i) {
+        const int rr = check_hip(hipEventRecord(p->join[i], p->side[i]), "plan join");
+        const int rw = rr ? rr : check_hip(hipStreamWaitEvent(stream, p->join[i], 0), "plan join wait");
+        if (!r) r = rw;
+    }
+    if (r) return r;
     return DCS_OK;
 }
