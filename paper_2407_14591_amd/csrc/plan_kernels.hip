@@ -310,14 +310,15 @@ extern "C" int dcs_plan_apply(const dcs_plan *pc, int dtype, const void *const *
         return r;
     if (int r = check_hip(hipEventRecord(p->io_copied, stream), "record plan io event")) return r;
     p->io_pending = true;
-    if (p->ntiles > 0) {
-        const int r = dtype == DCS_F32
-                          ? (p->nmax == 4 ? launch_plan<float, 4>(p, stream) : launch_plan<float, 8>(p, stream))
-                          : (p->nmax == 4 ? launch_plan<double, 4>(p, stream) : launch_plan<double, 8>(p, stream));
-        if (r) return r;
-    }
+    auto launch_core = [&]() -> int {
+        if (p->ntiles == 0) return DCS_OK;
+        return dtype == DCS_F32
+                   ? (p->nmax == 4 ? launch_plan<float, 4>(p, stream) : launch_plan<float, 8>(p, stream))
+                   : (p->nmax == 4 ? launch_plan<double, 4>(p, stream) : launch_plan<double, 8>(p, stream));
+    };
     const int di = dtype == DCS_F32 ? 0 : 1;
     if (!p->applied[di] || !p->fork) {  // the first apply of a dtype: one stream (autotuner timing)
+        if (int r = launch_core()) return r;
         for (const auto &o : p->own)
             if (int r = launch_hx(o.sector, o.terms, o.jxy, o.jz, nullptr, dtype, 1, xs[o.index], ys[o.index], stream))
                 return r;
@@ -328,14 +329,13 @@ extern "C" int dcs_plan_apply(const dcs_plan *pc, int dtype, const void *const *
     if (int r = check_hip(hipEventRecord(p->fork, stream), "plan fork")) return r;
     for (int i = 0; i < dcs_plan::kSideStreams; ++i)
         if (int r = check_hip(hipStreamWaitEvent(p->side[i], p->fork, 0), "plan fork wait")) return r;
-    // own products dealt round robin over the caller's stream and the side streams
+    // the one launch on the caller's stream, the own products on the side streams
     // (each sector has its own counters and tables, so they may run together)
-    int r = DCS_OK;
+    int r = launch_core();
     for (size_t q = 0; q < p->own.size() && !r; ++q) {
         const auto &o = p->own[q];
-        const int lane = (int)(q % (dcs_plan::kSideStreams + 1));
-        hipStream_t st = lane == 0 ? stream : p->side[lane - 1];
-        r = launch_hx(o.sector, o.terms, o.jxy, o.jz, nullptr, dtype, 1, xs[o.index], ys[o.index], st);
+        r = launch_hx(o.sector, o.terms, o.jxy, o.jz, nullptr, dtype, 1, xs[o.index], ys[o.index],
+                      p->side[q % dcs_plan::kSideStreams]);
     }
     // join, also after a failed launch, so that no side stream is left behind
     for (int i = 0; i < dcs_plan::kSideStreams; ++i) {
@@ -343,6 +343,5 @@ extern "C" int dcs_plan_apply(const dcs_plan *pc, int dtype, const void *const *
         const int rw = rr ? rr : check_hip(hipStreamWaitEvent(stream, p->join[i], 0), "plan join wait");
         if (!r) r = rw;
     }
-    if (r) return r;
-    return DCS_OK;
+    return r;
 }
