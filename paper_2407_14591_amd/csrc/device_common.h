@@ -99,7 +99,11 @@ __device__ __forceinline__ uint32_t small_quotient(IdxT rem, IdxT str, float rcp
 // peel off the offset and stride*index_k, read the word from the inverse table;
 // the last subsystem takes the remainder.  idx must be < dim.
 // Also returns, per subsystem, the word, lambda_k and the contribution c_k.
-template <typename IdxT, int NMAX>
+// COUNT: find each particle count by counting the offsets at or below the
+// remainder (every entry of the row read, independent loads) instead of a scan
+// that stops at the first larger one (fewer reads, each waiting on the last);
+// the batched unrank is faster with the count, the H*x decode with the scan.
+template <typename IdxT, int NMAX, bool COUNT = false>
 __device__ __forceinline__ uint64_t unrank_state(const SectorDesc &sd, const Tables<IdxT> &T,
                                                  IdxT idx, uint32_t *w_out, int *lam_out,
                                                  IdxT *c_out) {
@@ -113,7 +117,13 @@ __device__ __forceinline__ uint64_t unrank_state(const SectorDesc &sd, const Tab
             const int hi = min(sd.mk[k], sd.n - lam);
             const uint32_t row = sd.dec_row0[k] + (uint32_t)(lam - sd.lam_lo[k]) * (sd.mk[k] + 1);
             int m = lo;
-            while (m < hi && rem >= T.doff[row + m + 1]) ++m;
+            if constexpr (COUNT) {  // the offsets rise with m: m - lo = entries of [lo, hi) <= rem
+                const int mk = sd.mk[k];
+#pragma unroll 4
+                for (int i = 0; i < mk; ++i) m += (i >= lo && i < hi && rem >= T.doff[row + i + 1]) ? 1 : 0;
+            } else {
+                while (m < hi && rem >= T.doff[row + m + 1]) ++m;
+            }
             const IdxT off = T.doff[row + m];
             rem -= off;
             IdxT prod;

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kThreads) void unrank_kernel(SectorDesc sd_arg, con
             const uint64_t v = use_first ? first + i : idx[i];
             bad = v >= sd.dim;
             out[i] = bad ? DCS_INVALID_INDEX
-                         : unrank_state<IdxT, kMaxSub>(sd, T, (IdxT)v, nullptr, nullptr, nullptr);
+                         : unrank_state<IdxT, kMaxSub, true>(sd, T, (IdxT)v, nullptr, nullptr, nullptr);
         }
         count_bad(nbad, bad);
     }
