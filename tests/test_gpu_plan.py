@@ -116,3 +116,25 @@ def test_batched_workload_with_split_sectors():
             ref = native.hx_rows(ns, native.NativeTerms(bonds, jxy, jz), x.cpu().numpy(), rows)
             got = y[torch.tensor(rows.astype(np.int64), device=DEV)].double().cpu().numpy()
             assert rel_err(got, ref) <= 1e-5, specs[idx]
+
+
+def test_split_sectors_alternating_dtypes():
+    """Applies of one plan alternating FP32 and FP64 (the first of each dtype on the
+    caller's stream, later ones with the split sectors on the plan's streams): every
+    sector's y equals its own product bit for bit, every time."""
+    specs = [(2, 24, n) for n in (9, 12, 15)] + [(2, 22, n) for n in range(0, 23, 4)] + [(3, 12, 12)]
+    items = []
+    for Q, L, n in specs:
+        bonds, jxy, jz = synth.xxz_chain(L, 1.0, 1.0)
+        items.append((dq.Sector(L, n, Q), dq.Terms(bonds), dev_f64(jxy), dev_f64(jz)))
+    assert sum(1 for s, _, _, _ in items if s.dim >= (1 << 20)) == 3
+    plan = dq.Plan(items)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(11)
+    xs64 = [torch.randn(s.dim, generator=g, device=DEV, dtype=torch.float64) for s, _, _, _ in items]
+    for rep, dt in enumerate((torch.float32, torch.float64, torch.float32, torch.float64, torch.float32)):
+        xs = [x.to(dt) for x in xs64]
+        ys = plan.apply(xs)
+        torch.cuda.synchronize()
+        for (s, t, j, z), x, y in zip(items, xs, ys):
+            assert torch.equal(y, dq.hamiltonian_apply(s, t, j, z, x)), (rep, dt, s.L, s.n)
