@@ -8,10 +8,12 @@ whole sector: every row decoded (Alg. iii), every bond applied, every reached
 state ranked (eq. index), x gathered, y written.
 
 Three forms are timed: the batched FP32 block of k=8 columns (the headline
-`value`), FP32 k=1, and the plain FP64 k=1 product.  `value` counts sector
-states per second per column (dim * k / time).  One product is one call of
-dcs_hamiltonian_apply: on this sector the split product's launches (diagonal
-per side configuration, row pass, column pass).
+`value`), FP32 k=1, and the plain FP64 k=1 product.  `value` is sector states per
+second, dim / t, with t the median of the timed products (HIP events between
+consecutive products on the launch stream); the per-column rate dim * k / t is
+reported next to it.  One product is one call of dcs_hamiltonian_apply: on this
+sector the split product's launches (diagonal per side configuration, row pass,
+column pass, in the form the autotuner keeps; `roofline.kernel` names it).
 
 Besides the headline, `workloads` times the other measured cases of the
 method (skipped with --no-extras): rank and unrank of 2^24 random states of the
@@ -68,6 +70,8 @@ def read_traffic(variant: str):
 
 
 def time_variant(fn, stream, steps: int, warmup: int):
+    """Seconds of `steps` back-to-back launches of fn on `stream` (HIP events around
+    the whole loop), after `warmup` untimed launches."""
     import torch
     for _ in range(warmup):
         fn()
@@ -82,14 +86,37 @@ def time_variant(fn, stream, steps: int, warmup: int):
     return start.elapsed_time(end) / 1e3  # seconds for `steps` launches
 
 
+def time_steps(fn, stream, steps: int, warmup: int):
+    """Per-launch seconds of `steps` launches of fn: an event is recorded on `stream`
+    between consecutive launches, so every interval is one launch's device time."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for i in range(steps):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    return [ev[i].elapsed_time(ev[i + 1]) / 1e3 for i in range(steps)]
+
+
+def median(v):
+    v = sorted(v)
+    n = len(v)
+    return v[n // 2] if n % 2 else 0.5 * (v[n // 2 - 1] + v[n // 2])
+
+
 def extra_workloads(dq, synth, torch, steps: int, warmup: int):
-    """The other measured cases (dict of results); every input is seeded and synthetic."""
+    """The other measured cases (dict of results); every input is seeded and synthetic.
+    Times are medians of per-launch HIP-event intervals."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     out = {}
 
     def timed(fn, n=steps, w=warmup):
-        return time_variant(fn, stream, n, w) / n
+        return median(time_steps(fn, stream, max(n, 3), w))
 
     # rank and unrank of 2^24 uniformly random states of the L=32, n=16 sector (the paper's
     # random trial states: a uniform n-subset of the sites per state, drawn on the device)
@@ -106,8 +133,26 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
     per_u = timed(lambda: s.unrank(idx, out=back))
     assert torch.equal(back, states)
     out["rank_unrank_L32"] = {"states": cnt, "rank_ms": per_r * 1e3, "unrank_ms": per_u * 1e3,
-                              "rank_per_s": cnt / per_r, "unrank_per_s": cnt / per_u}
-    del states, idx, back, s
+                              "rank_per_s": cnt / per_r, "unrank_per_s": cnt / per_u,
+                              "rank_GBs": cnt * 16 / per_r / 1e9, "unrank_GBs": cnt * 16 / per_u / 1e9}
+    del states, idx, back
+
+    # FP32 adjoint on the L=32 sector: grad_x = H g and the 64 coupling sums
+    bonds, jxy, jz = synth.j1j2_chain(L, J1, J2, DELTA)
+    t = dq.Terms(bonds)
+    jd, zd = torch.tensor(jxy, device=dev), torch.tensor(jz, device=dev)
+    x = torch.randn(s.dim, generator=g, device=dev, dtype=torch.float32)
+    gv = torch.randn(s.dim, generator=g, device=dev, dtype=torch.float32)
+    per_f = timed(lambda: dq.hamiltonian_apply(s, t, jd, zd, x), n=max(3, steps // 2))
+    per_a = timed(lambda: dq.hamiltonian_apply_adjoint(s, t, jd, zd, x, gv), n=max(3, steps // 2))
+    out["adjoint_L32_f32"] = {"forward_ms": per_f * 1e3, "adjoint_ms": per_a * 1e3,
+                              "adjoint_over_forward": per_a / per_f,
+                              "adjoint_states_per_s": s.dim / per_a,
+                              "compulsory_bytes": s.dim * 12,
+                              "adjoint_compulsory_GBs": s.dim * 12 / per_a / 1e9,
+                              "frac_of_peak": s.dim * 12 / per_a / 1e9 / PEAK_HBM_GBS}
+    del x, gv, s, t
+    torch.cuda.empty_cache()
 
     # k=8 FP32 block on L=28, n=14 (40,116,600 rows), XXZ J = Delta = 1
     s = dq.Sector(28, 14, 2, [7, 7, 7, 7], device=0)
@@ -117,8 +162,10 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
     x = torch.randn((s.dim, 8), generator=g, device=dev, dtype=torch.float32)
     y = torch.empty_like(x)
     per = timed(lambda: dq.hamiltonian_apply(s, t, jd, zd, x, out=y))
-    out["hx_L28_f32k8"] = {"ms": per * 1e3, "states_per_s": s.dim * 8 / per,
-                           "achieved_GBs": s.dim * 8 * 2 * 4 / per / 1e9}
+    out["hx_L28_f32k8"] = {"ms": per * 1e3, "states_per_s": s.dim / per,
+                           "columns_per_s": s.dim * 8 / per,
+                           "achieved_GBs": s.dim * 8 * 2 * 4 / per / 1e9,
+                           "form": dq.hamiltonian_form(s, t, torch.float32, 8)}
     del x, y, s, t
 
     # fused adjoint on L=24, n=12, per-bond J_b, Delta_b (24 bonds), FP64
@@ -133,10 +180,11 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
     per_a = timed(lambda: dq.hamiltonian_apply_adjoint(s, t, jd, zd, x, gv))
     out["adjoint_L24_f64"] = {"forward_ms": per_f * 1e3, "adjoint_ms": per_a * 1e3,
                               "adjoint_states_per_s": s.dim / per_a,
-                              "adjoint_compulsory_GBs": s.dim * 24 / per_a / 1e9}
+                              "adjoint_compulsory_GBs": s.dim * 24 / per_a / 1e9,
+                              "frac_of_peak": s.dim * 24 / per_a / 1e9 / PEAK_HBM_GBS}
     del x, gv, s, t
 
-    # all sectors of L = 20..26 (spin 1/2, n = 0..L) and spin-1 L = 12..16 at Sz = 0, one launch
+    # all sectors of L = 20..26 (spin 1/2, n = 0..L) and spin-1 L = 12..16 at Sz = 0, one call
     items, xs, total = [], [], 0
     specs = [(2, ls, ns) for ls in (20, 22, 24, 26) for ns in range(ls + 1)]
     specs += [(3, ls, ls) for ls in range(12, 17)]
@@ -150,7 +198,8 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
     ys = [torch.empty_like(v) for v in xs]
     per = timed(lambda: plan.apply(xs, ys))
     out["plan_101_sectors_f32"] = {"sectors": len(items), "rows": total, "ms": per * 1e3,
-                                   "states_per_s": total / per}
+                                   "states_per_s": total / per,
+                                   "achieved_GBs": total * 8 / per / 1e9}
     del plan, items, xs, ys
 
     # 200 Lanczos steps on the L=32, n=16 J1-J2 sector (J2/J1 = 1/2: E0 = -3L/8 = -12)
@@ -167,7 +216,8 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         out[name] = {"steps": r["steps_done"], "seconds": el, "ms_per_step": el / r["steps_done"] * 1e3,
-                     "reorth": r["reorth"], "E0": r["eig"][0], "E0_error_vs_exact": r["eig"][0] + 12.0}
+                     "reorth": r["reorth"], "E0": r["eig"][0], "E0_exact": -12.0,
+                     "E0_error_vs_exact": r["eig"][0] + 12.0}
         del v0
         torch.cuda.empty_cache()
     del s, t
@@ -181,16 +231,19 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
     y = torch.empty_like(x)
     per = timed(lambda: dq.hamiltonian_apply(s, t, jd, zd, x, out=y), n=max(3, steps // 4), w=1)
     out["hx_L34_f32k1"] = {"ms": per * 1e3, "states_per_s": s.dim / per,
-                           "achieved_GBs": s.dim * 2 * 4 / per / 1e9}
+                           "achieved_GBs": s.dim * 2 * 4 / per / 1e9,
+                           "form": dq.hamiltonian_form(s, t, torch.float32, 1)}
     del y
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = dq.lanczos(s, t, jd, zd, x, 150, reorth="local")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    e_bethe = json.load(open(os.path.join(ROOT, "tests", "golden", "bethe_e0.json")))["E0"]["34"]
     out["lanczos_L34_f32vec"] = {"steps": r["steps_done"], "seconds": el,
                                  "ms_per_step": el / r["steps_done"] * 1e3, "reorth": r["reorth"],
-                                 "E0": r["eig"][0]}
+                                 "E0": r["eig"][0], "E0_bethe_ansatz": e_bethe,
+                                 "E0_error_vs_bethe": r["eig"][0] - e_bethe}
     del x
     torch.cuda.empty_cache()
     return out
@@ -224,27 +277,42 @@ def split_sweep(dq, synth, torch, steps: int, warmup: int):
             continue
         idx = torch.empty_like(states)
         back = torch.empty_like(states)
-        per_r = time_variant(lambda: s.rank(states, out=idx), stream, steps, warmup) / steps
-        per_u = time_variant(lambda: s.unrank(idx, out=back), stream, steps, warmup) / steps
+        per_r = median(time_steps(lambda: s.rank(states, out=idx), stream, steps, warmup))
+        per_u = median(time_steps(lambda: s.unrank(idx, out=back), stream, steps, warmup))
         ok = bool(torch.equal(back, states))
         t = dq.Terms(bonds)
-        per_h = time_variant(lambda: dq.hamiltonian_apply(s, t, jd, zd, x, out=y), stream,
-                             max(2, steps // 4), 1) / max(2, steps // 4)
+        per_h = median(time_steps(lambda: dq.hamiltonian_apply(s, t, jd, zd, x, out=y), stream,
+                                  max(3, steps // 4), 1))
         out[key] = {"supported": True, "rank_per_s": cnt / per_r, "unrank_per_s": cnt / per_u,
-                    "roundtrip_ok": ok, "hx_f32k1_ms": per_h * 1e3, "hx_states_per_s": s.dim / per_h}
+                    "roundtrip_ok": ok, "hx_f32k1_ms": per_h * 1e3, "hx_states_per_s": s.dim / per_h,
+                    "form": dq.hamiltonian_form(s, t, torch.float32, 1)}
         del idx, back, s, t
     return out
 
 
-def cpu_baseline(x_host, target_s: float = 15.0):
-    """The FP64 C oracle (OpenMP over contiguous row blocks, as the paper's
-    workers) timed on a contiguous block of rows from the middle of the sector."""
+def cpu_baseline(x_host, checks, runs: int = 3, target_s: float = 4.0, one_core_s: float = 6.0):
+    """The oracle leg: the FP64 C oracle (OpenMP over contiguous row blocks, as the
+    paper's workers) timed on a contiguous block of rows from the middle of the
+    sector, median of `runs` runs on all host threads and one run on one thread;
+    and the errors of the timed GPU variants against the oracle on their sampled
+    rows (`checks`: variant -> (host FP64 x, rows, GPU rows of y))."""
     import numpy as np
     import synth
     from oracle import native
     ns = native.NativeSector(2, L, N_UP, SPLIT)
     bonds, jxy, jz = synth.j1j2_chain(L, J1, J2, DELTA)
     t = native.NativeTerms(bonds, jxy, jz)
+    errors = {}
+    for v, (xh, rows, got) in checks.items():
+        ref = native.hx_rows(ns, t, xh, rows)
+        den = np.abs(ref).sum(axis=-1) if ref.ndim > 1 else np.abs(ref)
+        errors[v] = {"rows": int(len(rows)),
+                     "rel_err": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                     "max_abs_err": float(np.abs(got - ref).max()),
+                     "max_row_err_over_row_norm": float((np.abs(got - ref).reshape(len(rows), -1).sum(axis=1)
+                                                         / np.maximum(den.reshape(len(rows), -1).sum(axis=1),
+                                                                      1e-300)).max())}
+    threads = native.num_threads()
     probe = 1 << 18
     first = (ns.dim - probe) // 2
     t0 = time.perf_counter()
@@ -252,14 +320,37 @@ def cpu_baseline(x_host, target_s: float = 15.0):
     rate = probe / (time.perf_counter() - t0)
     rows = int(min(ns.dim, max(probe, rate * target_s)))
     first = (ns.dim - rows) // 2
-    t0 = time.perf_counter()
-    native.hx_range(ns, t, x_host, first, rows)
-    el = time.perf_counter() - t0
-    return {"value": rows / el, "unit": "sector states/s", "cores": native.num_threads(),
-            "kind": "oracle",
+    secs = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        native.hx_range(ns, t, x_host, first, rows)
+        secs.append(time.perf_counter() - t0)
+    el = median(secs)
+    native.set_threads(1)
+    try:
+        rows1 = int(max(1 << 14, rate / threads * one_core_s))
+        first1 = (ns.dim - rows1) // 2
+        t0 = time.perf_counter()
+        native.hx_range(ns, t, x_host, first1, rows1)
+        el1 = time.perf_counter() - t0
+    finally:
+        native.set_threads(threads)
+    return {"value": rows / el, "unit": "sector states/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 y=Hx on {rows} contiguous rows [{first}, {first + rows}) of the "
-                      f"L=32 n=16 sector ({el:.1f} s, OpenMP static row blocks)",
-            "seconds": el}
+                      f"L=32 n=16 sector, median of {runs} runs ({el:.2f} s each), OpenMP static "
+                      f"row blocks on {threads} threads; one thread: {rows1} rows in {el1:.2f} s",
+            "seconds": el, "runs_seconds": secs,
+            "one_core": {"value": rows1 / el1, "unit": "sector states/s", "cores": 1, "rows": rows1,
+                         "seconds": el1},
+            "variant_errors_vs_oracle": errors}
+
+
+FORM_KERNELS = {
+    "split_staged": "split_diag + split_rows (runs staged in LDS where they fit) + split_cols",
+    "split_global": "split_diag + split_rows + split_cols",
+    "split_fused": "split_diag + split_rows (left family fused in)",
+    "single": "hx_kernel (one pass)",
+}
 
 
 def main(argv=None) -> int:
@@ -269,13 +360,16 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--variants", default="f32k8,f32k1,f64k1",
                     help="comma list; the first is the headline")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (CPU timing and the variants' errors vs the oracle)")
     ap.add_argument("--no-extras", action="store_true", help="time the headline product only")
     ap.add_argument("--split-sweep", action="store_true",
                     help="also time rank, unrank and H*x versus the number of subsystems")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also time a plain device copy of the FP32 vector size (the reference "
-                         "kernel for scaling the HBM byte counters)")
+    ap.add_argument("--no-copy", action="store_true",
+                    help="skip the device copy of the FP32 vector size (the reference kernel for "
+                         "the achievable bandwidth and for scaling the HBM byte counters)")
+    ap.add_argument("--check-rows", type=int, default=100_000,
+                    help="sampled rows per variant checked against the oracle")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -284,7 +378,10 @@ def main(argv=None) -> int:
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: one process only", file=sys.stderr)
         return 2
+    if args.steps < 10:
+        print("bench.py: note: fewer than 10 timed steps; the median is less stable", file=sys.stderr)
 
+    import numpy as np
     import torch
     import paper_2407_14591_amd as dq
     import synth
@@ -297,47 +394,80 @@ def main(argv=None) -> int:
     jxy_d = torch.tensor(jxy, device=dev)
     jz_d = torch.tensor(jz, device=dev)
     D = s.dim
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(synth.SEED_X)
     stream = torch.cuda.current_stream(dev)
     results = {}
-    x_host = None
     copy_info = None
-    if args.calibrate_copy:
+    if not args.no_copy:
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(synth.SEED_G)
         a = torch.empty(D, dtype=torch.float32, device=dev).normal_(generator=gen)
         b = torch.empty_like(a)
-        el = time_variant(lambda: b.copy_(a), stream, args.steps, args.warmup)
+        per = median(time_steps(lambda: b.copy_(a), stream, max(args.steps, 10), args.warmup))
         copy_info = {"bytes_per_copy": 2 * a.numel() * 4, "read_bytes": a.numel() * 4,
-                     "write_bytes": a.numel() * 4,
-                     "GBs": 2 * a.numel() * 4 * args.steps / el / 1e9}
+                     "write_bytes": a.numel() * 4, "ms": per * 1e3,
+                     "GBs": 2 * a.numel() * 4 / per / 1e9}
         del a, b
         torch.cuda.empty_cache()
+    want_check = not args.no_cpu_baseline
+    rows = np.unique(np.concatenate([np.arange(4096), np.arange(D - 4096, D),
+                                     np.random.default_rng(31).integers(0, D, args.check_rows)])).astype(np.uint64)
+    rows_d = torch.from_numpy(rows.astype(np.int64)).to(dev)
+    checks = {}
+    x_host_k1 = None
     for v in args.variants.split(","):
         dt = torch.float32 if v.startswith("f32") else torch.float64
         k = int(v.split("k")[1])
         shape = (D,) if k == 1 else (D, k)
-        x = torch.randn(shape, generator=gen, device=dev, dtype=torch.float64)
-        if v == "f64k1" and not args.no_cpu_baseline:
-            x_host = x.cpu().numpy()
-        x = x.to(dt)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(synth.SEED_X)
+        x64 = torch.randn(shape, generator=gen, device=dev, dtype=torch.float64)
+        x = x64.to(dt)
+        xh = None
+        if want_check:
+            if k == 1 and x_host_k1 is not None:
+                xh = x_host_k1
+            else:
+                xh = x64.cpu().numpy()
+                if k == 1:
+                    x_host_k1 = xh
+        del x64
         y = torch.empty_like(x)
 
         def step():
             dq.hamiltonian_apply(s, terms, jxy_d, jz_d, x, out=y)
 
-        el = time_variant(step, stream, args.steps, args.warmup)
-        per = el / args.steps
+        per_steps = time_steps(step, stream, args.steps, args.warmup)
+        per = median(per_steps)
         es = 4 if dt == torch.float32 else 8
         bytes_alg = D * k * 2 * es  # read x once, write y once
         results[v] = {"k": k, "dtype": "f32" if es == 4 else "f64", "seconds_per_step": per,
-                      "states_per_s": D * k / per, "algorithmic_bytes": bytes_alg,
-                      "achieved_GBs": bytes_alg / per / 1e9}
-        del x, y
+                      "mean_seconds": sum(per_steps) / len(per_steps),
+                      "min_seconds": min(per_steps), "max_seconds": max(per_steps),
+                      "states_per_s": D / per, "columns_per_s": D * k / per,
+                      "algorithmic_bytes": bytes_alg, "achieved_GBs": bytes_alg / per / 1e9,
+                      "form": dq.hamiltonian_form(s, terms, dt, k)}
+        if want_check:
+            checks[v] = (xh, rows, y[rows_d].double().cpu().numpy())
+        del x, y, xh
         torch.cuda.empty_cache()
 
     head = args.variants.split(",")[0]
     r = results[head]
     traffic = read_traffic(head)
+    per = r["seconds_per_step"]
+    roofline = {"bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": r["achieved_GBs"] / PEAK_HBM_GBS, "traffic": traffic,
+                "kernel": f"one H*X product, form {r['form']}: {FORM_KERNELS.get(r['form'], r['form'])}; "
+                          f"algorithmic bytes = dim*k*(4+4) = {r['algorithmic_bytes']}: read X once, "
+                          f"write Y once; achieved = those bytes / median product time",
+                "byte_model": "compulsory"}
+    if traffic:
+        roofline["traffic_GBs"] = traffic / per / 1e9
+        roofline["traffic_frac"] = traffic / per / 1e9 / PEAK_HBM_GBS
+        roofline["amplification"] = traffic / r["algorithmic_bytes"]
+    if copy_info:
+        roofline["copy_GBs"] = copy_info["GBs"]
+        roofline["frac_of_copy"] = r["achieved_GBs"] / copy_info["GBs"]
     out = {
         "metric": METRIC,
         "value": r["states_per_s"],
@@ -345,7 +475,7 @@ def main(argv=None) -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r["seconds_per_step"] * 1e3,
+        "ms_per_step": per * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -354,24 +484,32 @@ def main(argv=None) -> int:
         "config": {"workload": "J1-J2 XXZ chain L=32 n=16 periodic, J1=1 J2=0.5 Delta=1, split 8/8/8/8",
                    "dim": D, "k": r["k"], "vector_dtype": r["dtype"], "variant": head,
                    "parallelism": "1 GPU"},
-        "roofline": {"bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": r["achieved_GBs"] / PEAK_HBM_GBS,
-                     "traffic": traffic,
-                     "kernel": "one H*X product (split_diag + split_rows + split_cols launches); "
-                               "algorithmic bytes = dim*k*(4+4): read X once, write Y once"},
-        "variants": {k_: {"states_per_s": v_["states_per_s"], "ms": v_["seconds_per_step"] * 1e3,
-                          "achieved_GBs": v_["achieved_GBs"]} for k_, v_ in results.items()},
+        "roofline": roofline,
+        "columns_per_s": r["columns_per_s"],
+        "variants": {k_: {"states_per_s": v_["states_per_s"], "columns_per_s": v_["columns_per_s"],
+                          "ms": v_["seconds_per_step"] * 1e3, "ms_mean": v_["mean_seconds"] * 1e3,
+                          "achieved_GBs": v_["achieved_GBs"],
+                          "frac_of_peak": v_["achieved_GBs"] / PEAK_HBM_GBS,
+                          "traffic": read_traffic(k_), "form": v_["form"]}
+                     for k_, v_ in results.items()},
     }
+    for k_, v_ in out["variants"].items():
+        if v_["traffic"]:
+            v_["amplification"] = v_["traffic"] / results[k_]["algorithmic_bytes"]
+            v_["traffic_GBs"] = v_["traffic"] / results[k_]["seconds_per_step"] / 1e9
     if copy_info:
         out["copy_calibration"] = copy_info
     if "f64k1" in results:
-        out["speedup_vs_plain_f64_per_column"] = r["states_per_s"] / results["f64k1"]["states_per_s"]
+        out["speedup_vs_plain_f64_per_column"] = r["columns_per_s"] / results["f64k1"]["columns_per_s"]
     if not args.no_extras:
         out["workloads"] = extra_workloads(dq, synth, torch, args.steps, args.warmup)
     if args.split_sweep:
         out["split_sweep"] = split_sweep(dq, synth, torch, args.steps, args.warmup)
-    if x_host is not None:
-        out["cpu_baseline"] = cpu_baseline(x_host)
+    if want_check and x_host_k1 is not None:
+        cb = cpu_baseline(x_host_k1, checks)
+        for k_, e in cb.pop("variant_errors_vs_oracle").items():
+            out["variants"][k_]["error_vs_oracle"] = e
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
     return 0
 

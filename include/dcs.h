@@ -199,6 +199,24 @@ int dcs_hamiltonian_apply(const dcs_sector *sector, const dcs_terms *terms, cons
                           const double *d_jz, const double *d_h, int dtype, int k,
                           const void *d_x, void *d_y, void *stream);
 
+/* Launch forms of a product (see dcs_hamiltonian_apply). */
+#define DCS_FORM_UNTUNED (-1)      /* split view, but no product of this key has run yet */
+#define DCS_FORM_SPLIT_STAGED 0    /* split product, runs staged in on-chip memory where they fit */
+#define DCS_FORM_SPLIT_GLOBAL 1    /* split product, row pass reading the runs from memory */
+#define DCS_FORM_SPLIT_FUSED 2     /* split product whose row pass also applies the left family */
+#define DCS_FORM_SINGLE 3          /* one pass with per-row decode and incremental ranks */
+
+/*
+ * The launch form that dcs_hamiltonian_apply uses for (terms, dtype, k) on the
+ * sector: the form the autotuner kept, DCS_FORM_UNTUNED before the first
+ * product of that key (with the autotuner on), the default form with the
+ * autotuner off (DCS_AUTOTUNE=0), DCS_FORM_SINGLE where the sector has no split
+ * view, the split is switched off (DCS_SPLIT=0) or its tables do not apply.
+ * Host only: reads the sector's record, launches nothing, builds nothing.
+ */
+int dcs_hamiltonian_form(const dcs_sector *sector, const dcs_terms *terms, int dtype, int k,
+                         int *form);
+
 /*
  * Workspace bytes that dcs_hamiltonian_apply_adjoint needs for this pair.
  */

@@ -350,6 +350,74 @@ void orc_hx_rows_xf32(const orc_sector *s, int nbonds, const int32_t *bi, const 
     for (int64_t r = 0; r < count; ++r) row_apply(s, &t, NULL, xf, k, rows[r], y + r * k);
 }
 
+/*
+ * Coupling and field derivatives of a scalar loss with upstream gradient g for
+ * y = H(theta) x (the sums O5 of the gradient definitions; H is linear in the
+ * couplings): for every bond b of the list
+ *     gxy[b] = sum_r sum_c g[r][c] (A_b x)[r][c],  A_b = (S+_i S-_j + S-_i S+_j)/2,
+ *     gz[b]  = sum_r sum_c g[r][c] (Z_b x)[r][c],  Z_b = Sz_i Sz_j,
+ * and, if gh != NULL, gh[i] = sum_r sum_c g[r][c] Sz_i(r) x[r][c] for every site,
+ * over the rows [first, first + count).  Row by row from the definition (each
+ * reached state ranked with eq. index); per-thread partial sums added at the end.
+ */
+void orc_bond_sums(const orc_sector *s, int nbonds, const int32_t *bi, const int32_t *bj,
+                   const double *x, const double *g, int k, uint64_t first, int64_t count,
+                   double *gxy, double *gz, double *gh) {
+    const int Q = s->Q, L = s->L, nb = s->nb;
+    const double S = 0.5 * (Q - 1);
+    const uint64_t dm = (1ull << nb) - 1;
+    const int nacc = 2 * nbonds + L;
+    double *tot = calloc((size_t)nacc, sizeof(double));
+#pragma omp parallel
+    {
+        double *acc = calloc((size_t)nacc, sizeof(double));
+#pragma omp for schedule(static)
+        for (int64_t r = 0; r < count; ++r) {
+            const uint64_t row = first + (uint64_t)r;
+            const uint64_t st = orc_unrank(s, row);
+            double gx_row = 0.0; /* sum_c g[row][c] x[row][c] */
+            for (int c = 0; c < k; ++c) gx_row += g[row * (uint64_t)k + c] * x[row * (uint64_t)k + c];
+            for (int b = 0; b < nbonds; ++b) {
+                int si = nb * (L - 1 - bi[b]), sj = nb * (L - 1 - bj[b]);
+                int di = (int)((st >> si) & dm), dj = (int)((st >> sj) & dm);
+                acc[2 * b + 1] += (di - S) * (dj - S) * gx_row;
+                for (int dir = 0; dir < 2; ++dir) {
+                    int a_d = dir ? dj : di, c_d = dir ? di : dj;
+                    int a_s = dir ? sj : si, c_s = dir ? si : sj;
+                    if (a_d < Q - 1 && c_d > 0) {
+                        double ma = a_d - S, mc = c_d - S;
+                        double amp = 0.5 * sqrt(S * (S + 1) - ma * (ma + 1)) * sqrt(S * (S + 1) - mc * (mc - 1));
+                        uint64_t col = orc_rank(s, st + (1ull << a_s) - (1ull << c_s));
+                        for (int c = 0; c < k; ++c)
+                            acc[2 * b] += amp * g[row * (uint64_t)k + c] * x[col * (uint64_t)k + c];
+                    }
+                }
+            }
+            if (gh)
+                for (int i = 0; i < L; ++i)
+                    acc[2 * nbonds + i] += ((int)((st >> (nb * (L - 1 - i))) & dm) - S) * gx_row;
+        }
+#pragma omp critical
+        for (int q = 0; q < nacc; ++q) tot[q] += acc[q];
+        free(acc);
+    }
+    for (int b = 0; b < nbonds; ++b) {
+        gxy[b] = tot[2 * b];
+        gz[b] = tot[2 * b + 1];
+    }
+    if (gh)
+        for (int i = 0; i < L; ++i) gh[i] = tot[2 * nbonds + i];
+    free(tot);
+}
+
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

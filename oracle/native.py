@@ -56,7 +56,10 @@ def lib():
         l.orc_hx_range.argtypes = hx + [_f64p, C.c_int, C.c_uint64, C.c_int64, _f64p]
         l.orc_hx_rows.argtypes = hx + [_f64p, C.c_int, _u64p, C.c_int64, _f64p]
         l.orc_hx_rows_xf32.argtypes = hx + [_f32p, C.c_int, _u64p, C.c_int64, _f64p]
+        l.orc_bond_sums.argtypes = [C.c_void_p, C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int,
+                                    C.c_uint64, C.c_int64, _f64p, _f64p, _f64p]
         l.orc_num_threads.restype = C.c_int
+        l.orc_set_threads.argtypes = [C.c_int]
         _lib = l
     return _lib
 
@@ -149,5 +152,32 @@ def hx_rows(sec: NativeSector, terms: NativeTerms, x: np.ndarray, rows) -> np.nd
     return y[:, 0] if x.ndim == 1 else y
 
 
+def bond_sums(sec: NativeSector, bonds, x: np.ndarray, g: np.ndarray, fields: bool = False,
+              first: int = 0, count: int | None = None):
+    """(g . A_b x, g . Z_b x) for every listed bond (and g . Sz_i x for every site if
+    ``fields``), summed over rows [first, first+count) and all columns; FP64.
+    x and g are [dim] or [dim, k] FP64."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    if x.shape != g.shape:
+        raise ValueError("x and g differ in shape")
+    k = 1 if x.ndim == 1 else x.shape[1]
+    count = sec.dim - first if count is None else count
+    bi = np.ascontiguousarray([b[0] for b in bonds], dtype=np.int32)
+    bj = np.ascontiguousarray([b[1] for b in bonds], dtype=np.int32)
+    gxy = np.zeros(max(len(bonds), 1))
+    gz = np.zeros(max(len(bonds), 1))
+    gh = np.zeros(sec.L) if fields else None
+    lib().orc_bond_sums(sec._h, len(bonds), _p(bi, _i32p), _p(bj, _i32p), _p(x, _f64p), _p(g, _f64p),
+                        k, first, count, _p(gxy, _f64p), _p(gz, _f64p),
+                        _p(gh, _f64p) if fields else None)
+    return gxy[:len(bonds)], gz[:len(bonds)], gh
+
+
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the following oracle calls (on the calling thread)."""
+    lib().orc_set_threads(int(n))

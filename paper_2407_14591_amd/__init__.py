@@ -21,6 +21,7 @@ from ._lib import (DCS_F32, DCS_F64, DCS_INVALID_INDEX, DCS_REORTH_FULL, DCS_REO
                    DCS_REORTH_NONE, DcsError, call)
 
 __all__ = ["Sector", "Terms", "Plan", "hamiltonian_apply", "hamiltonian_apply_adjoint",
+           "hamiltonian_form",
            "HApply", "lanczos", "tridiag_eigvals", "DcsError", "DCS_INVALID_INDEX",
            "library_path"]
 
@@ -46,13 +47,32 @@ def _dtype_code(dt) -> int:
     raise TypeError(f"vectors must be float32 or float64, not {dt}")
 
 
-def _check_dev(t, device, name, dtype=None):
+def _check_dev(t, device, name, dtype=None, shape=None, numel=None):
+    """Device, contiguity, dtype and size of a tensor handed to the library; every
+    pointer the C ABI receives is checked here against the extent the call reads or
+    writes, so that a wrong-sized tensor raises instead of reaching a kernel."""
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.device.index != device:
         raise ValueError(f"{name} must be a CUDA tensor on device {device}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if dtype is not None and t.dtype not in (dtype if isinstance(dtype, tuple) else (dtype,)):
         raise TypeError(f"{name} has dtype {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+def _block_shape(sector, x, name="x"):
+    """Shape checks of a vector or a block of k columns: [dim] or [dim, k], k in {1, 2, 4, 8}."""
+    if x.dim() not in (1, 2):
+        raise ValueError(f"{name} must be [dim] or [dim, k], not {tuple(x.shape)}")
+    if x.shape[0] != sector.dim:
+        raise ValueError(f"{name} has {x.shape[0]} rows, sector dimension is {sector.dim}")
+    k = 1 if x.dim() == 1 else x.shape[1]
+    if k not in (1, 2, 4, 8):
+        raise ValueError(f"{name} has {k} columns; k must be 1, 2, 4 or 8")
+    return k
 
 
 class Sector:
@@ -92,6 +112,7 @@ class Sector:
         """Indices of packed states (int64/uint64 tensor); invalid -> DCS_INVALID_INDEX."""
         _check_dev(states, self.device, "states", (torch.int64, torch.uint64))
         out = torch.empty_like(states) if out is None else out
+        _check_dev(out, self.device, "out", (torch.int64, torch.uint64), numel=states.numel())
         cnt = self._counter(count_invalid)
         call("dcs_rank", self._h, _ptr(states), _ptr(out), states.numel(), _ptr(cnt),
              _stream(self.device))
@@ -100,13 +121,17 @@ class Sector:
     def unrank(self, idx: torch.Tensor, out: torch.Tensor | None = None, count_invalid=False):
         _check_dev(idx, self.device, "idx", (torch.int64, torch.uint64))
         out = torch.empty_like(idx) if out is None else out
+        _check_dev(out, self.device, "out", (torch.int64, torch.uint64), numel=idx.numel())
         cnt = self._counter(count_invalid)
         call("dcs_unrank", self._h, _ptr(idx), _ptr(out), idx.numel(), _ptr(cnt),
              _stream(self.device))
         return (out, cnt) if count_invalid else out
 
     def enumerate(self, first: int, count: int, out: torch.Tensor | None = None):
+        if count < 0:
+            raise ValueError("count must be >= 0")
         out = torch.empty(count, dtype=torch.int64, device=f"cuda:{self.device}") if out is None else out
+        _check_dev(out, self.device, "out", (torch.int64, torch.uint64), numel=count)
         call("dcs_enumerate", self._h, first, count, _ptr(out), _stream(self.device))
         return out
 
@@ -150,14 +175,21 @@ def hamiltonian_apply(sector: Sector, terms: Terms, jxy, jz, x, h=None, out=None
     """Y = H X (dcs_hamiltonian_apply); X is [dim] or [dim, k] float32/float64."""
     _couplings(sector, terms, jxy, jz, h)
     _check_dev(x, sector.device, "x", (torch.float32, torch.float64))
-    k = 1 if x.dim() == 1 else x.shape[1]
-    if x.shape[0] != sector.dim:
-        raise ValueError(f"x has {x.shape[0]} rows, sector dimension is {sector.dim}")
+    k = _block_shape(sector, x)
     out = torch.empty_like(x) if out is None else out
-    _check_dev(out, sector.device, "out", x.dtype)
+    _check_dev(out, sector.device, "out", x.dtype, shape=x.shape)
     call("dcs_hamiltonian_apply", sector._h, terms._h, _ptr(jxy), _ptr(jz), _ptr(h),
          _dtype_code(x.dtype), k, _ptr(x), _ptr(out), _stream(sector.device))
     return out
+
+
+def hamiltonian_form(sector: Sector, terms: Terms, dtype=torch.float32, k: int = 1) -> str:
+    """Launch form of the product for (terms, dtype, k) on the sector (dcs_hamiltonian_form):
+    "split_staged", "split_global", "split_fused", "single", or "untuned" before the
+    autotuner has timed that key."""
+    f = C.c_int()
+    call("dcs_hamiltonian_form", sector._h, terms._h, _dtype_code(dtype), k, C.byref(f))
+    return _lib.FORM_NAMES[f.value]
 
 
 def hamiltonian_apply_adjoint(sector: Sector, terms: Terms, jxy, jz, x, g, h=None,
@@ -165,7 +197,9 @@ def hamiltonian_apply_adjoint(sector: Sector, terms: Terms, jxy, jz, x, g, h=Non
     """(H g, dL/dJxy, dL/dJz, dL/dh) for y = H x and dL/dy = g (dcs_hamiltonian_apply_adjoint)."""
     _couplings(sector, terms, jxy, jz, h)
     _check_dev(x, sector.device, "x", (torch.float32, torch.float64))
-    _check_dev(g, sector.device, "g", x.dtype)
+    if _block_shape(sector, x) != 1 or x.dim() != 1:
+        raise ValueError(f"the adjoint takes one vector of {sector.dim} entries, not {tuple(x.shape)}")
+    _check_dev(g, sector.device, "g", x.dtype, shape=x.shape)
     dev = x.device
     gx = torch.empty_like(x) if want_grad_x else None
     gj = torch.empty(terms.num_bonds, dtype=torch.float64, device=dev)
@@ -209,7 +243,9 @@ def lanczos(sector: Sector, terms: Terms, jxy, jz, v0, steps: int, reorth="auto"
     """Lanczos with FP64 scalars (dcs_lanczos).  Returns a dict with alpha, beta,
     steps_done, eig (lowest num_eig Ritz values), reorth mode and the ground vector."""
     _couplings(sector, terms, jxy, jz, h)
-    _check_dev(v0, sector.device, "v0", (torch.float32, torch.float64))
+    _check_dev(v0, sector.device, "v0", (torch.float32, torch.float64), shape=(sector.dim,))
+    if steps < 1:
+        raise ValueError("steps must be >= 1")
     dtype = _dtype_code(v0.dtype)
     modes = {"none": DCS_REORTH_NONE, "local": DCS_REORTH_LOCAL, "full": DCS_REORTH_FULL}
     if reorth == "auto":
@@ -274,7 +310,13 @@ class Plan:
             _check_dev(x, s.device, "x", dt)
             if x.numel() != s.dim:
                 raise ValueError("vector length differs from its sector dimension")
-        ys = [torch.empty_like(x) for x in xs] if ys is None else ys
+        ys = [torch.empty_like(x) for x in xs] if ys is None else list(ys)
+        if len(ys) != n:
+            raise ValueError("one output vector per sector")
+        for (s, _, _, _), x, y in zip(self.items, xs, ys):
+            if x.dim() != 1:
+                raise ValueError("plan vectors are one column per sector")
+            _check_dev(y, s.device, "y", dt, shape=x.shape)
         X = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
         Y = (C.c_void_p * n)(*[y.data_ptr() for y in ys])
         call("dcs_plan_apply", self._h, _dtype_code(dt), X, Y, _stream(self.device))

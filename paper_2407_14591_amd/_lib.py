@@ -23,6 +23,7 @@ DCS_REORTH_NONE = 0
 DCS_REORTH_LOCAL = 1
 DCS_REORTH_FULL = 2
 DCS_INVALID_INDEX = (1 << 64) - 1
+FORM_NAMES = {-1: "untuned", 0: "split_staged", 1: "split_global", 2: "split_fused", 3: "single"}
 
 # every entry point of include/dcs.h: name -> (restype, argtypes)
 _vp, _i, _sz, _u64 = C.c_void_p, C.c_int, C.c_size_t, C.c_uint64
@@ -46,6 +47,7 @@ SIGNATURES = {
     "dcs_terms_create": (_i, [_i, _i32p, _i32p, _pp]),
     "dcs_terms_destroy": (_i, [_vp]),
     "dcs_hamiltonian_apply": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp]),
+    "dcs_hamiltonian_form": (_i, [_vp, _vp, _i, _i, _ip]),
     "dcs_adjoint_workspace_size": (_i, [_vp, _vp, _szp]),
     "dcs_hamiltonian_apply_adjoint": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp, _vp,
                                            _vp, _vp, _sz, _vp]),

@@ -101,6 +101,16 @@ extern "C" int dcs_hamiltonian_apply(const dcs_sector *s, const dcs_terms *t, co
     return launch_hx(s, t, jxy, jz, h, dtype, k, x, y, (hipStream_t)stream);
 }
 
+extern "C" int dcs_hamiltonian_form(const dcs_sector *s, const dcs_terms *t, int dtype, int k,
+                                    int *form) {
+    clear_error();
+    if (!s || !t || !form) return set_error(DCS_EINVAL, "NULL argument");
+    if (dtype != DCS_F32 && dtype != DCS_F64) return set_error(DCS_EINVAL, "dtype %d", dtype);
+    if (k != 1 && k != 2 && k != 4 && k != 8) return set_error(DCS_EINVAL, "k=%d not in {1,2,4,8}", k);
+    *form = hx_form(s, t, dtype, k);
+    return DCS_OK;
+}
+
 extern "C" int dcs_adjoint_workspace_size(const dcs_sector *s, const dcs_terms *t,
                                           size_t *bytes) {
     clear_error();

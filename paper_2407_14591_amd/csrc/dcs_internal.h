@@ -152,6 +152,13 @@ struct SplitRows {
     uint16_t r_bond[kMaxBonds];      // bond index of every right-family bond
     CrossBond x[kMaxCross];
     DiagTerm d[kMaxBonds + kMaxSites];
+    // streams that have run products on these tables, with an event recorded
+    // after the last one on each; evicting the set waits for those events only
+    static constexpr int kUseStreams = 8;
+    hipStream_t use_stream[kUseStreams] = {};
+    hipEvent_t use_event[kUseStreams] = {};
+    int nuse = 0;
+    bool use_overflow = false;  // more streams than slots: eviction synchronises the device
 };
 
 struct LeftInfo {
@@ -224,6 +231,8 @@ void free_rows(SplitRows &c);
 // terms object); NULL if s has no split view or the tables do not apply (an
 // error is set only for a failure).
 SplitRows *split_rows(dcs_sector *s, const dcs_terms *t);
+// Records that work using c was enqueued on `stream` (nothing inside stream capture).
+void note_split_use(dcs_sector *s, SplitRows &c, hipStream_t stream);
 
 // kernels launchers (index_kernels.hip, hx_kernels.hip, lanczos.hip)
 int launch_rank(const dcs_sector *s, const uint64_t *st, uint64_t *idx, size_t count,
@@ -234,6 +243,7 @@ int launch_enumerate(const dcs_sector *s, uint64_t first, size_t count, uint64_t
                      hipStream_t stream);
 int launch_hx(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
               const double *h, int dtype, int k, const void *x, void *y, hipStream_t stream);
+int hx_form(const dcs_sector *s, const dcs_terms *t, int dtype, int k);
 size_t adjoint_ws_bytes(const dcs_sector *s, const dcs_terms *t);
 int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
                    const double *h, int dtype, const void *x, const void *g, void *gx,

@@ -209,6 +209,19 @@ int tuned_form(dcs_sector *s, const dcs_terms *t, const SplitRows &c, const doub
 
 }  // namespace
 
+int hx_form(const dcs_sector *s, const dcs_terms *t, int dtype, int k) {
+    static_assert(kFormSplitStaged == DCS_FORM_SPLIT_STAGED && kFormSplitGlobal == DCS_FORM_SPLIT_GLOBAL &&
+                      kFormSplitFused == DCS_FORM_SPLIT_FUSED && kFormSingle == DCS_FORM_SINGLE,
+                  "form codes of the ABI");
+    if (!(s->left.K > 0 && s->desc.Q == 2 && split_enabled())) return kFormSingle;
+    for (int m = 0; m < s->left.m_count; ++m)
+        if (s->left.ncols[m] >= 0xFFFFu) return kFormSingle;  // offsets of the split tables are 16-bit
+    if (!autotune_enabled()) return default_form();
+    std::lock_guard<std::mutex> g(*s->left.rows_lock);
+    auto it = s->left.tuned.find(tuned_key(t, dtype, k));
+    return it == s->left.tuned.end() ? DCS_FORM_UNTUNED : it->second;
+}
+
 int launch_hx(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
               const double *h, int dtype, int k, const void *x, void *y, hipStream_t stream) {
     DeviceGuard dg(s->device);
@@ -218,13 +231,14 @@ int launch_hx(const dcs_sector *s, const dcs_terms *t, const double *jxy, const 
                              s->desc.L);
         clear_error();
         dcs_sector *sm = const_cast<dcs_sector *>(s);
-        const SplitRows *c = split_rows(sm, t);
+        SplitRows *c = split_rows(sm, t);
         if (c) {
             bool ran = false;
             const int form = tuned_form(sm, t, *c, jxy, jz, h, dtype, k, x, y, stream, &ran);
             if (form < 0) return DCS_EHIP;
-            if (ran) return DCS_OK;
-            return launch_form(sm, t, *c, form, jxy, jz, h, dtype, k, x, y, stream);
+            const int r = ran ? DCS_OK : launch_form(sm, t, *c, form, jxy, jz, h, dtype, k, x, y, stream);
+            if (!r) note_split_use(sm, *c, stream);
+            return r;
         }
         if (dcs_last_error()[0]) return DCS_EHIP;
     }
@@ -307,7 +321,7 @@ int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, c
                          s->desc.L);
     clear_error();
     dcs_sector *sm = const_cast<dcs_sector *>(s);
-    const SplitRows *c = split_rows(sm, t);
+    SplitRows *c = split_rows(sm, t);
     if (!c) return dcs_last_error()[0] ? DCS_EHIP : fused();
     bool ran = false;
     const int form = tuned_form(sm, t, *c, jxy, jz, h, dtype, 1, g, gx, stream, &ran);
@@ -328,8 +342,11 @@ int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, c
     if (way < 0) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (!autotune_enabled() || hipStreamIsCapturing(stream, &cs) != hipSuccess ||
-            cs != hipStreamCaptureStatusNone)
-            return split_way();
+            cs != hipStreamCaptureStatusNone) {
+            const int r = split_way();
+            if (!r) note_split_use(sm, *c, stream);
+            return r;
+        }
         float best = 0.f;
         for (int w = 0; w < 2; ++w) {
             float ms = 0.f;
@@ -345,7 +362,9 @@ int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, c
         std::lock_guard<std::mutex> lk(*li.rows_lock);
         li.tuned[key] = way;
     }
-    return way == 0 ? fused() : split_way();
+    const int r = way == 0 ? fused() : split_way();
+    if (!r) note_split_use(sm, *c, stream);
+    return r;
 }
 
 }  // namespace dcs

@@ -532,8 +532,9 @@ __device__ __forceinline__ void lds_add(double *p, double v) {
 }
 
 // One bond class (A, B) of the adjoint for the R rows of every lane.  For Q = 2
-// the bonds go in batches of 8: every column of the batch, the gathers of g and
-// x, then the 16 bond sums of the batch in one transposed row sum.
+// the bonds go in batches of adj_batch() (two): every column of the batch, the
+// gathers of g and x, then the batch's bond sums (two per bond) in one
+// transposed row sum.
 template <typename IdxT, typename T, int NMAX, bool Q2, bool GX, int A, int B, int R>
 __device__ __forceinline__ void adjoint_class(const HxParams &P, const SectorDesc &sd,
                                               const Tables<IdxT> &Tb,

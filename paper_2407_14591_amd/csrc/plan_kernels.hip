@@ -138,6 +138,7 @@ struct dcs_plan {
         dcs_sector *sector;
         const dcs_terms *terms;
         const double *jxy, *jz;
+        int side;  // side stream; every product of one sector goes to the same one
     };
     std::vector<Own> own;
     // After the first apply of a dtype (whose products the autotuner times on the
@@ -220,10 +221,20 @@ extern "C" int dcs_plan_create(int nsec, dcs_sector *const *secs, dcs_terms *con
     p->nmax = nmax;
     p->ntiles = (uint32_t)tiles.size();
     p->lds_bytes = lds;
+    // A sector listed more than once (other terms or couplings) shares its tile
+    // counters, cached tables and diagonal buffer between its products, so those
+    // products must not overlap: they all go to the side stream of the sector's
+    // first appearance, in plan order.
+    int distinct = 0;
     for (int s = 0; s < nsec; ++s) {
         p->dims.push_back(secs[s]->desc.dim);
-        if (secs[s]->left.K > 0 && secs[s]->desc.Q == 2)
-            p->own.push_back(dcs_plan::Own{s, secs[s], terms[s], jxy[s], jz[s]});
+        if (secs[s]->left.K > 0 && secs[s]->desc.Q == 2) {
+            int side = -1;
+            for (const auto &o : p->own)
+                if (o.sector == secs[s]) side = o.side;
+            if (side < 0) side = distinct++ % dcs_plan::kSideStreams;
+            p->own.push_back(dcs_plan::Own{s, secs[s], terms[s], jxy[s], jz[s], side});
+        }
     }
     DeviceGuard g(device);
     int r = check_hip(hipMalloc(&p->d_secs, nsec * sizeof(PlanSector)), "hipMalloc plan");
@@ -330,12 +341,13 @@ extern "C" int dcs_plan_apply(const dcs_plan *pc, int dtype, const void *const *
     for (int i = 0; i < dcs_plan::kSideStreams; ++i)
         if (int r = check_hip(hipStreamWaitEvent(p->side[i], p->fork, 0), "plan fork wait")) return r;
     // the one launch on the caller's stream, the own products on the side streams
-    // (each sector has its own counters and tables, so they may run together)
+    // (distinct sectors have their own counters and tables, so they may run
+    // together; repeated sectors are serialised on one stream)
     int r = launch_core();
     for (size_t q = 0; q < p->own.size() && !r; ++q) {
         const auto &o = p->own[q];
         r = launch_hx(o.sector, o.terms, o.jxy, o.jz, nullptr, dtype, 1, xs[o.index], ys[o.index],
-                      p->side[q % dcs_plan::kSideStreams]);
+                      p->side[o.side]);
     }
     // join, also after a failed launch, so that no side stream is left behind
     for (int i = 0; i < dcs_plan::kSideStreams; ++i) {

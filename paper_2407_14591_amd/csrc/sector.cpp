@@ -333,6 +333,7 @@ void free_rows(SplitRows &c) {
     hipFree(c.d_clsize);
     hipFree(c.d_lrun);
     hipFree(c.d_diag);
+    for (int i = 0; i < c.nuse; ++i) hipEventDestroy(c.use_event[i]);
     c = SplitRows();
 }
 

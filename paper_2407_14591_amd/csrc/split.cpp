@@ -255,10 +255,34 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
     }
     SplitRows &slot = li.rows[li.next_slot];
     li.next_slot = (li.next_slot + 1) % kMaxSplitCache;
-    if (slot.terms_id) (void)hipDeviceSynchronize();  // the evicted tables may still be in use
+    if (slot.terms_id) {  // the evicted tables may still be in use on the streams that ran them
+        if (slot.use_overflow) {
+            (void)hipDeviceSynchronize();
+        } else {
+            for (int i = 0; i < slot.nuse; ++i) (void)hipEventSynchronize(slot.use_event[i]);
+        }
+    }
     free_rows(slot);
     slot = c;
     return &slot;
+}
+
+void note_split_use(dcs_sector *s, SplitRows &c, hipStream_t stream) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    std::lock_guard<std::mutex> guard(*s->left.rows_lock);
+    int i = 0;
+    while (i < c.nuse && c.use_stream[i] != stream) ++i;
+    if (i == c.nuse) {
+        if (c.nuse == SplitRows::kUseStreams ||
+            hipEventCreateWithFlags(&c.use_event[i], hipEventDisableTiming) != hipSuccess) {
+            c.use_overflow = true;
+            return;
+        }
+        c.use_stream[i] = stream;
+        ++c.nuse;
+    }
+    if (hipEventRecord(c.use_event[i], stream) != hipSuccess) c.use_overflow = true;
 }
 
 }  // namespace dcs

@@ -251,19 +251,23 @@ def test_split_matches_single_pass_L24(monkeypatch, k):
 
 def test_large_workload_L34_sampled():
     """L=34, n=17 (2,333,606,220 states, 8/8/9/9), Heisenberg chain, FP32 vectors: the
-    split product (rows of 18-site right halves, runs up to 48,620 rows) on 200k sampled
-    rows plus the first and last 4096, against the oracle on the same FP32 x."""
+    product (rows of 18-site right halves, runs up to 48,620 rows) on 200k sampled
+    rows plus the first and last 4096, against the FP64 oracle on the FP64 draws (the
+    FP32 vector is those draws rounded)."""
     L, n, sp = 34, 17, [8, 8, 9, 9]
     s = dq.Sector(L, n, 2, sp)
     assert s.dim == 2_333_606_220
     ns = native.NativeSector(2, L, n, sp)
     bonds, jxy, jz = synth.xxz_chain(L, 1.0, 1.0)
     say("generating x", s.dim)
-    xh = synth.vector(s.dim, synth.SEED_X, np.float32)
+    xh = synth.vector(s.dim, synth.SEED_X, np.float64)
+    xd = torch.empty(s.dim, dtype=torch.float32, device=DEV)
+    step = 1 << 27
+    for a in range(0, s.dim, step):
+        xd[a:a + step] = torch.from_numpy(xh[a:a + step]).to(DEV).float()
     rows = sampled_rows(s.dim, 200_000, 8)
     say("oracle rows")
     y_ref = native.hx_rows(ns, native.NativeTerms(bonds, jxy, jz), xh, rows)
-    xd = torch.from_numpy(xh).to(DEV)
     del xh
     y = dq.hamiltonian_apply(s, dq.Terms(bonds), dev_f64(jxy), dev_f64(jz), xd)
     got = y[torch.tensor(rows.astype(np.int64), device=DEV)].double().cpu().numpy()

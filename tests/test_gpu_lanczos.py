@@ -12,6 +12,7 @@ import paper_2407_14591_amd as dq
 import synth
 from gpu_common import DEV, say
 from oracle import native
+from oracle.closed_forms import bethe_e0
 from oracle.lanczos import lanczos as o_lanczos, ritz
 
 pytestmark = pytest.mark.gpu
@@ -19,19 +20,6 @@ pytestmark = pytest.mark.gpu
 
 def dev_f64(a):
     return torch.tensor(np.asarray(a, dtype=np.float64), device=DEV)
-
-
-def bethe_e0(L):
-    """XXX chain (J=1, periodic) ground energy at n = L/2 from the Bethe equations."""
-    M = L // 2
-    I = np.arange(M) - (M - 1) / 2.0
-
-    def eqs(lam):
-        d = lam[:, None] - lam[None, :]
-        return 2 * L * np.arctan(2 * lam) - 2 * np.pi * I - 2 * np.arctan(d).sum(axis=1)
-
-    lam = scipy.optimize.fsolve(eqs, 0.5 * np.tan(np.pi * I / L), xtol=1e-13)
-    return L / 4 - np.sum(2 / (1 + 4 * lam ** 2))
 
 
 def test_tridiagonal_eigensolver():

@@ -146,6 +146,83 @@ def test_native_hx_equals_python():
                            atol=1e-12)
 
 
+from oracle.closed_forms import bethe_e0 as bethe_ground_energy  # noqa: E402
+
+
+@pytest.mark.parametrize("L", [8, 10, 12])
+def test_majumdar_ghosh(L):
+    bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.5, 1.0)
+    ev = spectrum(2, L, L // 2, bonds, jxy, jz)
+    assert abs(ev[0] + 3 * L / 8) < 1e-11
+    assert abs(ev[1] + 3 * L / 8) < 1e-11      # dimer states: two-fold degenerate
+    assert ev[2] > ev[0] + 1e-3
+
+
+def test_two_site_spin_one():
+    """J S1.S2 with S=1: J/2 [S_t(S_t+1) - 4] for S_t = 0, 1, 2."""
+    bonds, jxy, jz = [(0, 1)], [1.0], [1.0]
+    assert np.allclose(spectrum(3, 2, 2, bonds, jxy, jz, [1, 1]), [-2.0, -1.0, 1.0])
+    assert np.allclose(spectrum(3, 2, 1, bonds, jxy, jz, [1, 1]), [-1.0, 1.0])
+    assert np.allclose(spectrum(3, 2, 0, bonds, jxy, jz, [2]), [1.0])
+    # spin-1/2 singlet and triplet
+    assert np.allclose(spectrum(2, 2, 1, bonds, jxy, jz, [1, 1]), [-0.75, 0.25])
+
+
+@pytest.mark.parametrize("Q,L", [(2, 8), (3, 5), (4, 4)])
+def test_heisenberg_multiplets(Q, L):
+    """Delta=1 is SU(2) symmetric: the ferromagnetic multiplet J S^2 (#bonds) is the top
+    level of every sector, and sector n contains the spectrum of sector n-1 below
+    half filling."""
+    S = (Q - 1) / 2
+    bonds, jxy, jz = synth.xxz_chain(L, 1.0, 1.0)
+    prev = None
+    for n in range(0, (Q - 1) * L + 1):
+        ev = spectrum(Q, L, n, bonds, jxy, jz)
+        assert abs(ev[-1] - S * S * len(bonds)) < 1e-10
+        if prev is not None and n <= (Q - 1) * L / 2:
+            for e in prev:
+                assert np.min(np.abs(ev - e)) < 1e-9
+        prev = ev
+        # particle-hole (spin flip) symmetry
+        ev2 = spectrum(Q, L, (Q - 1) * L - n, bonds, jxy, jz)
+        assert np.allclose(ev, ev2, atol=1e-10)
+
+
+def test_split_invariance_of_y():
+    Q, L, n = 2, 10, 4
+    rng = np.random.default_rng(5)
+    bonds, _, _ = synth.j1j2_chain(L, 1.0, 0.5, 1.0)
+    jxy, jz = rng.normal(size=len(bonds)), rng.normal(size=len(bonds))
+    a = BruteSector(Q, L, n, [10])
+    b = BruteSector(Q, L, n, [3, 3, 4])
+    xa = rng.normal(size=a.dim)
+    perm = b.rank(a.states)                  # position of a's states in b's order
+    xb = np.empty_like(xa)
+    xb[perm] = xa
+    ya = apply_h(a, bonds, jxy, jz, xa)
+    yb = apply_h(b, bonds, jxy, jz, xb)
+    assert np.allclose(yb[perm], ya, atol=1e-13)
+
+
+def test_native_hx_equals_python():
+    for Q, L, n, sp, k in [(2, 12, 5, [4, 4, 4], 1), (2, 11, 6, [5, 6], 3),
+                           (3, 6, 6, [2, 2, 2], 2), (4, 5, 5, [2, 3], 1)]:
+        b = BruteSector(Q, L, n, sp)
+        ns = native.NativeSector(Q, L, n, sp)
+        rng = np.random.default_rng(L)
+        bonds, _, _ = synth.j1j2_chain(L, 1.0, 0.5, 1.0)
+        jxy, jz, h = rng.normal(size=len(bonds)), rng.normal(size=len(bonds)), rng.normal(size=L)
+        x = rng.normal(size=(b.dim, k)) if k > 1 else rng.normal(size=b.dim)
+        t = native.NativeTerms(bonds, jxy, jz, h)
+        y = apply_h(b, bonds, jxy, jz, x, h)
+        assert np.allclose(native.hx_range(ns, t, x), y, atol=1e-13)
+        rows = rng.integers(0, b.dim, 50)
+        assert np.allclose(native.hx_rows(ns, t, x, rows), y[rows], atol=1e-13)
+        y32 = native.hx_rows(ns, t, x.astype(np.float32), rows)
+        assert np.allclose(y32, apply_h(b, bonds, jxy, jz, x.astype(np.float32).astype(np.float64), h)[rows],
+                           atol=1e-12)
+
+
 def bethe_ground_energy(L):
     """XXX chain, J=1, periodic, M=L/2: logarithmic Bethe equations
     2L arctan(2 l_j) = 2 pi I_j + 2 sum_k arctan(l_j - l_k),  E = L/4 - sum_j 2/(1+4 l_j^2)."""
@@ -180,3 +257,14 @@ def test_bethe_ansatz_sixteen_sites_lanczos():
     assert abs(e0 - bethe_ground_energy(L)) < 1e-9
     r = native.hx_range(ns, t, psi) - e0 * psi
     assert np.linalg.norm(r) < 1e-6
+
+
+def test_golden_bethe_values_match_the_oracle():
+    """tests/golden/bethe_e0.json (read by the benchmark for the L=34 energy error)
+    holds exactly what oracle.closed_forms.bethe_e0 gives."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "bethe_e0.json")
+    stored = json.load(open(path))["E0"]
+    for L in (8, 16, 34):
+        assert abs(stored[str(L)] - bethe_ground_energy(L)) <= 1e-12 * L

@@ -139,3 +139,35 @@ def test_hellmann_feynman_vs_dense_finite_differences():
         assert abs(fd - gj[k]) < 1e-7
         fd = (e0(jxy, jz + e)[0] - e0(jxy, jz - e)[0]) / (2 * eps)
         assert abs(fd - gz[k]) < 1e-7
+
+
+@pytest.mark.parametrize("Q,L,n,split,k", [(2, 12, 6, [4, 4, 4], 1), (2, 10, 4, [5, 5], 2),
+                                           (3, 6, 6, [2, 2, 2], 4)])
+def test_c_bond_sums_match_finite_differences(Q, L, n, split, k):
+    """The C oracle's coupling and field sums (g . A_b x, g . Z_b x, g . Sz_i x, summed
+    over rows and columns) against central differences of g . H(theta) x evaluated by
+    the C oracle's own row-by-row product (exact for a map linear in theta)."""
+    rng = np.random.default_rng(Q * L + k)
+    bonds = synth.chain_bonds(L, 1) + synth.chain_bonds(L, 2)
+    ns = native.NativeSector(Q, L, n, split)
+    shape = (ns.dim, k) if k > 1 else (ns.dim,)
+    x, g = rng.normal(size=shape), rng.normal(size=shape)
+    jxy, jz, h = rng.normal(size=len(bonds)), rng.normal(size=len(bonds)), rng.normal(size=L)
+    gxy, gz, gh = native.bond_sums(ns, bonds, x, g, fields=True)
+
+    def loss(a, b, f):
+        return float(np.sum(g * native.hx_range(ns, native.NativeTerms(bonds, a, b, f), x)))
+
+    eps = 0.5
+    for q in range(len(bonds)):
+        e = np.zeros(len(bonds))
+        e[q] = eps
+        fd_xy = (loss(jxy + e, jz, h) - loss(jxy - e, jz, h)) / (2 * eps)
+        fd_z = (loss(jxy, jz + e, h) - loss(jxy, jz - e, h)) / (2 * eps)
+        assert abs(fd_xy - gxy[q]) <= 1e-10 * max(1.0, abs(fd_xy)), (q, fd_xy, gxy[q])
+        assert abs(fd_z - gz[q]) <= 1e-10 * max(1.0, abs(fd_z)), (q, fd_z, gz[q])
+    for i in range(L):
+        e = np.zeros(L)
+        e[i] = eps
+        fd_h = (loss(jxy, jz, h + e) - loss(jxy, jz, h - e)) / (2 * eps)
+        assert abs(fd_h - gh[i]) <= 1e-10 * max(1.0, abs(fd_h)), (i, fd_h, gh[i])
