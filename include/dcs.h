@@ -248,6 +248,26 @@ int dcs_hamiltonian_apply_adjoint(const dcs_sector *sector, const dcs_terms *ter
                                   double *d_grad_jxy, double *d_grad_jz, double *d_grad_h,
                                   void *d_workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * The adjoint above without a workspace, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments and results as
+ * dcs_hamiltonian_apply_adjoint minus (d_workspace, workspace_bytes); always the
+ * fused single pass (it builds no split tables and times no launch forms, so
+ * d_grad_x may differ from the other entry point's by rounding in FP32; the
+ * coupling sums are the same).  The per-workgroup partial sums go to a fixed
+ * 4 MiB device array of the library, one per GPU, kept until the process ends;
+ * the call returns DCS_EUNSUPPORTED when dcs_adjoint_workspace_size exceeds
+ * 4 MiB.  It calls no allocating routine.  Every call on one GPU shares that
+ * array, so calls that overlap in time on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.
+ */
+int dcs_hamiltonian_apply_adjoint_noalloc(const dcs_sector *sector, const dcs_terms *terms,
+                                          const double *d_jxy, const double *d_jz,
+                                          const double *d_h, int dtype, const void *d_x,
+                                          const void *d_g, void *d_grad_x, double *d_grad_jxy,
+                                          double *d_grad_jz, double *d_grad_h, void *stream);
+
 /* ========================================================================== */
 /* Batched: many sectors in one launch                                        */
 /* ========================================================================== */

@@ -21,7 +21,7 @@ from ._lib import (DCS_F32, DCS_F64, DCS_INVALID_INDEX, DCS_REORTH_FULL, DCS_REO
                    DCS_REORTH_NONE, DcsError, call)
 
 __all__ = ["Sector", "Terms", "Plan", "hamiltonian_apply", "hamiltonian_apply_adjoint",
-           "hamiltonian_form",
+           "hamiltonian_form", "hamiltonian_apply_adjoint_noalloc",
            "HApply", "lanczos", "tridiag_eigvals", "DcsError", "DCS_INVALID_INDEX",
            "library_path"]
 
@@ -212,6 +212,26 @@ def hamiltonian_apply_adjoint(sector: Sector, terms: Terms, jxy, jz, x, g, h=Non
          _dtype_code(x.dtype), _ptr(x), _ptr(g), _ptr(gx), _ptr(gj), _ptr(gz), _ptr(gh), _ptr(ws),
          nbytes.value, _stream(sector.device))
     return gx, gj, gz, gh
+
+
+def hamiltonian_apply_adjoint_noalloc(sector: Sector, terms: Terms, jxy, jz, x, g, grad_x, grad_jxy,
+                                      grad_jz, h=None, grad_h=None):
+    """The adjoint into caller-given outputs with no workspace
+    (dcs_hamiltonian_apply_adjoint_noalloc): nothing is allocated, here or in the
+    library.  grad_x may be None (coupling sums only); grad_h None skips the fields."""
+    _couplings(sector, terms, jxy, jz, h)
+    _check_dev(x, sector.device, "x", (torch.float32, torch.float64), shape=(sector.dim,))
+    _check_dev(g, sector.device, "g", x.dtype, shape=x.shape)
+    if grad_x is not None:
+        _check_dev(grad_x, sector.device, "grad_x", x.dtype, shape=x.shape)
+    _check_dev(grad_jxy, sector.device, "grad_jxy", torch.float64, numel=terms.num_bonds)
+    _check_dev(grad_jz, sector.device, "grad_jz", torch.float64, numel=terms.num_bonds)
+    if grad_h is not None:
+        _check_dev(grad_h, sector.device, "grad_h", torch.float64, numel=sector.L)
+    call("dcs_hamiltonian_apply_adjoint_noalloc", sector._h, terms._h, _ptr(jxy), _ptr(jz), _ptr(h),
+         _dtype_code(x.dtype), _ptr(x), _ptr(g), _ptr(grad_x), _ptr(grad_jxy), _ptr(grad_jz),
+         _ptr(grad_h), _stream(sector.device))
+    return grad_x, grad_jxy, grad_jz, grad_h
 
 
 class HApply(torch.autograd.Function):

@@ -51,6 +51,8 @@ SIGNATURES = {
     "dcs_adjoint_workspace_size": (_i, [_vp, _vp, _szp]),
     "dcs_hamiltonian_apply_adjoint": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp, _vp,
                                            _vp, _vp, _sz, _vp]),
+    "dcs_hamiltonian_apply_adjoint_noalloc": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp,
+                                                   _vp, _vp, _vp]),
     "dcs_plan_create": (_i, [_i, _pp, _pp, _pp, _pp, _pp]),
     "dcs_plan_destroy": (_i, [_vp]),
     "dcs_plan_apply": (_i, [_vp, _i, _pp, _pp, _vp]),

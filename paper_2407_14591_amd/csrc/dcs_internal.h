@@ -39,6 +39,7 @@ constexpr int kMaxSites = DCS_MAX_SITES;
 constexpr int kMaxBonds = DCS_MAX_BONDS;
 constexpr int kMaxWordBits = 14;
 constexpr size_t kLdsTableBudget = 112 * 1024;
+constexpr int kMaxDevices = 64;
 
 template <typename IdxT>
 struct Bad;
@@ -245,6 +246,12 @@ int launch_hx(const dcs_sector *s, const dcs_terms *t, const double *jxy, const 
               const double *h, int dtype, int k, const void *x, void *y, hipStream_t stream);
 int hx_form(const dcs_sector *s, const dcs_terms *t, int dtype, int k);
 size_t adjoint_ws_bytes(const dcs_sector *s, const dcs_terms *t);
+// The adjoint in one fused pass over the rows (no split tables, no autotuner, no
+// allocation): workspace partials only.
+int launch_adjoint_single(const dcs_sector *s, const dcs_terms *t, const double *jxy,
+                          const double *jz, const double *h, int dtype, const void *x,
+                          const void *g, void *gx, double *gjxy, double *gjz, double *gh,
+                          void *ws, hipStream_t stream);
 int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
                    const double *h, int dtype, const void *x, const void *g, void *gx,
                    double *gjxy, double *gjz, double *gh, void *ws, size_t ws_bytes,

@@ -301,6 +301,14 @@ float time_on_stream(F &&fn, hipStream_t stream) {
 
 }  // namespace
 
+int launch_adjoint_single(const dcs_sector *s, const dcs_terms *t, const double *jxy,
+                          const double *jz, const double *h, int dtype, const void *x,
+                          const void *g, void *gx, double *gjxy, double *gjz, double *gh,
+                          void *ws, hipStream_t stream) {
+    DeviceGuard dg(s->device);
+    return adjoint_pass(s, t, jxy, jz, h, dtype, x, g, gx, gjxy, gjz, gh, ws, stream);
+}
+
 int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
                    const double *h, int dtype, const void *x, const void *g, void *gx,
                    double *gjxy, double *gjz, double *gh, void *ws, size_t ws_bytes,
