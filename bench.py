@@ -349,6 +349,7 @@ FORM_KERNELS = {
     "split_staged": "split_diag + split_rows (runs staged in LDS where they fit) + split_cols",
     "split_global": "split_diag + split_rows + split_cols",
     "split_fused": "split_diag + split_rows (left family fused in)",
+    "split_tiled": "split_diag + split_rows_tiled (whole n_K blocks of a run staged in LDS) + split_cols",
     "single": "hx_kernel (one pass)",
 }
 

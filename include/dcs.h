@@ -44,7 +44,8 @@
  *    (read by dcs_sector_create) changes the 2^20 threshold; DCS_SPLIT=0 (read
  *    at every product) forces the single pass; DCS_SPLIT_LDS=0 (likewise) keeps
  *    the row pass from staging runs of x in on-chip memory; DCS_SPLIT_FUSED=1
- *    (likewise) makes the fused form the default form.
+ *    (likewise) makes the fused form the default form, DCS_SPLIT_TILED=1 the
+ *    block-tiled one (DCS_FORM_SPLIT_TILED).
  */
 #ifndef DCS_H
 #define DCS_H
@@ -205,6 +206,8 @@ int dcs_hamiltonian_apply(const dcs_sector *sector, const dcs_terms *terms, cons
 #define DCS_FORM_SPLIT_GLOBAL 1    /* split product, row pass reading the runs from memory */
 #define DCS_FORM_SPLIT_FUSED 2     /* split product whose row pass also applies the left family */
 #define DCS_FORM_SINGLE 3          /* one pass with per-row decode and incremental ranks */
+#define DCS_FORM_SPLIT_TILED 4     /* split product whose row pass stages whole particle-number
+                                      blocks of a run in on-chip memory (rows of 16 to 64 bytes) */
 
 /*
  * The launch form that dcs_hamiltonian_apply uses for (terms, dtype, k) on the

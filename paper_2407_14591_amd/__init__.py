@@ -185,8 +185,8 @@ def hamiltonian_apply(sector: Sector, terms: Terms, jxy, jz, x, h=None, out=None
 
 def hamiltonian_form(sector: Sector, terms: Terms, dtype=torch.float32, k: int = 1) -> str:
     """Launch form of the product for (terms, dtype, k) on the sector (dcs_hamiltonian_form):
-    "split_staged", "split_global", "split_fused", "single", or "untuned" before the
-    autotuner has timed that key."""
+    "split_staged", "split_global", "split_fused", "split_tiled", "single", or "untuned"
+    before the autotuner has timed that key."""
     f = C.c_int()
     call("dcs_hamiltonian_form", sector._h, terms._h, _dtype_code(dtype), k, C.byref(f))
     return _lib.FORM_NAMES[f.value]

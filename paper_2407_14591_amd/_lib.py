@@ -23,7 +23,8 @@ DCS_REORTH_NONE = 0
 DCS_REORTH_LOCAL = 1
 DCS_REORTH_FULL = 2
 DCS_INVALID_INDEX = (1 << 64) - 1
-FORM_NAMES = {-1: "untuned", 0: "split_staged", 1: "split_global", 2: "split_fused", 3: "single"}
+FORM_NAMES = {-1: "untuned", 0: "split_staged", 1: "split_global", 2: "split_fused", 3: "single",
+              4: "split_tiled"}
 
 # every entry point of include/dcs.h: name -> (restype, argtypes)
 _vp, _i, _sz, _u64 = C.c_void_p, C.c_int, C.c_size_t, C.c_uint64

@@ -123,6 +123,29 @@ struct DiagTerm {
     uint16_t pad;
 };
 
+// Tiles of the row pass that stages whole blocks of a run in LDS (one tiling per
+// row size class RB = 16, 32, 64 bytes).  The rows of a run with equal particle
+// number on P_K (the first right subsystem) are contiguous ("n_K blocks"); a
+// tile is a contiguous range of whole n_K blocks of one run that fits the LDS
+// budget, or, for an n_K block larger than that, a range of whole sub-runs of
+// equal P_K word.  Bonds that keep n_K then read the tile in LDS.
+constexpr int kRowTilings = 3;             // RB = 16, 32, 64
+constexpr uint32_t kTileLdsTotal = 160 * 1024;  // LDS of one workgroup of the block-tiled row pass
+constexpr uint32_t kTileLdsStatic = 1024;       // its static LDS and slack
+constexpr int kMaxRunTiles = 64;           // tiles of one run
+struct RowTiling {
+    uint2 *d_tiles = nullptr;              // (left configuration, block | tile-in-run << 8), in launch order:
+                                           // groups of left configurations that differ only on the
+                                           // sites of bonds across the cut, tile index, configuration
+    uint2 *d_tiles_canon = nullptr;        // the same tiles in row order
+    uint2 *d_pat = nullptr;                // (first offset, rows) of tile j of block m: pat[pbase[m] + j]
+    uint64_t ntiles = 0;
+    uint32_t max_rows = 0;                 // rows of the largest tile
+    uint32_t pbase[kMaxLeftM] = {};
+    uint32_t ntile[kMaxLeftM] = {};
+    std::vector<uint2> h_pat, h_tiles, h_canon;  // host copies while building
+};
+
 struct SplitRows {
     uint64_t terms_id = 0;           // 0: empty slot
     uint32_t *d_lptr = nullptr;      // left family: entry range of every left configuration
@@ -148,9 +171,11 @@ struct SplitRows {
     double *d_diag = nullptr;        // per call: left | right configuration diagonals, coupling factors
     int nR = 0, nX = 0, nIs = 0, nJs = 0, nD = 0;
     int nRloc = 0;                   // right-family bonds inside the last subsystem (listed first)
+    int nRA = 0;                     // right-family bonds keeping n_K (listed before the others)
     uint32_t margin = 0;             // rows of the largest run of equal P_K..P_{N-2} words
     uint64_t lnnz = 0;
     uint16_t r_bond[kMaxBonds];      // bond index of every right-family bond
+    RowTiling tiling[kRowTilings];   // block tiles of the row pass, by row size
     CrossBond x[kMaxCross];
     DiagTerm d[kMaxBonds + kMaxSites];
     // streams that have run products on these tables, with an event recorded

@@ -124,15 +124,25 @@ enum Form {
     kFormSplitGlobal = 1,
     kFormSplitFused = 2,
     kFormSingle = 3,
-    kNumForms = 4
+    kFormSplitTiled = 4,
+    kNumForms = 5
 };
+
+// The block-tiled row pass exists for rows of 16 to 64 bytes with a tiling.
+bool tiled_applies(const SplitRows &c, int dtype, int k) {
+    const int rb = k * (dtype == DCS_F32 ? 4 : 8);
+    if (rb < 16 || rb > 64) return false;
+    return c.tiling[rb == 16 ? 0 : (rb == 32 ? 1 : 2)].ntiles > 0;
+}
 
 int launch_form(dcs_sector *s, const dcs_terms *t, const SplitRows &c, int form, const double *jxy,
                 const double *jz, const double *h, int dtype, int k, const void *x, void *y,
                 hipStream_t stream) {
     if (form == kFormSingle) return launch_single(s, t, jxy, jz, h, dtype, k, x, y, stream);
-    const int variant = form == kFormSplitStaged ? sp::kSplitStagedOk
-                                                 : (form == kFormSplitGlobal ? sp::kSplitGlobal : sp::kSplitFused);
+    const int variant = form == kFormSplitStaged  ? sp::kSplitStagedOk
+                        : form == kFormSplitGlobal ? sp::kSplitGlobal
+                        : form == kFormSplitTiled  ? sp::kSplitTiled
+                                                   : sp::kSplitFused;
     return dtype == DCS_F32 ? launch_split_k<float>(s, c, x, y, jxy, jz, h, t->num_bonds, k, variant, stream)
                             : launch_split_k<double>(s, c, x, y, jxy, jz, h, t->num_bonds, k, variant, stream);
 }
@@ -147,7 +157,9 @@ bool autotune_enabled() {
 // the split form whose rows pass also applies the left family.
 int default_form() {
     const char *e = getenv("DCS_SPLIT_FUSED");
-    return (e && e[0] == '1') ? kFormSplitFused : kFormSplitStaged;
+    if (e && e[0] == '1') return kFormSplitFused;
+    const char *t = getenv("DCS_SPLIT_TILED");
+    return (t && t[0] == '1') ? kFormSplitTiled : kFormSplitStaged;
 }
 
 // Autotuner: the first product of a (terms, dtype, k) on a split sector times
@@ -182,7 +194,10 @@ int tuned_form(dcs_sector *s, const dcs_terms *t, const SplitRows &c, const doub
     float best_ms = 0.f;
     int best = kFormSplitStaged;
     int r = DCS_OK;
+    int last = -1;
     for (int f = 0; f < kNumForms && !r; ++f) {
+        if (f == kFormSplitTiled && !tiled_applies(c, dtype, k)) continue;
+        last = f;
         float ms = 0.f;
         for (int rep = 0; rep < 2 && !r; ++rep) {
             r = check_hip(hipEventRecord(e0, stream), "autotune record");
@@ -203,7 +218,7 @@ int tuned_form(dcs_sector *s, const dcs_terms *t, const SplitRows &c, const doub
         std::lock_guard<std::mutex> g(*li.rows_lock);
         li.tuned[key] = best;
     }
-    *ran = best == kNumForms - 1;  // the fastest form was the last one timed: Y is its output
+    *ran = best == last;  // the fastest form was the last one timed: Y is its output
     return best;
 }
 
@@ -211,7 +226,8 @@ int tuned_form(dcs_sector *s, const dcs_terms *t, const SplitRows &c, const doub
 
 int hx_form(const dcs_sector *s, const dcs_terms *t, int dtype, int k) {
     static_assert(kFormSplitStaged == DCS_FORM_SPLIT_STAGED && kFormSplitGlobal == DCS_FORM_SPLIT_GLOBAL &&
-                      kFormSplitFused == DCS_FORM_SPLIT_FUSED && kFormSingle == DCS_FORM_SINGLE,
+                      kFormSplitFused == DCS_FORM_SPLIT_FUSED && kFormSingle == DCS_FORM_SINGLE &&
+                      kFormSplitTiled == DCS_FORM_SPLIT_TILED,
                   "form codes of the ABI");
     if (!(s->left.K > 0 && s->desc.Q == 2 && split_enabled())) return kFormSingle;
     for (int m = 0; m < s->left.m_count; ++m)

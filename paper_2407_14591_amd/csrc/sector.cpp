@@ -333,6 +333,11 @@ void free_rows(SplitRows &c) {
     hipFree(c.d_clsize);
     hipFree(c.d_lrun);
     hipFree(c.d_diag);
+    for (int i = 0; i < kRowTilings; ++i) {
+        hipFree(c.tiling[i].d_tiles);
+        hipFree(c.tiling[i].d_tiles_canon);
+        hipFree(c.tiling[i].d_pat);
+    }
     for (int i = 0; i < c.nuse; ++i) hipEventDestroy(c.use_event[i]);
     c = SplitRows();
 }

@@ -63,11 +63,16 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
     }
     for (int i = 0; i < sd.L; ++i)
         c.d[c.nD++] = DiagTerm{(uint8_t)(sd.site_sub[i] < K ? 0 : 1), packed_bit(i), 0, 1, (uint16_t)i, 0};
-    // bonds inside the last subsystem first: their targets share the row's words of
-    // P_K..P_{N-2}, i.e. lie within `margin` rows of it
+    // bonds that keep the particle number of P_K first (both sites in P_K or both
+    // beyond it: their targets stay in the row's n_K block), the others after them;
+    // among the first, the bonds inside the last subsystem lead: their targets
+    // share the row's words of P_K..P_{N-2}, i.e. lie within `margin` rows of it
+    auto keeps_nK = [&](const SideBond &fb) { return (fb.a == K) == (fb.b == K); };
+    std::stable_partition(right.begin(), right.end(), keeps_nK);
     std::stable_partition(right.begin(), right.end(),
                           [&](const SideBond &fb) { return fb.a == N - 1 && fb.b == N - 1; });
     for (const SideBond &fb : right) c.nRloc += (fb.a == N - 1 && fb.b == N - 1) ? 1 : 0;
+    for (const SideBond &fb : right) c.nRA += keeps_nK(fb) ? 1 : 0;
     {
         const int l = sd.wbits[N - 1];  // sites of the last subsystem (Q = 2)
         uint64_t best = 1;
@@ -221,6 +226,92 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
             }
         }
     }
+    // block tiles of the row pass for rows of 16, 32 and 64 bytes
+    {
+        uint32_t cross_mask = 0;
+        for (int si = 0; si < c.nIs; ++si) cross_mask |= 1u << packed_bit(lsites[si]);
+        const uint32_t maskK = (1u << sd.wbits[K]) - 1u;  // P_K's word: the low bits of a right word
+        std::vector<uint32_t> order(li.count);
+        for (uint32_t g = 0; g < li.count; ++g) order[g] = g;
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+            return (li.h_words[a] & ~cross_mask) < (li.h_words[b] & ~cross_mask);
+        });
+        std::vector<int> block_of(li.count);
+        for (int mi = 0; mi < li.m_count; ++mi)
+            for (uint32_t q = 0; q < li.nleft[mi]; ++q) block_of[li.lbase[mi] + q] = mi;
+        for (int ti = 0; ti < kRowTilings; ++ti) {
+            RowTiling &T = c.tiling[ti];
+            const uint32_t rb = 16u << ti;
+            const uint32_t maxrows = (kTileLdsTotal - kTileLdsStatic) / rb - 1;  // one zero row after the tile
+            std::vector<uint2> pat;
+            bool ok = true;
+            for (int mi = 0; mi < li.m_count && ok; ++mi) {
+                T.pbase[mi] = (uint32_t)pat.size();
+                const uint32_t *rw = li.h_rwords.data() + li.rbase[mi];
+                const uint32_t ncols = (uint32_t)li.ncols[mi];
+                uint32_t cur0 = 0, cur = 0;
+                // (first offset | 1 << 31 for a tile that holds part of an n_K block, rows)
+                auto flush = [&](bool part = false) {
+                    if (cur) pat.push_back(make_uint2(cur0 | (part ? 0x80000000u : 0u), cur));
+                    cur = 0;
+                };
+                uint32_t g0 = 0;
+                while (g0 < ncols) {  // n_K blocks
+                    uint32_t g1 = g0 + 1;
+                    while (g1 < ncols && __builtin_popcount(rw[g1] & maskK) == __builtin_popcount(rw[g0] & maskK)) ++g1;
+                    const uint32_t glen = g1 - g0;
+                    if (glen <= maxrows) {
+                        if (cur + glen > maxrows) flush();
+                        if (!cur) cur0 = g0;
+                        cur += glen;
+                    } else {  // whole sub-runs of equal P_K word
+                        flush();
+                        uint32_t u0 = g0;
+                        while (u0 < g1) {
+                            uint32_t u1 = u0 + 1;
+                            while (u1 < g1 && (rw[u1] & maskK) == (rw[u0] & maskK)) ++u1;
+                            for (uint32_t a = u0; a < u1;) {
+                                const uint32_t take = std::min(u1 - a, maxrows);
+                                if (cur + take > maxrows) flush(true);
+                                if (!cur) cur0 = a;
+                                cur += take;
+                                a += take;
+                            }
+                            u0 = u1;
+                        }
+                        flush(true);
+                    }
+                    g0 = g1;
+                }
+                flush();
+                T.ntile[mi] = (uint32_t)pat.size() - T.pbase[mi];
+                if (T.ntile[mi] > (uint32_t)kMaxRunTiles) ok = false;
+            }
+            if (!ok) continue;  // no tiling for this row size: the launcher keeps the other row passes
+            uint32_t maxt = 0;
+            for (const uint2 &p : pat) T.max_rows = std::max(T.max_rows, p.y);
+            for (int mi = 0; mi < li.m_count; ++mi) maxt = std::max(maxt, T.ntile[mi]);
+            std::vector<uint2> tiles, canon;
+            for (uint32_t g = 0; g < li.count; ++g)
+                for (uint32_t j = 0; j < T.ntile[block_of[g]]; ++j)
+                    canon.push_back(make_uint2(g, (uint32_t)block_of[g] | (j << 8)));
+            for (size_t a = 0; a < order.size();) {
+                size_t b = a + 1;
+                const uint32_t key = li.h_words[order[a]] & ~cross_mask;
+                while (b < order.size() && (li.h_words[order[b]] & ~cross_mask) == key) ++b;
+                for (uint32_t j = 0; j < maxt; ++j)
+                    for (size_t q = a; q < b; ++q) {
+                        const uint32_t g = order[q];
+                        if (j < T.ntile[block_of[g]]) tiles.push_back(make_uint2(g, (uint32_t)block_of[g] | (j << 8)));
+                    }
+                a = b;
+            }
+            T.ntiles = tiles.size();
+            T.h_pat = std::move(pat);
+            T.h_tiles = std::move(tiles);
+            T.h_canon = std::move(canon);
+        }
+    }
     DeviceGuard dg(s->device);
     // the left family with every target as a run start (bond << 48 | run), for the
     // rows pass that applies the left family itself
@@ -249,6 +340,17 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
               // diagonal of both sides, then the per-call coupling factors (1024 doubles + 1024 floats)
               check_hip(hipMalloc(&c.d_diag, ((li.count + li.rcount + 1) / 2 * 2 + 1536) * sizeof(double)),
                         "hipMalloc split diagonal") == DCS_OK;
+    for (int ti = 0; ti < kRowTilings && ok; ++ti) {
+        RowTiling &T = c.tiling[ti];
+        if (!T.ntiles) continue;
+        ok = up((void **)&T.d_tiles, T.h_tiles.data(), T.h_tiles.size() * sizeof(uint2)) &&
+             up((void **)&T.d_tiles_canon, T.h_canon.data(), T.h_canon.size() * sizeof(uint2)) &&
+             up((void **)&T.d_pat, T.h_pat.data(), T.h_pat.size() * sizeof(uint2));
+        T.h_tiles.clear();
+        T.h_tiles.shrink_to_fit();
+        T.h_canon.clear();
+        T.h_canon.shrink_to_fit();
+    }
     if (!ok) {
         free_rows(c);
         return nullptr;

@@ -635,6 +635,231 @@ __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_ker
     }
 }
 
+// ------------------------------------------------------------------ block tiles
+// Rows pass for rows of 16 bytes and more: one tile = a range of whole n_K blocks
+// of one run (RowTiling), staged in LDS, 1024 threads.  Right-family bonds that keep
+// the row inside the tile (every bond that does not move a particle into or out of
+// P_K, when the tile holds whole n_K blocks) read LDS; the others read the run in
+// HBM; bonds across the cut gather from the runs of the flipped left configurations.
+// Tiles come from a list ordered by groups of left configurations that differ
+// only on the crossing sites, so a tile's cross-cut gathers land in runs that the
+// same XCD stages at about the same time.
+struct TileParams {
+    const void *x;
+    void *y;
+    const void *amp;  // coupling factors of the compute type (kAmp* layout)
+    const uint32_t *lwords, *rwords;
+    const uint64_t *runs, *xl;
+    const uint16_t *vo, *xo;
+    const double *dl, *dr;
+    const uint2 *tiles, *pat;
+    uint32_t *counters;
+    uint64_t xbase[9];
+    uint32_t count, rcount;
+    int m_count, nR, nX;
+    int nRA;  // right-family bonds [0, nRA) keep n_K: inside a tile of whole n_K blocks
+    uint32_t pbase[kMaxLeftM], rbase[kMaxLeftM], ncols[kMaxLeftM];
+    CrossBond xb[kMaxCross];
+};
+static_assert(sizeof(TileParams) <= 4096, "kernel arguments are limited to 4 KiB");
+
+constexpr int kTileThreads = 1024;
+constexpr int kTileXF = 32;  // bonds across the cut with descriptors in LDS (more: set up per row)
+
+template <typename T, int K>
+__global__ __launch_bounds__(kTileThreads) void split_rows_tiled_kernel(const TileParams P_arg) {
+    (void)P_arg;
+    const TileParams &P = kernel_arg0<TileParams>();
+    using V = Acc<T, K>;
+    constexpr uint32_t RB = K * sizeof(T);
+    static_assert(RB % 16 == 0, "tiles hold rows of whole 16-byte units");
+    constexpr int NT = kTileThreads;
+    extern __shared__ __align__(16) char dyn[];
+    __shared__ uint4 xinfo[kTileXF];  // per bond across the cut: run base (lo, hi), bytes | bit << 31
+    __shared__ uint32_t slots[2];
+    const cptr<T> A = ro(reinterpret_cast<const T *>(P.amp));
+    const cptr<T> ramp = A + kAmpRight, xamp = A + kAmpCross, xjz = A + kJzCross;
+    const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
+    T *__restrict__ y = reinterpret_cast<T *>(P.y);
+    const int nRq = (P.nR + 7) >> 3;
+    const int nXF = P.nX < kTileXF ? P.nX : kTileXF;
+    AheadQueue Q(P.counters, P.xbase, slots);
+    uint64_t t;
+    while (Q.get(t)) {
+        const cptr<uint32_t> tw = ro(reinterpret_cast<const uint32_t *>(P.tiles));
+        const uint32_t gl = __builtin_amdgcn_readfirstlane(tw[2 * t]);
+        const uint32_t tb = __builtin_amdgcn_readfirstlane(tw[2 * t + 1]);
+        const int mi = (int)(tb & 0xFFu);
+        const uint32_t j = tb >> 8;
+        const cptr<uint32_t> pw = ro(reinterpret_cast<const uint32_t *>(P.pat));
+        const uint32_t sw = __builtin_amdgcn_readfirstlane(pw[2 * (P.pbase[mi] + j)]);
+        const uint32_t s0 = sw & 0x7FFFFFFFu;
+        const uint32_t len = __builtin_amdgcn_readfirstlane(pw[2 * (P.pbase[mi] + j) + 1]);
+        // bonds [0, nA) never leave a tile of whole n_K blocks: LDS only
+        const int nA = (sw >> 31) ? 0 : P.nRA;
+        const uint32_t ncols = P.ncols[mi];
+        const uint64_t R = ro(P.runs)[gl];
+        const uint32_t lw = ro(P.lwords)[gl];
+        const double dl = ro(P.dl)[gl];
+        const auto rs = rsrc(x + R * K, ncols * RB);
+        if ((int)threadIdx.x < nXF) {
+            const CrossBond cb = P.xb[threadIdx.x];
+            const uint32_t b0 = (lw >> cb.lbit) & 1u;
+            const uint64_t Rx = ro(P.xl)[(size_t)cb.si * P.count + gl];
+            int mx = mi + (b0 ? -1 : 1);
+            mx = mx < 0 ? 0 : (mx >= P.m_count ? P.m_count - 1 : mx);
+            const bool valid = Rx != ~0ull;
+            const uint64_t base = reinterpret_cast<uint64_t>(x + (valid ? Rx : 0ull) * K);
+            xinfo[threadIdx.x] = make_uint4((uint32_t)base, (uint32_t)(base >> 32),
+                                            (valid ? P.ncols[mx] * RB : 0u) | (b0 << 31), 0u);
+        }
+        // stage the tile: len rows of RB bytes in 16-byte pieces, then one zero row
+        {
+            const auto ts = rsrc(x + (R + s0) * K, len * RB);
+            uint4 *d16 = reinterpret_cast<uint4 *>(dyn);
+            const uint32_t n16 = len * (RB / 16);
+            for (uint32_t i = threadIdx.x; i < n16; i += NT) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(ts, i * 16u, 0, 0);
+                __builtin_memcpy(&d16[i], &v, 16);
+            }
+            if (threadIdx.x < RB / 16) d16[n16 + threadIdx.x] = make_uint4(0u, 0u, 0u, 0u);
+        }
+        __syncthreads();
+        const V *xr = reinterpret_cast<const V *>(dyn);
+        // per-row index data, loaded one pass ahead so its latency overlaps the pass before
+        struct RowIdx {
+            uint4 tv[4];  // right-family targets of the first 32 bonds
+            uint4 xw;     // flipped-right-site offsets of the first 8 site slots
+            uint32_t rw;
+            double dr;
+        };
+        auto load_idx = [&](uint32_t rrow) -> RowIdx {
+            RowIdx d;
+            const uint32_t gr = P.rbase[mi] + s0 + (rrow < len ? rrow : 0u);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                d.tv[i] = i < nRq ? *reinterpret_cast<const uint4 *>(P.vo + ((size_t)i * P.rcount + gr) * 8)
+                                  : make_uint4(~0u, ~0u, ~0u, ~0u);
+            d.xw = P.nX > 0 ? *reinterpret_cast<const uint4 *>(P.xo + (size_t)gr * 8) : make_uint4(~0u, ~0u, ~0u, ~0u);
+            d.rw = P.rwords[gr];
+            d.dr = P.dr[gr];
+            return d;
+        };
+        RowIdx cur = load_idx(threadIdx.x);
+        for (uint32_t rr = threadIdx.x; rr - threadIdx.x < len; rr += NT) {  // uniform trip count per wave
+            const bool active = rr < len;
+            const uint32_t r = s0 + (active ? rr : 0u);
+            const uint32_t gr = P.rbase[mi] + r;
+            RowIdx nxt = cur;
+            if (rr - threadIdx.x + NT < len) nxt = load_idx(rr + NT);  // uniform
+            V acc;
+#pragma unroll
+            for (int c = 0; c < K; ++c) acc.v[c] = (T)0;
+            auto targets = [&](int qr, uint32_t (&e)[8]) {  // 0xFFFF: no hop
+                uint4 tv = make_uint4(~0u, ~0u, ~0u, ~0u);
+                if (qr < 4) {
+#pragma unroll
+                    for (int z = 0; z < 4; ++z)
+                        if (z == qr) tv = cur.tv[z];
+                } else {
+                    tv = *reinterpret_cast<const uint4 *>(P.vo + ((size_t)qr * P.rcount + gr) * 8);
+                }
+                const uint32_t wv[4] = {tv.x, tv.y, tv.z, tv.w};
+#pragma unroll
+                for (int u = 0; u < 8; ++u) e[u] = (u & 1) ? (wv[u >> 1] >> 16) : (wv[u >> 1] & 0xFFFFu);
+            };
+            int q0 = 0;
+            // bonds that stay inside the tile: one LDS read each, the zero row where there is no hop
+            for (; q0 + 8 <= nA; q0 += 8) {
+                uint32_t e[8];
+                targets(q0 >> 3, e);
+                V xv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) xv[u] = xr[e[u] != 0xFFFFu ? e[u] - s0 : len];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) hx::fma_acc<T, K>(acc, ramp[q0 + u], xv[u]);
+            }
+            // the others (and the tail of the first): the tile where the target is inside
+            // it, else the run in HBM
+            for (; q0 < P.nR; q0 += 8) {
+                uint32_t e[8];
+                targets(q0 >> 3, e);
+                V xv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const bool okb = q0 + u < P.nR;  // uniform
+                    const bool hop = okb && e[u] != 0xFFFFu;
+                    const uint32_t lr = e[u] - s0;  // row inside the tile (wraps when below it)
+                    const bool in = hop && lr < len;
+                    const bool out = hop && !in && active;
+                    xv[u] = xr[in ? lr : len];
+                    if (__builtin_amdgcn_ballot_w64(out)) {
+                        const V g = buf_load<T, K>(rs, out ? e[u] * RB : kOob);
+#pragma unroll
+                        for (int c = 0; c < K; ++c) xv[u].v[c] += g.v[c];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) hx::fma_acc<T, K>(acc, q0 + u < P.nR ? (T)ramp[q0 + u] : (T)0, xv[u]);
+            }
+            // bonds across the cut
+            T diag = (T)(dl + cur.dr);
+            const uint32_t rw = cur.rw;
+            for (int q0x = 0; q0x < P.nX; q0x += 2) {
+                V xv[2];
+                bool hop[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const bool ok = q0x + u < P.nX;  // uniform
+                    const int q = ok ? q0x + u : 0;
+                    const CrossBond cb = P.xb[q];
+                    __amdgpu_buffer_rsrc_t rr2;
+                    uint32_t b0;
+                    if (q < kTileXF) {
+                        const uint4 info = xinfo[q];
+                        const uint32_t lo = __builtin_amdgcn_readfirstlane(info.x);
+                        const uint32_t hi = __builtin_amdgcn_readfirstlane(info.y);
+                        const uint32_t nb = __builtin_amdgcn_readfirstlane(info.z);
+                        rr2 = rsrc(reinterpret_cast<const void *>(((uint64_t)hi << 32) | lo), nb & 0x7FFFFFFFu);
+                        b0 = nb >> 31;
+                    } else {
+                        b0 = (lw >> cb.lbit) & 1u;
+                        const uint64_t Rx = ro(P.xl)[(size_t)cb.si * P.count + gl];
+                        int mx = mi + (b0 ? -1 : 1);
+                        mx = mx < 0 ? 0 : (mx >= P.m_count ? P.m_count - 1 : mx);
+                        const bool valid = Rx != ~0ull;
+                        rr2 = rsrc(x + (valid ? Rx : 0ull) * K, valid ? P.ncols[mx] * RB : 0u);
+                    }
+                    const uint32_t xo = cb.sj < 8 ? u16_of(cur.xw, cb.sj)
+                                                  : P.xo[((size_t)(cb.sj >> 3) * P.rcount + gr) * 8 + (cb.sj & 7u)];
+                    hop[u] = ok && b0 != ((rw >> cb.rbit) & 1u);
+                    if (__builtin_amdgcn_ballot_w64(active && hop[u])) {
+                        xv[u] = buf_load<T, K>(rr2, hop[u] ? xo * RB : kOob);
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < K; ++c) xv[u].v[c] = (T)0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    if (q0x + u < P.nX) {
+                        hx::fma_acc<T, K>(acc, xamp[q0x + u], xv[u]);
+                        diag += hop[u] ? -xjz[q0x + u] : xjz[q0x + u];
+                    }
+                }
+            }
+            if (active) {
+                const V xs = xr[rr];
+                T *yr = y + (R + r) * K;
+#pragma unroll
+                for (int c = 0; c < K; ++c) __builtin_nontemporal_store(acc.v[c] + diag * xs.v[c], yr + c);
+            }
+            cur = nxt;
+        }
+        Q.finish();  // its barrier also ends the reads of the staged tile and of xinfo
+    }
+}
+
 // ------------------------------------------------------------------ columns
 struct ColParams {
     const void *x;
@@ -752,6 +977,13 @@ inline bool rows_lds_enabled() {
     return !(e && e[0] == '0');
 }
 
+// DCS_ROW_ORDER=rows (read at every product) launches the block tiles of the row
+// pass in row order instead of by groups of crossing sites.
+inline bool rows_group_order() {
+    const char *e = getenv("DCS_ROW_ORDER");
+    return !(e && e[0] == 'r');
+}
+
 inline int split_grid(const dcs_sector *s, uint64_t tiles) {
     const uint64_t cus = (uint64_t)device_cu_count(s->device);
     uint64_t w = cus * 4;
@@ -764,12 +996,13 @@ inline int split_grid(const dcs_sector *s, uint64_t tiles) {
 // Variants of the split product: the staged-run rows pass allowed (rows of at
 // most 8 bytes whose runs fit LDS), the rows pass from HBM, or the rows pass
 // that also applies the left family (no column pass).
-constexpr int kSplitStagedOk = 0, kSplitGlobal = 1, kSplitFused = 2;
+constexpr int kSplitStagedOk = 0, kSplitGlobal = 1, kSplitFused = 2, kSplitTiled = 3;
 
 template <typename T, int K>
 int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, const double *jxy,
                    const double *jz, const double *h, int nbonds, int variant, hipStream_t stream) {
     const bool staged_ok = variant == kSplitStagedOk, fused = variant == kSplitFused;
+    const bool tiled = variant == kSplitTiled;
     const LeftInfo &li = s->left;
     const uint32_t count = (uint32_t)li.count, rcount = (uint32_t)li.rcount;
     double *amp64 = c.d_diag + (count + rcount + 1) / 2 * 2;  // 16-byte aligned after the diagonal
@@ -875,12 +1108,59 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
                 staged = true;
             }
         }
+        if constexpr (RowBatch<T, K>::RB >= 16 && RowBatch<T, K>::RB <= 64) {
+            constexpr int ti = RowBatch<T, K>::RB == 16 ? 0 : (RowBatch<T, K>::RB == 32 ? 1 : 2);
+            const RowTiling &Tl = c.tiling[ti];
+            if (tiled && Tl.ntiles) {
+                TileParams TP;
+                memset(&TP, 0, sizeof(TP));
+                TP.x = x;
+                TP.y = y;
+                TP.amp = amp;
+                TP.lwords = P.lwords;
+                TP.rwords = P.rwords;
+                TP.runs = c.d_runs;
+                TP.xl = c.d_xl;
+                TP.vo = c.d_vo;
+                TP.xo = c.d_xo;
+                TP.dl = P.dl;
+                TP.dr = P.dr;
+                TP.tiles = rows_group_order() ? Tl.d_tiles : Tl.d_tiles_canon;
+                TP.pat = Tl.d_pat;
+                TP.counters = s->dev.counters;
+                xcd_ranges(Tl.ntiles, TP.xbase);
+                TP.count = count;
+                TP.rcount = rcount;
+                TP.m_count = li.m_count;
+                TP.nR = c.nR;
+                TP.nX = c.nX;
+                TP.nRA = c.nRA;
+                for (int m = 0; m < li.m_count; ++m) {
+                    TP.pbase[m] = Tl.pbase[m];
+                    TP.rbase[m] = li.rbase[m];
+                    TP.ncols[m] = (uint32_t)li.ncols[m];
+                }
+                memcpy(TP.xb, c.x, sizeof(TP.xb));
+                const size_t lds = (size_t)(Tl.max_rows + 1) * RowBatch<T, K>::RB;
+                auto kern = split_rows_tiled_kernel<T, K>;
+                if (int r = ensure_lds(kern, lds)) return r;
+                const int wgs = (int)std::min<uint64_t>((uint64_t)device_cu_count(s->device), (Tl.ntiles + 7) / 8 * 8);
+                kern<<<(wgs + 7) / 8 * 8, kTileThreads, lds, stream>>>(TP);
+                if (int r = check_hip(hipGetLastError(), "split rows (block tiles) launch")) return r;
+                staged = true;
+            }
+        }
         if (!staged) {
             P.nRloc = c.nRloc;
             P.margin = c.margin;
             P.lptr = c.d_lptr;
             P.lrun = c.d_lrun;
-            const size_t wl = P.nRloc > 0 ? (size_t)(kThreads + 2 * c.margin + 1) * RowBatch<T, K>::RB : 0;
+            size_t wl = P.nRloc > 0 ? (size_t)(kThreads + 2 * c.margin + 1) * RowBatch<T, K>::RB : 0;
+            if (wl > kRowLdsMax) {  // the window does not fit on chip: every right-family gather from HBM
+                P.nRloc = 0;
+                P.margin = 0;
+                wl = 0;
+            }
             auto kern = fused ? split_rows_kernel<T, K, true> : split_rows_kernel<T, K, false>;
             if (int r = ensure_lds(kern, wl)) return r;
             kern<<<split_grid(s, tiles), kThreads, wl, stream>>>(P);

@@ -327,3 +327,39 @@ def test_autotuned_form(monkeypatch, k, dt):
             monkeypatch.setenv(key, v)
         y = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), xd)
         assert rel_err(y.double().cpu().numpy(), y_ref) <= TOL[dt], env
+
+
+@pytest.mark.parametrize("L,n,split,k,dt", [
+    (24, 12, [6, 6, 6, 6], 8, torch.float32), (24, 12, [6, 6, 6, 6], 4, torch.float32),
+    (24, 12, [6, 6, 6, 6], 2, torch.float64), (24, 11, [6, 6, 6, 6], 8, torch.float64),
+    (26, 13, [5, 5, 4, 12], 8, torch.float32), (26, 13, [5, 5, 4, 12], 8, torch.float64),
+    (24, 12, [6, 4, 14], 8, torch.float64), (22, 10, [4, 4, 4, 5, 5], 4, torch.float64)])
+def test_block_tiled_rows(monkeypatch, L, n, split, k, dt):
+    """The row pass that stages whole n_K blocks of a run in LDS (the split_tiled form,
+    rows of 16 bytes and more), in both tile orders, against the oracle on every row,
+    and the staged form beside it.  The splits include n_K blocks larger than one tile (whole
+    sub-runs of equal P_K word per tile: 4/12 right halves) and sub-runs larger than
+    a tile (a 14-site last subsystem at 64-byte rows, 6/4/14)."""
+    monkeypatch.setenv("DCS_SPLIT_MIN_DIM", "0")
+    monkeypatch.setenv("DCS_AUTOTUNE", "0")
+    s = dq.Sector(L, n, 2, split)
+    ns = native.NativeSector(2, L, n, split)
+    bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.5, 1.0)
+    hf = synth.gaussian(L, 9)
+    t = dq.Terms(bonds)
+    x = synth.vector(s.dim, synth.SEED_X, k=k)
+    y_ref = native.hx_range(ns, native.NativeTerms(bonds, jxy, jz, hf), x)
+    xd = torch.tensor(x, device=DEV).to(dt)
+    out = {}
+    for name, env in (("groups", {"DCS_SPLIT_TILED": "1"}),
+                      ("rows", {"DCS_SPLIT_TILED": "1", "DCS_ROW_ORDER": "rows"}), ("untiled", {})):
+        for key in ("DCS_ROW_ORDER", "DCS_SPLIT_TILED"):
+            monkeypatch.delenv(key, raising=False)
+        for key, v in env.items():
+            monkeypatch.setenv(key, v)
+        out[name] = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), xd, h=dev_f64(hf))
+        e = rel_err(out[name].double().cpu().numpy(), y_ref)
+        say("tiled rows", L, n, split, k, dt, name, e)
+        assert e <= TOL[dt], (name, e)
+    # the tile order changes which workgroup computes a row, not the row's arithmetic
+    assert torch.equal(out["groups"], out["rows"])
