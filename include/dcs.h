@@ -232,16 +232,20 @@ int dcs_adjoint_workspace_size(const dcs_sector *sector, const dcs_terms *terms,
  *   d_grad_jxy[b]   = sum_s g_s ((S+_i S-_j + S-_i S+_j)/2 x)_s
  *   d_grad_jz[b]    = sum_s g_s (Sz_i Sz_j x)_s
  *   d_grad_h[i]     = sum_s g_s (Sz_i x)_s            (skipped if d_grad_h == NULL)
- * One pass ranks every reached state once and uses it for both g and x.  On a
- * sector with a split view whose products run on the split tables (the form
- * the autotuner keeps for this terms object and dtype at k = 1, see
- * dcs_hamiltonian_apply, including its first-call timing), d_grad_x can also
- * come from that product applied to g, the pass then forming only the sums (it
- * gathers x, not g); the first call for a (terms, dtype) times both ways (each
- * twice, HIP events, synchronising the stream) and keeps the faster (the split
- * way inside stream capture or with DCS_AUTOTUNE=0).  The sums are reduced per
- * workgroup into d_workspace and then in a fixed order, so the result is
- * deterministic.  The coupling gradients are
+ Three ways compute it: (0) one fused pass that ranks every reached state once and
+ * uses it for both g and x; on a sector with a split view whose products run on
+ * the split tables (the form the autotuner keeps for this terms object and dtype
+ * at k = 1, see dcs_hamiltonian_apply, including its first-call timing), (1)
+ * d_grad_x from that product applied to g and a pass forming only the sums (it
+ * gathers x, not g), and for FP32 (2) the sums formed inside the split product of
+ * g itself: each hop's gathered g_t times x at the row gives the coupling sum (the
+ * hop is symmetric), and per-run / per-right-configuration sums of x_s g_s give
+ * the S^z S^z and field sums.  The first call for a (terms, dtype) times the ways
+ * that apply (each twice, HIP events, synchronising the stream) and keeps the
+ * fastest (way 2 where it applies, else 1, inside stream capture or with
+ * DCS_AUTOTUNE=0; DCS_ADJOINT_WAY=0/1/2 in the environment forces a way).  The
+ * sums are reduced per workgroup or per tile into d_workspace and then in a
+ * fixed order, so the result is deterministic.  The coupling gradients are
  * FP64 whatever dtype is.  d_grad_x may be NULL (only coupling gradients);
  * it must not overlap d_x or d_g.
  */
@@ -260,8 +264,8 @@ int dcs_hamiltonian_apply_adjoint(const dcs_sector *sector, const dcs_terms *ter
  * d_grad_x may differ from the other entry point's by rounding in FP32; the
  * coupling sums are the same).  The per-workgroup partial sums go to a fixed
  * 4 MiB device array of the library, one per GPU, kept until the process ends;
- * the call returns DCS_EUNSUPPORTED when dcs_adjoint_workspace_size exceeds
- * 4 MiB.  It calls no allocating routine.  Every call on one GPU shares that
+ * the call returns DCS_EUNSUPPORTED when the single pass needs more than 4 MiB
+ * of partial sums (one row of 2 * num_bonds + L doubles per workgroup).  It calls no allocating routine.  Every call on one GPU shares that
  * array, so calls that overlap in time on one GPU (other streams, other
  * threads) race and must be serialised by the caller.
  */

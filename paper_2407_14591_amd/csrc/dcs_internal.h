@@ -146,6 +146,18 @@ struct RowTiling {
     std::vector<uint2> h_pat, h_tiles, h_canon;  // host copies while building
 };
 
+// One output sum of the adjoint on the split view: a weighted sum over the
+// per-tile values the passes wrote (see split_adjoint.hip).
+struct AdjTask {
+    uint16_t out;     // [0, nb) d/dJxy, [nb, 2 nb) d/dJz, [2 nb, 2 nb + L) d/dh
+    uint8_t src;      // 0: row-pass value v per left configuration, 1: column-pass bond v per
+                      // column tile, 2: right-configuration sum of x_s g_s
+    uint8_t mode;     // weight from the entry's word: 0: 1, 1: s_a s_b / 4, 2: s_a / 4, 3: bit_a - 1/2
+    uint8_t ba, bb;   // bits a, b of the packed left (src 0) or right (src 2) word (s = 2 bit - 1)
+    uint16_t v;
+    float scale;
+};
+
 struct SplitRows {
     uint64_t terms_id = 0;           // 0: empty slot
     uint32_t *d_lptr = nullptr;      // left family: entry range of every left configuration
@@ -176,6 +188,9 @@ struct SplitRows {
     uint64_t lnnz = 0;
     uint16_t r_bond[kMaxBonds];      // bond index of every right-family bond
     RowTiling tiling[kRowTilings];   // block tiles of the row pass, by row size
+    AdjTask *d_adjtasks = nullptr;   // the adjoint's output sums (2 per bond, 1 per site)
+    int n_adjtasks = 0;
+    uint8_t jbit[8] = {};            // packed right bit of crossing right-site slot j (j < 8)
     CrossBond x[kMaxCross];
     DiagTerm d[kMaxBonds + kMaxSites];
     // streams that have run products on these tables, with an event recorded
@@ -271,6 +286,15 @@ int launch_hx(const dcs_sector *s, const dcs_terms *t, const double *jxy, const 
               const double *h, int dtype, int k, const void *x, void *y, hipStream_t stream);
 int hx_form(const dcs_sector *s, const dcs_terms *t, int dtype, int k);
 size_t adjoint_ws_bytes(const dcs_sector *s, const dcs_terms *t);
+size_t adjoint_single_ws_bytes(const dcs_sector *s, const dcs_terms *t);  // the fused single pass
+// The adjoint on the split view for FP32 (sums formed inside the split product of g);
+// DCS_EUNSUPPORTED (no error message) where it does not apply.
+int launch_split_adjoint(dcs_sector *s, const SplitRows &c, const double *jxy, const double *jz,
+                         const double *h, int nbonds, const void *x, const void *g, void *gx,
+                         double *gjxy, double *gjz, double *gh, void *ws, size_t ws_bytes,
+                         hipStream_t stream);
+size_t split_adjoint_ws_bytes(const dcs_sector *s, int nbonds);
+bool split_adjoint_applies(const dcs_sector *s, const SplitRows &c, int dtype);
 // The adjoint in one fused pass over the rows (no split tables, no autotuner, no
 // allocation): workspace partials only.
 int launch_adjoint_single(const dcs_sector *s, const dcs_terms *t, const double *jxy,

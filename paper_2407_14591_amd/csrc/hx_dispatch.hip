@@ -263,9 +263,13 @@ int launch_hx(const dcs_sector *s, const dcs_terms *t, const double *jxy, const 
 
 // An upper bound: the adjoint's tiles of several rows per thread need at most as many
 // workgroups as tiles of one row per thread.
-size_t adjoint_ws_bytes(const dcs_sector *s, const dcs_terms *t) {
+size_t adjoint_single_ws_bytes(const dcs_sector *s, const dcs_terms *t) {
     const Grid g = plan_grid(s, adj_lds_bytes(s, t->num_bonds, coeff_lds_bytes<double>()));
     return (size_t)g.wgs * (2 * t->num_bonds + s->desc.L) * sizeof(double);
+}
+
+size_t adjoint_ws_bytes(const dcs_sector *s, const dcs_terms *t) {
+    return std::max(adjoint_single_ws_bytes(s, t), split_adjoint_ws_bytes(s, t->num_bonds));
 }
 
 namespace {
@@ -330,7 +334,6 @@ int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, c
                    double *gjxy, double *gjz, double *gh, void *ws, size_t ws_bytes,
                    hipStream_t stream) {
     DeviceGuard dg(s->device);
-    (void)ws_bytes;
     auto fused = [&]() {
         return adjoint_pass(s, t, jxy, jz, h, dtype, x, g, gx, gjxy, gjz, gh, ws, stream);
     };
@@ -355,10 +358,20 @@ int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, c
         if (int r = launch_form(sm, t, *c, form, jxy, jz, h, dtype, 1, g, gx, stream)) return r;
         return adjoint_pass(s, t, jxy, jz, h, dtype, x, g, nullptr, gjxy, gjz, gh, ws, stream);
     };
+    // the adjoint on the split view with its sums formed inside the product (FP32)
+    const bool adj_ok = split_adjoint_applies(s, *c, dtype) && ws_bytes >= split_adjoint_ws_bytes(s, t->num_bonds);
+    auto split_adj = [&]() {
+        return launch_split_adjoint(sm, *c, jxy, jz, h, t->num_bonds, x, g, gx, gjxy, gjz, gh, ws, ws_bytes, stream);
+    };
+    auto run_way = [&](int w) { return w == 0 ? fused() : (w == 1 ? split_way() : split_adj()); };
     const uint64_t key = tuned_key(t, dtype, 0);  // k = 0: the adjoint's entry
     LeftInfo &li = sm->left;
     int way = -1;
-    {
+    if (const char *e = getenv("DCS_ADJOINT_WAY")) {  // 0 fused pass, 1 product + sums pass, 2 sums in the product
+        way = e[0] - '0';
+        if (way < 0 || way > 2 || (way == 2 && !adj_ok)) way = -1;
+    }
+    if (way < 0) {
         std::lock_guard<std::mutex> lk(*li.rows_lock);
         auto it = li.tuned.find(key);
         if (it != li.tuned.end()) way = it->second;
@@ -367,15 +380,15 @@ int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, c
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (!autotune_enabled() || hipStreamIsCapturing(stream, &cs) != hipSuccess ||
             cs != hipStreamCaptureStatusNone) {
-            const int r = split_way();
+            const int r = run_way(adj_ok ? 2 : 1);
             if (!r) note_split_use(sm, *c, stream);
             return r;
         }
         float best = 0.f;
-        for (int w = 0; w < 2; ++w) {
+        for (int w = 0; w < (adj_ok ? 3 : 2); ++w) {
             float ms = 0.f;
             for (int rep = 0; rep < 2; ++rep) {
-                ms = w == 0 ? time_on_stream(fused, stream) : time_on_stream(split_way, stream);
+                ms = time_on_stream([&]() { return run_way(w); }, stream);
                 if (ms < 0.f) return dcs_last_error()[0] ? DCS_EHIP : set_error(DCS_EHIP, "adjoint autotune timing");
             }
             if (w == 0 || ms < best) {
@@ -386,7 +399,7 @@ int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, c
         std::lock_guard<std::mutex> lk(*li.rows_lock);
         li.tuned[key] = way;
     }
-    const int r = way == 0 ? fused() : split_way();
+    const int r = run_way(way);
     if (!r) note_split_use(sm, *c, stream);
     return r;
 }

@@ -55,7 +55,7 @@ extern "C" int dcs_hamiltonian_apply_adjoint_noalloc(const dcs_sector *s, const 
     if (s->device < 0 || s->device >= kMaxDevices)
         return set_error(DCS_EUNSUPPORTED, "device %d beyond the %d devices of the scratch table",
                          s->device, kMaxDevices);
-    const size_t need = adjoint_ws_bytes(s, t);
+    const size_t need = adjoint_single_ws_bytes(s, t);
     if (need > kScratchBytes)
         return set_error(DCS_EUNSUPPORTED,
                          "the adjoint needs %zu bytes of partial sums here, more than the %zu of the "

@@ -338,6 +338,7 @@ void free_rows(SplitRows &c) {
         hipFree(c.tiling[i].d_tiles_canon);
         hipFree(c.tiling[i].d_pat);
     }
+    hipFree(c.d_adjtasks);
     for (int i = 0; i < c.nuse; ++i) hipEventDestroy(c.use_event[i]);
     c = SplitRows();
 }

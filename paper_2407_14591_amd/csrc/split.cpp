@@ -312,6 +312,34 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
             T.h_canon = std::move(canon);
         }
     }
+    // the adjoint's output sums (see split_adjoint.hip for the values they read)
+    std::vector<AdjTask> tasks;
+    {
+        const int nb = t->num_bonds;
+        for (int q = 0; q < c.nR; ++q) {
+            const SideBond &fb = right[q];
+            const uint8_t bi = (uint8_t)(li.word_shift[fb.a] + fb.pi), bj = (uint8_t)(li.word_shift[fb.b] + fb.pj);
+            tasks.push_back(AdjTask{fb.bond, 0, 0, 0, 0, (uint16_t)q, 0.5f});
+            tasks.push_back(AdjTask{(uint16_t)(nb + fb.bond), 2, 1, bi, bj, 0, 1.0f});
+        }
+        for (int q = 0; q < c.nX; ++q) {
+            const CrossBond &cb = c.x[q];
+            tasks.push_back(AdjTask{cb.bond, 0, 0, 0, 0, (uint16_t)(32 + q), 0.5f});
+            tasks.push_back(AdjTask{(uint16_t)(nb + cb.bond), 0, 2, cb.lbit, 0, (uint16_t)(41 + cb.sj), 1.0f});
+        }
+        for (const SideBond &fb : left) {
+            const uint8_t bi = (uint8_t)(li.word_shift[fb.a] + fb.pi), bj = (uint8_t)(li.word_shift[fb.b] + fb.pj);
+            tasks.push_back(AdjTask{fb.bond, 1, 0, 0, 0, fb.bond, 0.5f});
+            tasks.push_back(AdjTask{(uint16_t)(nb + fb.bond), 0, 1, bi, bj, 40, 1.0f});
+        }
+        for (int i = 0; i < sd.L; ++i) {
+            const bool lft = sd.site_sub[i] < K;
+            tasks.push_back(AdjTask{(uint16_t)(2 * nb + i), (uint8_t)(lft ? 0 : 2), 3, packed_bit(i), 0,
+                                    (uint16_t)(lft ? 40 : 0), 1.0f});
+        }
+        c.n_adjtasks = (int)tasks.size();
+        for (int j = 0; j < c.nJs && j < 8; ++j) c.jbit[j] = packed_bit(rsites[j]);
+    }
     DeviceGuard dg(s->device);
     // the left family with every target as a run start (bond << 48 | run), for the
     // rows pass that applies the left family itself
@@ -340,6 +368,7 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
               // diagonal of both sides, then the per-call coupling factors (1024 doubles + 1024 floats)
               check_hip(hipMalloc(&c.d_diag, ((li.count + li.rcount + 1) / 2 * 2 + 1536) * sizeof(double)),
                         "hipMalloc split diagonal") == DCS_OK;
+    ok = ok && up((void **)&c.d_adjtasks, tasks.data(), tasks.size() * sizeof(AdjTask));
     for (int ti = 0; ti < kRowTilings && ok; ++ti) {
         RowTiling &T = c.tiling[ti];
         if (!T.ntiles) continue;

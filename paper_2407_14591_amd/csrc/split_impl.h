@@ -216,8 +216,21 @@ struct RowParams {
     uint64_t tbase[kMaxLeftM + 1];
     uint16_t rbond[kMaxBonds];
     CrossBond xb[kMaxCross];
+    // adjoint (ADJ): the product is of g (x above); xprim is the primal vector x and
+    // part receives per-tile sums [value][tile] (kAdjRowValues values, one tile per run)
+    const void *xprim;
+    double *part;
+    uint32_t part_n;
+    int nJs;
+    uint8_t jbit[8];  // bit of crossing right-site slot j in a packed right word
 };
 static_assert(sizeof(RowParams) <= 4096, "kernel arguments are limited to 4 KiB");
+
+// Values of one run's tile in the adjoint row pass: sum_s x_s g_t over the hops of
+// right-family bonds 0..31 and bonds across the cut 0..7, then sum_s x_s g_s, then
+// sum_s (2 b_j(s) - 1) x_s g_s for crossing right-site slots 0..7.
+constexpr int kAdjR = 32, kAdjX = 8, kAdjJ = 8;
+constexpr int kAdjRowValues = kAdjR + kAdjX + 1 + kAdjJ;
 
 // Gathers in flight per batch, sized for about 96 registers of gathered data:
 // every gather is one whole row of K values (RB bytes, one to four 16-byte loads).
@@ -478,7 +491,10 @@ constexpr int lds_rows_threads() {
     return K * sizeof(T) == 4 ? 512 : 1024;
 }
 
-template <typename T, int K>
+// ADJ (k = 1): the product is y = H g (x is g); the pass also forms, per run, the
+// values of kAdjRowValues (hop sums of right-family and cross-cut bonds with the
+// primal vector at the row, and the diagonal sums) and writes them to P.part.
+template <typename T, int K, bool ADJ = false>
 __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_kernel(const RowParams P_arg) {
     (void)P_arg;
     const RowParams &P = kernel_arg0<RowParams>();
@@ -492,6 +508,8 @@ __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_ker
     V *xr = reinterpret_cast<V *>(dyn);
     __shared__ uint4 xinfo[XF];  // per bond across the cut: run base (lo, hi), bytes | bit << 31
     __shared__ uint32_t slots[2];
+    __shared__ double red[ADJ ? (NT / 64) * 64 : 1];  // ADJ: per-wave totals of the run's values
+    static_assert(!ADJ || K == 1, "the adjoint row pass takes one column");
     const cptr<T> A = ro(reinterpret_cast<const T *>(P.amp));
     const cptr<T> ramp = A + kAmpRight, xamp = A + kAmpCross, xjz = A + kJzCross;
     const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
@@ -539,6 +557,16 @@ __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_ker
             }
         }
         ChunkIdx cur = load_chunk_idx(P, mi, threadIdx.x, ncols, nRq);
+        float jr[ADJ ? kAdjR : 1], jx[ADJ ? kAdjX : 1], cj[ADJ ? kAdjJ : 1], pl = 0.f;
+        if constexpr (ADJ) {
+#pragma unroll
+            for (int i = 0; i < kAdjR; ++i) jr[i] = 0.f;
+#pragma unroll
+            for (int i = 0; i < kAdjX; ++i) jx[i] = 0.f;
+#pragma unroll
+            for (int i = 0; i < kAdjJ; ++i) cj[i] = 0.f;
+        }
+        const T *__restrict__ xp = reinterpret_cast<const T *>(P.xprim);
         __syncthreads();
         for (uint32_t c0 = 0; c0 < ncols; c0 += NT) {
             const uint32_t r = c0 + threadIdx.x;
@@ -548,6 +576,8 @@ __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_ker
             V acc;
 #pragma unroll
             for (int c = 0; c < K; ++c) acc.v[c] = (T)0;
+            float xo_own = 0.f;  // ADJ: the primal vector at this row (0 past the run)
+            if constexpr (ADJ) xo_own = active ? (float)xp[R + r] : 0.f;
             // right family from the staged run
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -555,7 +585,9 @@ __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_ker
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const uint32_t e = (u & 1) ? (wv[u >> 1] >> 16) : (wv[u >> 1] & 0xFFFFu);
-                    hx::fma_acc<T, K>(acc, ramp[i * 8 + u], xr[e < ncols ? e : ncols]);
+                    const V gv = xr[e < ncols ? e : ncols];
+                    hx::fma_acc<T, K>(acc, ramp[i * 8 + u], gv);
+                    if constexpr (ADJ) jr[i * 8 + u] += xo_own * (float)gv.v[0];
                 }
             }
             if (nRq > 4) {  // more than 32 right-family bonds
@@ -572,7 +604,27 @@ __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_ker
             }
             // bonds across the cut
             T diag = (T)(dl + cur.dr);
-            for (int q0 = 0; q0 < nXF; q0 += XB) {
+            if constexpr (ADJ) {  // at most kAdjX bonds, each with its own sum
+#pragma unroll
+                for (int q = 0; q < kAdjX; ++q) {
+                    if (q < P.nX) {  // uniform
+                        const CrossBond cb = P.xb[q];
+                        const uint4 info = xinfo[q];
+                        const uint32_t lo = __builtin_amdgcn_readfirstlane(info.x);
+                        const uint32_t hi = __builtin_amdgcn_readfirstlane(info.y);
+                        const uint32_t nb = __builtin_amdgcn_readfirstlane(info.z);
+                        const auto rr = rsrc(reinterpret_cast<const void *>(((uint64_t)hi << 32) | lo),
+                                             nb & 0x7FFFFFFFu);
+                        const uint32_t xo = u16_of(cur.xw, cb.sj);
+                        const bool h = (nb >> 31) != ((cur.rw >> cb.rbit) & 1u);
+                        const V gv = buf_load<T, K>(rr, h && active ? xo * RB : kOob);
+                        hx::fma_acc<T, K>(acc, xamp[q], gv);
+                        diag += h ? -xjz[q] : xjz[q];
+                        jx[q] += xo_own * (float)gv.v[0];
+                    }
+                }
+            }
+            for (int q0 = 0; q0 < (ADJ ? 0 : nXF); q0 += XB) {
                 V xv[XB];
                 bool hop[XB];
 #pragma unroll
@@ -609,7 +661,7 @@ __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_ker
                     }
                 }
             }
-            for (int q = XF; q < P.nX; ++q) {  // more than XF bonds across the cut
+            for (int q = XF; q < (ADJ ? 0 : P.nX); ++q) {  // more than XF bonds across the cut
                 const CrossBond cb = P.xb[q];
                 const uint32_t b0 = (lw >> cb.lbit) & 1u;
                 const uint64_t Rx = ro(P.xl)[(size_t)cb.si * P.count + gl];
@@ -629,9 +681,42 @@ __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_ker
 #pragma unroll
                 for (int c = 0; c < K; ++c) __builtin_nontemporal_store(acc.v[c] + diag * xs.v[c], yr + c);
             }
+            if constexpr (ADJ) {  // the diagonal sums: x_s g_s, and its signs by crossing right site
+                const float pg = xo_own * (float)xr[active ? r : ncols].v[0];
+                pl += pg;
+#pragma unroll
+                for (int j = 0; j < kAdjJ; ++j)
+                    if (j < P.nJs) cj[j] += ((cur.rw >> P.jbit[j]) & 1u) ? pg : -pg;
+            }
             cur = nxt;
         }
-        Q.finish();  // its barrier also ends the reads of the staged run
+        if constexpr (ADJ) {
+            // the run's values: transposed wave sums (fixed order), then the waves in order
+            const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+            double v16[16];
+#pragma unroll
+            for (int grp = 0; grp < 4; ++grp) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int q = grp * 16 + i;  // value index
+                    float f = 0.f;
+                    if (q < kAdjR) f = jr[q];
+                    else if (q < kAdjR + kAdjX) f = jx[q - kAdjR];
+                    else if (q == kAdjR + kAdjX) f = pl;
+                    else if (q < kAdjRowValues) f = cj[q - kAdjR - kAdjX - 1];
+                    v16[i] = (double)f;
+                }
+                const double tsum = hx::wave_transpose_sum<16>(v16);
+                if (lane < 16) red[wave * 64 + grp * 16 + lane] = tsum;
+            }
+            __syncthreads();
+            if ((int)threadIdx.x < kAdjRowValues) {
+                double tot = 0.0;
+                for (int w = 0; w < NT / 64; ++w) tot += red[w * 64 + threadIdx.x];
+                P.part[(size_t)threadIdx.x * P.part_n + gl] = tot;
+            }
+        }
+        Q.finish();  // its barrier also ends the reads of the staged run (and of red)
     }
 }
 
@@ -873,6 +958,11 @@ struct ColParams {
     int m_count, nbonds;
     uint32_t ncols[kMaxLeftM], clbase[kMaxLeftM], nclust[kMaxLeftM];
     uint64_t tbase[kMaxLeftM + 1];
+    // adjoint (ADJ): xprim is the primal vector; part receives per-tile sums
+    // sum_s x_s g_t of every left-family bond, [bond][tile]
+    const void *xprim;
+    double *part;
+    uint64_t part_n;
 };
 static_assert(sizeof(ColParams) <= 4096, "kernel arguments are limited to 4 KiB");
 
@@ -886,7 +976,10 @@ constexpr uint32_t kColWaveBytes = 64 * kColLaneBytes;
 // chunk of their runs.  The chunk of every run of the cluster is first copied
 // to LDS; the targets inside the cluster (bonds inside P_{K-1}) are then read
 // there, the others from HBM.  Wave w takes the cluster's runs w, w+8, ...
-template <typename T, int K>
+// ADJ (k = 1): the product is y += (left family) g (x is g); each hop also adds
+// x_s g_t to its bond's sum (per-wave LDS slots after the dynamic staging area, one
+// writing wave each, added in wave order at the end of the tile into P.part).
+template <typename T, int K, bool ADJ = false>
 __global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams P_arg) {
     (void)P_arg;
     const ColParams &P = kernel_arg0<ColParams>();
@@ -901,6 +994,10 @@ __global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams
     T *__restrict__ y = reinterpret_cast<T *>(P.y);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
+    static_assert(!ADJ || K == 1, "the adjoint column pass takes one column");
+    // ADJ: [wave][bond] sums after the staged chunks (kMaxClusterRuns of them)
+    double *wacc = reinterpret_cast<double *>(cl_lds + (size_t)kMaxClusterRuns * kColWaveBytes);
+    const T *__restrict__ xp = reinterpret_cast<const T *>(P.xprim);
     AheadQueue Q(P.counters, P.xbase, slots);
     BlockCursor blk(P.tbase, P.m_count);
     uint64_t t;
@@ -925,6 +1022,8 @@ __global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams
             }
             return v;
         };
+        if constexpr (ADJ)
+            for (int b = (int)lane; b < P.nbonds; b += 64) wacc[wave * P.nbonds + b] = 0.0;
         // stage the chunk of every run of the cluster (zeros past a run's end)
         for (uint32_t i = wave; i < size; i += kColWaves) {
             const vec_t v = load16(rsrc(x + ro(P.runs)[g0 + i] * K, nrec));
@@ -934,10 +1033,13 @@ __global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams
         for (uint32_t i = wave; i < size; i += kColWaves) {
             const uint32_t gl = g0 + i;
             vec_t acc = (vec_t)(T)0;
+            vec_t xo4 = (vec_t)(T)0;  // ADJ: the primal vector at this lane's rows
+            if constexpr (ADJ) xo4 = load16(rsrc(xp + ro(P.runs)[gl] * K, nrec));
             const uint32_t q1 = ro(P.lptr)[gl + 1];
             for (uint32_t q0 = ro(P.lptr)[gl]; q0 < q1; q0 += kColBatch) {
                 vec_t v[kColBatch];
                 T a[kColBatch];
+                uint32_t bnd[kColBatch];
 #pragma unroll
                 for (int u = 0; u < kColBatch; ++u) {
                     const bool ok = q0 + u < q1;
@@ -949,10 +1051,30 @@ __global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams
                     } else {
                         v[u] = load16(rsrc(x + (ent & 0xFFFFFFFFFFFFull) * K, ok ? nrec : 0u));
                     }
-                    a[u] = ok ? amp[(ent >> 48) & 0xFFu] : (T)0;
+                    bnd[u] = (uint32_t)(ent >> 48) & 0xFFu;
+                    a[u] = ok ? amp[bnd[u]] : (T)0;
                 }
 #pragma unroll
                 for (int u = 0; u < kColBatch; ++u) acc += a[u] * v[u];
+                if constexpr (ADJ) {
+                    // x_s g_t over this lane's rows, one value per hop; wave totals in
+                    // lanes 4u (transposed sum), added to the bond's slot of this wave
+                    double d[kColBatch];
+#pragma unroll
+                    for (int u = 0; u < kColBatch; ++u) {
+                        float f = 0.f;
+#pragma unroll
+                        for (int e = 0; e < V; ++e) f += (float)xo4[e] * (float)v[u][e];
+                        d[u] = q0 + u < q1 ? (double)f : 0.0;
+                    }
+                    static_assert(kColBatch == 4, "the transposed sum takes 4 values");
+                    const double tsum = hx::wave_transpose_sum<4>(d);
+                    const uint32_t u = lane >> 2;
+                    if (lane < 16 && (lane & 3u) == 0 && q0 + u < q1) {
+                        const uint32_t b = u == 0 ? bnd[0] : (u == 1 ? bnd[1] : (u == 2 ? bnd[2] : bnd[3]));
+                        wacc[wave * P.nbonds + b] += tsum;
+                    }
+                }
             }
             if (boff < nrec) {
                 T *ys = reinterpret_cast<T *>(reinterpret_cast<char *>(y + ro(P.runs)[gl] * K) + boff);
@@ -966,7 +1088,15 @@ __global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams
                 }
             }
         }
-        Q.finish();  // its barrier also ends the reads of the staged chunks
+        if constexpr (ADJ) {
+            __syncthreads();
+            for (int b = (int)threadIdx.x; b < P.nbonds; b += kColThreads) {
+                double tot = 0.0;
+                for (int w = 0; w < kColWaves; ++w) tot += wacc[w * P.nbonds + b];
+                P.part[(size_t)b * P.part_n + t] = tot;
+            }
+        }
+        Q.finish();  // its barrier also ends the reads of the staged chunks (and of wacc)
     }
 }
 
@@ -998,6 +1128,34 @@ inline int split_grid(const dcs_sector *s, uint64_t tiles) {
 // that also applies the left family (no column pass).
 constexpr int kSplitStagedOk = 0, kSplitGlobal = 1, kSplitFused = 2, kSplitTiled = 3;
 
+// The diagonal of each side per configuration and the call's coupling factors
+// (FP64 table, then FP32 copy) into c.d_diag.
+inline int launch_split_diag(dcs_sector *s, const SplitRows &c, const double *jxy, const double *jz,
+                             const double *h, int nbonds, hipStream_t stream) {
+    const LeftInfo &li = s->left;
+    const uint32_t count = (uint32_t)li.count, rcount = (uint32_t)li.rcount;
+    DiagParams D;
+    memset(&D, 0, sizeof(D));
+    D.lwords = (const uint32_t *)li.d_words;
+    D.rwords = (const uint32_t *)li.d_rwords;
+    D.jxy = jxy;
+    D.jz = jz;
+    D.h = h;
+    D.out = c.d_diag;
+    D.amp64 = c.d_diag + (count + rcount + 1) / 2 * 2;
+    D.count = count;
+    D.rcount = rcount;
+    D.nD = c.nD;
+    D.nR = c.nR;
+    D.nX = c.nX;
+    D.nbonds = nbonds;
+    memcpy(D.d, c.d, sizeof(D.d));
+    memcpy(D.rbond, c.r_bond, sizeof(D.rbond));
+    for (int q = 0; q < c.nX; ++q) D.xbond[q] = c.x[q].bond;
+    split_diag_kernel<0><<<(count + rcount + 255) / 256, 256, 0, stream>>>(D);
+    return check_hip(hipGetLastError(), "split diagonal launch");
+}
+
 template <typename T, int K>
 int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, const double *jxy,
                    const double *jz, const double *h, int nbonds, int variant, hipStream_t stream) {
@@ -1008,28 +1166,7 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
     double *amp64 = c.d_diag + (count + rcount + 1) / 2 * 2;  // 16-byte aligned after the diagonal
     const void *amp = sizeof(T) == 8 ? (const void *)amp64 : (const void *)(amp64 + kAmpEntries);
     // 1. diagonal per configuration of each side, coupling factors
-    {
-        DiagParams D;
-        memset(&D, 0, sizeof(D));
-        D.lwords = (const uint32_t *)li.d_words;
-        D.rwords = (const uint32_t *)li.d_rwords;
-        D.jxy = jxy;
-        D.jz = jz;
-        D.h = h;
-        D.out = c.d_diag;
-        D.amp64 = amp64;
-        D.count = count;
-        D.rcount = rcount;
-        D.nD = c.nD;
-        D.nR = c.nR;
-        D.nX = c.nX;
-        D.nbonds = nbonds;
-        memcpy(D.d, c.d, sizeof(D.d));
-        memcpy(D.rbond, c.r_bond, sizeof(D.rbond));
-        for (int q = 0; q < c.nX; ++q) D.xbond[q] = c.x[q].bond;
-        split_diag_kernel<0><<<(count + rcount + 255) / 256, 256, 0, stream>>>(D);
-        if (int r = check_hip(hipGetLastError(), "split diagonal launch")) return r;
-    }
+    if (int r = launch_split_diag(s, c, jxy, jz, h, nbonds, stream)) return r;
     hx::zero_counters<0><<<1, 64, 0, stream>>>(s->dev.counters, 16);
     // 2. right family, bonds across the cut, diagonal: tiles of 512 offsets of one run
     {
