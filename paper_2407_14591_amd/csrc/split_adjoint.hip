@@ -10,8 +10,8 @@
 //     and per right configuration the sum over the runs of its block (PR), give them.
 // The row pass (runs staged in LDS) writes per run the right-family and cross-cut
 // hop sums, PL and CJ; the column pass writes per tile the left-family hop sums;
-// a column-sum kernel forms PR in slices of the left configurations; a final kernel
-// adds each output sum over its values in a fixed order.  No atomics: the result
+// a column-sum kernel forms PR in slices of the left configurations, a second adds
+// the slices; a final kernel adds each output sum over its values in a fixed order.  No atomics: the result
 // is reproducible bit for bit.
 #include "split_impl.h"
 
@@ -50,9 +50,20 @@ __global__ __launch_bounds__(256) void adj_colsum_kernel(const ColSumParams P_ar
     P.prp[(size_t)sl * P.rcount + gr] = acc;
 }
 
+// PR[r] = sum over the slices in order (one thread per right configuration).
+template <int Unused = 0>
+__global__ __launch_bounds__(256) void adj_prsum_kernel(const double *__restrict__ prp, double *__restrict__ pr,
+                                                       uint32_t rcount) {
+    const uint32_t gr = blockIdx.x * 256u + threadIdx.x;
+    if (gr >= rcount) return;
+    double acc = 0.0;
+    for (int sl = 0; sl < kPrSplit; ++sl) acc += prp[(size_t)sl * rcount + gr];
+    pr[gr] = acc;
+}
+
 struct FinalParams {
     const AdjTask *tasks;
-    const double *rowpart, *colpart, *prp;
+    const double *rowpart, *colpart, *pr;
     const uint32_t *lwords, *rwords;
     double *gjxy, *gjz, *gh;
     uint64_t count, rcount, ncoltiles;
@@ -85,11 +96,7 @@ __global__ __launch_bounds__(kAdjFinalThreads) void adj_final_kernel(const Final
         const double *v = P.colpart + (size_t)k.v * P.ncoltiles;
         for (uint64_t i = threadIdx.x; i < P.ncoltiles; i += kAdjFinalThreads) acc += v[i];
     } else {
-        for (uint64_t i = threadIdx.x; i < P.rcount; i += kAdjFinalThreads) {
-            double pr = 0.0;
-            for (int sl = 0; sl < kPrSplit; ++sl) pr += P.prp[(size_t)sl * P.rcount + i];
-            acc += task_weight(k, P.rwords[i]) * pr;
-        }
+        for (uint64_t i = threadIdx.x; i < P.rcount; i += kAdjFinalThreads) acc += task_weight(k, P.rwords[i]) * P.pr[i];
     }
     acc = hx::wave_sum(acc);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
@@ -147,7 +154,7 @@ size_t split_adjoint_ws_bytes(const dcs_sector *s, int nbonds) {
     }
     const size_t rows = (size_t)sp::kAdjRowValues * li.count;
     const size_t cols = (size_t)std::max(nbonds, 1) * tiles;
-    const size_t pr = (size_t)sp::kPrSplit * li.rcount;
+    const size_t pr = (size_t)(sp::kPrSplit + 1) * li.rcount;
     return (rows + cols + pr) * sizeof(double);
 }
 
@@ -163,7 +170,8 @@ int launch_split_adjoint(dcs_sector *s, const SplitRows &c, const double *jxy, c
     double *rowpart = (double *)ws;
     double *colpart = rowpart + (size_t)kAdjRowValues * count;
     double *prp = colpart + (size_t)std::max(nbonds, 1) * ncoltiles;
-    const size_t need = (size_t)((prp + (size_t)kPrSplit * rcount) - rowpart) * sizeof(double);
+    double *pr = prp + (size_t)kPrSplit * rcount;
+    const size_t need = (size_t)((pr + rcount) - rowpart) * sizeof(double);
     if (need > ws_bytes) return DCS_EUNSUPPORTED;
     double *amp64 = c.d_diag + (count + rcount + 1) / 2 * 2;
     const void *amp = (const void *)(amp64 + kAmpEntries);  // the FP32 factors
@@ -227,7 +235,7 @@ int launch_split_adjoint(dcs_sector *s, const SplitRows &c, const double *jxy, c
         uint64_t max_cols = 0;
         for (int m = 0; m < li.m_count; ++m) max_cols = std::max<uint64_t>(max_cols, li.ncols[m]);
         const size_t lds = ((max_cols + 1) * sizeof(float) + 15) / 16 * 16;
-        auto kern = split_rows_lds_kernel<float, 1, true>;
+        auto kern = split_rows_lds_adj_kernel<float>;
         if (int r = ensure_lds(kern, lds)) return r;
         int per_cu = 1;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, lds_rows_threads<float, 1>(), lds) != hipSuccess ||
@@ -292,6 +300,8 @@ int launch_split_adjoint(dcs_sector *s, const SplitRows &c, const double *jxy, c
         P.rbase[li.m_count] = rcount;
         adj_colsum_kernel<0><<<dim3((rcount + 255) / 256, kPrSplit), 256, 0, stream>>>(P);
         if (int r = check_hip(hipGetLastError(), "split adjoint column sums launch")) return r;
+        adj_prsum_kernel<0><<<(rcount + 255) / 256, 256, 0, stream>>>(prp, pr, rcount);
+        if (int r = check_hip(hipGetLastError(), "split adjoint column sums launch")) return r;
     }
     // every output sum in a fixed order
     {
@@ -300,7 +310,7 @@ int launch_split_adjoint(dcs_sector *s, const SplitRows &c, const double *jxy, c
         P.tasks = c.d_adjtasks;
         P.rowpart = rowpart;
         P.colpart = colpart;
-        P.prp = prp;
+        P.pr = pr;
         P.lwords = (const uint32_t *)li.d_words;
         P.rwords = (const uint32_t *)li.d_rwords;
         P.gjxy = gjxy;

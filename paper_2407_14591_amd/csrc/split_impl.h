@@ -228,8 +228,8 @@ static_assert(sizeof(RowParams) <= 4096, "kernel arguments are limited to 4 KiB"
 
 // Values of one run's tile in the adjoint row pass: sum_s x_s g_t over the hops of
 // right-family bonds 0..31 and bonds across the cut 0..7, then sum_s x_s g_s, then
-// sum_s (2 b_j(s) - 1) x_s g_s for crossing right-site slots 0..7.
-constexpr int kAdjR = 32, kAdjX = 8, kAdjJ = 8;
+// sum_s (2 b_j(s) - 1) x_s g_s for crossing right-site slots 0..3.
+constexpr int kAdjR = 32, kAdjX = 8, kAdjJ = 4;
 constexpr int kAdjRowValues = kAdjR + kAdjX + 1 + kAdjJ;
 
 // Gathers in flight per batch, sized for about 96 registers of gathered data:
@@ -484,6 +484,33 @@ __device__ __forceinline__ uint32_t u16_of(const uint4 &v, uint32_t i) {  // i u
     return (i & 1u) ? (w >> 16) : (w & 0xFFFFu);
 }
 
+// Row sums of 16 FP32 values of every lane at once (as hx::row_transpose_sum, on
+// 32-bit moves): lane i of each 16-lane row ends with the row's total of v[i];
+// then the four rows are added.  Fixed order (deterministic).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int H, int CTRL>
+__device__ __forceinline__ void half_step_f(float (&v)[16], bool upper) {
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const float lo = v[k], hi = v[k + H];
+        v[k] = (upper ? hi : lo) + dpp_f<CTRL>(upper ? lo : hi);
+    }
+}
+__device__ __forceinline__ float wave_transpose_sum16f(float (&v)[16]) {
+    const int l = threadIdx.x & 15;
+    half_step_f<8, 0x140>(v, l & 8);  // row_mirror
+    half_step_f<4, 0x141>(v, l & 4);  // row_half_mirror
+    half_step_f<2, 0x1B>(v, l & 2);   // quad_perm [3,2,1,0]
+    half_step_f<1, 0xB1>(v, l & 1);   // quad_perm [1,0,3,2]
+    float s = v[0];
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    return s;
+}
+
 // Threads per workgroup of the staged-run pass: 512 for 4-byte rows (three runs
 // fit one CU's LDS), 1024 for 8-byte rows (one run per CU, shared by 16 waves).
 template <typename T, int K>
@@ -494,10 +521,8 @@ constexpr int lds_rows_threads() {
 // ADJ (k = 1): the product is y = H g (x is g); the pass also forms, per run, the
 // values of kAdjRowValues (hop sums of right-family and cross-cut bonds with the
 // primal vector at the row, and the diagonal sums) and writes them to P.part.
-template <typename T, int K, bool ADJ = false>
-__global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_kernel(const RowParams P_arg) {
-    (void)P_arg;
-    const RowParams &P = kernel_arg0<RowParams>();
+template <typename T, int K, bool ADJ>
+__device__ __forceinline__ void rows_lds_body(const RowParams &P) {
     using V = Acc<T, K>;
     constexpr uint32_t RB = K * sizeof(T);
     static_assert(RB <= 8, "staged runs hold rows of at most 8 bytes");
@@ -508,7 +533,7 @@ __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_ker
     V *xr = reinterpret_cast<V *>(dyn);
     __shared__ uint4 xinfo[XF];  // per bond across the cut: run base (lo, hi), bytes | bit << 31
     __shared__ uint32_t slots[2];
-    __shared__ double red[ADJ ? (NT / 64) * 64 : 1];  // ADJ: per-wave totals of the run's values
+    __shared__ double red[ADJ ? (NT / 64) * 64 : 1];  // ADJ: per-wave sums of the run's values
     static_assert(!ADJ || K == 1, "the adjoint row pass takes one column");
     const cptr<T> A = ro(reinterpret_cast<const T *>(P.amp));
     const cptr<T> ramp = A + kAmpRight, xamp = A + kAmpCross, xjz = A + kJzCross;
@@ -557,22 +582,22 @@ __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_ker
             }
         }
         ChunkIdx cur = load_chunk_idx(P, mi, threadIdx.x, ncols, nRq);
-        float jr[ADJ ? kAdjR : 1], jx[ADJ ? kAdjX : 1], cj[ADJ ? kAdjJ : 1], pl = 0.f;
-        if constexpr (ADJ) {
-#pragma unroll
-            for (int i = 0; i < kAdjR; ++i) jr[i] = 0.f;
-#pragma unroll
-            for (int i = 0; i < kAdjX; ++i) jx[i] = 0.f;
-#pragma unroll
-            for (int i = 0; i < kAdjJ; ++i) cj[i] = 0.f;
-        }
         const T *__restrict__ xp = reinterpret_cast<const T *>(P.xprim);
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        if constexpr (ADJ) red[wave * 64 + lane] = 0.0;  // this wave's slots (one writing lane each)
+        // ADJ: the pass's values of 16 at a time, summed over the wave (FP32) and added
+        // to the wave's FP64 slots (slot base + i written by lane i)
+        auto flush16 = [&](float (&v)[16], int base) {
+            const float tsum = wave_transpose_sum16f(v);
+            if (lane < 16) red[wave * 64 + base + lane] += (double)tsum;
+        };
         __syncthreads();
         for (uint32_t c0 = 0; c0 < ncols; c0 += NT) {
             const uint32_t r = c0 + threadIdx.x;
             const bool active = r < ncols;
-            ChunkIdx nxt = cur;
-            if (c0 + NT < ncols) nxt = load_chunk_idx(P, mi, r + NT, ncols, nRq);
+            ChunkIdx nxt = cur;  // the adjoint variant loads it at the end of the pass (registers)
+            if constexpr (!ADJ)
+                if (c0 + NT < ncols) nxt = load_chunk_idx(P, mi, r + NT, ncols, nRq);
             V acc;
 #pragma unroll
             for (int c = 0; c < K; ++c) acc.v[c] = (T)0;
@@ -580,15 +605,20 @@ __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_ker
             if constexpr (ADJ) xo_own = active ? (float)xp[R + r] : 0.f;
             // right family from the staged run
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t wv[4] = {cur.tv[i].x, cur.tv[i].y, cur.tv[i].z, cur.tv[i].w};
+            for (int i2 = 0; i2 < 2; ++i2) {
+                float pv[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const uint32_t e = (u & 1) ? (wv[u >> 1] >> 16) : (wv[u >> 1] & 0xFFFFu);
-                    const V gv = xr[e < ncols ? e : ncols];
-                    hx::fma_acc<T, K>(acc, ramp[i * 8 + u], gv);
-                    if constexpr (ADJ) jr[i * 8 + u] += xo_own * (float)gv.v[0];
+                for (int i = 2 * i2; i < 2 * i2 + 2; ++i) {
+                    const uint32_t wv[4] = {cur.tv[i].x, cur.tv[i].y, cur.tv[i].z, cur.tv[i].w};
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const uint32_t e = (u & 1) ? (wv[u >> 1] >> 16) : (wv[u >> 1] & 0xFFFFu);
+                        const V gv = xr[e < ncols ? e : ncols];
+                        hx::fma_acc<T, K>(acc, ramp[i * 8 + u], gv);
+                        if constexpr (ADJ) pv[(i - 2 * i2) * 8 + u] = xo_own * (float)gv.v[0];
+                    }
                 }
+                if constexpr (ADJ) flush16(pv, 16 * i2);
             }
             if (nRq > 4) {  // more than 32 right-family bonds
                 const uint32_t gr = P.rbase[mi] + (active ? r : 0u);
@@ -604,6 +634,9 @@ __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_ker
             }
             // bonds across the cut
             T diag = (T)(dl + cur.dr);
+            float px[16];  // ADJ: cross-cut hop sums, then the diagonal sums
+#pragma unroll
+            for (int q = 0; q < 16; ++q) px[q] = 0.f;
             if constexpr (ADJ) {  // at most kAdjX bonds, each with its own sum
 #pragma unroll
                 for (int q = 0; q < kAdjX; ++q) {
@@ -620,7 +653,7 @@ __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_ker
                         const V gv = buf_load<T, K>(rr, h && active ? xo * RB : kOob);
                         hx::fma_acc<T, K>(acc, xamp[q], gv);
                         diag += h ? -xjz[q] : xjz[q];
-                        jx[q] += xo_own * (float)gv.v[0];
+                        px[q] = xo_own * (float)gv.v[0];
                     }
                 }
             }
@@ -683,32 +716,17 @@ __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_ker
             }
             if constexpr (ADJ) {  // the diagonal sums: x_s g_s, and its signs by crossing right site
                 const float pg = xo_own * (float)xr[active ? r : ncols].v[0];
-                pl += pg;
+                px[kAdjX] = pg;
 #pragma unroll
                 for (int j = 0; j < kAdjJ; ++j)
-                    if (j < P.nJs) cj[j] += ((cur.rw >> P.jbit[j]) & 1u) ? pg : -pg;
+                    if (j < P.nJs) px[kAdjX + 1 + j] = ((cur.rw >> P.jbit[j]) & 1u) ? pg : -pg;
+                flush16(px, 32);
+                if (c0 + NT < ncols) nxt = load_chunk_idx(P, mi, r + NT, ncols, nRq);
             }
             cur = nxt;
         }
         if constexpr (ADJ) {
-            // the run's values: transposed wave sums (fixed order), then the waves in order
-            const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-            double v16[16];
-#pragma unroll
-            for (int grp = 0; grp < 4; ++grp) {
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int q = grp * 16 + i;  // value index
-                    float f = 0.f;
-                    if (q < kAdjR) f = jr[q];
-                    else if (q < kAdjR + kAdjX) f = jx[q - kAdjR];
-                    else if (q == kAdjR + kAdjX) f = pl;
-                    else if (q < kAdjRowValues) f = cj[q - kAdjR - kAdjX - 1];
-                    v16[i] = (double)f;
-                }
-                const double tsum = hx::wave_transpose_sum<16>(v16);
-                if (lane < 16) red[wave * 64 + grp * 16 + lane] = tsum;
-            }
+            // the run's values: the waves' slots added in wave order
             __syncthreads();
             if ((int)threadIdx.x < kAdjRowValues) {
                 double tot = 0.0;
@@ -718,6 +736,19 @@ __global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_ker
         }
         Q.finish();  // its barrier also ends the reads of the staged run (and of red)
     }
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__((lds_rows_threads<T, K>())) void split_rows_lds_kernel(const RowParams P_arg) {
+    (void)P_arg;
+    rows_lds_body<T, K, false>(kernel_arg0<RowParams>());
+}
+
+// The adjoint variant (k = 1).
+template <typename T>
+__global__ __launch_bounds__((lds_rows_threads<T, 1>())) void split_rows_lds_adj_kernel(const RowParams P_arg) {
+    (void)P_arg;
+    rows_lds_body<T, 1, true>(kernel_arg0<RowParams>());
 }
 
 // ------------------------------------------------------------------ block tiles
