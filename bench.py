@@ -151,7 +151,21 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
                               "compulsory_bytes": s.dim * 12,
                               "adjoint_compulsory_GBs": s.dim * 12 / per_a / 1e9,
                               "frac_of_peak": s.dim * 12 / per_a / 1e9 / PEAK_HBM_GBS}
-    del x, gv, s, t
+    del x, gv
+    torch.cuda.empty_cache()
+
+    # the batched FP32 form's adjoint on the same sector: a block of k=8 columns
+    xb = torch.randn((s.dim, 8), generator=g, device=dev, dtype=torch.float32)
+    gb = torch.randn((s.dim, 8), generator=g, device=dev, dtype=torch.float32)
+    per_f = timed(lambda: dq.hamiltonian_apply(s, t, jd, zd, xb), n=3, w=1)
+    per_a = timed(lambda: dq.hamiltonian_apply_adjoint(s, t, jd, zd, xb, gb), n=3, w=1)
+    out["adjoint_L32_f32k8"] = {"forward_ms": per_f * 1e3, "adjoint_ms": per_a * 1e3,
+                                "adjoint_over_forward": per_a / per_f,
+                                "adjoint_states_per_s": s.dim / per_a,
+                                "compulsory_bytes": s.dim * 8 * 12,
+                                "adjoint_compulsory_GBs": s.dim * 8 * 12 / per_a / 1e9,
+                                "frac_of_peak": s.dim * 8 * 12 / per_a / 1e9 / PEAK_HBM_GBS}
+    del xb, gb, s, t
     torch.cuda.empty_cache()
 
     # k=8 FP32 block on L=28, n=14 (40,116,600 rows), XXZ J = Delta = 1

@@ -227,11 +227,15 @@ int dcs_adjoint_workspace_size(const dcs_sector *sector, const dcs_terms *terms,
                                size_t *bytes);
 
 /*
- * Fused backward of y = H(theta) x for an upstream gradient g (k = 1):
- *   d_grad_x[s]     = (H g)_s                         (H^T = H)
- *   d_grad_jxy[b]   = sum_s g_s ((S+_i S-_j + S-_i S+_j)/2 x)_s
- *   d_grad_jz[b]    = sum_s g_s (Sz_i Sz_j x)_s
- *   d_grad_h[i]     = sum_s g_s (Sz_i x)_s            (skipped if d_grad_h == NULL)
+ * Fused backward of y = H(theta) X for an upstream gradient G, X and G of shape
+ * [D][k] row-major (k in {1, 2, 4, 8}, as dcs_hamiltonian_apply):
+ *   d_grad_x[s][c]  = (H G)_{s,c}                     (H^T = H)
+ *   d_grad_jxy[b]   = sum_{s,c} G_{s,c} ((S+_i S-_j + S-_i S+_j)/2 X)_{s,c}
+ *   d_grad_jz[b]    = sum_{s,c} G_{s,c} (Sz_i Sz_j X)_{s,c}
+ *   d_grad_h[i]     = sum_{s,c} G_{s,c} (Sz_i X)_{s,c}    (skipped if d_grad_h == NULL)
+ * For k > 1, d_grad_x is the block product H G (dcs_hamiltonian_apply, the same
+ * form) and the sums come from one pass over the rows that ranks every reached
+ * state and dots the k columns of X and G at every hop.  For k = 1:
  Three ways compute it: (0) one fused pass that ranks every reached state once and
  * uses it for both g and x; on a sector with a split view whose products run on
  * the split tables (the form the autotuner keeps for this terms object and dtype
@@ -247,11 +251,11 @@ int dcs_adjoint_workspace_size(const dcs_sector *sector, const dcs_terms *terms,
  * sums are reduced per workgroup or per tile into d_workspace and then in a
  * fixed order, so the result is deterministic.  The coupling gradients are
  * FP64 whatever dtype is.  d_grad_x may be NULL (only coupling gradients);
- * it must not overlap d_x or d_g.
+ * it must not overlap d_x or d_g (DCS_EINVAL).
  */
 int dcs_hamiltonian_apply_adjoint(const dcs_sector *sector, const dcs_terms *terms,
                                   const double *d_jxy, const double *d_jz, const double *d_h,
-                                  int dtype, const void *d_x, const void *d_g, void *d_grad_x,
+                                  int dtype, int k, const void *d_x, const void *d_g, void *d_grad_x,
                                   double *d_grad_jxy, double *d_grad_jz, double *d_grad_h,
                                   void *d_workspace, size_t workspace_bytes, void *stream);
 

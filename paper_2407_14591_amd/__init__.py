@@ -194,11 +194,11 @@ def hamiltonian_form(sector: Sector, terms: Terms, dtype=torch.float32, k: int =
 
 def hamiltonian_apply_adjoint(sector: Sector, terms: Terms, jxy, jz, x, g, h=None,
                               want_grad_x=True, want_grad_h=False):
-    """(H g, dL/dJxy, dL/dJz, dL/dh) for y = H x and dL/dy = g (dcs_hamiltonian_apply_adjoint)."""
+    """(H g, dL/dJxy, dL/dJz, dL/dh) for y = H x and dL/dy = g (dcs_hamiltonian_apply_adjoint);
+    x and g are [dim] or [dim, k] blocks (the sums run over the columns too)."""
     _couplings(sector, terms, jxy, jz, h)
     _check_dev(x, sector.device, "x", (torch.float32, torch.float64))
-    if _block_shape(sector, x) != 1 or x.dim() != 1:
-        raise ValueError(f"the adjoint takes one vector of {sector.dim} entries, not {tuple(x.shape)}")
+    k = _block_shape(sector, x)
     _check_dev(g, sector.device, "g", x.dtype, shape=x.shape)
     dev = x.device
     gx = torch.empty_like(x) if want_grad_x else None
@@ -209,7 +209,7 @@ def hamiltonian_apply_adjoint(sector: Sector, terms: Terms, jxy, jz, x, g, h=Non
     call("dcs_adjoint_workspace_size", sector._h, terms._h, C.byref(nbytes))
     ws = torch.empty(max(nbytes.value, 8), dtype=torch.uint8, device=dev)
     call("dcs_hamiltonian_apply_adjoint", sector._h, terms._h, _ptr(jxy), _ptr(jz), _ptr(h),
-         _dtype_code(x.dtype), _ptr(x), _ptr(g), _ptr(gx), _ptr(gj), _ptr(gz), _ptr(gh), _ptr(ws),
+         _dtype_code(x.dtype), k, _ptr(x), _ptr(g), _ptr(gx), _ptr(gj), _ptr(gz), _ptr(gh), _ptr(ws),
          nbytes.value, _stream(sector.device))
     return gx, gj, gz, gh
 
@@ -235,10 +235,11 @@ def hamiltonian_apply_adjoint_noalloc(sector: Sector, terms: Terms, jxy, jz, x, 
 
 
 class HApply(torch.autograd.Function):
-    """y = H(jxy, jz) x with the fused hand-written backward.
+    """y = H(jxy, jz) x with the fused hand-written backward; x is [dim] or a block [dim, k].
 
     backward: grad_x = H g (H is real symmetric), grad_jxy_b = g . (A_b x),
-    grad_jz_b = g . (Z_b x), all from one launch that ranks every reached state once.
+    grad_jz_b = g . (Z_b x) (dcs_hamiltonian_apply_adjoint: the sums formed inside the
+    product of g, or in a pass that ranks every reached state once).
     """
 
     @staticmethod

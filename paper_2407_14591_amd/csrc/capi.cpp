@@ -121,17 +121,24 @@ extern "C" int dcs_adjoint_workspace_size(const dcs_sector *s, const dcs_terms *
 
 extern "C" int dcs_hamiltonian_apply_adjoint(const dcs_sector *s, const dcs_terms *t,
                                              const double *jxy, const double *jz,
-                                             const double *h, int dtype, const void *x,
+                                             const double *h, int dtype, int k, const void *x,
                                              const void *g, void *gx, double *gjxy, double *gjz,
                                              double *gh, void *ws, size_t ws_bytes,
                                              void *stream) {
     clear_error();
     if (int r = check_apply_args(s, t, jxy, jz, dtype)) return r;
+    if (k != 1 && k != 2 && k != 4 && k != 8) return set_error(DCS_EINVAL, "k=%d not in {1,2,4,8}", k);
     if (!x || !g) return set_error(DCS_EINVAL, "NULL vector");
+    if (gx) {
+        const size_t bytes = (size_t)s->desc.dim * k * (dtype == DCS_F32 ? 4 : 8);
+        const char *a = (const char *)gx;
+        for (const char *b : {(const char *)x, (const char *)g})
+            if (a < b + bytes && b < a + bytes) return set_error(DCS_EINVAL, "grad_x overlaps x or g");
+    }
     if (t->num_bonds > 0 && (!gjxy || !gjz)) return set_error(DCS_EINVAL, "NULL coupling gradients");
     size_t need = adjoint_ws_bytes(s, t);
     if (!ws || ws_bytes < need)
         return set_error(DCS_EINVAL, "workspace of %zu bytes < %zu needed", ws_bytes, need);
-    return launch_adjoint(s, t, jxy, jz, h, dtype, x, g, gx, gjxy, gjz, gh, ws, ws_bytes,
+    return launch_adjoint(s, t, jxy, jz, h, dtype, k, x, g, gx, gjxy, gjz, gh, ws, ws_bytes,
                           (hipStream_t)stream);
 }

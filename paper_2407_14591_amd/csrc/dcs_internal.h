@@ -302,7 +302,7 @@ int launch_adjoint_single(const dcs_sector *s, const dcs_terms *t, const double 
                           const void *g, void *gx, double *gjxy, double *gjz, double *gh,
                           void *ws, hipStream_t stream);
 int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
-                   const double *h, int dtype, const void *x, const void *g, void *gx,
+                   const double *h, int dtype, int k, const void *x, const void *g, void *gx,
                    double *gjxy, double *gjz, double *gh, void *ws, size_t ws_bytes,
                    hipStream_t stream);
 

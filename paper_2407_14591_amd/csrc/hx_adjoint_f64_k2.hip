@@ -1,0 +1,15 @@
+// Instantiations of the adjoint sums launcher for blocks of 2 double columns.
+#include "hx_impl.h"
+
+namespace dcs {
+namespace hx {
+template int launch_adj_t<uint32_t, double, 4, 2>(const dcs_sector *, HxParams &, double *, double *,
+                                                  double *, hipStream_t);
+template int launch_adj_t<uint32_t, double, 8, 2>(const dcs_sector *, HxParams &, double *, double *,
+                                                  double *, hipStream_t);
+template int launch_adj_t<uint64_t, double, 4, 2>(const dcs_sector *, HxParams &, double *, double *,
+                                                  double *, hipStream_t);
+template int launch_adj_t<uint64_t, double, 8, 2>(const dcs_sector *, HxParams &, double *, double *,
+                                                  double *, hipStream_t);
+}  // namespace hx
+}  // namespace dcs

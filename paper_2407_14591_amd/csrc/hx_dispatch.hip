@@ -48,6 +48,21 @@ DCS_ADJ_EXTERN(uint32_t, double, 4)
 DCS_ADJ_EXTERN(uint32_t, double, 8)
 DCS_ADJ_EXTERN(uint64_t, double, 4)
 DCS_ADJ_EXTERN(uint64_t, double, 8)
+#define DCS_ADJK_EXTERN(T, KC)                                                                        \
+    extern template int launch_adj_t<uint32_t, T, 4, KC>(const dcs_sector *, HxParams &, double *,   \
+                                                         double *, double *, hipStream_t);           \
+    extern template int launch_adj_t<uint32_t, T, 8, KC>(const dcs_sector *, HxParams &, double *,   \
+                                                         double *, double *, hipStream_t);           \
+    extern template int launch_adj_t<uint64_t, T, 4, KC>(const dcs_sector *, HxParams &, double *,   \
+                                                         double *, double *, hipStream_t);           \
+    extern template int launch_adj_t<uint64_t, T, 8, KC>(const dcs_sector *, HxParams &, double *,   \
+                                                         double *, double *, hipStream_t);
+DCS_ADJK_EXTERN(float, 2)
+DCS_ADJK_EXTERN(float, 4)
+DCS_ADJK_EXTERN(float, 8)
+DCS_ADJK_EXTERN(double, 2)
+DCS_ADJK_EXTERN(double, 4)
+DCS_ADJK_EXTERN(double, 8)
 
 namespace {
 
@@ -300,6 +315,43 @@ int adjoint_pass(const dcs_sector *s, const dcs_terms *t, const double *jxy, con
                      : launch_adj_t<uint32_t, double, 8>(s, P, gjxy, gjz, gh, stream);
 }
 
+template <int KC>
+int adjoint_block_pass_k(const dcs_sector *s, HxParams &P, int dtype, int nmax, double *gjxy, double *gjz,
+                         double *gh, hipStream_t stream) {
+    if (s->wide) {
+        if (dtype == DCS_F32)
+            return nmax == 4 ? launch_adj_t<uint64_t, float, 4, KC>(s, P, gjxy, gjz, gh, stream)
+                             : launch_adj_t<uint64_t, float, 8, KC>(s, P, gjxy, gjz, gh, stream);
+        return nmax == 4 ? launch_adj_t<uint64_t, double, 4, KC>(s, P, gjxy, gjz, gh, stream)
+                         : launch_adj_t<uint64_t, double, 8, KC>(s, P, gjxy, gjz, gh, stream);
+    }
+    if (dtype == DCS_F32)
+        return nmax == 4 ? launch_adj_t<uint32_t, float, 4, KC>(s, P, gjxy, gjz, gh, stream)
+                         : launch_adj_t<uint32_t, float, 8, KC>(s, P, gjxy, gjz, gh, stream);
+    return nmax == 4 ? launch_adj_t<uint32_t, double, 4, KC>(s, P, gjxy, gjz, gh, stream)
+                     : launch_adj_t<uint32_t, double, 8, KC>(s, P, gjxy, gjz, gh, stream);
+}
+
+// The sums of a block of k columns in one pass (decode and rank per row, the k
+// columns of x and g dotted at every hop); grad_x is not formed here.
+int adjoint_block_pass(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
+                       const double *h, int dtype, int k, const void *x, const void *g, double *gjxy,
+                       double *gjz, double *gh, void *ws, hipStream_t stream) {
+    const int nmax = pick_nmax(s);
+    HxParams P;
+    if (int r = fill_params(s, t, nmax, jxy, jz, h, P)) return r;
+    P.x = x;
+    P.g = g;
+    P.gx = nullptr;
+    P.far_below = s->desc.dim >= (1ull << 22) ? s->desc.N / 2 : 0;
+    P.partials = (double *)ws;
+    switch (k) {
+        case 2: return adjoint_block_pass_k<2>(s, P, dtype, nmax, gjxy, gjz, gh, stream);
+        case 4: return adjoint_block_pass_k<4>(s, P, dtype, nmax, gjxy, gjz, gh, stream);
+        default: return adjoint_block_pass_k<8>(s, P, dtype, nmax, gjxy, gjz, gh, stream);
+    }
+}
+
 // Milliseconds of one run of fn on the stream (HIP events, synchronising); -1 on error.
 template <typename F>
 float time_on_stream(F &&fn, hipStream_t stream) {
@@ -330,10 +382,15 @@ int launch_adjoint_single(const dcs_sector *s, const dcs_terms *t, const double 
 }
 
 int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
-                   const double *h, int dtype, const void *x, const void *g, void *gx,
+                   const double *h, int dtype, int k, const void *x, const void *g, void *gx,
                    double *gjxy, double *gjz, double *gh, void *ws, size_t ws_bytes,
                    hipStream_t stream) {
     DeviceGuard dg(s->device);
+    if (k > 1) {  // a block: grad_x = H G by the block product, the sums in one pass over the rows
+        if (gx)
+            if (int r = launch_hx(s, t, jxy, jz, h, dtype, k, g, gx, stream)) return r;
+        return adjoint_block_pass(s, t, jxy, jz, h, dtype, k, x, g, gjxy, gjz, gh, ws, stream);
+    }
     auto fused = [&]() {
         return adjoint_pass(s, t, jxy, jz, h, dtype, x, g, gx, gjxy, gjz, gh, ws, stream);
     };

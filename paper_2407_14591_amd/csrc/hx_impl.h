@@ -467,12 +467,23 @@ constexpr int adj_batch() {
     return 2;
 }
 
-template <typename IdxT, typename T, int NMAX, int R>
+// KC columns (a block [D][KC] of x and g): the sums run over the columns too.
+template <typename IdxT, typename T, int NMAX, int R, int KC = 1>
 struct AdjRows {
     RowState<IdxT, NMAX> r[R];
     IdxT row[R];
-    T xr[R], grow[R], hg[R], diag[R];
+    Acc<T, KC> xr[R], grow[R];
+    T hg[R], diag[R];
 };
+
+// sum_c a_c b_c in FP64, columns in order.
+template <typename T, int KC>
+__device__ __forceinline__ double dotd(const Acc<T, KC> &a, const Acc<T, KC> &b) {
+    double s = (double)a.v[0] * (double)b.v[0];
+#pragma unroll
+    for (int c = 1; c < KC; ++c) s += (double)a.v[c] * (double)b.v[c];
+    return s;
+}
 
 // Row sums of N = 8 or 16 values at once.  Each step pairs every lane with a
 // lane of the same 16-lane row that holds the same subset of the values (row
@@ -535,13 +546,13 @@ __device__ __forceinline__ void lds_add(double *p, double v) {
 // the bonds go in batches of adj_batch() (two): every column of the batch, the
 // gathers of g and x, then the batch's bond sums (two per bond) in one
 // transposed row sum.
-template <typename IdxT, typename T, int NMAX, bool Q2, bool GX, int A, int B, int R>
+template <typename IdxT, typename T, int NMAX, bool Q2, bool GX, int A, int B, int R, int KC>
 __device__ __forceinline__ void adjoint_class(const HxParams &P, const SectorDesc &sd,
                                               const Tables<IdxT> &Tb,
                                               const T *__restrict__ x, const T *__restrict__ g,
                                               const T *bamp, const T *bjz, const T *ladder,
                                               const int *borig, double *wacc,
-                                              AdjRows<IdxT, T, NMAX, R> &W) {
+                                              AdjRows<IdxT, T, NMAX, R, KC> &W) {
     const int cls = A * NMAX - A * (A - 1) / 2 + (B - A);
     const int beg = P.cls_beg[cls], end = P.cls_beg[cls + 1];
     const int lane = threadIdx.x & 63;
@@ -567,27 +578,28 @@ __device__ __forceinline__ void adjoint_class(const HxParams &P, const SectorDes
                         amp[v] = (T)0;
                     }
                 }
-                T gv[NB], xv[NB];
+                T gv[NB];
+                Acc<T, KC> xv[NB];
                 if (A < P.far_below) {  // far targets: streamed past the caches, as in the forward pass
 #pragma unroll
                     for (int v = 0; v < NB; ++v) {
                         if constexpr (GX) gv[v] = __builtin_nontemporal_load(g + c[v]);
-                        xv[v] = __builtin_nontemporal_load(x + c[v]);
+                        xv[v] = gather_nt<T, KC>(x, c[v]);
                     }
                 } else {
 #pragma unroll
                     for (int v = 0; v < NB; ++v) {
                         if constexpr (GX) gv[v] = g[c[v]];
-                        xv[v] = x[c[v]];
+                        xv[v] = gather<T, KC>(x, c[v]);
                     }
                 }
-                const double p = (double)W.grow[u] * (double)W.xr[u];
+                const double p = dotd<T, KC>(W.grow[u], W.xr[u]);
 #pragma unroll
                 for (int v = 0; v < NB; ++v) {
                     const bool hop = c[v] != W.row[u];
                     if constexpr (GX) W.hg[u] += amp[v] * gv[v];
                     if (t + v < end) {
-                        val[2 * v] += hop ? (double)W.grow[u] * (double)((T)0.5 * xv[v]) : 0.0;
+                        val[2 * v] += hop ? 0.5 * dotd<T, KC>(W.grow[u], xv[v]) : 0.0;
                         val[2 * v + 1] += hop ? -0.25 * p : 0.25 * p;
                     }
                 }
@@ -612,7 +624,9 @@ __device__ __forceinline__ void adjoint_class(const HxParams &P, const SectorDes
                 const int di = (int)((r.w[A] >> pil) & dm), dj = (int)((r.w[B] >> pjl) & dm);
                 const T *up = ladder, *dn = ladder + 16, *mz = ladder + 32;
                 const T zz = mz[di] * mz[dj];
-                T hop_x = (T)0;  // sum over hops of (ladder factors / 2) * x[col]
+                Acc<T, KC> hop_x;  // sum over hops of (ladder factors / 2) * x[col]
+#pragma unroll
+                for (int cc = 0; cc < KC; ++cc) hop_x.v[cc] = (T)0;
                 if (di < Qm1 && dj > 0) {
                     const uint32_t wa = r.w[A] + (1u << pil);
                     IdxT col;
@@ -622,7 +636,11 @@ __device__ __forceinline__ void adjoint_class(const HxParams &P, const SectorDes
                         col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa, r.w[B] - (1u << pjl), 1);
                     const T f = (T)0.5 * up[di] * dn[dj];
                     if constexpr (GX) W.hg[u] += (T)2 * bamp[t] * f * g[col];
-                    hop_x += f * x[col];
+                    {
+                        const Acc<T, KC> xc = gather<T, KC>(x, col);
+#pragma unroll
+                        for (int cc = 0; cc < KC; ++cc) hop_x.v[cc] += f * xc.v[cc];
+                    }
                 }
                 if (di > 0 && dj < Qm1) {
                     const uint32_t wa = r.w[A] - (1u << pil);
@@ -633,11 +651,15 @@ __device__ __forceinline__ void adjoint_class(const HxParams &P, const SectorDes
                         col = hop_col<IdxT, NMAX, A, B>(sd, Tb, r, row, wa, r.w[B] + (1u << pjl), -1);
                     const T f = (T)0.5 * dn[di] * up[dj];
                     if constexpr (GX) W.hg[u] += (T)2 * bamp[t] * f * g[col];
-                    hop_x += f * x[col];
+                    {
+                        const Acc<T, KC> xc = gather<T, KC>(x, col);
+#pragma unroll
+                        for (int cc = 0; cc < KC; ++cc) hop_x.v[cc] += f * xc.v[cc];
+                    }
                 }
                 W.diag[u] += bjz[t] * zz;
-                sxy += (double)W.grow[u] * (double)hop_x;
-                sz += (double)W.grow[u] * (double)zz * (double)W.xr[u];
+                sxy += dotd<T, KC>(W.grow[u], hop_x);
+                sz += (double)zz * dotd<T, KC>(W.grow[u], W.xr[u]);
             }
             const double vxy = wave_sum(sxy);
             const double vz = wave_sum(sz);
@@ -650,23 +672,23 @@ __device__ __forceinline__ void adjoint_class(const HxParams &P, const SectorDes
     }
 }
 
-template <typename IdxT, typename T, int NMAX, bool Q2, bool GX, int A, int B, int R>
+template <typename IdxT, typename T, int NMAX, bool Q2, bool GX, int A, int B, int R, int KC>
 struct AdjLoop {
     __device__ __forceinline__ static void run(const HxParams &P, const SectorDesc &sd,
                                                const Tables<IdxT> &Tb,
                                                const T *__restrict__ x, const T *__restrict__ g,
                                                const T *bamp, const T *bjz, const T *ladder,
                                                const int *borig, double *wacc,
-                                               AdjRows<IdxT, T, NMAX, R> &W) {
+                                               AdjRows<IdxT, T, NMAX, R, KC> &W) {
         if constexpr (A < NMAX) {
             if constexpr (B < NMAX) {
                 if (B < sd.N)
-                    adjoint_class<IdxT, T, NMAX, Q2, GX, A, B, R>(P, sd, Tb, x, g, bamp, bjz, ladder,
+                    adjoint_class<IdxT, T, NMAX, Q2, GX, A, B, R, KC>(P, sd, Tb, x, g, bamp, bjz, ladder,
                                                               borig, wacc, W);
-                AdjLoop<IdxT, T, NMAX, Q2, GX, A, B + 1, R>::run(P, sd, Tb, x, g, bamp, bjz, ladder,
+                AdjLoop<IdxT, T, NMAX, Q2, GX, A, B + 1, R, KC>::run(P, sd, Tb, x, g, bamp, bjz, ladder,
                                                              borig, wacc, W);
             } else {
-                AdjLoop<IdxT, T, NMAX, Q2, GX, A + 1, A + 1, R>::run(P, sd, Tb, x, g, bamp, bjz,
+                AdjLoop<IdxT, T, NMAX, Q2, GX, A + 1, A + 1, R, KC>::run(P, sd, Tb, x, g, bamp, bjz,
                                                                  ladder, borig, wacc, W);
             }
         }
@@ -677,8 +699,9 @@ struct AdjLoop {
 // workgroup adds the slices in wave order and writes one partial row.  A tile is
 // kHxThreads * R rows; wave w takes R consecutive 64-row pieces of it.  GX: the
 // kernel also computes grad_x = H g (else only the sums: no gathers of g).
-template <typename IdxT, typename T, int NMAX, bool Q2, bool GX>
+template <typename IdxT, typename T, int NMAX, bool Q2, bool GX, int KC = 1>
 __device__ __forceinline__ void adjoint_body(const HxParams &P, char *lds) {
+    static_assert(!GX || KC == 1, "grad_x of a block comes from the block product");
     constexpr int R = adj_rows<IdxT, NMAX>();
     const SectorDesc &sd = P.sd;
     stage_blob(lds, P.blob, sd.lay_bytes);
@@ -703,7 +726,7 @@ __device__ __forceinline__ void adjoint_body(const HxParams &P, char *lds) {
     auto tile_rows = [&](uint64_t tile) {
         const uint64_t base = tile * ((uint64_t)kHxThreads * R) + (uint64_t)wave * (64 * R);
         if (base >= sd.dim) return;
-        AdjRows<IdxT, T, NMAX, R> W;
+        AdjRows<IdxT, T, NMAX, R, KC> W;
 #pragma unroll
         for (int u = 0; u < R; ++u) {
             const uint64_t row64 = base + 64 * u + lane;
@@ -711,12 +734,16 @@ __device__ __forceinline__ void adjoint_body(const HxParams &P, char *lds) {
             // a lane past the end decodes a valid row and adds nothing (g = 0)
             W.row[u] = (IdxT)(active ? row64 : base);
             decode_row<IdxT, NMAX>(sd, Tb, W.row[u], W.r[u]);
-            W.xr[u] = x[W.row[u]];
-            W.grow[u] = active ? g[W.row[u]] : (T)0;
+            W.xr[u] = gather<T, KC>(x, W.row[u]);
+            W.grow[u] = gather<T, KC>(g, W.row[u]);
+            if (!active) {
+#pragma unroll
+                for (int cc = 0; cc < KC; ++cc) W.grow[u].v[cc] = (T)0;
+            }
             W.hg[u] = (T)0;
             W.diag[u] = (T)0;
         }
-        AdjLoop<IdxT, T, NMAX, Q2, GX, 0, 0, R>::run(P, sd, Tb, x, g, bamp, bjz, ladder, borig, wacc,
+        AdjLoop<IdxT, T, NMAX, Q2, GX, 0, 0, R, KC>::run(P, sd, Tb, x, g, bamp, bjz, ladder, borig, wacc,
                                                      W);
         const uint32_t dm = (1u << sd.nb) - 1u;
         if (P.h || P.want_fields) {
@@ -733,7 +760,7 @@ __device__ __forceinline__ void adjoint_body(const HxParams &P, char *lds) {
                         for (int u = 0; u < R; ++u) {
                             const T mzi = ladder[32 + (int)((W.r[u].s >> sh) & dm)];
                             if (P.h) W.diag[u] += hf[i] * mzi;
-                            val[k] += (double)W.grow[u] * (double)mzi * (double)W.xr[u];
+                            val[k] += (double)mzi * dotd<T, KC>(W.grow[u], W.xr[u]);
                         }
                     }
                 }
@@ -749,7 +776,7 @@ __device__ __forceinline__ void adjoint_body(const HxParams &P, char *lds) {
         if constexpr (GX) {
 #pragma unroll
             for (int u = 0; u < R; ++u)
-                if (base + 64 * u + lane < sd.dim) gx[W.row[u]] = W.hg[u] + W.diag[u] * W.grow[u];
+                if (base + 64 * u + lane < sd.dim) gx[W.row[u]] = W.hg[u] + W.diag[u] * W.grow[u].v[0];
         }
     };
     // a static tile order: which workgroup adds which rows must not depend on timing,
@@ -777,11 +804,11 @@ adjoint_kernel(const HxParams P_arg) {
 }
 
 // The sums only (grad_x comes from the split product).
-template <typename IdxT, typename T, int NMAX, bool Q2>
+template <typename IdxT, typename T, int NMAX, bool Q2, int KC = 1>
 __global__ __launch_bounds__(kHxThreads) void adjoint_sums_kernel(const HxParams P_arg) {
     (void)P_arg;
     extern __shared__ __align__(16) char lds[];
-    adjoint_body<IdxT, T, NMAX, Q2, false>(kernel_arg0<HxParams>(), lds);
+    adjoint_body<IdxT, T, NMAX, Q2, false, KC>(kernel_arg0<HxParams>(), lds);
 }
 
 // Deterministic second stage: one workgroup of kAdjReduceThreads per sum; each
@@ -901,7 +928,9 @@ inline size_t adj_lds_bytes(const dcs_sector *s, int nbonds, size_t coeff_bytes)
            (size_t)kMaxBonds * sizeof(int);
 }
 
-template <typename IdxT, typename T, int NMAX>
+// KC > 1: the sums of a block of KC columns (P.gx must be NULL: grad_x of a block
+// comes from the block product).
+template <typename IdxT, typename T, int NMAX, int KC = 1>
 int launch_adj_t(const dcs_sector *s, HxParams &P, double *gjxy, double *gjz, double *gh,
                         hipStream_t stream) {
     const int nacc = 2 * P.nbonds + s->desc.L;
@@ -911,10 +940,17 @@ int launch_adj_t(const dcs_sector *s, HxParams &P, double *gjxy, double *gjz, do
     P.tiles = g.tiles;
     P.xcd_groups = g.xcd_groups;
     P.want_fields = gh != nullptr;
-    auto kern = s->desc.Q == 2 ? (P.gx ? adjoint_kernel<IdxT, T, NMAX, true>
-                                       : adjoint_sums_kernel<IdxT, T, NMAX, true>)
-                               : (P.gx ? adjoint_kernel<IdxT, T, NMAX, false>
-                                       : adjoint_sums_kernel<IdxT, T, NMAX, false>);
+    void (*kern)(const HxParams);
+    if constexpr (KC == 1) {
+        kern = s->desc.Q == 2 ? (P.gx ? adjoint_kernel<IdxT, T, NMAX, true>
+                                      : adjoint_sums_kernel<IdxT, T, NMAX, true>)
+                              : (P.gx ? adjoint_kernel<IdxT, T, NMAX, false>
+                                      : adjoint_sums_kernel<IdxT, T, NMAX, false>);
+    } else {
+        if (P.gx) return set_error(DCS_EINVAL, "internal: block adjoint with grad_x in the sums pass");
+        kern = s->desc.Q == 2 ? adjoint_sums_kernel<IdxT, T, NMAX, true, KC>
+                              : adjoint_sums_kernel<IdxT, T, NMAX, false, KC>;
+    }
     if (int r = ensure_lds(kern, lds)) return r;
     kern<<<g.wgs, kHxThreads, lds, stream>>>(P);
     if (int r = check_hip(hipGetLastError(), "adjoint kernel launch")) return r;

@@ -51,24 +51,23 @@ def test_apply_rejects_bad_shapes(small):
         dq.hamiltonian_apply(s, t, j[:-1].contiguous(), z, ok)
 
 
-def test_adjoint_rejects_blocks_and_bad_sizes(small):
+def test_adjoint_rejects_bad_sizes(small):
     s, t, j, z = small
     D = s.dim
     x = torch.zeros(D, dtype=torch.float64, device=DEV)
-    with pytest.raises(ValueError):
+    with pytest.raises(ValueError):  # block and vector mixed
         dq.hamiltonian_apply_adjoint(s, t, j, z, torch.zeros(D, 2, dtype=torch.float64, device=DEV),
-                                     torch.zeros(D, 2, dtype=torch.float64, device=DEV))
+                                     torch.zeros(D, dtype=torch.float64, device=DEV))
+    with pytest.raises(ValueError):  # 3 columns
+        dq.hamiltonian_apply_adjoint(s, t, j, z, torch.zeros(D, 3, dtype=torch.float64, device=DEV),
+                                     torch.zeros(D, 3, dtype=torch.float64, device=DEV))
     with pytest.raises(ValueError):
         dq.hamiltonian_apply_adjoint(s, t, j, z, x, torch.zeros(D - 1, dtype=torch.float64, device=DEV))
     with pytest.raises(ValueError):
         dq.hamiltonian_apply_adjoint(s, t, j, z, x[:-1].contiguous(), x[:-1].contiguous())
     with pytest.raises(TypeError):
         dq.hamiltonian_apply_adjoint(s, t, j, z, x, x.float())
-    # autograd through a k-block: the backward raises rather than returning wrong gradients
-    xb = torch.zeros(D, 2, dtype=torch.float64, device=DEV, requires_grad=True)
-    y = dq.HApply.apply(xb, j, z, s, t)
-    with pytest.raises(ValueError):
-        y.sum().backward()
+
 
 
 def test_index_and_lanczos_reject_bad_sizes(small):
