@@ -18,6 +18,8 @@ Contents
                   Q^L matrices (eq. H_30, App. D)
   lanczos.py      FP64 Lanczos with full re-orthogonalisation (Sec. 2.1 names it)
   gradients.py    adjoint of y = H(theta) x and the Hellmann-Feynman gradient
+  observables.py  lowest few Ritz pairs and expectation values of the terms of H
+                  (App. D)
   native.py       ctypes loader of c/dcs_oracle.c (same definitions in plain C,
                   FP64, OpenMP) for sectors too large for Python
 

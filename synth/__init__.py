@@ -56,6 +56,14 @@ def xxz_chain(L: int, J: float = 1.0, delta: float = 1.0, periodic: bool = True)
     return bonds, jxy, jxy * delta
 
 
+def tilted_field_chain(L: int, jz: float = 1.0):
+    """Open chain with Jxy = 1, Jz = jz on bonds (k, k+1), k < L-1, and the
+    site-dependent field h_k = k on every site k (App. D's example model)."""
+    bonds = chain_bonds(L, 1, periodic=False)
+    jxy = np.ones(len(bonds), dtype=np.float64)
+    return bonds, jxy, jxy * jz, np.arange(L, dtype=np.float64)
+
+
 def random_couplings(num_bonds: int, seed: int = SEED_COUPLINGS,
                      j_range=(0.5, 1.5), delta_range=(0.0, 2.0)):
     """Per-bond J_b ~ U(j_range) and Delta_b ~ U(delta_range), drawn J first then Delta."""
