@@ -279,6 +279,26 @@ int dcs_hamiltonian_apply_adjoint_noalloc(const dcs_sector *sector, const dcs_te
                                           const void *d_g, void *d_grad_x, double *d_grad_jxy,
                                           double *d_grad_jz, double *d_grad_h, void *stream);
 
+/*
+ * Expectation values of the terms of H (App. D's observables) in num real
+ * states psi_e (device, vec_dtype, D elements each, state e at d_psi + e*D):
+ *   d_exy[e*B + b] = psi_e^T ((S+_i S-_j + S-_i S+_j)/2) psi_e
+ *   d_ez [e*B + b] = psi_e^T (Sz_i Sz_j) psi_e                (bond b = (i, j), B bonds)
+ *   d_esz[e*L + i] = psi_e^T Sz_i psi_e                        (skipped if NULL)
+ * (device FP64 outputs).  The states are not normalised by the call: for a
+ * state of norm r the values are r^2 times the expectation.  <H> for couplings
+ * theta is sum_b (jxy_b exy_b + jz_b ez_b) + sum_i h_i esz_i.  Each value is
+ * the adjoint's coupling sum for that term with g = x = psi_e (the sums-only
+ * fused pass, one launch per state, deterministic).  d_workspace: at least
+ * dcs_expectation_workspace_size bytes.
+ */
+int dcs_expectation_workspace_size(const dcs_sector *sector, const dcs_terms *terms,
+                                   size_t *bytes);
+int dcs_expectation_values(const dcs_sector *sector, const dcs_terms *terms, int vec_dtype,
+                           int num, const void *d_psi, double *d_exy, double *d_ez,
+                           double *d_esz, void *d_workspace, size_t workspace_bytes,
+                           void *stream);
+
 /* ========================================================================== */
 /* Batched: many sectors in one launch                                        */
 /* ========================================================================== */
@@ -316,7 +336,7 @@ int dcs_plan_apply(const dcs_plan *plan, int dtype, const void *const *d_x, void
  * Device workspace bytes for dcs_lanczos with these arguments.
  */
 int dcs_lanczos_workspace_size(const dcs_sector *sector, int vec_dtype, int steps, int reorth,
-                               int want_vector, size_t *bytes);
+                               int num_vec, size_t *bytes);
 
 /*
  * Lanczos on the sector with FP64 scalars and vectors of vec_dtype:
@@ -344,15 +364,21 @@ int dcs_lanczos_workspace_size(const dcs_sector *sector, int vec_dtype, int step
  * d_v0: start vector (D elements, vec_dtype, device; not modified).
  * h_alpha[steps], h_beta[steps]: host outputs (beta has steps_done-1 valid entries).
  * h_steps_done: host output.  h_eig[num_eig]: the num_eig lowest Ritz values.
- * d_ground_vec: if not NULL, receives the normalised Ritz vector of the lowest
- * Ritz value (vec_dtype, D elements); it is assembled from the stored basis
- * (DCS_REORTH_FULL) or by repeating the recurrence (other modes).
+ * d_vecs: if not NULL, receives the normalised Ritz vectors of the num_vec
+ * (>= 1) lowest Ritz values, vector e at d_vecs + e*D (vec_dtype; the lowest
+ * num_vec states that App. D asks for).  Each is sum_j s_j v_j with s the
+ * eigenvector of T for that Ritz value (inverse iteration in FP64 on the
+ * device), assembled from the stored basis (DCS_REORTH_FULL) or by repeating
+ * the recurrence once for all of them (other modes).  Only the first
+ * min(num_vec, steps_done) are written.  Excited Ritz vectors converge later
+ * than the ground vector; the caller picks `steps` for the states it wants.
+ * num_vec must match the value given to dcs_lanczos_workspace_size.
  * Synchronises `stream` before returning (the outputs are on the host).
  */
 int dcs_lanczos(const dcs_sector *sector, const dcs_terms *terms, const double *d_jxy,
                 const double *d_jz, const double *d_h, int vec_dtype, int steps, int reorth,
                 const void *d_v0, double *h_alpha, double *h_beta, int *h_steps_done,
-                int num_eig, double *h_eig, void *d_ground_vec, void *d_workspace,
+                int num_eig, double *h_eig, void *d_vecs, int num_vec, void *d_workspace,
                 size_t workspace_bytes, void *stream);
 
 /*

@@ -260,40 +260,70 @@ class HApply(torch.autograd.Function):
 
 
 def lanczos(sector: Sector, terms: Terms, jxy, jz, v0, steps: int, reorth="auto",
-            num_eig: int = 1, want_vector=False, h=None, hbm_fraction: float = 0.5):
+            num_eig: int = 1, want_vector=False, h=None, hbm_fraction: float = 0.5,
+            num_vec: int = 0):
     """Lanczos with FP64 scalars (dcs_lanczos).  Returns a dict with alpha, beta,
-    steps_done, eig (lowest num_eig Ritz values), reorth mode and the ground vector."""
+    steps_done, eig (lowest num_eig Ritz values), reorth mode, "vector" (the ground
+    Ritz vector) and "vectors" ([num_vec, D], the Ritz vectors of the num_vec lowest
+    Ritz values; want_vector=True alone asks for one)."""
     _couplings(sector, terms, jxy, jz, h)
     _check_dev(v0, sector.device, "v0", (torch.float32, torch.float64), shape=(sector.dim,))
     if steps < 1:
         raise ValueError("steps must be >= 1")
+    if num_vec < 0:
+        raise ValueError("num_vec must be >= 0")
+    nvec = max(num_vec, 1 if want_vector else 0)
     dtype = _dtype_code(v0.dtype)
     modes = {"none": DCS_REORTH_NONE, "local": DCS_REORTH_LOCAL, "full": DCS_REORTH_FULL}
     if reorth == "auto":
         # full re-orthogonalisation when the stored basis fits in the given share of free HBM
         free, _ = torch.cuda.mem_get_info(sector.device)
         need = C.c_size_t()
-        call("dcs_lanczos_workspace_size", sector._h, dtype, steps, DCS_REORTH_FULL,
-             int(want_vector), C.byref(need))
+        call("dcs_lanczos_workspace_size", sector._h, dtype, steps, DCS_REORTH_FULL, nvec,
+             C.byref(need))
         reorth = "full" if need.value <= hbm_fraction * free else "local"
     mode = modes[reorth]
     nbytes = C.c_size_t()
-    call("dcs_lanczos_workspace_size", sector._h, dtype, steps, mode, int(want_vector),
-         C.byref(nbytes))
+    call("dcs_lanczos_workspace_size", sector._h, dtype, steps, mode, nvec, C.byref(nbytes))
     ws = torch.empty(nbytes.value, dtype=torch.uint8, device=v0.device)
     alpha = (C.c_double * steps)()
     beta = (C.c_double * steps)()
     done = C.c_int()
     ne = max(1, num_eig)
     eig = (C.c_double * ne)()
-    psi = torch.empty_like(v0) if want_vector else None
+    psi = torch.zeros((nvec, sector.dim), dtype=v0.dtype, device=v0.device) if nvec else None
     call("dcs_lanczos", sector._h, terms._h, _ptr(jxy), _ptr(jz), _ptr(h), dtype, steps, mode,
-         _ptr(v0), alpha, beta, C.byref(done), ne, eig, _ptr(psi), _ptr(ws), nbytes.value,
+         _ptr(v0), alpha, beta, C.byref(done), ne, eig, _ptr(psi), nvec, _ptr(ws), nbytes.value,
          _stream(sector.device))
     m = done.value
+    if psi is not None and m < nvec:
+        psi = psi[:m]  # at most steps_done Ritz vectors exist
     return {"alpha": [alpha[i] for i in range(m)], "beta": [beta[i] for i in range(max(m - 1, 0))],
             "steps_done": m, "eig": [eig[i] for i in range(min(ne, m))], "reorth": reorth,
-            "vector": psi}
+            "vector": psi[0] if psi is not None else None, "vectors": psi}
+
+
+def expectation_values(sector: Sector, terms: Terms, psi, fields: bool = True):
+    """<psi_e| term |psi_e> for every bond term and site field (dcs_expectation_values).
+    psi: [D] or [num, D] device tensor (float32/float64).  Returns a dict of FP64
+    tensors xy [num, B], z [num, B] and sz [num, L] (None unless fields)."""
+    if psi.dim() == 1:
+        psi = psi.unsqueeze(0)
+    _check_dev(psi, sector.device, "psi", (torch.float32, torch.float64))
+    if psi.dim() != 2 or psi.shape[1] != sector.dim:
+        raise ValueError(f"psi must be [num, {sector.dim}], got {tuple(psi.shape)}")
+    psi = psi.contiguous()
+    num, nb = psi.shape[0], terms.num_bonds
+    dev = psi.device
+    exy = torch.zeros((num, nb), dtype=torch.float64, device=dev)
+    ez = torch.zeros((num, nb), dtype=torch.float64, device=dev)
+    esz = torch.zeros((num, sector.L), dtype=torch.float64, device=dev) if fields else None
+    nbytes = C.c_size_t()
+    call("dcs_expectation_workspace_size", sector._h, terms._h, C.byref(nbytes))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    call("dcs_expectation_values", sector._h, terms._h, _dtype_code(psi.dtype), num, _ptr(psi),
+         _ptr(exy), _ptr(ez), _ptr(esz), _ptr(ws), nbytes.value, _stream(sector.device))
+    return {"xy": exy, "z": ez, "sz": esz}
 
 
 def tridiag_eigvals(alpha, beta, num: int, device: int = 0):

@@ -59,7 +59,9 @@ SIGNATURES = {
     "dcs_plan_apply": (_i, [_vp, _i, _pp, _pp, _vp]),
     "dcs_lanczos_workspace_size": (_i, [_vp, _i, _i, _i, _i, _szp]),
     "dcs_lanczos": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _dp, _dp, _ip, _i, _dp, _vp,
-                         _vp, _sz, _vp]),
+                         _i, _vp, _sz, _vp]),
+    "dcs_expectation_workspace_size": (_i, [_vp, _vp, _szp]),
+    "dcs_expectation_values": (_i, [_vp, _vp, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "dcs_tridiag_eigvals": (_i, [_dp, _dp, _i, _i, _dp, _i]),
 }
 

@@ -512,7 +512,8 @@ struct Layout {
     int m, nvec;
 };
 
-Layout layout(const dcs_sector *s, int dtype, int steps, int reorth, int want_vec) {
+Layout layout(const dcs_sector *s, int dtype, int steps, int reorth, int num_vec) {
+    const int want_vec = num_vec > 0;
     Layout L;
     const uint64_t n = s->desc.dim;
     const size_t es = dtype == DCS_F32 ? 4 : 8;
@@ -537,8 +538,8 @@ Layout layout(const dcs_sector *s, int dtype, int steps, int reorth, int want_ve
     p = align256(p + (size_t)(3 * L.m + 3) * sizeof(double));
     L.state = p;
     p = align256(p + sizeof(LzState));
-    L.trid = p;  // eigenvalues, eigenvector and inverse-iteration work
-    p = align256(p + (size_t)(7 * L.m + 16) * sizeof(double));
+    L.trid = p;  // eigenvalues, inverse-iteration work, eigenvectors of T (one per Ritz vector)
+    p = align256(p + (size_t)(7 * L.m + 16 + (size_t)std::max(num_vec, 1) * L.m) * sizeof(double));
     L.total = p;
     return L;
 }
@@ -588,10 +589,10 @@ int replay_steps(StepFn &step, T *ring0, T *ring1, int m, hipStream_t stream) {
 template <typename T>
 int run_lanczos(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
                 const double *h, int dtype, int steps, int reorth, const void *v0, double *h_alpha,
-                double *h_beta, int *h_steps, int num_eig, double *h_eig, void *ground, char *ws,
-                hipStream_t stream) {
+                double *h_beta, int *h_steps, int num_eig, double *h_eig, void *vecs, int num_vec,
+                char *ws, hipStream_t stream) {
     const uint64_t n = s->desc.dim;
-    const Layout L = layout(s, dtype, steps, reorth, ground != nullptr);
+    const Layout L = layout(s, dtype, steps, reorth, vecs ? num_vec : 0);
     T *V = (T *)(ws + L.V);
     T *w = (T *)(ws + L.w);
     double *part = (double *)(ws + L.partials);
@@ -687,8 +688,9 @@ int run_lanczos(const dcs_sector *s, const dcs_terms *t, const double *jxy, cons
         return DCS_EHIP;
     if (h_alpha) memcpy(h_alpha, ha.data(), md * sizeof(double));
     if (h_beta && md > 1) memcpy(h_beta, hb.data(), (md - 1) * sizeof(double));
-    const int ne = std::max(std::min(num_eig, md), ground ? 1 : 0);
-    double *eig = trid, *svec = trid + 16 + md, *work = trid + 16 + 2 * md;
+    const int nv = vecs ? std::min(num_vec, md) : 0;  // Ritz vectors asked for (at most md)
+    const int ne = std::max(std::min(num_eig, md), nv);
+    double *eig = trid, *work = trid + 16 + md, *svecs = trid + 16 + 7 * md;
     if (ne > 0) {
         k_tridiag_bisect<<<(ne + 63) / 64, 64, 0, stream>>>(alpha, beta, md, ne, eig);
         if (int r = chk("tridiagonal bisection")) return r;
@@ -701,33 +703,42 @@ int run_lanczos(const dcs_sector *s, const dcs_terms *t, const double *jxy, cons
         if (h_eig)
             for (int e = 0; e < std::min(num_eig, md); ++e) h_eig[e] = he[e];
     }
-    if (!ground) return DCS_OK;
-    // Ritz vector of the lowest Ritz value: psi = sum_j s_j v_j, normalised
-    k_tridiag_vec<<<1, 1, 0, stream>>>(alpha, beta, md, eig, svec, work);
-    T *psi = (T *)ground;
+    if (!nv) return DCS_OK;
+    // Ritz vectors of the nv lowest Ritz values: psi_e = sum_j s_e[j] v_j, normalised
+    // (s_e: eigenvector of T for eig[e] by inverse iteration)
+    for (int e = 0; e < nv; ++e)
+        k_tridiag_vec<<<1, 1, 0, stream>>>(alpha, beta, md, eig + e, svecs + (size_t)e * md, work);
+    auto psi_of = [&](int e) { return (T *)vecs + (uint64_t)e * n; };
     double *inv = coef + L.m;  // two spare scalars
     if (reorth == DCS_REORTH_FULL) {
-        for (int j = 0; j < md; ++j)
-            k_axpy_s<T><<<nb, kVecThreads, 0, stream>>>(psi, vec(j), n, svec, j, j == 0);
+        for (int e = 0; e < nv; ++e)
+            for (int j = 0; j < md; ++j)
+                k_axpy_s<T><<<nb, kVecThreads, 0, stream>>>(psi_of(e), vec(j), n, svecs + (size_t)e * md, j, j == 0);
     } else {
-        // repeat the recorded two-vector recurrence (same kernels, same vectors)
+        // repeat the recorded two-vector recurrence once (same kernels, same vectors),
+        // adding every step's vector to all nv Ritz vectors
         T *R = (T *)(ws + L.psi_tmp);
         auto rv = [&](int i) -> const T * { return i == 0 ? u0 : R + (uint64_t)(i & 1) * ring_stride(n); };
-        k_axpy_rec<T><<<nb, kVecThreads, 0, stream>>>(psi, rv(0), n, svec, rec, 0, 1);
+        for (int e = 0; e < nv; ++e)
+            k_axpy_rec<T><<<nb, kVecThreads, 0, stream>>>(psi_of(e), rv(0), n, svecs + (size_t)e * md, rec, 0, 1);
         for (int j = 0; j + 1 < md; ++j) {
             if (int r = launch_hx(s, t, jxy, jz, h, dtype, 1, rv(j), w, stream)) return r;
             k_lz_update<T><<<nb, kVecThreads, 0, stream>>>(w, rv(j), j > 0 ? rv(j - 1) : nullptr,
                                                            R + (uint64_t)((j + 1) & 1) * ring_stride(n), n,
                                                            rec, j, nullptr, nullptr);
-            k_axpy_rec<T><<<nb, kVecThreads, 0, stream>>>(psi, rv(j + 1), n, svec, rec, j + 1, 0);
+            for (int e = 0; e < nv; ++e)
+                k_axpy_rec<T><<<nb, kVecThreads, 0, stream>>>(psi_of(e), rv(j + 1), n, svecs + (size_t)e * md,
+                                                              rec, j + 1, 0);
             if (int r = chk("Ritz vector replay")) return r;
         }
     }
     if (int r = chk("Ritz vector")) return r;
-    k_norm2<T><<<nb, kVecThreads, 0, stream>>>(psi, n, part);
-    k_reduce<<<1, kReduceThreads, 0, stream>>>(part, nb, 1, inv + 1, 3, nullptr, alpha, beta, 0,
-                                               L.m);
-    k_scale<T><<<nb, kVecThreads, 0, stream>>>(psi, psi, n, inv + 1, nullptr);
+    for (int e = 0; e < nv; ++e) {
+        k_norm2<T><<<nb, kVecThreads, 0, stream>>>(psi_of(e), n, part);
+        k_reduce<<<1, kReduceThreads, 0, stream>>>(part, nb, 1, inv + 1, 3, nullptr, alpha, beta, 0,
+                                                   L.m);
+        k_scale<T><<<nb, kVecThreads, 0, stream>>>(psi_of(e), psi_of(e), n, inv + 1, nullptr);
+    }
     return chk("Ritz vector norm");
 }
 
@@ -737,22 +748,23 @@ int run_lanczos(const dcs_sector *s, const dcs_terms *t, const double *jxy, cons
 using namespace dcs;
 
 extern "C" int dcs_lanczos_workspace_size(const dcs_sector *s, int dtype, int steps, int reorth,
-                                          int want_vector, size_t *bytes) {
+                                          int num_vec, size_t *bytes) {
     clear_error();
     if (!s || !bytes) return set_error(DCS_EINVAL, "NULL argument");
     if (dtype != DCS_F32 && dtype != DCS_F64) return set_error(DCS_EINVAL, "dtype %d", dtype);
     if (reorth < DCS_REORTH_NONE || reorth > DCS_REORTH_FULL)
         return set_error(DCS_EINVAL, "reorth %d", reorth);
     if (steps < 1) return set_error(DCS_EINVAL, "steps %d < 1", steps);
-    *bytes = layout(s, dtype, steps, reorth, want_vector).total;
+    if (num_vec < 0) return set_error(DCS_EINVAL, "num_vec %d", num_vec);
+    *bytes = layout(s, dtype, steps, reorth, num_vec).total;
     return DCS_OK;
 }
 
 extern "C" int dcs_lanczos(const dcs_sector *s, const dcs_terms *t, const double *jxy,
                            const double *jz, const double *h, int dtype, int steps, int reorth,
                            const void *v0, double *h_alpha, double *h_beta, int *h_steps,
-                           int num_eig, double *h_eig, void *ground, void *ws, size_t ws_bytes,
-                           void *stream) {
+                           int num_eig, double *h_eig, void *vecs, int num_vec, void *ws,
+                           size_t ws_bytes, void *stream) {
     clear_error();
     if (!s || !t || !v0 || !h_steps) return set_error(DCS_EINVAL, "NULL argument");
     if (dtype != DCS_F32 && dtype != DCS_F64) return set_error(DCS_EINVAL, "dtype %d", dtype);
@@ -761,15 +773,17 @@ extern "C" int dcs_lanczos(const dcs_sector *s, const dcs_terms *t, const double
     if (steps < 1) return set_error(DCS_EINVAL, "steps %d < 1", steps);
     if (num_eig < 0 || (num_eig > 0 && !h_eig)) return set_error(DCS_EINVAL, "num_eig / h_eig");
     if (t->num_bonds > 0 && (!jxy || !jz)) return set_error(DCS_EINVAL, "NULL couplings");
-    const Layout L = layout(s, dtype, steps, reorth, ground != nullptr);
+    if (vecs && num_vec < 1) return set_error(DCS_EINVAL, "num_vec %d with a vector output", num_vec);
+    if (!vecs) num_vec = 0;
+    const Layout L = layout(s, dtype, steps, reorth, num_vec);
     if (!ws || ws_bytes < L.total)
         return set_error(DCS_EINVAL, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
     DeviceGuard dg(s->device);
     if (dtype == DCS_F32)
         return run_lanczos<float>(s, t, jxy, jz, h, dtype, steps, reorth, v0, h_alpha, h_beta,
-                                  h_steps, num_eig, h_eig, ground, (char *)ws, (hipStream_t)stream);
+                                  h_steps, num_eig, h_eig, vecs, num_vec, (char *)ws, (hipStream_t)stream);
     return run_lanczos<double>(s, t, jxy, jz, h, dtype, steps, reorth, v0, h_alpha, h_beta, h_steps,
-                               num_eig, h_eig, ground, (char *)ws, (hipStream_t)stream);
+                               num_eig, h_eig, vecs, num_vec, (char *)ws, (hipStream_t)stream);
 }
 
 extern "C" int dcs_tridiag_eigvals(const double *h_alpha, const double *h_beta, int m, int num,
