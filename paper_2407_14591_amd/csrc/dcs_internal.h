@@ -133,6 +133,7 @@ constexpr int kRowTilings = 3;             // RB = 16, 32, 64
 constexpr uint32_t kTileLdsTotal = 160 * 1024;  // LDS of one workgroup of the block-tiled row pass
 constexpr uint32_t kTileLdsStatic = 1024;       // its static LDS and slack
 constexpr int kMaxRunTiles = 64;           // tiles of one run
+constexpr uint32_t kSplitRowTile = 512;    // rows of one tile of the row pass (one per thread)
 struct RowTiling {
     uint2 *d_tiles = nullptr;              // (left configuration, block | tile-in-run << 8), in launch order:
                                            // groups of left configurations that differ only on the
@@ -177,6 +178,10 @@ struct SplitRows {
     uint32_t *d_clstart = nullptr;   // first left configuration of every cluster
     uint32_t *d_clsize = nullptr;    // its number of left configurations
     uint64_t *d_lrun = nullptr;      // the left family entries with run starts only: bond << 48 | run
+    uint32_t *d_rorder = nullptr;    // tiles of the row pass (left configuration << 8 | chunk) by
+                                     // groups of equal words outside the crossing sites
+    uint64_t n_rorder = 0;
+    std::vector<uint32_t> h_rorder;  // (host, while building)
     uint32_t clbase[kMaxLeftM];      // first cluster of block m - m_lo
     uint32_t nclust[kMaxLeftM];
     uint32_t max_cluster = 0;

@@ -332,6 +332,7 @@ void free_rows(SplitRows &c) {
     hipFree(c.d_clstart);
     hipFree(c.d_clsize);
     hipFree(c.d_lrun);
+    hipFree(c.d_rorder);
     hipFree(c.d_diag);
     for (int i = 0; i < kRowTilings; ++i) {
         hipFree(c.tiling[i].d_tiles);

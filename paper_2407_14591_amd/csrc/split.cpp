@@ -239,6 +239,31 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
         std::vector<int> block_of(li.count);
         for (int mi = 0; mi < li.m_count; ++mi)
             for (uint32_t q = 0; q < li.nleft[mi]; ++q) block_of[li.lbase[mi] + q] = mi;
+        // tiles of kSplitRowTile rows: each group of left configurations that differ
+        // only at the crossing sites (closed under every crossing bond) together,
+        // their runs interleaved at equal fractions of their lengths, so that the
+        // crossing targets of the tiles in flight lie in runs being read
+        {
+            std::vector<std::pair<double, uint32_t>> grp;
+            for (size_t a = 0; a < order.size();) {
+                size_t b = a + 1;
+                const uint32_t key = li.h_words[order[a]] & ~cross_mask;
+                while (b < order.size() && (li.h_words[order[b]] & ~cross_mask) == key) ++b;
+                grp.clear();
+                for (size_t q = a; q < b; ++q) {
+                    const uint32_t g = order[q];
+                    const uint32_t nsub = (uint32_t)((li.ncols[block_of[g]] + kSplitRowTile - 1) / kSplitRowTile);
+                    for (uint32_t j = 0; j < nsub; ++j)
+                        grp.emplace_back((j + 0.5) / nsub, (g << 8) | j);
+                }
+                std::stable_sort(grp.begin(), grp.end(),
+                                 [](const std::pair<double, uint32_t> &u, const std::pair<double, uint32_t> &v) {
+                                     return u.first < v.first;
+                                 });
+                for (const auto &e : grp) c.h_rorder.push_back(e.second);
+                a = b;
+            }
+        }
         for (int ti = 0; ti < kRowTilings; ++ti) {
             RowTiling &T = c.tiling[ti];
             const uint32_t rb = 16u << ti;
@@ -365,6 +390,7 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
               up((void **)&c.d_clstart, clstart.data(), clstart.size() * sizeof(uint32_t)) &&
               up((void **)&c.d_clsize, clsize.data(), clsize.size() * sizeof(uint32_t)) &&
               up((void **)&c.d_lrun, lrun.data(), lrun.size() * sizeof(uint64_t)) &&
+              up((void **)&c.d_rorder, c.h_rorder.data(), c.h_rorder.size() * sizeof(uint32_t)) &&
               // diagonal of both sides, then the per-call coupling factors (1024 doubles + 1024 floats)
               check_hip(hipMalloc(&c.d_diag, ((li.count + li.rcount + 1) / 2 * 2 + 1536) * sizeof(double)),
                         "hipMalloc split diagonal") == DCS_OK;
@@ -380,6 +406,9 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
         T.h_canon.clear();
         T.h_canon.shrink_to_fit();
     }
+    c.n_rorder = c.h_rorder.size();
+    c.h_rorder.clear();
+    c.h_rorder.shrink_to_fit();
     if (!ok) {
         free_rows(c);
         return nullptr;

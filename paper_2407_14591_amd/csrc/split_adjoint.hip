@@ -276,7 +276,7 @@ int launch_split_adjoint(dcs_sector *s, const SplitRows &c, const double *jxy, c
         P.xprim = x;
         P.part = colpart;
         P.part_n = tiles;
-        const size_t lds = (size_t)kMaxClusterRuns * kColWaveBytes + (size_t)kColWaves * std::max(nbonds, 1) * sizeof(double);
+        const size_t lds = col_params(P, li, c, kColWaveBytes, std::max(nbonds, 1));
         auto kern = split_cols_kernel<float, 1, true>;
         if (int r = ensure_lds(kern, lds)) return r;
         kern<<<split_grid(s, tiles), kColThreads, lds, stream>>>(P);

@@ -32,7 +32,7 @@ namespace sp {
 
 using hx::Acc;
 
-constexpr int kThreads = 512;
+constexpr int kThreads = (int)kSplitRowTile;
 constexpr uint32_t kOob = 0x80000000u;  // past every run: all record counts here are < 2^31
 constexpr uint32_t kBufferWord3 = 0x00020000u;  // 32-bit data format, no swizzle
 
@@ -206,6 +206,7 @@ struct RowParams {
     const double *dl, *dr;
     const uint32_t *lptr;  // left family (the fused form): entries of every left configuration
     const uint64_t *lrun;  // bond << 48 | run start of the target
+    const uint32_t *order;  // if not NULL: tile t is left configuration order[t] >> 8, chunk & 0xFF
     uint32_t *counters;
     uint64_t xbase[9];  // tile range of every XCD
     uint32_t count, rcount;
@@ -308,10 +309,21 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
     BlockCursor blk(P.tbase, P.m_count);
     uint64_t t;
     while (Q.get(t)) {
-        const int mi = blk(t);
-        const uint32_t local = (uint32_t)(t - P.tbase[mi]);
-        const uint32_t lq = local / P.nsub[mi], ch = local - lq * P.nsub[mi];
-        const uint32_t gl = P.lbase[mi] + lq;
+        int mi;
+        uint32_t gl, ch;
+        if (P.order) {  // uniform
+            const uint32_t e = ro(P.order)[t];
+            gl = e >> 8;
+            ch = e & 0xFFu;
+            mi = 0;
+            while (mi + 1 < P.m_count && gl >= P.lbase[mi + 1]) ++mi;
+        } else {
+            mi = blk(t);
+            const uint32_t local = (uint32_t)(t - P.tbase[mi]);
+            const uint32_t lq = local / P.nsub[mi];
+            ch = local - lq * P.nsub[mi];
+            gl = P.lbase[mi] + lq;
+        }
         const uint32_t ncols = P.ncols[mi];
         const uint32_t r = ch * kThreads + threadIdx.x;
         const bool active = r < ncols;
@@ -994,29 +1006,35 @@ struct ColParams {
     const void *xprim;
     double *part;
     uint64_t part_n;
+    uint32_t adj_lds_off;  // ADJ: byte offset of the per-wave sums
 };
 static_assert(sizeof(ColParams) <= 4096, "kernel arguments are limited to 4 KiB");
 
 constexpr int kColThreads = 1024;  // 16 waves share one staged cluster
 constexpr int kColWaves = kColThreads / 64;
-constexpr int kColBatch = 4;              // gathers in flight per wave (2, 6, 8, 16 measured slower)
+constexpr int kColBatch = 4;              // gathers in flight per wave (8 measured slower)
 constexpr uint32_t kColLaneBytes = 16;    // bytes of x per lane and gather
 constexpr uint32_t kColWaveBytes = 64 * kColLaneBytes;
 
 // One tile = one cluster of left configurations (see SplitRows) at one 1 KiB
-// chunk of their runs.  The chunk of every run of the cluster is first copied
-// to LDS; the targets inside the cluster (bonds inside P_{K-1}) are then read
-// there, the others from HBM.  Wave w takes the cluster's runs w, w+8, ...
+// chunk (64 lanes x 16 bytes) of their runs.  The chunk of every run of the cluster
+// is first copied to LDS; the targets inside the cluster (bonds inside P_{K-1})
+// are then read there, the others from HBM.  Wave w takes the cluster's runs
+// w, w + 16, ...: the entries of a run come in one vector load (lane q holds
+// entry q), fetched while the wave works on its previous run, so no gather
+// waits on a table load; kColBatch gathers are in flight per wave.
 // ADJ (k = 1): the product is y += (left family) g (x is g); each hop also adds
-// x_s g_t to its bond's sum (per-wave LDS slots after the dynamic staging area, one
+// x_s g_t to its bond's sum (per-wave LDS slots after the staged chunks, one
 // writing wave each, added in wave order at the end of the tile into P.part).
 template <typename T, int K, bool ADJ = false>
 __global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams P_arg) {
     (void)P_arg;
     const ColParams &P = kernel_arg0<ColParams>();
-    constexpr int V = kColLaneBytes / sizeof(T);
+    constexpr int LB = (int)kColLaneBytes;
+    constexpr int V = LB / sizeof(T);
+    constexpr uint32_t WB = kColWaveBytes;  // chunk bytes per run
     typedef T vec_t __attribute__((ext_vector_type(V)));
-    extern __shared__ __align__(16) char cl_lds[];  // [cluster run][kColWaveBytes]
+    extern __shared__ __align__(16) char cl_lds[];  // [cluster run][WB]
     __shared__ uint32_t slots[2];
     __shared__ T amp[kMaxBonds];
     for (int q = threadIdx.x; q < kMaxBonds; q += kColThreads)
@@ -1026,8 +1044,7 @@ __global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
     static_assert(!ADJ || K == 1, "the adjoint column pass takes one column");
-    // ADJ: [wave][bond] sums after the staged chunks (kMaxClusterRuns of them)
-    double *wacc = reinterpret_cast<double *>(cl_lds + (size_t)kMaxClusterRuns * kColWaveBytes);
+    double *wacc = reinterpret_cast<double *>(cl_lds + P.adj_lds_off);  // ADJ: [wave][bond]
     const T *__restrict__ xp = reinterpret_cast<const T *>(P.xprim);
     AheadQueue Q(P.counters, P.xbase, slots);
     BlockCursor blk(P.tbase, P.m_count);
@@ -1038,11 +1055,11 @@ __global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams
         const uint32_t c = local / P.nclust[mi], cl = P.clbase[mi] + (local - c * P.nclust[mi]);
         const uint32_t g0 = ro(P.clstart)[cl], size = ro(P.clsize)[cl];
         const uint32_t nrec = P.ncols[mi] * (uint32_t)(K * sizeof(T));
-        const uint32_t boff = c * kColWaveBytes + lane * kColLaneBytes;  // byte of the run
-        // the last chunk of a run may end inside a lane's 16 bytes: there every
+        const uint32_t boff = c * WB + lane * (uint32_t)LB;  // byte of the run
+        // the last chunk of a run may end inside a lane's bytes: there every
         // value is loaded on its own, so no load straddles the run end
-        const bool tail = (c + 1) * kColWaveBytes > nrec;  // uniform
-        auto load16 = [&](__amdgpu_buffer_rsrc_t r) -> vec_t {
+        const bool tail = (c + 1) * WB > nrec;  // uniform
+        auto loadv = [&](__amdgpu_buffer_rsrc_t r) -> vec_t {
             vec_t v;
             if (!tail) {
                 const auto raw = __builtin_amdgcn_raw_buffer_load_b128(r, boff, 0, 0);
@@ -1055,32 +1072,53 @@ __global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams
         };
         if constexpr (ADJ)
             for (int b = (int)lane; b < P.nbonds; b += 64) wacc[wave * P.nbonds + b] = 0.0;
+        // the entries of run i: range [qa, qb) of P.lent, entry qa + lane in ev
+        auto fetch = [&](uint32_t i, uint32_t &qa, uint32_t &qb, uint64_t &ev) {
+            qa = ro(P.lptr)[g0 + i];
+            qb = ro(P.lptr)[g0 + i + 1];
+            ev = qa + lane < qb ? P.lent[qa + lane] : 0ull;
+        };
+        uint32_t qa = 0, qb = 0;
+        uint64_t ev = 0;
+        if (wave < size) fetch(wave, qa, qb, ev);  // in flight with the staging below
         // stage the chunk of every run of the cluster (zeros past a run's end)
         for (uint32_t i = wave; i < size; i += kColWaves) {
-            const vec_t v = load16(rsrc(x + ro(P.runs)[g0 + i] * K, nrec));
-            *reinterpret_cast<vec_t *>(cl_lds + (size_t)i * kColWaveBytes + lane * kColLaneBytes) = v;
+            const vec_t v = loadv(rsrc(x + ro(P.runs)[g0 + i] * K, nrec));
+            *reinterpret_cast<vec_t *>(cl_lds + (size_t)i * WB + lane * (uint32_t)LB) = v;
         }
         __syncthreads();
         for (uint32_t i = wave; i < size; i += kColWaves) {
-            const uint32_t gl = g0 + i;
+            const uint64_t R = ro(P.runs)[g0 + i];
+            const auto yr = rsrc(y + R * K, nrec);
+            const vec_t yold = loadv(yr);  // in flight with the gathers
             vec_t acc = (vec_t)(T)0;
             vec_t xo4 = (vec_t)(T)0;  // ADJ: the primal vector at this lane's rows
-            if constexpr (ADJ) xo4 = load16(rsrc(xp + ro(P.runs)[gl] * K, nrec));
-            const uint32_t q1 = ro(P.lptr)[gl + 1];
-            for (uint32_t q0 = ro(P.lptr)[gl]; q0 < q1; q0 += kColBatch) {
+            if constexpr (ADJ) xo4 = loadv(rsrc(xp + R * K, nrec));
+            const uint32_t n = qb - qa, base = qa;
+            const uint64_t ecur = ev;
+            if (i + kColWaves < size) fetch(i + kColWaves, qa, qb, ev);  // the wave's next run
+            for (uint32_t q0 = 0; q0 < n; q0 += kColBatch) {
                 vec_t v[kColBatch];
                 T a[kColBatch];
                 uint32_t bnd[kColBatch];
 #pragma unroll
                 for (int u = 0; u < kColBatch; ++u) {
-                    const bool ok = q0 + u < q1;
-                    const uint64_t ent = ro(P.lent)[ok ? q0 + u : q0];
+                    const uint32_t q = q0 + u;
+                    const bool ok = q < n;
+                    uint64_t ent;
+                    if (q < 64) {
+                        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)ecur, ok ? q : 0);
+                        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(ecur >> 32), ok ? q : 0);
+                        ent = (uint64_t)hi << 32 | lo;
+                    } else {  // entries past the first 64 of a run (dense left families)
+                        ent = ro(P.lent)[base + (ok ? q : 0)];
+                    }
                     if (ok && (ent >> 63)) {  // uniform: a run of this cluster
                         const uint32_t j = (uint32_t)(ent & 0xFFFFu);
-                        v[u] = *reinterpret_cast<const vec_t *>(cl_lds + (size_t)(j < size ? j : 0) * kColWaveBytes +
-                                                                lane * kColLaneBytes);
+                        v[u] = *reinterpret_cast<const vec_t *>(cl_lds + (size_t)(j < size ? j : 0) * WB +
+                                                                lane * (uint32_t)LB);
                     } else {
-                        v[u] = load16(rsrc(x + (ent & 0xFFFFFFFFFFFFull) * K, ok ? nrec : 0u));
+                        v[u] = loadv(rsrc(x + (ent & 0xFFFFFFFFFFFFull) * K, ok ? nrec : 0u));
                     }
                     bnd[u] = (uint32_t)(ent >> 48) & 0xFFu;
                     a[u] = ok ? amp[bnd[u]] : (T)0;
@@ -1096,26 +1134,24 @@ __global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams
                         float f = 0.f;
 #pragma unroll
                         for (int e = 0; e < V; ++e) f += (float)xo4[e] * (float)v[u][e];
-                        d[u] = q0 + u < q1 ? (double)f : 0.0;
+                        d[u] = q0 + u < n ? (double)f : 0.0;
                     }
-                    static_assert(kColBatch == 4, "the transposed sum takes 4 values");
+                    static_assert(!ADJ || kColBatch == 4, "the transposed sum takes 4 values");
                     const double tsum = hx::wave_transpose_sum<4>(d);
                     const uint32_t u = lane >> 2;
-                    if (lane < 16 && (lane & 3u) == 0 && q0 + u < q1) {
+                    if (lane < 16 && (lane & 3u) == 0 && q0 + u < n) {
                         const uint32_t b = u == 0 ? bnd[0] : (u == 1 ? bnd[1] : (u == 2 ? bnd[2] : bnd[3]));
                         wacc[wave * P.nbonds + b] += tsum;
                     }
                 }
             }
             if (boff < nrec) {
-                T *ys = reinterpret_cast<T *>(reinterpret_cast<char *>(y + ro(P.runs)[gl] * K) + boff);
-                if (boff + kColLaneBytes <= nrec) {
-                    vec_t *yp = reinterpret_cast<vec_t *>(ys);
-                    __builtin_nontemporal_store(__builtin_nontemporal_load(yp) + acc, yp);
+                T *ys = reinterpret_cast<T *>(reinterpret_cast<char *>(y + R * K) + boff);
+                if (boff + (uint32_t)LB <= nrec) {
+                    __builtin_nontemporal_store(yold + acc, reinterpret_cast<vec_t *>(ys));
                 } else {
                     for (int e = 0; e < V; ++e)
-                        if (boff + e * (uint32_t)sizeof(T) < nrec)
-                            __builtin_nontemporal_store(__builtin_nontemporal_load(ys + e) + acc[e], ys + e);
+                        if (boff + e * (uint32_t)sizeof(T) < nrec) __builtin_nontemporal_store(yold[e] + acc[e], ys + e);
                 }
             }
         }
@@ -1138,11 +1174,22 @@ inline bool rows_lds_enabled() {
     return !(e && e[0] == '0');
 }
 
-// DCS_ROW_ORDER=rows (read at every product) launches the block tiles of the row
-// pass in row order instead of by groups of crossing sites.
+// DCS_ROW_ORDER=rows (read at every product) launches the tiles of the row pass
+// (both the block tiles and the 512-row tiles) in row order instead of by groups
+// of left configurations that differ only at the crossing sites.
 inline bool rows_group_order() {
     const char *e = getenv("DCS_ROW_ORDER");
     return !(e && e[0] == 'r');
+}
+
+// The column pass's block fields and its dynamic LDS bytes (chunk width wb; with
+// adj_nbonds > 0 also the adjoint's per-wave sums).
+inline size_t col_params(ColParams &P, const LeftInfo &li, const SplitRows &c, uint32_t wb, int adj_nbonds) {
+    (void)li;
+    size_t lds = (size_t)std::max<uint32_t>(c.max_cluster, 1) * wb;
+    P.adj_lds_off = (uint32_t)lds;
+    if (adj_nbonds > 0) lds += (size_t)kColWaves * adj_nbonds * sizeof(double);
+    return lds;
 }
 
 inline int split_grid(const dcs_sector *s, uint64_t tiles) {
@@ -1329,6 +1376,8 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
                 P.margin = 0;
                 wl = 0;
             }
+            // the tile list by crossing groups (DCS_ROW_ORDER=rows: run order)
+            if (rows_group_order() && c.d_rorder && c.n_rorder == tiles) P.order = c.d_rorder;
             auto kern = fused ? split_rows_kernel<T, K, true> : split_rows_kernel<T, K, false>;
             if (int r = ensure_lds(kern, wl)) return r;
             kern<<<split_grid(s, tiles), kThreads, wl, stream>>>(P);
@@ -1351,9 +1400,10 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
         P.counters = s->dev.counters + 8;
         P.m_count = li.m_count;
         P.nbonds = nbonds;
+        const uint32_t wb = kColWaveBytes;
         uint64_t tiles = 0;
         for (int m = 0; m < li.m_count; ++m) {
-            const uint64_t nchunk = (li.ncols[m] * K * sizeof(T) + kColWaveBytes - 1) / kColWaveBytes;
+            const uint64_t nchunk = (li.ncols[m] * K * sizeof(T) + wb - 1) / wb;
             P.ncols[m] = (uint32_t)li.ncols[m];
             P.clbase[m] = c.clbase[m];
             P.nclust[m] = c.nclust[m];
@@ -1362,7 +1412,7 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
         }
         P.tbase[li.m_count] = tiles;
         xcd_ranges(tiles, P.xbase);
-        const size_t lds = (size_t)std::max<uint32_t>(c.max_cluster, 1) * kColWaveBytes;
+        const size_t lds = col_params(P, li, c, wb, 0);
         auto kern = split_cols_kernel<T, K>;
         if (int r = ensure_lds(kern, lds)) return r;
         kern<<<split_grid(s, tiles), kColThreads, lds, stream>>>(P);
