@@ -111,6 +111,8 @@ def median(v):
 def extra_workloads(dq, synth, torch, steps: int, warmup: int):
     """The other measured cases (dict of results); every input is seeded and synthetic.
     Times are medians of per-launch HIP-event intervals."""
+    import numpy as np
+
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     out = {}
@@ -213,8 +215,26 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
     per = timed(lambda: plan.apply(xs, ys))
     out["plan_101_sectors_f32"] = {"sectors": len(items), "rows": total, "ms": per * 1e3,
                                    "states_per_s": total / per,
-                                   "achieved_GBs": total * 8 / per / 1e9}
-    del plan, items, xs, ys
+                                   "achieved_GBs": total * 8 / per / 1e9,
+                                   "frac_of_peak": total * 8 / per / 1e9 / PEAK_HBM_GBS,
+                                   "note": "sectors of >= 2^20 rows run their own split products beside the launch"}
+    del plan
+    # the same sectors without split views: every row in the one persistent launch
+    os.environ["DCS_SPLIT_MIN_DIM"] = str(1 << 62)
+    try:
+        items1 = []
+        for (sec, tt, j_, z_), (q_, ls, ns) in zip(items, specs):
+            items1.append((dq.Sector(ls, ns, q_, device=0), tt, j_, z_))
+    finally:
+        os.environ.pop("DCS_SPLIT_MIN_DIM", None)
+    plan1 = dq.Plan(items1)
+    per1 = timed(lambda: plan1.apply(xs, ys))
+    out["plan_101_sectors_f32_one_launch"] = {"sectors": len(items1), "rows": total, "ms": per1 * 1e3,
+                                              "states_per_s": total / per1,
+                                              "achieved_GBs": total * 8 / per1 / 1e9,
+                                              "frac_of_peak": total * 8 / per1 / 1e9 / PEAK_HBM_GBS,
+                                              "hybrid_over_one_launch": per / per1}
+    del plan1, items1, items, xs, ys
 
     # 200 Lanczos steps on the L=32, n=16 J1-J2 sector (J2/J1 = 1/2: E0 = -3L/8 = -12)
     s = dq.Sector(L, N_UP, 2, SPLIT, device=0)
@@ -258,16 +278,49 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
                                  "ms_per_step": el / r["steps_done"] * 1e3, "reorth": r["reorth"],
                                  "E0": r["eig"][0], "E0_bethe_ansatz": e_bethe,
                                  "E0_error_vs_bethe": r["eig"][0] - e_bethe}
-    del x
+    del x, s, t
+    torch.cuda.empty_cache()
+
+    # App. D's example: open L=28, n=14 chain in the field h_k = k, the four lowest
+    # states (240 Lanczos steps, stored basis, FP64) and <Sz_0> of each, against the
+    # values the oracle's deflated Lanczos wrote to tests/golden/appd_L28.json
+    s = dq.Sector(28, 14, 2, [7, 7, 7, 7], device=0)
+    bonds, jxy, jz, h = synth.tilted_field_chain(28)
+    t = dq.Terms(bonds)
+    jd, zd, hd = (torch.tensor(a, device=dev) for a in (jxy, jz, h))
+    v0 = torch.tensor(synth.vector(s.dim, synth.SEED_V0), device=dev)
+    dq.hamiltonian_apply(s, t, jd, zd, v0, h=hd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = dq.lanczos(s, t, jd, zd, v0, 240, reorth="full", num_eig=4, num_vec=4, h=hd)
+    t1 = time.perf_counter()
+    ex = dq.expectation_values(s, t, r["vectors"])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ref = json.load(open(os.path.join(ROOT, "tests", "golden", "appd_L28.json")))["states"]
+    sz0 = ex["sz"][:, 0].cpu().tolist()
+    out["appd_L28_lowest4"] = {
+        "steps": r["steps_done"], "reorth": r["reorth"], "lanczos_s": t1 - t0,
+        "expectation_s": t2 - t1, "ms_per_step": (t1 - t0) / r["steps_done"] * 1e3,
+        "E": r["eig"], "Sz0": sz0,
+        "E_error_vs_oracle": [r["eig"][e] - ref[e]["E"] for e in range(len(ref))],
+        "Sz_max_error_vs_oracle": max(
+            float(np.abs(ex["sz"][e].cpu().numpy() - np.array(ref[e]["sz"])).max())
+            for e in range(len(ref)))}
+    del r, ex, v0, s, t
     torch.cuda.empty_cache()
     return out
 
 
 def split_sweep(dq, synth, torch, steps: int, warmup: int):
     """Rank, unrank and FP32 H*x throughput on the L=32, n=16 sector versus the number
-    of subsystems (most-equal splits, shorter parts first): the paper's question of
-    the best split, asked of the GPU kernels.  Splits whose tables exceed on-chip
-    memory are reported as unsupported."""
+    of subsystems (most-equal splits, shorter parts first) and the placement of the
+    index tables: the paper's question of the best split, asked of the GPU kernels.
+    Tables up to the on-chip budget go to LDS ("lds"); larger ones (16/16, 10/11/11)
+    stay in device memory ("device"), and every split that fits LDS is run a second
+    time with its tables forced into device memory.  H*x is timed in the form the
+    autotuner keeps and, where that is the split product, also as the one-pass
+    kernel (DCS_SPLIT=0)."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     cnt = 1 << 24
@@ -281,14 +334,21 @@ def split_sweep(dq, synth, torch, steps: int, warmup: int):
     x = torch.randn(601080390, generator=g, device=dev, dtype=torch.float32)
     y = torch.empty_like(x)
     out = {}
-    for nsub in (2, 3, 4, 5, 6, 7, 8):
-        sizes = [L // nsub + (1 if i >= nsub - L % nsub else 0) for i in range(nsub)]
-        key = "/".join(map(str, sizes))
+
+    def run(sizes, force_device):
+        old = os.environ.get("DCS_GLOBAL_TABLES")
+        if force_device:
+            os.environ["DCS_GLOBAL_TABLES"] = "1"
         try:
             s = dq.Sector(L, N_UP, 2, sizes, device=0)
-        except Exception as e:  # tables beyond the on-chip budget
-            out[key] = {"supported": False, "reason": str(e).splitlines()[0][:160]}
-            continue
+        except Exception as e:
+            return {"supported": False, "reason": str(e).splitlines()[0][:160]}
+        finally:
+            if force_device:
+                if old is None:
+                    os.environ.pop("DCS_GLOBAL_TABLES", None)
+                else:
+                    os.environ["DCS_GLOBAL_TABLES"] = old
         idx = torch.empty_like(states)
         back = torch.empty_like(states)
         per_r = median(time_steps(lambda: s.rank(states, out=idx), stream, steps, warmup))
@@ -297,10 +357,31 @@ def split_sweep(dq, synth, torch, steps: int, warmup: int):
         t = dq.Terms(bonds)
         per_h = median(time_steps(lambda: dq.hamiltonian_apply(s, t, jd, zd, x, out=y), stream,
                                   max(3, steps // 4), 1))
-        out[key] = {"supported": True, "rank_per_s": cnt / per_r, "unrank_per_s": cnt / per_u,
-                    "roundtrip_ok": ok, "hx_f32k1_ms": per_h * 1e3, "hx_states_per_s": s.dim / per_h,
-                    "form": dq.hamiltonian_form(s, t, torch.float32, 1)}
+        form = dq.hamiltonian_form(s, t, torch.float32, 1)
+        rec = {"supported": True, "tables": "device" if s.tables_in_device_memory else "lds",
+               "table_bytes": s.table_bytes, "rank_per_s": cnt / per_r, "unrank_per_s": cnt / per_u,
+               "roundtrip_ok": ok, "hx_f32k1_ms": per_h * 1e3, "hx_states_per_s": s.dim / per_h,
+               "form": form}
+        if form != "single":
+            os.environ["DCS_SPLIT"] = "0"
+            try:
+                per_1 = median(time_steps(lambda: dq.hamiltonian_apply(s, t, jd, zd, x, out=y), stream,
+                                          max(3, steps // 4), 1))
+                rec["hx_f32k1_one_pass_ms"] = per_1 * 1e3
+            except Exception as e:
+                rec["hx_f32k1_one_pass_ms"] = None
+                rec["one_pass_reason"] = str(e).splitlines()[0][:160]
+            finally:
+                os.environ.pop("DCS_SPLIT", None)
         del idx, back, s, t
+        return rec
+
+    for nsub in (2, 3, 4, 5, 6, 7, 8):
+        sizes = [L // nsub + (1 if i >= nsub - L % nsub else 0) for i in range(nsub)]
+        key = "/".join(map(str, sizes))
+        out[key] = run(sizes, False)
+        if out[key].get("tables") == "lds":
+            out[key + " (device tables)"] = run(sizes, True)
     return out
 
 

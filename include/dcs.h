@@ -107,10 +107,22 @@ int dcs_version(void);
  * lookup tables (Sec. 4.2, memory-aligned list, lexicographic inside each
  * digit sum), then copies them to `device`.  The returned object owns them.
  *
+ * Table placement (Sec. 4.2 containers, Sec. 4.3 choice of N): tables of at
+ * most 112 KiB are copied into LDS by every kernel that reads them; larger
+ * tables (for instance the 16/16 and 10/11/11 splits of L = 32) stay in device
+ * memory and are read through the caches (DCS_GLOBAL_TABLES=1 in the
+ * environment at creation forces this placement).  With tables in device memory,
+ * rank, unrank, enumerate, the split product (Q = 2), the one-pass product of one
+ * column and the adjoint of one column work as usual; the one-pass product and the
+ * adjoint of a block of k > 1 columns need the tables in LDS (such a block product
+ * runs only on the split tables, else DCS_EUNSUPPORTED), and dcs_plan_create
+ * rejects such a sector unless it has a split view (which runs its own product).
+ *
  * Errors: DCS_EINVAL if Q < 2, L < 1, L*ceil(log2 Q) > 64, n outside
  * [0, (Q-1)L], sizes not positive or not summing to L; DCS_EUNSUPPORTED if
- * N > DCS_MAX_SUBSYSTEMS, a subsystem word wider than 14 bits, or tables too
- * large for on-chip memory (112 KiB); DCS_ENOMEM / DCS_EHIP on allocation.
+ * N > DCS_MAX_SUBSYSTEMS, a subsystem word wider than 16 bits, or a subsystem
+ * with more than 2^14 words of one digit sum (the decode's quotient bound);
+ * DCS_ENOMEM / DCS_EHIP on allocation.
  */
 int dcs_sector_create(int L, int n_particles, int local_dim, int num_subsystems,
                       const int *sizes, int device, dcs_sector **out);
@@ -123,6 +135,11 @@ int dcs_sector_dim(const dcs_sector *sector, uint64_t *dim);
 
 /* Number of subsystems and their sizes (sizes may be NULL; else >= N entries). */
 int dcs_sector_split(const dcs_sector *sector, int *num_subsystems, int *sizes);
+
+/* Placement of the sector's index tables (see dcs_sector_create): *in_device_memory
+ * is 1 when kernels read them in device memory, 0 when they stage them in LDS;
+ * *bytes is their size.  Either output may be NULL. */
+int dcs_sector_tables(const dcs_sector *sector, int *in_device_memory, size_t *bytes);
 
 /*
  * Batched rank, function (i) of Sec. 2.2 / Alg. i: d_idx[t] = index of

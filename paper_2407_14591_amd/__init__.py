@@ -93,6 +93,10 @@ class Sector:
         sizes = (C.c_int * 64)()
         call("dcs_sector_split", self._h, C.byref(num), sizes)
         self.split = [sizes[i] for i in range(num.value)]
+        gt, tb = C.c_int(), C.c_size_t()
+        call("dcs_sector_tables", self._h, C.byref(gt), C.byref(tb))
+        self.tables_in_device_memory = bool(gt.value)  # else staged in LDS by every kernel
+        self.table_bytes = int(tb.value)
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

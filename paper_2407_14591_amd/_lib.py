@@ -42,6 +42,7 @@ SIGNATURES = {
     "dcs_sector_destroy": (_i, [_vp]),
     "dcs_sector_dim": (_i, [_vp, _u64p]),
     "dcs_sector_split": (_i, [_vp, _ip, _ip]),
+    "dcs_sector_tables": (_i, [_vp, _ip, _szp]),
     "dcs_rank": (_i, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "dcs_unrank": (_i, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "dcs_enumerate": (_i, [_vp, _u64, _sz, _vp, _vp]),

@@ -37,7 +37,8 @@ namespace dcs {
 constexpr int kMaxSub = DCS_MAX_SUBSYSTEMS;
 constexpr int kMaxSites = DCS_MAX_SITES;
 constexpr int kMaxBonds = DCS_MAX_BONDS;
-constexpr int kMaxWordBits = 14;
+constexpr int kMaxWordBits = 16;       // inverse tables hold words in 16 bits
+constexpr uint64_t kMaxClassWords = 1u << 14;  // decode: the quotient index_k stays below 2^14
 constexpr size_t kLdsTableBudget = 112 * 1024;
 constexpr int kMaxDevices = 64;
 
@@ -235,6 +236,7 @@ struct dcs_sector {
     int device;
     int split[dcs::kMaxSub];
     bool wide;  // 64-bit indices (dim >= 2^32)
+    bool gtab;  // tables beyond the LDS budget: kernels read them in device memory
     dcs::SectorDesc desc;
     dcs::SectorDev dev;
     dcs::LeftInfo left;

@@ -212,6 +212,7 @@ int tuned_form(dcs_sector *s, const dcs_terms *t, const SplitRows &c, const doub
     int last = -1;
     for (int f = 0; f < kNumForms && !r; ++f) {
         if (f == kFormSplitTiled && !tiled_applies(c, dtype, k)) continue;
+        if (f == kFormSingle && s->gtab && k > 1) continue;  // no one-pass block kernel without LDS tables
         last = f;
         float ms = 0.f;
         for (int rep = 0; rep < 2 && !r; ++rep) {

@@ -393,17 +393,19 @@ struct CoeffLds {
     }
 };
 
-template <typename IdxT, typename T, int K, int NMAX, bool Q2>
+// GT: the sector's tables stay in device memory (too large for LDS); LDS holds
+// the coefficients only.
+template <typename IdxT, typename T, int K, int NMAX, bool Q2, bool GT = false>
 __global__ __launch_bounds__(kHxThreads) void hx_kernel(const HxParams P_arg) {
     (void)P_arg;
     const HxParams &P = kernel_arg0<HxParams>();
     extern __shared__ __align__(16) char lds[];
     const SectorDesc &sd = P.sd;
-    stage_blob(lds, P.blob, sd.lay_bytes);
-    const CoeffLds<T> C(lds, sd.lay_bytes);
+    if constexpr (!GT) stage_blob(lds, P.blob, sd.lay_bytes);
+    const CoeffLds<T> C(lds, GT ? 0u : sd.lay_bytes);
     stage_coefficients<T, Q2>(P, sd, C.bamp, C.bjz, C.ladder, C.hf);
     __syncthreads();
-    const Tables<IdxT> Tb = tables_at<IdxT>(lds, sd);
+    const Tables<IdxT> Tb = tables_at<IdxT>(GT ? P.blob : lds, sd);
     const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
     T *__restrict__ y = reinterpret_cast<T *>(P.y);
     const uint64_t wrow = (uint64_t)(threadIdx.x >> 6) * 64;
@@ -699,13 +701,14 @@ struct AdjLoop {
 // workgroup adds the slices in wave order and writes one partial row.  A tile is
 // kHxThreads * R rows; wave w takes R consecutive 64-row pieces of it.  GX: the
 // kernel also computes grad_x = H g (else only the sums: no gathers of g).
-template <typename IdxT, typename T, int NMAX, bool Q2, bool GX, int KC = 1>
+// GT: the sector's tables stay in device memory (LDS holds the rest).
+template <typename IdxT, typename T, int NMAX, bool Q2, bool GX, int KC = 1, bool GT = false>
 __device__ __forceinline__ void adjoint_body(const HxParams &P, char *lds) {
     static_assert(!GX || KC == 1, "grad_x of a block comes from the block product");
     constexpr int R = adj_rows<IdxT, NMAX>();
     const SectorDesc &sd = P.sd;
-    stage_blob(lds, P.blob, sd.lay_bytes);
-    T *bamp = reinterpret_cast<T *>(lds + sd.lay_bytes);
+    if constexpr (!GT) stage_blob(lds, P.blob, sd.lay_bytes);
+    T *bamp = reinterpret_cast<T *>(lds + (GT ? 0u : sd.lay_bytes));
     T *bjz = bamp + kMaxBonds;
     T *ladder = bjz + kMaxBonds;
     T *hf = ladder + 48;
@@ -718,7 +721,7 @@ __device__ __forceinline__ void adjoint_body(const HxParams &P, char *lds) {
     for (int t = threadIdx.x; t < P.nbonds; t += blockDim.x) borig[t] = (int)(P.pos[t] >> 16);
     __syncthreads();
     double *wacc = wacc_all + wave * nacc;
-    const Tables<IdxT> Tb = tables_at<IdxT>(lds, sd);
+    const Tables<IdxT> Tb = tables_at<IdxT>(GT ? P.blob : lds, sd);
     const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
     const T *__restrict__ g = reinterpret_cast<const T *>(P.g);
     T *__restrict__ gx = reinterpret_cast<T *>(P.gx);
@@ -795,20 +798,20 @@ __device__ __forceinline__ void adjoint_body(const HxParams &P, char *lds) {
 // The fused adjoint (grad_x and the sums), used where the single pass is the
 // faster product, i.e. on sectors whose tables leave room for eight waves per
 // SIMD: the register budget is set for that occupancy.
-template <typename IdxT, typename T, int NMAX, bool Q2>
+template <typename IdxT, typename T, int NMAX, bool Q2, bool GT = false>
 __global__ __launch_bounds__(kHxThreads) __attribute__((amdgpu_waves_per_eu(8))) void
 adjoint_kernel(const HxParams P_arg) {
     (void)P_arg;
     extern __shared__ __align__(16) char lds[];
-    adjoint_body<IdxT, T, NMAX, Q2, true>(kernel_arg0<HxParams>(), lds);
+    adjoint_body<IdxT, T, NMAX, Q2, true, 1, GT>(kernel_arg0<HxParams>(), lds);
 }
 
 // The sums only (grad_x comes from the split product).
-template <typename IdxT, typename T, int NMAX, bool Q2, int KC = 1>
+template <typename IdxT, typename T, int NMAX, bool Q2, int KC = 1, bool GT = false>
 __global__ __launch_bounds__(kHxThreads) void adjoint_sums_kernel(const HxParams P_arg) {
     (void)P_arg;
     extern __shared__ __align__(16) char lds[];
-    adjoint_body<IdxT, T, NMAX, Q2, false, KC>(kernel_arg0<HxParams>(), lds);
+    adjoint_body<IdxT, T, NMAX, Q2, false, KC, GT>(kernel_arg0<HxParams>(), lds);
 }
 
 // Deterministic second stage: one workgroup of kAdjReduceThreads per sum; each
@@ -897,6 +900,29 @@ inline size_t coeff_lds_bytes() {
 
 template <typename IdxT, typename T, int K, int NMAX>
 int launch_hx_t(const dcs_sector *s, HxParams &P, hipStream_t stream) {
+    if (s->gtab) {  // tables in device memory: the one-column pass only
+        if constexpr (K == 1) {
+            const size_t lds = coeff_lds_bytes<T>();
+            const Grid g = plan_grid(s, lds);
+            P.tiles = g.tiles;
+            P.xcd_groups = g.xcd_groups;
+            P.counters = nullptr;
+            P.per_xcd = 0;
+            if (g.xcd_groups && s->dev.counters) {
+                P.counters = s->dev.counters;
+                P.per_xcd = (g.tiles + 7) / 8;
+                zero_counters<0><<<1, 64, 0, stream>>>(P.counters, 8);
+            }
+            auto kern = s->desc.Q == 2 ? hx_kernel<IdxT, T, K, NMAX, true, true> : hx_kernel<IdxT, T, K, NMAX, false, true>;
+            if (int r = ensure_lds(kern, lds)) return r;
+            kern<<<g.wgs, kHxThreads, lds, stream>>>(P);
+            return check_hip(hipGetLastError(), "H*x kernel launch (tables in device memory)");
+        } else {
+            return set_error(DCS_EUNSUPPORTED,
+                             "a block of %d columns on a sector whose tables are in device memory needs the split "
+                             "product (Q = 2, runs below 65535 rows)", K);
+        }
+    }
     const size_t lds = s->desc.lay_bytes + coeff_lds_bytes<T>();
     const Grid g = plan_grid(s, lds);
     P.tiles = g.tiles;
@@ -923,7 +949,7 @@ int launch_hx_t(const dcs_sector *s, HxParams &P, hipStream_t stream) {
 // LDS of the adjoint kernel: tables, coefficients, one accumulator slice per
 // wave, the bond index of every plan slot.
 inline size_t adj_lds_bytes(const dcs_sector *s, int nbonds, size_t coeff_bytes) {
-    return s->desc.lay_bytes + coeff_bytes +
+    return (s->gtab ? 0 : s->desc.lay_bytes) + coeff_bytes +
            (size_t)(kHxThreads / 64) * (2 * nbonds + s->desc.L) * sizeof(double) +
            (size_t)kMaxBonds * sizeof(int);
 }
@@ -933,6 +959,9 @@ inline size_t adj_lds_bytes(const dcs_sector *s, int nbonds, size_t coeff_bytes)
 template <typename IdxT, typename T, int NMAX, int KC = 1>
 int launch_adj_t(const dcs_sector *s, HxParams &P, double *gjxy, double *gjz, double *gh,
                         hipStream_t stream) {
+    if (s->gtab && KC > 1)
+        return set_error(DCS_EUNSUPPORTED,
+                         "the adjoint of a block of %d columns needs the sector's tables in LDS", KC);
     const int nacc = 2 * P.nbonds + s->desc.L;
     const size_t lds = adj_lds_bytes(s, P.nbonds, coeff_lds_bytes<T>());
     const Grid g = plan_grid(s, adj_lds_bytes(s, P.nbonds, coeff_lds_bytes<double>()),
@@ -942,10 +971,16 @@ int launch_adj_t(const dcs_sector *s, HxParams &P, double *gjxy, double *gjz, do
     P.want_fields = gh != nullptr;
     void (*kern)(const HxParams);
     if constexpr (KC == 1) {
-        kern = s->desc.Q == 2 ? (P.gx ? adjoint_kernel<IdxT, T, NMAX, true>
-                                      : adjoint_sums_kernel<IdxT, T, NMAX, true>)
-                              : (P.gx ? adjoint_kernel<IdxT, T, NMAX, false>
-                                      : adjoint_sums_kernel<IdxT, T, NMAX, false>);
+        if (s->gtab)
+            kern = s->desc.Q == 2 ? (P.gx ? adjoint_kernel<IdxT, T, NMAX, true, true>
+                                          : adjoint_sums_kernel<IdxT, T, NMAX, true, 1, true>)
+                                  : (P.gx ? adjoint_kernel<IdxT, T, NMAX, false, true>
+                                          : adjoint_sums_kernel<IdxT, T, NMAX, false, 1, true>);
+        else
+            kern = s->desc.Q == 2 ? (P.gx ? adjoint_kernel<IdxT, T, NMAX, true>
+                                          : adjoint_sums_kernel<IdxT, T, NMAX, true>)
+                                  : (P.gx ? adjoint_kernel<IdxT, T, NMAX, false>
+                                          : adjoint_sums_kernel<IdxT, T, NMAX, false>);
     } else {
         if (P.gx) return set_error(DCS_EINVAL, "internal: block adjoint with grad_x in the sums pass");
         kern = s->desc.Q == 2 ? adjoint_sums_kernel<IdxT, T, NMAX, true, KC>

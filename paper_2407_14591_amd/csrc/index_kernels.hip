@@ -1,7 +1,8 @@
 // Batched rank (Alg. i), unrank (Alg. iii) and enumeration of a sector.
 //
 // Persistent grid-stride kernels: every workgroup stages the sector's tables
-// into LDS once, then each thread handles one item per iteration.  Invalid
+// into LDS once (GT: tables too large for LDS are read in device memory), then
+// each thread handles one item per iteration.  Invalid
 // items are counted with one atomic per wavefront (ballot + popcount).
 #include "device_common.h"
 
@@ -16,7 +17,7 @@ __device__ __forceinline__ void count_bad(uint64_t *nbad, bool bad) {
     if (mask && (threadIdx.x % warpSize) == 0) atomicAdd((unsigned long long *)nbad, (unsigned long long)__popcll(mask));
 }
 
-template <typename IdxT>
+template <typename IdxT, bool GT>
 __global__ __launch_bounds__(kThreads) void rank_kernel(SectorDesc sd_arg, const char *blob,
                                                         const uint64_t *__restrict__ st,
                                                         uint64_t *__restrict__ out, size_t count,
@@ -24,9 +25,11 @@ __global__ __launch_bounds__(kThreads) void rank_kernel(SectorDesc sd_arg, const
     (void)sd_arg;
     const SectorDesc &sd = kernel_arg0<SectorDesc>();
     extern __shared__ __align__(16) char lds[];
-    stage_blob(lds, blob, sd.lay_bytes);
-    __syncthreads();
-    const Tables<IdxT> T = tables_at<IdxT>(lds, sd);
+    if constexpr (!GT) {
+        stage_blob(lds, blob, sd.lay_bytes);
+        __syncthreads();
+    }
+    const Tables<IdxT> T = tables_at<IdxT>(GT ? blob : lds, sd);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t base = (size_t)blockIdx.x * blockDim.x; base < count; base += stride) {
         const size_t i = base + threadIdx.x;
@@ -40,7 +43,7 @@ __global__ __launch_bounds__(kThreads) void rank_kernel(SectorDesc sd_arg, const
     }
 }
 
-template <typename IdxT>
+template <typename IdxT, bool GT>
 __global__ __launch_bounds__(kThreads) void unrank_kernel(SectorDesc sd_arg, const char *blob,
                                                           const uint64_t *__restrict__ idx,
                                                           uint64_t *__restrict__ out, size_t count,
@@ -49,9 +52,11 @@ __global__ __launch_bounds__(kThreads) void unrank_kernel(SectorDesc sd_arg, con
     (void)sd_arg;
     const SectorDesc &sd = kernel_arg0<SectorDesc>();
     extern __shared__ __align__(16) char lds[];
-    stage_blob(lds, blob, sd.lay_bytes);
-    __syncthreads();
-    const Tables<IdxT> T = tables_at<IdxT>(lds, sd);
+    if constexpr (!GT) {
+        stage_blob(lds, blob, sd.lay_bytes);
+        __syncthreads();
+    }
+    const Tables<IdxT> T = tables_at<IdxT>(GT ? blob : lds, sd);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t base = (size_t)blockIdx.x * blockDim.x; base < count; base += stride) {
         const size_t i = base + threadIdx.x;
@@ -77,52 +82,43 @@ int grid_for(const dcs_sector *s, size_t count) {
 int launch_rank(const dcs_sector *s, const uint64_t *st, uint64_t *idx, size_t count,
                 uint64_t *nbad, hipStream_t stream) {
     DeviceGuard g(s->device);
-    if (int r = s->wide ? ensure_lds(rank_kernel<uint64_t>, s->desc.lay_bytes)
-                        : ensure_lds(rank_kernel<uint32_t>, s->desc.lay_bytes))
-        return r;
     const int grid = grid_for(s, count);
     const char *blob = (const char *)s->dev.base;
-    if (s->wide)
-        rank_kernel<uint64_t><<<grid, kThreads, s->desc.lay_bytes, stream>>>(s->desc, blob, st, idx,
-                                                                              count, nbad);
-    else
-        rank_kernel<uint32_t><<<grid, kThreads, s->desc.lay_bytes, stream>>>(s->desc, blob, st, idx,
-                                                                              count, nbad);
-    return check_hip(hipGetLastError(), "rank kernel launch");
+    const size_t lds = s->gtab ? 0 : s->desc.lay_bytes;  // tables in LDS or in device memory
+    auto go = [&](auto kern) -> int {
+        if (int r = ensure_lds(kern, lds)) return r;
+        kern<<<grid, kThreads, lds, stream>>>(s->desc, blob, st, idx, count, nbad);
+        return check_hip(hipGetLastError(), "rank kernel launch");
+    };
+    if (s->wide) return s->gtab ? go(rank_kernel<uint64_t, true>) : go(rank_kernel<uint64_t, false>);
+    return s->gtab ? go(rank_kernel<uint32_t, true>) : go(rank_kernel<uint32_t, false>);
+}
+
+// unrank of idx[0..count) (use_first = 0) or of first, first + 1, ... (enumerate)
+static int launch_unrank_any(const dcs_sector *s, const uint64_t *idx, uint64_t *st, size_t count,
+                             uint64_t first, int use_first, uint64_t *nbad, hipStream_t stream,
+                             const char *what) {
+    DeviceGuard g(s->device);
+    const int grid = grid_for(s, count);
+    const char *blob = (const char *)s->dev.base;
+    const size_t lds = s->gtab ? 0 : s->desc.lay_bytes;
+    auto go = [&](auto kern) -> int {
+        if (int r = ensure_lds(kern, lds)) return r;
+        kern<<<grid, kThreads, lds, stream>>>(s->desc, blob, idx, st, count, first, use_first, nbad);
+        return check_hip(hipGetLastError(), what);
+    };
+    if (s->wide) return s->gtab ? go(unrank_kernel<uint64_t, true>) : go(unrank_kernel<uint64_t, false>);
+    return s->gtab ? go(unrank_kernel<uint32_t, true>) : go(unrank_kernel<uint32_t, false>);
 }
 
 int launch_unrank(const dcs_sector *s, const uint64_t *idx, uint64_t *st, size_t count,
                   uint64_t *nbad, hipStream_t stream) {
-    DeviceGuard g(s->device);
-    if (int r = s->wide ? ensure_lds(unrank_kernel<uint64_t>, s->desc.lay_bytes)
-                        : ensure_lds(unrank_kernel<uint32_t>, s->desc.lay_bytes))
-        return r;
-    const int grid = grid_for(s, count);
-    const char *blob = (const char *)s->dev.base;
-    if (s->wide)
-        unrank_kernel<uint64_t><<<grid, kThreads, s->desc.lay_bytes, stream>>>(
-            s->desc, blob, idx, st, count, 0, 0, nbad);
-    else
-        unrank_kernel<uint32_t><<<grid, kThreads, s->desc.lay_bytes, stream>>>(
-            s->desc, blob, idx, st, count, 0, 0, nbad);
-    return check_hip(hipGetLastError(), "unrank kernel launch");
+    return launch_unrank_any(s, idx, st, count, 0, 0, nbad, stream, "unrank kernel launch");
 }
 
 int launch_enumerate(const dcs_sector *s, uint64_t first, size_t count, uint64_t *st,
                      hipStream_t stream) {
-    DeviceGuard g(s->device);
-    if (int r = s->wide ? ensure_lds(unrank_kernel<uint64_t>, s->desc.lay_bytes)
-                        : ensure_lds(unrank_kernel<uint32_t>, s->desc.lay_bytes))
-        return r;
-    const int grid = grid_for(s, count);
-    const char *blob = (const char *)s->dev.base;
-    if (s->wide)
-        unrank_kernel<uint64_t><<<grid, kThreads, s->desc.lay_bytes, stream>>>(
-            s->desc, blob, nullptr, st, count, first, 1, nullptr);
-    else
-        unrank_kernel<uint32_t><<<grid, kThreads, s->desc.lay_bytes, stream>>>(
-            s->desc, blob, nullptr, st, count, first, 1, nullptr);
-    return check_hip(hipGetLastError(), "enumerate kernel launch");
+    return launch_unrank_any(s, nullptr, st, count, first, 1, nullptr, stream, "enumerate kernel launch");
 }
 
 }  // namespace dcs

@@ -193,6 +193,9 @@ extern "C" int dcs_plan_create(int nsec, dcs_sector *const *secs, dcs_terms *con
         if (t->num_bonds > 0 && (!jxy[s] || !jz[s]))
             return set_error(DCS_EINVAL, "NULL couplings at %d", s);
         if (sec->desc.N > 4) nmax = 8;
+        if (sec->left.K > 0 && sec->desc.Q == 2) continue;  // a product of its own, outside the launch
+        if (sec->gtab)
+            return set_error(DCS_EUNSUPPORTED, "plan sector %d: tables in device memory and no split view", s);
         lds = std::max(lds, (size_t)sec->desc.lay_bytes + coeff_lds_bytes<double>());
     }
     for (int s = 0; s < nsec; ++s) {

@@ -434,6 +434,12 @@ extern "C" int dcs_sector_create(int L, int n, int Q, int N, const int *sizes, i
 
     DimTable Dt;
     if (!Dt.build(Q, L)) return set_error(DCS_EUNSUPPORTED, "sector dimensions exceed 2^63");
+    for (int k = 0; k < N; ++k)
+        for (int m = 0; m <= (Q - 1) * split[k]; ++m)
+            if (Dt.get(split[k], m) > kMaxClassWords)
+                return set_error(DCS_EUNSUPPORTED, "subsystem %d has %llu words of digit sum %d > %llu", k,
+                                 (unsigned long long)Dt.get(split[k], m), m,
+                                 (unsigned long long)kMaxClassWords);
     dcs_sector *s = new (std::nothrow) dcs_sector();
     if (!s) return set_error(DCS_ENOMEM, "host allocation failed");
     s->device = device;
@@ -479,9 +485,9 @@ extern "C" int dcs_sector_create(int L, int n, int Q, int N, const int *sizes, i
         if (!r) r = upload(s, ht);
         if (!r) r = build_left(Dt, s, ht, split);
     }
-    if (!r && s->dev.lds_bytes > kLdsTableBudget)
-        r = set_error(DCS_EUNSUPPORTED, "sector tables need %zu bytes > %zu of on-chip memory",
-                      s->dev.lds_bytes, kLdsTableBudget);
+    // tables beyond the on-chip budget (or DCS_GLOBAL_TABLES=1) stay in device memory
+    const char *gt = getenv("DCS_GLOBAL_TABLES");
+    s->gtab = s->dev.lds_bytes > kLdsTableBudget || (gt && gt[0] == '1');
     if (r) {
         if (s->dev.base) hipFree(s->dev.base);
         if (s->dev.counters) hipFree(s->dev.counters);
@@ -514,6 +520,14 @@ extern "C" int dcs_sector_dim(const dcs_sector *s, uint64_t *dim) {
     clear_error();
     if (!s || !dim) return set_error(DCS_EINVAL, "NULL argument");
     *dim = s->desc.dim;
+    return DCS_OK;
+}
+
+extern "C" int dcs_sector_tables(const dcs_sector *s, int *in_device_memory, size_t *bytes) {
+    clear_error();
+    if (!s) return set_error(DCS_EINVAL, "sector is NULL");
+    if (in_device_memory) *in_device_memory = s->gtab ? 1 : 0;
+    if (bytes) *bytes = s->dev.lds_bytes;
     return DCS_OK;
 }
 

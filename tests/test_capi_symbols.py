@@ -59,8 +59,10 @@ def test_host_side_errors(lib):
     assert l.dcs_sector_create(10, 11, 2, 0, None, 0, C.byref(out)) == _lib.DCS_EINVAL
     sizes = (C.c_int * 2)(4, 5)
     assert l.dcs_sector_create(10, 5, 2, 2, sizes, 0, C.byref(out)) == _lib.DCS_EINVAL
-    sizes = (C.c_int * 2)(5, 15)
+    sizes = (C.c_int * 2)(3, 17)  # a 17-bit subsystem word
     assert l.dcs_sector_create(20, 5, 2, 2, sizes, 0, C.byref(out)) == _lib.DCS_EUNSUPPORTED
+    sizes = (C.c_int * 2)(4, 8)  # Q = 3: an 8-site word of 16 bits (at most 1,107 words per digit sum)
+    assert l.dcs_sector_create(12, 5, 3, 2, sizes, 0, C.byref(out)) != _lib.DCS_EUNSUPPORTED
     si = (C.c_int32 * 2)(0, 1)
     sj = (C.c_int32 * 2)(1, 1)
     assert l.dcs_terms_create(2, si, sj, C.byref(out)) == _lib.DCS_EINVAL

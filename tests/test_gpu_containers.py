@@ -1,0 +1,136 @@
+"""Sectors whose index tables stay in device memory (table placement, Sec. 4.2
+containers and Sec. 4.3's choice of the number of subsystems): the 16/16 and
+10/11/11 splits of L = 32, whose tables exceed the on-chip budget, and small
+sectors forced there (DCS_GLOBAL_TABLES=1 at creation).  Against the C oracle:
+rank and unrank bit-exact on 2^20 random states; H*x on sampled rows at L = 32
+and on all rows at L = 24; the adjoint on the split tables; the calls that need
+tables in LDS refuse with DcsError."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2407_14591_amd as dq
+import synth
+from gpu_common import DEV, rel_err, say, to_dev, to_host_u64
+from oracle import native
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+
+
+def dev_f64(a):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device=DEV)
+
+
+def sampled_rows(dim, count, seed):
+    rng = np.random.default_rng(seed)
+    parts = [np.arange(0, 4096, dtype=np.uint64), np.arange(dim - 4096, dim, dtype=np.uint64),
+             rng.integers(0, dim, count).astype(np.uint64)]
+    return np.unique(np.concatenate(parts))
+
+
+@pytest.fixture(scope="module")
+def x32():
+    """The L=32, n=16 FP64 input (one seeded vector; each split reads it in its own order)."""
+    return synth.vector(601080390, synth.SEED_X, np.float64)
+
+
+@pytest.mark.parametrize("split", [[16, 16], [10, 11, 11]])
+def test_device_tables_L32_rank_unrank(split):
+    L, n = 32, 16
+    s = dq.Sector(L, n, 2, split)
+    assert s.dim == 601080390
+    ns = native.NativeSector(2, L, n, split)
+    st = synth.pack_digits(synth.random_states(2, L, n, 1 << 20, seed=11), 2)
+    ref = ns.rank(st)
+    idx = s.rank(to_dev(st))
+    got = to_host_u64(idx)
+    say("rank", split, int((got != ref).sum()))
+    assert np.array_equal(got, ref)
+    back = s.unrank(idx)
+    assert np.array_equal(to_host_u64(back), st)
+    # the ends of the canonical order and a ragged enumeration
+    ends = np.array([0, 1, s.dim - 2, s.dim - 1], dtype=np.uint64)
+    assert np.array_equal(to_host_u64(s.unrank(to_dev(ends))), ns.unrank(ends))
+    first = s.dim - 1000
+    assert np.array_equal(to_host_u64(s.enumerate(first, 1000)), ns.unrank(np.arange(first, s.dim, dtype=np.uint64)))
+    # states outside the sector
+    bad = st.copy()
+    bad[:100] ^= np.uint64(1)  # one site flipped: digit sum n +- 1
+    _, nbad = s.rank(to_dev(bad), count_invalid=True)
+    assert int(nbad.item()) == 100
+
+
+@pytest.mark.parametrize("split", [[16, 16], [10, 11, 11]])
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_device_tables_L32_product_sampled(x32, split, dt):
+    """J1-J2 (J2 = 0.5), k = 1: 16/16 runs the split product, 10/11/11 (runs of up
+    to 705,432 rows) the one-pass kernel reading its tables in device memory."""
+    L, n = 32, 16
+    s = dq.Sector(L, n, 2, split)
+    ns = native.NativeSector(2, L, n, split)
+    bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.5, 1.0)
+    t = dq.Terms(bonds)
+    rows = sampled_rows(s.dim, 200_000, 9)
+    y_ref = native.hx_rows(ns, native.NativeTerms(bonds, jxy, jz), x32, rows)
+    y = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), torch.from_numpy(x32).to(DEV).to(dt))
+    got = y[torch.tensor(rows.astype(np.int64), device=DEV)].double().cpu().numpy()
+    err = rel_err(got, y_ref)
+    say("L32", split, dt, dq.hamiltonian_form(s, t, dt, 1), "rel err", err)
+    assert err <= TOL[dt]
+
+
+@pytest.mark.parametrize("split", [[12, 12], [8, 8, 8], [6, 6, 6, 6]])
+@pytest.mark.parametrize("k", [1, 8])
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_forced_device_tables_L24_all_rows(monkeypatch, split, k, dt):
+    """L = 24, n = 12 with tables forced into device memory, every row against the
+    oracle; k = 8 needs the split product, which every split here has."""
+    monkeypatch.setenv("DCS_GLOBAL_TABLES", "1")
+    L, n = 24, 12
+    s = dq.Sector(L, n, 2, split)
+    ns = native.NativeSector(2, L, n, split)
+    bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.5, 1.0)
+    h = np.linspace(-0.5, 0.5, L)
+    x = synth.vector(s.dim, synth.SEED_X, np.float64, k=k)
+    y_ref = native.hx_range(ns, native.NativeTerms(bonds, jxy, jz, h), x)
+    y = dq.hamiltonian_apply(s, dq.Terms(bonds), dev_f64(jxy), dev_f64(jz), torch.from_numpy(x).to(DEV).to(dt),
+                             h=dev_f64(h))
+    err = rel_err(y.double().cpu().numpy(), y_ref)
+    say("L24 device tables", split, k, dt, "rel err", err)
+    assert err <= TOL[dt]
+    st = synth.pack_digits(synth.random_states(2, L, n, 1 << 16, seed=5), 2)
+    assert np.array_equal(to_host_u64(s.rank(to_dev(st))), ns.rank(st))
+
+
+def test_device_tables_adjoint_and_refusals(monkeypatch):
+    """The adjoint with tables in device memory (FP32 and FP64, k = 1, every way the
+    autotuner times; the split view exists from 2^20 rows) against the oracle; the
+    calls that need tables in LDS raise DcsError instead of running."""
+    monkeypatch.setenv("DCS_GLOBAL_TABLES", "1")
+    L, n, split = 24, 12, [12, 12]
+    s = dq.Sector(L, n, 2, split)
+    ns = native.NativeSector(2, L, n, split)
+    bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.5, 1.0)
+    t = dq.Terms(bonds)
+    x = synth.vector(s.dim, synth.SEED_X, np.float32).astype(np.float64)
+    g = synth.vector(s.dim, synth.SEED_G, np.float32).astype(np.float64)
+    gx_ref = native.hx_range(ns, native.NativeTerms(bonds, jxy, jz), g)
+    gj_ref, gz_ref, _ = native.bond_sums(ns, bonds, x, g)
+    xd, gd = (torch.from_numpy(v).to(DEV).float() for v in (x, g))
+    gx, gj, gz, _ = dq.hamiltonian_apply_adjoint(s, t, dev_f64(jxy), dev_f64(jz), xd, gd)
+    errs = [rel_err(gx.double().cpu().numpy(), gx_ref), rel_err(gj.cpu().numpy(), gj_ref),
+            rel_err(gz.cpu().numpy(), gz_ref)]
+    say("adjoint on device tables", errs)
+    assert max(errs) <= 1e-5
+    gx, gj, gz, _ = dq.hamiltonian_apply_adjoint(s, t, dev_f64(jxy), dev_f64(jz), xd.double(), gd.double())
+    errs = [rel_err(gx.cpu().numpy(), gx_ref), rel_err(gj.cpu().numpy(), gj_ref), rel_err(gz.cpu().numpy(), gz_ref)]
+    say("FP64 adjoint on device tables", errs)
+    assert max(errs) <= 1e-12
+    xb = torch.stack([xd, gd], dim=1).repeat(1, 4).contiguous()
+    with pytest.raises(dq.DcsError):  # a block's sums pass needs the tables in LDS
+        dq.hamiltonian_apply_adjoint(s, t, dev_f64(jxy), dev_f64(jz), xb, xb)
+    with pytest.raises(dq.DcsError):  # a plan needs LDS tables for sectors without a split view
+        dq.Plan([(dq.Sector(9, 4, 3, [3, 3, 3]), dq.Terms(synth.chain_bonds(9, 1)),
+                  dev_f64(np.ones(9)), dev_f64(np.ones(9)))])
