@@ -325,11 +325,13 @@ int dcs_expectation_values(const dcs_sector *sector, const dcs_terms *terms, int
  * single persistent launch.  Sector s uses terms[s] with couplings
  * d_jxy[s], d_jz[s] (device FP64 arrays; the pointers are recorded, the
  * values are read at apply time).  The sectors may differ in L, n, Q and
- * split.  Sectors that have a split view (Q = 2, see "Split product") are
- * left out of the launch and run their own product, in the form the autotuner
- * keeps for them (dcs_hamiltonian_apply): after the launch on the caller's
- * stream at the first apply of a dtype, later beside it on three streams of the
- * plan (created with it, default priority), forked from and joined back to the
+ * split.  Every sector is in the one launch, except sectors with a split view
+ * (Q = 2, see "Split product") whose tables are in device memory, or all
+ * sectors with a split view when DCS_PLAN_HYBRID=1 is set at creation: those
+ * run their own product, in the form the autotuner keeps for them
+ * (dcs_hamiltonian_apply): after the launch on the caller's stream at the
+ * first apply of a dtype, later beside it on three streams of the plan
+ * (created with it, default priority), forked from and joined back to the
  * caller's stream with events, so the call is still ordered on that stream.
  * Tiles go to the workgroups through per-XCD counters; every row is written
  * by one thread, so the result does not depend on the schedule.  The plan

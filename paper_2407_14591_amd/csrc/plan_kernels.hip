@@ -131,8 +131,8 @@ struct dcs_plan {
     bool io_pending = false;
     std::vector<uint64_t> dims;
     uint32_t *d_counters = nullptr;  // the tile queue's per-XCD counters
-    // sectors with a split view run their own product after the launch, in the
-    // form the autotuner keeps for them
+    // sectors that run their own product (own_product) after or beside the launch,
+    // in the form the autotuner keeps for them
     struct Own {
         int index;
         dcs_sector *sector;
@@ -173,6 +173,16 @@ static void plan_free(dcs_plan *p) {
     delete p;
 }
 
+// Whether a sector runs its own product beside the launch instead of inside it:
+// only sectors with a split view (Q = 2, the split product) can, and they do when
+// their tables are in device memory (the launch stages tables in LDS) or when
+// DCS_PLAN_HYBRID=1 (read at plan creation).  By default every other sector is in
+// the one launch: for the 101 sectors of L = 20..26 and spin-1 L = 12..16 that
+// is 2.33 ms against 2.39 ms with the 18 largest on their own split products.
+static bool own_product(const dcs_sector *sec, bool hybrid) {
+    return sec->left.K > 0 && sec->desc.Q == 2 && (hybrid || sec->gtab);
+}
+
 extern "C" int dcs_plan_create(int nsec, dcs_sector *const *secs, dcs_terms *const *terms,
                                const double *const *jxy, const double *const *jz, dcs_plan **out) {
     clear_error();
@@ -180,6 +190,8 @@ extern "C" int dcs_plan_create(int nsec, dcs_sector *const *secs, dcs_terms *con
     *out = nullptr;
     if (nsec < 1 || !secs || !terms || !jxy || !jz) return set_error(DCS_EINVAL, "empty plan");
     const int device = secs[0] ? secs[0]->device : 0;
+    const char *hy = getenv("DCS_PLAN_HYBRID");
+    const bool hybrid = hy && hy[0] == '1';
     int nmax = 4;
     size_t lds = 0;
     std::vector<PlanSector> hs(nsec);
@@ -193,7 +205,7 @@ extern "C" int dcs_plan_create(int nsec, dcs_sector *const *secs, dcs_terms *con
         if (t->num_bonds > 0 && (!jxy[s] || !jz[s]))
             return set_error(DCS_EINVAL, "NULL couplings at %d", s);
         if (sec->desc.N > 4) nmax = 8;
-        if (sec->left.K > 0 && sec->desc.Q == 2) continue;  // a product of its own, outside the launch
+        if (own_product(sec, hybrid)) continue;  // a product of its own, outside the launch
         if (sec->gtab)
             return set_error(DCS_EUNSUPPORTED, "plan sector %d: tables in device memory and no split view", s);
         lds = std::max(lds, (size_t)sec->desc.lay_bytes + coeff_lds_bytes<double>());
@@ -214,7 +226,7 @@ extern "C" int dcs_plan_create(int nsec, dcs_sector *const *secs, dcs_terms *con
         ps.far_below = ps.sd.dim >= (1ull << 22) ? ps.sd.N / 2 : 0;  // as for one sector
         for (int c = 0; c <= bp.nclasses; ++c) ps.cls_beg[c] = bp.cls_beg[c];
         for (int b = 0; b < bp.nbonds; ++b) ps.pos[b] = bp.pos[b];
-        if (secs[s]->left.K > 0 && secs[s]->desc.Q == 2) continue;  // a product of its own
+        if (own_product(secs[s], hybrid)) continue;  // a product of its own
         for (uint64_t r0 = 0; r0 < ps.sd.dim; r0 += kHxThreads) tiles.push_back(make_uint2(s, (uint32_t)r0));
     }
     dcs_plan *p = new (std::nothrow) dcs_plan();
@@ -231,7 +243,7 @@ extern "C" int dcs_plan_create(int nsec, dcs_sector *const *secs, dcs_terms *con
     int distinct = 0;
     for (int s = 0; s < nsec; ++s) {
         p->dims.push_back(secs[s]->desc.dim);
-        if (secs[s]->left.K > 0 && secs[s]->desc.Q == 2) {
+        if (own_product(secs[s], hybrid)) {
             int side = -1;
             for (const auto &o : p->own)
                 if (o.sector == secs[s]) side = o.side;

@@ -101,8 +101,10 @@ def test_plan_rejects_bad_outputs(small):
 
 def test_plan_repeated_split_sector(monkeypatch):
     """One split-view sector listed three times (two terms objects, three coupling sets)
-    next to an ordinary sector; from the second apply on the split products run on the
-    plan's side streams.  Every apply equals the one-sector products bit for bit."""
+    next to an ordinary sector, with the split products beside the launch
+    (DCS_PLAN_HYBRID=1); from the second apply on they run on the plan's side
+    streams.  Every apply equals the one-sector products bit for bit."""
+    monkeypatch.setenv("DCS_PLAN_HYBRID", "1")
     monkeypatch.setenv("DCS_SPLIT_MIN_DIM", "0")
     L, n = 20, 10
     s = dq.Sector(L, n, 2, [5, 5, 5, 5])

@@ -86,11 +86,15 @@ def test_batched_workload_one_launch(monkeypatch):
         assert rel_err(got, ref) <= 1e-5
 
 
-def test_batched_workload_with_split_sectors():
-    """The batched workload with the default split threshold: the sectors of at least
-    2^20 states run their own split product after the one launch; every sector's y
-    equals its own product bit for bit, and sampled rows of those sectors match the
-    oracle."""
+@pytest.mark.parametrize("hybrid", [False, True])
+def test_batched_workload_with_split_sectors(monkeypatch, hybrid):
+    """The batched workload with the default split threshold.  By default every
+    sector is in the one launch; every sector's y equals its one-pass product
+    (DCS_SPLIT=0) bit for bit.  With DCS_PLAN_HYBRID=1 the sectors of at least 2^20
+    states run their own split product beside the launch; every sector's y equals
+    its own product bit for bit.  Sampled rows of those sectors match the oracle."""
+    if hybrid:
+        monkeypatch.setenv("DCS_PLAN_HYBRID", "1")
     specs = batched_workload()
     items, xs = [], []
     for Q, L, n in specs:
@@ -105,6 +109,8 @@ def test_batched_workload_with_split_sectors():
     ys2 = plan.apply(xs)
     torch.cuda.synchronize()
     rng = np.random.default_rng(5)
+    if not hybrid:
+        monkeypatch.setenv("DCS_SPLIT", "0")  # the per-sector products in the launch's (one-pass) form
     for idx, ((s, t, j, z), x, y, y2) in enumerate(zip(items, xs, ys, ys2)):
         assert torch.equal(y, y2)
         assert torch.equal(y, dq.hamiltonian_apply(s, t, j, z, x)), specs[idx]
@@ -118,10 +124,11 @@ def test_batched_workload_with_split_sectors():
             assert rel_err(got, ref) <= 1e-5, specs[idx]
 
 
-def test_split_sectors_alternating_dtypes():
-    """Applies of one plan alternating FP32 and FP64 (the first of each dtype on the
-    caller's stream, later ones with the split sectors on the plan's streams): every
-    sector's y equals its own product bit for bit, every time."""
+def test_split_sectors_alternating_dtypes(monkeypatch):
+    """Applies of one plan (DCS_PLAN_HYBRID=1) alternating FP32 and FP64 (the first
+    of each dtype on the caller's stream, later ones with the split sectors on the
+    plan's streams): every sector's y equals its own product bit for bit, every time."""
+    monkeypatch.setenv("DCS_PLAN_HYBRID", "1")
     specs = [(2, 24, n) for n in (9, 12, 15)] + [(2, 22, n) for n in range(0, 23, 4)] + [(3, 12, 12)]
     items = []
     for Q, L, n in specs:
