@@ -40,7 +40,9 @@
  *    product runs three kernels: the diagonal per configuration of each side,
  *    one pass over the rows for the bonds right of and across the cut, and one
  *    over column chunks for the bonds left of it (or, in the fused form, two:
- *    the row pass also applies the bonds left of the cut).  DCS_SPLIT_MIN_DIM
+ *    the row pass also applies the bonds left of the cut).  Target offsets
+ *    inside a run are 16-bit for runs below 65,535 rows and 32-bit for longer
+ *    runs (up to 2^25 rows; beyond that the single pass runs).  DCS_SPLIT_MIN_DIM
  *    (read by dcs_sector_create) changes the 2^20 threshold; DCS_SPLIT=0 (read
  *    at every product) forces the single pass; DCS_SPLIT_LDS=0 (likewise) keeps
  *    the row pass from staging runs of x in on-chip memory; DCS_SPLIT_FUSED=1

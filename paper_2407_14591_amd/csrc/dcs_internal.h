@@ -165,6 +165,8 @@ struct SplitRows {
     uint32_t *d_lptr = nullptr;      // left family: entry range of every left configuration
     uint64_t *d_lent = nullptr;      // target run start (low 48 bits) | bond << 48, or, for a target
                                      // in the own cluster, 1 << 63 | bond << 48 | index in the cluster
+    bool wide_off = false;           // runs of 65,535 rows or more: 32-bit entries in vo / xo,
+                                     // four per 16-byte row ([group][r][4]), 0xFFFFFFFF = no hop
     uint16_t *d_vo = nullptr;        // right family: [bond group][right configuration][8] target
                                      // offset in the run, 0xFFFF where the bond does not hop
     uint64_t *d_xl = nullptr;        // crossing: [left site slot][left configuration] run start of

@@ -146,7 +146,7 @@ enum Form {
 // The block-tiled row pass exists for rows of 16 to 64 bytes with a tiling.
 bool tiled_applies(const SplitRows &c, int dtype, int k) {
     const int rb = k * (dtype == DCS_F32 ? 4 : 8);
-    if (rb < 16 || rb > 64) return false;
+    if (rb < 16 || rb > 64 || c.wide_off) return false;  // the tiled pass reads 16-bit offsets
     return c.tiling[rb == 16 ? 0 : (rb == 32 ? 1 : 2)].ntiles > 0;
 }
 
@@ -247,7 +247,7 @@ int hx_form(const dcs_sector *s, const dcs_terms *t, int dtype, int k) {
                   "form codes of the ABI");
     if (!(s->left.K > 0 && s->desc.Q == 2 && split_enabled())) return kFormSingle;
     for (int m = 0; m < s->left.m_count; ++m)
-        if (s->left.ncols[m] >= 0xFFFFu) return kFormSingle;  // offsets of the split tables are 16-bit
+        if (s->left.ncols[m] >= (1u << 25)) return kFormSingle;  // no split tables for such runs
     if (!autotune_enabled()) return default_form();
     std::lock_guard<std::mutex> g(*s->left.rows_lock);
     auto it = s->left.tuned.find(tuned_key(t, dtype, k));

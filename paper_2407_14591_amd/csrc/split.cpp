@@ -3,6 +3,7 @@
 // sector.  Every target is the rank of eq. index of a configuration that one
 // bond reaches, evaluated per side of the cut.
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "dcs_internal.h"
@@ -27,13 +28,17 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
     for (int i = 0; i < kMaxSplitCache; ++i)
         if (li.rows[i].terms_id == t->id) return &li.rows[i];
     const int K = li.K, N = sd.N;
-    for (int mi = 0; mi < li.m_count; ++mi)
-        if (li.ncols[mi] >= 0xFFFFu) return nullptr;  // offsets are 16-bit
+    bool wide = false;  // 32-bit target offsets for runs of 65,535 rows or more
+    for (int mi = 0; mi < li.m_count; ++mi) {
+        if (li.ncols[mi] >= 0xFFFFu) wide = true;
+        if (li.ncols[mi] >= (1u << 25)) return nullptr;  // byte offsets of rows of up to 64 B stay below 2^31
+    }
     auto packed_bit = [&](int site) -> uint8_t {
         return (uint8_t)(li.word_shift[sd.site_sub[site]] + sd.site_bit[site]);
     };
     SplitRows c;
     c.terms_id = t->id;
+    c.wide_off = wide;
     std::vector<SideBond> left, right;
     std::vector<int> lsites, rsites;  // crossing sites per slot
     for (int q = 0; q < t->num_bonds; ++q) {
@@ -188,11 +193,14 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
     lptr[li.count] = (uint32_t)lent.size();
     c.lnnz = lent.size();
 
-    // right family targets and crossing right flips
-    const int nRq = (c.nR + 7) / 8;
-    std::vector<uint16_t> vo((size_t)nRq * li.rcount * 8, 0xFFFFu);
-    const int nJq = (c.nJs + 7) / 8;
-    std::vector<uint16_t> xo((size_t)nJq * li.rcount * 8, 0xFFFFu);
+    // right family targets and crossing right flips: 16-byte rows of eight 16-bit
+    // offsets, or of four 32-bit ones for runs of 65,535 rows or more
+    const int per = wide ? 4 : 8;
+    const uint32_t nohop = wide ? 0xFFFFFFFFu : 0xFFFFu;
+    const int nRq = (c.nR + per - 1) / per;
+    const int nJq = (c.nJs + per - 1) / per;
+    std::vector<uint32_t> vo((size_t)nRq * li.rcount * per, nohop);
+    std::vector<uint32_t> xo((size_t)nJq * li.rcount * per, nohop);
     for (int mi = 0; mi < li.m_count; ++mi) {
         const int m = li.m_lo + mi;
         for (uint64_t r = 0; r < li.ncols[mi]; ++r) {
@@ -209,7 +217,7 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
                 const uint64_t off = rank_part(w2, K, N, m);
                 if (off >= li.ncols[mi])
                     return set_error(DCS_EHIP, "internal: right offset out of its run"), nullptr;
-                vo[((size_t)(b / 8) * li.rcount + g) * 8 + b % 8] = (uint16_t)off;
+                vo[((size_t)(b / per) * li.rcount + g) * per + b % per] = (uint32_t)off;
             }
             for (int sj = 0; sj < c.nJs; ++sj) {
                 const int site = rsites[sj], k = sd.site_sub[site];
@@ -222,7 +230,7 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
                 const uint64_t off = rank_part(w2, K, N, m2);
                 if (off >= li.ncols[m2 - li.m_lo])
                     return set_error(DCS_EHIP, "internal: flipped right configuration"), nullptr;
-                xo[((size_t)(sj / 8) * li.rcount + g) * 8 + sj % 8] = (uint16_t)off;
+                xo[((size_t)(sj / per) * li.rcount + g) * per + sj % per] = (uint32_t)off;
             }
         }
     }
@@ -242,8 +250,12 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
         // tiles of kSplitRowTile rows: each group of left configurations that differ
         // only at the crossing sites (closed under every crossing bond) together,
         // their runs interleaved at equal fractions of their lengths, so that the
-        // crossing targets of the tiles in flight lie in runs being read
-        {
+        // crossing targets of the tiles in flight lie in runs being read.  An entry
+        // keeps the chunk in 8 bits: runs of more than 256 tiles keep the run order.
+        uint64_t max_nsub = 0;
+        for (int mi = 0; mi < li.m_count; ++mi)
+            max_nsub = std::max<uint64_t>(max_nsub, (li.ncols[mi] + kSplitRowTile - 1) / kSplitRowTile);
+        if (max_nsub <= 256 && li.count < (1u << 24)) {
             std::vector<std::pair<double, uint32_t>> grp;
             for (size_t a = 0; a < order.size();) {
                 size_t b = a + 1;
@@ -375,6 +387,20 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
             lrun[q] = (e >> 63) ? ((e & (0xFFull << 48)) | li.h_runs[clstart[cl_of[g]] + (uint32_t)(e & 0xFFFFu)])
                                 : e;
         }
+    // the offset tables in their device width (16 or 32 bits per entry)
+    auto narrow = [&](const std::vector<uint32_t> &v) {
+        std::vector<char> out(v.size() * (wide ? 4 : 2));
+        for (size_t i = 0; i < v.size(); ++i) {
+            if (wide) {
+                memcpy(out.data() + 4 * i, &v[i], 4);
+            } else {
+                const uint16_t h = (uint16_t)v[i];
+                memcpy(out.data() + 2 * i, &h, 2);
+            }
+        }
+        return out;
+    };
+    const std::vector<char> vo_dev = narrow(vo), xo_dev = narrow(xo);
     auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
         if (check_hip(hipMalloc(dst, bytes ? bytes : 16), "hipMalloc split tables")) return false;
         if (bytes && check_hip(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), "copy split tables"))
@@ -383,9 +409,9 @@ SplitRows *split_rows(dcs_sector *s, const dcs_terms *t) {
     };
     bool ok = up((void **)&c.d_lptr, lptr.data(), lptr.size() * sizeof(uint32_t)) &&
               up((void **)&c.d_lent, lent.data(), lent.size() * sizeof(uint64_t)) &&
-              up((void **)&c.d_vo, vo.data(), vo.size() * sizeof(uint16_t)) &&
+              up((void **)&c.d_vo, vo_dev.data(), vo_dev.size()) &&
               up((void **)&c.d_xl, xl.data(), xl.size() * sizeof(uint64_t)) &&
-              up((void **)&c.d_xo, xo.data(), xo.size() * sizeof(uint16_t)) &&
+              up((void **)&c.d_xo, xo_dev.data(), xo_dev.size()) &&
               up((void **)&c.d_runs, li.h_runs.data(), li.h_runs.size() * sizeof(uint64_t)) &&
               up((void **)&c.d_clstart, clstart.data(), clstart.size() * sizeof(uint32_t)) &&
               up((void **)&c.d_clsize, clsize.data(), clsize.size() * sizeof(uint32_t)) &&

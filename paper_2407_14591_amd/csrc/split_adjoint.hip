@@ -122,7 +122,7 @@ inline uint64_t col_tiles(const LeftInfo &li, const SplitRows &c) {
 
 bool split_adjoint_applies(const dcs_sector *s, const SplitRows &c, int dtype) {
     const LeftInfo &li = s->left;
-    if (dtype != DCS_F32 || li.K == 0) return false;
+    if (dtype != DCS_F32 || li.K == 0 || c.wide_off) return false;
     if (c.nR > sp::kAdjR || c.nX > sp::kAdjX || c.nJs > sp::kAdjJ) return false;
     uint64_t max_cols = 0;
     for (int m = 0; m < li.m_count; ++m) max_cols = std::max<uint64_t>(max_cols, li.ncols[m]);

@@ -244,6 +244,35 @@ struct RowBatch {
     static constexpr int X = RB <= 16 ? 8 : 1;                    // across the cut
 };
 
+// Entries of the target tables' 16-byte rows: eight 16-bit offsets (runs below
+// 65,535 rows; 0xFFFF: no hop), or, for longer runs (W32), four 32-bit ones
+// (0xFFFFFFFF: no hop).  byte(): the entry as a byte offset into the run, an
+// offset past every run for "no hop".
+template <bool W32>
+struct OffRow {
+    static constexpr int PER = W32 ? 4 : 8;
+    static constexpr uint32_t NOHOP = W32 ? 0xFFFFFFFFu : 0xFFFFu;
+    static __device__ __forceinline__ uint32_t get(const uint4 &t, int u) {
+        if constexpr (W32) {
+            return u == 0 ? t.x : (u == 1 ? t.y : (u == 2 ? t.z : t.w));
+        } else {
+            const int h = u >> 1;
+            const uint32_t w = h == 0 ? t.x : (h == 1 ? t.y : (h == 2 ? t.z : t.w));
+            return (u & 1) ? (w >> 16) : (w & 0xFFFFu);
+        }
+    }
+    template <uint32_t RB>
+    static __device__ __forceinline__ uint32_t byte(uint32_t off) {
+        if constexpr (W32) return off == NOHOP ? kOob : off * RB;
+        else return off * RB;  // 0xFFFF * RB lies past every run of fewer than 0xFFFF rows
+    }
+    template <uint32_t RB>
+    static __device__ __forceinline__ bool hop(uint32_t ob) {
+        if constexpr (W32) return ob < kOob;
+        else return ob < 0xFFFFu * RB;
+    }
+};
+
 // Rows of x staged in LDS per tile: the tile's rows and `margin` rows on either
 // side (bonds inside the last subsystem never leave that window), then one zero
 // row.  Dwords, or 16-byte pieces when rows are whole 16-byte units.
@@ -277,11 +306,15 @@ __device__ __forceinline__ Acc<T, K> lds_row(const char *lds, uint32_t row) {
 // LEFT: the pass also applies the left family (the fused form, no column pass):
 // a left bond maps the tile's run onto another run of the same block, row r onto
 // row r, so its gathers are contiguous across the wave.
-template <typename T, int K, bool LEFT>
+template <typename T, int K, bool LEFT, bool W32 = false>
 __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_arg) {
     (void)P_arg;
     const RowParams &P = kernel_arg0<RowParams>();
     using B = RowBatch<T, K>;
+    using OR = OffRow<W32>;
+    static_assert(B::R % OR::PER == 0, "whole table rows per batch");
+    const char *vob = reinterpret_cast<const char *>(P.vo);
+    const char *xob = reinterpret_cast<const char *>(P.xo);
     constexpr uint32_t RB = B::RB;
     extern __shared__ __align__(16) char rows_lds[];
     __shared__ T ramp[kAmpCross - kAmpRight];
@@ -304,7 +337,7 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
     }
     const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
     T *__restrict__ y = reinterpret_cast<T *>(P.y);
-    const int nRq = (P.nR + 7) >> 3;
+    const int nRq = (P.nR + OR::PER - 1) / OR::PER;
     AheadQueue Q(P.counters, P.xbase, slots);  // its barrier also publishes the LDS above
     BlockCursor blk(P.tbase, P.m_count);
     uint64_t t;
@@ -338,9 +371,9 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
         uint4 tv0[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            tv0[i] = i < nRq ? *reinterpret_cast<const uint4 *>(P.vo + ((size_t)i * P.rcount + gr) * 8)
+            tv0[i] = i < nRq ? *reinterpret_cast<const uint4 *>(vob + ((size_t)i * P.rcount + gr) * 16)
                              : make_uint4(~0u, ~0u, ~0u, ~0u);
-        const uint4 xw0 = P.nX > 0 ? *reinterpret_cast<const uint4 *>(P.xo + (size_t)gr * 8)
+        const uint4 xw0 = P.nX > 0 ? *reinterpret_cast<const uint4 *>(xob + (size_t)gr * 16)
                                    : make_uint4(~0u, ~0u, ~0u, ~0u);
         // the tile's window of the run in LDS (when bonds inside the last subsystem exist)
         const bool staged = P.nRloc > 0;
@@ -374,13 +407,11 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
                 mx = mx < 0 ? 0 : (mx >= P.m_count ? P.m_count - 1 : mx);
                 const bool valid = Rx != ~0ull;
                 const auto rx = rsrc(x + (valid ? Rx : 0ull) * K, valid ? P.ncols[mx] * RB : 0u);
-                if ((int)(cb.sj >> 3) != xw_group) {  // uniform: table row of this site group
-                    xw_group = cb.sj >> 3;
-                    xw = *reinterpret_cast<const uint4 *>(P.xo + ((size_t)xw_group * P.rcount + gr) * 8);
+                if ((int)(cb.sj / OR::PER) != xw_group) {  // uniform: table row of this site group
+                    xw_group = cb.sj / OR::PER;
+                    xw = *reinterpret_cast<const uint4 *>(xob + ((size_t)xw_group * P.rcount + gr) * 16);
                 }
-                const uint32_t sj = cb.sj & 7u;
-                const uint32_t wsel = sj >> 1 == 0 ? xw.x : (sj >> 1 == 1 ? xw.y : (sj >> 1 == 2 ? xw.z : xw.w));
-                const uint32_t xo = (sj & 1u) ? (wsel >> 16) : (wsel & 0xFFFFu);
+                const uint32_t xo = OR::get(xw, cb.sj % OR::PER);
                 hop[u] = ok && bi != ((rw >> cb.rbit) & 1u);
                 if (__builtin_amdgcn_ballot_w64(active && hop[u])) {
                     xv[u] = buf_load<T, K>(rx, hop[u] ? xo * RB : kOob);
@@ -395,26 +426,24 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
                 diag += hop[u] ? -xjz[x0 + u] : xjz[x0 + u];
             }
         }
-        // right family: B::R targets per batch, 8 per 16-byte table row; bonds
+        // right family: B::R targets per batch, OR::PER per 16-byte table row; bonds
         // [0, nRloc) from the staged window, the others from the run in HBM.  The
-        // first four table rows (32 bonds) were loaded at the start of the tile.
-        for (int q0 = 0; q0 < nRq * 8; q0 += B::R) {
+        // first four table rows were loaded at the start of the tile.
+        for (int q0 = 0; q0 < nRq * OR::PER; q0 += B::R) {
             uint32_t ov[B::R];
 #pragma unroll
-            for (int i = 0; i < B::R / 8; ++i) {
-                const int qr = (q0 >> 3) + i;
+            for (int i = 0; i < B::R / OR::PER; ++i) {
+                const int qr = q0 / OR::PER + i;
                 uint4 tv = make_uint4(~0u, ~0u, ~0u, ~0u);
                 if (qr < 4) {
 #pragma unroll
                     for (int z = 0; z < 4; ++z)
                         if (z == qr) tv = tv0[z];
                 } else if (qr < nRq) {
-                    tv = *reinterpret_cast<const uint4 *>(P.vo + ((size_t)qr * P.rcount + gr) * 8);
+                    tv = *reinterpret_cast<const uint4 *>(vob + ((size_t)qr * P.rcount + gr) * 16);
                 }
-                const uint32_t wv[4] = {tv.x, tv.y, tv.z, tv.w};
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    ov[i * 8 + u] = ((u & 1) ? (wv[u >> 1] >> 16) : (wv[u >> 1] & 0xFFFFu)) * RB;
+                for (int u = 0; u < OR::PER; ++u) ov[i * OR::PER + u] = OR::template byte<RB>(OR::get(tv, u));
             }
             // a bond with no hop on any lane of the wave (frequent for bonds inside
             // the first right subsystem, whose hops are shared by runs of rows) is skipped
@@ -423,9 +452,9 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
             for (int u = 0; u < B::R; ++u) {
                 if (q0 + u < P.nRloc) {
                     const uint32_t e = ov[u] / RB;
-                    const uint32_t wr = (e < s0 || e >= s1) ? zero_row : e - s0;  // 0xFFFF: no hop
+                    const uint32_t wr = (e < s0 || e >= s1) ? zero_row : e - s0;  // no hop: past s1
                     xv[u] = lds_row<T, K>(rows_lds, wr);
-                } else if (__builtin_amdgcn_ballot_w64(active && ov[u] < 0xFFFFu * RB)) {
+                } else if (__builtin_amdgcn_ballot_w64(active && OR::template hop<RB>(ov[u]))) {
                     xv[u] = buf_load<T, K>(rs, ov[u]);
                 } else {
 #pragma unroll
@@ -1285,7 +1314,7 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
         const size_t lds = ((max_cols + 1) * RowBatch<T, K>::RB + 15) / 16 * 16;
         bool staged = false;
         if constexpr (RowBatch<T, K>::RB <= 8) {
-            if (lds <= kRowLdsMax && staged_ok && rows_lds_enabled()) {
+            if (lds <= kRowLdsMax && staged_ok && rows_lds_enabled() && !c.wide_off) {
                 // one tile per left configuration
                 // one tile per left configuration; the XCD ranges hold equal row counts
                 for (int m = 0; m < li.m_count; ++m) P.tbase[m] = li.lbase[m];
@@ -1326,7 +1355,7 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
         if constexpr (RowBatch<T, K>::RB >= 16 && RowBatch<T, K>::RB <= 64) {
             constexpr int ti = RowBatch<T, K>::RB == 16 ? 0 : (RowBatch<T, K>::RB == 32 ? 1 : 2);
             const RowTiling &Tl = c.tiling[ti];
-            if (tiled && Tl.ntiles) {
+            if (tiled && Tl.ntiles && !c.wide_off) {
                 TileParams TP;
                 memset(&TP, 0, sizeof(TP));
                 TP.x = x;
@@ -1378,7 +1407,8 @@ int launch_split_t(dcs_sector *s, const SplitRows &c, const void *x, void *y, co
             }
             // the tile list by crossing groups (DCS_ROW_ORDER=rows: run order)
             if (rows_group_order() && c.d_rorder && c.n_rorder == tiles) P.order = c.d_rorder;
-            auto kern = fused ? split_rows_kernel<T, K, true> : split_rows_kernel<T, K, false>;
+            auto kern = c.wide_off ? (fused ? split_rows_kernel<T, K, true, true> : split_rows_kernel<T, K, false, true>)
+                                   : (fused ? split_rows_kernel<T, K, true> : split_rows_kernel<T, K, false>);
             if (int r = ensure_lds(kern, wl)) return r;
             kern<<<split_grid(s, tiles), kThreads, wl, stream>>>(P);
             if (int r = check_hip(hipGetLastError(), "split rows launch")) return r;

@@ -134,3 +134,47 @@ def test_device_tables_adjoint_and_refusals(monkeypatch):
     with pytest.raises(dq.DcsError):  # a plan needs LDS tables for sectors without a split view
         dq.Plan([(dq.Sector(9, 4, 3, [3, 3, 3]), dq.Terms(synth.chain_bonds(9, 1)),
                   dev_f64(np.ones(9)), dev_f64(np.ones(9)))])
+
+
+@pytest.mark.parametrize("L,n,split,min_dim", [(24, 12, [2, 2, 7, 7, 6], None), (22, 11, [1, 1, 10, 10], "0")])
+@pytest.mark.parametrize("k,dt", [(1, torch.float32), (1, torch.float64), (2, torch.float64), (8, torch.float32)])
+@pytest.mark.parametrize("fused", ["0", "1"])
+def test_split_long_runs_all_rows(monkeypatch, L, n, split, min_dim, k, dt, fused):
+    """Cuts that leave runs of 65,535 rows or more (C(20, 10) = 184,756 here): the
+    split product with 32-bit target offsets, every row against the oracle, in the
+    default form and in the fused one."""
+    if min_dim is not None:
+        monkeypatch.setenv("DCS_SPLIT_MIN_DIM", min_dim)
+    monkeypatch.setenv("DCS_AUTOTUNE", "0")
+    monkeypatch.setenv("DCS_SPLIT_FUSED", fused)
+    s = dq.Sector(L, n, 2, split)
+    ns = native.NativeSector(2, L, n, split)
+    bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.5, 1.0)
+    h = np.linspace(-0.3, 0.4, L)
+    t = dq.Terms(bonds)
+    x = synth.vector(s.dim, synth.SEED_X, np.float64, k=k)
+    y_ref = native.hx_range(ns, native.NativeTerms(bonds, jxy, jz, h), x)
+    y = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), torch.from_numpy(x).to(DEV).to(dt), h=dev_f64(h))
+    form = dq.hamiltonian_form(s, t, dt, k)
+    err = rel_err(y.double().cpu().numpy(), y_ref)
+    say("long runs", L, split, k, dt, form, "rel err", err)
+    assert form == ("split_fused" if fused == "1" else "split_staged")
+    assert err <= TOL[dt]
+
+
+def test_split_long_runs_L32_sampled(x32):
+    """L=32 split 6/6/6/7/7 (cut 12 | 20, runs up to 184,756 rows), FP32 k=1 in the
+    autotuner's form, sampled rows against the oracle."""
+    L, n, split = 32, 16, [6, 6, 6, 7, 7]
+    s = dq.Sector(L, n, 2, split)
+    ns = native.NativeSector(2, L, n, split)
+    bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.5, 1.0)
+    t = dq.Terms(bonds)
+    rows = sampled_rows(s.dim, 200_000, 10)
+    y_ref = native.hx_rows(ns, native.NativeTerms(bonds, jxy, jz), x32, rows)
+    y = dq.hamiltonian_apply(s, t, dev_f64(jxy), dev_f64(jz), torch.from_numpy(x32).to(DEV).float())
+    got = y[torch.tensor(rows.astype(np.int64), device=DEV)].double().cpu().numpy()
+    err = rel_err(got, y_ref)
+    form = dq.hamiltonian_form(s, t, torch.float32, 1)
+    say("L32 6/6/6/7/7", form, "rel err", err)
+    assert err <= TOL[torch.float32]
