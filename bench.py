@@ -379,6 +379,14 @@ def split_sweep(dq, synth, torch, steps: int, warmup: int):
         out[key] = run(sizes, False)
         if out[key].get("tables") == "lds":
             out[key + " (device tables)"] = run(sizes, True)
+    # N = L: the on-the-fly order without tables (rank and unrank only; no sector object)
+    idx = torch.empty_like(states)
+    back = torch.empty_like(states)
+    per_r = median(time_steps(lambda: dq.lex_rank(L, N_UP, states, out=idx), stream, steps, warmup))
+    per_u = median(time_steps(lambda: dq.lex_unrank(L, N_UP, idx, out=back), stream, steps, warmup))
+    out["1x32 (N=L, on the fly)"] = {"supported": True, "tables": "none", "table_bytes": 0,
+                                     "rank_per_s": cnt / per_r, "unrank_per_s": cnt / per_u,
+                                     "roundtrip_ok": bool(torch.equal(back, states))}
     return out
 
 

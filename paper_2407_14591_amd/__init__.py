@@ -22,7 +22,7 @@ from ._lib import (DCS_F32, DCS_F64, DCS_INVALID_INDEX, DCS_REORTH_FULL, DCS_REO
 
 __all__ = ["Sector", "Terms", "Plan", "hamiltonian_apply", "hamiltonian_apply_adjoint",
            "hamiltonian_form", "hamiltonian_apply_adjoint_noalloc",
-           "HApply", "lanczos", "tridiag_eigvals", "DcsError", "DCS_INVALID_INDEX",
+           "HApply", "lanczos", "tridiag_eigvals", "lex_rank", "lex_unrank", "expectation_values", "DcsError", "DCS_INVALID_INDEX",
            "library_path"]
 
 
@@ -328,6 +328,28 @@ def expectation_values(sector: Sector, terms: Terms, psi, fields: bool = True):
     call("dcs_expectation_values", sector._h, terms._h, _dtype_code(psi.dtype), num, _ptr(psi),
          _ptr(exy), _ptr(ez), _ptr(esz), _ptr(ws), nbytes.value, _stream(sector.device))
     return {"xy": exy, "z": ez, "sz": esz}
+
+
+def lex_rank(L: int, n: int, states: torch.Tensor, out: torch.Tensor | None = None, count_invalid=False):
+    """Ranks in the lexicographic (N = L, on-the-fly) order of the Q = 2 sector (dcs_lex_rank)."""
+    dev = states.device.index if states.is_cuda else 0
+    _check_dev(states, dev, "states", (torch.int64, torch.uint64))
+    out = torch.empty_like(states) if out is None else out
+    _check_dev(out, dev, "out", (torch.int64, torch.uint64), numel=states.numel())
+    cnt = torch.zeros(1, dtype=torch.int64, device=states.device) if count_invalid else None
+    call("dcs_lex_rank", L, n, _ptr(states), _ptr(out), states.numel(), _ptr(cnt), _stream(dev))
+    return (out, cnt) if count_invalid else out
+
+
+def lex_unrank(L: int, n: int, idx: torch.Tensor, out: torch.Tensor | None = None, count_invalid=False):
+    """States at lexicographic (N = L, on-the-fly) positions of the Q = 2 sector (dcs_lex_unrank)."""
+    dev = idx.device.index if idx.is_cuda else 0
+    _check_dev(idx, dev, "idx", (torch.int64, torch.uint64))
+    out = torch.empty_like(idx) if out is None else out
+    _check_dev(out, dev, "out", (torch.int64, torch.uint64), numel=idx.numel())
+    cnt = torch.zeros(1, dtype=torch.int64, device=idx.device) if count_invalid else None
+    call("dcs_lex_unrank", L, n, _ptr(idx), _ptr(out), idx.numel(), _ptr(cnt), _stream(dev))
+    return (out, cnt) if count_invalid else out
 
 
 def tridiag_eigvals(alpha, beta, num: int, device: int = 0):

@@ -43,6 +43,8 @@ SIGNATURES = {
     "dcs_sector_dim": (_i, [_vp, _u64p]),
     "dcs_sector_split": (_i, [_vp, _ip, _ip]),
     "dcs_sector_tables": (_i, [_vp, _ip, _szp]),
+    "dcs_lex_rank": (_i, [_i, _i, _vp, _vp, _sz, _vp, _vp]),
+    "dcs_lex_unrank": (_i, [_i, _i, _vp, _vp, _sz, _vp, _vp]),
     "dcs_rank": (_i, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "dcs_unrank": (_i, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "dcs_enumerate": (_i, [_vp, _u64, _sz, _vp, _vp]),

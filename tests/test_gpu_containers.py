@@ -5,6 +5,8 @@ sectors forced there (DCS_GLOBAL_TABLES=1 at creation).  Against the C oracle:
 rank and unrank bit-exact on 2^20 random states; H*x on sampled rows at L = 32
 and on all rows at L = 24; the adjoint on the split tables; the calls that need
 tables in LDS refuse with DcsError."""
+import itertools
+
 import numpy as np
 import pytest
 import torch
@@ -178,3 +180,54 @@ def test_split_long_runs_L32_sampled(x32):
     form = dq.hamiltonian_form(s, t, torch.float32, 1)
     say("L32 6/6/6/7/7", form, "rel err", err)
     assert err <= TOL[torch.float32]
+
+
+@pytest.mark.parametrize("L,n", [(1, 0), (1, 1), (12, 0), (12, 12), (16, 8), (20, 7), (24, 12), (64, 1), (64, 63)])
+def test_lex_rank_unrank_full(L, n):
+    """The table-free N = L order (Alg. on-the-fly) is the numeric order of the packed
+    states: every state of the sector, sorted by brute force, against rank and unrank."""
+    if L <= 24:
+        st = np.array(sorted(sum(1 << b for b in c) for c in itertools.combinations(range(L), n)),
+                      dtype=np.uint64) if L <= 16 else _all_states(L, n)
+    else:  # L = 64 with one particle or one hole
+        bits = [1 << b for b in range(64)]
+        st = np.array(sorted(bits if n == 1 else [(2 ** 64 - 1) ^ b for b in bits]), dtype=np.uint64)
+    idx, bad = dq.lex_rank(L, n, to_dev(st), count_invalid=True)
+    assert int(bad.item()) == 0
+    assert np.array_equal(to_host_u64(idx), np.arange(len(st), dtype=np.uint64))
+    back, bad = dq.lex_unrank(L, n, to_dev(np.arange(len(st), dtype=np.uint64)), count_invalid=True)
+    assert np.array_equal(to_host_u64(back), st) and int(bad.item()) == 0
+
+
+def _all_states(L, n):
+    """All L-bit words with n ones in increasing numeric order (numpy, by popcount filter)."""
+    w = np.arange(1 << L, dtype=np.uint64)
+    pc = np.zeros(len(w), dtype=np.int64)
+    v = w.copy()
+    for _ in range(L):
+        pc += (v & np.uint64(1)).astype(np.int64)
+        v >>= np.uint64(1)
+    return w[pc == n]
+
+
+def test_lex_rank_L32_against_oracle():
+    """L = 32, n = 16: 2^20 random states round-trip; 4096 of them against the oracle's
+    lexicographic rank (eq. N=L, written from the paper); invalid states and indices counted."""
+    from oracle.sector import lex_rank as o_lex_rank
+    L, n = 32, 16
+    dig = synth.random_states(2, L, n, 1 << 20, seed=21)
+    st = synth.pack_digits(dig, 2)
+    idx = dq.lex_rank(L, n, to_dev(st))
+    got = to_host_u64(idx)
+    ref = np.array([o_lex_rank(list(d), 2) for d in dig[:4096]], dtype=np.uint64)
+    assert np.array_equal(got[:4096], ref)
+    assert np.array_equal(to_host_u64(dq.lex_unrank(L, n, idx)), st)
+    assert int(got.max()) < 601080390
+    bad = st.copy()
+    bad[:50] ^= np.uint64(1 << 40)  # a bit above L
+    bad[50:80] ^= np.uint64(1)      # the wrong particle number
+    _, nb = dq.lex_rank(L, n, to_dev(bad), count_invalid=True)
+    assert int(nb.item()) == 80
+    _, nb = dq.lex_unrank(L, n, to_dev(np.array([601080389, 601080390, 2 ** 40], dtype=np.uint64)),
+                          count_invalid=True)
+    assert int(nb.item()) == 2
