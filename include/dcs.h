@@ -258,9 +258,11 @@ int dcs_hamiltonian_form(const dcs_sector *sector, const dcs_terms *terms, int d
                          int *form);
 
 /*
- * Workspace bytes that dcs_hamiltonian_apply_adjoint needs for this pair.
+ * Workspace bytes that dcs_hamiltonian_apply_adjoint needs for this pair and
+ * blocks of k columns (k in {1, 2, 4, 8}).  For k > 1 a smaller workspace (the
+ * size for k = 1) is accepted and then rules out the split-table way.
  */
-int dcs_adjoint_workspace_size(const dcs_sector *sector, const dcs_terms *terms,
+int dcs_adjoint_workspace_size(const dcs_sector *sector, const dcs_terms *terms, int k,
                                size_t *bytes);
 
 /*
@@ -270,18 +272,21 @@ int dcs_adjoint_workspace_size(const dcs_sector *sector, const dcs_terms *terms,
  *   d_grad_jxy[b]   = sum_{s,c} G_{s,c} ((S+_i S-_j + S-_i S+_j)/2 X)_{s,c}
  *   d_grad_jz[b]    = sum_{s,c} G_{s,c} (Sz_i Sz_j X)_{s,c}
  *   d_grad_h[i]     = sum_{s,c} G_{s,c} (Sz_i X)_{s,c}    (skipped if d_grad_h == NULL)
- * For k > 1, d_grad_x is the block product H G (dcs_hamiltonian_apply, the same
- * form) and the sums come from one pass over the rows that ranks every reached
- * state and dots the k columns of X and G at every hop.  For k = 1:
- Three ways compute it: (0) one fused pass that ranks every reached state once and
- * uses it for both g and x; on a sector with a split view whose products run on
- * the split tables (the form the autotuner keeps for this terms object and dtype
- * at k = 1, see dcs_hamiltonian_apply, including its first-call timing), (1)
- * d_grad_x from that product applied to g and a pass forming only the sums (it
- * gathers x, not g), and for FP32 (2) the sums formed inside the split product of
- * g itself: each hop's gathered g_t times x at the row gives the coupling sum (the
- * hop is symmetric), and per-run / per-right-configuration sums of x_s g_s give
- * the S^z S^z and field sums.  The first call for a (terms, dtype) times the ways
+ * For k = 1 three ways compute it: (0) one fused pass that ranks every reached
+ * state once and uses it for both g and x; on a sector with a split view whose
+ * products run on the split tables (the form the autotuner keeps for this terms
+ * object and dtype at k = 1, see dcs_hamiltonian_apply, including its first-call
+ * timing), (1) d_grad_x from that product applied to g and a pass forming only
+ * the sums (it gathers x, not g), and for FP32 (2) the sums formed inside the
+ * split product of g itself: each hop's gathered g_t times x at the row gives the
+ * coupling sum (the hop is symmetric), and per-run / per-right-configuration sums
+ * of x_s g_s give the S^z S^z and field sums.  For k > 1 two ways: (1) d_grad_x
+ * from the block product H G (dcs_hamiltonian_apply, the same form) and one pass
+ * over the rows that ranks every reached state and dots the k columns of X and G
+ * at every hop; and for FP32 on a split view (2) the sums formed inside the split
+ * block product of G as for k = 1, each hop's value the dot of the k gathered
+ * columns of G with the k columns of X at the row.  The first call for a
+ * (terms, dtype, k) times the ways
  * that apply (each twice, HIP events, synchronising the stream) and keeps the
  * fastest (way 2 where it applies, else 1, inside stream capture or with
  * DCS_AUTOTUNE=0; DCS_ADJOINT_WAY=0/1/2 in the environment forces a way).  The

@@ -210,7 +210,7 @@ def hamiltonian_apply_adjoint(sector: Sector, terms: Terms, jxy, jz, x, g, h=Non
     gz = torch.empty(terms.num_bonds, dtype=torch.float64, device=dev)
     gh = torch.empty(sector.L, dtype=torch.float64, device=dev) if want_grad_h else None
     nbytes = C.c_size_t()
-    call("dcs_adjoint_workspace_size", sector._h, terms._h, C.byref(nbytes))
+    call("dcs_adjoint_workspace_size", sector._h, terms._h, k, C.byref(nbytes))
     ws = torch.empty(max(nbytes.value, 8), dtype=torch.uint8, device=dev)
     call("dcs_hamiltonian_apply_adjoint", sector._h, terms._h, _ptr(jxy), _ptr(jz), _ptr(h),
          _dtype_code(x.dtype), k, _ptr(x), _ptr(g), _ptr(gx), _ptr(gj), _ptr(gz), _ptr(gh), _ptr(ws),

@@ -52,7 +52,7 @@ SIGNATURES = {
     "dcs_terms_destroy": (_i, [_vp]),
     "dcs_hamiltonian_apply": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp]),
     "dcs_hamiltonian_form": (_i, [_vp, _vp, _i, _i, _ip]),
-    "dcs_adjoint_workspace_size": (_i, [_vp, _vp, _szp]),
+    "dcs_adjoint_workspace_size": (_i, [_vp, _vp, _i, _szp]),
     "dcs_hamiltonian_apply_adjoint": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp, _vp,
                                            _vp, _vp, _sz, _vp]),
     "dcs_hamiltonian_apply_adjoint_noalloc": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp,

@@ -111,11 +111,12 @@ extern "C" int dcs_hamiltonian_form(const dcs_sector *s, const dcs_terms *t, int
     return DCS_OK;
 }
 
-extern "C" int dcs_adjoint_workspace_size(const dcs_sector *s, const dcs_terms *t,
+extern "C" int dcs_adjoint_workspace_size(const dcs_sector *s, const dcs_terms *t, int k,
                                           size_t *bytes) {
     clear_error();
     if (!s || !t || !bytes) return set_error(DCS_EINVAL, "NULL argument");
-    *bytes = adjoint_ws_bytes(s, t);
+    if (k != 1 && k != 2 && k != 4 && k != 8) return set_error(DCS_EINVAL, "k=%d not in {1,2,4,8}", k);
+    *bytes = adjoint_ws_bytes(s, t, k);
     return DCS_OK;
 }
 

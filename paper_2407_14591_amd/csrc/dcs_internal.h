@@ -294,16 +294,16 @@ int launch_enumerate(const dcs_sector *s, uint64_t first, size_t count, uint64_t
 int launch_hx(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
               const double *h, int dtype, int k, const void *x, void *y, hipStream_t stream);
 int hx_form(const dcs_sector *s, const dcs_terms *t, int dtype, int k);
-size_t adjoint_ws_bytes(const dcs_sector *s, const dcs_terms *t);
+size_t adjoint_ws_bytes(const dcs_sector *s, const dcs_terms *t, int k = 1);  // blocks of k columns
 size_t adjoint_single_ws_bytes(const dcs_sector *s, const dcs_terms *t);  // the fused single pass
-// The adjoint on the split view for FP32 (sums formed inside the split product of g);
-// DCS_EUNSUPPORTED (no error message) where it does not apply.
+// The adjoint on the split view for FP32 blocks of k columns (sums formed inside
+// the split product of g); DCS_EUNSUPPORTED (no error message) where it does not apply.
 int launch_split_adjoint(dcs_sector *s, const SplitRows &c, const double *jxy, const double *jz,
-                         const double *h, int nbonds, const void *x, const void *g, void *gx,
+                         const double *h, int nbonds, int k, const void *x, const void *g, void *gx,
                          double *gjxy, double *gjz, double *gh, void *ws, size_t ws_bytes,
                          hipStream_t stream);
-size_t split_adjoint_ws_bytes(const dcs_sector *s, int nbonds);
-bool split_adjoint_applies(const dcs_sector *s, const SplitRows &c, int dtype);
+size_t split_adjoint_ws_bytes(const dcs_sector *s, int nbonds, int k = 1);
+bool split_adjoint_applies(const dcs_sector *s, const SplitRows &c, int dtype, int k = 1);
 // The adjoint in one fused pass over the rows (no split tables, no autotuner, no
 // allocation): workspace partials only.
 int launch_adjoint_single(const dcs_sector *s, const dcs_terms *t, const double *jxy,

@@ -284,8 +284,8 @@ size_t adjoint_single_ws_bytes(const dcs_sector *s, const dcs_terms *t) {
     return (size_t)g.wgs * (2 * t->num_bonds + s->desc.L) * sizeof(double);
 }
 
-size_t adjoint_ws_bytes(const dcs_sector *s, const dcs_terms *t) {
-    return std::max(adjoint_single_ws_bytes(s, t), split_adjoint_ws_bytes(s, t->num_bonds));
+size_t adjoint_ws_bytes(const dcs_sector *s, const dcs_terms *t, int k) {
+    return std::max(adjoint_single_ws_bytes(s, t), split_adjoint_ws_bytes(s, t->num_bonds, k));
 }
 
 namespace {
@@ -387,10 +387,65 @@ int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, c
                    double *gjxy, double *gjz, double *gh, void *ws, size_t ws_bytes,
                    hipStream_t stream) {
     DeviceGuard dg(s->device);
-    if (k > 1) {  // a block: grad_x = H G by the block product, the sums in one pass over the rows
-        if (gx)
-            if (int r = launch_hx(s, t, jxy, jz, h, dtype, k, g, gx, stream)) return r;
-        return adjoint_block_pass(s, t, jxy, jz, h, dtype, k, x, g, gjxy, gjz, gh, ws, stream);
+    if (k > 1) {
+        // a block: (1) grad_x = H G by the block product and the sums in one pass over
+        // the rows, or, for FP32 on the split tables, (2) the sums formed inside the
+        // split product of G; the first call for a (terms, dtype, k) times both
+        auto way1 = [&]() -> int {
+            if (gx)
+                if (int r = launch_hx(s, t, jxy, jz, h, dtype, k, g, gx, stream)) return r;
+            return adjoint_block_pass(s, t, jxy, jz, h, dtype, k, x, g, gjxy, gjz, gh, ws, stream);
+        };
+        if (!(gx && s->left.K > 0 && s->desc.Q == 2 && split_enabled() && dtype == DCS_F32)) return way1();
+        if (t->max_site >= s->desc.L)
+            return set_error(DCS_EINVAL, "bond site %d outside the sector's %d sites", t->max_site, s->desc.L);
+        clear_error();
+        dcs_sector *sm = const_cast<dcs_sector *>(s);
+        SplitRows *c = split_rows(sm, t);
+        if (!c) return dcs_last_error()[0] ? DCS_EHIP : way1();
+        if (!(split_adjoint_applies(s, *c, dtype, k) && ws_bytes >= split_adjoint_ws_bytes(s, t->num_bonds, k)))
+            return way1();
+        auto way2 = [&]() -> int {
+            return launch_split_adjoint(sm, *c, jxy, jz, h, t->num_bonds, k, x, g, gx, gjxy, gjz, gh, ws, ws_bytes,
+                                        stream);
+        };
+        const uint64_t key = tuned_key(t, dtype, k) | (1ull << 62);  // the block adjoint's entry
+        int way = -1;
+        if (const char *e = getenv("DCS_ADJOINT_WAY")) {
+            way = e[0] - '0';
+            if (way != 1 && way != 2) way = -1;
+        }
+        if (way < 0) {
+            std::lock_guard<std::mutex> lk(*sm->left.rows_lock);
+            auto it = sm->left.tuned.find(key);
+            if (it != sm->left.tuned.end()) way = it->second;
+        }
+        if (way < 0) {
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (!autotune_enabled() || hipStreamIsCapturing(stream, &cs) != hipSuccess ||
+                cs != hipStreamCaptureStatusNone) {
+                way = 2;
+            } else {
+                float best = 0.f;
+                for (int w = 1; w <= 2; ++w) {
+                    float ms = 0.f;
+                    for (int rep = 0; rep < 2; ++rep) {
+                        ms = time_on_stream([&]() { return w == 1 ? way1() : way2(); }, stream);
+                        if (ms < 0.f)
+                            return dcs_last_error()[0] ? DCS_EHIP : set_error(DCS_EHIP, "adjoint autotune timing");
+                    }
+                    if (w == 1 || ms < best) {
+                        best = ms;
+                        way = w;
+                    }
+                }
+                std::lock_guard<std::mutex> lk(*sm->left.rows_lock);
+                sm->left.tuned[key] = way;
+            }
+        }
+        const int r = way == 1 ? way1() : way2();
+        if (!r) note_split_use(sm, *c, stream);
+        return r;
     }
     auto fused = [&]() {
         return adjoint_pass(s, t, jxy, jz, h, dtype, x, g, gx, gjxy, gjz, gh, ws, stream);
@@ -417,9 +472,9 @@ int launch_adjoint(const dcs_sector *s, const dcs_terms *t, const double *jxy, c
         return adjoint_pass(s, t, jxy, jz, h, dtype, x, g, nullptr, gjxy, gjz, gh, ws, stream);
     };
     // the adjoint on the split view with its sums formed inside the product (FP32)
-    const bool adj_ok = split_adjoint_applies(s, *c, dtype) && ws_bytes >= split_adjoint_ws_bytes(s, t->num_bonds);
+    const bool adj_ok = split_adjoint_applies(s, *c, dtype, 1) && ws_bytes >= split_adjoint_ws_bytes(s, t->num_bonds, 1);
     auto split_adj = [&]() {
-        return launch_split_adjoint(sm, *c, jxy, jz, h, t->num_bonds, x, g, gx, gjxy, gjz, gh, ws, ws_bytes, stream);
+        return launch_split_adjoint(sm, *c, jxy, jz, h, t->num_bonds, 1, x, g, gx, gjxy, gjz, gh, ws, ws_bytes, stream);
     };
     auto run_way = [&](int w) { return w == 0 ? fused() : (w == 1 ? split_way() : split_adj()); };
     const uint64_t key = tuned_key(t, dtype, 0);  // k = 0: the adjoint's entry

@@ -27,6 +27,7 @@ struct ColSumParams {
     double *prp;  // [slice][right configuration]
     uint32_t rcount;
     int m_count;
+    int k;  // columns
     uint32_t rbase[kMaxLeftM + 1], lbase[kMaxLeftM], nleft[kMaxLeftM];
 };
 
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(256) void adj_colsum_kernel(const ColSumParams P_ar
     double acc = 0.0;
     for (uint32_t q = a; q < b; ++q) {
         const uint64_t row = P.runs[P.lbase[mi] + q] + r;
-        acc += (double)P.x[row] * (double)P.g[row];
+        for (int c = 0; c < P.k; ++c) acc += (double)P.x[row * P.k + c] * (double)P.g[row * P.k + c];
     }
     P.prp[(size_t)sl * P.rcount + gr] = acc;
 }
@@ -108,22 +109,57 @@ __global__ __launch_bounds__(kAdjFinalThreads) void adj_final_kernel(const Final
     }
 }
 
-// Column tiles of the column pass for FP32 k = 1 (as launch_split_t counts them).
-inline uint64_t col_tiles(const LeftInfo &li, const SplitRows &c) {
+// Column tiles of the column pass for FP32 blocks of k columns (as launch_split_t counts them).
+inline uint64_t col_tiles(const LeftInfo &li, const SplitRows &c, int k) {
     uint64_t tiles = 0;
     for (int m = 0; m < li.m_count; ++m) {
-        const uint64_t nchunk = (li.ncols[m] * sizeof(float) + kColWaveBytes - 1) / kColWaveBytes;
+        const uint64_t nchunk = (li.ncols[m] * k * sizeof(float) + kColWaveBytes - 1) / kColWaveBytes;
         tiles += nchunk * c.nclust[m];
     }
     return tiles;
 }
 
+// Row tiles of 512 rows (the row pass of blocks), in run order.
+inline uint64_t row_tiles(const LeftInfo &li) {
+    uint64_t tiles = 0;
+    for (int m = 0; m < li.m_count; ++m) tiles += (uint64_t)li.nleft[m] * ((li.ncols[m] + kSplitRowTile - 1) / kSplitRowTile);
+    return tiles;
+}
+
+// The run values of the block row pass: the sum of each run's tile values in
+// chunk order (one thread per value and left configuration).
+struct FoldParams {
+    const double *tilepart;
+    double *runpart;
+    uint64_t ntiles;
+    uint32_t count;
+    int m_count;
+    uint32_t lbase[kMaxLeftM + 1], nsub[kMaxLeftM];
+    uint64_t tbase[kMaxLeftM];
+};
+
+template <int Unused = 0>
+__global__ __launch_bounds__(256) void adj_fold_kernel(const FoldParams P_arg) {
+    (void)P_arg;
+    const FoldParams &P = kernel_arg0<FoldParams>();
+    const uint32_t gl = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t v = blockIdx.y;
+    if (gl >= P.count) return;
+    int mi = 0;
+    while (mi + 1 < P.m_count && gl >= P.lbase[mi + 1]) ++mi;
+    const uint64_t t0 = P.tbase[mi] + (uint64_t)(gl - P.lbase[mi]) * P.nsub[mi];
+    double acc = 0.0;
+    for (uint32_t ch = 0; ch < P.nsub[mi]; ++ch) acc += P.tilepart[(size_t)v * P.ntiles + t0 + ch];
+    P.runpart[(size_t)v * P.count + gl] = acc;
+}
+
 }  // namespace sp
 
-bool split_adjoint_applies(const dcs_sector *s, const SplitRows &c, int dtype) {
+bool split_adjoint_applies(const dcs_sector *s, const SplitRows &c, int dtype, int k) {
     const LeftInfo &li = s->left;
     if (dtype != DCS_F32 || li.K == 0 || c.wide_off) return false;
     if (c.nR > sp::kAdjR || c.nX > sp::kAdjX || c.nJs > sp::kAdjJ) return false;
+    if (k != 1) return k == 2 || k == 4 || k == 8;  // the block row pass reads its runs from HBM
     uint64_t max_cols = 0;
     for (int m = 0; m < li.m_count; ++m) max_cols = std::max<uint64_t>(max_cols, li.ncols[m]);
     return (max_cols + 1) * sizeof(float) <= sp::kRowLdsMax;  // the row pass stages whole runs
@@ -133,7 +169,7 @@ bool split_adjoint_applies(const dcs_sector *s, const SplitRows &c, int dtype) {
 // bond sums per column tile (clusters counted as the split tables form them:
 // consecutive left configurations of one block with equal words of P_0..P_{K-2},
 // at most kMaxClusterRuns), PR slices.
-size_t split_adjoint_ws_bytes(const dcs_sector *s, int nbonds) {
+size_t split_adjoint_ws_bytes(const dcs_sector *s, int nbonds, int k) {
     const LeftInfo &li = s->left;
     if (li.K == 0 || li.h_words.empty()) return 0;
     const uint32_t keep = li.K >= 2 ? ((1u << li.word_shift[li.K - 1]) - 1u) : 0u;
@@ -150,25 +186,132 @@ size_t split_adjoint_ws_bytes(const dcs_sector *s, int nbonds) {
             }
             ++size;
         }
-        tiles += (li.ncols[m] * sizeof(float) + sp::kColWaveBytes - 1) / sp::kColWaveBytes * nclust;
+        tiles += (li.ncols[m] * k * sizeof(float) + sp::kColWaveBytes - 1) / sp::kColWaveBytes * nclust;
     }
-    const size_t rows = (size_t)sp::kAdjRowValues * li.count;
+    const size_t rows = (size_t)sp::kAdjRowValues * (li.count + (k > 1 ? sp::row_tiles(li) : 0));
     const size_t cols = (size_t)std::max(nbonds, 1) * tiles;
     const size_t pr = (size_t)(sp::kPrSplit + 1) * li.rcount;
     return (rows + cols + pr) * sizeof(double);
 }
 
+namespace {
+
+// The row pass of a block of K columns: the product's 512-row tiles (in the product's
+// tile order) with the adjoint's values per tile in run order (tilepart).
+template <int K>
+int rows_adj_block(dcs_sector *s, const SplitRows &c, const void *amp, const void *x, const void *g, void *gx,
+                   double *tilepart, uint64_t ntiles, hipStream_t stream) {
+    using namespace sp;
+    const LeftInfo &li = s->left;
+    const uint32_t count = (uint32_t)li.count, rcount = (uint32_t)li.rcount;
+    RowParams P;
+    memset(&P, 0, sizeof(P));
+    P.x = g;
+    P.y = gx;
+    P.amp = amp;
+    P.lwords = (const uint32_t *)li.d_words;
+    P.rwords = (const uint32_t *)li.d_rwords;
+    P.runs = c.d_runs;
+    P.xl = c.d_xl;
+    P.vo = c.d_vo;
+    P.xo = c.d_xo;
+    P.dl = c.d_diag;
+    P.dr = c.d_diag + count;
+    P.counters = s->dev.counters;
+    P.count = count;
+    P.rcount = rcount;
+    P.m_count = li.m_count;
+    P.nR = c.nR;
+    P.nX = c.nX;
+    uint64_t tiles = 0;
+    for (int m = 0; m < li.m_count; ++m) {
+        P.lbase[m] = li.lbase[m];
+        P.rbase[m] = li.rbase[m];
+        P.ncols[m] = (uint32_t)li.ncols[m];
+        P.nsub[m] = (uint32_t)((li.ncols[m] + kThreads - 1) / kThreads);
+        P.tbase[m] = tiles;
+        tiles += (uint64_t)li.nleft[m] * P.nsub[m];
+    }
+    P.tbase[li.m_count] = tiles;
+    if (tiles != ntiles) return set_error(DCS_EHIP, "internal: block adjoint row tiles");
+    xcd_ranges(tiles, P.xbase);
+    memcpy(P.rbond, c.r_bond, sizeof(P.rbond));
+    memcpy(P.xb, c.x, sizeof(P.xb));
+    P.nRloc = c.nRloc;
+    P.margin = c.margin;
+    size_t wl = P.nRloc > 0 ? (size_t)(kThreads + 2 * c.margin + 1) * RowBatch<float, K>::RB : 0;
+    if (wl > kRowLdsMax) {
+        P.nRloc = 0;
+        P.margin = 0;
+        wl = 0;
+    }
+    if (rows_group_order() && c.d_rorder && c.n_rorder == tiles) P.order = c.d_rorder;
+    P.xprim = x;
+    P.part = tilepart;
+    P.part_n = (uint32_t)tiles;
+    P.nJs = c.nJs;
+    memcpy(P.jbit, c.jbit, sizeof(P.jbit));
+    auto kern = split_rows_kernel<float, K, false, false, true>;
+    if (int r = ensure_lds(kern, wl)) return r;
+    kern<<<split_grid(s, tiles), kThreads, wl, stream>>>(P);
+    return check_hip(hipGetLastError(), "split adjoint rows (block) launch");
+}
+
+template <int K>
+int cols_adj(dcs_sector *s, const SplitRows &c, int nbonds, const void *amp, const void *x, const void *g,
+             void *gx, double *colpart, uint64_t ntiles, hipStream_t stream) {
+    using namespace sp;
+    const LeftInfo &li = s->left;
+    ColParams P;
+    memset(&P, 0, sizeof(P));
+    P.x = g;
+    P.y = gx;
+    P.amp = amp;
+    P.lptr = c.d_lptr;
+    P.lent = c.d_lent;
+    P.runs = c.d_runs;
+    P.clstart = c.d_clstart;
+    P.clsize = c.d_clsize;
+    P.counters = s->dev.counters + 8;
+    P.m_count = li.m_count;
+    P.nbonds = nbonds;
+    uint64_t tiles = 0;
+    for (int m = 0; m < li.m_count; ++m) {
+        const uint64_t nchunk = (li.ncols[m] * K * sizeof(float) + kColWaveBytes - 1) / kColWaveBytes;
+        P.ncols[m] = (uint32_t)li.ncols[m];
+        P.clbase[m] = c.clbase[m];
+        P.nclust[m] = c.nclust[m];
+        P.tbase[m] = tiles;
+        tiles += nchunk * c.nclust[m];
+    }
+    P.tbase[li.m_count] = tiles;
+    if (tiles != ntiles) return set_error(DCS_EHIP, "internal: adjoint column tiles");
+    xcd_ranges(tiles, P.xbase);
+    P.xprim = x;
+    P.part = colpart;
+    P.part_n = tiles;
+    const size_t lds = col_params(P, li, c, kColWaveBytes, std::max(nbonds, 1));
+    auto kern = split_cols_kernel<float, K, true>;
+    if (int r = ensure_lds(kern, lds)) return r;
+    kern<<<split_grid(s, tiles), kColThreads, lds, stream>>>(P);
+    return check_hip(hipGetLastError(), "split adjoint columns launch");
+}
+
+}  // namespace
+
 int launch_split_adjoint(dcs_sector *s, const SplitRows &c, const double *jxy, const double *jz,
-                         const double *h, int nbonds, const void *x, const void *g, void *gx,
+                         const double *h, int nbonds, int k, const void *x, const void *g, void *gx,
                          double *gjxy, double *gjz, double *gh, void *ws, size_t ws_bytes,
                          hipStream_t stream) {
     using namespace sp;
     const LeftInfo &li = s->left;
-    if (!gx || !split_adjoint_applies(s, c, DCS_F32)) return DCS_EUNSUPPORTED;
+    if (!gx || !split_adjoint_applies(s, c, DCS_F32, k)) return DCS_EUNSUPPORTED;
     const uint32_t count = (uint32_t)li.count, rcount = (uint32_t)li.rcount;
-    const uint64_t ncoltiles = col_tiles(li, c);
+    const uint64_t ncoltiles = col_tiles(li, c, k);
+    const uint64_t nrowtiles = k > 1 ? row_tiles(li) : 0;
     double *rowpart = (double *)ws;
-    double *colpart = rowpart + (size_t)kAdjRowValues * count;
+    double *tilepart = rowpart + (size_t)kAdjRowValues * count;  // blocks: per row tile
+    double *colpart = tilepart + (size_t)kAdjRowValues * nrowtiles;
     double *prp = colpart + (size_t)std::max(nbonds, 1) * ncoltiles;
     double *pr = prp + (size_t)kPrSplit * rcount;
     const size_t need = (size_t)((pr + rcount) - rowpart) * sizeof(double);
@@ -178,8 +321,30 @@ int launch_split_adjoint(dcs_sector *s, const SplitRows &c, const double *jxy, c
     if (int r = launch_split_diag(s, c, jxy, jz, h, nbonds, stream)) return r;
     hx::zero_counters<0><<<1, 64, 0, stream>>>(s->dev.counters, 16);
     // row pass: grad_x for the right family, bonds across the cut and the diagonal,
-    // and the run values
-    {
+    // and the run values (blocks: per 512-row tile, then summed per run)
+    if (k > 1) {
+        int r = k == 2 ? rows_adj_block<2>(s, c, amp, x, g, gx, tilepart, nrowtiles, stream)
+                       : (k == 4 ? rows_adj_block<4>(s, c, amp, x, g, gx, tilepart, nrowtiles, stream)
+                                 : rows_adj_block<8>(s, c, amp, x, g, gx, tilepart, nrowtiles, stream));
+        if (r) return r;
+        FoldParams F;
+        memset(&F, 0, sizeof(F));
+        F.tilepart = tilepart;
+        F.runpart = rowpart;
+        F.ntiles = nrowtiles;
+        F.count = count;
+        F.m_count = li.m_count;
+        uint64_t tb = 0;
+        for (int m = 0; m < li.m_count; ++m) {
+            F.lbase[m] = li.lbase[m];
+            F.nsub[m] = (uint32_t)((li.ncols[m] + kSplitRowTile - 1) / kSplitRowTile);
+            F.tbase[m] = tb;
+            tb += (uint64_t)li.nleft[m] * F.nsub[m];
+        }
+        F.lbase[li.m_count] = count;
+        adj_fold_kernel<0><<<dim3((count + 255) / 256, kAdjRowValues), 256, 0, stream>>>(F);
+        if (int r2 = check_hip(hipGetLastError(), "split adjoint fold launch")) return r2;
+    } else {
         RowParams P;
         memset(&P, 0, sizeof(P));
         P.x = g;
@@ -248,7 +413,12 @@ int launch_split_adjoint(dcs_sector *s, const SplitRows &c, const double *jxy, c
         if (int r = check_hip(hipGetLastError(), "split adjoint rows launch")) return r;
     }
     // column pass: grad_x += left family, and the left-family hop sums per tile
-    {
+    if (k > 1) {
+        int r = k == 2 ? cols_adj<2>(s, c, nbonds, amp, x, g, gx, colpart, ncoltiles, stream)
+                       : (k == 4 ? cols_adj<4>(s, c, nbonds, amp, x, g, gx, colpart, ncoltiles, stream)
+                                 : cols_adj<8>(s, c, nbonds, amp, x, g, gx, colpart, ncoltiles, stream));
+        if (r) return r;
+    } else {
         ColParams P;
         memset(&P, 0, sizeof(P));
         P.x = g;
@@ -298,6 +468,7 @@ int launch_split_adjoint(dcs_sector *s, const SplitRows &c, const double *jxy, c
             P.nleft[m] = li.nleft[m];
         }
         P.rbase[li.m_count] = rcount;
+        P.k = k;
         adj_colsum_kernel<0><<<dim3((rcount + 255) / 256, kPrSplit), 256, 0, stream>>>(P);
         if (int r = check_hip(hipGetLastError(), "split adjoint column sums launch")) return r;
         adj_prsum_kernel<0><<<(rcount + 255) / 256, 256, 0, stream>>>(prp, pr, rcount);

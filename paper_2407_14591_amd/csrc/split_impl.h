@@ -244,6 +244,33 @@ struct RowBatch {
     static constexpr int X = RB <= 16 ? 8 : 1;                    // across the cut
 };
 
+// Row sums of 16 FP32 values of every lane at once (as hx::row_transpose_sum, on
+// 32-bit moves): lane i of each 16-lane row ends with the row's total of v[i];
+// then the four rows are added.  Fixed order (deterministic).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int H, int CTRL>
+__device__ __forceinline__ void half_step_f(float (&v)[16], bool upper) {
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const float lo = v[k], hi = v[k + H];
+        v[k] = (upper ? hi : lo) + dpp_f<CTRL>(upper ? lo : hi);
+    }
+}
+__device__ __forceinline__ float wave_transpose_sum16f(float (&v)[16]) {
+    const int l = threadIdx.x & 15;
+    half_step_f<8, 0x140>(v, l & 8);  // row_mirror
+    half_step_f<4, 0x141>(v, l & 4);  // row_half_mirror
+    half_step_f<2, 0x1B>(v, l & 2);   // quad_perm [3,2,1,0]
+    half_step_f<1, 0xB1>(v, l & 1);   // quad_perm [1,0,3,2]
+    float s = v[0];
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    return s;
+}
+
 // Entries of the target tables' 16-byte rows: eight 16-bit offsets (runs below
 // 65,535 rows; 0xFFFF: no hop), or, for longer runs (W32), four 32-bit ones
 // (0xFFFFFFFF: no hop).  byte(): the entry as a byte offset into the run, an
@@ -306,12 +333,24 @@ __device__ __forceinline__ Acc<T, K> lds_row(const char *lds, uint32_t row) {
 // LEFT: the pass also applies the left family (the fused form, no column pass):
 // a left bond maps the tile's run onto another run of the same block, row r onto
 // row r, so its gathers are contiguous across the wave.
-template <typename T, int K, bool LEFT, bool W32 = false>
+// ADJ (FP32 blocks of K columns, the adjoint's way 2): the product is y = H g (x is
+// g); each hop also adds sum_c x_s,c g_t,c to its bond's value, and the row adds
+// its sum_c x_s,c g_s,c to the diagonal values (as the staged-run adjoint pass, see
+// there), summed over the wave (FP32) into per-wave FP64 slots; at the end of the
+// tile the slots go, in wave order, to P.part[value][tile in run order].
+template <typename T, int K, bool LEFT, bool W32 = false, bool ADJ = false>
 __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_arg) {
     (void)P_arg;
     const RowParams &P = kernel_arg0<RowParams>();
     using B = RowBatch<T, K>;
     using OR = OffRow<W32>;
+    static_assert(!ADJ || (!LEFT && sizeof(T) == 4), "the adjoint row pass: FP32, no fused left family");
+    __shared__ double red[ADJ ? (kThreads / 64) * 64 : 1];
+    const uint32_t wave_id = threadIdx.x >> 6, lane_id = threadIdx.x & 63u;
+    auto flush16 = [&](float (&v)[16], int base) {
+        const float tsum = wave_transpose_sum16f(v);
+        if (lane_id < 16) red[wave_id * 64 + base + lane_id] += (double)tsum;
+    };
     static_assert(B::R % OR::PER == 0, "whole table rows per batch");
     const char *vob = reinterpret_cast<const char *>(P.vo);
     const char *xob = reinterpret_cast<const char *>(P.xo);
@@ -362,6 +401,18 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
         const bool active = r < ncols;
         const uint32_t gr = P.rbase[mi] + (active ? r : 0u);
         const uint64_t R = ro(P.runs)[gl];
+        // ADJ: the primal row (zero past the run) and this wave's slots
+        Acc<T, K> xo;
+        if constexpr (ADJ) {
+            xo = buf_load<T, K>(rsrc(reinterpret_cast<const T *>(P.xprim) + R * K, ncols * B::RB), r * B::RB);
+            red[wave_id * 64 + lane_id] = 0.0;
+        }
+        auto dotx = [&](const Acc<T, K> &v) -> float {
+            float d = 0.f;
+#pragma unroll
+            for (int c = 0; c < K; ++c) d += (float)xo.v[c] * (float)v.v[c];
+            return d;
+        };
         const uint32_t lw = ro(P.lwords)[gl];
         const double dl = ro(P.dl)[gl];
         const auto rs = rsrc(x + R * K, ncols * RB);
@@ -394,6 +445,9 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
         T diag = (T)(dl + dr);
         uint4 xw = xw0;
         int xw_group = 0;
+        float px[16];  // ADJ: cross-cut hop values, then the diagonal values
+#pragma unroll
+        for (int q = 0; q < 16; ++q) px[q] = 0.f;
         for (int x0 = 0; x0 < P.nX; x0 += B::X) {
             Acc<T, K> xv[B::X];
             bool hop[B::X];
@@ -424,6 +478,11 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
             for (int u = 0; u < B::X; ++u) {
                 hx::fma_acc<T, K>(acc, xamp[x0 + u], xv[u]);
                 diag += hop[u] ? -xjz[x0 + u] : xjz[x0 + u];
+                if constexpr (ADJ) {
+#pragma unroll
+                    for (int q = 0; q < kAdjX; ++q)
+                        if (q == x0 + u) px[q] = dotx(xv[u]);
+                }
             }
         }
         // right family: B::R targets per batch, OR::PER per 16-byte table row; bonds
@@ -463,6 +522,19 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
             }
 #pragma unroll
             for (int u = 0; u < B::R; ++u) hx::fma_acc<T, K>(acc, ramp[q0 + u], xv[u]);
+            if constexpr (ADJ) {  // right-family hop values, 16 bonds per flush (bonds < kAdjR)
+#pragma unroll
+                for (int h = 0; h < B::R; h += 16) {
+                    float pv[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) pv[u] = (u < B::R - h) ? dotx(xv[h + u < B::R ? h + u : 0]) : 0.f;
+                    if (B::R >= 16) {
+                        flush16(pv, q0 + h);
+                    } else {  // batches of 8: the second half of a 16-slot group
+                        flush16(pv, q0);
+                    }
+                }
+            }
         }
         if constexpr (LEFT) {
             // left family: B::R target runs per batch (wave-uniform list), row r of each;
@@ -488,7 +560,25 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
 #pragma unroll
             for (int c = 0; c < K; ++c) __builtin_nontemporal_store(acc.v[c] + diag * xs.v[c], yr + c);
         }
-        Q.finish();
+        if constexpr (ADJ) {
+            // the diagonal values: sum_c x_s,c g_s,c, and its signs by crossing right site
+            const float pg = dotx(xs);
+            px[kAdjX] = pg;
+#pragma unroll
+            for (int j = 0; j < kAdjJ; ++j)
+                if (j < P.nJs) px[kAdjX + 1 + j] = ((rw >> P.jbit[j]) & 1u) ? pg : -pg;
+            flush16(px, 32);
+            // the tile's values: the waves' slots added in wave order, at the tile's
+            // place in run order (its run's tiles are consecutive there)
+            __syncthreads();
+            if ((int)threadIdx.x < kAdjRowValues) {
+                double tot = 0.0;
+                for (int w = 0; w < kThreads / 64; ++w) tot += red[w * 64 + threadIdx.x];
+                const uint64_t tr = P.tbase[mi] + (uint64_t)(gl - P.lbase[mi]) * P.nsub[mi] + ch;
+                P.part[(size_t)threadIdx.x * P.part_n + tr] = tot;
+            }
+        }
+        Q.finish();  // its barrier also ends the reads of red
     }
 }
 
@@ -523,33 +613,6 @@ __device__ __forceinline__ ChunkIdx load_chunk_idx(const RowParams &P, int mi, u
 __device__ __forceinline__ uint32_t u16_of(const uint4 &v, uint32_t i) {  // i uniform, < 8
     const uint32_t w = (i >> 1) == 0 ? v.x : ((i >> 1) == 1 ? v.y : ((i >> 1) == 2 ? v.z : v.w));
     return (i & 1u) ? (w >> 16) : (w & 0xFFFFu);
-}
-
-// Row sums of 16 FP32 values of every lane at once (as hx::row_transpose_sum, on
-// 32-bit moves): lane i of each 16-lane row ends with the row's total of v[i];
-// then the four rows are added.  Fixed order (deterministic).
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
-}
-template <int H, int CTRL>
-__device__ __forceinline__ void half_step_f(float (&v)[16], bool upper) {
-#pragma unroll
-    for (int k = 0; k < H; ++k) {
-        const float lo = v[k], hi = v[k + H];
-        v[k] = (upper ? hi : lo) + dpp_f<CTRL>(upper ? lo : hi);
-    }
-}
-__device__ __forceinline__ float wave_transpose_sum16f(float (&v)[16]) {
-    const int l = threadIdx.x & 15;
-    half_step_f<8, 0x140>(v, l & 8);  // row_mirror
-    half_step_f<4, 0x141>(v, l & 4);  // row_half_mirror
-    half_step_f<2, 0x1B>(v, l & 2);   // quad_perm [3,2,1,0]
-    half_step_f<1, 0xB1>(v, l & 1);   // quad_perm [1,0,3,2]
-    float s = v[0];
-    s += __shfl_xor(s, 16);
-    s += __shfl_xor(s, 32);
-    return s;
 }
 
 // Threads per workgroup of the staged-run pass: 512 for 4-byte rows (three runs
@@ -1072,7 +1135,7 @@ __global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams
     T *__restrict__ y = reinterpret_cast<T *>(P.y);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
-    static_assert(!ADJ || K == 1, "the adjoint column pass takes one column");
+    static_assert(!ADJ || sizeof(T) == 4, "the adjoint column pass is FP32");
     double *wacc = reinterpret_cast<double *>(cl_lds + P.adj_lds_off);  // ADJ: [wave][bond]
     const T *__restrict__ xp = reinterpret_cast<const T *>(P.xprim);
     AheadQueue Q(P.counters, P.xbase, slots);

@@ -278,3 +278,40 @@ def test_block_adjoint_L24_k8_and_autograd():
     bz = torch.tensor(rng.uniform(0, 2, len(b8)), device=DEV, requires_grad=True)
     f = lambda x_, a_, b_: dq.HApply.apply(x_, a_, b_, s8, t8)
     assert torch.autograd.gradcheck(f, (xb, a, bz), eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+@pytest.mark.parametrize("L,n,split,k,min_dim", [(24, 12, [6, 6, 6, 6], 8, None), (24, 12, [6, 6, 6, 6], 2, None),
+                                                 (22, 11, [5, 6, 5, 6], 4, "0"), (20, 8, [5, 5, 5, 5], 8, "0")])
+def test_block_adjoint_ways_split(monkeypatch, L, n, split, k, min_dim):
+    """Both ways of the FP32 block adjoint on a split view (J1-J2 bonds, fields):
+    1 the block product of G plus a sums pass, 2 the sums formed inside the split
+    block product (per-tile values folded per run, then reduced in a fixed order).
+    Each against the C oracle's sums over every row and column and grad_X = H G on
+    every row; repeated calls are bitwise equal, and the two ways' sums are formed
+    in different orders, so they are not bitwise equal (the forced way ran)."""
+    if min_dim is not None:
+        monkeypatch.setenv("DCS_SPLIT_MIN_DIM", min_dim)
+    bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.5, 0.8)
+    rng = np.random.default_rng(L + k)
+    jxy = jxy * rng.uniform(0.5, 1.5, len(bonds))
+    hf = rng.normal(size=L)
+    ns = native.NativeSector(2, L, n, split)
+    x = synth.vector(ns.dim, synth.SEED_X, k=k)
+    g = synth.vector(ns.dim, synth.SEED_G, k=k)
+    ref_gx = native.hx_range(ns, native.NativeTerms(bonds, jxy, jz, hf), g)
+    rxy, rz, rh = native.bond_sums(ns, bonds, x, g, fields=True)
+    xd, gd = torch.tensor(x, device=DEV).float(), torch.tensor(g, device=DEV).float()
+    outs = {}
+    for way in ("1", "2"):
+        monkeypatch.setenv("DCS_ADJOINT_WAY", way)
+        s, t = dq.Sector(L, n, 2, split), dq.Terms(bonds)
+        args = (s, t, dev_f64(jxy), dev_f64(jz), xd, gd)
+        out = dq.hamiltonian_apply_adjoint(*args, h=dev_f64(hf), want_grad_h=True)
+        errs = [rel_err(out[0].double().cpu().numpy(), ref_gx), rel_err(out[1].cpu().numpy(), rxy),
+                rel_err(out[2].cpu().numpy(), rz), rel_err(out[3].cpu().numpy(), rh)]
+        say("block adjoint way", way, L, n, split, k, errs)
+        assert max(errs) <= 1e-5
+        again = dq.hamiltonian_apply_adjoint(*args, h=dev_f64(hf), want_grad_h=True)
+        assert all(torch.equal(a, b) for a, b in zip(out, again))
+        outs[way] = out
+    assert not torch.equal(outs["1"][1], outs["2"][1])
