@@ -23,6 +23,7 @@ constexpr int kAdjFinalThreads = 256;
 
 struct ColSumParams {
     const float *x, *g;
+    const float *dots;  // if not NULL: sum_c x_s,c g_s,c per row (x and g unused)
     const uint64_t *runs;
     double *prp;  // [slice][right configuration]
     uint32_t rcount;
@@ -31,6 +32,8 @@ struct ColSumParams {
     uint32_t rbase[kMaxLeftM + 1], lbase[kMaxLeftM], nleft[kMaxLeftM];
 };
 
+// PR in slices: thread = right configuration, the left configurations of the slice
+// in order (eight loads in flight, then added in order).
 template <int Unused = 0>
 __global__ __launch_bounds__(256) void adj_colsum_kernel(const ColSumParams P_arg) {
     (void)P_arg;
@@ -43,10 +46,24 @@ __global__ __launch_bounds__(256) void adj_colsum_kernel(const ColSumParams P_ar
     const uint32_t r = gr - P.rbase[mi];
     const uint32_t n = P.nleft[mi];
     const uint32_t a = (uint32_t)((uint64_t)n * sl / kPrSplit), b = (uint32_t)((uint64_t)n * (sl + 1) / kPrSplit);
+    const uint64_t *runs = P.runs + P.lbase[mi];
     double acc = 0.0;
-    for (uint32_t q = a; q < b; ++q) {
-        const uint64_t row = P.runs[P.lbase[mi] + q] + r;
-        for (int c = 0; c < P.k; ++c) acc += (double)P.x[row * P.k + c] * (double)P.g[row * P.k + c];
+    constexpr int U = 8;
+    if (P.dots) {
+        uint32_t q = a;
+        for (; q + U <= b; q += U) {
+            float v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = P.dots[runs[q + u] + r];
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += (double)v[u];
+        }
+        for (; q < b; ++q) acc += (double)P.dots[runs[q] + r];
+    } else {
+        for (uint32_t q = a; q < b; ++q) {
+            const uint64_t row = runs[q] + r;
+            for (int c = 0; c < P.k; ++c) acc += (double)P.x[row * P.k + c] * (double)P.g[row * P.k + c];
+        }
     }
     P.prp[(size_t)sl * P.rcount + gr] = acc;
 }
@@ -191,7 +208,8 @@ size_t split_adjoint_ws_bytes(const dcs_sector *s, int nbonds, int k) {
     const size_t rows = (size_t)sp::kAdjRowValues * (li.count + (k > 1 ? sp::row_tiles(li) : 0));
     const size_t cols = (size_t)std::max(nbonds, 1) * tiles;
     const size_t pr = (size_t)(sp::kPrSplit + 1) * li.rcount;
-    return (rows + cols + pr) * sizeof(double);
+    const size_t dots = k > 1 ? (size_t)s->desc.dim * sizeof(float) : 0;  // blocks: x . g per row
+    return (rows + cols + pr) * sizeof(double) + dots;
 }
 
 namespace {
@@ -200,7 +218,7 @@ namespace {
 // tile order) with the adjoint's values per tile in run order (tilepart).
 template <int K>
 int rows_adj_block(dcs_sector *s, const SplitRows &c, const void *amp, const void *x, const void *g, void *gx,
-                   double *tilepart, uint64_t ntiles, hipStream_t stream) {
+                   double *tilepart, uint64_t ntiles, float *dots, hipStream_t stream) {
     using namespace sp;
     const LeftInfo &li = s->left;
     const uint32_t count = (uint32_t)li.count, rcount = (uint32_t)li.rcount;
@@ -248,6 +266,7 @@ int rows_adj_block(dcs_sector *s, const SplitRows &c, const void *amp, const voi
     if (rows_group_order() && c.d_rorder && c.n_rorder == tiles) P.order = c.d_rorder;
     P.xprim = x;
     P.part = tilepart;
+    P.dots = dots;
     P.part_n = (uint32_t)tiles;
     P.nJs = c.nJs;
     memcpy(P.jbit, c.jbit, sizeof(P.jbit));
@@ -314,7 +333,8 @@ int launch_split_adjoint(dcs_sector *s, const SplitRows &c, const double *jxy, c
     double *colpart = tilepart + (size_t)kAdjRowValues * nrowtiles;
     double *prp = colpart + (size_t)std::max(nbonds, 1) * ncoltiles;
     double *pr = prp + (size_t)kPrSplit * rcount;
-    const size_t need = (size_t)((pr + rcount) - rowpart) * sizeof(double);
+    float *dots = k > 1 ? (float *)(pr + rcount) : nullptr;  // blocks: x . g per row
+    const size_t need = (size_t)((pr + rcount) - rowpart) * sizeof(double) + (k > 1 ? (size_t)s->desc.dim * sizeof(float) : 0);
     if (need > ws_bytes) return DCS_EUNSUPPORTED;
     double *amp64 = c.d_diag + (count + rcount + 1) / 2 * 2;
     const void *amp = (const void *)(amp64 + kAmpEntries);  // the FP32 factors
@@ -323,9 +343,9 @@ int launch_split_adjoint(dcs_sector *s, const SplitRows &c, const double *jxy, c
     // row pass: grad_x for the right family, bonds across the cut and the diagonal,
     // and the run values (blocks: per 512-row tile, then summed per run)
     if (k > 1) {
-        int r = k == 2 ? rows_adj_block<2>(s, c, amp, x, g, gx, tilepart, nrowtiles, stream)
-                       : (k == 4 ? rows_adj_block<4>(s, c, amp, x, g, gx, tilepart, nrowtiles, stream)
-                                 : rows_adj_block<8>(s, c, amp, x, g, gx, tilepart, nrowtiles, stream));
+        int r = k == 2 ? rows_adj_block<2>(s, c, amp, x, g, gx, tilepart, nrowtiles, dots, stream)
+                       : (k == 4 ? rows_adj_block<4>(s, c, amp, x, g, gx, tilepart, nrowtiles, dots, stream)
+                                 : rows_adj_block<8>(s, c, amp, x, g, gx, tilepart, nrowtiles, dots, stream));
         if (r) return r;
         FoldParams F;
         memset(&F, 0, sizeof(F));
@@ -458,6 +478,7 @@ int launch_split_adjoint(dcs_sector *s, const SplitRows &c, const double *jxy, c
         memset(&P, 0, sizeof(P));
         P.x = (const float *)x;
         P.g = (const float *)g;
+        P.dots = dots;
         P.runs = c.d_runs;
         P.prp = prp;
         P.rcount = rcount;

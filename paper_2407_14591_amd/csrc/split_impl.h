@@ -221,6 +221,7 @@ struct RowParams {
     // part receives per-tile sums [value][tile] (kAdjRowValues values, one tile per run)
     const void *xprim;
     double *part;
+    float *dots;  // ADJ blocks: sum_c x_s,c g_s,c per row (row order of the sector), or NULL
     uint32_t part_n;
     int nJs;
     uint8_t jbit[8];  // bit of crossing right-site slot j in a packed right word
@@ -231,6 +232,7 @@ static_assert(sizeof(RowParams) <= 4096, "kernel arguments are limited to 4 KiB"
 // right-family bonds 0..31 and bonds across the cut 0..7, then sum_s x_s g_s, then
 // sum_s (2 b_j(s) - 1) x_s g_s for crossing right-site slots 0..3.
 constexpr int kAdjR = 32, kAdjX = 8, kAdjJ = 4;
+static_assert(kAdjX == 8 && 1 + kAdjJ <= 8, "the row pass flushes these values in groups of 8");
 constexpr int kAdjRowValues = kAdjR + kAdjX + 1 + kAdjJ;
 
 // Gathers in flight per batch, sized for about 96 registers of gathered data:
@@ -266,6 +268,27 @@ __device__ __forceinline__ float wave_transpose_sum16f(float (&v)[16]) {
     half_step_f<2, 0x1B>(v, l & 2);   // quad_perm [3,2,1,0]
     half_step_f<1, 0xB1>(v, l & 1);   // quad_perm [1,0,3,2]
     float s = v[0];
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    return s;
+}
+// The same for 8 values: lane i of each 8-lane group ends with the group's total
+// of v[i & 7], then the two groups of a row, then the four rows are added.
+template <int H, int CTRL>
+__device__ __forceinline__ void half_step_f8(float (&v)[8], bool upper) {
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const float lo = v[k], hi = v[k + H];
+        v[k] = (upper ? hi : lo) + dpp_f<CTRL>(upper ? lo : hi);
+    }
+}
+__device__ __forceinline__ float wave_transpose_sum8f(float (&v)[8]) {
+    const int l = threadIdx.x & 7;
+    half_step_f8<4, 0x141>(v, l & 4);  // row_half_mirror
+    half_step_f8<2, 0x1B>(v, l & 2);   // quad_perm [3,2,1,0]
+    half_step_f8<1, 0xB1>(v, l & 1);   // quad_perm [1,0,3,2]
+    float s = v[0];
+    s += dpp_f<0x128>(s);  // row_ror:8, the other 8-lane group of the row
     s += __shfl_xor(s, 16);
     s += __shfl_xor(s, 32);
     return s;
@@ -337,9 +360,11 @@ __device__ __forceinline__ Acc<T, K> lds_row(const char *lds, uint32_t row) {
 // g); each hop also adds sum_c x_s,c g_t,c to its bond's value, and the row adds
 // its sum_c x_s,c g_s,c to the diagonal values (as the staged-run adjoint pass, see
 // there), summed over the wave (FP32) into per-wave FP64 slots; at the end of the
-// tile the slots go, in wave order, to P.part[value][tile in run order].
+// tile the slots go, in wave order, to P.part[value][tile in run order].  The row's
+// sum_c x_s,c g_s,c also goes to P.dots[row] (the per-right-configuration sums read
+// it there instead of re-reading both blocks).
 template <typename T, int K, bool LEFT, bool W32 = false, bool ADJ = false>
-__global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_arg) {
+__global__ __launch_bounds__(kThreads, ADJ ? 4 : 2) void split_rows_kernel(const RowParams P_arg) {
     (void)P_arg;
     const RowParams &P = kernel_arg0<RowParams>();
     using B = RowBatch<T, K>;
@@ -350,6 +375,10 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
     auto flush16 = [&](float (&v)[16], int base) {
         const float tsum = wave_transpose_sum16f(v);
         if (lane_id < 16) red[wave_id * 64 + base + lane_id] += (double)tsum;
+    };
+    auto flush8 = [&](float (&v)[8], int base) {
+        const float tsum = wave_transpose_sum8f(v);
+        if (lane_id < 8) red[wave_id * 64 + base + lane_id] += (double)tsum;
     };
     static_assert(B::R % OR::PER == 0, "whole table rows per batch");
     const char *vob = reinterpret_cast<const char *>(P.vo);
@@ -436,8 +465,12 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
             stage_rows<T, K>(rows_lds, x, R, s0, s1, zero_row);
             __syncthreads();
         }
-        const Acc<T, K> xs = staged ? lds_row<T, K>(rows_lds, active ? r - s0 : zero_row)
-                                    : buf_load<T, K>(rs, r * RB);  // past the run: zero
+        auto load_xs = [&]() {
+            return staged ? lds_row<T, K>(rows_lds, active ? r - s0 : zero_row)
+                          : buf_load<T, K>(rs, r * RB);  // past the run: zero
+        };
+        Acc<T, K> xs;
+        if constexpr (!ADJ) xs = load_xs();  // ADJ: after the gathers (registers)
         Acc<T, K> acc;
 #pragma unroll
         for (int c = 0; c < K; ++c) acc.v[c] = (T)0;
@@ -445,9 +478,9 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
         T diag = (T)(dl + dr);
         uint4 xw = xw0;
         int xw_group = 0;
-        float px[16];  // ADJ: cross-cut hop values, then the diagonal values
+        float px[kAdjX];  // ADJ: cross-cut hop values
 #pragma unroll
-        for (int q = 0; q < 16; ++q) px[q] = 0.f;
+        for (int q = 0; q < kAdjX; ++q) px[q] = 0.f;
         for (int x0 = 0; x0 < P.nX; x0 += B::X) {
             Acc<T, K> xv[B::X];
             bool hop[B::X];
@@ -485,6 +518,7 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
                 }
             }
         }
+        if constexpr (ADJ) flush8(px, kAdjR);
         // right family: B::R targets per batch, OR::PER per 16-byte table row; bonds
         // [0, nRloc) from the staged window, the others from the run in HBM.  The
         // first four table rows were loaded at the start of the tile.
@@ -522,17 +556,20 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
             }
 #pragma unroll
             for (int u = 0; u < B::R; ++u) hx::fma_acc<T, K>(acc, ramp[q0 + u], xv[u]);
-            if constexpr (ADJ) {  // right-family hop values, 16 bonds per flush (bonds < kAdjR)
+            if constexpr (ADJ) {  // right-family hop values, 16 (or 8) bonds per flush (bonds < kAdjR)
+                if constexpr (B::R >= 16) {
 #pragma unroll
-                for (int h = 0; h < B::R; h += 16) {
-                    float pv[16];
+                    for (int h = 0; h < B::R; h += 16) {
+                        float pv[16];
 #pragma unroll
-                    for (int u = 0; u < 16; ++u) pv[u] = (u < B::R - h) ? dotx(xv[h + u < B::R ? h + u : 0]) : 0.f;
-                    if (B::R >= 16) {
+                        for (int u = 0; u < 16; ++u) pv[u] = dotx(xv[h + u]);
                         flush16(pv, q0 + h);
-                    } else {  // batches of 8: the second half of a 16-slot group
-                        flush16(pv, q0);
                     }
+                } else {
+                    float pv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) pv[u] = dotx(xv[u]);
+                    flush8(pv, q0);
                 }
             }
         }
@@ -555,6 +592,7 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
                 for (int u = 0; u < B::R; ++u) hx::fma_acc<T, K>(acc, a[u], xv[u]);
             }
         }
+        if constexpr (ADJ) xs = load_xs();
         if (active) {
             T *yr = y + (R + r) * K;
 #pragma unroll
@@ -563,11 +601,14 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const RowParams P_
         if constexpr (ADJ) {
             // the diagonal values: sum_c x_s,c g_s,c, and its signs by crossing right site
             const float pg = dotx(xs);
-            px[kAdjX] = pg;
+            if (P.dots && active) __builtin_nontemporal_store(pg, P.dots + R + r);
+            float pd[8];
+            pd[0] = pg;
 #pragma unroll
-            for (int j = 0; j < kAdjJ; ++j)
-                if (j < P.nJs) px[kAdjX + 1 + j] = ((rw >> P.jbit[j]) & 1u) ? pg : -pg;
-            flush16(px, 32);
+            for (int j = 0; j < kAdjJ; ++j) pd[1 + j] = j < P.nJs ? (((rw >> P.jbit[j]) & 1u) ? pg : -pg) : 0.f;
+#pragma unroll
+            for (int j = 1 + kAdjJ; j < 8; ++j) pd[j] = 0.f;
+            flush8(pd, kAdjR + kAdjX);
             // the tile's values: the waves' slots added in wave order, at the tile's
             // place in run order (its run's tiles are consecutive there)
             __syncthreads();
@@ -1115,11 +1156,11 @@ constexpr uint32_t kColWaveBytes = 64 * kColLaneBytes;
 // w, w + 16, ...: the entries of a run come in one vector load (lane q holds
 // entry q), fetched while the wave works on its previous run, so no gather
 // waits on a table load; kColBatch gathers are in flight per wave.
-// ADJ (k = 1): the product is y += (left family) g (x is g); each hop also adds
-// x_s g_t to its bond's sum (per-wave LDS slots after the staged chunks, one
-// writing wave each, added in wave order at the end of the tile into P.part).
+// ADJ (FP32): the product is y += (left family) g (x is g); each hop also adds
+// sum_c x_s,c g_t,c to its bond's sum (per-wave LDS slots after the staged chunks,
+// one writing wave each, added in wave order at the end of the tile into P.part).
 template <typename T, int K, bool ADJ = false>
-__global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams P_arg) {
+__global__ __launch_bounds__(kColThreads, ADJ ? 8 : 4) void split_cols_kernel(const ColParams P_arg) {
     (void)P_arg;
     const ColParams &P = kernel_arg0<ColParams>();
     constexpr int LB = (int)kColLaneBytes;
@@ -1189,6 +1230,9 @@ __global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams
             const uint32_t n = qb - qa, base = qa;
             const uint64_t ecur = ev;
             if (i + kColWaves < size) fetch(i + kColWaves, qa, qb, ev);  // the wave's next run
+            float pv[8];  // ADJ: x_s g_t of this lane's elements, hops [q0 & ~7, +8) of the run
+#pragma unroll
+            for (int j = 0; j < 8; ++j) pv[j] = 0.f;
             for (uint32_t q0 = 0; q0 < n; q0 += kColBatch) {
                 vec_t v[kColBatch];
                 T a[kColBatch];
@@ -1218,22 +1262,34 @@ __global__ __launch_bounds__(kColThreads) void split_cols_kernel(const ColParams
 #pragma unroll
                 for (int u = 0; u < kColBatch; ++u) acc += a[u] * v[u];
                 if constexpr (ADJ) {
-                    // x_s g_t over this lane's rows, one value per hop; wave totals in
-                    // lanes 4u (transposed sum), added to the bond's slot of this wave
-                    double d[kColBatch];
+                    // x_s g_t over this lane's elements, one value per hop, 8 hops per
+                    // wave sum (FP32), each total added to its bond's slot of this wave
+                    static_assert(8 % kColBatch == 0, "whole batches per 8 hops");
+                    float f[kColBatch];
 #pragma unroll
                     for (int u = 0; u < kColBatch; ++u) {
-                        float f = 0.f;
+                        float d = 0.f;
 #pragma unroll
-                        for (int e = 0; e < V; ++e) f += (float)xo4[e] * (float)v[u][e];
-                        d[u] = q0 + u < n ? (double)f : 0.0;
+                        for (int e = 0; e < V; ++e) d += (float)xo4[e] * (float)v[u][e];
+                        f[u] = q0 + u < n ? d : 0.f;
                     }
-                    static_assert(!ADJ || kColBatch == 4, "the transposed sum takes 4 values");
-                    const double tsum = hx::wave_transpose_sum<4>(d);
-                    const uint32_t u = lane >> 2;
-                    if (lane < 16 && (lane & 3u) == 0 && q0 + u < n) {
-                        const uint32_t b = u == 0 ? bnd[0] : (u == 1 ? bnd[1] : (u == 2 ? bnd[2] : bnd[3]));
-                        wacc[wave * P.nbonds + b] += tsum;
+                    const uint32_t slot = q0 & 7u;  // uniform
+#pragma unroll
+                    for (int j = 0; j < 8; j += kColBatch)
+                        if (slot == (uint32_t)j)
+#pragma unroll
+                            for (int u = 0; u < kColBatch; ++u) pv[j + u] = f[u];
+                    if (slot + kColBatch == 8 || q0 + kColBatch >= n) {  // uniform
+                        const float tsum = wave_transpose_sum8f(pv);
+                        const uint32_t h = (q0 & ~7u) + lane;  // the hop of this lane's total (lanes < 8)
+                        const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(ecur >> 32), (int)(h & 63u));
+                        if (lane < 8 && h < n) {
+                            const uint32_t b = h < 64 ? (hi >> 16) & 0xFFu
+                                                      : (uint32_t)(ro(P.lent)[base + h] >> 48) & 0xFFu;
+                            wacc[wave * P.nbonds + b] += (double)tsum;
+                        }
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) pv[j] = 0.f;
                     }
                 }
             }
