@@ -59,6 +59,20 @@ __global__ __launch_bounds__(256) void adj_colsum_kernel(const ColSumParams P_ar
             for (int u = 0; u < U; ++u) acc += (double)v[u];
         }
         for (; q < b; ++q) acc += (double)P.dots[runs[q] + r];
+    } else if (P.k == 1) {
+        uint32_t q = a;
+        for (; q + U <= b; q += U) {
+            float xv[U], gv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t row = runs[q + u] + r;
+                xv[u] = P.x[row];
+                gv[u] = P.g[row];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += (double)xv[u] * (double)gv[u];
+        }
+        for (; q < b; ++q) acc += (double)P.x[runs[q] + r] * (double)P.g[runs[q] + r];
     } else {
         for (uint32_t q = a; q < b; ++q) {
             const uint64_t row = runs[q] + r;
