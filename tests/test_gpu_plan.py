@@ -145,3 +145,35 @@ def test_split_sectors_alternating_dtypes(monkeypatch):
         torch.cuda.synchronize()
         for (s, t, j, z), x, y in zip(items, xs, ys):
             assert torch.equal(y, dq.hamiltonian_apply(s, t, j, z, x)), (rep, dt, s.L, s.n)
+
+
+def test_repeated_split_sector_in_hybrid_plan(monkeypatch):
+    """One split sector listed three times (twice with one Terms object and different
+    couplings, once with its own Terms), beside a second split sector, with
+    DCS_PLAN_HYBRID=1: the repeated products share the sector's tile queue and split
+    tables, so the plan runs them on one stream.  Three applies; every y equals the
+    sector's own product bit for bit, and sampled rows match the oracle."""
+    monkeypatch.setenv("DCS_PLAN_HYBRID", "1")
+    L, n = 24, 12
+    bonds, jxy, jz = synth.xxz_chain(L, 1.0, 1.0)
+    s, s2 = dq.Sector(L, n, 2), dq.Sector(L, 11, 2)
+    t, t_other = dq.Terms(bonds), dq.Terms(bonds)
+    rng = np.random.default_rng(17)
+    cpl = [(jxy * rng.uniform(0.5, 1.5, len(bonds)), jz * rng.uniform(0.5, 1.5, len(bonds))) for _ in range(4)]
+    items = [(s, t, dev_f64(cpl[0][0]), dev_f64(cpl[0][1])), (s2, t_other, dev_f64(cpl[1][0]), dev_f64(cpl[1][1])),
+             (s, t, dev_f64(cpl[2][0]), dev_f64(cpl[2][1])), (s, t_other, dev_f64(cpl[3][0]), dev_f64(cpl[3][1]))]
+    plan = dq.Plan(items)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(23)
+    xs = [torch.randn(sec.dim, generator=g, device=DEV, dtype=torch.float32) for sec, _, _, _ in items]
+    for rep in range(3):
+        ys = plan.apply(xs)
+        torch.cuda.synchronize()
+        for i, ((sec, tt, j, z), x, y) in enumerate(zip(items, xs, ys)):
+            assert torch.equal(y, dq.hamiltonian_apply(sec, tt, j, z, x)), (rep, i)
+    ns = native.NativeSector(2, L, n, s.split)
+    rows = rng.integers(0, s.dim, 20000).astype(np.uint64)
+    for i in (0, 2, 3):
+        ref = native.hx_rows(ns, native.NativeTerms(bonds, cpl[i][0], cpl[i][1]), xs[i].cpu().numpy(), rows)
+        got = ys[i][torch.tensor(rows.astype(np.int64), device=DEV)].double().cpu().numpy()
+        assert rel_err(got, ref) <= 1e-5, i
