@@ -20,6 +20,9 @@ Contents
   gradients.py    adjoint of y = H(theta) x and the Hellmann-Feynman gradient
   observables.py  lowest few Ritz pairs and expectation values of the terms of H
                   (App. D)
+  operators.py    generic number-conserving local operators (Sec. 4.1 operator
+                  strings, App. C terms): y = O x term by term, and the operator on
+                  the whole Q^L space from tensor contractions
   native.py       ctypes loader of c/dcs_oracle.c (same definitions in plain C,
                   FP64, OpenMP) for sectors too large for Python
 

@@ -152,3 +152,22 @@ def pack_digits(digits: np.ndarray, Q: int) -> np.ndarray:
     for i in range(L):
         out |= digits[..., i] << np.uint64(nbits * (L - 1 - i))
     return out
+
+
+def random_local_matrix(Q: int, m: int, seed: int, density: float = 1.0) -> np.ndarray:
+    """Seeded real Q^m x Q^m matrix with N(0,1) entries, kept only where the local digit
+    strings of the row and the column have equal digit sums (the structure of a
+    particle-number conserving term; local index sum_j d_j Q^(m-1-j)); ``density``
+    keeps that fraction of those entries."""
+    rng = np.random.default_rng([seed, Q, m])
+    n = Q ** m
+    sums = np.zeros(n, dtype=np.int64)
+    for a in range(n):
+        v, s = a, 0
+        for _ in range(m):
+            s += v % Q
+            v //= Q
+        sums[a] = s
+    M = rng.standard_normal((n, n))
+    mask = (sums[:, None] == sums[None, :]) & (rng.random((n, n)) < density)
+    return np.where(mask, M, 0.0)

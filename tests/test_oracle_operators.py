@@ -1,0 +1,78 @@
+"""Pins of the generic-operator oracle (Sec. 4.1 operator strings, App. C terms):
+closed forms of the spin matrices, the XXZ Hamiltonian rebuilt from operator strings
+against the XXZ oracle, and the push-form product against the operator built on the
+whole Q^L space from tensor contractions alone."""
+import numpy as np
+import pytest
+
+import synth
+from oracle.hamiltonian import apply_h
+from oracle.operators import apply_operator, sector_matrix, spin_matrices, string
+from oracle.sector import BruteSector
+
+
+@pytest.mark.parametrize("Q", [2, 3, 4, 5])
+def test_spin_matrices_closed_forms(Q):
+    m = spin_matrices(Q)
+    S = (Q - 1) / 2
+    sp, sm, sz = m["S+"], m["S-"], m["Sz"]
+    assert np.allclose(sp.T, sm)
+    assert np.allclose(sp @ sm - sm @ sp, 2 * sz)                      # [S+, S-] = 2 Sz
+    assert np.allclose(sz @ sp - sp @ sz, sp)                          # [Sz, S+] = S+
+    assert np.allclose((sp @ sm + sm @ sp) / 2 + sz @ sz, S * (S + 1) * np.eye(Q))  # Casimir
+    assert np.allclose(np.diag(sz), np.arange(Q) - S)
+
+
+def xxz_terms(Q, bonds, jxy, jz, h):
+    terms = []
+    for (i, j), a, z in zip(bonds, jxy, jz):
+        terms.append(string(a / 2, (i, j), ("S+", "S-"), Q))
+        terms.append(string(a / 2, (i, j), ("S-", "S+"), Q))
+        terms.append(string(z, (i, j), ("Sz", "Sz"), Q))
+    for i, hi in enumerate(h):
+        terms.append(string(hi, (i,), ("Sz",), Q))
+    return terms
+
+
+@pytest.mark.parametrize("Q,L,n", [(2, 10, 5), (2, 9, 3), (3, 6, 6), (4, 5, 7)])
+def test_xxz_from_operator_strings(Q, L, n):
+    rng = np.random.default_rng(Q * 100 + L)
+    bonds = synth.chain_bonds(L, 1) + synth.chain_bonds(L, 2)
+    jxy, jz, h = rng.normal(size=len(bonds)), rng.normal(size=len(bonds)), rng.normal(size=L)
+    bs = BruteSector(Q, L, n)
+    x = rng.normal(size=bs.dim)
+    y = apply_operator(bs, xxz_terms(Q, bonds, jxy, jz, h), x)
+    assert np.allclose(y, apply_h(bs, bonds, jxy, jz, x, h=h), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("Q,L,n", [(2, 8, 4), (2, 7, 2), (3, 5, 4), (4, 4, 6)])
+def test_push_form_against_full_space(Q, L, n):
+    """Random conserving terms on 1, 2 and 3 sites, site lists in any order, matrices not
+    symmetric: the sector block of the full-space operator times x."""
+    rng = np.random.default_rng(Q * 10 + L)
+    terms = [(1.5, (3,), synth.random_local_matrix(Q, 1, 1)),
+             (-0.7, (L - 1, 1), synth.random_local_matrix(Q, 2, 2)),
+             (0.3, (0, 2, L - 1), synth.random_local_matrix(Q, 3, 3, density=0.5)),
+             (1.1, (2, 0), synth.random_local_matrix(Q, 2, 4))]
+    bs = BruteSector(Q, L, n)
+    x = rng.normal(size=bs.dim)
+    assert np.allclose(apply_operator(bs, terms, x), sector_matrix(bs, terms) @ x, rtol=1e-12, atol=1e-12)
+
+
+def test_nonconserving_term_rejected():
+    bs = BruteSector(2, 6, 3)
+    with pytest.raises(ValueError):
+        apply_operator(bs, [string(1.0, (0,), ("S+",), 2)], np.ones(bs.dim))
+
+
+def test_full_space_pin_catches_a_transposed_term():
+    """The full-space construction distinguishes M from its transpose (a plausible
+    mistake in either form)."""
+    Q, L = 2, 6
+    M = synth.random_local_matrix(Q, 2, 9)
+    bs = BruteSector(Q, L, 3)
+    x = np.random.default_rng(1).normal(size=bs.dim)
+    a = sector_matrix(bs, [(1.0, (1, 4), M)]) @ x
+    b = sector_matrix(bs, [(1.0, (1, 4), M.T)]) @ x
+    assert not np.allclose(a, b)
+    assert np.allclose(apply_operator(bs, [(1.0, (1, 4), M)], x), a, rtol=1e-12, atol=1e-12)
