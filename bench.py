@@ -304,7 +304,32 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
         "Sz_max_error_vs_oracle": max(
             float(np.abs(ex["sz"][e].cpu().numpy() - np.array(ref[e]["sz"])).max())
             for e in range(len(ref)))}
-    del r, ex, v0, s, t
+    del r, ex, v0
+
+    # the same Hamiltonian as a generic operator (Sec. 4.1 strings S+S-, S-S+, SzSz, Sz;
+    # App. C clusters of 4 sites): one product per dtype against the XXZ product,
+    # and the largest difference between the two
+    terms = []
+    for (i, j), a, z in zip(bonds, jxy, jz):
+        terms += [dq.operator_string(a / 2, (i, j), ("S+", "S-"), 2),
+                  dq.operator_string(a / 2, (i, j), ("S-", "S+"), 2),
+                  dq.operator_string(z, (i, j), ("Sz", "Sz"), 2)]
+    terms += [dq.operator_string(hv, (i,), ("Sz",), 2) for i, hv in enumerate(h)]
+    op = dq.Operator(2, 28, terms, cluster_sites=4)
+    for dt, tag, es in ((torch.float64, "f64", 8), (torch.float32, "f32", 4)):
+        x = torch.randn(s.dim, generator=g, device=dev, dtype=dt)
+        y = torch.empty_like(x)
+        y2 = torch.empty_like(x)
+        per_o = timed(lambda: dq.operator_apply(s, op, x, out=y), n=max(3, steps // 4), w=1)
+        per_h = timed(lambda: dq.hamiltonian_apply(s, t, jd, zd, x, h=hd, out=y2), n=max(3, steps // 4), w=1)
+        out[f"operator_L28_appd_{tag}"] = {
+            "ms": per_o * 1e3, "xxz_product_ms": per_h * 1e3, "over_xxz": per_o / per_h,
+            "clusters": op.num_clusters, "nnz": op.nnz, "states_per_s": s.dim / per_o,
+            "achieved_GBs": s.dim * 2 * es / per_o / 1e9,
+            "frac_of_peak": s.dim * 2 * es / per_o / 1e9 / PEAK_HBM_GBS,
+            "max_rel_diff_vs_xxz": float(((y - y2).abs().max() / y2.abs().max()).item())}
+        del x, y, y2
+    del op, s, t
     torch.cuda.empty_cache()
     return out
 

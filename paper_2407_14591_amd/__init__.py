@@ -23,7 +23,7 @@ from ._lib import (DCS_F32, DCS_F64, DCS_INVALID_INDEX, DCS_REORTH_FULL, DCS_REO
 __all__ = ["Sector", "Terms", "Plan", "hamiltonian_apply", "hamiltonian_apply_adjoint",
            "hamiltonian_form", "hamiltonian_apply_adjoint_noalloc",
            "HApply", "lanczos", "tridiag_eigvals", "lex_rank", "lex_unrank", "expectation_values", "DcsError", "DCS_INVALID_INDEX",
-           "library_path"]
+           "library_path", "Operator", "operator_apply", "local_operator", "operator_string"]
 
 
 def library_path() -> str:
@@ -162,6 +162,99 @@ class Terms:
             self.close()
         except Exception:
             pass
+
+
+def local_operator(name: str, Q: int):
+    """Single-site matrix on digits 0..Q-1 (spin S = (Q-1)/2, m = d - S): "Id", "Sz",
+    "S+" (raises d by one, factor sqrt(S(S+1) - m(m+1))) or "S-" (lowers it,
+    sqrt(S(S+1) - m(m-1))), the ladder factors of the XXZ terms."""
+    import numpy as np
+    S = (Q - 1) / 2.0
+    M = np.zeros((Q, Q))
+    for d in range(Q):
+        m = d - S
+        if name == "Id":
+            M[d, d] = 1.0
+        elif name == "Sz":
+            M[d, d] = m
+        elif name == "S+":
+            if d + 1 < Q:
+                M[d + 1, d] = np.sqrt(S * (S + 1) - m * (m + 1))
+        elif name == "S-":
+            if d > 0:
+                M[d - 1, d] = np.sqrt(S * (S + 1) - m * (m - 1))
+        else:
+            raise ValueError(f"unknown local operator {name!r}")
+    return M
+
+
+def operator_string(coef: float, sites, names, Q: int):
+    """The term coef * op_0(sites[0]) op_1(sites[1]) ... as (coef, sites, matrix): the
+    Kronecker product of the named single-site matrices, first site most significant."""
+    import numpy as np
+    if len(sites) != len(names):
+        raise ValueError("one local operator name per site")
+    M = np.ones((1, 1))
+    for nm in names:
+        M = np.kron(M, local_operator(nm, Q))
+    return (float(coef), tuple(int(s) for s in sites), M)
+
+
+class Operator:
+    """A generic number-conserving operator (dcs_operator_create): terms (coef, sites,
+    matrix) with a Q^m x Q^m matrix on the m listed sites, merged into clusters of at
+    most ``cluster_sites`` sites and stored sparse on the device."""
+
+    def __init__(self, Q: int, L: int, terms, cluster_sites: int = 4, device=None):
+        import numpy as np
+        self.Q, self.L = int(Q), int(L)
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        terms = list(terms)
+        nsites, sites, coefs, mats = [], [], [], []
+        for coef, st, M in terms:
+            st = [int(v) for v in st]
+            M = np.ascontiguousarray(M, dtype=np.float64)
+            n = self.Q ** len(st)
+            if M.shape != (n, n):
+                raise ValueError(f"term on {len(st)} sites needs a {n} x {n} matrix, got {M.shape}")
+            nsites.append(len(st))
+            sites.extend(st)
+            coefs.append(float(coef))
+            mats.append(M.ravel())
+        nt = len(terms)
+        a_ns = (C.c_int32 * max(nt, 1))(*nsites)
+        a_st = (C.c_int32 * max(len(sites), 1))(*sites)
+        a_cf = (C.c_double * max(nt, 1))(*coefs)
+        flat = np.concatenate(mats) if mats else np.zeros(1)
+        self._mats = flat  # kept alive for the call
+        self._h = C.c_void_p()
+        call("dcs_operator_create", self.Q, self.L, nt, a_ns, a_st, a_cf,
+             flat.ctypes.data_as(C.POINTER(C.c_double)), int(cluster_sites), self.device, C.byref(self._h))
+        ncl, nnz, mx = C.c_int(), C.c_uint64(), C.c_int()
+        call("dcs_operator_info", self._h, C.byref(ncl), C.byref(nnz), C.byref(mx))
+        self.num_clusters, self.nnz, self.max_cluster_sites = ncl.value, nnz.value, mx.value
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.lib().dcs_operator_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def operator_apply(sector: "Sector", op: Operator, x, out=None):
+    """y = O x on the sector (dcs_operator_apply), x of shape [dim], FP32 or FP64."""
+    _check_dev(x, sector.device, "x", (torch.float32, torch.float64), shape=(sector.dim,))
+    out = torch.empty_like(x) if out is None else out
+    _check_dev(out, sector.device, "out", x.dtype, shape=x.shape)
+    dt = _lib.DCS_F32 if x.dtype == torch.float32 else _lib.DCS_F64
+    call("dcs_operator_apply", sector._h, op._h, dt, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
+         _stream(sector.device))
+    return out
 
 
 def _couplings(sector, terms, jxy, jz, h):

@@ -86,3 +86,35 @@ def test_tables_fit_the_workloads():
                         (2, 24, [8, 8, 8]), (2, 28, [7, 7, 7, 7]), (3, 16, default_split(3, 16))]:
         nb = (Q - 1).bit_length()
         assert max(split) * nb <= 14
+
+
+def test_operator_host_checks(lib):
+    """dcs_operator_create checks its terms before any device call (CPU): a term that
+    does not conserve the particle number, repeated or out-of-range sites, too many
+    sites, a bad cluster size and bad Q / L are refused with their codes."""
+    from paper_2407_14591_amd import _lib
+    l = _lib.lib()
+    out = C.c_void_p()
+
+    def create(Q, L, nsites, sites, coefs, mats, cluster=4):
+        ns = (C.c_int32 * max(len(nsites), 1))(*nsites)
+        st = (C.c_int32 * max(len(sites), 1))(*sites)
+        cf = (C.c_double * max(len(coefs), 1))(*coefs)
+        mt = (C.c_double * max(len(mats), 1))(*mats)
+        return l.dcs_operator_create(Q, L, len(nsites), ns, st, cf, mt, cluster, 0, C.byref(out))
+
+    sp = [0, 0, 1, 0]  # S+ of spin 1/2: <1|S+|0> = 1 (does not conserve)
+    assert create(2, 4, [1], [2], [1.0], sp) == _lib.DCS_EINVAL
+    assert b"conserve" in l.dcs_last_error()
+    hop = [0] * 16
+    hop[1 * 4 + 2] = hop[2 * 4 + 1] = 1.0  # S+S- + S-S+ on two sites: conserves
+    assert create(2, 4, [2], [1, 1], [1.0], hop) == _lib.DCS_EINVAL  # site listed twice
+    assert create(2, 4, [2], [1, 4], [1.0], hop) == _lib.DCS_EINVAL  # site outside [0, L)
+    assert create(2, 4, [2], [1, 2], [1.0], hop, cluster=0) == _lib.DCS_EINVAL
+    assert create(2, 4, [2], [1, 2], [1.0], hop, cluster=9) == _lib.DCS_EINVAL
+    assert create(1, 4, [2], [1, 2], [1.0], hop) == _lib.DCS_EINVAL
+    assert create(2, 0, [2], [1, 2], [1.0], hop) == _lib.DCS_EINVAL
+    assert create(2, 12, [9], list(range(9)), [1.0], [0.0] * (512 * 512)) == _lib.DCS_EUNSUPPORTED
+    assert create(2, 4, [2], [1, 2], [float("nan")], hop) == _lib.DCS_EINVAL
+    assert l.dcs_operator_info(None, None, None, None) == _lib.DCS_EINVAL
+    assert l.dcs_operator_destroy(None) == _lib.DCS_OK

@@ -1,0 +1,163 @@
+"""GPU generic local operators (Sec. 4.1 operator strings and custom local matrices,
+App. C clusters): parity with the term-by-term oracle on every row, cluster merging,
+the XXZ Hamiltonian rebuilt from operator strings against the XXZ product and the C
+oracle, edge cases."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2407_14591_amd as dq
+import synth
+from gpu_common import DEV, rel_err, say
+from oracle import native
+from oracle.operators import apply_operator
+from oracle.sector import BruteSector
+
+pytestmark = pytest.mark.gpu
+
+
+def random_terms(Q, L, seed):
+    """Conserving terms on 1, 2 and 3 sites, site lists in any order, matrices not
+    symmetric, some on the same sites (merged into one cluster entry)."""
+    rng = np.random.default_rng(seed)
+    terms = []
+    for t in range(2 * L):
+        m = 1 + t % 3
+        sites = rng.choice(L, size=m, replace=False)
+        terms.append((float(rng.normal()), tuple(int(s) for s in sites),
+                      synth.random_local_matrix(Q, m, seed * 1000 + t, density=0.7)))
+    terms.append((0.5, terms[1][1], synth.random_local_matrix(Q, len(terms[1][1]), seed + 77)))
+    return terms
+
+
+@pytest.mark.parametrize("Q,L,n,split", [(2, 12, 6, [4, 4, 4]), (2, 11, 3, [2, 3, 3, 3]), (3, 7, 7, [3, 4]),
+                                         (4, 5, 6, [2, 3]), (5, 4, 8, [2, 2])])
+@pytest.mark.parametrize("cluster", [1, 2, 4, 6])
+def test_operator_matches_oracle(Q, L, n, split, cluster):
+    terms = random_terms(Q, L, Q * 10 + L)
+    op = dq.Operator(Q, L, terms, cluster_sites=cluster)
+    assert op.max_cluster_sites <= max(cluster, 3)
+    bs = BruteSector(Q, L, n, split)
+    s = dq.Sector(L, n, Q, split)
+    x = np.random.default_rng(L).normal(size=bs.dim)
+    ref = apply_operator(bs, terms, x)
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        y = dq.operator_apply(s, op, torch.tensor(x, device=DEV).to(dt))
+        err = rel_err(y.double().cpu().numpy(), ref)
+        say("operator", Q, L, n, cluster, dt, op.num_clusters, op.nnz, err)
+        assert err <= tol
+
+
+def test_cluster_merging_open_chain():
+    """Nearest-neighbour bonds of an open chain of 12 sites in order, clusters of 4
+    sites: {0..3}, {3..6}, {6..9}, {9..11}; the fields join the first cluster that
+    holds their site."""
+    Q, L = 2, 12
+    terms = []
+    for i in range(L - 1):
+        terms.append(dq.operator_string(0.5, (i, i + 1), ("S+", "S-"), Q))
+        terms.append(dq.operator_string(0.5, (i, i + 1), ("S-", "S+"), Q))
+        terms.append(dq.operator_string(1.0, (i, i + 1), ("Sz", "Sz"), Q))
+    for i in range(L):
+        terms.append(dq.operator_string(0.1 * i, (i,), ("Sz",), Q))
+    op = dq.Operator(Q, L, terms, cluster_sites=4)
+    assert (op.num_clusters, op.max_cluster_sites) == (4, 4)
+    op2 = dq.Operator(Q, L, terms, cluster_sites=2)
+    assert (op2.num_clusters, op2.max_cluster_sites) == (L - 1, 2)
+    s = dq.Sector(L, 6, Q)
+    bs = BruteSector(Q, L, 6, s.split)
+    x = np.random.default_rng(3).normal(size=bs.dim)
+    ref = apply_operator(bs, terms, x)
+    for o in (op, op2):
+        assert rel_err(dq.operator_apply(s, o, torch.tensor(x, device=DEV)).cpu().numpy(), ref) <= 1e-12
+
+
+def xxz_strings(Q, bonds, jxy, jz, h=None):
+    terms = []
+    for (i, j), a, z in zip(bonds, jxy, jz):
+        terms.append(dq.operator_string(a / 2, (i, j), ("S+", "S-"), Q))
+        terms.append(dq.operator_string(a / 2, (i, j), ("S-", "S+"), Q))
+        terms.append(dq.operator_string(z, (i, j), ("Sz", "Sz"), Q))
+    if h is not None:
+        for i, hi in enumerate(h):
+            terms.append(dq.operator_string(hi, (i,), ("Sz",), Q))
+    return terms
+
+
+def test_xxz_strings_equal_the_xxz_product_L24():
+    """The J1-J2 chain with random couplings and fields, built from S+S-, S-S+, SzSz
+    and Sz strings (clusters of 4 sites), against the library's own XXZ product on
+    every row (FP64 and FP32)."""
+    L, n = 24, 12
+    bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.5, 0.8)
+    rng = np.random.default_rng(9)
+    jxy = jxy * rng.uniform(0.5, 1.5, len(bonds))
+    h = rng.normal(size=L)
+    op = dq.Operator(2, L, xxz_strings(2, bonds, jxy, jz, h), cluster_sites=4)
+    s, t = dq.Sector(L, n, 2), dq.Terms(bonds)
+    x = torch.tensor(synth.vector(s.dim, synth.SEED_X), device=DEV)
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        xd = x.to(dt)
+        y = dq.operator_apply(s, op, xd)
+        ref = dq.hamiltonian_apply(s, t, torch.tensor(jxy, device=DEV), torch.tensor(jz, device=DEV), xd,
+                                   h=torch.tensor(h, device=DEV))
+        err = rel_err(y.double().cpu().numpy(), ref.double().cpu().numpy())
+        say("operator xxz L24", dt, op.num_clusters, err)
+        assert err <= tol
+
+
+def test_app_d_hamiltonian_from_strings_L28_sampled():
+    """App. D's Hamiltonian (open chain, tilted field k S^z_k) at L=28, n=14 built from
+    operator strings: 20,000 sampled rows against the C oracle (FP64)."""
+    L, n = 28, 14
+    bonds, jxy, jz, h = synth.tilted_field_chain(L)
+    op = dq.Operator(2, L, xxz_strings(2, bonds, jxy, jz, h), cluster_sites=4)
+    s = dq.Sector(L, n, 2)
+    ns = native.NativeSector(2, L, n, s.split)
+    x = synth.vector(s.dim, synth.SEED_X)
+    y = dq.operator_apply(s, op, torch.tensor(x, device=DEV))
+    rows = np.random.default_rng(4).integers(0, s.dim, 20000).astype(np.uint64)
+    ref = native.hx_rows(ns, native.NativeTerms(bonds, jxy, jz, h), x, rows)
+    got = y[torch.tensor(rows.astype(np.int64), device=DEV)].cpu().numpy()
+    err = rel_err(got, ref)
+    say("operator App. D L28 sampled", op.num_clusters, op.nnz, err)
+    assert err <= 1e-12
+
+
+def test_operator_edge_cases():
+    """No terms (y = 0); a sector of one state (n = 0); one term on every site of a
+    small chain; a Q = 3 sector with tables in device memory."""
+    Q, L = 2, 8
+    s0 = dq.Sector(L, 0, Q)
+    zero = dq.Operator(Q, L, [])
+    assert zero.num_clusters == 0
+    x0 = torch.ones(s0.dim, device=DEV, dtype=torch.float64)
+    assert torch.equal(dq.operator_apply(s0, zero, x0), torch.zeros_like(x0))
+    terms = [(0.7, tuple(range(L)), synth.random_local_matrix(Q, L, 5, density=0.3))]
+    op = dq.Operator(Q, L, terms, cluster_sites=8)
+    for n in (0, 1, 4, 8):
+        bs = BruteSector(Q, L, n)
+        s = dq.Sector(L, n, Q)
+        x = np.random.default_rng(n).normal(size=bs.dim)
+        assert rel_err(dq.operator_apply(s, op, torch.tensor(x, device=DEV)).cpu().numpy(),
+                       apply_operator(bs, terms, x)) <= 1e-12
+    with pytest.raises(dq.DcsError):
+        dq.operator_apply(dq.Sector(L + 1, 4, Q), op, torch.zeros(dq.Sector(L + 1, 4, Q).dim, device=DEV,
+                                                                   dtype=torch.float64))
+    with pytest.raises(ValueError):
+        dq.operator_apply(s0, zero, torch.ones(s0.dim + 1, device=DEV, dtype=torch.float64))
+
+
+def test_operator_device_tables(monkeypatch):
+    """The kernel reading its tables in device memory (DCS_GLOBAL_TABLES=1) equals the
+    oracle on every row."""
+    monkeypatch.setenv("DCS_GLOBAL_TABLES", "1")
+    Q, L, n = 3, 8, 8
+    terms = random_terms(Q, L, 31)
+    s = dq.Sector(L, n, Q, [4, 4])
+    assert s.tables_in_device_memory
+    bs = BruteSector(Q, L, n, [4, 4])
+    op = dq.Operator(Q, L, terms, cluster_sites=3)
+    x = np.random.default_rng(2).normal(size=bs.dim)
+    assert rel_err(dq.operator_apply(s, op, torch.tensor(x, device=DEV)).cpu().numpy(),
+                   apply_operator(bs, terms, x)) <= 1e-12
