@@ -10,9 +10,13 @@
 // the packed digits of its input state and its value.
 //
 // Device: one thread per row s of the sector (pull form, y_s = sum_t O_st x_t):
-// unrank s, and for each cluster read the local index of s on the cluster's sites,
-// walk that row's entries, write the entry's digits into s, rank the result with the
-// fused tables (a diagonal entry keeps s and its index), gather x there.
+// unrank s (keeping each subsystem's word, particles before it and contribution to
+// the index), and for each cluster read the local index of s on the cluster's
+// sites, walk that row's entries, write the entry's digits into s and re-rank only
+// the subsystems from the first to the last one the cluster touches (eq. index is a
+// sum over subsystems; the particles before the first and after the last are
+// unchanged), gather x there.  The operator's arrays are staged in LDS next to the
+// sector's tables when they fit.
 #include "device_common.h"
 
 #include <algorithm>
@@ -26,6 +30,7 @@ namespace op {
 constexpr int kOpMaxSites = 8;       // sites of one cluster
 constexpr uint32_t kOpMaxLocal = 4096;  // Q^m of one cluster
 constexpr int kOpThreads = 256;
+constexpr uint64_t kOpLdsMax = 128 * 1024;  // tables + operator arrays staged per workgroup
 
 struct OpCluster {
     uint8_t m;
@@ -35,63 +40,93 @@ struct OpCluster {
 };
 static_assert(sizeof(OpCluster) == 16, "cluster record");
 
+// The operator's arrays for one compute type, one contiguous blob (16-byte
+// aligned segments): clusters | row pointers (per cluster Q^m + 1 offsets into the
+// entries) | input digits of each entry (site j's digit at bits nb * j) | values.
 struct OpParams {
     SectorDesc sd;  // first: read in place in the kernel argument segment
     const char *blob;
-    const OpCluster *cl;
-    const uint32_t *rowptr;  // per cluster Q^m + 1 offsets into the entries
-    const uint32_t *dep;     // input digits of each entry: site j's digit at bits nb * j
-    const void *val;         // entry values in the compute type
+    const char *opblob;
+    uint32_t op_bytes, off_rp, off_dep, off_val;
+    uint32_t lds_tabs;  // LDS bytes of the sector's tables (0: read in device memory)
     const void *x;
     void *y;
     int ncl;
 };
 static_assert(sizeof(OpParams) <= 4096, "kernel arguments are limited to 4 KiB");
 
-template <typename IdxT, typename T, bool GT>
+template <typename IdxT, typename T, bool GT, bool OPL>
 __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
     (void)P_arg;
     const OpParams &P = kernel_arg0<OpParams>();
     const SectorDesc &sd = P.sd;
     extern __shared__ __align__(16) char lds[];
-    if constexpr (!GT) {
-        stage_blob(lds, P.blob, sd.lay_bytes);
-        __syncthreads();
-    }
+    if constexpr (!GT) stage_blob(lds, P.blob, sd.lay_bytes);
+    if constexpr (OPL) stage_blob(lds + P.lds_tabs, P.opblob, P.op_bytes);
+    if constexpr (!GT || OPL) __syncthreads();
     const Tables<IdxT> Tb = tables_at<IdxT>(GT ? P.blob : lds, sd);
+    const char *ob = OPL ? (const char *)(lds + P.lds_tabs) : P.opblob;
+    const OpCluster *cl = reinterpret_cast<const OpCluster *>(ob);
+    const uint32_t *rowptr = reinterpret_cast<const uint32_t *>(ob + P.off_rp);
+    const uint32_t *dep = reinterpret_cast<const uint32_t *>(ob + P.off_dep);
+    const T *val = reinterpret_cast<const T *>(ob + P.off_val);
     const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
     T *__restrict__ y = reinterpret_cast<T *>(P.y);
-    const T *__restrict__ val = reinterpret_cast<const T *>(P.val);
     const uint64_t dmask = (1ull << sd.nb) - 1ull;
     const uint64_t stride = (uint64_t)gridDim.x * kOpThreads;
     for (uint64_t i = (uint64_t)blockIdx.x * kOpThreads + threadIdx.x; i < sd.dim; i += stride) {
-        const uint64_t s = unrank_state<IdxT, kMaxSub>(sd, Tb, (IdxT)i, nullptr, nullptr, nullptr);
+        uint32_t w[kMaxSub];
+        int lam[kMaxSub];
+        IdxT cpart[kMaxSub];
+        const uint64_t s = unrank_state<IdxT, kMaxSub>(sd, Tb, (IdxT)i, w, lam, cpart);
         T acc = (T)0;
         for (int c = 0; c < P.ncl; ++c) {  // uniform
-            const OpCluster C = P.cl[c];
+            const OpCluster C = cl[c];
             int pos[kOpMaxSites];
             uint64_t clmask = 0;
             uint32_t a = 0;
+            int k1 = kMaxSub, k2 = -1;  // subsystems the cluster touches
 #pragma unroll
             for (int j = 0; j < kOpMaxSites; ++j) {
                 if (j < C.m) {
                     const int site = C.site[j];
-                    pos[j] = sd.shift[sd.site_sub[site]] + sd.site_bit[site];
+                    const int k = sd.site_sub[site];
+                    k1 = min(k1, k);
+                    k2 = max(k2, k);
+                    pos[j] = sd.shift[k] + sd.site_bit[site];
                     a = a * (uint32_t)sd.Q + (uint32_t)((s >> pos[j]) & dmask);
                     clmask |= dmask << pos[j];
                 } else {
                     pos[j] = 0;
                 }
             }
+            // the index without the touched subsystems' contributions; particles before k1
+            IdxT base_idx = (IdxT)i;
+            int lam0 = 0;
+#pragma unroll
+            for (int k = 0; k < kMaxSub; ++k) {
+                if (k >= k1 && k <= k2) base_idx -= cpart[k];
+                if (k == k1) lam0 = lam[k];
+            }
             const uint64_t keep = s & ~clmask;
-            const uint32_t e1 = P.rowptr[C.row0 + a + 1];
-            for (uint32_t e = P.rowptr[C.row0 + a]; e < e1; ++e) {
-                const uint32_t d = P.dep[e];
+            const uint32_t e1 = rowptr[C.row0 + a + 1];
+            for (uint32_t e = rowptr[C.row0 + a]; e < e1; ++e) {
+                const uint32_t d = dep[e];
                 uint64_t s2 = keep;
 #pragma unroll
                 for (int j = 0; j < kOpMaxSites; ++j)
                     if (j < C.m) s2 |= (uint64_t)((d >> (sd.nb * j)) & (uint32_t)dmask) << pos[j];
-                const uint64_t t = s2 == s ? i : (uint64_t)rank_state<IdxT, false>(sd, Tb, s2);
+                uint64_t t = i;
+                if (s2 != s) {
+                    IdxT v = base_idx;
+                    int l = lam0;
+                    for (int k = k1; k <= k2; ++k) {
+                        const uint32_t wk = sub_word(sd, s2, k);
+                        v += Tb.ctab[sd.ctab_row0[k] + (uint32_t)(l - sd.lam_lo[k]) * sd.ctab_rowlen[k] + wk];
+                        l += digit_sum(sd, wk);
+                    }
+                    t = (uint64_t)v;
+                }
                 acc += val[e] * (t < sd.dim ? x[t] : (T)0);
             }
         }
@@ -107,10 +142,9 @@ struct dcs_operator {
     int ncl = 0, max_sites = 0;
     uint64_t nnz = 0;
     void *d_base = nullptr;
-    const dcs::op::OpCluster *d_cl = nullptr;
-    const uint32_t *d_rowptr = nullptr, *d_dep = nullptr;
-    const double *d_val = nullptr;
-    const float *d_valf = nullptr;
+    const char *blob64 = nullptr, *blob32 = nullptr;  // the OpParams layout with FP64 / FP32 values
+    uint64_t bytes64 = 0, bytes32 = 0;
+    uint32_t off_rp = 0, off_dep = 0, off_val = 0;
 };
 
 namespace {
@@ -283,13 +317,20 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
     o->ncl = (int)hcl.size();
     o->max_sites = max_sites;
     o->nnz = val.size();
-    // one device allocation: clusters | row pointers | digits | FP64 values | FP32 values
-    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    const size_t b_cl = al(std::max<size_t>(hcl.size(), 1) * sizeof(OpCluster));
-    const size_t b_rp = al(std::max<size_t>(rowptr.size(), 1) * 4);
-    const size_t b_dep = al(std::max<size_t>(dep.size(), 1) * 4);
-    const size_t b_val = al(std::max<size_t>(val.size(), 1) * 8);
-    const size_t b_valf = al(std::max<size_t>(val.size(), 1) * 4);
+    // two blobs (FP64 and FP32 values), each clusters | row pointers | digits | values
+    auto a16 = [](uint64_t b) { return (b + 15) / 16 * 16; };
+    const uint64_t b_cl = a16(std::max<size_t>(hcl.size(), 1) * sizeof(OpCluster));
+    const uint64_t b_rp = a16(rowptr.size() * 4), b_dep = a16(dep.size() * 4);
+    o->off_rp = (uint32_t)b_cl;
+    o->off_dep = (uint32_t)(b_cl + b_rp);
+    o->off_val = (uint32_t)(b_cl + b_rp + b_dep);
+    if (b_cl + b_rp + b_dep + a16(val.size() * 8) > 0xFFFFFFF0ull) {
+        delete o;
+        return set_error(DCS_EUNSUPPORTED, "operator arrays beyond 4 GiB");
+    }
+    o->bytes64 = o->off_val + a16(std::max<size_t>(val.size(), 1) * 8);
+    o->bytes32 = o->off_val + a16(std::max<size_t>(val.size(), 1) * 4);
+    const uint64_t at32 = (o->bytes64 + 255) / 256 * 256;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
         (void)hipGetLastError();
@@ -298,24 +339,27 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
     }
     DeviceGuard g(device);
     char *base = nullptr;
-    if (hipMalloc((void **)&base, b_cl + b_rp + b_dep + b_val + b_valf) != hipSuccess) {
+    if (hipMalloc((void **)&base, at32 + o->bytes32) != hipSuccess) {
         (void)hipGetLastError();
         delete o;
-        return set_error(DCS_ENOMEM, "device allocation of %zu bytes failed", b_cl + b_rp + b_dep + b_val + b_valf);
+        return set_error(DCS_ENOMEM, "device allocation of %llu bytes failed", (unsigned long long)(at32 + o->bytes32));
     }
     o->d_base = base;
-    o->d_cl = (const OpCluster *)base;
-    o->d_rowptr = (const uint32_t *)(base + b_cl);
-    o->d_dep = (const uint32_t *)(base + b_cl + b_rp);
-    o->d_val = (const double *)(base + b_cl + b_rp + b_dep);
-    o->d_valf = (const float *)(base + b_cl + b_rp + b_dep + b_val);
-    std::vector<float> valf(val.begin(), val.end());
-    int r = DCS_OK;
-    if (!hcl.empty()) r = check_hip(hipMemcpy((void *)o->d_cl, hcl.data(), hcl.size() * sizeof(OpCluster), hipMemcpyHostToDevice), "operator upload");
-    if (!r && !rowptr.empty()) r = check_hip(hipMemcpy((void *)o->d_rowptr, rowptr.data(), rowptr.size() * 4, hipMemcpyHostToDevice), "operator upload");
-    if (!r && !dep.empty()) r = check_hip(hipMemcpy((void *)o->d_dep, dep.data(), dep.size() * 4, hipMemcpyHostToDevice), "operator upload");
-    if (!r && !val.empty()) r = check_hip(hipMemcpy((void *)o->d_val, val.data(), val.size() * 8, hipMemcpyHostToDevice), "operator upload");
-    if (!r && !val.empty()) r = check_hip(hipMemcpy((void *)o->d_valf, valf.data(), valf.size() * 4, hipMemcpyHostToDevice), "operator upload");
+    o->blob64 = base;
+    o->blob32 = base + at32;
+    std::vector<char> h64(o->bytes64, 0), h32(o->bytes32, 0);
+    for (std::vector<char> *h : {&h64, &h32}) {
+        if (!hcl.empty()) memcpy(h->data(), hcl.data(), hcl.size() * sizeof(OpCluster));
+        if (!rowptr.empty()) memcpy(h->data() + o->off_rp, rowptr.data(), rowptr.size() * 4);
+        if (!dep.empty()) memcpy(h->data() + o->off_dep, dep.data(), dep.size() * 4);
+    }
+    if (!val.empty()) memcpy(h64.data() + o->off_val, val.data(), val.size() * 8);
+    for (size_t e = 0; e < val.size(); ++e) {
+        const float f = (float)val[e];
+        memcpy(h32.data() + o->off_val + e * 4, &f, 4);
+    }
+    int r = check_hip(hipMemcpy(base, h64.data(), h64.size(), hipMemcpyHostToDevice), "operator upload");
+    if (!r) r = check_hip(hipMemcpy(base + at32, h32.data(), h32.size(), hipMemcpyHostToDevice), "operator upload");
     if (r) {
         (void)hipFree(base);
         delete o;
@@ -365,14 +409,18 @@ extern "C" int dcs_operator_apply(const dcs_sector *s, const dcs_operator *o, in
     memset(&P, 0, sizeof(P));
     P.sd = s->desc;
     P.blob = (const char *)s->dev.base;
-    P.cl = o->d_cl;
-    P.rowptr = o->d_rowptr;
-    P.dep = o->d_dep;
-    P.val = dtype == DCS_F32 ? (const void *)o->d_valf : (const void *)o->d_val;
+    P.opblob = dtype == DCS_F32 ? o->blob32 : o->blob64;
+    P.op_bytes = (uint32_t)(dtype == DCS_F32 ? o->bytes32 : o->bytes64);
+    P.off_rp = o->off_rp;
+    P.off_dep = o->off_dep;
+    P.off_val = o->off_val;
+    P.lds_tabs = s->gtab ? 0u : (uint32_t)s->desc.lay_bytes;  // a multiple of 16
     P.x = x;
     P.y = y;
     P.ncl = o->ncl;
-    const size_t lds = s->gtab ? 0 : s->desc.lay_bytes;
+    // the operator's arrays go to LDS beside the tables when both fit the budget
+    const bool opl = (uint64_t)P.lds_tabs + P.op_bytes <= kOpLdsMax;
+    const size_t lds = (size_t)P.lds_tabs + (opl ? P.op_bytes : 0u);
     const uint64_t blocks = (s->desc.dim + kOpThreads - 1) / kOpThreads;
     const uint64_t cap = (uint64_t)device_cu_count(s->device) * 8;
     const int grid = (int)std::max<uint64_t>(1, std::min(blocks, cap));
@@ -382,10 +430,14 @@ extern "C" int dcs_operator_apply(const dcs_sector *s, const dcs_operator *o, in
         kern<<<grid, kOpThreads, lds, st>>>(P);
         return check_hip(hipGetLastError(), "operator kernel launch");
     };
-    if (dtype == DCS_F32) {
-        if (s->wide) return s->gtab ? go(op_kernel<uint64_t, float, true>) : go(op_kernel<uint64_t, float, false>);
-        return s->gtab ? go(op_kernel<uint32_t, float, true>) : go(op_kernel<uint32_t, float, false>);
-    }
-    if (s->wide) return s->gtab ? go(op_kernel<uint64_t, double, true>) : go(op_kernel<uint64_t, double, false>);
-    return s->gtab ? go(op_kernel<uint32_t, double, true>) : go(op_kernel<uint32_t, double, false>);
+    auto pick = [&](auto tag) -> int {
+        using T = decltype(tag);
+        if (s->wide) {
+            if (s->gtab) return opl ? go(op_kernel<uint64_t, T, true, true>) : go(op_kernel<uint64_t, T, true, false>);
+            return opl ? go(op_kernel<uint64_t, T, false, true>) : go(op_kernel<uint64_t, T, false, false>);
+        }
+        if (s->gtab) return opl ? go(op_kernel<uint32_t, T, true, true>) : go(op_kernel<uint32_t, T, true, false>);
+        return opl ? go(op_kernel<uint32_t, T, false, true>) : go(op_kernel<uint32_t, T, false, false>);
+    };
+    return dtype == DCS_F32 ? pick(0.0f) : pick(0.0);
 }
