@@ -1,11 +1,11 @@
 """Oracle: generic number-conserving local operators, y = O x by definition.
 
-TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  FP64 throughout.
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  FP64 (or complex128) throughout.
 
 The operator class of Sec. 4.1 builds a Hamiltonian from strings of local
 operators (S+, S-, Sz and user-defined local matrices) on lists of sites;
 App. C stores the sum of the terms that live inside one cluster of sites as one
-sparse matrix.  Here an operator is a list of terms (coef, sites, M): M is a real
+sparse matrix.  Here an operator is a list of terms (coef, sites, M): M is a
 Q^m x Q^m matrix acting on the digits of the m listed sites, <b|M|a>, with the
 local index of a digit string (d_0, ..., d_{m-1}) over those sites being
 sum_j d_j Q^(m-1-j) (the first listed site most significant).  The operator is
@@ -14,6 +14,10 @@ sum_j d_j Q^(m-1-j) (the first listed site most significant).  The operator is
 
 A term conserves the particle number when every nonzero <b|M|a> joins digit
 strings of equal sums; only such terms map a U(1) sector into itself.
+
+Matrices may be complex (the operator's scalar type of Sec. 4.1 is real or complex);
+the product is then complex.  ``spin_matrices`` also gives Sx = (S+ + S-)/2 and
+Sy = (S+ - S-)/(2i).
 
 The oracle applies the terms one by one in the push form (every basis state of
 the sector sends coef <b|M|a> x_s to the state with the term's digits replaced);
@@ -30,7 +34,7 @@ from .sector import BruteSector, nbits_for
 
 def spin_matrices(Q: int) -> dict:
     """Single-site matrices on digits 0..Q-1 (m = d - S): Id, Sz, S+ (raises d by one),
-    S- (lowers it), with the ladder factors of the XXZ oracle."""
+    S- (lowers it), with the ladder factors of the XXZ oracle, and Sx, Sy (complex)."""
     S = spin(Q)
     sz = np.diag([d - S for d in range(Q)])
     sp = np.zeros((Q, Q))
@@ -39,7 +43,7 @@ def spin_matrices(Q: int) -> dict:
         sp[d + 1, d] = ladder_up(Q, d)
     for d in range(1, Q):
         sm[d - 1, d] = ladder_down(Q, d)
-    return {"Id": np.eye(Q), "Sz": sz, "S+": sp, "S-": sm}
+    return {"Id": np.eye(Q), "Sz": sz, "S+": sp, "S-": sm, "Sx": (sp + sm) / 2, "Sy": (sp - sm) / 2j}
 
 
 def string(coef: float, sites, names, Q: int):
@@ -65,16 +69,20 @@ def conserves(Q: int, m: int, M) -> bool:
 
 
 def apply_operator(bs: BruteSector, terms, x):
-    """y = O x on the sector of ``bs`` (rows in its canonical order), FP64, x of shape [D]."""
+    """y = O x on the sector of ``bs`` (rows in its canonical order), x of shape [D];
+    FP64, or complex128 when x or a matrix is complex."""
     Q, L = bs.Q, bs.L
     nb = nbits_for(Q)
     dmask = np.uint64((1 << nb) - 1)
-    x = np.asarray(x, dtype=np.float64)
+    x = np.asarray(x)
+    x = x.astype(np.complex128 if np.iscomplexobj(x) else np.float64)
+    cplx = np.iscomplexobj(x) or any(np.iscomplexobj(M) for _, _, M in terms)
     st = bs.states
-    y = np.zeros(bs.dim)
+    y = np.zeros(bs.dim, dtype=np.complex128 if cplx else np.float64)
     for coef, sites, M in terms:
         m = len(sites)
-        M = np.asarray(M, dtype=np.float64)
+        M = np.asarray(M)
+        M = M.astype(np.complex128 if np.iscomplexobj(M) else np.float64)
         if M.shape != (Q ** m, Q ** m):
             raise ValueError("term matrix shape")
         if not conserves(Q, m, M):
@@ -103,10 +111,11 @@ def full_space_matrix(Q: int, L: int, terms):
     """O on the whole Q^L space (basis index sum_i d_i Q^(L-1-i)), by contracting each
     term's matrix into the tensor legs of its sites."""
     dim = Q ** L
-    out = np.zeros((dim, dim))
+    cplx = any(np.iscomplexobj(M) for _, _, M in terms)
+    out = np.zeros((dim, dim), dtype=np.complex128 if cplx else np.float64)
     for coef, sites, M in terms:
         m = len(sites)
-        T = np.asarray(M, dtype=np.float64).reshape([Q] * (2 * m))  # out legs, then in legs
+        T = np.asarray(M).reshape([Q] * (2 * m))  # out legs, then in legs
         eye = np.eye(dim).reshape([Q] * L + [dim])
         # apply the term to every basis column: contract its in legs with the sites' legs
         res = np.tensordot(T, eye, axes=(list(range(m, 2 * m)), list(sites)))

@@ -76,3 +76,41 @@ def test_full_space_pin_catches_a_transposed_term():
     b = sector_matrix(bs, [(1.0, (1, 4), M.T)]) @ x
     assert not np.allclose(a, b)
     assert np.allclose(apply_operator(bs, [(1.0, (1, 4), M)], x), a, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("Q,L,n", [(2, 8, 4), (3, 5, 5)])
+def test_complex_sy_strings_rebuild_the_real_xxz(Q, L, n):
+    """Sx Sx + Sy Sy with the complex Sy = (S+ - S-)/(2i) equals (S+S- + S-S+)/2: the
+    XXZ Hamiltonian built from Sx and Sy strings (complex matrices) has no imaginary
+    part and equals the XXZ oracle on complex and real vectors."""
+    rng = np.random.default_rng(Q + L)
+    bonds = synth.chain_bonds(L, 1)
+    jxy, jz = rng.normal(size=len(bonds)), rng.normal(size=len(bonds))
+    terms = []
+    for (i, j), a, z in zip(bonds, jxy, jz):
+        # Sx Sx and Sy Sy each change the particle number; their sum does not
+        xy = string(1.0, (i, j), ("Sx", "Sx"), Q)[2] + string(1.0, (i, j), ("Sy", "Sy"), Q)[2]
+        terms += [(a, (i, j), xy), string(z, (i, j), ("Sz", "Sz"), Q)]
+    assert any(np.iscomplexobj(M) for _, _, M in terms)
+    bs = BruteSector(Q, L, n)
+    xr, xi = rng.normal(size=bs.dim), rng.normal(size=bs.dim)
+    y = apply_operator(bs, terms, xr + 1j * xi)
+    assert np.allclose(y, apply_h(bs, bonds, jxy, jz, xr) + 1j * apply_h(bs, bonds, jxy, jz, xi),
+                       rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("Q,L,n", [(2, 7, 3), (3, 5, 4)])
+def test_complex_push_form_against_full_space(Q, L, n):
+    """Complex conserving terms (random phases, a Dzyaloshinskii-Moriya-like
+    i(S+S- - S-S+) term): the push form against the full-space tensor contraction, and
+    the Hermitian part of the operator gives a Hermitian sector matrix."""
+    rng = np.random.default_rng(L)
+    M2 = synth.random_local_matrix(Q, 2, 3) * np.exp(1j * rng.uniform(0, 2 * np.pi, (Q * Q, Q * Q)))
+    dm = 1j * (string(1.0, (0, 1), ("S+", "S-"), Q)[2] - string(1.0, (0, 1), ("S-", "S+"), Q)[2])
+    terms = [(0.8, (1, L - 1), M2), (1.3, (2, 3), dm), (0.4, (0,), synth.random_local_matrix(Q, 1, 8) + 0j)]
+    bs = BruteSector(Q, L, n)
+    x = rng.normal(size=bs.dim) + 1j * rng.normal(size=bs.dim)
+    A = sector_matrix(bs, terms)
+    assert np.allclose(apply_operator(bs, terms, x), A @ x, rtol=1e-12, atol=1e-12)
+    H = sector_matrix(bs, [(1.3, (2, 3), dm)])
+    assert np.allclose(H, H.conj().T) and np.abs(H.imag).max() > 0
