@@ -329,6 +329,15 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
             "frac_of_peak": s.dim * 2 * es / per_o / 1e9 / PEAK_HBM_GBS,
             "max_rel_diff_vs_xxz": float(((y - y2).abs().max() / y2.abs().max()).item())}
         del x, y, y2
+    # complex128 vectors (a real operator on the real and imaginary parts at once)
+    xc = torch.complex(torch.randn(s.dim, generator=g, device=dev, dtype=torch.float64),
+                       torch.randn(s.dim, generator=g, device=dev, dtype=torch.float64))
+    yc = torch.empty_like(xc)
+    per_c = timed(lambda: dq.operator_apply(s, op, xc, out=yc), n=max(3, steps // 4), w=1)
+    out["operator_L28_appd_c128"] = {"ms": per_c * 1e3, "states_per_s": s.dim / per_c,
+                                     "achieved_GBs": s.dim * 32 / per_c / 1e9,
+                                     "frac_of_peak": s.dim * 32 / per_c / 1e9 / PEAK_HBM_GBS}
+    del xc, yc
     del op, s, t
     torch.cuda.empty_cache()
     return out

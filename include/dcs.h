@@ -70,6 +70,8 @@ extern "C" {
 /* ---- element types of vectors ------------------------------------------- */
 #define DCS_F32 0
 #define DCS_F64 1
+#define DCS_C64 2  /* complex, interleaved FP32 (re, im) pairs (generic operators only) */
+#define DCS_C128 3 /* complex, interleaved FP64 (re, im) pairs (generic operators only) */
 
 /* ---- Lanczos re-orthogonalisation modes --------------------------------- */
 #define DCS_REORTH_NONE 0  /* plain three-term recurrence */
@@ -350,8 +352,9 @@ typedef struct dcs_operator dcs_operator;
 /*
  * O = sum_t coef_t M_t, the operator class of Sec. 4.1: each term acts on the
  * m_t = term_nsites[t] sites listed in term_sites (concatenated over the terms,
- * sites distinct, in [0, L)) with a real Q^m x Q^m matrix <b|M|a> in term_mats
- * (concatenated, row-major: row = output), the local index of a digit string
+ * sites distinct, in [0, L)) with a Q^m x Q^m matrix <b|M|a> in term_mats
+ * (concatenated, row-major: row = output; real, or with complex_mats = 1 complex
+ * as interleaved (re, im) doubles: Sec. 4.1's scalar type), the local index of a digit string
  * (d_0, .., d_{m-1}) over the listed sites being sum_j d_j Q^(m-1-j) (the first
  * listed site most significant).  An operator string such as S+_i S-_j is the
  * Kronecker product of its single-site matrices; a custom local operator is any
@@ -363,15 +366,16 @@ typedef struct dcs_operator dcs_operator;
  * a term joins the first cluster whose site set, extended by the term's sites,
  * has at most cluster_sites sites (1..8) and Q^sites <= 4096, else it opens a new
  * cluster.  Each cluster's summed matrix is stored sparse, row by row, with the
- * packed input digits and the value (FP64 and FP32 copies) of every nonzero,
+ * packed input digits and the value (FP64 and FP32 copies, complex for a complex
+ * operator) of every nonzero,
  * in device memory of `device` (owned by the object, freed by destroy).
  * Limits: 1..8 sites and Q^m <= 4096 per term (DCS_EUNSUPPORTED), Q in [2, 16],
  * L in [1, DCS_MAX_SITES].  Checks run before any device call.  Host call.
  */
 int dcs_operator_create(int Q, int L, int num_terms, const int32_t *term_nsites,
                         const int32_t *term_sites, const double *term_coefs,
-                        const double *term_mats, int cluster_sites, int device,
-                        dcs_operator **out);
+                        const double *term_mats, int complex_mats, int cluster_sites,
+                        int device, dcs_operator **out);
 int dcs_operator_destroy(dcs_operator *op);
 
 /* Clusters, stored nonzeros and the largest cluster's site count (any may be NULL). */
@@ -380,8 +384,10 @@ int dcs_operator_info(const dcs_operator *op, int *num_clusters, uint64_t *nnz,
 
 /*
  * d_y = O d_x on one sector (Q and L of the operator, same device), vectors of D
- * entries of dtype (DCS_F32 / DCS_F64, the stored values rounded to FP32 for
- * FP32), pull form: one thread per row s unranks s (Alg. iii), and per cluster
+ * entries of dtype: DCS_F32 / DCS_F64 for a real operator, DCS_C64 / DCS_C128
+ * (interleaved re, im) for a real or a complex one (a complex operator on real
+ * vectors is DCS_EINVAL); the stored values are rounded to FP32 for the FP32
+ * types.  Pull form: one thread per row s unranks s (Alg. iii), and per cluster
  * reads s's local index on the cluster's sites, walks that row of the cluster
  * matrix, writes each entry's digits into s, ranks the result (eq. index; a
  * diagonal entry keeps s) and accumulates value * x there.  d_y must not overlap

@@ -166,9 +166,13 @@ class Terms:
 
 def local_operator(name: str, Q: int):
     """Single-site matrix on digits 0..Q-1 (spin S = (Q-1)/2, m = d - S): "Id", "Sz",
-    "S+" (raises d by one, factor sqrt(S(S+1) - m(m+1))) or "S-" (lowers it,
-    sqrt(S(S+1) - m(m-1))), the ladder factors of the XXZ terms."""
+    "S+" (raises d by one, factor sqrt(S(S+1) - m(m+1))), "S-" (lowers it,
+    sqrt(S(S+1) - m(m-1))), the ladder factors of the XXZ terms, or "Sx" = (S+ + S-)/2,
+    "Sy" = (S+ - S-)/(2i) (complex)."""
     import numpy as np
+    if name in ("Sx", "Sy"):
+        sp, sm = local_operator("S+", Q), local_operator("S-", Q)
+        return (sp + sm) / 2 if name == "Sx" else (sp - sm) / 2j
     S = (Q - 1) / 2.0
     M = np.zeros((Q, Q))
     for d in range(Q):
@@ -202,25 +206,26 @@ def operator_string(coef: float, sites, names, Q: int):
 
 class Operator:
     """A generic number-conserving operator (dcs_operator_create): terms (coef, sites,
-    matrix) with a Q^m x Q^m matrix on the m listed sites, merged into clusters of at
-    most ``cluster_sites`` sites and stored sparse on the device."""
+    matrix) with a real or complex Q^m x Q^m matrix on the m listed sites, merged into
+    clusters of at most ``cluster_sites`` sites and stored sparse on the device."""
 
     def __init__(self, Q: int, L: int, terms, cluster_sites: int = 4, device=None):
         import numpy as np
         self.Q, self.L = int(Q), int(L)
         self.device = torch.cuda.current_device() if device is None else int(device)
         terms = list(terms)
+        self.is_complex = any(np.iscomplexobj(M) for _, _, M in terms)
         nsites, sites, coefs, mats = [], [], [], []
         for coef, st, M in terms:
             st = [int(v) for v in st]
-            M = np.ascontiguousarray(M, dtype=np.float64)
+            M = np.ascontiguousarray(M, dtype=np.complex128 if self.is_complex else np.float64)
             n = self.Q ** len(st)
             if M.shape != (n, n):
                 raise ValueError(f"term on {len(st)} sites needs a {n} x {n} matrix, got {M.shape}")
             nsites.append(len(st))
             sites.extend(st)
             coefs.append(float(coef))
-            mats.append(M.ravel())
+            mats.append(M.ravel().view(np.float64))  # complex: interleaved re, im
         nt = len(terms)
         a_ns = (C.c_int32 * max(nt, 1))(*nsites)
         a_st = (C.c_int32 * max(len(sites), 1))(*sites)
@@ -229,7 +234,8 @@ class Operator:
         self._mats = flat  # kept alive for the call
         self._h = C.c_void_p()
         call("dcs_operator_create", self.Q, self.L, nt, a_ns, a_st, a_cf,
-             flat.ctypes.data_as(C.POINTER(C.c_double)), int(cluster_sites), self.device, C.byref(self._h))
+             flat.ctypes.data_as(C.POINTER(C.c_double)), int(self.is_complex), int(cluster_sites), self.device,
+             C.byref(self._h))
         ncl, nnz, mx = C.c_int(), C.c_uint64(), C.c_int()
         call("dcs_operator_info", self._h, C.byref(ncl), C.byref(nnz), C.byref(mx))
         self.num_clusters, self.nnz, self.max_cluster_sites = ncl.value, nnz.value, mx.value
@@ -247,11 +253,14 @@ class Operator:
 
 
 def operator_apply(sector: "Sector", op: Operator, x, out=None):
-    """y = O x on the sector (dcs_operator_apply), x of shape [dim], FP32 or FP64."""
-    _check_dev(x, sector.device, "x", (torch.float32, torch.float64), shape=(sector.dim,))
+    """y = O x on the sector (dcs_operator_apply), x of shape [dim]: float32 / float64,
+    or complex64 / complex128 (required for a complex operator)."""
+    codes = {torch.float32: _lib.DCS_F32, torch.float64: _lib.DCS_F64, torch.complex64: _lib.DCS_C64,
+             torch.complex128: _lib.DCS_C128}
+    _check_dev(x, sector.device, "x", tuple(codes), shape=(sector.dim,))
     out = torch.empty_like(x) if out is None else out
     _check_dev(out, sector.device, "out", x.dtype, shape=x.shape)
-    dt = _lib.DCS_F32 if x.dtype == torch.float32 else _lib.DCS_F64
+    dt = codes[x.dtype]
     call("dcs_operator_apply", sector._h, op._h, dt, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
          _stream(sector.device))
     return out

@@ -19,6 +19,8 @@ DCS_EHIP = -4
 DCS_EUNSUPPORTED = -5
 DCS_F32 = 0
 DCS_F64 = 1
+DCS_C64 = 2
+DCS_C128 = 3
 DCS_REORTH_NONE = 0
 DCS_REORTH_LOCAL = 1
 DCS_REORTH_FULL = 2
@@ -66,7 +68,7 @@ SIGNATURES = {
     "dcs_expectation_workspace_size": (_i, [_vp, _vp, _szp]),
     "dcs_expectation_values": (_i, [_vp, _vp, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "dcs_tridiag_eigvals": (_i, [_dp, _dp, _i, _i, _dp, _i]),
-    "dcs_operator_create": (_i, [_i, _i, _i, _i32p, _i32p, _dp, _dp, _i, _i, _pp]),
+    "dcs_operator_create": (_i, [_i, _i, _i, _i32p, _i32p, _dp, _dp, _i, _i, _i, _pp]),
     "dcs_operator_destroy": (_i, [_vp]),
     "dcs_operator_info": (_i, [_vp, _ip, _u64p, _ip]),
     "dcs_operator_apply": (_i, [_vp, _vp, _i, _vp, _vp, _vp]),

@@ -21,7 +21,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 namespace dcs {
@@ -55,8 +57,36 @@ struct OpParams {
 };
 static_assert(sizeof(OpParams) <= 4096, "kernel arguments are limited to 4 KiB");
 
-template <typename IdxT, typename T, bool GT, bool OPL>
+// Values and vectors of the compute type T, each real or complex (interleaved
+// re, im); a real operator may act on complex vectors.
+template <typename T, bool C>
+struct OpScalar {
+    using type = T;
+};
+template <typename T>
+struct OpScalar<T, true> {
+    struct type {
+        T re, im;
+    };
+};
+template <typename X, typename V>
+__device__ __forceinline__ void op_fma(X &acc, const V &v, const X &x) {
+    if constexpr (std::is_arithmetic<X>::value) {
+        acc += v * x;
+    } else if constexpr (std::is_arithmetic<V>::value) {  // real value, complex vector
+        acc.re += v * x.re;
+        acc.im += v * x.im;
+    } else {  // complex value and vector
+        acc.re += v.re * x.re - v.im * x.im;
+        acc.im += v.re * x.im + v.im * x.re;
+    }
+}
+
+template <typename IdxT, typename T, bool VC, bool XC, bool GT, bool OPL>
 __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
+    static_assert(XC || !VC, "a complex operator needs complex vectors");
+    using V = typename OpScalar<T, VC>::type;
+    using X = typename OpScalar<T, XC>::type;
     (void)P_arg;
     const OpParams &P = kernel_arg0<OpParams>();
     const SectorDesc &sd = P.sd;
@@ -69,9 +99,9 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
     const OpCluster *cl = reinterpret_cast<const OpCluster *>(ob);
     const uint32_t *rowptr = reinterpret_cast<const uint32_t *>(ob + P.off_rp);
     const uint32_t *dep = reinterpret_cast<const uint32_t *>(ob + P.off_dep);
-    const T *val = reinterpret_cast<const T *>(ob + P.off_val);
-    const T *__restrict__ x = reinterpret_cast<const T *>(P.x);
-    T *__restrict__ y = reinterpret_cast<T *>(P.y);
+    const V *val = reinterpret_cast<const V *>(ob + P.off_val);
+    const X *__restrict__ x = reinterpret_cast<const X *>(P.x);
+    X *__restrict__ y = reinterpret_cast<X *>(P.y);
     const uint64_t dmask = (1ull << sd.nb) - 1ull;
     const uint64_t stride = (uint64_t)gridDim.x * kOpThreads;
     for (uint64_t i = (uint64_t)blockIdx.x * kOpThreads + threadIdx.x; i < sd.dim; i += stride) {
@@ -79,7 +109,8 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
         int lam[kMaxSub];
         IdxT cpart[kMaxSub];
         const uint64_t s = unrank_state<IdxT, kMaxSub>(sd, Tb, (IdxT)i, w, lam, cpart);
-        T acc = (T)0;
+        X acc;
+        memset(&acc, 0, sizeof(acc));
         for (int c = 0; c < P.ncl; ++c) {  // uniform
             const OpCluster C = cl[c];
             int pos[kOpMaxSites];
@@ -127,7 +158,10 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
                     }
                     t = (uint64_t)v;
                 }
-                acc += val[e] * (t < sd.dim ? x[t] : (T)0);
+                X xt;
+                if (t < sd.dim) xt = x[t];
+                else memset(&xt, 0, sizeof(xt));
+                op_fma(acc, val[e], xt);
             }
         }
         y[i] = acc;
@@ -140,6 +174,7 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
 struct dcs_operator {
     int Q = 0, L = 0, nb = 0, device = 0;
     int ncl = 0, max_sites = 0;
+    bool cplx = false;  // complex values (interleaved re, im)
     uint64_t nnz = 0;
     void *d_base = nullptr;
     const char *blob64 = nullptr, *blob32 = nullptr;  // the OpParams layout with FP64 / FP32 values
@@ -175,15 +210,15 @@ inline uint32_t ipow(int Q, int m) {
 
 struct Entry {
     uint32_t row, col;
-    double v;
+    std::complex<double> v;
 };
 
 }  // namespace
 
 extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *term_nsites,
                                    const int32_t *term_sites, const double *term_coefs,
-                                   const double *term_mats, int cluster_sites, int device,
-                                   dcs_operator **out) {
+                                   const double *term_mats, int complex_mats, int cluster_sites,
+                                   int device, dcs_operator **out) {
     clear_error();
     if (!out) return set_error(DCS_EINVAL, "out is NULL");
     *out = nullptr;
@@ -194,6 +229,10 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
         return set_error(DCS_EINVAL, "NULL term array");
     if (cluster_sites < 1 || cluster_sites > kOpMaxSites)
         return set_error(DCS_EINVAL, "cluster_sites=%d outside [1, %d]", cluster_sites, kOpMaxSites);
+    if (complex_mats != 0 && complex_mats != 1) return set_error(DCS_EINVAL, "complex_mats=%d", complex_mats);
+    const int nc = complex_mats ? 2 : 1;  // doubles per matrix entry
+    using cd = std::complex<double>;
+    auto entry = [&](const double *M, size_t k) { return complex_mats ? cd(M[2 * k], M[2 * k + 1]) : cd(M[k], 0.0); };
     // check every term; offsets of its sites and matrix
     std::vector<size_t> site_off(num_terms + 1, 0), mat_off(num_terms + 1, 0);
     for (int t = 0; t < num_terms; ++t) {
@@ -203,7 +242,7 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
         const uint32_t n = ipow(Q, m);
         if (n > kOpMaxLocal) return set_error(DCS_EUNSUPPORTED, "term %d: Q^m = %u > %u", t, n, kOpMaxLocal);
         site_off[t + 1] = site_off[t] + (size_t)m;
-        mat_off[t + 1] = mat_off[t] + (size_t)n * n;
+        mat_off[t + 1] = mat_off[t] + (size_t)n * n * nc;
     }
     for (int t = 0; t < num_terms; ++t) {
         const int m = term_nsites[t];
@@ -218,8 +257,9 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
         const double *M = term_mats + mat_off[t];
         for (uint32_t b = 0; b < n; ++b)
             for (uint32_t a = 0; a < n; ++a) {
-                const double v = M[(size_t)b * n + a];
-                if (!std::isfinite(v)) return set_error(DCS_EINVAL, "term %d: matrix entry not finite", t);
+                const cd v = entry(M, (size_t)b * n + a);
+                if (!std::isfinite(v.real()) || !std::isfinite(v.imag()))
+                    return set_error(DCS_EINVAL, "term %d: matrix entry not finite", t);
                 if (v != 0.0 && digit_sum_local(b, m, Q) != digit_sum_local(a, m, Q))
                     return set_error(DCS_EINVAL,
                                      "term %d does not conserve the particle number (entry %u, %u)", t, b, a);
@@ -252,7 +292,7 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
     const int nb = (Q - 1) > 0 ? 32 - __builtin_clz((unsigned)(Q - 1)) : 1;
     std::vector<OpCluster> hcl(cl_sites.size());
     std::vector<uint32_t> rowptr, dep;
-    std::vector<double> val;
+    std::vector<std::complex<double>> val;
     int max_sites = 0;
     for (size_t c = 0; c < cl_sites.size(); ++c) {
         const int m = (int)cl_sites[c].size();
@@ -273,7 +313,7 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
                 uint32_t at = 0;
                 for (int j = 0; j < mt; ++j) at = at * (uint32_t)Q + (uint32_t)da[p[j]];
                 for (uint32_t bt = 0; bt < nt; ++bt) {
-                    const double v = M[(size_t)bt * nt + at];
+                    const cd v = entry(M, (size_t)bt * nt + at);
                     if (v == 0.0) continue;
                     int db[kOpMaxSites];
                     std::copy(da, da + m, db);
@@ -297,7 +337,7 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
             rowptr.push_back((uint32_t)val.size());
             while (e < ents.size() && ents[e].row == b) {
                 const uint32_t col = ents[e].col;
-                double v = 0.0;
+                cd v = 0.0;
                 while (e < ents.size() && ents[e].row == b && ents[e].col == col) v += ents[e++].v;
                 if (v == 0.0) continue;
                 uint32_t d = 0;
@@ -317,6 +357,7 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
     o->ncl = (int)hcl.size();
     o->max_sites = max_sites;
     o->nnz = val.size();
+    o->cplx = complex_mats != 0;
     // two blobs (FP64 and FP32 values), each clusters | row pointers | digits | values
     auto a16 = [](uint64_t b) { return (b + 15) / 16 * 16; };
     const uint64_t b_cl = a16(std::max<size_t>(hcl.size(), 1) * sizeof(OpCluster));
@@ -324,12 +365,13 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
     o->off_rp = (uint32_t)b_cl;
     o->off_dep = (uint32_t)(b_cl + b_rp);
     o->off_val = (uint32_t)(b_cl + b_rp + b_dep);
-    if (b_cl + b_rp + b_dep + a16(val.size() * 8) > 0xFFFFFFF0ull) {
+    const uint64_t vb = o->cplx ? 16 : 8;  // bytes of one FP64 value
+    if (b_cl + b_rp + b_dep + a16(val.size() * vb) > 0xFFFFFFF0ull) {
         delete o;
         return set_error(DCS_EUNSUPPORTED, "operator arrays beyond 4 GiB");
     }
-    o->bytes64 = o->off_val + a16(std::max<size_t>(val.size(), 1) * 8);
-    o->bytes32 = o->off_val + a16(std::max<size_t>(val.size(), 1) * 4);
+    o->bytes64 = o->off_val + a16(std::max<size_t>(val.size(), 1) * vb);
+    o->bytes32 = o->off_val + a16(std::max<size_t>(val.size(), 1) * vb / 2);
     const uint64_t at32 = (o->bytes64 + 255) / 256 * 256;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
@@ -353,10 +395,11 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
         if (!rowptr.empty()) memcpy(h->data() + o->off_rp, rowptr.data(), rowptr.size() * 4);
         if (!dep.empty()) memcpy(h->data() + o->off_dep, dep.data(), dep.size() * 4);
     }
-    if (!val.empty()) memcpy(h64.data() + o->off_val, val.data(), val.size() * 8);
     for (size_t e = 0; e < val.size(); ++e) {
-        const float f = (float)val[e];
-        memcpy(h32.data() + o->off_val + e * 4, &f, 4);
+        const double d2[2] = {val[e].real(), val[e].imag()};
+        const float f2[2] = {(float)d2[0], (float)d2[1]};
+        memcpy(h64.data() + o->off_val + e * vb, d2, vb);
+        memcpy(h32.data() + o->off_val + e * vb / 2, f2, vb / 2);
     }
     int r = check_hip(hipMemcpy(base, h64.data(), h64.size(), hipMemcpyHostToDevice), "operator upload");
     if (!r) r = check_hip(hipMemcpy(base + at32, h32.data(), h32.size(), hipMemcpyHostToDevice), "operator upload");
@@ -399,9 +442,13 @@ extern "C" int dcs_operator_apply(const dcs_sector *s, const dcs_operator *o, in
                          s->desc.L);
     if (o->device != s->device)
         return set_error(DCS_EINVAL, "operator on device %d, sector on device %d", o->device, s->device);
-    if (dtype != DCS_F32 && dtype != DCS_F64) return set_error(DCS_EINVAL, "dtype %d", dtype);
+    if (dtype != DCS_F32 && dtype != DCS_F64 && dtype != DCS_C64 && dtype != DCS_C128)
+        return set_error(DCS_EINVAL, "dtype %d", dtype);
+    const bool xc = dtype == DCS_C64 || dtype == DCS_C128;
+    const bool single = dtype == DCS_F32 || dtype == DCS_C64;
+    if (o->cplx && !xc) return set_error(DCS_EINVAL, "a complex operator needs complex vectors (DCS_C64 / DCS_C128)");
     if (!x || !y) return set_error(DCS_EINVAL, "NULL vector");
-    const size_t bytes = (size_t)s->desc.dim * (dtype == DCS_F32 ? 4 : 8);
+    const size_t bytes = (size_t)s->desc.dim * (single ? 4 : 8) * (xc ? 2 : 1);
     if ((const char *)y < (const char *)x + bytes && (const char *)x < (const char *)y + bytes)
         return set_error(DCS_EINVAL, "y overlaps x");
     DeviceGuard g(s->device);
@@ -409,8 +456,8 @@ extern "C" int dcs_operator_apply(const dcs_sector *s, const dcs_operator *o, in
     memset(&P, 0, sizeof(P));
     P.sd = s->desc;
     P.blob = (const char *)s->dev.base;
-    P.opblob = dtype == DCS_F32 ? o->blob32 : o->blob64;
-    P.op_bytes = (uint32_t)(dtype == DCS_F32 ? o->bytes32 : o->bytes64);
+    P.opblob = single ? o->blob32 : o->blob64;
+    P.op_bytes = (uint32_t)(single ? o->bytes32 : o->bytes64);
     P.off_rp = o->off_rp;
     P.off_dep = o->off_dep;
     P.off_val = o->off_val;
@@ -430,14 +477,21 @@ extern "C" int dcs_operator_apply(const dcs_sector *s, const dcs_operator *o, in
         kern<<<grid, kOpThreads, lds, st>>>(P);
         return check_hip(hipGetLastError(), "operator kernel launch");
     };
-    auto pick = [&](auto tag) -> int {
+    auto pick = [&](auto tag, auto vc, auto xcc) -> int {
         using T = decltype(tag);
+        constexpr bool VC = decltype(vc)::value, XC = decltype(xcc)::value;
         if (s->wide) {
-            if (s->gtab) return opl ? go(op_kernel<uint64_t, T, true, true>) : go(op_kernel<uint64_t, T, true, false>);
-            return opl ? go(op_kernel<uint64_t, T, false, true>) : go(op_kernel<uint64_t, T, false, false>);
+            if (s->gtab)
+                return opl ? go(op_kernel<uint64_t, T, VC, XC, true, true>) : go(op_kernel<uint64_t, T, VC, XC, true, false>);
+            return opl ? go(op_kernel<uint64_t, T, VC, XC, false, true>) : go(op_kernel<uint64_t, T, VC, XC, false, false>);
         }
-        if (s->gtab) return opl ? go(op_kernel<uint32_t, T, true, true>) : go(op_kernel<uint32_t, T, true, false>);
-        return opl ? go(op_kernel<uint32_t, T, false, true>) : go(op_kernel<uint32_t, T, false, false>);
+        if (s->gtab)
+            return opl ? go(op_kernel<uint32_t, T, VC, XC, true, true>) : go(op_kernel<uint32_t, T, VC, XC, true, false>);
+        return opl ? go(op_kernel<uint32_t, T, VC, XC, false, true>) : go(op_kernel<uint32_t, T, VC, XC, false, false>);
     };
-    return dtype == DCS_F32 ? pick(0.0f) : pick(0.0);
+    using F = std::false_type;
+    using Tt = std::true_type;
+    if (!xc) return single ? pick(0.0f, F{}, F{}) : pick(0.0, F{}, F{});
+    if (!o->cplx) return single ? pick(0.0f, F{}, Tt{}) : pick(0.0, F{}, Tt{});
+    return single ? pick(0.0f, Tt{}, Tt{}) : pick(0.0, Tt{}, Tt{});
 }

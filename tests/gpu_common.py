@@ -17,9 +17,10 @@ def to_host_u64(t: torch.Tensor) -> np.ndarray:
 
 
 def rel_err(y, y_ref) -> float:
-    """Norm-wise relative error |y - y_ref|_2 / |y_ref|_2 (FP64)."""
-    y = np.asarray(y, dtype=np.float64)
-    y_ref = np.asarray(y_ref, dtype=np.float64)
+    """Norm-wise relative error |y - y_ref|_2 / |y_ref|_2 (FP64, complex128 when either is complex)."""
+    cplx = np.iscomplexobj(y) or np.iscomplexobj(y_ref)
+    y = np.asarray(y, dtype=np.complex128 if cplx else np.float64)
+    y_ref = np.asarray(y_ref, dtype=np.complex128 if cplx else np.float64)
     den = np.linalg.norm(y_ref)
     return float(np.linalg.norm(y - y_ref) / (den if den > 0 else 1.0))
 

@@ -101,7 +101,7 @@ def test_operator_host_checks(lib):
         st = (C.c_int32 * max(len(sites), 1))(*sites)
         cf = (C.c_double * max(len(coefs), 1))(*coefs)
         mt = (C.c_double * max(len(mats), 1))(*mats)
-        return l.dcs_operator_create(Q, L, len(nsites), ns, st, cf, mt, cluster, 0, C.byref(out))
+        return l.dcs_operator_create(Q, L, len(nsites), ns, st, cf, mt, 0, cluster, 0, C.byref(out))
 
     sp = [0, 0, 1, 0]  # S+ of spin 1/2: <1|S+|0> = 1 (does not conserve)
     assert create(2, 4, [1], [2], [1.0], sp) == _lib.DCS_EINVAL
