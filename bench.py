@@ -134,9 +134,14 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
     per_r = timed(lambda: s.rank(states, out=idx))
     per_u = timed(lambda: s.unrank(idx, out=back))
     assert torch.equal(back, states)
+    idx2 = torch.empty_like(states)
+    per_rs = timed(lambda: s.rank_search(states, out=idx2))  # the sorted-list container
+    assert torch.equal(idx2, idx)
     out["rank_unrank_L32"] = {"states": cnt, "rank_ms": per_r * 1e3, "unrank_ms": per_u * 1e3,
                               "rank_per_s": cnt / per_r, "unrank_per_s": cnt / per_u,
-                              "rank_GBs": cnt * 16 / per_r / 1e9, "unrank_GBs": cnt * 16 / per_u / 1e9}
+                              "rank_GBs": cnt * 16 / per_r / 1e9, "unrank_GBs": cnt * 16 / per_u / 1e9,
+                              "rank_search_ms": per_rs * 1e3, "rank_search_per_s": cnt / per_rs}
+    del idx2
     del states, idx, back
 
     # FP32 adjoint on the L=32 sector: grad_x = H g and the 64 coupling sums
@@ -385,12 +390,15 @@ def split_sweep(dq, synth, torch, steps: int, warmup: int):
         per_r = median(time_steps(lambda: s.rank(states, out=idx), stream, steps, warmup))
         per_u = median(time_steps(lambda: s.unrank(idx, out=back), stream, steps, warmup))
         ok = bool(torch.equal(back, states))
+        per_rs = median(time_steps(lambda: s.rank_search(states, out=back), stream, steps, warmup))
+        ok = ok and bool(torch.equal(back, idx))
         t = dq.Terms(bonds)
         per_h = median(time_steps(lambda: dq.hamiltonian_apply(s, t, jd, zd, x, out=y), stream,
                                   max(3, steps // 4), 1))
         form = dq.hamiltonian_form(s, t, torch.float32, 1)
         rec = {"supported": True, "tables": "device" if s.tables_in_device_memory else "lds",
                "table_bytes": s.table_bytes, "rank_per_s": cnt / per_r, "unrank_per_s": cnt / per_u,
+               "rank_search_per_s": cnt / per_rs,
                "roundtrip_ok": ok, "hx_f32k1_ms": per_h * 1e3, "hx_states_per_s": s.dim / per_h,
                "form": form}
         if form != "single":

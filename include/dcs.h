@@ -158,6 +158,18 @@ int dcs_rank(const dcs_sector *sector, const uint64_t *d_states, uint64_t *d_idx
              uint64_t *d_num_invalid, void *stream);
 
 /*
+ * dcs_rank with the subsystem lookup kept as container (ii) of Sec. 4.2 instead of
+ * (i): each subsystem's index comes from a binary search for its word among the
+ * valid words of the same digit sum, stored in lexicographic order (the sector's
+ * inverse tables, D_Q(L_k, m) entries per digit sum m), not from the table indexed
+ * by the word's integer value (2^(L_k ceil(log2 Q)) entries); then eq. ck as
+ * dcs_rank.  Same results, invalid states and counting as dcs_rank; for comparing
+ * the containers on the device.
+ */
+int dcs_rank_search(const dcs_sector *sector, const uint64_t *d_states, uint64_t *d_idx,
+                    size_t count, uint64_t *d_num_invalid, void *stream);
+
+/*
  * Batched unrank, function (iii) of Sec. 2.2 / Alg. iii: d_states[t] = the state
  * with index d_idx[t].  Indices >= D give DCS_INVALID_INDEX (as a state value)
  * and are counted like dcs_rank's invalid states.

@@ -122,6 +122,17 @@ class Sector:
              _stream(self.device))
         return (out, cnt) if count_invalid else out
 
+    def rank_search(self, states: torch.Tensor, out: torch.Tensor | None = None, count_invalid=False):
+        """As ``rank``, with each subsystem's index found by binary search in its sorted
+        list of valid words (the sorted-list container, dcs_rank_search)."""
+        _check_dev(states, self.device, "states", (torch.int64, torch.uint64))
+        out = torch.empty_like(states) if out is None else out
+        _check_dev(out, self.device, "out", (torch.int64, torch.uint64), numel=states.numel())
+        cnt = self._counter(count_invalid)
+        call("dcs_rank_search", self._h, _ptr(states), _ptr(out), states.numel(), _ptr(cnt),
+             _stream(self.device))
+        return (out, cnt) if count_invalid else out
+
     def unrank(self, idx: torch.Tensor, out: torch.Tensor | None = None, count_invalid=False):
         _check_dev(idx, self.device, "idx", (torch.int64, torch.uint64))
         out = torch.empty_like(idx) if out is None else out

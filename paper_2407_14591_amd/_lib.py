@@ -48,6 +48,7 @@ SIGNATURES = {
     "dcs_lex_rank": (_i, [_i, _i, _vp, _vp, _sz, _vp, _vp]),
     "dcs_lex_unrank": (_i, [_i, _i, _vp, _vp, _sz, _vp, _vp]),
     "dcs_rank": (_i, [_vp, _vp, _vp, _sz, _vp, _vp]),
+    "dcs_rank_search": (_i, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "dcs_unrank": (_i, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "dcs_enumerate": (_i, [_vp, _u64, _sz, _vp, _vp]),
     "dcs_terms_create": (_i, [_i, _i32p, _i32p, _pp]),

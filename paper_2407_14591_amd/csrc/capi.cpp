@@ -55,6 +55,15 @@ extern "C" int dcs_rank(const dcs_sector *s, const uint64_t *st, uint64_t *idx, 
     return launch_rank(s, st, idx, count, nbad, (hipStream_t)stream);
 }
 
+extern "C" int dcs_rank_search(const dcs_sector *s, const uint64_t *st, uint64_t *idx, size_t count,
+                               uint64_t *nbad, void *stream) {
+    clear_error();
+    if (!s) return set_error(DCS_EINVAL, "sector is NULL");
+    if (count == 0) return DCS_OK;
+    if (!st || !idx) return set_error(DCS_EINVAL, "NULL array");
+    return launch_rank_search(s, st, idx, count, nbad, (hipStream_t)stream);
+}
+
 extern "C" int dcs_unrank(const dcs_sector *s, const uint64_t *idx, uint64_t *st, size_t count,
                           uint64_t *nbad, void *stream) {
     clear_error();

@@ -287,6 +287,8 @@ void note_split_use(dcs_sector *s, SplitRows &c, hipStream_t stream);
 // kernels launchers (index_kernels.hip, hx_kernels.hip, lanczos.hip)
 int launch_rank(const dcs_sector *s, const uint64_t *st, uint64_t *idx, size_t count,
                 uint64_t *nbad, hipStream_t stream);
+int launch_rank_search(const dcs_sector *s, const uint64_t *st, uint64_t *idx, size_t count,
+                       uint64_t *nbad, hipStream_t stream);
 int launch_unrank(const dcs_sector *s, const uint64_t *idx, uint64_t *st, size_t count,
                   uint64_t *nbad, hipStream_t stream);
 int launch_enumerate(const dcs_sector *s, uint64_t first, size_t count, uint64_t *st,

@@ -43,6 +43,72 @@ __global__ __launch_bounds__(kThreads) void rank_kernel(SectorDesc sd_arg, const
     }
 }
 
+// Container (ii) of Sec. 4.2: each subsystem's local index from a search among the
+// valid words of its digit sum in lexicographic (numeric) order -- the inverse
+// table, a sorted list -- instead of the dense table indexed by the word; then
+// c_k = offset_k(m, lambda) + stride_k(m, lambda) * index (eq. ck), the last
+// subsystem contributing its index.  Words with a digit >= Q are not in the list.
+template <typename IdxT, bool GT>
+__global__ __launch_bounds__(kThreads) void rank_search_kernel(SectorDesc sd_arg, const char *blob,
+                                                               const uint64_t *__restrict__ st,
+                                                               uint64_t *__restrict__ out, size_t count,
+                                                               uint64_t *nbad) {
+    (void)sd_arg;
+    const SectorDesc &sd = kernel_arg0<SectorDesc>();
+    extern __shared__ __align__(16) char lds[];
+    if constexpr (!GT) {
+        stage_blob(lds, blob, sd.lay_bytes);
+        __syncthreads();
+    }
+    const Tables<IdxT> T = tables_at<IdxT>(GT ? blob : lds, sd);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t base = (size_t)blockIdx.x * blockDim.x; base < count; base += stride) {
+        const size_t i = base + threadIdx.x;
+        bool bad = false;
+        if (i < count) {
+            const uint64_t s = st[i];
+            bad = sd.total_bits < 64 && (s >> sd.total_bits) != 0;
+            IdxT idx = 0;
+            int lam = 0;
+            for (int k = 0; k < sd.N && !bad; ++k) {
+                const uint32_t w = sub_word(sd, s, k);
+                const int m = digit_sum(sd, w);
+                if (m > sd.mk[k] || lam < sd.lam_lo[k] || lam > sd.lam_hi[k]) {
+                    bad = true;
+                    break;
+                }
+                const uint32_t b = T.invs[sd.inv_start0[k] + m], e = T.invs[sd.inv_start0[k] + m + 1];
+                uint32_t lo = b, hi = e;
+                while (lo < hi) {  // first entry >= w
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if ((uint32_t)T.inv[mid] < w) lo = mid + 1;
+                    else hi = mid;
+                }
+                if (lo == e || (uint32_t)T.inv[lo] != w) {
+                    bad = true;
+                    break;
+                }
+                const IdxT sigma = (IdxT)(lo - b);
+                if (k < sd.N - 1) {
+                    const uint32_t row = sd.dec_row0[k] + (uint32_t)(lam - sd.lam_lo[k]) * (sd.mk[k] + 1) + m;
+                    const IdxT str = T.dstr[row];
+                    if (str == 0) {  // no completion of this prefix has n particles
+                        bad = true;
+                        break;
+                    }
+                    idx += T.doff[row] + str * sigma;
+                } else {
+                    idx += sigma;
+                }
+                lam += m;
+            }
+            bad = bad || lam != sd.n;
+            out[i] = bad ? DCS_INVALID_INDEX : (uint64_t)idx;
+        }
+        count_bad(nbad, bad);
+    }
+}
+
 template <typename IdxT, bool GT>
 __global__ __launch_bounds__(kThreads) void unrank_kernel(SectorDesc sd_arg, const char *blob,
                                                           const uint64_t *__restrict__ idx,
@@ -92,6 +158,21 @@ int launch_rank(const dcs_sector *s, const uint64_t *st, uint64_t *idx, size_t c
     };
     if (s->wide) return s->gtab ? go(rank_kernel<uint64_t, true>) : go(rank_kernel<uint64_t, false>);
     return s->gtab ? go(rank_kernel<uint32_t, true>) : go(rank_kernel<uint32_t, false>);
+}
+
+int launch_rank_search(const dcs_sector *s, const uint64_t *st, uint64_t *idx, size_t count,
+                       uint64_t *nbad, hipStream_t stream) {
+    DeviceGuard g(s->device);
+    const int grid = grid_for(s, count);
+    const char *blob = (const char *)s->dev.base;
+    const size_t lds = s->gtab ? 0 : s->desc.lay_bytes;
+    auto go = [&](auto kern) -> int {
+        if (int r = ensure_lds(kern, lds)) return r;
+        kern<<<grid, kThreads, lds, stream>>>(s->desc, blob, st, idx, count, nbad);
+        return check_hip(hipGetLastError(), "rank (search) kernel launch");
+    };
+    if (s->wide) return s->gtab ? go(rank_search_kernel<uint64_t, true>) : go(rank_search_kernel<uint64_t, false>);
+    return s->gtab ? go(rank_search_kernel<uint32_t, true>) : go(rank_search_kernel<uint32_t, false>);
 }
 
 // unrank of idx[0..count) (use_first = 0) or of first, first + 1, ... (enumerate)

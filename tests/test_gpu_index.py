@@ -134,3 +134,40 @@ def test_full_sector_bijection_L32():
         pos += cnt
         say("bijection", pos)
     assert pos == s.dim == math.comb(32, 16)
+
+
+@pytest.mark.parametrize("bits", ["32", "64"])
+def test_rank_search_container_small(monkeypatch, bits):
+    """The sorted-list container (binary search per subsystem, dcs_rank_search) ranks
+    every state of ~100 small sectors as the sorted order says, bit-exact (both index
+    widths), and flags the same invalid states as dcs_rank."""
+    if bits == "64":
+        monkeypatch.setenv("DCS_INDEX_BITS", "64")
+    for Q, L, n, sp in cases():
+        b = BruteSector(Q, L, n, sp)
+        s = dq.Sector(L, n, Q, sp)
+        idx, bad = s.rank_search(to_dev(b.states), count_invalid=True)
+        assert np.array_equal(to_host_u64(idx), np.arange(b.dim, dtype=np.uint64)), (Q, L, n, sp)
+        assert int(bad.item()) == 0
+        s.close()
+    s = dq.Sector(9, 4, 2, [3, 3, 3])
+    bad_states = np.array([pack([1] * 5 + [0] * 4, 2), 0, 1 << 9, (1 << 9) | 0b1111, 0b111100000,
+                           ~np.uint64(0)], dtype=np.uint64)
+    a, ca = s.rank(to_dev(bad_states), count_invalid=True)
+    b_, cb = s.rank_search(to_dev(bad_states), count_invalid=True)
+    assert np.array_equal(to_host_u64(a), to_host_u64(b_)) and int(ca.item()) == int(cb.item()) == 5
+    s3 = dq.Sector(4, 4, 3, [2, 2])
+    st = np.array([pack([3, 1, 0, 0], 4), pack([2, 2, 0, 0], 4), pack([0, 0, 2, 3], 4)], dtype=np.uint64)
+    assert np.array_equal(to_host_u64(s3.rank_search(to_dev(st))), to_host_u64(s3.rank(to_dev(st))))
+
+
+@pytest.mark.parametrize("L,n,split", [(32, 16, [8, 8, 8, 8]), (32, 16, [16, 16]), (40, 20, [5] * 8),
+                                       (32, 4, [16, 16])])
+def test_rank_search_container_large(L, n, split):
+    """2^20 random states of large sectors (16-site subsystems with tables in device
+    memory, 64-bit indices, a low filling) against the C oracle."""
+    ns = native.NativeSector(2, L, n, split)
+    s = dq.Sector(L, n, 2, split)
+    states = synth.pack_digits(synth.random_states(2, L, n, 1 << 20, seed=L + n), 2)
+    got = to_host_u64(s.rank_search(to_dev(states)))
+    assert np.array_equal(got, ns.rank(states))
