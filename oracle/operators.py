@@ -142,3 +142,19 @@ def sector_matrix(bs: BruteSector, terms):
         idx = idx * Q + ((bs.states >> np.uint64(nb * (L - 1 - i))) & dmask).astype(np.int64)
     F = full_space_matrix(Q, L, terms)
     return F[np.ix_(idx, idx)]
+
+
+def lindbladian_dense(bs: BruteSector, h_terms, jumps, rho):
+    """L[rho] = -i [H, rho] + sum_k g_k (A_k rho A_k^+ - 1/2 {A_k^+ A_k, rho}) (the
+    Lindblad form the paper's operator class targets, Sec. 4.1), with H and every jump
+    operator A_k = coef_k M_k given as terms on the sector of ``bs`` (A_k must conserve
+    the particle number so that the (n, n) block of rho maps to itself).  Dense
+    matrices in the sector basis; ``jumps`` is a list of (g_k, term)."""
+    H = sector_matrix(bs, h_terms)
+    rho = np.asarray(rho, dtype=np.complex128)
+    out = -1j * (H @ rho - rho @ H)
+    for g, term in jumps:
+        A = sector_matrix(bs, [term])
+        AdA = A.conj().T @ A
+        out += g * (A @ rho @ A.conj().T - 0.5 * (AdA @ rho + rho @ AdA))
+    return out

@@ -114,3 +114,28 @@ def test_complex_push_form_against_full_space(Q, L, n):
     assert np.allclose(apply_operator(bs, terms, x), A @ x, rtol=1e-12, atol=1e-12)
     H = sector_matrix(bs, [(1.3, (2, 3), dm)])
     assert np.allclose(H, H.conj().T) and np.abs(H.imag).max() > 0
+
+
+def test_lindbladian_dense_pins():
+    """Trace and Hermiticity preservation; a pure dephasing channel A = Sz_i damps each
+    element rho_ss' at the closed-form rate g/2 (m_i(s) - m_i(s'))^2; an eigenprojector
+    of H is stationary without jumps."""
+    from oracle.operators import lindbladian_dense
+    Q, L, n = 2, 6, 3
+    bs = BruteSector(Q, L, n)
+    rng = np.random.default_rng(4)
+    bonds = synth.chain_bonds(L, 1)
+    h_terms = xxz_terms(Q, bonds, rng.uniform(0.5, 1.5, len(bonds)), rng.normal(size=len(bonds)), rng.normal(size=L))
+    jumps = [(0.7, string(1.0, (2,), ("Sz",), Q)), (0.3, string(1.0, (0, 1), ("S+", "S-"), Q))]
+    R = rng.normal(size=(bs.dim, bs.dim)) + 1j * rng.normal(size=(bs.dim, bs.dim))
+    rho = R @ R.conj().T
+    out = lindbladian_dense(bs, h_terms, jumps, rho)
+    assert abs(np.trace(out)) < 1e-10 * np.abs(rho).sum()
+    assert np.allclose(out, out.conj().T, atol=1e-12)
+    g = 0.9
+    deph = lindbladian_dense(bs, [], [(g, string(1.0, (3,), ("Sz",), Q))], rho)
+    m = np.array([(int(st) >> (L - 1 - 3)) & 1 for st in bs.states]) - 0.5
+    assert np.allclose(deph, -g / 2 * (m[:, None] - m[None, :]) ** 2 * rho, atol=1e-12)
+    w, v = np.linalg.eigh(sector_matrix(bs, h_terms))
+    P = np.outer(v[:, 0], v[:, 0].conj())
+    assert np.abs(lindbladian_dense(bs, h_terms, [], P)).max() < 1e-12
