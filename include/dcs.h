@@ -370,9 +370,13 @@ typedef struct dcs_operator dcs_operator;
  * (d_0, .., d_{m-1}) over the listed sites being sum_j d_j Q^(m-1-j) (the first
  * listed site most significant).  An operator string such as S+_i S-_j is the
  * Kronecker product of its single-site matrices; a custom local operator is any
- * such matrix.  Every nonzero entry must join digit strings of equal digit sums
- * (the term conserves the particle number, so O maps each U(1) sector into
- * itself): DCS_EINVAL names the first term that does not.
+ * such matrix.  The sum of the terms merged into each cluster (below) must
+ * conserve the particle number, so that O maps each U(1) sector into itself:
+ * its entries that join digit strings of different digit sums must cancel (to
+ * 1e-13 of the cluster's largest entry; they are then dropped), else DCS_EINVAL
+ * names the cluster.  A single term need not conserve (Sx Sx and Sy Sy on one
+ * bond do not, their sum does) as long as the terms that restore it share its
+ * cluster.
  *
  * As in App. C, the terms are merged into clusters of sites: in the given order
  * a term joins the first cluster whose site set, extended by the term's sites,

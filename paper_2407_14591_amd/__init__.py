@@ -23,7 +23,8 @@ from ._lib import (DCS_F32, DCS_F64, DCS_INVALID_INDEX, DCS_REORTH_FULL, DCS_REO
 __all__ = ["Sector", "Terms", "Plan", "hamiltonian_apply", "hamiltonian_apply_adjoint",
            "hamiltonian_form", "hamiltonian_apply_adjoint_noalloc",
            "HApply", "lanczos", "tridiag_eigvals", "lex_rank", "lex_unrank", "expectation_values", "DcsError", "DCS_INVALID_INDEX",
-           "library_path", "Operator", "operator_apply", "local_operator", "operator_string"]
+           "library_path", "Operator", "operator_apply", "local_operator", "operator_string",
+           "lindbladian_terms"]
 
 
 def library_path() -> str:
@@ -213,6 +214,33 @@ def operator_string(coef: float, sites, names, Q: int):
     for nm in names:
         M = np.kron(M, local_operator(nm, Q))
     return (float(coef), tuple(int(s) for s in sites), M)
+
+
+def lindbladian_terms(L: int, hamiltonian, jumps):
+    """Terms of the Lindblad superoperator (Sec. 4.1's Lindbladian operators) on the
+    doubled chain of 2L sites: ket sites 0..L-1, bra sites L..2L-1, acting on
+    vec(rho) with vec(rho)[(s, s')] = rho_ss' (the ket state the high digits):
+
+        -i (H x I - I x H^T) + sum_k g_k (A_k x A_k^* - 1/2 A_k^+A_k x I - 1/2 I x (A_k^+A_k)^T)
+
+    ``hamiltonian``: terms (coef, sites, M); ``jumps``: (g_k, (coef, sites, M)) with
+    A_k = coef M.  Number-conserving H and A_k keep the ket and the bra particle
+    numbers, so the doubled sector of 2n particles holds the (n, n) block of rho."""
+    import numpy as np
+    out = []
+    for coef, sites, M in hamiltonian:
+        M = np.asarray(M)
+        bra = tuple(int(s) + L for s in sites)
+        out.append((1.0, tuple(sites), -1j * coef * M))
+        out.append((1.0, bra, 1j * coef * M.T))
+    for g, (coef, sites, M) in jumps:
+        A = coef * np.asarray(M, dtype=np.complex128)
+        AdA = A.conj().T @ A
+        bra = tuple(int(s) + L for s in sites)
+        out.append((float(g), tuple(sites) + bra, np.kron(A, A.conj())))
+        out.append((-0.5 * g, tuple(sites), AdA))
+        out.append((-0.5 * g, bra, AdA.T))
+    return out
 
 
 class Operator:

@@ -260,9 +260,6 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
                 const cd v = entry(M, (size_t)b * n + a);
                 if (!std::isfinite(v.real()) || !std::isfinite(v.imag()))
                     return set_error(DCS_EINVAL, "term %d: matrix entry not finite", t);
-                if (v != 0.0 && digit_sum_local(b, m, Q) != digit_sum_local(a, m, Q))
-                    return set_error(DCS_EINVAL,
-                                     "term %d does not conserve the particle number (entry %u, %u)", t, b, a);
             }
     }
     // clusters (App. C): greedy, in the order of the terms
@@ -333,12 +330,28 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
         C.row0 = (uint32_t)rowptr.size();
         if (val.size() + ents.size() > 0xFFFFFFF0ull) return set_error(DCS_EUNSUPPORTED, "more than 2^32 entries");
         size_t e = 0;
+        // the cluster's sum must conserve the particle number (a single term need not:
+        // Sx Sx and Sy Sy on one bond change it, their sum does not); entries that join
+        // different digit sums must cancel to rounding, relative to the cluster's largest
+        double vmax = 0.0;
+        for (const Entry &en : ents) vmax = std::max(vmax, std::abs(en.v));
         for (uint32_t b = 0; b < n; ++b) {
             rowptr.push_back((uint32_t)val.size());
             while (e < ents.size() && ents[e].row == b) {
                 const uint32_t col = ents[e].col;
                 cd v = 0.0;
-                while (e < ents.size() && ents[e].row == b && ents[e].col == col) v += ents[e++].v;
+                double vabs = 0.0;  // magnitude of the summed contributions
+                while (e < ents.size() && ents[e].row == b && ents[e].col == col) {
+                    vabs += std::abs(ents[e].v);
+                    v += ents[e++].v;
+                }
+                if (digit_sum_local(b, m, Q) != digit_sum_local(col, m, Q)) {
+                    if (std::abs(v) > 1e-13 * std::max(vabs, vmax))
+                        return set_error(DCS_EINVAL,
+                                         "the terms on sites of cluster %zu do not conserve the particle number "
+                                         "(entry %u, %u)", c, b, col);
+                    continue;
+                }
                 if (v == 0.0) continue;
                 uint32_t d = 0;
                 for (int j = 0; j < m; ++j) d |= (uint32_t)local_digit(col, j, m, Q) << (nb * j);

@@ -8,7 +8,7 @@ import torch
 
 import paper_2407_14591_amd as dq
 import synth
-from gpu_common import DEV, rel_err, say
+from gpu_common import DEV, rel_err, say, to_dev
 from oracle import native
 from oracle.operators import apply_operator
 from oracle.sector import BruteSector
@@ -230,3 +230,73 @@ def test_complex_sy_strings_and_hermiticity_L20():
     rhs = torch.vdot(dq.operator_apply(s, hop, u), v)
     say("hermiticity", lhs.item(), rhs.item())
     assert abs((lhs - rhs).item()) <= 1e-10 * abs(lhs.item())
+
+
+def heisenberg_sxsysz(L, Q=2):
+    """The Heisenberg chain with open boundaries as Sx Sx, Sy Sy and Sz Sz strings, each
+    its own term (as Sec. 4.1's example adds them): Sx Sx and Sy Sy alone change the
+    particle number, their sum in one cluster does not."""
+    terms = []
+    for i in range(L - 1):
+        for nm in ("Sx", "Sy", "Sz"):
+            terms.append(dq.operator_string(1.0, (i, i + 1), (nm, nm), Q))
+    return terms
+
+
+def test_sec41_example_hamiltonian_from_separate_sx_sy_sz():
+    """Sec. 4.1's Heisenberg chain (N = 10, n = 5, open) from separate Sx Sx, Sy Sy, Sz Sz
+    terms equals the XXZ product (Jxy = Jz = 1) on every row; an Sx Sx term alone is
+    refused."""
+    L, n = 10, 5
+    op = dq.Operator(2, L, heisenberg_sxsysz(L), cluster_sites=4)
+    s = dq.Sector(L, n, 2)
+    bonds = synth.chain_bonds(L, 1, periodic=False)
+    t = dq.Terms(bonds)
+    ones = torch.ones(len(bonds), dtype=torch.float64, device=DEV)
+    x = torch.tensor(synth.vector(s.dim, synth.SEED_X) + 1j * synth.vector(s.dim, synth.SEED_G), device=DEV)
+    y = dq.operator_apply(s, op, x)
+    ref = torch.complex(dq.hamiltonian_apply(s, t, ones, ones, x.real.contiguous()),
+                        dq.hamiltonian_apply(s, t, ones, ones, x.imag.contiguous()))
+    assert rel_err(y.cpu().numpy(), ref.cpu().numpy()) <= 1e-12
+    with pytest.raises(dq.DcsError):
+        dq.Operator(2, L, [dq.operator_string(1.0, (0, 1), ("Sx", "Sx"), 2)])
+
+
+@pytest.mark.parametrize("L,n", [(6, 3), (8, 4)])
+def test_lindbladian_on_the_doubled_chain(L, n):
+    """Sec. 4.1's Lindbladian example (Heisenberg chain from Sx, Sy, Sz strings, a
+    dephasing jump Sz on site 0) plus a hopping jump S+_1 S-_2, as a complex operator on
+    the doubled chain of 2L sites and 2n particles: L[rho] of a random density matrix
+    against the oracle's dense Lindbladian (complex128 1e-12, complex64 1e-5); the
+    result is traceless and Hermitian."""
+    from oracle.operators import lindbladian_dense
+    Q = 2
+    h = heisenberg_sxsysz(L)
+    jumps = [(1.0, dq.operator_string(1.0, (0,), ("Sz",), Q)), (0.4, dq.operator_string(1.0, (1, 2), ("S+", "S-"), Q))]
+    op = dq.Operator(Q, 2 * L, dq.lindbladian_terms(L, h, jumps), cluster_sites=4)
+    assert op.is_complex
+    bs = BruteSector(Q, L, n)
+    rng = np.random.default_rng(L)
+    R = rng.normal(size=(bs.dim, bs.dim)) + 1j * rng.normal(size=(bs.dim, bs.dim))
+    rho = R @ R.conj().T
+    rho /= np.trace(rho).real
+    ref = lindbladian_dense(bs, h, jumps, rho)
+    # vec(rho) in the doubled sector: the position of every (s, s') pair
+    big = dq.Sector(2 * L, 2 * n, Q)
+    pairs = (bs.states[:, None] << np.uint64(L)) | bs.states[None, :]
+    pos = torch.tensor(big.rank(to_dev(pairs.ravel())).cpu().numpy(), device=DEV)
+    for dt, tol in ((torch.complex128, 1e-12), (torch.complex64, 1e-5)):
+        v = torch.zeros(big.dim, dtype=dt, device=DEV)
+        v[pos] = torch.tensor(rho.ravel(), device=DEV).to(dt)
+        out = dq.operator_apply(big, op, v)
+        got = out[pos].to(torch.complex128).cpu().numpy().reshape(bs.dim, bs.dim)
+        err = rel_err(got, ref)
+        say("lindbladian", L, n, dt, op.num_clusters, err)
+        assert err <= tol
+        if dt == torch.complex128:
+            assert abs(np.trace(got)) <= 1e-12 * np.abs(got).sum()
+            assert np.abs(got - got.conj().T).max() <= 1e-12 * np.abs(got).max()
+            # nothing leaves the (n, n) block
+            outside = out.clone()
+            outside[pos] = 0
+            assert outside.abs().max().item() <= 1e-14 * out.abs().max().item()
