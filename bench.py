@@ -344,6 +344,24 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
                                      "frac_of_peak": s.dim * 32 / per_c / 1e9 / PEAK_HBM_GBS}
     del xc, yc
     del op, s, t
+
+    # Sec. 4.1's Lindbladian example at L=12, n=6 (Heisenberg chain from Sx, Sy, Sz strings,
+    # dephasing on site 0) on the doubled chain of 24 sites and 12 particles, complex128
+    Lh, nh = 12, 6
+    hterms = [dq.operator_string(1.0, (i, i + 1), (nm, nm), 2) for i in range(Lh - 1) for nm in ("Sx", "Sy", "Sz")]
+    lop = dq.Operator(2, 2 * Lh, dq.lindbladian_terms(Lh, hterms, [(1.0, dq.operator_string(1.0, (0,), ("Sz",), 2))]),
+                      cluster_sites=4)
+    big = dq.Sector(2 * Lh, 2 * nh, 2, device=0)
+    xc = torch.complex(torch.randn(big.dim, generator=g, device=dev, dtype=torch.float64),
+                       torch.randn(big.dim, generator=g, device=dev, dtype=torch.float64))
+    yc = torch.empty_like(xc)
+    per_l = timed(lambda: dq.operator_apply(big, lop, xc, out=yc), n=max(3, steps // 4), w=1)
+    out["lindbladian_L12_c128"] = {"ms": per_l * 1e3, "doubled_sector_dim": big.dim,
+                                   "clusters": lop.num_clusters, "nnz": lop.nnz,
+                                   "states_per_s": big.dim / per_l,
+                                   "achieved_GBs": big.dim * 32 / per_l / 1e9,
+                                   "frac_of_peak": big.dim * 32 / per_l / 1e9 / PEAK_HBM_GBS}
+    del xc, yc, lop, big
     torch.cuda.empty_cache()
     return out
 
