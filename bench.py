@@ -343,6 +343,14 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
                                      "achieved_GBs": s.dim * 32 / per_c / 1e9,
                                      "frac_of_peak": s.dim * 32 / per_c / 1e9 / PEAK_HBM_GBS}
     del xc, yc
+    # a block of 8 FP32 columns (one unrank and one rank per reached state serve all 8)
+    xb = torch.randn((s.dim, 8), generator=g, device=dev, dtype=torch.float32)
+    yb = torch.empty_like(xb)
+    per_b = timed(lambda: dq.operator_apply(s, op, xb, out=yb), n=max(3, steps // 4), w=1)
+    out["operator_L28_appd_f32k8"] = {"ms": per_b * 1e3, "columns_per_s": s.dim * 8 / per_b,
+                                      "achieved_GBs": s.dim * 8 * 8 / per_b / 1e9,
+                                      "frac_of_peak": s.dim * 8 * 8 / per_b / 1e9 / PEAK_HBM_GBS}
+    del xb, yb
     del op, s, t
 
     # Sec. 4.1's Lindbladian example at L=12, n=6 (Heisenberg chain from Sx, Sy, Sz strings,

@@ -399,17 +399,19 @@ int dcs_operator_info(const dcs_operator *op, int *num_clusters, uint64_t *nnz,
                       int *max_cluster_sites);
 
 /*
- * d_y = O d_x on one sector (Q and L of the operator, same device), vectors of D
- * entries of dtype: DCS_F32 / DCS_F64 for a real operator, DCS_C64 / DCS_C128
+ * d_y = O d_x on one sector (Q and L of the operator, same device): d_x, d_y of
+ * D rows of dtype, DCS_F32 / DCS_F64 for a real operator, DCS_C64 / DCS_C128
  * (interleaved re, im) for a real or a complex one (a complex operator on real
  * vectors is DCS_EINVAL); the stored values are rounded to FP32 for the FP32
- * types.  Pull form: one thread per row s unranks s (Alg. iii), and per cluster
+ * types.  Real vectors may be blocks of k columns, [D][k] row-major with k in
+ * {1, 2, 4, 8} (one unrank and one rank per reached state serve all k); complex
+ * vectors take k = 1 (else DCS_EUNSUPPORTED).  Pull form: one thread per row s unranks s (Alg. iii), and per cluster
  * reads s's local index on the cluster's sites, walks that row of the cluster
  * matrix, writes each entry's digits into s, ranks the result (eq. index; a
  * diagonal entry keeps s) and accumulates value * x there.  d_y must not overlap
  * d_x (DCS_EINVAL).  Asynchronous on `stream`.
  */
-int dcs_operator_apply(const dcs_sector *sector, const dcs_operator *op, int dtype,
+int dcs_operator_apply(const dcs_sector *sector, const dcs_operator *op, int dtype, int k,
                        const void *d_x, void *d_y, void *stream);
 
 /* ========================================================================== */

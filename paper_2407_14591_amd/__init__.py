@@ -292,15 +292,19 @@ class Operator:
 
 
 def operator_apply(sector: "Sector", op: Operator, x, out=None):
-    """y = O x on the sector (dcs_operator_apply), x of shape [dim]: float32 / float64,
-    or complex64 / complex128 (required for a complex operator)."""
+    """y = O x on the sector (dcs_operator_apply): x of shape [dim] or, for float32 /
+    float64, a block [dim, k] (k in 1, 2, 4, 8); complex64 / complex128 vectors of
+    shape [dim] (required for a complex operator)."""
     codes = {torch.float32: _lib.DCS_F32, torch.float64: _lib.DCS_F64, torch.complex64: _lib.DCS_C64,
              torch.complex128: _lib.DCS_C128}
-    _check_dev(x, sector.device, "x", tuple(codes), shape=(sector.dim,))
+    _check_dev(x, sector.device, "x", tuple(codes))
+    k = _block_shape(sector, x)
+    if x.is_complex() and k != 1:
+        raise ValueError("complex vectors take one column")
     out = torch.empty_like(x) if out is None else out
     _check_dev(out, sector.device, "out", x.dtype, shape=x.shape)
     dt = codes[x.dtype]
-    call("dcs_operator_apply", sector._h, op._h, dt, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
+    call("dcs_operator_apply", sector._h, op._h, dt, k, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
          _stream(sector.device))
     return out
 

@@ -72,7 +72,7 @@ SIGNATURES = {
     "dcs_operator_create": (_i, [_i, _i, _i, _i32p, _i32p, _dp, _dp, _i, _i, _i, _pp]),
     "dcs_operator_destroy": (_i, [_vp]),
     "dcs_operator_info": (_i, [_vp, _ip, _u64p, _ip]),
-    "dcs_operator_apply": (_i, [_vp, _vp, _i, _vp, _vp, _vp]),
+    "dcs_operator_apply": (_i, [_vp, _vp, _i, _i, _vp, _vp, _vp]),
 }
 
 

@@ -69,11 +69,17 @@ struct OpScalar<T, true> {
         T re, im;
     };
 };
-template <typename X, typename V>
-__device__ __forceinline__ void op_fma(X &acc, const V &v, const X &x) {
-    if constexpr (std::is_arithmetic<X>::value) {
-        acc += v * x;
-    } else if constexpr (std::is_arithmetic<V>::value) {  // real value, complex vector
+// A row of K real columns as one vector (K > 1).
+template <typename T, int K>
+struct OpVecK {
+    typedef T type __attribute__((ext_vector_type(K)));
+};
+
+template <bool VC, bool XC, typename A, typename V>
+__device__ __forceinline__ void op_fma(A &acc, const V &v, const A &x) {
+    if constexpr (!XC) {
+        acc += v * x;  // real value on a real row (one column or K)
+    } else if constexpr (!VC) {  // real value, complex vector
         acc.re += v * x.re;
         acc.im += v * x.im;
     } else {  // complex value and vector
@@ -82,11 +88,14 @@ __device__ __forceinline__ void op_fma(X &acc, const V &v, const X &x) {
     }
 }
 
-template <typename IdxT, typename T, bool VC, bool XC, bool GT, bool OPL>
+// K: columns of a block [D][K] of real vectors (one unrank and one rank per target
+// serve all K); complex vectors take one column.
+template <typename IdxT, typename T, bool VC, bool XC, bool GT, bool OPL, int K>
 __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
     static_assert(XC || !VC, "a complex operator needs complex vectors");
+    static_assert(!XC || K == 1, "complex vectors take one column");
     using V = typename OpScalar<T, VC>::type;
-    using X = typename OpScalar<T, XC>::type;
+    using X = std::conditional_t<(K > 1), typename OpVecK<T, K>::type, typename OpScalar<T, XC>::type>;
     (void)P_arg;
     const OpParams &P = kernel_arg0<OpParams>();
     const SectorDesc &sd = P.sd;
@@ -161,7 +170,7 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
                 X xt;
                 if (t < sd.dim) xt = x[t];
                 else memset(&xt, 0, sizeof(xt));
-                op_fma(acc, val[e], xt);
+                op_fma<VC, XC>(acc, val[e], xt);
             }
         }
         y[i] = acc;
@@ -446,8 +455,8 @@ extern "C" int dcs_operator_info(const dcs_operator *o, int *num_clusters, uint6
     return DCS_OK;
 }
 
-extern "C" int dcs_operator_apply(const dcs_sector *s, const dcs_operator *o, int dtype, const void *x, void *y,
-                                  void *stream) {
+extern "C" int dcs_operator_apply(const dcs_sector *s, const dcs_operator *o, int dtype, int k, const void *x,
+                                  void *y, void *stream) {
     clear_error();
     if (!s || !o) return set_error(DCS_EINVAL, "NULL sector or operator");
     if (o->Q != s->desc.Q || o->L != s->desc.L)
@@ -460,8 +469,10 @@ extern "C" int dcs_operator_apply(const dcs_sector *s, const dcs_operator *o, in
     const bool xc = dtype == DCS_C64 || dtype == DCS_C128;
     const bool single = dtype == DCS_F32 || dtype == DCS_C64;
     if (o->cplx && !xc) return set_error(DCS_EINVAL, "a complex operator needs complex vectors (DCS_C64 / DCS_C128)");
+    if (k != 1 && k != 2 && k != 4 && k != 8) return set_error(DCS_EINVAL, "k=%d not in {1,2,4,8}", k);
+    if (xc && k != 1) return set_error(DCS_EUNSUPPORTED, "complex vectors take one column (k=%d)", k);
     if (!x || !y) return set_error(DCS_EINVAL, "NULL vector");
-    const size_t bytes = (size_t)s->desc.dim * (single ? 4 : 8) * (xc ? 2 : 1);
+    const size_t bytes = (size_t)s->desc.dim * (single ? 4 : 8) * (xc ? 2 : 1) * (size_t)k;
     if ((const char *)y < (const char *)x + bytes && (const char *)x < (const char *)y + bytes)
         return set_error(DCS_EINVAL, "y overlaps x");
     DeviceGuard g(s->device);
@@ -490,17 +501,32 @@ extern "C" int dcs_operator_apply(const dcs_sector *s, const dcs_operator *o, in
         kern<<<grid, kOpThreads, lds, st>>>(P);
         return check_hip(hipGetLastError(), "operator kernel launch");
     };
-    auto pick = [&](auto tag, auto vc, auto xcc) -> int {
+    auto pick_k = [&](auto tag, auto vc, auto xcc, auto kk) -> int {
         using T = decltype(tag);
         constexpr bool VC = decltype(vc)::value, XC = decltype(xcc)::value;
+        constexpr int K = decltype(kk)::value;
         if (s->wide) {
             if (s->gtab)
-                return opl ? go(op_kernel<uint64_t, T, VC, XC, true, true>) : go(op_kernel<uint64_t, T, VC, XC, true, false>);
-            return opl ? go(op_kernel<uint64_t, T, VC, XC, false, true>) : go(op_kernel<uint64_t, T, VC, XC, false, false>);
+                return opl ? go(op_kernel<uint64_t, T, VC, XC, true, true, K>)
+                           : go(op_kernel<uint64_t, T, VC, XC, true, false, K>);
+            return opl ? go(op_kernel<uint64_t, T, VC, XC, false, true, K>)
+                       : go(op_kernel<uint64_t, T, VC, XC, false, false, K>);
         }
         if (s->gtab)
-            return opl ? go(op_kernel<uint32_t, T, VC, XC, true, true>) : go(op_kernel<uint32_t, T, VC, XC, true, false>);
-        return opl ? go(op_kernel<uint32_t, T, VC, XC, false, true>) : go(op_kernel<uint32_t, T, VC, XC, false, false>);
+            return opl ? go(op_kernel<uint32_t, T, VC, XC, true, true, K>) : go(op_kernel<uint32_t, T, VC, XC, true, false, K>);
+        return opl ? go(op_kernel<uint32_t, T, VC, XC, false, true, K>) : go(op_kernel<uint32_t, T, VC, XC, false, false, K>);
+    };
+    auto pick = [&](auto tag, auto vc, auto xcc) -> int {
+        if constexpr (decltype(xcc)::value) {
+            return pick_k(tag, vc, xcc, std::integral_constant<int, 1>{});
+        } else {
+            switch (k) {
+                case 2: return pick_k(tag, vc, xcc, std::integral_constant<int, 2>{});
+                case 4: return pick_k(tag, vc, xcc, std::integral_constant<int, 4>{});
+                case 8: return pick_k(tag, vc, xcc, std::integral_constant<int, 8>{});
+                default: return pick_k(tag, vc, xcc, std::integral_constant<int, 1>{});
+            }
+        }
     };
     using F = std::false_type;
     using Tt = std::true_type;

@@ -300,3 +300,24 @@ def test_lindbladian_on_the_doubled_chain(L, n):
             outside = out.clone()
             outside[pos] = 0
             assert outside.abs().max().item() <= 1e-14 * out.abs().max().item()
+
+
+@pytest.mark.parametrize("k", [2, 4, 8])
+def test_operator_blocks(k):
+    """A block of k real columns equals k single-column products bit for bit (same
+    entry order per column) and the oracle on every row (FP64 and FP32)."""
+    Q, L, n = 2, 12, 5
+    terms = random_terms(Q, L, 40 + k)
+    op = dq.Operator(Q, L, terms, cluster_sites=4)
+    s = dq.Sector(L, n, Q, [4, 4, 4])
+    bs = BruteSector(Q, L, n, [4, 4, 4])
+    X = np.random.default_rng(k).normal(size=(bs.dim, k))
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        xb = torch.tensor(X, device=DEV).to(dt)
+        yb = dq.operator_apply(s, op, xb)
+        for c in range(k):
+            yc = dq.operator_apply(s, op, xb[:, c].contiguous())
+            assert torch.equal(yb[:, c], yc)
+            assert rel_err(yb[:, c].double().cpu().numpy(), apply_operator(bs, terms, X[:, c])) <= tol
+    with pytest.raises(ValueError):
+        dq.operator_apply(s, op, torch.zeros((s.dim, 3), device=DEV, dtype=torch.float64))
