@@ -394,9 +394,12 @@ int dcs_operator_create(int Q, int L, int num_terms, const int32_t *term_nsites,
                         int device, dcs_operator **out);
 int dcs_operator_destroy(dcs_operator *op);
 
-/* Clusters, stored nonzeros and the largest cluster's site count (any may be NULL). */
+/* Clusters, stored nonzeros, the largest cluster's site count, and whether the stored
+ * values are complex (any output may be NULL).  Complex terms whose merged sums are
+ * real (imaginary parts within 1e-13 of the largest entry, e.g. Sx Sx + Sy Sy) give
+ * a real operator. */
 int dcs_operator_info(const dcs_operator *op, int *num_clusters, uint64_t *nnz,
-                      int *max_cluster_sites);
+                      int *max_cluster_sites, int *is_complex);
 
 /*
  * d_y = O d_x on one sector (Q and L of the operator, same device): d_x, d_y of
@@ -497,6 +500,21 @@ int dcs_lanczos(const dcs_sector *sector, const dcs_terms *terms, const double *
                 const void *d_v0, double *h_alpha, double *h_beta, int *h_steps_done,
                 int num_eig, double *h_eig, void *d_vecs, int num_vec, void *d_workspace,
                 size_t workspace_bytes, void *stream);
+
+/*
+ * dcs_lanczos for a generic operator (dcs_operator_create) in place of the XXZ
+ * terms: the same iteration, re-orthogonalisation modes, Ritz values and vectors,
+ * workspace (dcs_lanczos_workspace_size) and graph replay, with w = O v from
+ * dcs_operator_apply's kernel.  O must be real symmetric on the sector (a real
+ * operator whose terms sum to a symmetric matrix: Sec. 4.1's Hamiltonians built
+ * from operator strings); the call does not check that.  Real vectors only
+ * (DCS_F32 / DCS_F64); a complex operator is DCS_EINVAL.
+ */
+int dcs_lanczos_operator(const dcs_sector *sector, const dcs_operator *op, int vec_dtype,
+                         int steps, int reorth, const void *d_v0, double *h_alpha,
+                         double *h_beta, int *h_steps_done, int num_eig, double *h_eig,
+                         void *d_vecs, int num_vec, void *d_workspace, size_t workspace_bytes,
+                         void *stream);
 
 /*
  * Eigenvalues of a symmetric tridiagonal matrix (diagonal h_alpha[m],

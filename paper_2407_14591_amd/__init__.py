@@ -253,11 +253,11 @@ class Operator:
         self.Q, self.L = int(Q), int(L)
         self.device = torch.cuda.current_device() if device is None else int(device)
         terms = list(terms)
-        self.is_complex = any(np.iscomplexobj(M) for _, _, M in terms)
+        cplx_in = any(np.iscomplexobj(M) for _, _, M in terms)
         nsites, sites, coefs, mats = [], [], [], []
         for coef, st, M in terms:
             st = [int(v) for v in st]
-            M = np.ascontiguousarray(M, dtype=np.complex128 if self.is_complex else np.float64)
+            M = np.ascontiguousarray(M, dtype=np.complex128 if cplx_in else np.float64)
             n = self.Q ** len(st)
             if M.shape != (n, n):
                 raise ValueError(f"term on {len(st)} sites needs a {n} x {n} matrix, got {M.shape}")
@@ -273,11 +273,12 @@ class Operator:
         self._mats = flat  # kept alive for the call
         self._h = C.c_void_p()
         call("dcs_operator_create", self.Q, self.L, nt, a_ns, a_st, a_cf,
-             flat.ctypes.data_as(C.POINTER(C.c_double)), int(self.is_complex), int(cluster_sites), self.device,
+             flat.ctypes.data_as(C.POINTER(C.c_double)), int(cplx_in), int(cluster_sites), self.device,
              C.byref(self._h))
-        ncl, nnz, mx = C.c_int(), C.c_uint64(), C.c_int()
-        call("dcs_operator_info", self._h, C.byref(ncl), C.byref(nnz), C.byref(mx))
+        ncl, nnz, mx, cx = C.c_int(), C.c_uint64(), C.c_int(), C.c_int()
+        call("dcs_operator_info", self._h, C.byref(ncl), C.byref(nnz), C.byref(mx), C.byref(cx))
         self.num_clusters, self.nnz, self.max_cluster_sites = ncl.value, nnz.value, mx.value
+        self.is_complex = bool(cx.value)  # complex terms with real sums make a real operator
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -408,14 +409,17 @@ class HApply(torch.autograd.Function):
         return gx, gj, gz, None, None
 
 
-def lanczos(sector: Sector, terms: Terms, jxy, jz, v0, steps: int, reorth="auto",
+def lanczos(sector: Sector, terms, jxy, jz, v0, steps: int, reorth="auto",
             num_eig: int = 1, want_vector=False, h=None, hbm_fraction: float = 0.5,
             num_vec: int = 0):
-    """Lanczos with FP64 scalars (dcs_lanczos).  Returns a dict with alpha, beta,
+    """Lanczos with FP64 scalars (dcs_lanczos; with an Operator in place of the terms,
+    dcs_lanczos_operator, jxy / jz / h unused).  Returns a dict with alpha, beta,
     steps_done, eig (lowest num_eig Ritz values), reorth mode, "vector" (the ground
     Ritz vector) and "vectors" ([num_vec, D], the Ritz vectors of the num_vec lowest
     Ritz values; want_vector=True alone asks for one)."""
-    _couplings(sector, terms, jxy, jz, h)
+    is_op = isinstance(terms, Operator)
+    if not is_op:
+        _couplings(sector, terms, jxy, jz, h)
     _check_dev(v0, sector.device, "v0", (torch.float32, torch.float64), shape=(sector.dim,))
     if steps < 1:
         raise ValueError("steps must be >= 1")
@@ -441,9 +445,13 @@ def lanczos(sector: Sector, terms: Terms, jxy, jz, v0, steps: int, reorth="auto"
     ne = max(1, num_eig)
     eig = (C.c_double * ne)()
     psi = torch.zeros((nvec, sector.dim), dtype=v0.dtype, device=v0.device) if nvec else None
-    call("dcs_lanczos", sector._h, terms._h, _ptr(jxy), _ptr(jz), _ptr(h), dtype, steps, mode,
-         _ptr(v0), alpha, beta, C.byref(done), ne, eig, _ptr(psi), nvec, _ptr(ws), nbytes.value,
-         _stream(sector.device))
+    if is_op:
+        call("dcs_lanczos_operator", sector._h, terms._h, dtype, steps, mode, _ptr(v0), alpha, beta,
+             C.byref(done), ne, eig, _ptr(psi), nvec, _ptr(ws), nbytes.value, _stream(sector.device))
+    else:
+        call("dcs_lanczos", sector._h, terms._h, _ptr(jxy), _ptr(jz), _ptr(h), dtype, steps, mode,
+             _ptr(v0), alpha, beta, C.byref(done), ne, eig, _ptr(psi), nvec, _ptr(ws), nbytes.value,
+             _stream(sector.device))
     m = done.value
     if psi is not None and m < nvec:
         psi = psi[:m]  # at most steps_done Ritz vectors exist

@@ -69,9 +69,10 @@ SIGNATURES = {
     "dcs_expectation_workspace_size": (_i, [_vp, _vp, _szp]),
     "dcs_expectation_values": (_i, [_vp, _vp, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "dcs_tridiag_eigvals": (_i, [_dp, _dp, _i, _i, _dp, _i]),
+    "dcs_lanczos_operator": (_i, [_vp, _vp, _i, _i, _i, _vp, _dp, _dp, _ip, _i, _dp, _vp, _i, _vp, _sz, _vp]),
     "dcs_operator_create": (_i, [_i, _i, _i, _i32p, _i32p, _dp, _dp, _i, _i, _i, _pp]),
     "dcs_operator_destroy": (_i, [_vp]),
-    "dcs_operator_info": (_i, [_vp, _ip, _u64p, _ip]),
+    "dcs_operator_info": (_i, [_vp, _ip, _u64p, _ip, _ip]),
     "dcs_operator_apply": (_i, [_vp, _vp, _i, _i, _vp, _vp, _vp]),
 }
 

@@ -289,6 +289,10 @@ int launch_rank(const dcs_sector *s, const uint64_t *st, uint64_t *idx, size_t c
                 uint64_t *nbad, hipStream_t stream);
 int launch_rank_search(const dcs_sector *s, const uint64_t *st, uint64_t *idx, size_t count,
                        uint64_t *nbad, hipStream_t stream);
+// generic operators (operator.hip): argument checks, and y = O x (no checks) on a stream
+int operator_check(const dcs_sector *s, const dcs_operator *o, int dtype, int k);
+int launch_operator(const dcs_sector *s, const dcs_operator *o, int dtype, int k, const void *x, void *y,
+                    hipStream_t stream);
 int launch_unrank(const dcs_sector *s, const uint64_t *idx, uint64_t *st, size_t count,
                   uint64_t *nbad, hipStream_t stream);
 int launch_enumerate(const dcs_sector *s, uint64_t first, size_t count, uint64_t *st,

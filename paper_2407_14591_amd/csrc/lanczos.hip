@@ -586,11 +586,12 @@ int replay_steps(StepFn &step, T *ring0, T *ring1, int m, hipStream_t stream) {
     return r;
 }
 
-template <typename T>
-int run_lanczos(const dcs_sector *s, const dcs_terms *t, const double *jxy, const double *jz,
-                const double *h, int dtype, int steps, int reorth, const void *v0, double *h_alpha,
-                double *h_beta, int *h_steps, int num_eig, double *h_eig, void *vecs, int num_vec,
-                char *ws, hipStream_t stream) {
+// apply(in, out, stream) launches w = A v for the operator of the run (the XXZ
+// Hamiltonian of a terms object, or a generic operator); it must be capturable.
+template <typename T, typename Apply>
+int run_lanczos(const dcs_sector *s, const Apply &apply, int dtype, int steps, int reorth,
+                const void *v0, double *h_alpha, double *h_beta, int *h_steps, int num_eig,
+                double *h_eig, void *vecs, int num_vec, char *ws, hipStream_t stream) {
     const uint64_t n = s->desc.dim;
     const Layout L = layout(s, dtype, steps, reorth, vecs ? num_vec : 0);
     T *V = (T *)(ws + L.V);
@@ -621,7 +622,7 @@ int run_lanczos(const dcs_sector *s, const dcs_terms *t, const double *jxy, cons
         // one step; the kernels take the step index from the device state, so the
         // same launches serve every step of one parity (u_j, u_{j-1}, u_{j+1} slots)
         auto step = [&](const T *uj, const T *ujm1, T *out, hipStream_t q) -> int {
-            if (int r = launch_hx(s, t, jxy, jz, h, dtype, 1, uj, w, q)) return r;
+            if (int r = apply(uj, w, q)) return r;
             k_gram<T><<<nb, kVecThreads, 0, q>>>(w, uj, ujm1, n, part, st);
             k_reduce<<<1, kReduceThreads, 0, q>>>(part, nb, 3, coef, 0, st, alpha, beta, 0, L.m);
             k_lz_coef<<<1, 64, 0, q>>>(coef, st, alpha, beta, rec, local);
@@ -650,7 +651,7 @@ int run_lanczos(const dcs_sector *s, const dcs_terms *t, const double *jxy, cons
         k_scale<T><<<nb, kVecThreads, 0, stream>>>((const T *)v0, vec(0), n, &st->inv_beta, nullptr);
         if (int r = chk("Lanczos start")) return r;
         for (int j = 0; j < L.m; ++j) {
-            if (int r = launch_hx(s, t, jxy, jz, h, dtype, 1, vec(j), w, stream)) return r;
+            if (int r = apply(vec(j), w, stream)) return r;
             k_sub_dot<T><<<nb, kVecThreads, 0, stream>>>(w, vec(j), j > 0 ? vec(j - 1) : nullptr,
                                                          j > 0 ? beta + j - 1 : nullptr, n, part, st);
             k_reduce<<<1, kReduceThreads, 0, stream>>>(part, nb, 1, nullptr, 1, st, alpha, beta, j,
@@ -722,7 +723,7 @@ int run_lanczos(const dcs_sector *s, const dcs_terms *t, const double *jxy, cons
         for (int e = 0; e < nv; ++e)
             k_axpy_rec<T><<<nb, kVecThreads, 0, stream>>>(psi_of(e), rv(0), n, svecs + (size_t)e * md, rec, 0, 1);
         for (int j = 0; j + 1 < md; ++j) {
-            if (int r = launch_hx(s, t, jxy, jz, h, dtype, 1, rv(j), w, stream)) return r;
+            if (int r = apply(rv(j), w, stream)) return r;
             k_lz_update<T><<<nb, kVecThreads, 0, stream>>>(w, rv(j), j > 0 ? rv(j - 1) : nullptr,
                                                            R + (uint64_t)((j + 1) & 1) * ring_stride(n), n,
                                                            rec, j, nullptr, nullptr);
@@ -779,11 +780,42 @@ extern "C" int dcs_lanczos(const dcs_sector *s, const dcs_terms *t, const double
     if (!ws || ws_bytes < L.total)
         return set_error(DCS_EINVAL, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
     DeviceGuard dg(s->device);
+    auto apply = [&](const void *in, void *out, hipStream_t q) {
+        return launch_hx(s, t, jxy, jz, h, dtype, 1, in, out, q);
+    };
     if (dtype == DCS_F32)
-        return run_lanczos<float>(s, t, jxy, jz, h, dtype, steps, reorth, v0, h_alpha, h_beta,
-                                  h_steps, num_eig, h_eig, vecs, num_vec, (char *)ws, (hipStream_t)stream);
-    return run_lanczos<double>(s, t, jxy, jz, h, dtype, steps, reorth, v0, h_alpha, h_beta, h_steps,
-                               num_eig, h_eig, vecs, num_vec, (char *)ws, (hipStream_t)stream);
+        return run_lanczos<float>(s, apply, dtype, steps, reorth, v0, h_alpha, h_beta, h_steps, num_eig, h_eig,
+                                  vecs, num_vec, (char *)ws, (hipStream_t)stream);
+    return run_lanczos<double>(s, apply, dtype, steps, reorth, v0, h_alpha, h_beta, h_steps, num_eig, h_eig,
+                               vecs, num_vec, (char *)ws, (hipStream_t)stream);
+}
+
+extern "C" int dcs_lanczos_operator(const dcs_sector *s, const dcs_operator *op, int dtype, int steps,
+                                    int reorth, const void *v0, double *h_alpha, double *h_beta,
+                                    int *h_steps, int num_eig, double *h_eig, void *vecs, int num_vec,
+                                    void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (!s || !op || !v0 || !h_steps) return set_error(DCS_EINVAL, "NULL argument");
+    if (dtype != DCS_F32 && dtype != DCS_F64) return set_error(DCS_EINVAL, "dtype %d", dtype);
+    if (reorth < DCS_REORTH_NONE || reorth > DCS_REORTH_FULL)
+        return set_error(DCS_EINVAL, "reorth %d", reorth);
+    if (steps < 1) return set_error(DCS_EINVAL, "steps %d < 1", steps);
+    if (num_eig < 0 || (num_eig > 0 && !h_eig)) return set_error(DCS_EINVAL, "num_eig / h_eig");
+    if (vecs && num_vec < 1) return set_error(DCS_EINVAL, "num_vec %d with a vector output", num_vec);
+    if (!vecs) num_vec = 0;
+    if (int r = operator_check(s, op, dtype, 1)) return r;
+    const Layout L = layout(s, dtype, steps, reorth, num_vec);
+    if (!ws || ws_bytes < L.total)
+        return set_error(DCS_EINVAL, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
+    DeviceGuard dg(s->device);
+    auto apply = [&](const void *in, void *out, hipStream_t q) {
+        return launch_operator(s, op, dtype, 1, in, out, q);
+    };
+    if (dtype == DCS_F32)
+        return run_lanczos<float>(s, apply, dtype, steps, reorth, v0, h_alpha, h_beta, h_steps, num_eig, h_eig,
+                                  vecs, num_vec, (char *)ws, (hipStream_t)stream);
+    return run_lanczos<double>(s, apply, dtype, steps, reorth, v0, h_alpha, h_beta, h_steps, num_eig, h_eig,
+                               vecs, num_vec, (char *)ws, (hipStream_t)stream);
 }
 
 extern "C" int dcs_tridiag_eigvals(const double *h_alpha, const double *h_beta, int m, int num,

@@ -379,7 +379,15 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
     o->ncl = (int)hcl.size();
     o->max_sites = max_sites;
     o->nnz = val.size();
-    o->cplx = complex_mats != 0;
+    // complex terms whose sums are real (Sx Sx + Sy Sy) make a real operator
+    double vmax_all = 0.0, imax = 0.0;
+    for (const cd &v : val) {
+        vmax_all = std::max(vmax_all, std::abs(v));
+        imax = std::max(imax, std::abs(v.imag()));
+    }
+    o->cplx = complex_mats != 0 && imax > 1e-13 * vmax_all;
+    if (!o->cplx)
+        for (cd &v : val) v = cd(v.real(), 0.0);
     // two blobs (FP64 and FP32 values), each clusters | row pointers | digits | values
     auto a16 = [](uint64_t b) { return (b + 15) / 16 * 16; };
     const uint64_t b_cl = a16(std::max<size_t>(hcl.size(), 1) * sizeof(OpCluster));
@@ -446,18 +454,22 @@ extern "C" int dcs_operator_destroy(dcs_operator *o) {
     return r;
 }
 
-extern "C" int dcs_operator_info(const dcs_operator *o, int *num_clusters, uint64_t *nnz, int *max_cluster_sites) {
+extern "C" int dcs_operator_info(const dcs_operator *o, int *num_clusters, uint64_t *nnz, int *max_cluster_sites,
+                                 int *is_complex) {
     clear_error();
     if (!o) return set_error(DCS_EINVAL, "operator is NULL");
+    if (is_complex) *is_complex = o->cplx ? 1 : 0;
     if (num_clusters) *num_clusters = o->ncl;
     if (nnz) *nnz = o->nnz;
     if (max_cluster_sites) *max_cluster_sites = o->max_sites;
     return DCS_OK;
 }
 
-extern "C" int dcs_operator_apply(const dcs_sector *s, const dcs_operator *o, int dtype, int k, const void *x,
-                                  void *y, void *stream) {
-    clear_error();
+namespace dcs {
+
+using namespace op;
+
+int operator_check(const dcs_sector *s, const dcs_operator *o, int dtype, int k) {
     if (!s || !o) return set_error(DCS_EINVAL, "NULL sector or operator");
     if (o->Q != s->desc.Q || o->L != s->desc.L)
         return set_error(DCS_EINVAL, "operator of Q=%d, L=%d on a sector of Q=%d, L=%d", o->Q, o->L, s->desc.Q,
@@ -467,14 +479,16 @@ extern "C" int dcs_operator_apply(const dcs_sector *s, const dcs_operator *o, in
     if (dtype != DCS_F32 && dtype != DCS_F64 && dtype != DCS_C64 && dtype != DCS_C128)
         return set_error(DCS_EINVAL, "dtype %d", dtype);
     const bool xc = dtype == DCS_C64 || dtype == DCS_C128;
-    const bool single = dtype == DCS_F32 || dtype == DCS_C64;
     if (o->cplx && !xc) return set_error(DCS_EINVAL, "a complex operator needs complex vectors (DCS_C64 / DCS_C128)");
     if (k != 1 && k != 2 && k != 4 && k != 8) return set_error(DCS_EINVAL, "k=%d not in {1,2,4,8}", k);
     if (xc && k != 1) return set_error(DCS_EUNSUPPORTED, "complex vectors take one column (k=%d)", k);
-    if (!x || !y) return set_error(DCS_EINVAL, "NULL vector");
-    const size_t bytes = (size_t)s->desc.dim * (single ? 4 : 8) * (xc ? 2 : 1) * (size_t)k;
-    if ((const char *)y < (const char *)x + bytes && (const char *)x < (const char *)y + bytes)
-        return set_error(DCS_EINVAL, "y overlaps x");
+    return DCS_OK;
+}
+
+int launch_operator(const dcs_sector *s, const dcs_operator *o, int dtype, int k, const void *x, void *y,
+                    hipStream_t stream) {
+    const bool xc = dtype == DCS_C64 || dtype == DCS_C128;
+    const bool single = dtype == DCS_F32 || dtype == DCS_C64;
     DeviceGuard g(s->device);
     OpParams P;
     memset(&P, 0, sizeof(P));
@@ -495,7 +509,7 @@ extern "C" int dcs_operator_apply(const dcs_sector *s, const dcs_operator *o, in
     const uint64_t blocks = (s->desc.dim + kOpThreads - 1) / kOpThreads;
     const uint64_t cap = (uint64_t)device_cu_count(s->device) * 8;
     const int grid = (int)std::max<uint64_t>(1, std::min(blocks, cap));
-    hipStream_t st = (hipStream_t)stream;
+    hipStream_t st = stream;
     auto go = [&](auto kern) -> int {
         if (int r = ensure_lds(kern, lds)) return r;
         kern<<<grid, kOpThreads, lds, st>>>(P);
@@ -533,4 +547,19 @@ extern "C" int dcs_operator_apply(const dcs_sector *s, const dcs_operator *o, in
     if (!xc) return single ? pick(0.0f, F{}, F{}) : pick(0.0, F{}, F{});
     if (!o->cplx) return single ? pick(0.0f, F{}, Tt{}) : pick(0.0, F{}, Tt{});
     return single ? pick(0.0f, Tt{}, Tt{}) : pick(0.0, Tt{}, Tt{});
+}
+
+}  // namespace dcs
+
+extern "C" int dcs_operator_apply(const dcs_sector *s, const dcs_operator *o, int dtype, int k, const void *x,
+                                  void *y, void *stream) {
+    clear_error();
+    if (int r = operator_check(s, o, dtype, k)) return r;
+    if (!x || !y) return set_error(DCS_EINVAL, "NULL vector");
+    const bool xc = dtype == DCS_C64 || dtype == DCS_C128;
+    const bool single = dtype == DCS_F32 || dtype == DCS_C64;
+    const size_t bytes = (size_t)s->desc.dim * (single ? 4 : 8) * (xc ? 2 : 1) * (size_t)k;
+    if ((const char *)y < (const char *)x + bytes && (const char *)x < (const char *)y + bytes)
+        return set_error(DCS_EINVAL, "y overlaps x");
+    return launch_operator(s, o, dtype, k, x, y, (hipStream_t)stream);
 }

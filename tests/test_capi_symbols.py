@@ -116,5 +116,5 @@ def test_operator_host_checks(lib):
     assert create(2, 0, [2], [1, 2], [1.0], hop) == _lib.DCS_EINVAL
     assert create(2, 12, [9], list(range(9)), [1.0], [0.0] * (512 * 512)) == _lib.DCS_EUNSUPPORTED
     assert create(2, 4, [2], [1, 2], [float("nan")], hop) == _lib.DCS_EINVAL
-    assert l.dcs_operator_info(None, None, None, None) == _lib.DCS_EINVAL
+    assert l.dcs_operator_info(None, None, None, None, None) == _lib.DCS_EINVAL
     assert l.dcs_operator_destroy(None) == _lib.DCS_OK
