@@ -363,3 +363,41 @@ def test_lanczos_on_generic_operators():
     r2 = dq.lanczos(s, t, torch.tensor(jxy, device=DEV), torch.tensor(jz, device=DEV), v0, 150, reorth="full",
                     num_eig=4, h=torch.tensor(h, device=DEV))
     assert np.allclose(r["eig"], r2["eig"], rtol=0, atol=1e-10)
+
+
+def test_operator_64bit_indices(monkeypatch):
+    """The kernels with 64-bit index arithmetic (DCS_INDEX_BITS=64, as sectors beyond
+    2^32 states use) on small sectors against the oracle on every row, real and complex."""
+    monkeypatch.setenv("DCS_INDEX_BITS", "64")
+    for Q, L, n, split in ((2, 12, 6, [4, 4, 4]), (3, 6, 5, [3, 3])):
+        terms = random_terms(Q, L, 50 + Q)
+        cterms = complex_terms(Q, L, 60 + Q)
+        s = dq.Sector(L, n, Q, split)
+        bs = BruteSector(Q, L, n, split)
+        x = np.random.default_rng(Q).normal(size=bs.dim)
+        for tt, xx in ((terms, x), (cterms, x + 0.5j * x[::-1])):
+            op = dq.Operator(Q, L, tt, cluster_sites=3)
+            y = dq.operator_apply(s, op, torch.tensor(xx, device=DEV))
+            assert rel_err(y.cpu().numpy(), apply_operator(bs, tt, xx)) <= 1e-12
+
+
+def test_operator_L32_device_tables_sampled():
+    """The J1-J2 chain from strings on the L=32, n=16 sector split 16/16 (tables in
+    device memory, 601,080,390 rows), FP32, against the C oracle on 20,000 sampled rows
+    of the FP64 draws."""
+    L, n = 32, 16
+    bonds, jxy, jz = synth.j1j2_chain(L, 1.0, 0.5, 1.0)
+    op = dq.Operator(2, L, xxz_strings(2, bonds, jxy, jz), cluster_sites=4)
+    s = dq.Sector(L, n, 2, [16, 16])
+    assert s.tables_in_device_memory
+    ns = native.NativeSector(2, L, n, [16, 16])
+    x = synth.vector(s.dim, synth.SEED_X)  # FP64 draws; the GPU takes them rounded to FP32
+    y = dq.operator_apply(s, op, torch.from_numpy(x.astype(np.float32)).to(DEV))
+    rows = np.random.default_rng(32).integers(0, s.dim, 20000).astype(np.uint64)
+    rows[:2] = [0, s.dim - 1]
+    ref = native.hx_rows(ns, native.NativeTerms(bonds, jxy, jz), x, rows)
+    del x
+    got = y[torch.tensor(rows.astype(np.int64), device=DEV)].double().cpu().numpy()
+    err = rel_err(got, ref)
+    say("operator L32 16/16 sampled", err)
+    assert err <= 1e-5
