@@ -32,6 +32,7 @@ namespace op {
 constexpr int kOpMaxSites = 8;       // sites of one cluster
 constexpr uint32_t kOpMaxLocal = 4096;  // Q^m of one cluster
 constexpr int kOpThreads = 256;
+constexpr int kOpBatch = 4;  // entries of a cluster row whose gathers are in flight together
 constexpr uint64_t kOpLdsMax = 128 * 1024;  // tables + operator arrays staged per workgroup
 
 struct OpCluster {
@@ -150,27 +151,41 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
             }
             const uint64_t keep = s & ~clmask;
             const uint32_t e1 = rowptr[C.row0 + a + 1];
-            for (uint32_t e = rowptr[C.row0 + a]; e < e1; ++e) {
-                const uint32_t d = dep[e];
-                uint64_t s2 = keep;
+            // kOpBatch entries at a time: their targets first, then their gathers (in flight
+            // together), then the products in entry order
+            for (uint32_t e0 = rowptr[C.row0 + a]; e0 < e1; e0 += kOpBatch) {
+                uint64_t t[kOpBatch];
 #pragma unroll
-                for (int j = 0; j < kOpMaxSites; ++j)
-                    if (j < C.m) s2 |= (uint64_t)((d >> (sd.nb * j)) & (uint32_t)dmask) << pos[j];
-                uint64_t t = i;
-                if (s2 != s) {
-                    IdxT v = base_idx;
-                    int l = lam0;
-                    for (int k = k1; k <= k2; ++k) {
-                        const uint32_t wk = sub_word(sd, s2, k);
-                        v += Tb.ctab[sd.ctab_row0[k] + (uint32_t)(l - sd.lam_lo[k]) * sd.ctab_rowlen[k] + wk];
-                        l += digit_sum(sd, wk);
+                for (int u = 0; u < kOpBatch; ++u) {
+                    t[u] = ~0ull;  // no entry: past the sector, reads zero
+                    if (e0 + u < e1) {
+                        const uint32_t d = dep[e0 + u];
+                        uint64_t s2 = keep;
+#pragma unroll
+                        for (int j = 0; j < kOpMaxSites; ++j)
+                            if (j < C.m) s2 |= (uint64_t)((d >> (sd.nb * j)) & (uint32_t)dmask) << pos[j];
+                        t[u] = i;
+                        if (s2 != s) {
+                            IdxT v = base_idx;
+                            int l = lam0;
+                            for (int k = k1; k <= k2; ++k) {
+                                const uint32_t wk = sub_word(sd, s2, k);
+                                v += Tb.ctab[sd.ctab_row0[k] + (uint32_t)(l - sd.lam_lo[k]) * sd.ctab_rowlen[k] + wk];
+                                l += digit_sum(sd, wk);
+                            }
+                            t[u] = (uint64_t)v;
+                        }
                     }
-                    t = (uint64_t)v;
                 }
-                X xt;
-                if (t < sd.dim) xt = x[t];
-                else memset(&xt, 0, sizeof(xt));
-                op_fma<VC, XC>(acc, val[e], xt);
+                X xt[kOpBatch];
+#pragma unroll
+                for (int u = 0; u < kOpBatch; ++u) {
+                    if (t[u] < sd.dim) xt[u] = x[t[u]];
+                    else memset(&xt[u], 0, sizeof(X));
+                }
+#pragma unroll
+                for (int u = 0; u < kOpBatch; ++u)
+                    if (e0 + u < e1) op_fma<VC, XC>(acc, val[e0 + u], xt[u]);
             }
         }
         y[i] = acc;
