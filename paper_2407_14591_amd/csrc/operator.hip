@@ -52,6 +52,7 @@ struct OpParams {
     const char *opblob;
     uint32_t op_bytes, off_rp, off_dep, off_val;
     uint32_t lds_tabs;  // LDS bytes of the sector's tables (0: read in device memory)
+    uint32_t lds_cpos;  // LDS byte offset of the per-cluster site positions (16 bytes each)
     const void *x;
     void *y;
     int ncl;
@@ -103,7 +104,28 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
     extern __shared__ __align__(16) char lds[];
     if constexpr (!GT) stage_blob(lds, P.blob, sd.lay_bytes);
     if constexpr (OPL) stage_blob(lds + P.lds_tabs, P.opblob, P.op_bytes);
-    if constexpr (!GT || OPL) __syncthreads();
+    const OpCluster *gcl = reinterpret_cast<const OpCluster *>(P.opblob);
+    // per cluster, the bit position of each site's digit in this sector's packed
+    // states and the first and last subsystem it touches (once per workgroup)
+    uint8_t *cpos = reinterpret_cast<uint8_t *>(lds + P.lds_cpos);  // [cluster][16]
+    for (int c = threadIdx.x; c < P.ncl; c += kOpThreads) {
+        const OpCluster C = gcl[c];
+        int k1 = kMaxSub, k2 = -1;
+        for (int j = 0; j < kOpMaxSites; ++j) {
+            int p = 0;
+            if (j < C.m) {
+                const int k = sd.site_sub[C.site[j]];
+                k1 = min(k1, k);
+                k2 = max(k2, k);
+                p = sd.shift[k] + sd.site_bit[C.site[j]];
+            }
+            cpos[c * 16 + j] = (uint8_t)p;
+        }
+        cpos[c * 16 + 8] = (uint8_t)k1;
+        cpos[c * 16 + 9] = (uint8_t)k2;
+        cpos[c * 16 + 10] = C.m;
+    }
+    __syncthreads();
     const Tables<IdxT> Tb = tables_at<IdxT>(GT ? P.blob : lds, sd);
     const char *ob = OPL ? (const char *)(lds + P.lds_tabs) : P.opblob;
     const OpCluster *cl = reinterpret_cast<const OpCluster *>(ob);
@@ -122,23 +144,18 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
         X acc;
         memset(&acc, 0, sizeof(acc));
         for (int c = 0; c < P.ncl; ++c) {  // uniform
-            const OpCluster C = cl[c];
+            const uint32_t row0 = cl[c].row0;
+            const uint8_t *cp = cpos + c * 16;  // the same address on every lane
+            const int m = cp[10], k1 = cp[8], k2 = cp[9];
             int pos[kOpMaxSites];
             uint64_t clmask = 0;
             uint32_t a = 0;
-            int k1 = kMaxSub, k2 = -1;  // subsystems the cluster touches
 #pragma unroll
             for (int j = 0; j < kOpMaxSites; ++j) {
-                if (j < C.m) {
-                    const int site = C.site[j];
-                    const int k = sd.site_sub[site];
-                    k1 = min(k1, k);
-                    k2 = max(k2, k);
-                    pos[j] = sd.shift[k] + sd.site_bit[site];
+                pos[j] = cp[j];
+                if (j < m) {
                     a = a * (uint32_t)sd.Q + (uint32_t)((s >> pos[j]) & dmask);
                     clmask |= dmask << pos[j];
-                } else {
-                    pos[j] = 0;
                 }
             }
             // the index without the touched subsystems' contributions; particles before k1
@@ -150,10 +167,10 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
                 if (k == k1) lam0 = lam[k];
             }
             const uint64_t keep = s & ~clmask;
-            const uint32_t e1 = rowptr[C.row0 + a + 1];
+            const uint32_t e1 = rowptr[row0 + a + 1];
             // kOpBatch entries at a time: their targets first, then their gathers (in flight
             // together), then the products in entry order
-            for (uint32_t e0 = rowptr[C.row0 + a]; e0 < e1; e0 += kOpBatch) {
+            for (uint32_t e0 = rowptr[row0 + a]; e0 < e1; e0 += kOpBatch) {
                 uint64_t t[kOpBatch];
 #pragma unroll
                 for (int u = 0; u < kOpBatch; ++u) {
@@ -163,7 +180,7 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
                         uint64_t s2 = keep;
 #pragma unroll
                         for (int j = 0; j < kOpMaxSites; ++j)
-                            if (j < C.m) s2 |= (uint64_t)((d >> (sd.nb * j)) & (uint32_t)dmask) << pos[j];
+                            if (j < m) s2 |= (uint64_t)((d >> (sd.nb * j)) & (uint32_t)dmask) << pos[j];
                         t[u] = i;
                         if (s2 != s) {
                             IdxT v = base_idx;
@@ -519,8 +536,10 @@ int launch_operator(const dcs_sector *s, const dcs_operator *o, int dtype, int k
     P.y = y;
     P.ncl = o->ncl;
     // the operator's arrays go to LDS beside the tables when both fit the budget
-    const bool opl = (uint64_t)P.lds_tabs + P.op_bytes <= kOpLdsMax;
-    const size_t lds = (size_t)P.lds_tabs + (opl ? P.op_bytes : 0u);
+    const bool opl = (uint64_t)P.lds_tabs + P.op_bytes + 16ull * o->ncl <= kOpLdsMax;
+    P.lds_cpos = P.lds_tabs + (opl ? P.op_bytes : 0u);
+    const size_t lds = (size_t)P.lds_cpos + 16u * (size_t)std::max(o->ncl, 1);
+    if (lds > 160 * 1024) return set_error(DCS_EUNSUPPORTED, "operator of %d clusters beyond the LDS budget", o->ncl);
     const uint64_t blocks = (s->desc.dim + kOpThreads - 1) / kOpThreads;
     const uint64_t cap = (uint64_t)device_cu_count(s->device) * 8;
     const int grid = (int)std::max<uint64_t>(1, std::min(blocks, cap));
