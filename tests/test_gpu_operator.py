@@ -401,3 +401,37 @@ def test_operator_L32_device_tables_sampled():
     err = rel_err(got, ref)
     say("operator L32 16/16 sampled", err)
     assert err <= 1e-5
+
+
+def test_app_d_through_operator_strings_L28():
+    """App. D's example as the paper writes it, through the operator class: the open
+    chain from separate Sx Sx, Sy Sy, Sz Sz strings and the field k Sz_k at L = 28,
+    n = 14; the four lowest levels from dcs_lanczos_operator (240 steps, full
+    re-orthogonalisation) and <Sz_0> of each Ritz vector (the one-term operator Sz_0
+    applied, then a dot product) against the oracle's deflated Lanczos values."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "appd_L28.json")))
+    L, n = ref["L"], ref["n"]
+    terms = []
+    for i in range(L - 1):
+        for nm in ("Sx", "Sy", "Sz"):
+            terms.append(dq.operator_string(1.0, (i, i + 1), (nm, nm), 2))
+    terms += [dq.operator_string(float(k), (k,), ("Sz",), 2) for k in range(L)]
+    op = dq.Operator(2, L, terms, cluster_sites=4)
+    assert not op.is_complex
+    s = dq.Sector(L, n, 2, [7, 7, 7, 7])
+    assert s.dim == ref["dim"]
+    v0 = torch.tensor(synth.vector(s.dim, synth.SEED_V0), device=DEV)
+    num = len(ref["states"])
+    res = dq.lanczos(s, op, None, None, v0, 240, reorth="full", num_eig=num + 1, num_vec=num)
+    sz0 = dq.Operator(2, L, [dq.operator_string(1.0, (0,), ("Sz",), 2)], cluster_sites=1)
+    E = np.array(res["eig"])
+    for e, st in enumerate(ref["states"]):
+        psi = res["vectors"][e]
+        psi = psi / torch.linalg.vector_norm(psi)
+        ez = torch.dot(psi, dq.operator_apply(s, sz0, psi.contiguous())).item()
+        gap = np.min(np.abs(np.delete(E, e) - E[e]))
+        say("appd operator", e, E[e], st["E"], "<Sz0>", ez, st["sz"][0], "gap", gap)
+        assert abs(E[e] - st["E"]) <= 1e-10 * abs(st["E"])
+        assert abs(ez - st["sz"][0]) <= 2 * st["residual_norm"] / gap + 1e-9
