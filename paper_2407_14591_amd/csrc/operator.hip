@@ -6,17 +6,22 @@
 // particle number and grouped greedily into clusters of at most `cluster_sites`
 // sites (a term joins the first cluster whose site set it can extend within the
 // limit, else it opens one); each cluster's sum of embedded terms is stored row by
-// row (CSR over the cluster's local index of the output state), every entry with
-// the packed digits of its input state and its value.
+// row, every entry with the digits of its input state and its value.  Rows are keyed
+// by the output state's digits on the cluster's sites packed nb bits each, first
+// site most significant (keys holding a digit >= Q are empty rows), and entries
+// carry their input digits packed the same way: for a cluster of adjacent sites both
+// are the bit field the digits occupy in a packed state.
 //
 // Device: one thread per row s of the sector (pull form, y_s = sum_t O_st x_t):
 // unrank s (keeping each subsystem's word, particles before it and contribution to
-// the index), and for each cluster read the local index of s on the cluster's
-// sites, walk that row's entries, write the entry's digits into s and re-rank only
-// the subsystems from the first to the last one the cluster touches (eq. index is a
-// sum over subsystems; the particles before the first and after the last are
+// the index), and for each cluster read the key of s on the cluster's sites, walk
+// that row's entries, write the entry's digits into s and re-rank only the
+// subsystems from the first to the last one the cluster touches (eq. index is a sum
+// over subsystems; the particles before the first and after the last are
 // unchanged), gather x there.  The operator's arrays are staged in LDS next to the
-// sector's tables when they fit.
+// sector's tables when they fit; each workgroup derives per cluster the bit
+// positions and table rows it needs from the sector's layout, and every lane reads
+// them into scalar registers.
 #include "device_common.h"
 
 #include <algorithm>
@@ -44,15 +49,16 @@ struct OpCluster {
 static_assert(sizeof(OpCluster) == 16, "cluster record");
 
 // The operator's arrays for one compute type, one contiguous blob (16-byte
-// aligned segments): clusters | row pointers (per cluster Q^m + 1 offsets into the
-// entries) | input digits of each entry (site j's digit at bits nb * j) | values.
+// aligned segments): clusters | row pointers (offsets into the
+// entries, 2^(nb m) + 1 per cluster) | packed input digits of each entry (site j's
+// digit at bits nb (m-1-j)) | values.
 struct OpParams {
     SectorDesc sd;  // first: read in place in the kernel argument segment
     const char *blob;
     const char *opblob;
     uint32_t op_bytes, off_rp, off_dep, off_val;
     uint32_t lds_tabs;  // LDS bytes of the sector's tables (0: read in device memory)
-    uint32_t lds_cpos;  // LDS byte offset of the per-cluster site positions (16 bytes each)
+    uint32_t lds_cpos;  // LDS byte offset of the per-cluster records (kOpRecBytes each)
     const void *x;
     void *y;
     int ncl;
@@ -90,6 +96,54 @@ __device__ __forceinline__ void op_fma(A &acc, const V &v, const A &x) {
     }
 }
 
+// Per cluster one 48-byte record, built once per workgroup from the sector's layout:
+//   r0: posA | posB << 8 | bitsB << 16 | nk << 24, the first row pointer,
+//       k1 | m << 8 | runs << 16, the key mask 2^(nb m) - 1
+//   r1: the bit positions of sites 0..7 (one byte each), then shift | wbits << 8 of the
+//       first two touched subsystems (A in bits 0-15, B in bits 16-31)
+//   r2: row length and base (row0 - lam_lo * row length) of the fused table rows of A, B
+// The sites (in increasing order) fall into runs whose digits lie next to each other
+// in the packed state.  With at most two runs, the cluster's packed digits are two bit
+// fields: the first run's, whose lowest bit is posA, above the second run's bitsB bits
+// at posB (one run: bitsB = 0).  nk = k2 - k1 + 1 subsystems are touched.
+constexpr uint32_t kOpRecBytes = 48;
+
+__device__ __forceinline__ void op_fill_record(const SectorDesc &sd, const OpCluster &C, uint32_t *r) {
+    int k1 = kMaxSub, k2 = -1;
+    uint32_t p03 = 0, p47 = 0;
+    int pos_prev = 0, pos = 0, runs = 0, posA = 0, endA = 0;
+    for (int j = 0; j < C.m; ++j) {
+        const int k = sd.site_sub[C.site[j]];
+        k1 = min(k1, k);
+        k2 = max(k2, k);
+        pos = sd.shift[k] + sd.site_bit[C.site[j]];
+        if (j == 0 || pos + sd.nb != pos_prev) ++runs;
+        if (runs == 1) {  // the first run ends at site j
+            posA = pos;
+            endA = j + 1;
+        }
+        pos_prev = pos;
+        if (j < 4) p03 |= (uint32_t)pos << (8 * j);
+        else p47 |= (uint32_t)pos << (8 * (j - 4));
+    }
+    const int nk = k2 - k1 + 1;
+    const int kb = nk >= 2 ? k1 + 1 : k1;
+    const int bitsB = sd.nb * (C.m - endA);
+    const int posB = runs == 2 ? pos : 0;
+    r[0] = (uint32_t)posA | ((uint32_t)posB << 8) | ((uint32_t)bitsB << 16) | ((uint32_t)nk << 24);
+    r[1] = C.row0;
+    r[2] = (uint32_t)k1 | ((uint32_t)C.m << 8) | ((uint32_t)runs << 16);
+    r[3] = (uint32_t)((1ull << (sd.nb * C.m)) - 1ull);
+    r[4] = p03;
+    r[5] = p47;
+    r[6] = sd.shift[k1] | (sd.wbits[k1] << 8) | (sd.shift[kb] << 16) | (sd.wbits[kb] << 24);
+    r[7] = 0;
+    r[8] = sd.ctab_rowlen[k1];
+    r[9] = sd.ctab_row0[k1] - (uint32_t)sd.lam_lo[k1] * sd.ctab_rowlen[k1];
+    r[10] = sd.ctab_rowlen[kb];
+    r[11] = sd.ctab_row0[kb] - (uint32_t)sd.lam_lo[kb] * sd.ctab_rowlen[kb];
+}
+
 // K: columns of a block [D][K] of real vectors (one unrank and one rank per target
 // serve all K); complex vectors take one column.
 template <typename IdxT, typename T, bool VC, bool XC, bool GT, bool OPL, int K>
@@ -105,36 +159,20 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
     if constexpr (!GT) stage_blob(lds, P.blob, sd.lay_bytes);
     if constexpr (OPL) stage_blob(lds + P.lds_tabs, P.opblob, P.op_bytes);
     const OpCluster *gcl = reinterpret_cast<const OpCluster *>(P.opblob);
-    // per cluster, the bit position of each site's digit in this sector's packed
-    // states and the first and last subsystem it touches (once per workgroup)
-    uint8_t *cpos = reinterpret_cast<uint8_t *>(lds + P.lds_cpos);  // [cluster][16]
+    uint32_t *recs = reinterpret_cast<uint32_t *>(lds + P.lds_cpos);  // [cluster][12]
     for (int c = threadIdx.x; c < P.ncl; c += kOpThreads) {
-        const OpCluster C = gcl[c];
-        int k1 = kMaxSub, k2 = -1;
-        for (int j = 0; j < kOpMaxSites; ++j) {
-            int p = 0;
-            if (j < C.m) {
-                const int k = sd.site_sub[C.site[j]];
-                k1 = min(k1, k);
-                k2 = max(k2, k);
-                p = sd.shift[k] + sd.site_bit[C.site[j]];
-            }
-            cpos[c * 16 + j] = (uint8_t)p;
-        }
-        cpos[c * 16 + 8] = (uint8_t)k1;
-        cpos[c * 16 + 9] = (uint8_t)k2;
-        cpos[c * 16 + 10] = C.m;
+        op_fill_record(sd, gcl[c], recs + c * (kOpRecBytes / 4));
     }
     __syncthreads();
     const Tables<IdxT> Tb = tables_at<IdxT>(GT ? P.blob : lds, sd);
     const char *ob = OPL ? (const char *)(lds + P.lds_tabs) : P.opblob;
-    const OpCluster *cl = reinterpret_cast<const OpCluster *>(ob);
     const uint32_t *rowptr = reinterpret_cast<const uint32_t *>(ob + P.off_rp);
     const uint32_t *dep = reinterpret_cast<const uint32_t *>(ob + P.off_dep);
     const V *val = reinterpret_cast<const V *>(ob + P.off_val);
     const X *__restrict__ x = reinterpret_cast<const X *>(P.x);
     X *__restrict__ y = reinterpret_cast<X *>(P.y);
-    const uint64_t dmask = (1ull << sd.nb) - 1ull;
+    const uint32_t nb = sd.nb;
+    const uint32_t dmask = (1u << nb) - 1u;
     const uint64_t stride = (uint64_t)gridDim.x * kOpThreads;
     for (uint64_t i = (uint64_t)blockIdx.x * kOpThreads + threadIdx.x; i < sd.dim; i += stride) {
         uint32_t w[kMaxSub];
@@ -144,55 +182,95 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
         X acc;
         memset(&acc, 0, sizeof(acc));
         for (int c = 0; c < P.ncl; ++c) {  // uniform
-            const uint32_t row0 = cl[c].row0;
-            const uint8_t *cp = cpos + c * 16;  // the same address on every lane
-            const int m = cp[10], k1 = cp[8], k2 = cp[9];
-            int pos[kOpMaxSites];
-            uint64_t clmask = 0;
-            uint32_t a = 0;
-#pragma unroll
-            for (int j = 0; j < kOpMaxSites; ++j) {
-                pos[j] = cp[j];
-                if (j < m) {
-                    a = a * (uint32_t)sd.Q + (uint32_t)((s >> pos[j]) & dmask);
-                    clmask |= dmask << pos[j];
+            // the record is the same on every lane: read it once into scalar registers,
+            // so that every test on it below is a scalar branch
+            const uint4 *rp4 = reinterpret_cast<const uint4 *>(recs + c * (kOpRecBytes / 4));
+            const uint4 q0 = rp4[0], q1 = rp4[1], q2 = rp4[2];
+            const uint32_t hdr = __builtin_amdgcn_readfirstlane(q0.x);
+            const uint32_t row0 = __builtin_amdgcn_readfirstlane(q0.y);
+            const uint32_t hdr2 = __builtin_amdgcn_readfirstlane(q0.z);
+            const uint32_t fmask = __builtin_amdgcn_readfirstlane(q0.w);
+            const uint32_t p03 = __builtin_amdgcn_readfirstlane(q1.x);
+            const uint32_t p47 = __builtin_amdgcn_readfirstlane(q1.y);
+            const uint32_t shw = __builtin_amdgcn_readfirstlane(q1.z);
+            const uint32_t rlA = __builtin_amdgcn_readfirstlane(q2.x);
+            const uint32_t baseA = __builtin_amdgcn_readfirstlane(q2.y);
+            const uint32_t rlB = __builtin_amdgcn_readfirstlane(q2.z);
+            const uint32_t baseB = __builtin_amdgcn_readfirstlane(q2.w);
+            const uint32_t posA = hdr & 0xffu, posB = (hdr >> 8) & 0xffu, bitsB = (hdr >> 16) & 0xffu;
+            const int nk = (int)(hdr >> 24);
+            const int k1 = (int)(hdr2 & 0xffu), m = (int)((hdr2 >> 8) & 0xffu);
+            const int runs = (int)(hdr2 >> 16);
+            const uint32_t maskA = fmask >> bitsB, maskB = (1u << bitsB) - 1u;
+            const uint32_t shA = shw & 0xffu, mA = (1u << ((shw >> 8) & 0xffu)) - 1u;
+            const uint32_t shB = (shw >> 16) & 0xffu, mB = (1u << (shw >> 24)) - 1u;
+            const uint64_t pp = ((uint64_t)p47 << 32) | p03;
+            // the row's packed digits on the cluster's sites (the row key) and the state
+            // with those digits cleared
+            uint32_t f;
+            uint64_t keep;
+            if (runs == 1) {
+                f = (uint32_t)(s >> posA) & fmask;
+                keep = s & ~((uint64_t)fmask << posA);
+            } else if (runs == 2) {
+                f = (((uint32_t)(s >> posA) & maskA) << bitsB) | ((uint32_t)(s >> posB) & maskB);
+                keep = s & ~(((uint64_t)maskA << posA) | ((uint64_t)maskB << posB));
+            } else {
+                f = 0;
+                uint64_t clmask = 0;
+                for (int j = 0; j < m; ++j) {
+                    const uint32_t pj = (uint32_t)(pp >> (8 * j)) & 0xffu;
+                    f = (f << nb) | ((uint32_t)(s >> pj) & dmask);
+                    clmask |= (uint64_t)dmask << pj;
                 }
+                keep = s & ~clmask;
             }
             // the index without the touched subsystems' contributions; particles before k1
             IdxT base_idx = (IdxT)i;
             int lam0 = 0;
 #pragma unroll
             for (int k = 0; k < kMaxSub; ++k) {
-                if (k >= k1 && k <= k2) base_idx -= cpart[k];
+                if (k >= k1 && k < k1 + nk) base_idx -= cpart[k];
                 if (k == k1) lam0 = lam[k];
             }
-            const uint64_t keep = s & ~clmask;
-            const uint32_t e1 = rowptr[row0 + a + 1];
+            const uint32_t rowA = baseA + (uint32_t)lam0 * rlA;
+            const uint32_t eb = rowptr[row0 + f], ee = rowptr[row0 + f + 1];
             // kOpBatch entries at a time: their targets first, then their gathers (in flight
             // together), then the products in entry order
-            for (uint32_t e0 = rowptr[row0 + a]; e0 < e1; e0 += kOpBatch) {
+            for (uint32_t e0 = eb; e0 < ee; e0 += kOpBatch) {
                 uint64_t t[kOpBatch];
 #pragma unroll
                 for (int u = 0; u < kOpBatch; ++u) {
-                    t[u] = ~0ull;  // no entry: past the sector, reads zero
-                    if (e0 + u < e1) {
-                        const uint32_t d = dep[e0 + u];
-                        uint64_t s2 = keep;
-#pragma unroll
-                        for (int j = 0; j < kOpMaxSites; ++j)
-                            if (j < m) s2 |= (uint64_t)((d >> (sd.nb * j)) & (uint32_t)dmask) << pos[j];
-                        t[u] = i;
-                        if (s2 != s) {
-                            IdxT v = base_idx;
-                            int l = lam0;
-                            for (int k = k1; k <= k2; ++k) {
+                    const bool ok = e0 + u < ee;
+                    const uint32_t d = dep[ok ? e0 + u : e0];
+                    uint64_t s2 = keep;
+                    if (runs == 1) {
+                        s2 |= (uint64_t)d << posA;
+                    } else if (runs == 2) {
+                        s2 |= ((uint64_t)(d >> bitsB) << posA) | ((uint64_t)(d & maskB) << posB);
+                    } else {
+                        uint32_t dd = d;
+                        for (int j = m - 1; j >= 0; --j) {
+                            s2 |= (uint64_t)(dd & dmask) << ((uint32_t)(pp >> (8 * j)) & 0xffu);
+                            dd >>= nb;
+                        }
+                    }
+                    const uint32_t wa = (uint32_t)(s2 >> shA) & mA;
+                    IdxT v = base_idx + Tb.ctab[rowA + wa];
+                    if (nk >= 2) {
+                        int l = lam0 + digit_sum(sd, wa);
+                        const uint32_t wb = (uint32_t)(s2 >> shB) & mB;
+                        v += Tb.ctab[baseB + (uint32_t)l * rlB + wb];
+                        if (nk >= 3) {
+                            l += digit_sum(sd, wb);
+                            for (int k = k1 + 2; k < k1 + nk; ++k) {
                                 const uint32_t wk = sub_word(sd, s2, k);
                                 v += Tb.ctab[sd.ctab_row0[k] + (uint32_t)(l - sd.lam_lo[k]) * sd.ctab_rowlen[k] + wk];
                                 l += digit_sum(sd, wk);
                             }
-                            t[u] = (uint64_t)v;
                         }
                     }
+                    t[u] = ok ? (uint64_t)v : ~0ull;  // no entry: past the sector, reads zero
                 }
                 X xt[kOpBatch];
 #pragma unroll
@@ -202,7 +280,7 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
                 }
 #pragma unroll
                 for (int u = 0; u < kOpBatch; ++u)
-                    if (e0 + u < e1) op_fma<VC, XC>(acc, val[e0 + u], xt[u]);
+                    if (e0 + u < ee) op_fma<VC, XC>(acc, val[e0 + u], xt[u]);
             }
         }
         y[i] = acc;
@@ -241,6 +319,14 @@ inline int digit_sum_local(uint32_t a, int m, int Q) {
         a /= (uint32_t)Q;
     }
     return s;
+}
+
+// the digits of the local index a packed nb bits each, the first site most significant
+// (the cluster's digits as they lie in a packed state when its sites are adjacent)
+inline uint32_t pack_local(uint32_t a, int m, int Q, int nb) {
+    uint32_t d = 0;
+    for (int j = 0; j < m; ++j) d |= (uint32_t)local_digit(a, j, m, Q) << (nb * (m - 1 - j));
+    return d;
 }
 
 inline uint32_t ipow(int Q, int m) {
@@ -376,8 +462,19 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
         // different digit sums must cancel to rounding, relative to the cluster's largest
         double vmax = 0.0;
         for (const Entry &en : ents) vmax = std::max(vmax, std::abs(en.v));
-        for (uint32_t b = 0; b < n; ++b) {
+        // rows keyed by the packed output digits; keys with a digit >= Q stay empty, and
+        // the key order is the order of the local index, so the entries are met in turn
+        const uint32_t nkeys = 1u << (nb * m);
+        for (uint32_t key = 0; key < nkeys; ++key) {
             rowptr.push_back((uint32_t)val.size());
+            uint32_t b = 0;
+            bool valid = true;
+            for (int j = 0; j < m; ++j) {
+                const uint32_t dj = (key >> (nb * (m - 1 - j))) & ((1u << nb) - 1u);
+                valid = valid && dj < (uint32_t)Q;
+                b = b * (uint32_t)Q + dj;
+            }
+            if (!valid) continue;
             while (e < ents.size() && ents[e].row == b) {
                 const uint32_t col = ents[e].col;
                 cd v = 0.0;
@@ -394,9 +491,7 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
                     continue;
                 }
                 if (v == 0.0) continue;
-                uint32_t d = 0;
-                for (int j = 0; j < m; ++j) d |= (uint32_t)local_digit(col, j, m, Q) << (nb * j);
-                dep.push_back(d);
+                dep.push_back(pack_local(col, m, Q, nb));
                 val.push_back(v);
             }
         }
@@ -536,9 +631,9 @@ int launch_operator(const dcs_sector *s, const dcs_operator *o, int dtype, int k
     P.y = y;
     P.ncl = o->ncl;
     // the operator's arrays go to LDS beside the tables when both fit the budget
-    const bool opl = (uint64_t)P.lds_tabs + P.op_bytes + 16ull * o->ncl <= kOpLdsMax;
+    const bool opl = (uint64_t)P.lds_tabs + P.op_bytes + (uint64_t)kOpRecBytes * o->ncl <= kOpLdsMax;
     P.lds_cpos = P.lds_tabs + (opl ? P.op_bytes : 0u);
-    const size_t lds = (size_t)P.lds_cpos + 16u * (size_t)std::max(o->ncl, 1);
+    const size_t lds = (size_t)P.lds_cpos + kOpRecBytes * (size_t)std::max(o->ncl, 1);
     if (lds > 160 * 1024) return set_error(DCS_EUNSUPPORTED, "operator of %d clusters beyond the LDS budget", o->ncl);
     const uint64_t blocks = (s->desc.dim + kOpThreads - 1) / kOpThreads;
     const uint64_t cap = (uint64_t)device_cu_count(s->device) * 8;

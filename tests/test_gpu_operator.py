@@ -48,6 +48,31 @@ def test_operator_matches_oracle(Q, L, n, split, cluster):
         assert err <= tol
 
 
+@pytest.mark.parametrize("Q,L,n,split", [(2, 12, 5, [3, 3, 3, 3]), (3, 9, 8, [2, 3, 2, 2])])
+def test_operator_cluster_shapes(Q, L, n, split):
+    """One cluster per site pattern the kernel tells apart: adjacent sites (one bit
+    field of the packed state), two runs of adjacent sites (a ket site with its bra
+    site on a doubled chain; the bond that closes a ring), three or more runs, each
+    within one subsystem, across two and across three or more; every row against the
+    term-by-term oracle."""
+    patterns = [(1, 2), (0, 1, 2), (2, 3, 4, 5), (L - 1, 0), (0, 1, L - 2, L - 1), (1, 4, 5, L - 1),
+                (0, 3, 6), (0, 2, 4, 6, 8)]
+    terms = []
+    for t, sites in enumerate(patterns):
+        terms.append((float(0.3 + 0.1 * t), sites, synth.random_local_matrix(Q, len(sites), 500 + t, density=0.6)))
+    op = dq.Operator(Q, L, terms, cluster_sites=1)
+    assert op.num_clusters == len(patterns)
+    bs = BruteSector(Q, L, n, split)
+    s = dq.Sector(L, n, Q, split)
+    x = np.random.default_rng(3).normal(size=bs.dim)
+    ref = apply_operator(bs, terms, x)
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        y = dq.operator_apply(s, op, torch.tensor(x, device=DEV).to(dt))
+        err = rel_err(y.double().cpu().numpy(), ref)
+        say("operator cluster shapes", Q, L, n, dt, err)
+        assert err <= tol
+
+
 def test_cluster_merging_open_chain():
     """Nearest-neighbour bonds of an open chain of 12 sites in order, clusters of 4
     sites: {0..3}, {3..6}, {6..9}, {9..11}; the fields join the first cluster that
