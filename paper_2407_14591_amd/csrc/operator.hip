@@ -179,6 +179,11 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
         int lam[kMaxSub];
         IdxT cpart[kMaxSub];
         const uint64_t s = unrank_state<IdxT, kMaxSub>(sd, Tb, (IdxT)i, w, lam, cpart);
+        // cpre[k]: the index's contributions of the subsystems before k
+        IdxT cpre[kMaxSub + 1];
+        cpre[0] = 0;
+#pragma unroll
+        for (int k = 0; k < kMaxSub; ++k) cpre[k + 1] = cpre[k] + (k < sd.N ? cpart[k] : (IdxT)0);
         X acc;
         memset(&acc, 0, sizeof(acc));
         for (int c = 0; c < P.ncl; ++c) {  // uniform
@@ -226,13 +231,8 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
                 keep = s & ~clmask;
             }
             // the index without the touched subsystems' contributions; particles before k1
-            IdxT base_idx = (IdxT)i;
-            int lam0 = 0;
-#pragma unroll
-            for (int k = 0; k < kMaxSub; ++k) {
-                if (k >= k1 && k < k1 + nk) base_idx -= cpart[k];
-                if (k == k1) lam0 = lam[k];
-            }
+            const IdxT base_idx = (IdxT)i - (cpre[k1 + nk] - cpre[k1]);
+            const int lam0 = lam[k1];
             const uint32_t rowA = baseA + (uint32_t)lam0 * rlA;
             const uint32_t eb = rowptr[row0 + f], ee = rowptr[row0 + f + 1];
             // kOpBatch entries at a time: their targets first, then their gathers (in flight
