@@ -409,7 +409,8 @@ int dcs_operator_info(const dcs_operator *op, int *num_clusters, uint64_t *nnz,
  * types.  Real vectors may be blocks of k columns, [D][k] row-major with k in
  * {1, 2, 4, 8} (one unrank and one rank per reached state serve all k); complex
  * vectors take k = 1 (else DCS_EUNSUPPORTED).  Pull form: one thread per row s unranks s (Alg. iii), and per cluster
- * reads s's local index on the cluster's sites, walks that row of the cluster
+ * reads s's digits on the cluster's sites (packed nb bits per site, the row
+ * key), walks that row of the cluster
  * matrix, writes each entry's digits into s, ranks the result (eq. index; a
  * diagonal entry keeps s) and accumulates value * x there.  d_y must not overlap
  * d_x (DCS_EINVAL).  Asynchronous on `stream`.
