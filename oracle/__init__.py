@@ -23,6 +23,9 @@ Contents
   operators.py    generic number-conserving local operators (Sec. 4.1 operator
                   strings, App. C terms): y = O x term by term, and the operator on
                   the whole Q^L space from tensor contractions
+  mixed.py        sectors and local operators on sites of different local
+                  dimensions (Sec. 5's generalisation): dimension from the
+                  generating function, order by brute-force sort, y = O x term by term
   native.py       ctypes loader of c/dcs_oracle.c (same definitions in plain C,
                   FP64, OpenMP) for sectors too large for Python
 

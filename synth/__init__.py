@@ -171,3 +171,22 @@ def random_local_matrix(Q: int, m: int, seed: int, density: float = 1.0) -> np.n
     M = rng.standard_normal((n, n))
     mask = (sums[:, None] == sums[None, :]) & (rng.random((n, n)) < density)
     return np.where(mask, M, 0.0)
+
+
+def random_local_matrix_dims(dims, seed: int, density: float = 1.0) -> np.ndarray:
+    """The same on sites of local dimensions ``dims`` (one per listed site): an
+    n x n matrix, n the product of the dims, local index the mixed-radix number of
+    the digits with the first site most significant."""
+    dims = [int(q) for q in dims]
+    rng = np.random.default_rng([seed, len(dims)] + dims)
+    n = int(np.prod(dims))
+    sums = np.zeros(n, dtype=np.int64)
+    for a in range(n):
+        v, s = a, 0
+        for q in reversed(dims):
+            s += v % q
+            v //= q
+        sums[a] = s
+    M = rng.standard_normal((n, n))
+    mask = (sums[:, None] == sums[None, :]) & (rng.random((n, n)) < density)
+    return np.where(mask, M, 0.0)
