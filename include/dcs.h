@@ -131,6 +131,28 @@ int dcs_version(void);
 int dcs_sector_create(int L, int n_particles, int local_dim, int num_subsystems,
                       const int *sizes, int device, dcs_sector **out);
 
+/*
+ * The same with a local dimension per site (Sec. 5 names sites of different Q,
+ * such as mixed spins, as a direct generalisation): site i has local_dims[i]
+ * states in [2, 16]; the digits are packed ceil(log2 max_i local_dims[i]) bits
+ * per site, and a state whose digit on site i is >= local_dims[i] is outside the
+ * sector (rank gives the sentinel).  Every count of the index becomes a product
+ * over the sites' own (1 + x + ... + x^{q_i - 1}) (App. A), each subsystem's
+ * words are those with valid digits, and the offsets, strides and bounds of
+ * eq. offset / eq. stride follow from them; rank, unrank, enumerate, the
+ * sorted-list rank and the generic operators (dcs_operator_create_mixed) work
+ * on such a sector.  The XXZ products (dcs_hamiltonian_apply and its adjoint,
+ * expectation values, plans, dcs_lanczos) take one local dimension on every site
+ * and return DCS_EUNSUPPORTED for a sector with several.  A list with one value
+ * everywhere gives the same sector as dcs_sector_create.  Errors as there, with
+ * n outside [0, sum_i (local_dims[i] - 1)], and DCS_EINVAL for a NULL list.
+ */
+int dcs_sector_create_mixed(int L, int n_particles, const int32_t *local_dims, int num_subsystems,
+                            const int *sizes, int device, dcs_sector **out);
+
+/* The local dimension of every site (L entries). */
+int dcs_sector_local_dims(const dcs_sector *sector, int32_t *local_dims);
+
 /* Free the sector's device tables and the object.  NULL is accepted. */
 int dcs_sector_destroy(dcs_sector *sector);
 
@@ -392,6 +414,20 @@ int dcs_operator_create(int Q, int L, int num_terms, const int32_t *term_nsites,
                         const int32_t *term_sites, const double *term_coefs,
                         const double *term_mats, int complex_mats, int cluster_sites,
                         int device, dcs_operator **out);
+
+/*
+ * The same on sites of different local dimensions (Sec. 5's generalisation; the
+ * sectors of dcs_sector_create_mixed): site i has local_dims[i] states, a term's
+ * matrix has one row and one column per digit string on its sites (the product
+ * of their dimensions, <= 4096, as is a cluster's), and the local index of
+ * (d_0, .., d_{m-1}) is the mixed-radix number with the first listed site most
+ * significant.  dcs_operator_apply requires the sector's local dimensions to match
+ * site by site (DCS_EINVAL).  Errors as dcs_operator_create.
+ */
+int dcs_operator_create_mixed(int L, const int32_t *local_dims, int num_terms, const int32_t *term_nsites,
+                              const int32_t *term_sites, const double *term_coefs,
+                              const double *term_mats, int complex_mats, int cluster_sites,
+                              int device, dcs_operator **out);
 int dcs_operator_destroy(dcs_operator *op);
 
 /* Clusters, stored nonzeros, the largest cluster's site count, and whether the stored

@@ -77,16 +77,28 @@ def _block_shape(sector, x, name="x"):
 
 
 class Sector:
-    """One particle-number sector with its divide-and-conquer index (dcs_sector_create)."""
+    """One particle-number sector with its divide-and-conquer index (dcs_sector_create).
 
-    def __init__(self, L: int, n: int, Q: int = 2, split=None, device: int = 0):
+    Q is one local dimension for every site, or a sequence of L local dimensions
+    (dcs_sector_create_mixed: sites of different Q, Sec. 5); then ``Q`` holds the
+    largest and ``local_dims`` the list."""
+
+    def __init__(self, L: int, n: int, Q=2, split=None, device: int = 0):
         self._h = C.c_void_p()
-        if split is None:
-            call("dcs_sector_create", L, n, Q, 0, None, device, C.byref(self._h))
+        arr = None if split is None else (C.c_int * len(split))(*split)
+        nsplit = 0 if split is None else len(split)
+        if not hasattr(Q, "__len__"):
+            call("dcs_sector_create", L, n, int(Q), nsplit, arr, device, C.byref(self._h))
         else:
-            arr = (C.c_int * len(split))(*split)
-            call("dcs_sector_create", L, n, Q, len(split), arr, device, C.byref(self._h))
-        self.L, self.n, self.Q, self.device = L, n, Q, device
+            dims = [int(q) for q in Q]
+            if len(dims) != L:
+                raise ValueError(f"{len(dims)} local dimensions for {L} sites")
+            call("dcs_sector_create_mixed", L, n, (C.c_int32 * L)(*dims), nsplit, arr, device,
+                 C.byref(self._h))
+        ld = (C.c_int32 * L)()
+        call("dcs_sector_local_dims", self._h, ld)
+        self.local_dims = [int(ld[i]) for i in range(L)]
+        self.L, self.n, self.Q, self.device = L, n, max(self.local_dims), device
         d = C.c_uint64()
         call("dcs_sector_dim", self._h, C.byref(d))
         self.dim = int(d.value)
@@ -204,15 +216,16 @@ def local_operator(name: str, Q: int):
     return M
 
 
-def operator_string(coef: float, sites, names, Q: int):
+def operator_string(coef: float, sites, names, Q):
     """The term coef * op_0(sites[0]) op_1(sites[1]) ... as (coef, sites, matrix): the
-    Kronecker product of the named single-site matrices, first site most significant."""
+    Kronecker product of the named single-site matrices, first site most significant.
+    Q is one local dimension, or the sequence of every site's (mixed dimensions)."""
     import numpy as np
     if len(sites) != len(names):
         raise ValueError("one local operator name per site")
     M = np.ones((1, 1))
-    for nm in names:
-        M = np.kron(M, local_operator(nm, Q))
+    for st, nm in zip(sites, names):
+        M = np.kron(M, local_operator(nm, int(Q[st]) if hasattr(Q, "__len__") else Q))
     return (float(coef), tuple(int(s) for s in sites), M)
 
 
@@ -246,11 +259,18 @@ def lindbladian_terms(L: int, hamiltonian, jumps):
 class Operator:
     """A generic number-conserving operator (dcs_operator_create): terms (coef, sites,
     matrix) with a real or complex Q^m x Q^m matrix on the m listed sites, merged into
-    clusters of at most ``cluster_sites`` sites and stored sparse on the device."""
+    clusters of at most ``cluster_sites`` sites and stored sparse on the device.  Q may
+    be a sequence of L local dimensions (dcs_operator_create_mixed); a term's matrix
+    then has the product of its sites' dimensions as size."""
 
-    def __init__(self, Q: int, L: int, terms, cluster_sites: int = 4, device=None):
+    def __init__(self, Q, L: int, terms, cluster_sites: int = 4, device=None):
         import numpy as np
-        self.Q, self.L = int(Q), int(L)
+        self.L = int(L)
+        mixed = hasattr(Q, "__len__")
+        self.local_dims = [int(q) for q in Q] if mixed else [int(Q)] * self.L
+        if len(self.local_dims) != self.L:
+            raise ValueError(f"{len(self.local_dims)} local dimensions for {self.L} sites")
+        self.Q = max(self.local_dims)
         self.device = torch.cuda.current_device() if device is None else int(device)
         terms = list(terms)
         cplx_in = any(np.iscomplexobj(M) for _, _, M in terms)
@@ -258,7 +278,9 @@ class Operator:
         for coef, st, M in terms:
             st = [int(v) for v in st]
             M = np.ascontiguousarray(M, dtype=np.complex128 if cplx_in else np.float64)
-            n = self.Q ** len(st)
+            if any(v < 0 or v >= self.L for v in st):
+                raise ValueError(f"term sites {st} outside [0, {self.L})")
+            n = int(np.prod([self.local_dims[v] for v in st]))
             if M.shape != (n, n):
                 raise ValueError(f"term on {len(st)} sites needs a {n} x {n} matrix, got {M.shape}")
             nsites.append(len(st))
@@ -272,9 +294,14 @@ class Operator:
         flat = np.concatenate(mats) if mats else np.zeros(1)
         self._mats = flat  # kept alive for the call
         self._h = C.c_void_p()
-        call("dcs_operator_create", self.Q, self.L, nt, a_ns, a_st, a_cf,
-             flat.ctypes.data_as(C.POINTER(C.c_double)), int(cplx_in), int(cluster_sites), self.device,
-             C.byref(self._h))
+        mat_p = flat.ctypes.data_as(C.POINTER(C.c_double))
+        if mixed:
+            dims = (C.c_int32 * self.L)(*self.local_dims)
+            call("dcs_operator_create_mixed", self.L, dims, nt, a_ns, a_st, a_cf, mat_p, int(cplx_in),
+                 int(cluster_sites), self.device, C.byref(self._h))
+        else:
+            call("dcs_operator_create", self.Q, self.L, nt, a_ns, a_st, a_cf, mat_p, int(cplx_in),
+                 int(cluster_sites), self.device, C.byref(self._h))
         ncl, nnz, mx, cx = C.c_int(), C.c_uint64(), C.c_int(), C.c_int()
         call("dcs_operator_info", self._h, C.byref(ncl), C.byref(nnz), C.byref(mx), C.byref(cx))
         self.num_clusters, self.nnz, self.max_cluster_sites = ncl.value, nnz.value, mx.value

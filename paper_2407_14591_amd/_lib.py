@@ -41,6 +41,8 @@ SIGNATURES = {
     "dcs_last_error": (C.c_char_p, []),
     "dcs_version": (_i, []),
     "dcs_sector_create": (_i, [_i, _i, _i, _i, _ip, _i, _pp]),
+    "dcs_sector_create_mixed": (_i, [_i, _i, _i32p, _i, _ip, _i, _pp]),
+    "dcs_sector_local_dims": (_i, [_vp, _i32p]),
     "dcs_sector_destroy": (_i, [_vp]),
     "dcs_sector_dim": (_i, [_vp, _u64p]),
     "dcs_sector_split": (_i, [_vp, _ip, _ip]),
@@ -71,6 +73,7 @@ SIGNATURES = {
     "dcs_tridiag_eigvals": (_i, [_dp, _dp, _i, _i, _dp, _i]),
     "dcs_lanczos_operator": (_i, [_vp, _vp, _i, _i, _i, _vp, _dp, _dp, _ip, _i, _dp, _vp, _i, _vp, _sz, _vp]),
     "dcs_operator_create": (_i, [_i, _i, _i, _i32p, _i32p, _dp, _dp, _i, _i, _i, _pp]),
+    "dcs_operator_create_mixed": (_i, [_i, _i32p, _i, _i32p, _i32p, _dp, _dp, _i, _i, _i, _pp]),
     "dcs_operator_destroy": (_i, [_vp]),
     "dcs_operator_info": (_i, [_vp, _ip, _u64p, _ip, _ip]),
     "dcs_operator_apply": (_i, [_vp, _vp, _i, _i, _vp, _vp, _vp]),

@@ -88,6 +88,7 @@ extern "C" int dcs_enumerate(const dcs_sector *s, uint64_t first, size_t count, 
 static int check_apply_args(const dcs_sector *s, const dcs_terms *t, const double *jxy,
                             const double *jz, int dtype) {
     if (!s || !t) return set_error(DCS_EINVAL, "sector or terms is NULL");
+    if (int r = refuse_mixed(s)) return r;
     if (dtype != DCS_F32 && dtype != DCS_F64) return set_error(DCS_EINVAL, "dtype %d", dtype);
     if (t->num_bonds > 0 && (!jxy || !jz)) return set_error(DCS_EINVAL, "NULL couplings");
     if (t->max_site >= s->desc.L)
@@ -114,6 +115,7 @@ extern "C" int dcs_hamiltonian_form(const dcs_sector *s, const dcs_terms *t, int
                                     int *form) {
     clear_error();
     if (!s || !t || !form) return set_error(DCS_EINVAL, "NULL argument");
+    if (int r = refuse_mixed(s)) return r;
     if (dtype != DCS_F32 && dtype != DCS_F64) return set_error(DCS_EINVAL, "dtype %d", dtype);
     if (k != 1 && k != 2 && k != 4 && k != 8) return set_error(DCS_EINVAL, "k=%d not in {1,2,4,8}", k);
     *form = hx_form(s, t, dtype, k);
@@ -124,6 +126,7 @@ extern "C" int dcs_adjoint_workspace_size(const dcs_sector *s, const dcs_terms *
                                           size_t *bytes) {
     clear_error();
     if (!s || !t || !bytes) return set_error(DCS_EINVAL, "NULL argument");
+    if (int r = refuse_mixed(s)) return r;
     if (k != 1 && k != 2 && k != 4 && k != 8) return set_error(DCS_EINVAL, "k=%d not in {1,2,4,8}", k);
     *bytes = adjoint_ws_bytes(s, t, k);
     return DCS_OK;

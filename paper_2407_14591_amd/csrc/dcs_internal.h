@@ -56,12 +56,12 @@ struct Bad<uint64_t> {
 // Everything a kernel needs to know about a sector; passed by value.
 struct SectorDesc {
     uint64_t dim;
-    int Q, nb, L, n, N;
+    int Q, nb, L, n, N;             // Q: the largest local dimension (sets nb)
     int total_bits;                 // nb * L
     int shift[kMaxSub];             // bit position of P_k's word in the state
     int wbits[kMaxSub];             // nb * L_k
-    int gamma[kMaxSub];             // sites to the right of P_k
-    int mk[kMaxSub];                // (Q-1) * L_k
+    int rest_max[kMaxSub];          // largest digit sum of the sites to the right of P_k
+    int mk[kMaxSub];                // largest digit sum of P_k's sites ((Q-1) L_k for one Q)
     int lam_lo[kMaxSub], lam_hi[kMaxSub];
     uint32_t ctab_row0[kMaxSub];    // entry of C_k[lam_lo[k]][0]
     uint32_t ctab_rowlen[kMaxSub];  // entries per lambda row: 2^wbits, 0 for the last subsystem
@@ -239,6 +239,8 @@ struct dcs_sector {
     int split[dcs::kMaxSub];
     bool wide;  // 64-bit indices (dim >= 2^32)
     bool gtab;  // tables beyond the LDS budget: kernels read them in device memory
+    bool mixed;  // local dimensions differ between sites (qsite); XXZ products refuse it
+    int qsite[dcs::kMaxSites];  // local dimension of each site
     dcs::SectorDesc desc;
     dcs::SectorDev dev;
     dcs::LeftInfo left;
@@ -258,6 +260,13 @@ namespace dcs {
 int set_error(int code, const char *fmt, ...);
 int check_hip(hipError_t e, const char *what);
 void clear_error();
+
+// the XXZ products, their adjoint, expectation values and plans assume one local
+// dimension on every site: DCS_EUNSUPPORTED for a sector with several
+inline int refuse_mixed(const dcs_sector *s) {
+    if (s && s->mixed) return set_error(DCS_EUNSUPPORTED, "the XXZ products take one local dimension on every site");
+    return DCS_OK;
+}
 
 // Bond plan of one (sector, terms) pair: bonds sorted into classes (a, b) of
 // the subsystems of their two sites, a <= b, with i in P_a and j in P_b.

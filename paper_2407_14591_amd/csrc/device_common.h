@@ -113,7 +113,7 @@ __device__ __forceinline__ uint64_t unrank_state(const SectorDesc &sd, const Tab
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) {
         if (k < sd.N - 1) {
-            const int lo = max(0, sd.n - lam - (sd.Q - 1) * sd.gamma[k]);
+            const int lo = max(0, sd.n - lam - sd.rest_max[k]);
             const int hi = min(sd.mk[k], sd.n - lam);
             const uint32_t row = sd.dec_row0[k] + (uint32_t)(lam - sd.lam_lo[k]) * (sd.mk[k] + 1);
             int m = lo;

@@ -21,6 +21,7 @@ extern "C" int dcs_expectation_workspace_size(const dcs_sector *s, const dcs_ter
                                               size_t *bytes) {
     clear_error();
     if (!s || !t || !bytes) return set_error(DCS_EINVAL, "NULL argument");
+    if (int r = refuse_mixed(s)) return r;
     *bytes = align256(adjoint_ws_bytes(s, t)) + align256((size_t)std::max(t->num_bonds, 1) * sizeof(double));
     return DCS_OK;
 }
@@ -30,6 +31,7 @@ extern "C" int dcs_expectation_values(const dcs_sector *s, const dcs_terms *t, i
                                       void *ws, size_t ws_bytes, void *stream) {
     clear_error();
     if (!s || !t) return set_error(DCS_EINVAL, "sector or terms is NULL");
+    if (int r = refuse_mixed(s)) return r;
     if (dtype != DCS_F32 && dtype != DCS_F64) return set_error(DCS_EINVAL, "dtype %d", dtype);
     if (num < 0) return set_error(DCS_EINVAL, "num %d", num);
     if (num == 0) return DCS_OK;

@@ -768,6 +768,7 @@ extern "C" int dcs_lanczos(const dcs_sector *s, const dcs_terms *t, const double
                            size_t ws_bytes, void *stream) {
     clear_error();
     if (!s || !t || !v0 || !h_steps) return set_error(DCS_EINVAL, "NULL argument");
+    if (int r = refuse_mixed(s)) return r;
     if (dtype != DCS_F32 && dtype != DCS_F64) return set_error(DCS_EINVAL, "dtype %d", dtype);
     if (reorth < DCS_REORTH_NONE || reorth > DCS_REORTH_FULL)
         return set_error(DCS_EINVAL, "reorth %d", reorth);

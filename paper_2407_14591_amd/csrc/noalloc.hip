@@ -45,6 +45,7 @@ extern "C" int dcs_hamiltonian_apply_adjoint_noalloc(const dcs_sector *s, const 
                                                      double *gjz, double *gh, void *stream) {
     clear_error();
     if (!s || !t) return set_error(DCS_EINVAL, "sector or terms is NULL");
+    if (int r = refuse_mixed(s)) return r;
     if (dtype != DCS_F32 && dtype != DCS_F64) return set_error(DCS_EINVAL, "dtype %d", dtype);
     if (t->num_bonds > 0 && (!jxy || !jz)) return set_error(DCS_EINVAL, "NULL couplings");
     if (t->max_site >= s->desc.L)

@@ -291,7 +291,8 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
 }  // namespace dcs
 
 struct dcs_operator {
-    int Q = 0, L = 0, nb = 0, device = 0;
+    int Q = 0, L = 0, nb = 0, device = 0;  // Q: the largest local dimension
+    int qsite[dcs::kMaxSites] = {};        // local dimension of each site
     int ncl = 0, max_sites = 0;
     bool cplx = false;  // complex values (interleaved re, im)
     uint64_t nnz = 0;
@@ -306,33 +307,38 @@ namespace {
 using namespace dcs;
 using namespace dcs::op;
 
-// digit j (first site most significant) of the local index a over m sites
-inline int local_digit(uint32_t a, int j, int m, int Q) {
-    for (int k = m - 1; k > j; --k) a /= (uint32_t)Q;
-    return (int)(a % (uint32_t)Q);
+// The local index of digits (d_0, ..., d_{m-1}) on m sites of local dimensions
+// r_0, ..., r_{m-1} is the mixed-radix number with the first site most significant
+// (sum_j d_j Q^(m-1-j) when every r_j = Q).
+
+// digit j of the local index a
+inline int local_digit(uint32_t a, int j, int m, const int *r) {
+    for (int k = m - 1; k > j; --k) a /= (uint32_t)r[k];
+    return (int)(a % (uint32_t)r[j]);
 }
 
-inline int digit_sum_local(uint32_t a, int m, int Q) {
+inline int digit_sum_local(uint32_t a, int m, const int *r) {
     int s = 0;
-    for (int k = 0; k < m; ++k) {
-        s += (int)(a % (uint32_t)Q);
-        a /= (uint32_t)Q;
+    for (int k = m - 1; k >= 0; --k) {
+        s += (int)(a % (uint32_t)r[k]);
+        a /= (uint32_t)r[k];
     }
     return s;
 }
 
 // the digits of the local index a packed nb bits each, the first site most significant
 // (the cluster's digits as they lie in a packed state when its sites are adjacent)
-inline uint32_t pack_local(uint32_t a, int m, int Q, int nb) {
+inline uint32_t pack_local(uint32_t a, int m, const int *r, int nb) {
     uint32_t d = 0;
-    for (int j = 0; j < m; ++j) d |= (uint32_t)local_digit(a, j, m, Q) << (nb * (m - 1 - j));
+    for (int j = 0; j < m; ++j) d |= (uint32_t)local_digit(a, j, m, r) << (nb * (m - 1 - j));
     return d;
 }
 
-inline uint32_t ipow(int Q, int m) {
+// the number of digit strings on sites with local dimensions r_0..r_{m-1} (saturating)
+inline uint32_t local_size(const int *r, int m) {
     uint64_t v = 1;
-    for (int k = 0; k < m; ++k) v *= (uint64_t)Q;
-    return v > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)v;
+    for (int k = 0; k < m; ++k) v = std::min<uint64_t>(v * (uint64_t)r[k], 0xFFFFFFFFull);
+    return (uint32_t)v;
 }
 
 struct Entry {
@@ -342,15 +348,22 @@ struct Entry {
 
 }  // namespace
 
-extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *term_nsites,
-                                   const int32_t *term_sites, const double *term_coefs,
-                                   const double *term_mats, int complex_mats, int cluster_sites,
-                                   int device, dcs_operator **out) {
-    clear_error();
+namespace {
+
+// The operator on L sites, site i with qs[i] states (one Q for all, or one per site).
+int operator_create(const int *qs, int L, int num_terms, const int32_t *term_nsites, const int32_t *term_sites,
+                    const double *term_coefs, const double *term_mats, int complex_mats, int cluster_sites,
+                    int device, dcs_operator **out) {
     if (!out) return set_error(DCS_EINVAL, "out is NULL");
     *out = nullptr;
-    if (Q < 2 || Q > 16) return set_error(DCS_EINVAL, "Q=%d outside [2, 16]", Q);
-    if (L < 1 || L > kMaxSites) return set_error(DCS_EINVAL, "L=%d outside [1, %d]", L, kMaxSites);
+    int Q = 0;
+    for (int i = 0; i < L; ++i) {
+        if (qs[i] < 2 || qs[i] > 16) return set_error(DCS_EINVAL, "local dimension %d of site %d outside [2, 16]", qs[i], i);
+        Q = std::max(Q, qs[i]);
+    }
+    auto dims_of = [&](const int32_t *sites, int m, int *r) {
+        for (int j = 0; j < m; ++j) r[j] = qs[sites[j]];
+    };
     if (num_terms < 0) return set_error(DCS_EINVAL, "num_terms %d < 0", num_terms);
     if (num_terms > 0 && (!term_nsites || !term_sites || !term_coefs || !term_mats))
         return set_error(DCS_EINVAL, "NULL term array");
@@ -360,16 +373,14 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
     const int nc = complex_mats ? 2 : 1;  // doubles per matrix entry
     using cd = std::complex<double>;
     auto entry = [&](const double *M, size_t k) { return complex_mats ? cd(M[2 * k], M[2 * k + 1]) : cd(M[k], 0.0); };
-    // check every term; offsets of its sites and matrix
+    // check every term; offsets of its sites and matrix (a term's matrix has one row
+    // and one column per digit string on its sites: the product of their dimensions)
     std::vector<size_t> site_off(num_terms + 1, 0), mat_off(num_terms + 1, 0);
     for (int t = 0; t < num_terms; ++t) {
         const int m = term_nsites[t];
         if (m < 1 || m > kOpMaxSites)
             return set_error(DCS_EUNSUPPORTED, "term %d has %d sites (1..%d)", t, m, kOpMaxSites);
-        const uint32_t n = ipow(Q, m);
-        if (n > kOpMaxLocal) return set_error(DCS_EUNSUPPORTED, "term %d: Q^m = %u > %u", t, n, kOpMaxLocal);
         site_off[t + 1] = site_off[t] + (size_t)m;
-        mat_off[t + 1] = mat_off[t] + (size_t)n * n * nc;
     }
     for (int t = 0; t < num_terms; ++t) {
         const int m = term_nsites[t];
@@ -379,8 +390,13 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
             for (int k = 0; k < j; ++k)
                 if (st[k] == st[j]) return set_error(DCS_EINVAL, "term %d lists site %d twice", t, st[j]);
         }
+        int r[kOpMaxSites];
+        dims_of(st, m, r);
+        const uint32_t n = local_size(r, m);
+        if (n > kOpMaxLocal)
+            return set_error(DCS_EUNSUPPORTED, "term %d: %u digit strings on its sites > %u", t, n, kOpMaxLocal);
+        mat_off[t + 1] = mat_off[t] + (size_t)n * n * nc;
         if (!std::isfinite(term_coefs[t])) return set_error(DCS_EINVAL, "term %d: coefficient not finite", t);
-        const uint32_t n = ipow(Q, m);
         const double *M = term_mats + mat_off[t];
         for (uint32_t b = 0; b < n; ++b)
             for (uint32_t a = 0; a < n; ++a) {
@@ -399,8 +415,10 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
         for (size_t c = 0; c < cl_sites.size() && found < 0; ++c) {
             std::vector<int> U;
             std::set_union(cl_sites[c].begin(), cl_sites[c].end(), S.begin(), S.end(), std::back_inserter(U));
+            int ru[kMaxSites];
+            for (size_t j = 0; j < U.size() && j < (size_t)kMaxSites; ++j) ru[j] = qs[U[j]];
             if (U.size() == cl_sites[c].size() ||
-                ((int)U.size() <= cluster_sites && ipow(Q, (int)U.size()) <= kOpMaxLocal)) {
+                ((int)U.size() <= cluster_sites && local_size(ru, (int)U.size()) <= kOpMaxLocal)) {
                 found = (int)c;
                 cl_sites[c] = U;
             }
@@ -420,30 +438,34 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
     int max_sites = 0;
     for (size_t c = 0; c < cl_sites.size(); ++c) {
         const int m = (int)cl_sites[c].size();
-        const uint32_t n = ipow(Q, m);
+        int rc[kOpMaxSites];  // the cluster's local dimensions
+        for (int j = 0; j < m; ++j) rc[j] = qs[cl_sites[c][j]];
+        const uint32_t n = local_size(rc, m);
         max_sites = std::max(max_sites, m);
         std::vector<Entry> ents;
         for (int t : cl_terms[c]) {
             const int mt = term_nsites[t];
             const int32_t *st = term_sites + site_off[t];
-            const uint32_t nt = ipow(Q, mt);
+            int rt[kOpMaxSites];  // the term's local dimensions
+            dims_of(st, mt, rt);
+            const uint32_t nt = local_size(rt, mt);
             const double *M = term_mats + mat_off[t];
             int p[kOpMaxSites];  // cluster position of term site j
             for (int j = 0; j < mt; ++j)
                 p[j] = (int)(std::lower_bound(cl_sites[c].begin(), cl_sites[c].end(), st[j]) - cl_sites[c].begin());
             int da[kOpMaxSites];
             for (uint32_t a = 0; a < n; ++a) {  // input state of the cluster
-                for (int j = 0; j < m; ++j) da[j] = local_digit(a, j, m, Q);
+                for (int j = 0; j < m; ++j) da[j] = local_digit(a, j, m, rc);
                 uint32_t at = 0;
-                for (int j = 0; j < mt; ++j) at = at * (uint32_t)Q + (uint32_t)da[p[j]];
+                for (int j = 0; j < mt; ++j) at = at * (uint32_t)rt[j] + (uint32_t)da[p[j]];
                 for (uint32_t bt = 0; bt < nt; ++bt) {
                     const cd v = entry(M, (size_t)bt * nt + at);
                     if (v == 0.0) continue;
                     int db[kOpMaxSites];
                     std::copy(da, da + m, db);
-                    for (int j = 0; j < mt; ++j) db[p[j]] = local_digit(bt, j, mt, Q);
+                    for (int j = 0; j < mt; ++j) db[p[j]] = local_digit(bt, j, mt, rt);
                     uint32_t b = 0;
-                    for (int j = 0; j < m; ++j) b = b * (uint32_t)Q + (uint32_t)db[j];
+                    for (int j = 0; j < m; ++j) b = b * (uint32_t)rc[j] + (uint32_t)db[j];
                     ents.push_back({b, a, term_coefs[t] * v});
                 }
             }
@@ -471,8 +493,8 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
             bool valid = true;
             for (int j = 0; j < m; ++j) {
                 const uint32_t dj = (key >> (nb * (m - 1 - j))) & ((1u << nb) - 1u);
-                valid = valid && dj < (uint32_t)Q;
-                b = b * (uint32_t)Q + dj;
+                valid = valid && dj < (uint32_t)rc[j];
+                b = b * (uint32_t)rc[j] + dj;
             }
             if (!valid) continue;
             while (e < ents.size() && ents[e].row == b) {
@@ -483,7 +505,7 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
                     vabs += std::abs(ents[e].v);
                     v += ents[e++].v;
                 }
-                if (digit_sum_local(b, m, Q) != digit_sum_local(col, m, Q)) {
+                if (digit_sum_local(b, m, rc) != digit_sum_local(col, m, rc)) {
                     if (std::abs(v) > 1e-13 * std::max(vabs, vmax))
                         return set_error(DCS_EINVAL,
                                          "the terms on sites of cluster %zu do not conserve the particle number "
@@ -491,7 +513,7 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
                     continue;
                 }
                 if (v == 0.0) continue;
-                dep.push_back(pack_local(col, m, Q, nb));
+                dep.push_back(pack_local(col, m, rc, nb));
                 val.push_back(v);
             }
         }
@@ -500,6 +522,7 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
     dcs_operator *o = new (std::nothrow) dcs_operator();
     if (!o) return set_error(DCS_ENOMEM, "host allocation failed");
     o->Q = Q;
+    for (int i = 0; i < L; ++i) o->qsite[i] = qs[i];
     o->L = L;
     o->nb = nb;
     o->device = device;
@@ -569,6 +592,34 @@ extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *t
     return DCS_OK;
 }
 
+}  // namespace
+
+extern "C" int dcs_operator_create(int Q, int L, int num_terms, const int32_t *term_nsites,
+                                   const int32_t *term_sites, const double *term_coefs,
+                                   const double *term_mats, int complex_mats, int cluster_sites,
+                                   int device, dcs_operator **out) {
+    clear_error();
+    if (Q < 2 || Q > 16) return set_error(DCS_EINVAL, "Q=%d outside [2, 16]", Q);
+    if (L < 1 || L > kMaxSites) return set_error(DCS_EINVAL, "L=%d outside [1, %d]", L, kMaxSites);
+    int qs[kMaxSites];
+    for (int i = 0; i < L; ++i) qs[i] = Q;
+    return operator_create(qs, L, num_terms, term_nsites, term_sites, term_coefs, term_mats, complex_mats,
+                           cluster_sites, device, out);
+}
+
+extern "C" int dcs_operator_create_mixed(int L, const int32_t *local_dims, int num_terms,
+                                         const int32_t *term_nsites, const int32_t *term_sites,
+                                         const double *term_coefs, const double *term_mats, int complex_mats,
+                                         int cluster_sites, int device, dcs_operator **out) {
+    clear_error();
+    if (!local_dims) return set_error(DCS_EINVAL, "local_dims is NULL");
+    if (L < 1 || L > kMaxSites) return set_error(DCS_EINVAL, "L=%d outside [1, %d]", L, kMaxSites);
+    int qs[kMaxSites];
+    for (int i = 0; i < L; ++i) qs[i] = local_dims[i];
+    return operator_create(qs, L, num_terms, term_nsites, term_sites, term_coefs, term_mats, complex_mats,
+                           cluster_sites, device, out);
+}
+
 extern "C" int dcs_operator_destroy(dcs_operator *o) {
     clear_error();
     if (!o) return DCS_OK;
@@ -598,6 +649,10 @@ using namespace op;
 
 int operator_check(const dcs_sector *s, const dcs_operator *o, int dtype, int k) {
     if (!s || !o) return set_error(DCS_EINVAL, "NULL sector or operator");
+    for (int i = 0; i < o->L && o->L == s->desc.L; ++i)
+        if (o->qsite[i] != s->qsite[i])
+            return set_error(DCS_EINVAL, "site %d: local dimension %d in the operator, %d in the sector", i,
+                             o->qsite[i], s->qsite[i]);
     if (o->Q != s->desc.Q || o->L != s->desc.L)
         return set_error(DCS_EINVAL, "operator of Q=%d, L=%d on a sector of Q=%d, L=%d", o->Q, o->L, s->desc.Q,
                          s->desc.L);

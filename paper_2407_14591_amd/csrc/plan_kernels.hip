@@ -200,6 +200,7 @@ extern "C" int dcs_plan_create(int nsec, dcs_sector *const *secs, dcs_terms *con
         const dcs_sector *sec = secs[s];
         const dcs_terms *t = terms[s];
         if (!sec || !t) return set_error(DCS_EINVAL, "NULL sector or terms at %d", s);
+        if (int r = refuse_mixed(sec)) return r;
         if (sec->device != device) return set_error(DCS_EINVAL, "sectors on different devices");
         if (sec->wide) return set_error(DCS_EUNSUPPORTED, "plan sectors need dimension < 2^32");
         if (t->num_bonds > 0 && (!jxy[s] || !jz[s]))

@@ -13,32 +13,45 @@ namespace {
 
 typedef unsigned __int128 u128;
 
-// D_Q(l, m) for 0 <= l <= L, 0 <= m <= (Q-1) L, by the recurrence
-// D(l, m) = sum_{d<Q} D(l-1, m-d): the coefficients of (1 + x + ... + x^{Q-1})^l
-// (App. A).  Values must stay below 2^63; returns false on overflow.
+// get(l, m): the number of digit strings on the last l sites with digit sum m, for
+// 0 <= l <= L, by the recurrence D(l, m) = sum_{d < q} D(l-1, m-d) with q the local
+// dimension of the site that the l-th step adds: the coefficients of the product of
+// (1 + x + ... + x^{q_i - 1}) over those sites (App. A; with one Q, D_Q(l, m)).
+// Values must stay below 2^63; returns false on overflow.
 struct DimTable {
-    int Q = 0, L = 0, mmax = 0;
+    int L = 0, mmax = 0;
     std::vector<uint64_t> v;
-    bool build(int Q_, int L_) {
-        Q = Q_;
+    bool build(const int *qs, int L_) {
         L = L_;
-        mmax = (Q - 1) * L;
+        mmax = 0;
+        for (int i = 0; i < L; ++i) mmax += qs[i] - 1;
         v.assign((size_t)(L + 1) * (mmax + 1), 0);
         v[0] = 1;
-        for (int l = 1; l <= L; ++l)
-            for (int m = 0; m <= (Q - 1) * l; ++m) {
+        int cap = 0;
+        for (int l = 1; l <= L; ++l) {
+            const int q = qs[L - l];
+            cap += q - 1;
+            for (int m = 0; m <= cap; ++m) {
                 u128 acc = 0;
-                for (int d = 0; d < Q && d <= m; ++d) acc += get(l - 1, m - d);
+                for (int d = 0; d < q && d <= m; ++d) acc += get(l - 1, m - d);
                 if (acc >> 63) return false;
                 v[(size_t)l * (mmax + 1) + m] = (uint64_t)acc;
             }
+        }
         return true;
     }
     uint64_t get(int l, int m) const {
-        if (l < 0 || m < 0 || m > (Q - 1) * l) return 0;
+        if (l < 0 || l > L || m < 0 || m > mmax) return 0;
         return v[(size_t)l * (mmax + 1) + m];
     }
 };
+
+// the largest digit sum of sites [a, b)
+inline int max_sum(const int *qs, int a, int b) {
+    int t = 0;
+    for (int i = a; i < b; ++i) t += qs[i] - 1;
+    return t;
+}
 
 template <typename IdxT>
 struct HostTables {
@@ -49,19 +62,19 @@ struct HostTables {
 };
 
 template <typename IdxT>
-int build_tables(const DimTable &Dt, SectorDesc &sd, const int *split, HostTables<IdxT> &ht) {
-    const int Q = sd.Q, n = sd.n, L = sd.L;
+int build_tables(const DimTable &Dt, SectorDesc &sd, const int *split, const int *qs, HostTables<IdxT> &ht) {
+    const int n = sd.n, L = sd.L;
     int start = 0;
     uint32_t ctab_pos = 0, dec_pos = 0, inv_pos = 0, invs_pos = 0;
     for (int k = 0; k < sd.N; ++k) {
         const int Lk = split[k];
-        const int mk = (Q - 1) * Lk;
+        const int mk = max_sum(qs, start, start + Lk);
         const int g = L - start - Lk;
         const uint32_t W = 1u << sd.wbits[k];
-        sd.gamma[k] = g;
+        sd.rest_max[k] = max_sum(qs, start + Lk, L);
         sd.mk[k] = mk;
-        sd.lam_lo[k] = std::max(0, n - (Q - 1) * (L - start));
-        sd.lam_hi[k] = std::min(n, (Q - 1) * start);
+        sd.lam_lo[k] = std::max(0, n - max_sum(qs, start, L));
+        sd.lam_hi[k] = std::min(n, max_sum(qs, 0, start));
         // local tables: digit sum and lexicographic index of every word
         std::vector<int> sum(W);
         std::vector<uint32_t> lidx(W);
@@ -71,7 +84,7 @@ int build_tables(const DimTable &Dt, SectorDesc &sd, const int *split, HostTable
             bool ok = true;
             for (int i = 0; i < Lk; ++i) {
                 int d = (int)((w >> (sd.nb * i)) & ((1u << sd.nb) - 1));
-                ok = ok && d < Q;
+                ok = ok && d < qs[start + Lk - 1 - i];  // bits nb i hold the site's digit Lk-1-i
                 s += d;
             }
             sum[w] = ok ? s : -1;
@@ -100,14 +113,14 @@ int build_tables(const DimTable &Dt, SectorDesc &sd, const int *split, HostTable
             ctab_pos += W;
         }
         for (int lam = sd.lam_lo[k]; lam <= sd.lam_hi[k]; ++lam) {
-            const int lo = std::max(0, n - lam - (Q - 1) * g);
+            const int lo = std::max(0, n - lam - sd.rest_max[k]);
             const int hi = std::min(mk, n - lam);
             std::vector<u128> off(mk + 1, 0), str(mk + 1, 0);
             u128 run = 0;
             for (int m = 0; m <= mk; ++m) {
                 off[m] = run;
                 str[m] = (m >= lo && m <= hi) ? Dt.get(g, n - lam - m) : 0;
-                if (m >= lo && m <= hi) run += (u128)Dt.get(Lk, m) * Dt.get(g, n - lam - m);
+                if (m >= lo && m <= hi) run += (u128)cnt[m] * Dt.get(g, n - lam - m);
             }
             for (int m = 0; m <= mk; ++m) {
                 ht.dec_off.push_back((IdxT)off[m]);
@@ -202,7 +215,7 @@ int build_left(const DimTable &Dt, dcs_sector *s, const HostTables<IdxT> &ht, co
     li.K = 0;
     uint64_t min_dim = kSplitMinDim;
     if (const char *e = getenv("DCS_SPLIT_MIN_DIM")) min_dim = strtoull(e, nullptr, 10);
-    if (sd.N < 2 || sd.Q != 2 || sd.dim < min_dim) return DCS_OK;
+    if (sd.N < 2 || sd.Q != 2 || s->mixed || sd.dim < min_dim) return DCS_OK;
     const int K = sd.N / 2;
     int L_left = 0, bits = 0;
     for (int k = 0; k < K; ++k) {
@@ -355,6 +368,8 @@ void free_split(dcs_sector *s) {
 
 int make_bond_plan(const dcs_sector *s, const dcs_terms *t, int nmax, BondPlan *p) {
     const SectorDesc &sd = s->desc;
+    if (s->mixed)
+        return set_error(DCS_EUNSUPPORTED, "the XXZ products take one local dimension on every site");
     if (t->max_site >= sd.L)
         return set_error(DCS_EINVAL, "bond site %d outside the sector's %d sites", t->max_site,
                          sd.L);
@@ -393,17 +408,27 @@ int make_bond_plan(const dcs_sector *s, const dcs_terms *t, int nmax, BondPlan *
 
 using namespace dcs;
 
-extern "C" int dcs_sector_create(int L, int n, int Q, int N, const int *sizes, int device,
-                                 dcs_sector **out) {
-    clear_error();
+namespace {
+
+// The sector of n particles on L sites, site i with qs[i] states (one Q for all
+// sites, or a local dimension per site: Sec. 5 names this generalisation; every
+// count becomes a product over the sites' own (1 + x + ... + x^{q_i - 1})).
+int sector_create(int L, int n, const int *qs, int N, const int *sizes, int device, dcs_sector **out) {
     if (!out) return set_error(DCS_EINVAL, "out is NULL");
     *out = nullptr;
-    if (Q < 2 || Q > 16) return set_error(DCS_EINVAL, "local_dim %d outside [2, 16]", Q);
+    if (L < 1 || L > kMaxSites) return set_error(DCS_EINVAL, "L=%d outside [1, %d]", L, kMaxSites);
+    int Q = 0;
+    bool mixed = false;
+    for (int i = 0; i < L; ++i) {
+        if (qs[i] < 2 || qs[i] > 16) return set_error(DCS_EINVAL, "local_dim %d of site %d outside [2, 16]", qs[i], i);
+        Q = std::max(Q, qs[i]);
+        mixed = mixed || qs[i] != qs[0];
+    }
     int nb = 0;
     while ((1 << nb) < Q) ++nb;
-    if (L < 1 || L * nb > 64) return set_error(DCS_EINVAL, "L=%d needs %d bits > 64", L, L * nb);
-    if (n < 0 || n > (Q - 1) * L)
-        return set_error(DCS_EINVAL, "n_particles %d outside [0, %d]", n, (Q - 1) * L);
+    if (L * nb > 64) return set_error(DCS_EINVAL, "L=%d needs %d bits > 64", L, L * nb);
+    const int nmax = max_sum(qs, 0, L);
+    if (n < 0 || n > nmax) return set_error(DCS_EINVAL, "n_particles %d outside [0, %d]", n, nmax);
     int split[kMaxSub];
     if (sizes == nullptr) {
         int per = std::max(1, 9 / nb);
@@ -433,16 +458,21 @@ extern "C" int dcs_sector_create(int L, int n, int Q, int N, const int *sizes, i
         return set_error(DCS_EINVAL, "device %d outside [0, %d)", device, ndev);
 
     DimTable Dt;
-    if (!Dt.build(Q, L)) return set_error(DCS_EUNSUPPORTED, "sector dimensions exceed 2^63");
-    for (int k = 0; k < N; ++k)
-        for (int m = 0; m <= (Q - 1) * split[k]; ++m)
-            if (Dt.get(split[k], m) > kMaxClassWords)
+    if (!Dt.build(qs, L)) return set_error(DCS_EUNSUPPORTED, "sector dimensions exceed 2^63");
+    for (int k = 0, start = 0; k < N; start += split[k++]) {
+        DimTable Dk;  // the words of subsystem k alone
+        Dk.build(qs + start, split[k]);
+        for (int m = 0; m <= Dk.mmax; ++m)
+            if (Dk.get(split[k], m) > kMaxClassWords)
                 return set_error(DCS_EUNSUPPORTED, "subsystem %d has %llu words of digit sum %d > %llu", k,
-                                 (unsigned long long)Dt.get(split[k], m), m,
+                                 (unsigned long long)Dk.get(split[k], m), m,
                                  (unsigned long long)kMaxClassWords);
+    }
     dcs_sector *s = new (std::nothrow) dcs_sector();
     if (!s) return set_error(DCS_ENOMEM, "host allocation failed");
     s->device = device;
+    s->mixed = mixed;
+    for (int i = 0; i < L; ++i) s->qsite[i] = qs[i];
     SectorDesc &sd = s->desc;
     memset(&sd, 0, sizeof(sd));
     sd.Q = Q;
@@ -476,12 +506,12 @@ extern "C" int dcs_sector_create(int L, int n, int Q, int N, const int *sizes, i
     int r;
     if (s->wide) {
         HostTables<uint64_t> ht;
-        r = build_tables(Dt, sd, split, ht);
+        r = build_tables(Dt, sd, split, qs, ht);
         if (!r) r = upload(s, ht);
         if (!r) r = build_left(Dt, s, ht, split);
     } else {
         HostTables<uint32_t> ht;
-        r = build_tables(Dt, sd, split, ht);
+        r = build_tables(Dt, sd, split, qs, ht);
         if (!r) r = upload(s, ht);
         if (!r) r = build_left(Dt, s, ht, split);
     }
@@ -496,6 +526,35 @@ extern "C" int dcs_sector_create(int L, int n, int Q, int N, const int *sizes, i
         return r;
     }
     *out = s;
+    return DCS_OK;
+}
+
+}  // namespace
+
+extern "C" int dcs_sector_create(int L, int n, int Q, int N, const int *sizes, int device,
+                                 dcs_sector **out) {
+    clear_error();
+    if (Q < 2 || Q > 16) return set_error(DCS_EINVAL, "local_dim %d outside [2, 16]", Q);
+    if (L < 1 || L > kMaxSites) return set_error(DCS_EINVAL, "L=%d outside [1, %d]", L, kMaxSites);
+    int qs[kMaxSites];
+    for (int i = 0; i < L; ++i) qs[i] = Q;
+    return sector_create(L, n, qs, N, sizes, device, out);
+}
+
+extern "C" int dcs_sector_create_mixed(int L, int n, const int32_t *local_dims, int N, const int *sizes,
+                                       int device, dcs_sector **out) {
+    clear_error();
+    if (!local_dims) return set_error(DCS_EINVAL, "local_dims is NULL");
+    if (L < 1 || L > kMaxSites) return set_error(DCS_EINVAL, "L=%d outside [1, %d]", L, kMaxSites);
+    int qs[kMaxSites];
+    for (int i = 0; i < L; ++i) qs[i] = local_dims[i];
+    return sector_create(L, n, qs, N, sizes, device, out);
+}
+
+extern "C" int dcs_sector_local_dims(const dcs_sector *s, int32_t *local_dims) {
+    clear_error();
+    if (!s || !local_dims) return set_error(DCS_EINVAL, "NULL argument");
+    for (int i = 0; i < s->desc.L; ++i) local_dims[i] = s->qsite[i];
     return DCS_OK;
 }
 
