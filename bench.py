@@ -370,6 +370,40 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
                                    "achieved_GBs": big.dim * 32 / per_l / 1e9,
                                    "frac_of_peak": big.dim * 32 / per_l / 1e9 / PEAK_HBM_GBS}
     del xc, yc, lop, big
+
+    # sites of different local dimensions (Sec. 5's generalisation): the antiferromagnetic
+    # Heisenberg ring of alternating spin-1/2 and spin-1 sites, L=24, Sz=0 (n=18), as
+    # operator strings; one FP64 and one FP32 product, and rank / unrank of 2^24 states
+    dims = [2, 3] * 12
+    mterms = []
+    for i in range(24):
+        j = (i + 1) % 24
+        mterms += [dq.operator_string(1.0, (i, j), ("Sz", "Sz"), dims),
+                   dq.operator_string(0.5, (i, j), ("S+", "S-"), dims),
+                   dq.operator_string(0.5, (i, j), ("S-", "S+"), dims)]
+    mop = dq.Operator(dims, 24, mterms, cluster_sites=4)
+    ms = dq.Sector(24, 18, dims, device=0)
+    entry = {"dim": ms.dim, "split": ms.split, "clusters": mop.num_clusters, "nnz": mop.nnz}
+    for tag, dt, vb in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+        xm = torch.randn(ms.dim, generator=g, device=dev, dtype=torch.float64).to(dt)
+        ym = torch.empty_like(xm)
+        per_m = timed(lambda: dq.operator_apply(ms, mop, xm, out=ym), n=max(3, steps // 4), w=1)
+        entry[f"{tag}_ms"] = per_m * 1e3
+        entry[f"{tag}_states_per_s"] = ms.dim / per_m
+        entry[f"{tag}_frac_of_peak"] = ms.dim * 2 * vb / per_m / 1e9 / PEAK_HBM_GBS
+        del xm, ym
+    nr = 1 << 24
+    ids = torch.randint(0, ms.dim, (nr,), generator=g, device=dev, dtype=torch.int64)
+    sts = ms.unrank(ids)
+    back = torch.empty_like(ids)
+    per_u = timed(lambda: ms.unrank(ids, out=sts), n=max(3, steps // 4), w=1)
+    per_r = timed(lambda: ms.rank(sts, out=back), n=max(3, steps // 4), w=1)
+    if not torch.equal(back, ids):
+        raise RuntimeError("mixed sector: rank(unrank(i)) != i")
+    entry["unrank_per_s"] = nr / per_u
+    entry["rank_per_s"] = nr / per_r
+    out["mixed_ring_L24_operator"] = entry
+    del ids, sts, back, mop, ms
     torch.cuda.empty_cache()
     return out
 
