@@ -218,6 +218,24 @@ int dcs_lex_unrank(int L, int n_particles, const uint64_t *d_idx, uint64_t *d_st
                    uint64_t *d_num_invalid, void *stream);
 
 /*
+ * The same for any local dimension Q in [2, 16] (eq. N=L with D_Q): the canonical
+ * order of L single-site subsystems is the lexicographic order of the digit strings
+ * (ceil(log2 Q) bits per site, site 0 most significant), and Alg. on-the-fly gives
+ * the rank as the sum over the sites i of sum_{k < q_i} D_Q(L-1-i, n - lambda_i - k).
+ * No sector object and no tables of states: every workgroup derives the counts
+ * D_Q(g, m), g < L, m <= n, in LDS by App. A's recurrence before serving its states,
+ * and unrank walks them digit by digit.  States with a digit >= Q, set bits above the
+ * L fields or another digit sum rank to DCS_INVALID_INDEX; indices >= D unrank to it;
+ * both are counted as in dcs_rank.  DCS_EINVAL for Q outside [2, 16], L < 1 or
+ * L ceil(log2 Q) > 64, n outside [0, (Q-1) L]; DCS_EUNSUPPORTED if a count reaches
+ * 2^64 or the count table passes 64 KiB of LDS.
+ */
+int dcs_lex_rank_q(int L, int n_particles, int Q, const uint64_t *d_states, uint64_t *d_idx, size_t count,
+                   uint64_t *d_num_invalid, void *stream);
+int dcs_lex_unrank_q(int L, int n_particles, int Q, const uint64_t *d_idx, uint64_t *d_states, size_t count,
+                     uint64_t *d_num_invalid, void *stream);
+
+/*
  * Enumeration, function (ii) of Sec. 2.2 applied count-1 times from state
  * `first`: d_states[t] = state with index first + t.  Does not wrap: returns
  * DCS_ERANGE if first + count > D (the paper's increment wraps to the first

@@ -510,25 +510,33 @@ def expectation_values(sector: Sector, terms: Terms, psi, fields: bool = True):
     return {"xy": exy, "z": ez, "sz": esz}
 
 
-def lex_rank(L: int, n: int, states: torch.Tensor, out: torch.Tensor | None = None, count_invalid=False):
-    """Ranks in the lexicographic (N = L, on-the-fly) order of the Q = 2 sector (dcs_lex_rank)."""
+def lex_rank(L: int, n: int, states: torch.Tensor, out: torch.Tensor | None = None, count_invalid=False, Q: int = 2):
+    """Ranks in the lexicographic (N = L, on-the-fly) order of the sector (dcs_lex_rank for
+    Q = 2, dcs_lex_rank_q for any Q)."""
     dev = states.device.index if states.is_cuda else 0
     _check_dev(states, dev, "states", (torch.int64, torch.uint64))
     out = torch.empty_like(states) if out is None else out
     _check_dev(out, dev, "out", (torch.int64, torch.uint64), numel=states.numel())
     cnt = torch.zeros(1, dtype=torch.int64, device=states.device) if count_invalid else None
-    call("dcs_lex_rank", L, n, _ptr(states), _ptr(out), states.numel(), _ptr(cnt), _stream(dev))
+    if Q == 2:
+        call("dcs_lex_rank", L, n, _ptr(states), _ptr(out), states.numel(), _ptr(cnt), _stream(dev))
+    else:
+        call("dcs_lex_rank_q", L, n, Q, _ptr(states), _ptr(out), states.numel(), _ptr(cnt), _stream(dev))
     return (out, cnt) if count_invalid else out
 
 
-def lex_unrank(L: int, n: int, idx: torch.Tensor, out: torch.Tensor | None = None, count_invalid=False):
-    """States at lexicographic (N = L, on-the-fly) positions of the Q = 2 sector (dcs_lex_unrank)."""
+def lex_unrank(L: int, n: int, idx: torch.Tensor, out: torch.Tensor | None = None, count_invalid=False, Q: int = 2):
+    """States at lexicographic (N = L, on-the-fly) positions of the sector (dcs_lex_unrank for
+    Q = 2, dcs_lex_unrank_q for any Q)."""
     dev = idx.device.index if idx.is_cuda else 0
     _check_dev(idx, dev, "idx", (torch.int64, torch.uint64))
     out = torch.empty_like(idx) if out is None else out
     _check_dev(out, dev, "out", (torch.int64, torch.uint64), numel=idx.numel())
     cnt = torch.zeros(1, dtype=torch.int64, device=idx.device) if count_invalid else None
-    call("dcs_lex_unrank", L, n, _ptr(idx), _ptr(out), idx.numel(), _ptr(cnt), _stream(dev))
+    if Q == 2:
+        call("dcs_lex_unrank", L, n, _ptr(idx), _ptr(out), idx.numel(), _ptr(cnt), _stream(dev))
+    else:
+        call("dcs_lex_unrank_q", L, n, Q, _ptr(idx), _ptr(out), idx.numel(), _ptr(cnt), _stream(dev))
     return (out, cnt) if count_invalid else out
 
 

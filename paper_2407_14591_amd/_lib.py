@@ -49,6 +49,8 @@ SIGNATURES = {
     "dcs_sector_tables": (_i, [_vp, _ip, _szp]),
     "dcs_lex_rank": (_i, [_i, _i, _vp, _vp, _sz, _vp, _vp]),
     "dcs_lex_unrank": (_i, [_i, _i, _vp, _vp, _sz, _vp, _vp]),
+    "dcs_lex_rank_q": (_i, [_i, _i, _i, _vp, _vp, _sz, _vp, _vp]),
+    "dcs_lex_unrank_q": (_i, [_i, _i, _i, _vp, _vp, _sz, _vp, _vp]),
     "dcs_rank": (_i, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "dcs_rank_search": (_i, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "dcs_unrank": (_i, [_vp, _vp, _vp, _sz, _vp, _vp]),

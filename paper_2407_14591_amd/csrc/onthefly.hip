@@ -9,6 +9,9 @@
 // sector the host admits (checked there).
 #include "dcs_internal.h"
 
+#include <algorithm>
+#include <vector>
+
 namespace {
 
 constexpr int kThreads = 256;
@@ -90,6 +93,92 @@ __global__ __launch_bounds__(kThreads) void lex_unrank_kernel(int L, int n, uint
     }
 }
 
+// Any Q (eq. N=L with D_Q): the rank is the sum over the sites i of
+// sum_{k < q_i} D_Q(L-1-i, n - lambda_i - k), the number of completions that put a
+// smaller digit at site i.  D_Q(g, m) for g < L and m <= n is a small count table,
+// not a table of states: every workgroup builds it in LDS by App. A's recurrence
+// D(g, m) = sum_{d < Q} D(g-1, m-d), one row per step, and then serves its states.
+// The host checks that every entry stays below 2^64.
+__device__ void build_counts(uint64_t *Dt, int L, int n, int Q) {
+    const int W = n + 1;
+    for (int m = threadIdx.x; m <= n; m += blockDim.x) Dt[m] = m == 0 ? 1u : 0u;
+    __syncthreads();
+    for (int g = 1; g < L; ++g) {
+        for (int m = threadIdx.x; m <= n; m += blockDim.x) {
+            uint64_t acc = 0;
+            for (int d = 0; d < Q && d <= m; ++d) acc += Dt[(g - 1) * W + m - d];
+            Dt[g * W + m] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void lexq_rank_kernel(int L, int n, int Q, int nb, const uint64_t *__restrict__ st,
+                                                             uint64_t *__restrict__ out, size_t count, uint64_t *nbad) {
+    extern __shared__ uint64_t Dt[];  // [L][n + 1]
+    build_counts(Dt, L, n, Q);
+    const int W = n + 1;
+    const uint64_t dmask = (1ull << nb) - 1ull;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t base = (size_t)blockIdx.x * blockDim.x; base < count; base += stride) {
+        const size_t t = base + threadIdx.x;
+        bool bad = false;
+        if (t < count) {
+            const uint64_t s = st[t];
+            bad = L * nb < 64 && (s >> (L * nb)) != 0;
+            uint64_t idx = 0;
+            int lam = 0;
+            for (int i = 0; i < L && !bad; ++i) {
+                const int g = L - 1 - i;
+                const int q = (int)((s >> (nb * g)) & dmask);
+                bad = q >= Q || lam + q > n;
+                for (int k = 0; k < q && !bad; ++k) {
+                    const int m = n - lam - k;  // in [0, n]: lam + q <= n
+                    idx += Dt[g * W + m];
+                }
+                lam += q;
+            }
+            bad = bad || lam != n;
+            out[t] = bad ? DCS_INVALID_INDEX : idx;
+        }
+        count_bad(nbad, bad);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void lexq_unrank_kernel(int L, int n, int Q, int nb, uint64_t dim,
+                                                               const uint64_t *__restrict__ ix, uint64_t *__restrict__ out,
+                                                               size_t count, uint64_t *nbad) {
+    extern __shared__ uint64_t Dt[];  // [L][n + 1]
+    build_counts(Dt, L, n, Q);
+    const int W = n + 1;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t base = (size_t)blockIdx.x * blockDim.x; base < count; base += stride) {
+        const size_t t = base + threadIdx.x;
+        bool bad = false;
+        if (t < count) {
+            uint64_t idx = ix[t];
+            bad = idx >= dim;
+            uint64_t s = 0;
+            int rem = n;
+            for (int i = 0; i < L && !bad; ++i) {
+                const int g = L - 1 - i;
+                // the digit: skip the completions of every smaller digit
+                int d = 0;
+                for (; d < Q - 1 && d <= rem; ++d) {
+                    const uint64_t c = Dt[g * W + rem - d];
+                    if (idx < c) break;
+                    idx -= c;
+                }
+                s |= (uint64_t)d << (nb * g);
+                rem -= d;
+            }
+            bad = bad || rem != 0;
+            out[t] = bad ? DCS_INVALID_INDEX : s;
+        }
+        count_bad(nbad, bad);
+    }
+}
+
 // C(a, b) exactly (host, 128-bit), and the largest product the kernels form
 unsigned __int128 binom(int a, int b) {
     if (b < 0 || b > a) return 0;
@@ -111,6 +200,33 @@ int check_args(int L, int n, uint64_t *dim_out) {
         }
     if (worst >> 64) return dcs::set_error(DCS_EUNSUPPORTED, "L=%d, n=%d: the on-the-fly coefficients pass 2^64", L, n);
     *dim_out = (uint64_t)binom(L, n);
+    return DCS_OK;
+}
+
+// the checks of the any-Q calls; the dimension and the LDS bytes of the count table
+int check_args_q(int L, int n, int Q, int *nb_out, uint64_t *dim_out, size_t *lds_out) {
+    if (Q < 2 || Q > 16) return dcs::set_error(DCS_EINVAL, "Q=%d outside [2, 16]", Q);
+    int nb = 0;
+    while ((1 << nb) < Q) ++nb;
+    if (L < 1 || L * nb > 64) return dcs::set_error(DCS_EINVAL, "L=%d outside [1, %d]", L, 64 / nb);
+    if (n < 0 || n > (Q - 1) * L) return dcs::set_error(DCS_EINVAL, "n_particles %d outside [0, %d]", n, (Q - 1) * L);
+    // D_Q(g, m) for g <= L, m <= n in 128 bits: every entry the kernels hold (g < L) and
+    // the dimension D_Q(L, n) must stay below 2^64
+    std::vector<unsigned __int128> prev(n + 1, 0), cur(n + 1, 0);
+    prev[0] = 1;
+    for (int g = 1; g <= L; ++g) {
+        for (int m = 0; m <= n; ++m) {
+            unsigned __int128 acc = 0;
+            for (int d = 0; d < Q && d <= m; ++d) acc += prev[m - d];
+            if (acc >> 64) return dcs::set_error(DCS_EUNSUPPORTED, "L=%d, n=%d, Q=%d: counts pass 2^64", L, n, Q);
+            cur[m] = acc;
+        }
+        std::swap(prev, cur);
+    }
+    *nb_out = nb;
+    *dim_out = (uint64_t)prev[n];
+    *lds_out = (size_t)L * (size_t)(n + 1) * sizeof(uint64_t);
+    if (*lds_out > 64 * 1024) return dcs::set_error(DCS_EUNSUPPORTED, "count table of %zu bytes", *lds_out);
     return DCS_OK;
 }
 
@@ -143,5 +259,31 @@ extern "C" int dcs_lex_unrank(int L, int n, const uint64_t *idx, uint64_t *st, s
     if (!st || !idx) return set_error(DCS_EINVAL, "NULL array");
     const uint64_t c0 = (uint64_t)binom(L - 1, n);
     lex_unrank_kernel<<<grid(count), kThreads, 0, (hipStream_t)stream>>>(L, n, dim, idx, st, count, c0, nbad);
+    return check_hip(hipGetLastError(), "lex unrank launch");
+}
+
+extern "C" int dcs_lex_rank_q(int L, int n, int Q, const uint64_t *st, uint64_t *idx, size_t count, uint64_t *nbad,
+                              void *stream) {
+    clear_error();
+    int nb = 0;
+    uint64_t dim = 0;
+    size_t lds = 0;
+    if (int r = check_args_q(L, n, Q, &nb, &dim, &lds)) return r;
+    if (count == 0) return DCS_OK;
+    if (!st || !idx) return set_error(DCS_EINVAL, "NULL array");
+    lexq_rank_kernel<<<grid(count), kThreads, lds, (hipStream_t)stream>>>(L, n, Q, nb, st, idx, count, nbad);
+    return check_hip(hipGetLastError(), "lex rank launch");
+}
+
+extern "C" int dcs_lex_unrank_q(int L, int n, int Q, const uint64_t *idx, uint64_t *st, size_t count, uint64_t *nbad,
+                                void *stream) {
+    clear_error();
+    int nb = 0;
+    uint64_t dim = 0;
+    size_t lds = 0;
+    if (int r = check_args_q(L, n, Q, &nb, &dim, &lds)) return r;
+    if (count == 0) return DCS_OK;
+    if (!st || !idx) return set_error(DCS_EINVAL, "NULL array");
+    lexq_unrank_kernel<<<grid(count), kThreads, lds, (hipStream_t)stream>>>(L, n, Q, nb, dim, idx, st, count, nbad);
     return check_hip(hipGetLastError(), "lex unrank launch");
 }

@@ -231,3 +231,54 @@ def test_lex_rank_L32_against_oracle():
     _, nb = dq.lex_unrank(L, n, to_dev(np.array([601080389, 601080390, 2 ** 40], dtype=np.uint64)),
                           count_invalid=True)
     assert int(nb.item()) == 2
+
+
+@pytest.mark.parametrize("Q,L,n", [(3, 1, 2), (3, 6, 6), (3, 8, 3), (3, 9, 0), (3, 9, 18), (4, 5, 7), (5, 4, 8),
+                                   (7, 3, 9), (16, 3, 20), (2, 12, 6)])
+def test_lex_rank_any_q_full(Q, L, n):
+    """Any Q (eq. N=L with D_Q): every state of the sector in the canonical order of L
+    one-site subsystems (the brute-force oracle's sort) against rank and unrank."""
+    from oracle.sector import BruteSector
+    bs = BruteSector(Q, L, n, [1] * L)
+    st = to_dev(bs.states)
+    ar = np.arange(bs.dim, dtype=np.uint64)
+    if Q == 2:  # the any-Q kernels through the C ABI, beside the binomial ones
+        out = torch.empty_like(st)
+        dq._lib.call("dcs_lex_rank_q", L, n, 2, st.data_ptr(), out.data_ptr(), bs.dim, None, None)
+        assert np.array_equal(to_host_u64(out), ar)
+    idx, bad = dq.lex_rank(L, n, st, count_invalid=True, Q=Q)
+    assert int(bad.item()) == 0 and np.array_equal(to_host_u64(idx), ar)
+    back, bad = dq.lex_unrank(L, n, to_dev(ar), count_invalid=True, Q=Q)
+    assert int(bad.item()) == 0 and np.array_equal(to_host_u64(back), bs.states)
+
+
+@pytest.mark.parametrize("Q,L,n", [(3, 32, 32), (5, 21, 42)])
+def test_lex_rank_any_q_against_oracle(Q, L, n):
+    """2^16 random states of a large sector round-trip; 1024 of them against the oracle's
+    lexicographic rank; digits >= Q, bits above the fields, other digit sums and indices
+    >= D are counted."""
+    from oracle.sector import dim_closed
+    from oracle.sector import lex_rank as o_lex_rank
+    dig = synth.random_states(Q, L, n, 1 << 16, seed=23)
+    st = synth.pack_digits(dig, Q)
+    idx = dq.lex_rank(L, n, to_dev(st), Q=Q)
+    got = to_host_u64(idx)
+    ref = np.array([o_lex_rank(list(int(v) for v in d), Q) for d in dig[:1024]], dtype=np.uint64)
+    assert np.array_equal(got[:1024], ref)
+    assert np.array_equal(to_host_u64(dq.lex_unrank(L, n, idx, Q=Q)), st)
+    dim = dim_closed(Q, L, n)
+    assert int(got.max()) < dim
+    nb = (Q - 1).bit_length()
+    bad = st.copy()
+    bad[:40] ^= np.uint64(1 << (nb * L)) if nb * L < 64 else np.uint64(0)  # a bit above the fields
+    hi = np.uint64((1 << nb) - 1)
+    # a digit >= Q at site 0 (all ones in its field) where the field allows one
+    bad[40:60] = (bad[40:60] & ~(hi << np.uint64(nb * (L - 1)))) | (hi << np.uint64(nb * (L - 1)))
+    bad[60:90] ^= np.uint64(1)  # another digit sum, or a digit >= Q
+    _, cnt = dq.lex_rank(L, n, to_dev(bad), count_invalid=True, Q=Q)
+    want = (40 if nb * L < 64 else 0) + 20 + 30
+    assert int(cnt.item()) == want
+    _, cnt = dq.lex_unrank(L, n, to_dev(np.array([dim - 1, dim, 2 ** 62], dtype=np.uint64)), count_invalid=True, Q=Q)
+    assert int(cnt.item()) == 2
+    with pytest.raises(dq.DcsError):
+        dq.lex_rank(L + 64, n, to_dev(st[:4]), Q=Q)
