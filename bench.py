@@ -404,6 +404,19 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
     entry["rank_per_s"] = nr / per_r
     out["mixed_ring_L24_operator"] = entry
     del ids, sts, back, mop, ms
+
+    # the on-the-fly limit (eq. N=L) for Q = 3, L = 32, n = 32 (1.6e14 states): unrank 2^24
+    # random indices and rank them back, with no tables of states
+    d3 = dq.Sector(32, 32, 3, device=0).dim
+    ids = torch.randint(0, d3, (nr,), generator=g, device=dev, dtype=torch.int64)
+    sts = dq.lex_unrank(32, 32, ids, Q=3)
+    back = torch.empty_like(ids)
+    per_u = timed(lambda: dq.lex_unrank(32, 32, ids, out=sts, Q=3), n=max(3, steps // 4), w=1)
+    per_r = timed(lambda: dq.lex_rank(32, 32, sts, out=back, Q=3), n=max(3, steps // 4), w=1)
+    if not torch.equal(back, ids):
+        raise RuntimeError("on-the-fly Q=3: rank(unrank(i)) != i")
+    out["onthefly_Q3_L32"] = {"dim": d3, "unrank_per_s": nr / per_u, "rank_per_s": nr / per_r}
+    del ids, sts, back
     torch.cuda.empty_cache()
     return out
 
