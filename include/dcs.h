@@ -472,6 +472,25 @@ int dcs_operator_info(const dcs_operator *op, int *num_clusters, uint64_t *nnz,
 int dcs_operator_apply(const dcs_sector *sector, const dcs_operator *op, int dtype, int k,
                        const void *d_x, void *d_y, void *stream);
 
+/*
+ * Expectation values of a generic operator (the measurements App. D takes with the
+ * operator class): d_out[c] = sum_s x[s][c] (O x)[s][c] for each of the k real
+ * columns (k in {1, 2, 4, 8}; <x|O|x> when O is symmetric), or, for complex vectors
+ * (k = 1), d_out[0] + i d_out[1] = sum_s conj(x_s) (O x)_s.  The product is the one of
+ * dcs_operator_apply, but no y is stored: each row's contribution is summed in FP64,
+ * every workgroup writes its sum to d_ws, and a second kernel adds those in workgroup
+ * order, so the result does not depend on timing.  d_out is device memory of k
+ * doubles (2 for complex vectors); d_ws of at least the bytes
+ * dcs_operator_expectation_workspace_size gives (caller-owned, reused freely between
+ * calls, not shared by calls that overlap).  Errors as dcs_operator_apply, and
+ * DCS_EINVAL for a NULL output or workspace or a workspace too small.  Asynchronous
+ * on `stream`.
+ */
+int dcs_operator_expectation_workspace_size(const dcs_sector *sector, const dcs_operator *op, int k,
+                                            size_t *bytes);
+int dcs_operator_expectation(const dcs_sector *sector, const dcs_operator *op, int dtype, int k,
+                             const void *d_x, double *d_out, void *d_ws, size_t ws_bytes, void *stream);
+
 /* ========================================================================== */
 /* Batched: many sectors in one launch                                        */
 /* ========================================================================== */

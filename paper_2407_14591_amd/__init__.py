@@ -22,7 +22,7 @@ from ._lib import (DCS_F32, DCS_F64, DCS_INVALID_INDEX, DCS_REORTH_FULL, DCS_REO
 
 __all__ = ["Sector", "Terms", "Plan", "hamiltonian_apply", "hamiltonian_apply_adjoint",
            "hamiltonian_form", "hamiltonian_apply_adjoint_noalloc",
-           "HApply", "lanczos", "tridiag_eigvals", "lex_rank", "lex_unrank", "expectation_values", "DcsError", "DCS_INVALID_INDEX",
+           "HApply", "lanczos", "tridiag_eigvals", "lex_rank", "lex_unrank", "expectation_values", "DcsError", "DCS_INVALID_INDEX", "operator_expectation",
            "library_path", "Operator", "operator_apply", "local_operator", "operator_string",
            "lindbladian_terms"]
 
@@ -317,6 +317,27 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+
+def operator_expectation(sector: "Sector", op: Operator, x):
+    """Expectation values without storing O x (dcs_operator_expectation): for real x of
+    shape [dim] or [dim, k], a float64 tensor of the k sums sum_s x[s, c] (O x)[s, c];
+    for complex x of shape [dim], the complex sum_s conj(x_s) (O x)_s (complex128)."""
+    codes = {torch.float32: _lib.DCS_F32, torch.float64: _lib.DCS_F64, torch.complex64: _lib.DCS_C64,
+             torch.complex128: _lib.DCS_C128}
+    _check_dev(x, sector.device, "x", tuple(codes))
+    k = _block_shape(sector, x)
+    if x.is_complex() and k != 1:
+        raise ValueError("complex vectors take one column")
+    nb = C.c_size_t()
+    call("dcs_operator_expectation_workspace_size", sector._h, op._h, k, C.byref(nb))
+    ws = torch.empty(max(int(nb.value), 8), dtype=torch.uint8, device=x.device)
+    out = torch.empty(2 if x.is_complex() else k, dtype=torch.float64, device=x.device)
+    call("dcs_operator_expectation", sector._h, op._h, codes[x.dtype], k, _ptr(x), _ptr(out), _ptr(ws),
+         ws.numel(), _stream(sector.device))
+    if x.is_complex():
+        return torch.complex(out[0], out[1])
+    return out
 
 
 def operator_apply(sector: "Sector", op: Operator, x, out=None):

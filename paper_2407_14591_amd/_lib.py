@@ -79,6 +79,8 @@ SIGNATURES = {
     "dcs_operator_destroy": (_i, [_vp]),
     "dcs_operator_info": (_i, [_vp, _ip, _u64p, _ip, _ip]),
     "dcs_operator_apply": (_i, [_vp, _vp, _i, _i, _vp, _vp, _vp]),
+    "dcs_operator_expectation_workspace_size": (_i, [_vp, _vp, _i, _szp]),
+    "dcs_operator_expectation": (_i, [_vp, _vp, _i, _i, _vp, _vp, _vp, _sz, _vp]),
 }
 
 

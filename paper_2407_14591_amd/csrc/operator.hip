@@ -145,8 +145,10 @@ __device__ __forceinline__ void op_fill_record(const SectorDesc &sd, const OpClu
 }
 
 // K: columns of a block [D][K] of real vectors (one unrank and one rank per target
-// serve all K); complex vectors take one column.
-template <typename IdxT, typename T, bool VC, bool XC, bool GT, bool OPL, int K>
+// serve all K); complex vectors take one column.  EXP: instead of storing (O x)_i,
+// sum x_i (O x)_i over the rows (conj(x_i) for complex vectors) in FP64, and write
+// the workgroup's sum (K values, or re and im) to P.y at its block index.
+template <typename IdxT, typename T, bool VC, bool XC, bool GT, bool OPL, int K, bool EXP = false>
 __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
     static_assert(XC || !VC, "a complex operator needs complex vectors");
     static_assert(!XC || K == 1, "complex vectors take one column");
@@ -174,6 +176,10 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
     const uint32_t nb = sd.nb;
     const uint32_t dmask = (1u << nb) - 1u;
     const uint64_t stride = (uint64_t)gridDim.x * kOpThreads;
+    constexpr int NV = XC ? 2 : K;  // values an expectation sums
+    double part[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) part[c] = 0.0;
     for (uint64_t i = (uint64_t)blockIdx.x * kOpThreads + threadIdx.x; i < sd.dim; i += stride) {
         uint32_t w[kMaxSub];
         int lam[kMaxSub];
@@ -283,7 +289,46 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
                     if (e0 + u < ee) op_fma<VC, XC>(acc, val[e0 + u], xt[u]);
             }
         }
-        y[i] = acc;
+        if constexpr (EXP) {
+            const X xi = x[i];
+            if constexpr (XC) {  // conj(x_i) (O x)_i
+                part[0] += (double)xi.re * (double)acc.re + (double)xi.im * (double)acc.im;
+                part[1] += (double)xi.re * (double)acc.im - (double)xi.im * (double)acc.re;
+            } else if constexpr (K > 1) {
+#pragma unroll
+                for (int c = 0; c < K; ++c) part[c] += (double)xi[c] * (double)acc[c];
+            } else {
+                part[0] += (double)xi * (double)acc;
+            }
+        } else {
+            y[i] = acc;
+        }
+    }
+    if constexpr (EXP) {  // the workgroup's sums: across each wave, then the waves in order
+        __shared__ double red[kOpThreads / 64][NV];
+        const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            double v = part[c];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) red[wave][c] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < NV) {
+            double t = 0.0;
+            for (int wv = 0; wv < kOpThreads / 64; ++wv) t += red[wv][threadIdx.x];
+            reinterpret_cast<double *>(P.y)[(size_t)blockIdx.x * NV + threadIdx.x] = t;
+        }
+    }
+}
+
+// the workgroups' sums added in block order (deterministic): out[c] for c < nv
+__global__ void op_exp_final(const double *__restrict__ part, int nblocks, int nv, double *__restrict__ out) {
+    const int c = threadIdx.x;
+    if (c < nv) {
+        double t = 0.0;
+        for (int b = 0; b < nblocks; ++b) t += part[(size_t)b * nv + c];
+        out[c] = t;
     }
 }
 
@@ -667,8 +712,17 @@ int operator_check(const dcs_sector *s, const dcs_operator *o, int dtype, int k)
     return DCS_OK;
 }
 
-int launch_operator(const dcs_sector *s, const dcs_operator *o, int dtype, int k, const void *x, void *y,
-                    hipStream_t stream) {
+// workgroups of an operator launch on the sector (the expectation's partial sums)
+static int op_grid(const dcs_sector *s) {
+    const uint64_t blocks = (s->desc.dim + kOpThreads - 1) / kOpThreads;
+    const uint64_t cap = (uint64_t)device_cu_count(s->device) * 8;
+    return (int)std::max<uint64_t>(1, std::min(blocks, cap));
+}
+
+// EXP: y is the workspace of the workgroups' sums, out the expectation (device)
+template <bool EXP>
+static int launch_operator_t(const dcs_sector *s, const dcs_operator *o, int dtype, int k, const void *x, void *y,
+                             double *out, hipStream_t stream) {
     const bool xc = dtype == DCS_C64 || dtype == DCS_C128;
     const bool single = dtype == DCS_F32 || dtype == DCS_C64;
     DeviceGuard g(s->device);
@@ -690,14 +744,17 @@ int launch_operator(const dcs_sector *s, const dcs_operator *o, int dtype, int k
     P.lds_cpos = P.lds_tabs + (opl ? P.op_bytes : 0u);
     const size_t lds = (size_t)P.lds_cpos + kOpRecBytes * (size_t)std::max(o->ncl, 1);
     if (lds > 160 * 1024) return set_error(DCS_EUNSUPPORTED, "operator of %d clusters beyond the LDS budget", o->ncl);
-    const uint64_t blocks = (s->desc.dim + kOpThreads - 1) / kOpThreads;
-    const uint64_t cap = (uint64_t)device_cu_count(s->device) * 8;
-    const int grid = (int)std::max<uint64_t>(1, std::min(blocks, cap));
+    const int grid = op_grid(s);
     hipStream_t st = stream;
     auto go = [&](auto kern) -> int {
         if (int r = ensure_lds(kern, lds)) return r;
         kern<<<grid, kOpThreads, lds, st>>>(P);
-        return check_hip(hipGetLastError(), "operator kernel launch");
+        if (int r = check_hip(hipGetLastError(), "operator kernel launch")) return r;
+        if constexpr (EXP) {
+            op_exp_final<<<1, 64, 0, st>>>(reinterpret_cast<const double *>(y), grid, xc ? 2 : k, out);
+            return check_hip(hipGetLastError(), "expectation sum launch");
+        }
+        return DCS_OK;
     };
     auto pick_k = [&](auto tag, auto vc, auto xcc, auto kk) -> int {
         using T = decltype(tag);
@@ -705,14 +762,16 @@ int launch_operator(const dcs_sector *s, const dcs_operator *o, int dtype, int k
         constexpr int K = decltype(kk)::value;
         if (s->wide) {
             if (s->gtab)
-                return opl ? go(op_kernel<uint64_t, T, VC, XC, true, true, K>)
-                           : go(op_kernel<uint64_t, T, VC, XC, true, false, K>);
-            return opl ? go(op_kernel<uint64_t, T, VC, XC, false, true, K>)
-                       : go(op_kernel<uint64_t, T, VC, XC, false, false, K>);
+                return opl ? go(op_kernel<uint64_t, T, VC, XC, true, true, K, EXP>)
+                           : go(op_kernel<uint64_t, T, VC, XC, true, false, K, EXP>);
+            return opl ? go(op_kernel<uint64_t, T, VC, XC, false, true, K, EXP>)
+                       : go(op_kernel<uint64_t, T, VC, XC, false, false, K, EXP>);
         }
         if (s->gtab)
-            return opl ? go(op_kernel<uint32_t, T, VC, XC, true, true, K>) : go(op_kernel<uint32_t, T, VC, XC, true, false, K>);
-        return opl ? go(op_kernel<uint32_t, T, VC, XC, false, true, K>) : go(op_kernel<uint32_t, T, VC, XC, false, false, K>);
+            return opl ? go(op_kernel<uint32_t, T, VC, XC, true, true, K, EXP>)
+                       : go(op_kernel<uint32_t, T, VC, XC, true, false, K, EXP>);
+        return opl ? go(op_kernel<uint32_t, T, VC, XC, false, true, K, EXP>)
+                   : go(op_kernel<uint32_t, T, VC, XC, false, false, K, EXP>);
     };
     auto pick = [&](auto tag, auto vc, auto xcc) -> int {
         if constexpr (decltype(xcc)::value) {
@@ -733,6 +792,11 @@ int launch_operator(const dcs_sector *s, const dcs_operator *o, int dtype, int k
     return single ? pick(0.0f, Tt{}, Tt{}) : pick(0.0, Tt{}, Tt{});
 }
 
+int launch_operator(const dcs_sector *s, const dcs_operator *o, int dtype, int k, const void *x, void *y,
+                    hipStream_t stream) {
+    return launch_operator_t<false>(s, o, dtype, k, x, y, nullptr, stream);
+}
+
 }  // namespace dcs
 
 extern "C" int dcs_operator_apply(const dcs_sector *s, const dcs_operator *o, int dtype, int k, const void *x,
@@ -746,4 +810,24 @@ extern "C" int dcs_operator_apply(const dcs_sector *s, const dcs_operator *o, in
     if ((const char *)y < (const char *)x + bytes && (const char *)x < (const char *)y + bytes)
         return set_error(DCS_EINVAL, "y overlaps x");
     return launch_operator(s, o, dtype, k, x, y, (hipStream_t)stream);
+}
+
+extern "C" int dcs_operator_expectation_workspace_size(const dcs_sector *s, const dcs_operator *o, int k,
+                                                       size_t *bytes) {
+    clear_error();
+    if (!s || !o || !bytes) return set_error(DCS_EINVAL, "NULL argument");
+    if (k != 1 && k != 2 && k != 4 && k != 8) return set_error(DCS_EINVAL, "k=%d not in {1,2,4,8}", k);
+    *bytes = (size_t)op_grid(s) * (size_t)std::max(k, 2) * sizeof(double);
+    return DCS_OK;
+}
+
+extern "C" int dcs_operator_expectation(const dcs_sector *s, const dcs_operator *o, int dtype, int k, const void *x,
+                                        double *out, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (int r = operator_check(s, o, dtype, k)) return r;
+    if (!x || !out || !ws) return set_error(DCS_EINVAL, "NULL argument");
+    const bool xc = dtype == DCS_C64 || dtype == DCS_C128;
+    const size_t need = (size_t)op_grid(s) * (size_t)(xc ? 2 : k) * sizeof(double);
+    if (ws_bytes < need) return set_error(DCS_EINVAL, "workspace of %zu bytes < %zu", ws_bytes, need);
+    return launch_operator_t<true>(s, o, dtype, k, x, ws, out, (hipStream_t)stream);
 }

@@ -460,3 +460,68 @@ def test_app_d_through_operator_strings_L28():
         say("appd operator", e, E[e], st["E"], "<Sz0>", ez, st["sz"][0], "gap", gap)
         assert abs(E[e] - st["E"]) <= 1e-10 * abs(st["E"])
         assert abs(ez - st["sz"][0]) <= 2 * st["residual_norm"] / gap + 1e-9
+
+
+@pytest.mark.parametrize("Q,L,n,split", [(2, 12, 5, [4, 4, 4]), (3, 7, 6, [3, 4])])
+def test_operator_expectation(Q, L, n, split):
+    """sum_s x_s (O x)_s per column without storing O x, against the oracle's product
+    dotted with x (FP64 1e-12, FP32 1e-5 of |x| |O x|); complex vectors give
+    sum conj(x) (O x); two calls agree bit for bit."""
+    terms = random_terms(Q, L, 70 + Q)
+    op = dq.Operator(Q, L, terms, cluster_sites=4)
+    bs = BruteSector(Q, L, n, split)
+    s = dq.Sector(L, n, Q, split)
+    rng = np.random.default_rng(5)
+    for k in (1, 2, 4, 8):
+        X = rng.normal(size=(bs.dim, k))
+        for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+            xd = torch.tensor(X if k > 1 else X[:, 0], device=DEV).to(dt)
+            got = dq.operator_expectation(s, op, xd).cpu().numpy()
+            for c in range(k):
+                y = apply_operator(bs, terms, X[:, c])
+                scale = np.linalg.norm(X[:, c]) * np.linalg.norm(y)
+                assert abs(got[c] - X[:, c] @ y) <= tol * scale, (k, dt, c)
+            if dt == torch.float64:
+                again = dq.operator_expectation(s, op, xd).cpu().numpy()
+                assert np.array_equal(got, again)
+    # complex terms on complex vectors
+    cterms = [(c, st, M * np.exp(0.3j * t)) for t, (c, st, M) in enumerate(terms)]
+    cop = dq.Operator(Q, L, cterms, cluster_sites=4)
+    xc = rng.normal(size=bs.dim) + 1j * rng.normal(size=bs.dim)
+    ref = np.vdot(xc, apply_operator(bs, cterms, xc))
+    for dt, tol in ((torch.complex128, 1e-12), (torch.complex64, 1e-5)):
+        got = complex(dq.operator_expectation(s, cop, torch.tensor(xc, device=DEV).to(dt)).item())
+        scale = np.linalg.norm(xc) * np.linalg.norm(apply_operator(bs, cterms, xc))
+        say("operator expectation", Q, L, dt, got, ref)
+        assert abs(got - ref) <= tol * scale
+
+
+def test_operator_expectation_mixed_and_appd():
+    """On sites of different dimensions against the mixed oracle; App. D's S^z_0 at
+    L = 28 (40,116,600 states) against the stored product dotted on the device; a
+    workspace too small is refused."""
+    from oracle import mixed
+    dims = [2, 3, 2, 3, 2, 3, 2]
+    terms = [(1.0, (0,), np.diag([-0.5, 0.5])), (0.7, (1, 2), synth.random_local_matrix_dims([3, 2], 3)),
+             (0.4, (6, 0, 3), synth.random_local_matrix_dims([2, 2, 3], 4, 0.6))]
+    ms = mixed.MixedSector(dims, 5)
+    s = dq.Sector(7, 5, dims)
+    op = dq.Operator(dims, 7, terms, cluster_sites=3)
+    x = np.random.default_rng(8).normal(size=ms.dim)
+    y = mixed.apply_operator(ms, terms, x)
+    got = dq.operator_expectation(s, op, torch.tensor(x, device=DEV)).item()
+    assert abs(got - x @ y) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(y)
+    L, n = 28, 14
+    big = dq.Sector(L, n, 2)
+    sz0 = dq.Operator(2, L, [dq.operator_string(1.0, (0,), ("Sz",), 2)])
+    xb = torch.randn(big.dim, dtype=torch.float64, device=DEV)
+    e = dq.operator_expectation(big, sz0, xb).item()
+    ref = torch.dot(xb, dq.operator_apply(big, sz0, xb)).item()
+    say("App. D Sz0 expectation", e, ref)
+    assert abs(e - ref) <= 1e-12 * torch.dot(xb, xb).item()
+    out = torch.empty(1, dtype=torch.float64, device=DEV)
+    ws = torch.empty(8, dtype=torch.uint8, device=DEV)
+    with pytest.raises(dq.DcsError):
+        dq._lib.call("dcs_operator_expectation", big._h, sz0._h, dq._lib.DCS_F64, 1, xb.data_ptr(), out.data_ptr(),
+                      ws.data_ptr(), 8, None)
+    big.close()
