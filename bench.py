@@ -333,6 +333,11 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
             "achieved_GBs": s.dim * 2 * es / per_o / 1e9,
             "frac_of_peak": s.dim * 2 * es / per_o / 1e9 / PEAK_HBM_GBS,
             "max_rel_diff_vs_xxz": float(((y - y2).abs().max() / y2.abs().max()).item())}
+        if tag == "f64":  # <x|H|x> without storing H x (reads x once, writes nothing)
+            per_e = timed(lambda: dq.operator_expectation(s, op, x), n=max(3, steps // 4), w=1)
+            out["operator_L28_appd_f64"]["expectation_ms"] = per_e * 1e3
+            out["operator_L28_appd_f64"]["expectation_rel_diff"] = float(
+                abs(dq.operator_expectation(s, op, x).item() - torch.dot(x, y).item()) / abs(torch.dot(x, y).item()))
         del x, y, y2
     # complex128 vectors (a real operator on the real and imaginary parts at once)
     xc = torch.complex(torch.randn(s.dim, generator=g, device=dev, dtype=torch.float64),
