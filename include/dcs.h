@@ -235,6 +235,16 @@ int dcs_lex_rank_q(int L, int n_particles, int Q, const uint64_t *d_states, uint
 int dcs_lex_unrank_q(int L, int n_particles, int Q, const uint64_t *d_idx, uint64_t *d_states, size_t count,
                      uint64_t *d_num_invalid, void *stream);
 
+/* The same with a local dimension per site (Sec. 5's generalisation; local_dims: L
+ * host entries in [2, 16], digits packed ceil(log2 max) bits per site): the counts
+ * become those of the last g sites with their own dimensions, and a digit at or above
+ * its site's dimension is invalid.  Errors as dcs_lex_rank_q, DCS_EINVAL for a NULL
+ * list or n outside [0, sum_i (local_dims[i] - 1)]. */
+int dcs_lex_rank_mixed(int L, int n_particles, const int32_t *local_dims, const uint64_t *d_states,
+                       uint64_t *d_idx, size_t count, uint64_t *d_num_invalid, void *stream);
+int dcs_lex_unrank_mixed(int L, int n_particles, const int32_t *local_dims, const uint64_t *d_idx,
+                         uint64_t *d_states, size_t count, uint64_t *d_num_invalid, void *stream);
+
 /*
  * Enumeration, function (ii) of Sec. 2.2 applied count-1 times from state
  * `first`: d_states[t] = state with index first + t.  Does not wrap: returns

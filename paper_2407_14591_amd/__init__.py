@@ -533,13 +533,19 @@ def expectation_values(sector: Sector, terms: Terms, psi, fields: bool = True):
 
 def lex_rank(L: int, n: int, states: torch.Tensor, out: torch.Tensor | None = None, count_invalid=False, Q: int = 2):
     """Ranks in the lexicographic (N = L, on-the-fly) order of the sector (dcs_lex_rank for
-    Q = 2, dcs_lex_rank_q for any Q)."""
+    Q = 2, dcs_lex_rank_q for any Q, dcs_lex_rank_mixed when Q is a list of L local
+    dimensions)."""
     dev = states.device.index if states.is_cuda else 0
     _check_dev(states, dev, "states", (torch.int64, torch.uint64))
     out = torch.empty_like(states) if out is None else out
     _check_dev(out, dev, "out", (torch.int64, torch.uint64), numel=states.numel())
     cnt = torch.zeros(1, dtype=torch.int64, device=states.device) if count_invalid else None
-    if Q == 2:
+    if hasattr(Q, "__len__"):
+        if len(Q) != L:
+            raise ValueError(f"{len(Q)} local dimensions for {L} sites")
+        dims = (C.c_int32 * L)(*[int(q) for q in Q])
+        call("dcs_lex_rank_mixed", L, n, dims, _ptr(states), _ptr(out), states.numel(), _ptr(cnt), _stream(dev))
+    elif Q == 2:
         call("dcs_lex_rank", L, n, _ptr(states), _ptr(out), states.numel(), _ptr(cnt), _stream(dev))
     else:
         call("dcs_lex_rank_q", L, n, Q, _ptr(states), _ptr(out), states.numel(), _ptr(cnt), _stream(dev))
@@ -548,13 +554,18 @@ def lex_rank(L: int, n: int, states: torch.Tensor, out: torch.Tensor | None = No
 
 def lex_unrank(L: int, n: int, idx: torch.Tensor, out: torch.Tensor | None = None, count_invalid=False, Q: int = 2):
     """States at lexicographic (N = L, on-the-fly) positions of the sector (dcs_lex_unrank for
-    Q = 2, dcs_lex_unrank_q for any Q)."""
+    Q = 2, dcs_lex_unrank_q for any Q, dcs_lex_unrank_mixed for a list of local dimensions)."""
     dev = idx.device.index if idx.is_cuda else 0
     _check_dev(idx, dev, "idx", (torch.int64, torch.uint64))
     out = torch.empty_like(idx) if out is None else out
     _check_dev(out, dev, "out", (torch.int64, torch.uint64), numel=idx.numel())
     cnt = torch.zeros(1, dtype=torch.int64, device=idx.device) if count_invalid else None
-    if Q == 2:
+    if hasattr(Q, "__len__"):
+        if len(Q) != L:
+            raise ValueError(f"{len(Q)} local dimensions for {L} sites")
+        dims = (C.c_int32 * L)(*[int(q) for q in Q])
+        call("dcs_lex_unrank_mixed", L, n, dims, _ptr(idx), _ptr(out), idx.numel(), _ptr(cnt), _stream(dev))
+    elif Q == 2:
         call("dcs_lex_unrank", L, n, _ptr(idx), _ptr(out), idx.numel(), _ptr(cnt), _stream(dev))
     else:
         call("dcs_lex_unrank_q", L, n, Q, _ptr(idx), _ptr(out), idx.numel(), _ptr(cnt), _stream(dev))

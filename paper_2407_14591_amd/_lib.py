@@ -51,6 +51,8 @@ SIGNATURES = {
     "dcs_lex_unrank": (_i, [_i, _i, _vp, _vp, _sz, _vp, _vp]),
     "dcs_lex_rank_q": (_i, [_i, _i, _i, _vp, _vp, _sz, _vp, _vp]),
     "dcs_lex_unrank_q": (_i, [_i, _i, _i, _vp, _vp, _sz, _vp, _vp]),
+    "dcs_lex_rank_mixed": (_i, [_i, _i, _i32p, _vp, _vp, _sz, _vp, _vp]),
+    "dcs_lex_unrank_mixed": (_i, [_i, _i, _i32p, _vp, _vp, _sz, _vp, _vp]),
     "dcs_rank": (_i, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "dcs_rank_search": (_i, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "dcs_unrank": (_i, [_vp, _vp, _vp, _sz, _vp, _vp]),

@@ -215,3 +215,44 @@ def test_mixed_refusals():
     u = dq.Sector(8, 4, [2] * 8, [4, 4])
     v = dq.Sector(8, 4, 2, [4, 4])
     assert u.dim == v.dim and torch.equal(u.enumerate(0, u.dim), v.enumerate(0, v.dim))
+
+
+@pytest.mark.parametrize("dims,n", [([2, 3] * 4, 5), ([3, 2, 4, 2, 3], 6), ([5, 2, 3, 4, 2], 7), ([2, 3], 2),
+                                    ([4, 2, 2, 3, 2, 2, 4], 0), ([2, 3, 2, 3, 2, 3], 9)])
+def test_mixed_on_the_fly_full(dims, n):
+    """The on-the-fly container (N = L, no tables of states) with a local dimension per
+    site: every state in the order of L one-site subsystems (the brute-force mixed oracle)
+    against rank and unrank; a digit above its site's dimension ranked out."""
+    L = len(dims)
+    ms = mixed.MixedSector(dims, n, [1] * L)
+    ar = np.arange(ms.dim, dtype=np.uint64)
+    idx, bad = dq.lex_rank(L, n, to_dev(ms.states), count_invalid=True, Q=dims)
+    assert int(bad.item()) == 0 and np.array_equal(to_host_u64(idx), ar)
+    back, bad = dq.lex_unrank(L, n, to_dev(ar), count_invalid=True, Q=dims)
+    assert int(bad.item()) == 0 and np.array_equal(to_host_u64(back), ms.states)
+    if min(dims) == 2 and max(dims) > 2:  # site with dimension 2 holding digit 2
+        nb = nbits_for(max(dims))
+        i2 = dims.index(2)
+        s = np.uint64(2) << np.uint64(nb * (L - 1 - i2))
+        _, cnt = dq.lex_rank(L, 2, to_dev(np.array([s], dtype=np.uint64)), count_invalid=True, Q=dims)
+        assert int(cnt.item()) == 1
+
+
+def test_mixed_on_the_fly_large():
+    """Alternating spin-1/2, spin-1 sites, L = 32, Sz = 0 (64 packed bits): 2^20 random
+    indices unrank to valid states whose numeric order is the index order (the
+    lexicographic order of L one-site subsystems), rank back to themselves; indices >= D
+    are counted."""
+    dims = [2, 3] * 16
+    L, n = 32, 24
+    dim = mixed.dim_poly(dims, n)
+    ids = np.sort(np.random.default_rng(4).integers(0, dim, size=1 << 20, dtype=np.int64)).astype(np.uint64)
+    ids = np.unique(ids)
+    st = dq.lex_unrank(L, n, to_dev(ids), Q=dims)
+    h = to_host_u64(st)
+    assert np.all(np.diff(h.astype(object)) > 0) if len(h) < 1000 else np.all(h[1:] > h[:-1])
+    dig = np.stack([((h >> np.uint64(2 * (L - 1 - i))) & np.uint64(3)).astype(np.int64) for i in range(L)], axis=1)
+    assert np.all(dig < np.array(dims)) and np.all(dig.sum(axis=1) == n)
+    assert np.array_equal(to_host_u64(dq.lex_rank(L, n, st, Q=dims)), ids)
+    _, cnt = dq.lex_unrank(L, n, to_dev(np.array([dim - 1, dim, dim + 5], dtype=np.uint64)), count_invalid=True, Q=dims)
+    assert int(cnt.item()) == 2
