@@ -256,3 +256,27 @@ def test_mixed_on_the_fly_large():
     assert np.array_equal(to_host_u64(dq.lex_rank(L, n, st, Q=dims)), ids)
     _, cnt = dq.lex_unrank(L, n, to_dev(np.array([dim - 1, dim, dim + 5], dtype=np.uint64)), count_invalid=True, Q=dims)
     assert int(cnt.item()) == 2
+
+
+def test_mixed_tables_in_device_memory(monkeypatch):
+    """The same sectors with their tables read in device memory (the kernels' global-table
+    path): rank, sorted-list rank, unrank, enumerate and an operator product."""
+    monkeypatch.setenv("DCS_GLOBAL_TABLES", "1")
+    for dims, n, sp in [([2, 3] * 4, 5, [4, 4]), ([3, 2, 4, 2, 3], 6, [2, 3]), ([2] * 6 + [3] * 6, 7, [6, 6])]:
+        ms = mixed.MixedSector(dims, n, sp)
+        s = dq.Sector(len(dims), n, dims, sp)
+        assert s.tables_in_device_memory
+        st = to_dev(ms.states)
+        ar = np.arange(ms.dim, dtype=np.uint64)
+        assert np.array_equal(to_host_u64(s.rank(st)), ar)
+        assert np.array_equal(to_host_u64(s.rank_search(st)), ar)
+        assert np.array_equal(to_host_u64(s.unrank(to_dev(ar))), ms.states)
+        assert np.array_equal(to_host_u64(s.enumerate(0, ms.dim)), ms.states)
+        terms = random_terms(dims, 40 + len(dims))
+        op = dq.Operator(dims, len(dims), terms, cluster_sites=4)
+        x = np.random.default_rng(6).normal(size=ms.dim)
+        err = rel_err(dq.operator_apply(s, op, torch.tensor(x, device=DEV)).cpu().numpy(),
+                      mixed.apply_operator(ms, terms, x))
+        say("mixed global tables", dims, n, err)
+        assert err <= 1e-12
+        s.close()
