@@ -311,6 +311,29 @@ def extra_workloads(dq, synth, torch, steps: int, warmup: int):
             for e in range(len(ref)))}
     del r, ex, v0
 
+    del s, t, jd, zd, hd
+    torch.cuda.empty_cache()
+    out.update(operator_workloads(dq, synth, torch, steps, warmup))
+    return out
+
+
+def operator_workloads(dq, synth, torch, steps: int, warmup: int):
+    """Generic operators (Sec. 4.1, App. C), the Lindbladian, sites of different local
+    dimensions (Sec. 5) and the on-the-fly container for Q = 3: the bench's workloads of
+    the operator class (run alone with --operator-workloads-only)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+
+    def timed(fn, n=steps, w=warmup):
+        return median(time_steps(fn, stream, max(n, 3), w))
+
+    g = torch.Generator(device=dev)
+    g.manual_seed(synth.SEED_X)
+    s = dq.Sector(28, 14, 2, [7, 7, 7, 7], device=0)
+    bonds, jxy, jz, h = synth.tilted_field_chain(28)
+    t = dq.Terms(bonds)
+    jd, zd, hd = (torch.tensor(a, device=dev) for a in (jxy, jz, h))
     # the same Hamiltonian as a generic operator (Sec. 4.1 strings S+S-, S-S+, SzSz, Sz;
     # App. C clusters of 4 sites): one product per dtype against the XXZ product,
     # and the largest difference between the two
@@ -584,6 +607,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (CPU timing and the variants' errors vs the oracle)")
     ap.add_argument("--no-extras", action="store_true", help="time the headline product only")
+    ap.add_argument("--operator-workloads-only", action="store_true",
+                    help="of the other workloads, time only those of the operator class")
     ap.add_argument("--split-sweep", action="store_true",
                     help="also time rank, unrank and H*x versus the number of subsystems")
     ap.add_argument("--no-copy", action="store_true",
@@ -723,7 +748,9 @@ def main(argv=None) -> int:
     if "f64k1" in results:
         out["speedup_vs_plain_f64_per_column"] = r["columns_per_s"] / results["f64k1"]["columns_per_s"]
     if not args.no_extras:
-        out["workloads"] = extra_workloads(dq, synth, torch, args.steps, args.warmup)
+        out["workloads"] = (operator_workloads(dq, synth, torch, args.steps, args.warmup)
+                            if args.operator_workloads_only else
+                            extra_workloads(dq, synth, torch, args.steps, args.warmup))
     if args.split_sweep:
         out["split_sweep"] = split_sweep(dq, synth, torch, args.steps, args.warmup)
     if want_check and x_host_k1 is not None:

@@ -488,8 +488,8 @@ int dcs_operator_apply(const dcs_sector *sector, const dcs_operator *op, int dty
  * columns (k in {1, 2, 4, 8}; <x|O|x> when O is symmetric), or, for complex vectors
  * (k = 1), d_out[0] + i d_out[1] = sum_s conj(x_s) (O x)_s.  The product is the one of
  * dcs_operator_apply, but no y is stored: each row's contribution is summed in FP64,
- * every workgroup writes its sum to d_ws, and a second kernel adds those in workgroup
- * order, so the result does not depend on timing.  d_out is device memory of k
+ * every workgroup writes its sum to d_ws, and a second kernel adds those in a fixed
+ * order (strided per thread, then a fixed tree), so the result does not depend on timing.  d_out is device memory of k
  * doubles (2 for complex vectors); d_ws of at least the bytes
  * dcs_operator_expectation_workspace_size gives (caller-owned, reused freely between
  * calls, not shared by calls that overlap).  Errors as dcs_operator_apply, and

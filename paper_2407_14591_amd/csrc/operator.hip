@@ -322,13 +322,23 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
     }
 }
 
-// the workgroups' sums added in block order (deterministic): out[c] for c < nv
-__global__ void op_exp_final(const double *__restrict__ part, int nblocks, int nv, double *__restrict__ out) {
-    const int c = threadIdx.x;
-    if (c < nv) {
+// the workgroups' sums added in a fixed order (deterministic): out[c] for c < nv; each
+// of 256 threads sums a strided subset in block order, then a fixed tree in LDS
+constexpr int kExpFinalThreads = 256;
+__global__ __launch_bounds__(kExpFinalThreads) void op_exp_final(const double *__restrict__ part, int nblocks, int nv,
+                                                                 double *__restrict__ out) {
+    __shared__ double red[kExpFinalThreads];
+    for (int c = 0; c < nv; ++c) {
         double t = 0.0;
-        for (int b = 0; b < nblocks; ++b) t += part[(size_t)b * nv + c];
-        out[c] = t;
+        for (int b = threadIdx.x; b < nblocks; b += kExpFinalThreads) t += part[(size_t)b * nv + c];
+        red[threadIdx.x] = t;
+        __syncthreads();
+        for (int w = kExpFinalThreads / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[c] = red[0];
+        __syncthreads();
     }
 }
 
@@ -751,7 +761,7 @@ static int launch_operator_t(const dcs_sector *s, const dcs_operator *o, int dty
         kern<<<grid, kOpThreads, lds, st>>>(P);
         if (int r = check_hip(hipGetLastError(), "operator kernel launch")) return r;
         if constexpr (EXP) {
-            op_exp_final<<<1, 64, 0, st>>>(reinterpret_cast<const double *>(y), grid, xc ? 2 : k, out);
+            op_exp_final<<<1, kExpFinalThreads, 0, st>>>(reinterpret_cast<const double *>(y), grid, xc ? 2 : k, out);
             return check_hip(hipGetLastError(), "expectation sum launch");
         }
         return DCS_OK;
