@@ -118,3 +118,39 @@ def test_operator_host_checks(lib):
     assert create(2, 4, [2], [1, 2], [float("nan")], hop) == _lib.DCS_EINVAL
     assert l.dcs_operator_info(None, None, None, None, None) == _lib.DCS_EINVAL
     assert l.dcs_operator_destroy(None) == _lib.DCS_OK
+
+
+def test_mixed_and_on_the_fly_host_checks(lib):
+    """The per-site-dimension and any-Q calls check their arguments before any device
+    call (CPU): NULL or out-of-range local dimensions, too many bits, n out of range;
+    the on-the-fly calls with count 0 need no device; a mixed operator checks the size
+    of each term's matrix against its sites' dimensions."""
+    from paper_2407_14591_amd import _lib
+    l = _lib.lib()
+    out = C.c_void_p()
+    i32 = lambda v: (C.c_int32 * len(v))(*v)
+    assert l.dcs_sector_create_mixed(4, 1, None, 0, None, 0, C.byref(out)) == _lib.DCS_EINVAL
+    assert l.dcs_sector_create_mixed(4, 1, i32([2, 1, 2, 2]), 0, None, 0, C.byref(out)) == _lib.DCS_EINVAL
+    assert l.dcs_sector_create_mixed(4, 1, i32([2, 17, 2, 2]), 0, None, 0, C.byref(out)) == _lib.DCS_EINVAL
+    assert l.dcs_sector_create_mixed(4, 7, i32([2, 3, 2, 3]), 0, None, 0, C.byref(out)) == _lib.DCS_EINVAL  # n > 6
+    assert l.dcs_sector_create_mixed(33, 1, i32([3] + [2] * 32), 0, None, 0, C.byref(out)) == _lib.DCS_EINVAL  # 66 bits
+    assert l.dcs_sector_create_mixed(0, 0, i32([2]), 0, None, 0, C.byref(out)) == _lib.DCS_EINVAL
+    # on the fly: bad Q / dims / n are refused; count 0 returns at once
+    assert l.dcs_lex_rank_q(8, 2, 17, None, None, 0, None, None) == _lib.DCS_EINVAL
+    assert l.dcs_lex_rank_q(33, 2, 3, None, None, 0, None, None) == _lib.DCS_EINVAL
+    assert l.dcs_lex_rank_q(8, 17, 3, None, None, 0, None, None) == _lib.DCS_EINVAL
+    assert l.dcs_lex_unrank_q(8, 4, 3, None, None, 0, None, None) == _lib.DCS_OK
+    assert l.dcs_lex_rank_mixed(4, 2, None, None, None, 0, None, None) == _lib.DCS_EINVAL
+    assert l.dcs_lex_rank_mixed(4, 7, i32([2, 3, 2, 3]), None, None, 0, None, None) == _lib.DCS_EINVAL
+    assert l.dcs_lex_unrank_mixed(4, 5, i32([2, 3, 2, 3]), None, None, 0, None, None) == _lib.DCS_OK
+    # a mixed operator: a term on sites of dimensions 2 and 3 needs a 6 x 6 matrix; NULL dimensions refused
+    ns, st, cf = i32([2]), i32([0, 1]), (C.c_double * 1)(1.0)
+    mt = (C.c_double * 36)(*([0.0] * 36))
+    assert l.dcs_operator_create_mixed(4, None, 1, ns, st, cf, mt, 0, 4, 0, C.byref(out)) == _lib.DCS_EINVAL
+    assert l.dcs_operator_create_mixed(4, i32([2, 3, 2, 3]), 1, ns, st, cf, mt, 0, 0, 0, C.byref(out)) == _lib.DCS_EINVAL
+    assert l.dcs_operator_create_mixed(4, i32([2, 1, 2, 3]), 1, ns, st, cf, mt, 0, 4, 0, C.byref(out)) == _lib.DCS_EINVAL
+    bad = [0.0] * 36
+    bad[0 * 6 + 1] = 1.0  # <0,0|M|0,1>: digit sums 0 and 1
+    mb = (C.c_double * 36)(*bad)
+    assert l.dcs_operator_create_mixed(4, i32([2, 3, 2, 3]), 1, ns, st, cf, mb, 0, 4, 0, C.byref(out)) == _lib.DCS_EINVAL
+    assert b"conserve" in l.dcs_last_error()
