@@ -58,7 +58,7 @@ struct OpParams {
     const char *opblob;
     uint32_t op_bytes, off_rp, off_dep, off_val;
     uint32_t lds_tabs;  // LDS bytes of the sector's tables (0: read in device memory)
-    uint32_t lds_cpos;  // LDS byte offset of the per-cluster records (kOpRecBytes each)
+    uint32_t lds_recs;  // LDS byte offset of the per-cluster records (kOpRecBytes each)
     const void *x;
     void *y;
     int ncl;
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kOpThreads) void op_kernel(const OpParams P_arg) {
     if constexpr (!GT) stage_blob(lds, P.blob, sd.lay_bytes);
     if constexpr (OPL) stage_blob(lds + P.lds_tabs, P.opblob, P.op_bytes);
     const OpCluster *gcl = reinterpret_cast<const OpCluster *>(P.opblob);
-    uint32_t *recs = reinterpret_cast<uint32_t *>(lds + P.lds_cpos);  // [cluster][12]
+    uint32_t *recs = reinterpret_cast<uint32_t *>(lds + P.lds_recs);  // [cluster][12]
     for (int c = threadIdx.x; c < P.ncl; c += kOpThreads) {
         op_fill_record(sd, gcl[c], recs + c * (kOpRecBytes / 4));
     }
@@ -485,7 +485,7 @@ int operator_create(const int *qs, int L, int num_terms, const int32_t *term_nsi
         }
         cl_terms[found].push_back(t);
     }
-    // each cluster's matrix, CSR by output local index
+    // each cluster's matrix, CSR by the packed output digits (see the key loop below)
     const int nb = (Q - 1) > 0 ? 32 - __builtin_clz((unsigned)(Q - 1)) : 1;
     std::vector<OpCluster> hcl(cl_sites.size());
     std::vector<uint32_t> rowptr, dep;
@@ -751,8 +751,8 @@ static int launch_operator_t(const dcs_sector *s, const dcs_operator *o, int dty
     P.ncl = o->ncl;
     // the operator's arrays go to LDS beside the tables when both fit the budget
     const bool opl = (uint64_t)P.lds_tabs + P.op_bytes + (uint64_t)kOpRecBytes * o->ncl <= kOpLdsMax;
-    P.lds_cpos = P.lds_tabs + (opl ? P.op_bytes : 0u);
-    const size_t lds = (size_t)P.lds_cpos + kOpRecBytes * (size_t)std::max(o->ncl, 1);
+    P.lds_recs = P.lds_tabs + (opl ? P.op_bytes : 0u);
+    const size_t lds = (size_t)P.lds_recs + kOpRecBytes * (size_t)std::max(o->ncl, 1);
     if (lds > 160 * 1024) return set_error(DCS_EUNSUPPORTED, "operator of %d clusters beyond the LDS budget", o->ncl);
     const int grid = op_grid(s);
     hipStream_t st = stream;
