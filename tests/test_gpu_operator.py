@@ -432,8 +432,10 @@ def test_app_d_through_operator_strings_L28():
     """App. D's example as the paper writes it, through the operator class: the open
     chain from separate Sx Sx, Sy Sy, Sz Sz strings and the field k Sz_k at L = 28,
     n = 14; the four lowest levels from dcs_lanczos_operator (240 steps, full
-    re-orthogonalisation) and <Sz_0> of each Ritz vector (the one-term operator Sz_0
-    applied, then a dot product) against the oracle's deflated Lanczos values."""
+    re-orthogonalisation), <Sz_0> of each Ritz vector (the one-term operator Sz_0
+    applied, then a dot product), and <Sz_i> on every site for all four states (the
+    expectation call on a block of the four vectors) against the oracle's deflated
+    Lanczos values."""
     import json
     import os
     ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "appd_L28.json")))
@@ -460,6 +462,20 @@ def test_app_d_through_operator_strings_L28():
         say("appd operator", e, E[e], st["E"], "<Sz0>", ez, st["sz"][0], "gap", gap)
         assert abs(E[e] - st["E"]) <= 1e-10 * abs(st["E"])
         assert abs(ez - st["sz"][0]) <= 2 * st["residual_norm"] / gap + 1e-9
+    # <Sz_i> on every site for the four states at once: the Ritz vectors as a block of four
+    # columns, one expectation call per one-term operator Sz_i (no O x stored)
+    X = torch.stack([res["vectors"][e] / torch.linalg.vector_norm(res["vectors"][e]) for e in range(num)],
+                    dim=1).contiguous()
+    worst = 0.0
+    for i in range(L):
+        szi = dq.Operator(2, L, [dq.operator_string(1.0, (i,), ("Sz",), 2)], cluster_sites=1)
+        got = dq.operator_expectation(s, szi, X).cpu().numpy()
+        for e, st in enumerate(ref["states"]):
+            gap = np.min(np.abs(np.delete(E, e) - E[e]))
+            bound = 2 * st["residual_norm"] / gap + 1e-9
+            worst = max(worst, abs(got[e] - st["sz"][i]) / bound)
+            assert abs(got[e] - st["sz"][i]) <= bound, (i, e)
+    say("appd <Sz_i> via expectation, worst error / bound", worst)
 
 
 @pytest.mark.parametrize("Q,L,n,split", [(2, 12, 5, [4, 4, 4]), (3, 7, 6, [3, 4])])
