@@ -541,3 +541,26 @@ def test_operator_expectation_mixed_and_appd():
         dq._lib.call("dcs_operator_expectation", big._h, sz0._h, dq._lib.DCS_F64, 1, xb.data_ptr(), out.data_ptr(),
                       ws.data_ptr(), 8, None)
     big.close()
+
+
+@pytest.mark.parametrize("Q,L,n,m", [(3, 8, 8, 7), (5, 6, 10, 5)])
+def test_operator_large_clusters(Q, L, n, m):
+    """Clusters whose packed row keys need 2^(nb m) row pointers (Q = 3 on 7 sites:
+    16,384; Q = 5 on 5 sites: 32,768), so the operator no longer fits LDS and the kernel
+    reads it in device memory: every row against the term-by-term oracle."""
+    rng = np.random.default_rng(Q * 100 + m)
+    sites = tuple(int(v) for v in rng.permutation(L)[:m])
+    terms = [(0.8, sites, synth.random_local_matrix(Q, m, 900 + Q, density=0.02)),
+             (0.3, (0, L - 1), synth.random_local_matrix(Q, 2, 901 + Q)),
+             (-0.5, (L // 2,), synth.random_local_matrix(Q, 1, 902 + Q))]
+    op = dq.Operator(Q, L, terms, cluster_sites=m)
+    assert op.max_cluster_sites == m
+    bs = BruteSector(Q, L, n, None)
+    s = dq.Sector(L, n, Q)
+    x = np.random.default_rng(1).normal(size=bs.dim)
+    ref = apply_operator(bs, terms, x)
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        y = dq.operator_apply(s, op, torch.tensor(x, device=DEV).to(dt))
+        err = rel_err(y.double().cpu().numpy(), ref)
+        say("operator large clusters", Q, L, m, op.nnz, dt, err)
+        assert err <= tol
