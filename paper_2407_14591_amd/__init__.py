@@ -306,6 +306,17 @@ class Operator:
         call("dcs_operator_info", self._h, C.byref(ncl), C.byref(nnz), C.byref(mx), C.byref(cx))
         self.num_clusters, self.nnz, self.max_cluster_sites = ncl.value, nnz.value, mx.value
         self.is_complex = bool(cx.value)  # complex terms with real sums make a real operator
+        self._spec = (list(terms), int(cluster_sites))
+
+    def adjoint(self) -> "Operator":
+        """O^+: every term (coef, sites, M) as (coef, sites, M^+) (the coefficients are
+        real), built by the library like this operator (the Heisenberg-picture map of a
+        Lindbladian, the transpose of a real operator)."""
+        import numpy as np
+        terms, cs = self._spec
+        dims = self.local_dims if len(set(self.local_dims)) > 1 else self.Q
+        return Operator(dims, self.L, [(c, st, np.conj(np.asarray(M)).T) for c, st, M in terms],
+                        cluster_sites=cs, device=self.device)
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

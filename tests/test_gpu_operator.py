@@ -564,3 +564,33 @@ def test_operator_large_clusters(Q, L, n, m):
         err = rel_err(y.double().cpu().numpy(), ref)
         say("operator large clusters", Q, L, m, op.nnz, dt, err)
         assert err <= tol
+
+
+def test_operator_adjoint():
+    """<u, O v> = <O^+ u, v> for a non-Hermitian complex operator (random terms with phases),
+    a Lindbladian on the doubled chain, and a non-symmetric real operator on sites of
+    mixed dimensions; O^+ from Operator.adjoint() applied by the same kernel."""
+    Q, L, n = 3, 7, 6
+    terms = [(c, st, M * np.exp(0.7j * t)) for t, (c, st, M) in enumerate(random_terms(Q, L, 12))]
+    cases = [(dq.Operator(Q, L, terms, cluster_sites=4), dq.Sector(L, n, Q))]
+    Lh = 4
+    h = [dq.operator_string(1.0, (i, i + 1), (nm, nm), 2) for i in range(Lh - 1) for nm in ("Sx", "Sy", "Sz")]
+    lop = dq.Operator(2, 2 * Lh, dq.lindbladian_terms(Lh, h, [(0.7, dq.operator_string(1.0, (0, 1), ("S+", "S-"), 2))]))
+    cases.append((lop, dq.Sector(2 * Lh, Lh, 2)))
+    dims = [2, 3, 2, 3, 2, 3]
+    mterms = [(0.6, (0, 1), synth.random_local_matrix_dims([2, 3], 21)), (-0.4, (5, 2, 3), synth.random_local_matrix_dims([3, 2, 3], 22, 0.6))]
+    cases.append((dq.Operator(dims, 6, mterms, cluster_sites=3), dq.Sector(6, 4, dims)))
+    rng = np.random.default_rng(13)
+    for op, s in cases:
+        opd = op.adjoint()
+        cplx = op.is_complex
+        mk = (lambda: rng.normal(size=s.dim) + 1j * rng.normal(size=s.dim)) if cplx else (lambda: rng.normal(size=s.dim))
+        u, v = mk(), mk()
+        tu, tv = torch.tensor(u, device=DEV), torch.tensor(v, device=DEV)
+        ov = dq.operator_apply(s, op, tv).cpu().numpy()
+        odu = dq.operator_apply(s, opd, tu).cpu().numpy()
+        lhs, rhs = np.vdot(u, ov), np.vdot(odu, v)
+        say("operator adjoint", s.L, cplx, lhs, rhs)
+        assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(ov)
+        if not cplx:  # a real non-symmetric operator differs from its transpose
+            assert np.linalg.norm(ov - dq.operator_apply(s, opd, tv).cpu().numpy()) > 1e-3 * np.linalg.norm(ov)
