@@ -22,7 +22,7 @@ from ._lib import (DCS_F32, DCS_F64, DCS_INVALID_INDEX, DCS_REORTH_FULL, DCS_REO
 
 __all__ = ["Sector", "Terms", "Plan", "hamiltonian_apply", "hamiltonian_apply_adjoint",
            "hamiltonian_form", "hamiltonian_apply_adjoint_noalloc",
-           "HApply", "lanczos", "tridiag_eigvals", "lex_rank", "lex_unrank", "expectation_values", "DcsError", "DCS_INVALID_INDEX", "operator_expectation",
+           "HApply", "lanczos", "tridiag_eigvals", "lex_rank", "lex_unrank", "expectation_values", "DcsError", "DCS_INVALID_INDEX", "operator_expectation", "OperatorApply",
            "library_path", "Operator", "operator_apply", "local_operator", "operator_string",
            "lindbladian_terms"]
 
@@ -466,6 +466,26 @@ class HApply(torch.autograd.Function):
                                                   x.detach().contiguous(), g.contiguous(),
                                                   want_grad_x=ctx.needs_input_grad[0])
         return gx, gj, gz, None, None
+
+
+class OperatorApply(torch.autograd.Function):
+    """y = O x for a generic operator (dcs_operator_apply); x is [dim], a real block
+    [dim, k] or a complex vector.  backward: grad_x = O^+ g, the adjoint operator
+    (Operator.adjoint, built once and kept on the operator) applied by the same kernel
+    (for complex vectors this is torch's conjugate convention for a linear map)."""
+
+    @staticmethod
+    def forward(ctx, x, sector, op):
+        ctx.sector, ctx.op = sector, op
+        return operator_apply(sector, op, x.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        op = ctx.op
+        if getattr(op, "_adjoint_op", None) is None:
+            op._adjoint_op = op.adjoint()
+        gx = operator_apply(ctx.sector, op._adjoint_op, g.contiguous()) if ctx.needs_input_grad[0] else None
+        return gx, None, None
 
 
 def lanczos(sector: Sector, terms, jxy, jz, v0, steps: int, reorth="auto",

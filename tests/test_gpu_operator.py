@@ -594,3 +594,21 @@ def test_operator_adjoint():
         assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(ov)
         if not cplx:  # a real non-symmetric operator differs from its transpose
             assert np.linalg.norm(ov - dq.operator_apply(s, opd, tv).cpu().numpy()) > 1e-3 * np.linalg.norm(ov)
+
+
+def test_operator_autograd():
+    """OperatorApply's backward (the adjoint operator on the device) against torch's
+    finite-difference gradcheck for a real non-symmetric operator (FP64, a vector and a
+    block of 2 columns) and a complex non-Hermitian one (complex128)."""
+    Q, L, n = 2, 8, 3
+    rterms = random_terms(Q, L, 41)
+    s = dq.Sector(L, n, Q)
+    op = dq.Operator(Q, L, rterms, cluster_sites=3)
+    x = torch.randn(s.dim, dtype=torch.float64, device=DEV, requires_grad=True)
+    assert torch.autograd.gradcheck(lambda v: dq.OperatorApply.apply(v, s, op), (x,), atol=1e-8, rtol=1e-6)
+    xb = torch.randn(s.dim, 2, dtype=torch.float64, device=DEV, requires_grad=True)
+    assert torch.autograd.gradcheck(lambda v: dq.OperatorApply.apply(v, s, op), (xb,), atol=1e-8, rtol=1e-6)
+    cterms = [(c, st, M * np.exp(0.5j * t)) for t, (c, st, M) in enumerate(rterms)]
+    cop = dq.Operator(Q, L, cterms, cluster_sites=3)
+    xc = torch.randn(s.dim, dtype=torch.complex128, device=DEV, requires_grad=True)
+    assert torch.autograd.gradcheck(lambda v: dq.OperatorApply.apply(v, s, cop), (xc,), atol=1e-8, rtol=1e-6)
