@@ -200,17 +200,17 @@ int dcs_unrank(const dcs_sector *sector, const uint64_t *d_idx, uint64_t *d_stat
                uint64_t *d_num_invalid, void *stream);
 
 /*
- * Rank and unrank without tables, for spin-1/2 (Q = 2) sectors of L sites and
- * n particles cut into L single-site subsystems (eq. N=L): the canonical order
- * is then the lexicographic order of the site strings, site 0 first (the
- * numeric order of the packed states), and Alg. on-the-fly gives the rank as
- * the sum over occupied sites i of C(L-1-i, n - lambda_i).  Each thread steps
- * one binomial coefficient along the sites by exact integer updates, so no
- * sector object and no tables are involved (the paper's on-the-fly limit, the
- * counterpart of the table containers in the split sweep).  States, indices,
- * invalid entries and counting as dcs_rank / dcs_unrank.  DCS_EINVAL for L
- * outside [1, 64] or n outside [0, L]; DCS_EUNSUPPORTED where a coefficient
- * times (L + 1) would pass 2^64 (large L near half filling, e.g. L = 64, n = 32).
+ * Rank and unrank without tables of states, for spin-1/2 (Q = 2) sectors of L sites
+ * and n particles cut into L single-site subsystems (eq. N=L): the canonical order is
+ * then the lexicographic order of the site strings, site 0 first (the numeric order of
+ * the packed states), and Alg. on-the-fly gives the rank as the sum over occupied
+ * sites i of C(L-1-i, n - lambda_i).  No sector object and no stored tables: every
+ * workgroup derives the binomials it needs (L rows of n + 1 counts) in LDS by App. A's
+ * recurrence before serving its states (the paper's on-the-fly limit, the counterpart
+ * of the table containers in the split sweep).  The same kernels serve any Q
+ * (dcs_lex_rank_q) and per-site dimensions (dcs_lex_rank_mixed).  States, indices,
+ * invalid entries and counting as dcs_rank / dcs_unrank.  DCS_EINVAL for L outside
+ * [1, 64] or n outside [0, L].
  */
 int dcs_lex_rank(int L, int n_particles, const uint64_t *d_states, uint64_t *d_idx, size_t count,
                  uint64_t *d_num_invalid, void *stream);

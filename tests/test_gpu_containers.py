@@ -282,3 +282,23 @@ def test_lex_rank_any_q_against_oracle(Q, L, n):
     assert int(cnt.item()) == 2
     with pytest.raises(dq.DcsError):
         dq.lex_rank(L + 64, n, to_dev(st[:4]), Q=Q)
+
+
+def test_lex_rank_L64_half_filling():
+    """L = 64, n = 32 (1.8e18 states, the largest spin-1/2 sector of 64 sites): 2^16
+    random states round-trip, 256 of them against the oracle's lexicographic rank, and
+    the first and last states rank to 0 and D - 1."""
+    import math
+    from oracle.sector import lex_rank as o_lex_rank
+    L, n = 64, 32
+    dim = math.comb(L, n)
+    dig = synth.random_states(2, L, n, 1 << 16, seed=29)
+    st = synth.pack_digits(dig, 2)
+    idx = dq.lex_rank(L, n, to_dev(st))
+    got = to_host_u64(idx)
+    ref = np.array([o_lex_rank(list(int(v) for v in d), 2) for d in dig[:256]], dtype=np.uint64)
+    assert np.array_equal(got[:256], ref)
+    assert int(got.max()) < dim
+    assert np.array_equal(to_host_u64(dq.lex_unrank(L, n, idx)), st)
+    ends = np.array([(1 << 32) - 1, ((1 << 32) - 1) << 32], dtype=np.uint64)  # first and last states
+    assert to_host_u64(dq.lex_rank(L, n, to_dev(ends))).tolist() == [0, dim - 1]
