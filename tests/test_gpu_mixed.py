@@ -280,3 +280,32 @@ def test_mixed_tables_in_device_memory(monkeypatch):
         say("mixed global tables", dims, n, err)
         assert err <= 1e-12
         s.close()
+
+
+def test_mixed_ring_full_size_properties():
+    """The bench's mixed-dimension workload at its size (alternating spin-1/2 / spin-1
+    Heisenberg ring, L = 24, Sz = 0, 259,258,780 states), by properties that hold at any
+    size: the operator is symmetric (<u, H v> = <H u, v> to 1e-12), the FP32 product
+    agrees with the FP64 one to 1e-5, and the expectation call equals x . (H x)."""
+    dims = [2, 3] * 12
+    L, n = 24, 18
+    op = dq.Operator(dims, L, heisenberg_ring(dims), cluster_sites=4)
+    s = dq.Sector(L, n, dims)
+    assert s.dim == mixed.dim_poly(dims, n) == 259258780
+    g = torch.Generator(device=DEV)
+    g.manual_seed(17)
+    u = torch.randn(s.dim, generator=g, device=DEV, dtype=torch.float64)
+    v = torch.randn(s.dim, generator=g, device=DEV, dtype=torch.float64)
+    hv = dq.operator_apply(s, op, v)
+    hu = dq.operator_apply(s, op, u)
+    lhs, rhs = torch.dot(u, hv).item(), torch.dot(hu, v).item()
+    scale = torch.linalg.vector_norm(u).item() * torch.linalg.vector_norm(hv).item()
+    say("mixed ring L24 symmetry", lhs, rhs, scale)
+    assert abs(lhs - rhs) <= 1e-12 * scale
+    hv32 = dq.operator_apply(s, op, v.float()).double()
+    err = (torch.linalg.vector_norm(hv32 - hv) / torch.linalg.vector_norm(hv)).item()
+    assert err <= 1e-5
+    e = dq.operator_expectation(s, op, u).item()
+    assert abs(e - torch.dot(u, hu).item()) <= 1e-12 * torch.linalg.vector_norm(u).item() * torch.linalg.vector_norm(hu).item()
+    del u, v, hu, hv, hv32
+    s.close()
