@@ -612,3 +612,31 @@ def test_operator_autograd():
     cop = dq.Operator(Q, L, cterms, cluster_sites=3)
     xc = torch.randn(s.dim, dtype=torch.complex128, device=DEV, requires_grad=True)
     assert torch.autograd.gradcheck(lambda v: dq.OperatorApply.apply(v, s, cop), (xc,), atol=1e-8, rtol=1e-6)
+
+
+def test_lindbladian_bench_size_properties():
+    """Sec. 4.1's Lindbladian at the bench's size (L = 12 on the doubled chain, 24 sites,
+    2,704,156 states), with a hopping jump added: for a random Hermitian rho, L[rho] is
+    Hermitian (the entry at (s', s) is the conjugate of the one at (s, s'), to 1e-12) and
+    traceless (the diagonal entries sum to zero); the index maps come from the oracle's
+    sorted sector."""
+    Lh, nh = 12, 6
+    h = [dq.operator_string(1.0, (i, i + 1), (nm, nm), 2) for i in range(Lh - 1) for nm in ("Sx", "Sy", "Sz")]
+    jumps = [(1.0, dq.operator_string(1.0, (0,), ("Sz",), 2)), (0.4, dq.operator_string(1.0, (3, 4), ("S+", "S-"), 2))]
+    lop = dq.Operator(2, 2 * Lh, dq.lindbladian_terms(Lh, h, jumps), cluster_sites=4)
+    s = dq.Sector(2 * Lh, 2 * nh, 2)
+    bs = BruteSector(2, 2 * Lh, 2 * nh, s.split)
+    assert bs.dim == s.dim == 2704156
+    ket, bra = bs.states >> np.uint64(Lh), bs.states & np.uint64((1 << Lh) - 1)
+    swap = bs.rank((bra << np.uint64(Lh)) | ket)
+    assert np.all(swap >= 0)
+    diag = np.nonzero(ket == bra)[0]
+    rng = np.random.default_rng(19)
+    x = rng.normal(size=s.dim) + 1j * rng.normal(size=s.dim)
+    rho = 0.5 * (x + np.conj(x[swap]))  # Hermitian: rho[s, s'] = conj(rho[s', s])
+    y = dq.operator_apply(s, lop, torch.tensor(rho, device=DEV)).cpu().numpy()
+    ny = np.linalg.norm(y)
+    herm = np.linalg.norm(y - np.conj(y[swap])) / ny
+    tr = abs(y[diag].sum()) / (ny * np.sqrt(len(diag)))
+    say("lindbladian L12 properties", herm, tr, len(diag))
+    assert herm <= 1e-12 and tr <= 1e-12
