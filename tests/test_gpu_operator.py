@@ -640,3 +640,26 @@ def test_lindbladian_bench_size_properties():
     tr = abs(y[diag].sum()) / (ny * np.sqrt(len(diag)))
     say("lindbladian L12 properties", herm, tr, len(diag))
     assert herm <= 1e-12 and tr <= 1e-12
+
+
+@pytest.mark.parametrize("env", [{"DCS_INDEX_BITS": "64"}, {"DCS_GLOBAL_TABLES": "1"},
+                                 {"DCS_INDEX_BITS": "64", "DCS_GLOBAL_TABLES": "1"}])
+def test_operator_expectation_wide_and_global(monkeypatch, env):
+    """The expectation kernels with 64-bit indices and with the sector's tables in device
+    memory (set at sector creation) against the oracle's product dotted with x."""
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    Q, L, n = 2, 12, 5
+    terms = random_terms(Q, L, 88)
+    op = dq.Operator(Q, L, terms, cluster_sites=4)
+    bs = BruteSector(Q, L, n, [4, 4, 4])
+    s = dq.Sector(L, n, Q, [4, 4, 4])
+    if "DCS_GLOBAL_TABLES" in env:
+        assert s.tables_in_device_memory
+    X = np.random.default_rng(2).normal(size=(bs.dim, 2))
+    got = dq.operator_expectation(s, op, torch.tensor(X, device=DEV)).cpu().numpy()
+    for c in range(2):
+        y = apply_operator(bs, terms, X[:, c])
+        assert abs(got[c] - X[:, c] @ y) <= 1e-12 * np.linalg.norm(X[:, c]) * np.linalg.norm(y)
+    yg = dq.operator_apply(s, op, torch.tensor(X[:, 0], device=DEV)).cpu().numpy()
+    assert rel_err(yg, apply_operator(bs, terms, X[:, 0])) <= 1e-12
