@@ -646,7 +646,8 @@ def test_lindbladian_bench_size_properties():
                                  {"DCS_INDEX_BITS": "64", "DCS_GLOBAL_TABLES": "1"}])
 def test_operator_expectation_wide_and_global(monkeypatch, env):
     """The expectation kernels with 64-bit indices and with the sector's tables in device
-    memory (set at sector creation) against the oracle's product dotted with x."""
+    memory (set at sector creation) against the oracle's product dotted with x; a complex
+    operator's product and expectation on complex128 vectors the same way."""
     for k, v in env.items():
         monkeypatch.setenv(k, v)
     Q, L, n = 2, 12, 5
@@ -663,3 +664,12 @@ def test_operator_expectation_wide_and_global(monkeypatch, env):
         assert abs(got[c] - X[:, c] @ y) <= 1e-12 * np.linalg.norm(X[:, c]) * np.linalg.norm(y)
     yg = dq.operator_apply(s, op, torch.tensor(X[:, 0], device=DEV)).cpu().numpy()
     assert rel_err(yg, apply_operator(bs, terms, X[:, 0])) <= 1e-12
+    # a complex operator on complex128 vectors through the same kernels
+    cterms = [(c, st, M * np.exp(0.9j * t)) for t, (c, st, M) in enumerate(terms)]
+    cop = dq.Operator(Q, L, cterms, cluster_sites=4)
+    xc = X[:, 0] + 1j * X[:, 1]
+    yc = dq.operator_apply(s, cop, torch.tensor(xc, device=DEV)).cpu().numpy()
+    ref = apply_operator(bs, cterms, xc)
+    assert rel_err(yc, ref) <= 1e-12
+    ec = complex(dq.operator_expectation(s, cop, torch.tensor(xc, device=DEV)).item())
+    assert abs(ec - np.vdot(xc, ref)) <= 1e-12 * np.linalg.norm(xc) * np.linalg.norm(ref)
